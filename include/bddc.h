@@ -1,0 +1,187 @@
+/*
+ * bddc.h - C ABI of the MI355X (gfx950) adaptive BDDC library.
+ *
+ * The library solves the assembled problem R^T A R u = R^T f of a
+ * substructured finite element discretization (Sec. 2, eq. (assembled)) by
+ * PCG preconditioned with BDDC in the algebraic form of Algorithm 2 (Sec. 5),
+ * with corner, edge-average and adaptively selected face constraints
+ * (Sec. 3, Algorithm 1).  Constraints are imposed by the generalized change
+ * of variables of Sec. 5 (QR with column pivoting, eq. (T)); every
+ * substructure matrix is then factored by dense Cholesky on the GPU.
+ *
+ * Conventions
+ * - Meshes are Q1 hexahedra.  Degrees of freedom are node-major,
+ *   component-minor (dpn = 1 for the scalar problem, 3 for elasticity).  The
+ *   *global* numbering skips Dirichlet dofs and keeps that order; every
+ *   vector passed to apply / solve uses it (length n_glob, see bddc_info).
+ * - Ownership: the caller owns every array it passes.  bddc_setup copies
+ *   what it needs and keeps no caller pointer.  Vectors passed to
+ *   bddc_apply / bddc_pcg_solve are DEVICE pointers (e.g. a torch tensor's
+ *   data_ptr()) on the context's device, caller-allocated, used on the
+ *   context's stream; the call returns after the result is complete.
+ * - Call order: create -> setup -> [adapt] -> factor -> apply / pcg_solve.
+ *   adapt changes the constraints and invalidates the factors.  A call out of
+ *   order returns BDDC_ERR_STATE.
+ * - Errors: no exception crosses the ABI.  Every function returns a status;
+ *   bddc_last_error() gives a message for the last failing call on a context.
+ * - Threads: one context per host thread.
+ */
+#ifndef BDDC_H
+#define BDDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bddc_ctx bddc_ctx;
+
+typedef enum {
+  BDDC_OK = 0,
+  BDDC_ERR_ARG = 1,                 /* invalid argument (null pointer, size) */
+  BDDC_ERR_STATE = 2,               /* call out of order */
+  BDDC_ERR_OOM = 3,                 /* device or host allocation failed */
+  BDDC_ERR_NOT_SPD = 4,             /* non-positive pivot in a substructure factor */
+  BDDC_ERR_SINGULAR_COARSE = 5,     /* non-positive pivot in the coarse factor */
+  BDDC_ERR_NO_CONVERGENCE = 6,      /* PCG hit maxit, or a NaN / breakdown */
+  BDDC_ERR_INSUFFICIENT_CORNERS = 7,/* Assumption 1 or 2 cannot hold */
+  BDDC_ERR_DEVICE = 8               /* HIP runtime error */
+} bddc_status;
+
+/* Library-wide options.  Zero-initialize and set what you need. */
+typedef struct {
+  int device;                        /* HIP device ordinal */
+  void *hip_stream;                  /* hipStream_t to run on; NULL: library stream */
+  int factor_precision;              /* 64 (default, 0 means 64) or 32: substructure
+                                        factors and local solves in FP32, PCG,
+                                        averaging, coarse problem in FP64 */
+  /* optional device allocator (e.g. a framework's caching allocator);
+     NULL: hipMalloc / hipFree */
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *alloc_user;
+} bddc_options;
+
+/* Q1 hexahedral mesh (Sec. 2: substructure matrices are subassembled from
+   element matrices).  Host pointers. */
+typedef struct {
+  int kind;                  /* 0: scalar Poisson (1 dof/node), 1: elasticity (3) */
+  int64_t n_nodes;
+  const double *xyz;         /* n_nodes x 3, row-major */
+  int64_t n_elems;
+  const int64_t *hex8;       /* n_elems x 8; nodes (0,0,0)(1,0,0)(1,1,0)(0,1,0)
+                                (0,0,1)(1,0,1)(1,1,1)(0,1,1) of the element */
+  const double *coef;        /* n_elems: conductivity k or Young's modulus E */
+  double nu;                 /* Poisson ratio (elasticity) */
+  const uint8_t *dirichlet;  /* n_nodes*dpn: 1 = dof fixed to zero */
+} bddc_mesh;
+
+/* Nonoverlapping decomposition into substructures (Sec. 2). */
+typedef struct {
+  int32_t n_sub;
+  const int32_t *elem_sub;   /* n_elems, values in [0, n_sub) */
+} bddc_partition;
+
+/* Coarse degrees of freedom (Sec. 2 and 7): corners, plus arithmetic averages
+   over edges (mode >= 1) and faces (mode >= 2). */
+typedef struct {
+  int mode;                  /* 0: c, 1: c+e, 2: c+e+f, 3: every glob dof constrained */
+  int augment_corners;       /* nonzero: add face nodes as corners until each face
+                                pair sees 1 (scalar) / 3 non-collinear (elasticity)
+                                corners in its closure (Assumptions 1 and 2) */
+  double qr_drop_tol;        /* rows of U with |U_kk| <= tol*|U_11| are dropped
+                                (Sec. 5 after eq. (T)); 0 means 1e-10 */
+} bddc_constraints;
+
+typedef struct {
+  double rtol;               /* stop when ||r_k||_2 <= rtol ||r_0||_2; 0 means 1e-8 */
+  int maxit;                 /* 0 means 1000 */
+} bddc_pcg_params;
+
+typedef struct {
+  int iters;                 /* PCG iterations (operator applications) */
+  int converged;
+  double relres;             /* ||r_k|| / ||r_0|| at exit */
+  double kappa, lmin, lmax;  /* Lanczos estimates from the CG coefficients */
+  double seconds;            /* wall time of the call */
+} bddc_pcg_info;
+
+typedef struct {
+  double omega;              /* condition number indicator (eq. (cond-ind)): the
+                                largest eigenvalue not selected, over all pairs */
+  int64_t nc;                /* rows of D after adaptation */
+  int64_t n_added;           /* adaptive face rows added by this call */
+  int64_t n_pairs;           /* face pairs solved */
+  int64_t lobpcg_iters;      /* total LOBPCG iterations over all pairs */
+  int64_t unconverged;       /* pairs whose LOBPCG did not converge */
+  double seconds;
+} bddc_adapt_info;
+
+typedef struct {
+  int64_t n_glob;            /* global dofs (Dirichlet dofs removed) */
+  int64_t n_sub;
+  int64_t n_corners, n_edges, n_faces;
+  int64_t nc;                /* rows of D = sum over globs of m_g (k_g - 1) */
+  int64_t n_coarse;          /* coarse unknowns: corner dofs + explicit averages */
+  int64_t n_iface_total;     /* sum of substructure interface sizes */
+  int64_t max_interior, max_iface;
+  double factor_flops;       /* flops of the last bddc_factor (dense, executed) */
+  double factor_seconds;
+  double apply_bytes;        /* bytes the PCG-internal apply streams per RHS */
+  double pcg_iter_bytes;     /* bytes one PCG iteration streams per RHS */
+  size_t device_bytes;       /* device memory held by the context */
+} bddc_info;
+
+bddc_status bddc_create(const bddc_options *opt, bddc_ctx **ctx);
+
+/* Build substructure matrices, interface globs, weights and constraints
+   (host), and upload the substructure matrices (device). */
+bddc_status bddc_setup(bddc_ctx *ctx, const bddc_mesh *mesh, const bddc_partition *part,
+                       const bddc_constraints *cons);
+
+/* Algorithm 1: solve the face-pair eigenproblems on the GPU and add, on every
+   face, the rows of the eigenvectors with lambda >= tau (edge parts dropped).
+   Requires a prior bddc_setup; invalidates factors. */
+bddc_status bddc_adapt(bddc_ctx *ctx, double tau, bddc_adapt_info *info);
+
+/* Factor: Dirichlet factors A_II, Schur complements, constrained local factors,
+   coarse basis and coarse factor, all substructures batched. */
+bddc_status bddc_factor(bddc_ctx *ctx);
+
+/* z = M_BDDC r (Algorithm 2) for nrhs columns.  r, z: device, n_glob x nrhs,
+   column-major with leading dimensions ldr, ldz >= n_glob. */
+bddc_status bddc_apply(bddc_ctx *ctx, int nrhs, const double *r, int64_t ldr, double *z,
+                       int64_t ldz);
+
+/* Solve R^T A R u = f by BDDC-PCG.  f, u: device, n_glob x nrhs column-major;
+   each column is an independent solve.  info may be NULL, else nrhs entries. */
+bddc_status bddc_pcg_solve(bddc_ctx *ctx, int nrhs, const double *f, int64_t ldf, double *u,
+                           int64_t ldu, const bddc_pcg_params *params, bddc_pcg_info *info);
+
+bddc_status bddc_get_info(const bddc_ctx *ctx, bddc_info *info);
+
+/* Adaptive rows of one face glob (after bddc_adapt), for inspection:
+   face index f in [0, n_faces).  Writes up to max_rows rows of n_dofs
+   entries (row-major, face dofs in ascending global order), and the face's
+   global dof ids if dofs != NULL.  Returns the counts through *rows, *n_dofs
+   and the face's two substructures through subs[2]. */
+bddc_status bddc_get_face_rows(const bddc_ctx *ctx, int64_t f, int64_t max_rows, double *out,
+                               int64_t *dofs, int64_t *rows, int64_t *n_dofs, int32_t *subs);
+
+/* Eigenvalues of the last bddc_adapt for face f, descending (up to max). */
+bddc_status bddc_get_face_eigs(const bddc_ctx *ctx, int64_t f, int64_t max, double *out,
+                               int64_t *count);
+
+/* Relative residual history ||r_k||_2 / ||r_0||_2, k = 0..iters, of the last
+   right-hand side solved by bddc_pcg_solve on this context. */
+bddc_status bddc_pcg_history(const bddc_ctx *ctx, int64_t max, double *out, int64_t *count);
+
+const char *bddc_last_error(const bddc_ctx *ctx);
+void bddc_destroy(bddc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDDC_H */

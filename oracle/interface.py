@@ -171,13 +171,16 @@ class Interface:
                 continue
             cen = xyz[cand].mean(axis=0)
             while _noncollinear_count(cpts) < need and cand:
+                # distances equal within 1e-9 (relative) count as ties, which
+                # go to the lowest node id
                 if not cpts:
                     d = ((xyz[cand] - cen) ** 2).sum(1)
-                    k = int(np.lexsort((cand, d))[0])
+                    ok = d <= d.min() * (1 + 1e-9) + 1e-300
                 else:
                     C = np.array(cpts)
                     d = np.min(((xyz[cand][:, None, :] - C[None]) ** 2).sum(2), axis=1)
-                    k = int(np.lexsort((cand, -d))[0])
+                    ok = d >= d.max() * (1 - 1e-9)
+                k = int(np.flatnonzero(ok)[0])
                 n = cand.pop(k)
                 corner_set.add(n)
                 cpts.append(xyz[n])

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import time
+
 import numpy as np
 import scipy.sparse.linalg as spla
 
@@ -33,11 +34,25 @@ class OracleBDDC:
         return self.M.apply(r)
 
     def solve(self, f=None, rtol=1e-8, maxit=1000):
+        """PCG on the reduced problem (eq. (reduced-problem)).  Vectors are
+        global, but every residual is kept exactly zero in the interiors, as
+        the Remark after Lemma 1 states it is: the interior rows of R^T A R u
+        are satisfied by the interior Dirichlet solves of the start and by the
+        discrete harmonic search directions, so they are not iterated on."""
         if f is None:
             f = self.prob.f
         t0 = time.perf_counter()
+        interior = np.flatnonzero(self.itf.mult == 1)
         u0 = self.M.harm.interior_solve(f)
-        out = pcg(lambda v: self.K @ v, f, self.M.apply, u0, rtol=rtol, maxit=maxit)
+        fr = f.copy()
+        fr[interior] = 0.0
+
+        def Aop(v):
+            q = self.K @ v
+            q[interior] = 0.0
+            return q
+
+        out = pcg(Aop, fr, self.M.apply, u0, rtol=rtol, maxit=maxit)
         out["t_solve"] = time.perf_counter() - t0
         out["Nc"] = self.cons.Nc()
         return out

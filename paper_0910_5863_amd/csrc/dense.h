@@ -1,0 +1,77 @@
+// Batched dense linear algebra on gfx950 for the per-substructure factors:
+// MFMA GEMM, left-looking blocked Cholesky, multi-right-hand-side triangular
+// solves, and a flag-synchronized blocked triangular solve for few
+// right-hand sides.  All matrices are column-major; every batch entry has its
+// own sizes and leading dimensions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <vector>
+
+namespace bddc {
+
+constexpr int NB = 64;  // block size of the blocked factorizations and solves
+
+// One batch entry: an n x n lower-triangular factor (or SPD matrix) at
+// pool + a_off with leading dimension lda, and an n x nrhs right-hand side at
+// pool + b_off with leading dimension ldb.
+struct MatDesc {
+  int64_t a_off;
+  int64_t b_off;
+  int n;
+  int nrhs;
+  int lda;
+  int ldb;
+};
+
+// General batched GEMM descriptor: C = beta C + alpha op(A) op(B),
+// op(A) is M x K, op(B) is K x N.
+struct GemmDesc {
+  int64_t a_off, b_off, c_off;
+  int M, N, K;
+  int lda, ldb, ldc;
+};
+
+template <class T>
+struct DenseOps {
+  // C = beta*C + alpha*op(A)*op(B) for every entry; lower != 0 computes only
+  // tiles that intersect the lower triangle (i >= j).
+  static hipError_t gemm(hipStream_t st, const T *A, const T *B, T *C, const GemmDesc *d_desc,
+                         int batch, int maxM, int maxN, bool transA, bool transB, T alpha,
+                         T beta, bool lower);
+  // In-place lower Cholesky of every entry's A (n x n).  status[e] is set to
+  // (column+1) of the first non-positive pivot (left untouched if none).
+  static hipError_t potrf(hipStream_t st, T *pool, const MatDesc *d_desc, const MatDesc *h_desc,
+                          int batch, int *status);
+  // B <- L^{-1} B (forward) or L^{-T} B (backward), L the lower factor at a_off.
+  static hipError_t trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc *d_desc,
+                         const MatDesc *h_desc, int batch, bool transpose);
+};
+
+// Copy the lower triangle onto the upper one (entries A at a_off, n x n).
+template <class T>
+hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn);
+
+// Few-RHS triangular solves with per-block completion flags (one launch per
+// direction).  x <- L^{-1} x (forward) or L^{-T} x (backward), nrhs <= 8,
+// x at xpool + b_off with leading dimension ldb.  work must hold
+// 1 + sum over entries of ceil(n/NB) ints; it is cleared by the call.
+struct TrsvPlan {
+  int batch = 0;
+  int total_blocks = 0;
+  int *d_order_fwd = nullptr;  // (entry, block) pairs in dependency order
+  int *d_order_bwd = nullptr;
+  int *d_flag_off = nullptr;   // first flag of every entry
+};
+
+template <class T>
+hipError_t trsv_blocked(hipStream_t st, const T *apool, T *xpool, const MatDesc *d_desc,
+                        const TrsvPlan &plan, bool transpose, int nrhs, int *work, int *err);
+
+// Host: ticket orders for entries of sizes n (forward: block index upwards,
+// backward: downwards, level by level across entries) and flag offsets.
+void make_trsv_orders(const std::vector<int> &n, std::vector<int> &fwd, std::vector<int> &bwd,
+                      std::vector<int> &flag_off, int &total);
+
+}  // namespace bddc

@@ -1,0 +1,625 @@
+// Batched dense kernels for the substructure factors (gfx950).
+//
+// GEMM tiles run on the matrix cores: v_mfma_f64_16x16x4f64 in FP64 and
+// v_mfma_f32_16x16x4f32 in FP32 (FP32 accumulate).  A work-group of 256
+// lanes (4 wave64) owns a 64x64 tile of C; each wave owns a 32x32 quadrant
+// as 2x2 MFMA blocks.  Operand tiles are staged through LDS in K-steps of 16.
+// Work-group ids are remapped so that the tiles of one batch entry stay on
+// one XCD (consecutive hardware ids are dealt round-robin to the 8 XCDs),
+// which keeps an entry's shared operand panels in one L2.
+//
+// Cholesky and multi-RHS triangular solves are left-looking and blocked with
+// NB = 64: per block column one GEMM launch (update with all previous
+// columns, large K) and one launch that factors / solves the 64x64 diagonal
+// block in LDS.  The few-RHS triangular solve used in every preconditioner
+// application is a single launch per direction: one work-group per 64-row
+// block, ordered by an atomic ticket, waiting on per-block completion flags.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "dense.h"
+
+namespace bddc {
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int NXCD = 8;
+
+template <class T>
+struct Mfma;
+// Output layout of the 16x16x4 MFMA: lane l, item t holds D[row][l % 16] with
+// row = (l / 16) + 4 t for FP64 and row = 4 (l / 16) + t for FP32 (A and B:
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] for both).
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lane, int t) { return (lane >> 4) + 4 * t; }
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lane, int t) { return 4 * (lane >> 4) + t; }
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Linear work-group id -> (entry, tile) with all tiles of one entry on the
+// same XCD when the grid is a multiple of NXCD.
+// Returns false for the padding work-groups past the last entry.
+__device__ __forceinline__ bool xcd_remap(int nwg, int tiles_per_entry, int batch, int &entry,
+                                          int &tile) {
+  int b = blockIdx.x;
+  int logical = b;
+  if ((nwg % NXCD) == 0) logical = (b % NXCD) * (nwg / NXCD) + (b / NXCD);
+  entry = logical / tiles_per_entry;
+  tile = logical % tiles_per_entry;
+  return entry < batch;
+}
+
+// C[m0:m0+64, n0:n0+64] = beta*C + alpha*op(A)*op(B), bounds-checked.
+template <class T, bool TA, bool TB>
+__device__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C,
+                          int M, int N, int K, int lda, int ldb, int ldc, T alpha, T beta, int m0,
+                          int n0) {
+  typedef typename Mfma<T>::v4 v4;
+  __shared__ T As[BK][BM + 2];
+  __shared__ T Bs[BK][BN + 2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  v4 acc[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int it = 0; it < (BM * BK) / 256; ++it) {
+      const int e = tid + it * 256;
+      int r, kk;
+      if (!TA) {
+        r = e % BM;
+        kk = e / BM;
+      } else {
+        kk = e % BK;
+        r = e / BK;
+      }
+      const int gr = m0 + r, gk = k0 + kk;
+      T v = 0;
+      if (gr < M && gk < K) v = TA ? A[gk + (int64_t)gr * lda] : A[gr + (int64_t)gk * lda];
+      As[kk][r] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < (BN * BK) / 256; ++it) {
+      const int e = tid + it * 256;
+      int c, kk;
+      if (!TB) {
+        kk = e % BK;
+        c = e / BK;
+      } else {
+        c = e % BN;
+        kk = e / BN;
+      }
+      const int gc = n0 + c, gk = k0 + kk;
+      T v = 0;
+      if (gc < N && gk < K) v = TB ? B[gc + (int64_t)gk * ldb] : B[gk + (int64_t)gc * ldb];
+      Bs[kk][c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int k = kk + (lane >> 4);
+      const int l16 = lane & 15;
+      const T a0 = As[k][wr * 32 + l16], a1 = As[k][wr * 32 + 16 + l16];
+      const T b0 = Bs[k][wc * 32 + l16], b1 = Bs[k][wc * 32 + 16 + l16];
+      acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = m0 + wr * 32 + x * 16 + Mfma<T>::row(lane, j);
+        const int col = n0 + wc * 32 + y * 16 + (lane & 15);
+        if (row < M && col < N) {
+          T *c = &C[row + (int64_t)col * ldc];
+          const T v = alpha * acc[x][y][j];
+          *c = (beta == T(0)) ? v : v + beta * (*c);
+        }
+      }
+}
+
+template <class T, bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_kernel(const T *A, const T *B, T *C,
+                                                   const GemmDesc *desc, int tm, int tn, T alpha,
+                                                   T beta, int lower, int batch) {
+  int e, t;
+  if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
+  const GemmDesc d = desc[e];
+  const int ti = t % tm, tj = t / tm;
+  const int m0 = ti * BM, n0 = tj * BN;
+  if (m0 >= d.M || n0 >= d.N) return;
+  if (lower && m0 + BM - 1 < n0) return;
+  gemm_tile<T, TA, TB>(A + d.a_off, B + d.b_off, C + d.c_off, d.M, d.N, d.K, d.lda, d.ldb, d.ldc,
+                       alpha, beta, m0, n0);
+}
+
+// --- Cholesky -------------------------------------------------------------
+
+// Left-looking update of block column k: A[kb:, kb:kb+w] -= A[kb:, :kb] A[kb:kb+w, :kb]^T
+template <class T>
+__global__ __launch_bounds__(256) void chol_update_kernel(T *pool, const MatDesc *desc, int k,
+                                                          int tm, int batch) {
+  int e, t;
+  if (!xcd_remap(gridDim.x, tm, batch, e, t)) return;
+  const MatDesc d = desc[e];
+  const int kb = k * NB;
+  if (kb >= d.n || k == 0) return;
+  const int M = d.n - kb, N = min(NB, d.n - kb), K = kb;
+  if (t * BM >= M) return;
+  T *A = pool + d.a_off;
+  gemm_tile<T, false, true>(A + kb, A + kb, A + kb + (int64_t)kb * d.lda, M, N, K, d.lda, d.lda,
+                            d.lda, T(-1), T(1), t * BM, 0);
+}
+
+// Factor the diagonal block of column k in LDS; row tiles below solve
+// X <- X L_kk^{-T}.  Every work-group of the column factors the diagonal
+// block itself (64^3/3 flops) instead of waiting for another launch.
+template <class T>
+__global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc *desc, int k,
+                                                         int tm, int *status, int batch) {
+  __shared__ T D[NB][NB + 1];
+  __shared__ T X[NB][NB + 1];
+  __shared__ int s_fail;
+  int e, t;
+  if (!xcd_remap(gridDim.x, tm, batch, e, t)) return;
+  const MatDesc d = desc[e];
+  const int kb = k * NB;
+  if (kb >= d.n) return;
+  const int w = min(NB, d.n - kb);
+  const int r0 = kb + t * NB;
+  if (r0 >= d.n) return;
+  const int nr = min(NB, d.n - r0);
+  T *A = pool + d.a_off;
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_fail = 0;
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i % NB, c = i / NB;
+    D[r][c] = (r < w && c < w && r >= c) ? A[(kb + r) + (kb + c) * lda] : T(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < w; ++c) {
+    T piv = D[c][c];
+    if (!(piv > T(0))) {
+      if (tid == 0 && s_fail == 0) s_fail = kb + c + 1;
+      piv = T(1);
+    }
+    const T lcc = sqrt(piv);
+    __syncthreads();
+    if (tid == 0) D[c][c] = lcc;
+    for (int r = c + 1 + tid; r < w; r += 256) D[r][c] /= lcc;
+    __syncthreads();
+    const int m = w - c - 1;
+    for (int i = tid; i < m * m; i += 256) {
+      const int r = c + 1 + i % m, s = c + 1 + i / m;
+      if (r >= s) D[r][s] -= D[r][c] * D[s][c];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (tid == 0 && s_fail && status) atomicCAS(&status[e], 0, s_fail);
+    for (int i = tid; i < w * w; i += 256) {
+      const int r = i % w, c = i / w;
+      if (r >= c) A[(kb + r) + (kb + c) * lda] = D[r][c];
+    }
+    return;
+  }
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i % NB, c = i / NB;
+    X[r][c] = (r < nr && c < w) ? A[(r0 + r) + (kb + c) * lda] : T(0);
+  }
+  __syncthreads();
+  // X L^T = B  ->  column by column, right-looking
+  for (int c = 0; c < w; ++c) {
+    const T inv = T(1) / D[c][c];
+    for (int r = tid; r < nr; r += 256) X[r][c] *= inv;
+    __syncthreads();
+    const int m = w - c - 1;
+    for (int i = tid; i < nr * m; i += 256) {
+      const int r = i % nr, s = c + 1 + i / nr;
+      X[r][s] -= X[r][c] * D[s][c];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < nr * w; i += 256) {
+    const int r = i % nr, c = i / nr;
+    A[(r0 + r) + (kb + c) * lda] = X[r][c];
+  }
+}
+
+// --- multi-RHS triangular solves -------------------------------------------
+
+// forward: B[kb:kb+w, :] -= L[kb:kb+w, :kb] B[:kb, :]
+// backward: B[kb:kb+w, :] -= L[kb+w:n, kb:kb+w]^T B[kb+w:n, :]
+template <class T, bool BWD>
+__global__ __launch_bounds__(256) void trsm_update_kernel(const T *apool, T *bpool,
+                                                          const MatDesc *desc, int k, int tn,
+                                                          int batch) {
+  int e, t;
+  if (!xcd_remap(gridDim.x, tn, batch, e, t)) return;
+  const MatDesc d = desc[e];
+  const int kb = k * NB;
+  if (kb >= d.n) return;
+  const int w = min(NB, d.n - kb);
+  if (t * BN >= d.nrhs) return;
+  const T *L = apool + d.a_off;
+  T *B = bpool + d.b_off;
+  if (!BWD) {
+    if (kb == 0) return;
+    gemm_tile<T, false, false>(L + kb, B, B + kb, w, d.nrhs, kb, d.lda, d.ldb, d.ldb, T(-1), T(1),
+                               0, t * BN);
+  } else {
+    const int K = d.n - kb - w;
+    if (K <= 0) return;
+    gemm_tile<T, true, false>(L + (kb + w) + (int64_t)kb * d.lda, B + kb + w, B + kb, w, d.nrhs,
+                              K, d.lda, d.ldb, d.ldb, T(-1), T(1), 0, t * BN);
+  }
+}
+
+template <class T, bool BWD>
+__global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool,
+                                                        const MatDesc *desc, int k, int tn,
+                                                        int batch) {
+  __shared__ T D[NB][NB + 1];
+  __shared__ T X[NB][NB + 1];
+  int e, t;
+  if (!xcd_remap(gridDim.x, tn, batch, e, t)) return;
+  const MatDesc d = desc[e];
+  const int kb = k * NB;
+  if (kb >= d.n) return;
+  const int w = min(NB, d.n - kb);
+  const int c0 = t * NB;
+  if (c0 >= d.nrhs) return;
+  const int nc = min(NB, d.nrhs - c0);
+  const T *L = apool + d.a_off;
+  T *B = bpool + d.b_off;
+  const int64_t lda = d.lda, ldb = d.ldb;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < w * w; i += 256) {
+    const int r = i % w, c = i / w;
+    D[r][c] = (r >= c) ? L[(kb + r) + (kb + c) * lda] : T(0);
+  }
+  for (int i = tid; i < w * nc; i += 256) {
+    const int r = i % w, c = i / w;
+    X[r][c] = B[(kb + r) + (c0 + c) * ldb];
+  }
+  __syncthreads();
+  if (!BWD) {
+    for (int r = 0; r < w; ++r) {
+      const T inv = T(1) / D[r][r];
+      for (int c = tid; c < nc; c += 256) X[r][c] *= inv;
+      __syncthreads();
+      const int m = w - r - 1;
+      for (int i = tid; i < m * nc; i += 256) {
+        const int rr = r + 1 + i % m, c = i / m;
+        X[rr][c] -= D[rr][r] * X[r][c];
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int r = w - 1; r >= 0; --r) {
+      const T inv = T(1) / D[r][r];
+      for (int c = tid; c < nc; c += 256) X[r][c] *= inv;
+      __syncthreads();
+      for (int i = tid; i < r * nc; i += 256) {
+        const int rr = i % r, c = i / r;
+        X[rr][c] -= D[r][rr] * X[r][c];
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < w * nc; i += 256) {
+    const int r = i % w, c = i / w;
+    B[(kb + r) + (c0 + c) * ldb] = X[r][c];
+  }
+}
+
+template <class T>
+__global__ void symmetrize_kernel(T *pool, const MatDesc *desc, int maxn) {
+  const MatDesc d = desc[blockIdx.y];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = d.n;
+  if (idx >= n * n) return;
+  const int r = (int)(idx % n), c = (int)(idx / n);
+  if (r < c) {
+    T *A = pool + d.a_off;
+    A[r + (int64_t)c * d.lda] = A[c + (int64_t)r * d.lda];
+  }
+}
+
+// --- few-RHS blocked triangular solve with completion flags ----------------
+
+constexpr int TRSV_MAXRHS = 8;
+
+template <class T>
+__device__ __forceinline__ T ld_coherent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_coherent(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ bool wait_flag(int *flag, int *err) {
+  // bounded spin: the block waited on holds a smaller ticket, so it is
+  // resident or done; the bound only guards against an earlier fault
+  for (long it = 0; it < (1L << 26); ++it) {
+    if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) return true;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  atomicExch(err, 1);
+  return false;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One work-group per 64-row block (entry e, block kb), taken in ticket order:
+// forward solves walk kb upwards, backward solves downwards, so every block a
+// work-group waits on belongs to a smaller ticket.
+template <class T, bool BWD>
+__global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, const MatDesc *desc,
+                                                   const int *order, const int *flag_off,
+                                                   int total, int *work, int nrhs, int *err) {
+  __shared__ int s_ticket, s_ok;
+  __shared__ T D[NB][NB + 1];
+  __shared__ T Tl[NB][NB + 1];
+  __shared__ T ys[NB][TRSV_MAXRHS];
+  __shared__ T part[4][NB][TRSV_MAXRHS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    s_ticket = atomicAdd(&work[0], 1);
+    s_ok = 1;
+  }
+  __syncthreads();
+  const int tk = s_ticket;
+  if (tk >= total) return;
+  const int e = order[2 * tk], kbk = order[2 * tk + 1];
+  const MatDesc d = desc[e];
+  const T *L = apool + d.a_off;
+  T *x = xpool + d.b_off;
+  const int64_t lda = d.lda, ldb = d.ldb;
+  const int nblk = (d.n + NB - 1) / NB;
+  const int r0 = kbk * NB, w = min(NB, d.n - r0);
+  int *flags = work + 1 + flag_off[e];
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i % NB, c = i / NB;
+    D[r][c] = (r < w && c < w && r >= c) ? L[(r0 + r) + (r0 + c) * lda] : T(0);
+  }
+  T acc[TRSV_MAXRHS];
+#pragma unroll
+  for (int q = 0; q < TRSV_MAXRHS; ++q) acc[q] = T(0);
+  const int jfirst = BWD ? nblk - 1 : 0;
+  const int jstep = BWD ? -1 : 1;
+  for (int jb = jfirst; BWD ? (jb > kbk) : (jb < kbk); jb += jstep) {
+    const int c0 = jb * NB, wc = min(NB, d.n - c0);
+    if (BWD) {
+      // L block (jb, kbk): rows c0.., columns r0..; staged for a transposed use
+      for (int i = tid; i < NB * NB; i += 256) {
+        const int r = i % NB, c = i / NB;
+        Tl[r][c] = (r < wc && c < w) ? L[(c0 + r) + (int64_t)(r0 + c) * lda] : T(0);
+      }
+    }
+    if (tid == 0 && !wait_flag(&flags[jb], err)) s_ok = 0;
+    __syncthreads();
+    for (int i = tid; i < wc * nrhs; i += 256) {
+      const int r = i % wc, q = i / wc;
+      ys[r][q] = ld_coherent(&x[(c0 + r) + q * ldb]);
+    }
+    __syncthreads();
+    if (!BWD) {
+      // acc[row] -= L[r0+row, c0+c] y[c], the wave's quarter of the columns
+      if (lane < w)
+        for (int c = wave; c < wc; c += 4) {
+          const T l = L[(r0 + lane) + (int64_t)(c0 + c) * lda];
+          for (int q = 0; q < nrhs; ++q) acc[q] -= l * ys[c][q];
+        }
+    } else {
+      // acc[col] -= L[c0+r, r0+col] x[r], the wave's quarter of the rows
+      if (lane < w)
+        for (int r = wave; r < wc; r += 4) {
+          const T l = Tl[r][lane];
+          for (int q = 0; q < nrhs; ++q) acc[q] -= l * ys[r][q];
+        }
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < nrhs; ++q) part[wave][lane][q] = acc[q];
+  __syncthreads();
+  // the diagonal block: one wave per right-hand side, values in registers
+  if (wave < nrhs) {
+    const int q = wave;
+    T v = T(0);
+    if (lane < w)
+      v = x[(r0 + lane) + q * ldb] + part[0][lane][q] + part[1][lane][q] + part[2][lane][q] +
+          part[3][lane][q];
+    if (!BWD) {
+      for (int r = 0; r < w; ++r) {
+        const T s = wave_sum((lane < r) ? D[r][lane] * v : T(0));
+        if (lane == r) v = (v - s) / D[r][r];
+      }
+    } else {
+      for (int r = w - 1; r >= 0; --r) {
+        const T s = wave_sum((lane > r && lane < w) ? D[lane][r] * v : T(0));
+        if (lane == r) v = (v - s) / D[r][r];
+      }
+    }
+    if (lane < w) st_coherent(&x[(r0 + lane) + q * ldb], v);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    __hip_atomic_store(&flags[kbk], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (!s_ok) atomicExch(err, 1);
+  }
+}
+
+__global__ void zero_ints_kernel(int *p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+}  // namespace bddc
+
+// --------------------------------------------------------------------------
+// host wrappers
+
+namespace bddc {
+
+namespace {
+inline int grid_round(int n) { return ((n + NXCD - 1) / NXCD) * NXCD; }
+}  // namespace
+
+template <class T>
+hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const GemmDesc *d_desc,
+                             int batch, int maxM, int maxN, bool transA, bool transB, T alpha,
+                             T beta, bool lower) {
+  if (batch <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
+  const int tm = (maxM + BM - 1) / BM, tn = (maxN + BN - 1) / BN;
+  const int nwg = grid_round(batch * tm * tn);
+  dim3 g(nwg), b(256);
+  if (!transA && !transB)
+    gemm_kernel<T, false, false><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+  else if (transA && !transB)
+    gemm_kernel<T, true, false><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+  else if (!transA && transB)
+    gemm_kernel<T, false, true><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+  else
+    gemm_kernel<T, true, true><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
+                              const MatDesc *h_desc, int batch, int *status) {
+  int maxn = 0;
+  for (int e = 0; e < batch; ++e) maxn = std::max(maxn, h_desc[e].n);
+  if (maxn == 0) return hipSuccess;
+  const int nblk = (maxn + NB - 1) / NB;
+  for (int k = 0; k < nblk; ++k) {
+    const int tm = nblk - k;  // row tiles of block column k (for the largest entry)
+    const int nwg = grid_round(batch * tm);
+    if (k > 0) chol_update_kernel<T><<<nwg, 256, 0, st>>>(pool, d_desc, k, tm, batch);
+    chol_panel_kernel<T><<<nwg, 256, 0, st>>>(pool, d_desc, k, tm, status, batch);
+  }
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc *d_desc,
+                             const MatDesc *h_desc, int batch, bool transpose) {
+  int maxn = 0, maxr = 0;
+  for (int e = 0; e < batch; ++e) {
+    maxn = std::max(maxn, h_desc[e].n);
+    maxr = std::max(maxr, h_desc[e].nrhs);
+  }
+  if (maxn == 0 || maxr == 0) return hipSuccess;
+  const int nblk = (maxn + NB - 1) / NB;
+  const int tn = (maxr + NB - 1) / NB;
+  const int nwg = grid_round(batch * tn);
+  if (!transpose) {
+    for (int k = 0; k < nblk; ++k) {
+      if (k > 0) trsm_update_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+      trsm_diag_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+    }
+  } else {
+    // entries of different sizes: block k of an entry is its k-th from the
+    // top; walking k downwards from the largest still visits every entry's
+    // blocks bottom-up
+    for (int k = nblk - 1; k >= 0; --k) {
+      trsm_update_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+      trsm_diag_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn) {
+  if (batch <= 0 || maxn <= 0) return hipSuccess;
+  const int64_t nn = (int64_t)maxn * maxn;
+  dim3 g((unsigned)((nn + 255) / 256), batch);
+  symmetrize_kernel<T><<<g, 256, 0, st>>>(pool, d_desc, maxn);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t trsv_blocked(hipStream_t st, const T *apool, T *xpool, const MatDesc *d_desc,
+                        const TrsvPlan &plan, bool transpose, int nrhs, int *work, int *err) {
+  if (plan.total_blocks == 0) return hipSuccess;
+  if (nrhs > TRSV_MAXRHS) return hipErrorInvalidValue;
+  const int nz = 1 + plan.total_blocks;
+  zero_ints_kernel<<<(nz + 255) / 256, 256, 0, st>>>(work, nz);
+  const int *order = transpose ? plan.d_order_bwd : plan.d_order_fwd;
+  if (!transpose)
+    trsv_kernel<T, false><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, order,
+                                                            plan.d_flag_off, plan.total_blocks,
+                                                            work, nrhs, err);
+  else
+    trsv_kernel<T, true><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, order,
+                                                           plan.d_flag_off, plan.total_blocks,
+                                                           work, nrhs, err);
+  return hipGetLastError();
+}
+
+void make_trsv_orders(const std::vector<int> &n, std::vector<int> &fwd, std::vector<int> &bwd,
+                      std::vector<int> &flag_off, int &total) {
+  const int batch = (int)n.size();
+  std::vector<int> nblk(batch);
+  int maxb = 0;
+  total = 0;
+  flag_off.resize(batch);
+  for (int e = 0; e < batch; ++e) {
+    nblk[e] = (n[e] + NB - 1) / NB;
+    flag_off[e] = total;
+    total += nblk[e];
+    maxb = std::max(maxb, nblk[e]);
+  }
+  fwd.clear();
+  bwd.clear();
+  for (int lvl = 0; lvl < maxb; ++lvl)
+    for (int e = 0; e < batch; ++e)
+      if (lvl < nblk[e]) {
+        fwd.push_back(e), fwd.push_back(lvl);
+        bwd.push_back(e), bwd.push_back(nblk[e] - 1 - lvl);
+      }
+}
+
+template struct DenseOps<double>;
+template struct DenseOps<float>;
+template hipError_t symmetrize_lower<double>(hipStream_t, double *, const MatDesc *, int, int);
+template hipError_t symmetrize_lower<float>(hipStream_t, float *, const MatDesc *, int, int);
+template hipError_t trsv_blocked<double>(hipStream_t, const double *, double *, const MatDesc *,
+                                         const TrsvPlan &, bool, int, int *, int *);
+template hipError_t trsv_blocked<float>(hipStream_t, const float *, float *, const MatDesc *,
+                                        const TrsvPlan &, bool, int, int *, int *);
+
+}  // namespace bddc

@@ -1,0 +1,116 @@
+// Device solver of one BDDC problem (see solver.hip for the formulation).
+#pragma once
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "host.h"
+
+namespace bddc {
+
+struct BddcError : std::runtime_error {
+  int code;
+  BddcError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+struct ArgError : BddcError {
+  explicit ArgError(const std::string &m) : BddcError(1, m) {}
+};
+struct StateError : BddcError {
+  explicit StateError(const std::string &m) : BddcError(2, m) {}
+};
+struct OomError : BddcError {
+  explicit OomError(const std::string &m) : BddcError(3, m) {}
+};
+struct NotSpdError : BddcError {
+  explicit NotSpdError(const std::string &m) : BddcError(4, m) {}
+};
+struct SingularCoarseError : BddcError {
+  explicit SingularCoarseError(const std::string &m) : BddcError(5, m) {}
+};
+struct NoConvergenceError : BddcError {
+  explicit NoConvergenceError(const std::string &m) : BddcError(6, m) {}
+};
+struct CornersError : BddcError {
+  explicit CornersError(const std::string &m) : BddcError(7, m) {}
+};
+struct DeviceError : BddcError {
+  explicit DeviceError(const std::string &m) : BddcError(8, m) {}
+};
+
+struct PcgResult {
+  int iters = 0;
+  bool converged = false;
+  double relres = 0, lmin = 0, lmax = 0, seconds = 0;
+  std::vector<double> alphas, betas;
+  std::vector<double> history;  // ||r_k|| / ||r_0||, k = 0..iters
+};
+
+void lanczos_extremes(const std::vector<double> &a, const std::vector<double> &b, double &lmin,
+                      double &lmax);
+
+class Solver {
+ public:
+  static constexpr int kMaxRhs = 1;
+  static constexpr int kMaxIt = 5000;
+
+  DevAlloc alloc;
+  hipStream_t stream = nullptr;
+  Layout L;
+  bool factored = false;
+  double factor_seconds = 0, factor_flops = 0;
+  std::vector<double> last_history;
+
+  ~Solver();
+  void build(const Problem &P, hipStream_t st);
+  void factor();
+  void apply_global(const double *r, double *z);
+  PcgResult pcg(const double *f, double *u, double rtol, int maxit);
+  void free_all();
+
+  // bytes streamed per PCG-internal preconditioner application and per
+  // iteration (one right-hand side), counted from the stored operands
+  double apply_bytes() const;
+  double iter_bytes() const;
+
+  // internals (public for the adaptive module)
+  void apply_gamma(const double *r, double *z);
+  void apply_gamma_condensed(const double *r, const double *vG_cond, double *z);
+  void apply_local(double *b, double *z);
+  void apply_T_vec(double *x);
+  void apply_Tt_vec(double *b);
+  void schur_gamma(const double *p, double *q);
+  void harmonic_extension(const double *zg, double *z);
+  void interior_solve(double *vI);
+  void dot(const double *a, const double *b, int64_t n, double *out);
+  void scatter_gamma(const double *zg, double *z);
+  void scatter_interior(const double *vI, double *z);
+  void scatter64(const double *src, const int64_t *idx, int64_t n, double *dst);
+  void trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, double *x, bool t, int nrhs);
+  void release(DBuf &b);
+  std::vector<DBuf *> all_buffers();
+
+  int64_t n_rows = 0, nnz = 0;
+  int n_gx = 0;
+  TrsvPlan plan_rr, plan_II, plan_c;
+  std::vector<MatDesc> h_descII, h_descRR, h_descGG, h_descC;
+
+  DBuf d_row_sub, d_row_loc, d_rowptr, d_col, d_val, d_nI, d_nG, d_nr, d_np;
+  DBuf d_offI, d_offG, d_offR, d_offP, d_offII, d_offIG, d_offGG, d_offRR, d_offRP, d_offPP;
+  DBuf d_AII, d_AIG, d_S, d_W, d_Lrr, d_Phi, d_Spi, d_Lc;
+  DBuf d_descII, d_descRR, d_descC, d_syrk, d_spi_desc, d_descGG, d_descRRvec, d_descIIvec,
+      d_descCvec;
+  DBuf d_gx, d_gx_ptr, d_trow, d_pos, d_wmat, d_gk_glob, d_gk_k, d_scr;
+  int64_t scrS_elems = 0;
+  int n_gk = 0;
+  DBuf d_ridx, d_ridx_off, d_pidx, d_pidx_off, d_rabs, d_pabs, d_pcid, d_sub_cids;
+  DBuf d_c_ptr, d_c_sub, d_c_loc, d_c_copies;
+  DBuf d_ifc_gamma, d_ifc_delta, d_gamma_ptr, d_gamma_copies, d_gamma_gdof, d_int_gdof, d_ifc_gdof;
+  DBuf d_trsv_rr_fwd, d_trsv_rr_bwd, d_trsv_rr_off, d_trsv_II_fwd, d_trsv_II_bwd, d_trsv_II_off;
+  DBuf d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, d_work_i, d_status;
+  DBuf d_vG, d_vG2, d_vR, d_vR2, d_vP, d_vI, d_vI2, d_vc;
+  DBuf d_gam_r, d_gam_z, d_gam_p, d_gam_q, d_gam_x, d_sc, d_part, d_alphas, d_betas;
+};
+
+}  // namespace bddc

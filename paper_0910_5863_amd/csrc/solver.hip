@@ -1,0 +1,1269 @@
+// BDDC on the device: factorization of every substructure (batched), the
+// preconditioner application and PCG on the reduced (interface) problem.
+//
+// Formulation.  The preconditioner is Algorithm 2 (Sec. 5).  Following the
+// Remark after Algorithm 2 the explicit (average) variables produced by the
+// change of variables are assembled like corners ("primal"), which gives the
+// same operator as the projected system with Pibar and t (the projection
+// averages the copies of every explicit variable).  Because (I - P) discards
+// interior values and the residuals of the reduced problem vanish in the
+// interiors (Remark after Lemma 1), every substructure problem is condensed
+// onto its interface with the Schur complement S_i = A_GG - A_GI A_II^-1 A_IG:
+//
+//   factor:  A_II = L L^T (Cholesky),  Y = L^-1 A_IG,  S_i = A_GG - Y^T Y,
+//            Sbar_i = T_i^T S_i T_i,   split into r (remaining) and pi
+//            (corners and explicit averages) dofs,
+//            Sbar_rr = Lr Lr^T,  Phi_i = -Sbar_rr^-1 Sbar_rpi,
+//            S_pi^i = Sbar_pipi + Sbar_pir Phi_i,  S_c = sum R_pi^T S_pi R_pi,
+//            S_c = Lc Lc^T.
+//   apply:   b = T^T (delta . r_i) ;  y_r = Sbar_rr^-1 b_r ;
+//            x_c = S_c^-1 sum R_pi^T (b_pi + Phi^T b_r) ;
+//            x_r = y_r + Phi x_pi ;  z = sum_i R_i^T delta_i T_i x_i,
+//            then (I - P): z_I = -A_II^-1 A_IG z_G per substructure.
+//   PCG:     on interface vectors with q = sum R_i^T S_i R_i p; the interior
+//            values of the solution are recovered at the end by one Dirichlet
+//            solve per substructure.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+
+#include "device.h"
+#include "solver.h"
+
+namespace bddc {
+
+#define HIPCHK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess)                                                            \
+      throw DeviceError(std::string(#x) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+void *DevAlloc::get(size_t bytes) {
+  if (bytes == 0) return nullptr;
+  void *p = nullptr;
+  if (alloc) {
+    p = alloc(bytes, user);
+    if (!p) throw OomError("device allocation of " + std::to_string(bytes) + " bytes failed");
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw OomError("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  held += bytes;
+  return p;
+}
+
+void DevAlloc::put(void *p, size_t bytes) {
+  if (!p) return;
+  if (free)
+    free(p, user);
+  else
+    (void)hipFree(p);
+  held -= bytes;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+
+namespace {
+
+constexpr int TPB = 256;
+
+// at least one block: kernels bound-check their index, so empty work is a
+// launch that returns at once instead of an invalid grid
+inline unsigned nblocks(int64_t n, int tpb = TPB) {
+  return (unsigned)std::max<int64_t>(1, (n + tpb - 1) / tpb);
+}
+
+// scatter the CSR substructure matrices into the dense blocks A_II, A_IG, A_GG
+__global__ void scatter_dense_kernel(const int *row_sub, const int *row_loc, const int64_t *rowptr,
+                                     const int *col, const double *val, int64_t nrows,
+                                     const int *nI, const int *nG, const int64_t *offII,
+                                     const int64_t *offIG, const int64_t *offGG, double *AII,
+                                     double *AIG, double *AGG) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nrows) return;
+  const int s = row_sub[g], r = row_loc[g];
+  const int ni = nI[s], ng = nG[s];
+  for (int64_t k = rowptr[g]; k < rowptr[g + 1]; ++k) {
+    const int c = col[k];
+    const double v = val[k];
+    if (r < ni && c < ni)
+      AII[offII[s] + r + (int64_t)c * ni] = v;
+    else if (r < ni && c >= ni)
+      AIG[offIG[s] + r + (int64_t)(c - ni) * ni] = v;
+    else if (r >= ni && c >= ni)
+      AGG[offGG[s] + (r - ni) + (int64_t)(c - ni) * ng] = v;
+  }
+}
+
+// S <- S T on every substructure (column pass) and S <- T^T S (row pass).
+// T = I + E_p W per constrained glob (W = rows of T at the pivots minus the
+// identity there), so a pass adds, for every glob position q_t, the pivot
+// columns (rows) weighted by W[k, t].  Pivot values are copied to scratch
+// first, so the update may overwrite them.
+__global__ void xform_copy_pivots_kernel(const double *pool, const int64_t *offGG, const int *nG,
+                                         const GlobXf *gx, int ngx, const int *pos,
+                                         const int64_t *offG, double *scr, int rows) {
+  const int g = blockIdx.y;
+  if (g >= ngx) return;
+  const GlobXf x = gx[g];
+  const int s = x.sub, ng = nG[s];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ng) return;
+  const double *S = pool + offGG[s];
+  for (int k = 0; k < x.m; ++k) {
+    const int p = pos[x.piv_off + k] - (int)offG[s];
+    // rows == 0: column p (entry i); rows == 1: row p (entry i)
+    scr[x.scrS_off + (int64_t)k * ng + i] = rows ? S[p + (int64_t)i * ng] : S[i + (int64_t)p * ng];
+  }
+}
+
+__global__ void xform_cols_kernel(double *pool, const int64_t *offGG, const int *nG,
+                                  const GlobXf *gx, const int *gx_ptr, const double *wmat,
+                                  const int *pos, const int64_t *offG, const double *scr) {
+  const int s = blockIdx.y;
+  const int ng = nG[s];
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= ng) return;
+  double *S = pool + offGG[s];
+  const int base = (int)offG[s];
+  for (int g = gx_ptr[s]; g < gx_ptr[s + 1]; ++g) {
+    const GlobXf x = gx[g];
+    for (int t = 0; t < x.ng; ++t) {
+      const int q = pos[x.pos_off + t] - base;
+      double acc = 0;
+      for (int k = 0; k < x.m; ++k)
+        acc += wmat[x.trow_off + (int64_t)k * x.ng + t] * scr[x.scrS_off + (int64_t)k * ng + row];
+      S[row + (int64_t)q * ng] += acc;
+    }
+  }
+}
+
+__global__ void xform_rows_kernel(double *pool, const int64_t *offGG, const int *nG,
+                                  const GlobXf *gx, const int *gx_ptr, const double *wmat,
+                                  const int *pos, const int64_t *offG, const double *scr) {
+  const int s = blockIdx.y;
+  const int ng = nG[s];
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (col >= ng) return;
+  double *S = pool + offGG[s] + (int64_t)col * ng;
+  const int base = (int)offG[s];
+  for (int g = gx_ptr[s]; g < gx_ptr[s + 1]; ++g) {
+    const GlobXf x = gx[g];
+    for (int t = lane; t < x.ng; t += 64) {
+      const int q = pos[x.pos_off + t] - base;
+      double acc = 0;
+      for (int k = 0; k < x.m; ++k)
+        acc += wmat[x.trow_off + (int64_t)k * x.ng + t] * scr[x.scrS_off + (int64_t)k * ng + col];
+      S[q] += acc;
+    }
+  }
+}
+
+// gather a sub-block: dst[a + b*ldd] = src[idx_r[a] + idx_c[b]*lds] per entry
+__global__ void gather_block_kernel(const double *src, const int64_t *src_off, const int *lds,
+                                    double *dst, const int64_t *dst_off, const int *ldd,
+                                    const int *ridx, const int64_t *ridx_off, const int *nrows,
+                                    const int *cidx, const int64_t *cidx_off, const int *ncols,
+                                    double scale) {
+  const int s = blockIdx.y;
+  const int64_t nr = nrows[s], nc = ncols[s];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr * nc) return;
+  const int a = (int)(i % nr), b = (int)(i / nr);
+  const int ra = ridx[ridx_off[s] + a], cb = cidx[cidx_off[s] + b];
+  dst[dst_off[s] + a + (int64_t)b * ldd[s]] = scale * src[src_off[s] + ra + (int64_t)cb * lds[s]];
+}
+
+// coarse matrix: S_c[a,b] = sum over substructures holding both a and b
+__global__ void coarse_assemble_kernel(int nc, const int *c_ptr, const int *c_sub,
+                                       const int *c_loc, const int64_t *offPP, const int *np,
+                                       const double *Spi, const int *sub_cids,
+                                       const int64_t *offP, double *Sc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nc * nc) return;
+  const int a = (int)(i % nc), b = (int)(i / nc);
+  double acc = 0;
+  for (int k = c_ptr[a]; k < c_ptr[a + 1]; ++k) {
+    const int s = c_sub[k], la = c_loc[k];
+    // local index of b in substructure s: coarse ids of s are ascending
+    const int *ids = sub_cids + offP[s];
+    int lo = 0, hi = np[s];
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (ids[mid] < b)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo < np[s] && ids[lo] == b) acc += Spi[offPP[s] + la + (int64_t)lo * np[s]];
+  }
+  Sc[a + (int64_t)b * nc] = acc;
+}
+
+// dst[i] = src[idx[i]] * (w ? w[i] : 1), multi-column
+__global__ void gather_kernel(const double *src, int64_t lds, const int64_t *idx,
+                              const double *w, double *dst, int64_t ldd, int64_t n, int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = idx[i];
+  const double ww = w ? w[i] : 1.0;
+  for (int q = 0; q < nrhs; ++q) dst[i + q * ldd] = ww * src[j + q * lds];
+}
+
+__global__ void gather32_kernel(const double *src, int64_t lds, const int *idx, double *dst,
+                                int64_t ldd, int64_t n, int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = idx[i];
+  for (int q = 0; q < nrhs; ++q) dst[i + q * ldd] = src[j + q * lds];
+}
+
+__global__ void scatter32_kernel(const double *src, int64_t lds, const int *idx, double *dst,
+                                 int64_t ldd, int64_t n, int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = idx[i];
+  for (int q = 0; q < nrhs; ++q) dst[j + q * ldd] = src[i + q * lds];
+}
+
+// dst[g] = sum over the copies of g (fixed order) of w[c] * src[c]
+__global__ void reduce_copies_kernel(const double *src, int64_t lds, const int *ptr,
+                                     const int64_t *copies, const double *w, double *dst,
+                                     int64_t ldd, int64_t n, int nrhs, double alpha, double beta) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  for (int q = 0; q < nrhs; ++q) {
+    double acc = 0;
+    for (int k = ptr[g]; k < ptr[g + 1]; ++k) {
+      const int64_t c = copies[k];
+      acc += (w ? w[c] : 1.0) * src[c + q * lds];
+    }
+    double *o = &dst[g + q * ldd];
+    *o = (beta == 0.0) ? alpha * acc : alpha * acc + beta * (*o);
+  }
+}
+
+// b <- T^T b on every constrained glob: pivot values to scratch, then one
+// wave per (substructure, glob) adds W^T v to the glob positions.
+__global__ void vec_pivots_kernel(const double *b, const GlobXf *gx, int ngx, const int *pos,
+                                  double *scr) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngx) return;
+  const GlobXf x = gx[g];
+  for (int k = 0; k < x.m; ++k) scr[x.scr_off + k] = b[pos[x.piv_off + k]];
+}
+
+__global__ void apply_Tt_kernel(double *b, const GlobXf *gx, int ngx, const double *wmat,
+                                const int *pos, const double *scr) {
+  const int g = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= ngx) return;
+  const GlobXf x = gx[g];
+  for (int t = lane; t < x.ng; t += 64) {
+    double acc = 0;
+    for (int k = 0; k < x.m; ++k) acc += wmat[x.trow_off + (int64_t)k * x.ng + t] * scr[x.scr_off + k];
+    b[pos[x.pos_off + t]] += acc;
+  }
+}
+
+// x <- T x: new pivot values sum_t trow[k, t] x[q_t] into scratch (one wave
+// per (glob, k)), then stored at the pivots.
+__global__ void apply_T_dots_kernel(const double *xv, const GlobXf *gx, const int *gk_glob,
+                                    const int *gk_k, int ngk, const double *trow, const int *pos,
+                                    double *scr) {
+  const int w = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= ngk) return;
+  const GlobXf x = gx[gk_glob[w]];
+  const int k = gk_k[w];
+  double acc = 0;
+  for (int t = lane; t < x.ng; t += 64) acc += trow[x.trow_off + (int64_t)k * x.ng + t] * xv[pos[x.pos_off + t]];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) scr[x.scr_off + k] = acc;
+}
+
+__global__ void apply_T_store_kernel(double *xv, const GlobXf *gx, const int *gk_glob,
+                                     const int *gk_k, int ngk, const int *pos, const double *scr) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= ngk) return;
+  const GlobXf x = gx[gk_glob[w]];
+  const int k = gk_k[w];
+  xv[pos[x.piv_off + k]] = scr[x.scr_off + k];
+}
+
+// batched GEMV on column-major blocks: y_i = alpha op(A_i) x_i + beta y_i.
+// trans: y[j] = sum_r A[r, j] x[r] (a wave per output, coalesced columns);
+// notrans: y[r] = sum_j A[r, j] x[j] (a thread per output row).
+__global__ void gemv_t_kernel(const double *apool, const int64_t *aoff, const int *rows,
+                              const int *cols, const double *x, const int64_t *xoff,
+                              double *y, const int64_t *yoff, double alpha, double beta) {
+  const int s = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (j >= cols[s]) return;
+  const int m = rows[s];
+  const double *A = apool + aoff[s] + (int64_t)j * m;
+  const double *xx = x + xoff[s];
+  double acc = 0;
+  for (int r = lane; r < m; r += 64) acc += A[r] * xx[r];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    double *o = y + yoff[s] + j;
+    *o = (beta == 0.0) ? alpha * acc : alpha * acc + beta * (*o);
+  }
+}
+
+__global__ void gemv_n_kernel(const double *apool, const int64_t *aoff, const int *rows,
+                              const int *cols, const double *x, const int64_t *xoff, double *y,
+                              const int64_t *yoff, double alpha, double beta) {
+  const int s = blockIdx.y;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = rows[s];
+  if (r >= m) return;
+  const int n = cols[s];
+  const double *A = apool + aoff[s];
+  const double *xx = x + xoff[s];
+  double acc = 0;
+  for (int j = 0; j < n; ++j) acc += A[r + (int64_t)j * m] * xx[j];
+  double *o = y + yoff[s] + r;
+  *o = (beta == 0.0) ? alpha * acc : alpha * acc + beta * (*o);
+}
+
+// per-substructure CSR products between interior and interface parts:
+// mode 0: y_G = A_GI x_I  (rows >= nI, cols < nI)
+// mode 1: y_I = A_IG x_G  (rows < nI, cols >= nI)
+__global__ void spmv_coupling_kernel(const int *row_sub, const int *row_loc, const int64_t *rowptr,
+                                     const int *col, const double *val, int64_t nrows,
+                                     const int *nI, const int64_t *offI, const int64_t *offG,
+                                     const double *xI, const double *xG, double *yI, double *yG,
+                                     int mode, int nrhs, int64_t ldI, int64_t ldG) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nrows) return;
+  const int s = row_sub[g], r = row_loc[g];
+  const int ni = nI[s];
+  if (mode == 0 && r < ni) return;
+  if (mode == 1 && r >= ni) return;
+  for (int q = 0; q < nrhs; ++q) {
+    double acc = 0;
+    for (int64_t k = rowptr[g]; k < rowptr[g + 1]; ++k) {
+      const int c = col[k];
+      if (mode == 0 && c < ni) acc += val[k] * xI[offI[s] + c + q * ldI];
+      if (mode == 1 && c >= ni) acc += val[k] * xG[offG[s] + (c - ni) + q * ldG];
+    }
+    if (mode == 0)
+      yG[offG[s] + (r - ni) + q * ldG] = acc;
+    else
+      yI[offI[s] + r + q * ldI] = acc;
+  }
+}
+
+__global__ void axpby_kernel(double *y, const double *x, double a, double b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = b * y[i] + a * x[i];
+}
+
+// deterministic dot products: stage 1 partial sums per block (fixed order)
+constexpr int DOT_BLOCKS = 1024;
+__global__ void dot_partial_kernel(const double *a, const double *b, int64_t n, double *part) {
+  __shared__ double sh[TPB];
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += a[i] * b[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = TPB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void dot_final_kernel(const double *part, int nb, double *out) {
+  __shared__ double sh[TPB];
+  double acc = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = TPB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// PCG scalar updates on the device.  sc: [0] rz, [1] pq, [2] rr, [3] alpha,
+// [4] beta, [5] rz_new
+__global__ void pcg_alpha_kernel(double *sc, double *alphas, int it) {
+  const double a = sc[0] / sc[1];
+  sc[3] = a;
+  alphas[it] = a;
+}
+__global__ void pcg_beta_kernel(double *sc, double *betas, int it) {
+  const double b = sc[5] / sc[0];
+  sc[4] = b;
+  betas[it] = b;
+  sc[0] = sc[5];
+}
+// x += alpha p ; r -= alpha q
+__global__ void pcg_update_kernel(double *x, double *r, const double *p, const double *q,
+                                  const double *sc, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = sc[3];
+  x[i] += a * p[i];
+  r[i] -= a * q[i];
+}
+// p = z + beta p
+__global__ void pcg_dir_kernel(double *p, const double *z, const double *sc, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = z[i] + sc[4] * p[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+
+template <class T>
+static DBuf upload(DevAlloc &A, hipStream_t st, const std::vector<T> &v) {
+  DBuf b;
+  b.bytes = std::max<size_t>(v.size() * sizeof(T), 1);
+  b.p = A.get(b.bytes);
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return b;
+}
+
+static DBuf alloc0(DevAlloc &A, hipStream_t st, size_t bytes) {
+  DBuf b;
+  b.bytes = std::max<size_t>(bytes, 8);
+  b.p = A.get(b.bytes);
+  HIPCHK(hipMemsetAsync(b.p, 0, b.bytes, st));
+  return b;
+}
+
+void Solver::release(DBuf &b) {
+  if (b.p) alloc.put(b.p, b.bytes);
+  b = DBuf();
+}
+
+void Solver::free_all() {
+  for (DBuf *b : all_buffers()) release(*b);
+}
+
+Solver::~Solver() { free_all(); }
+
+std::vector<DBuf *> Solver::all_buffers() {
+  return {&d_row_sub, &d_row_loc, &d_rowptr, &d_col, &d_val, &d_nI, &d_nG, &d_nr, &d_np,
+          &d_offI, &d_offG, &d_offR, &d_offP, &d_offII, &d_offIG, &d_offGG, &d_offRR, &d_offRP,
+          &d_offPP, &d_AII, &d_AIG, &d_S, &d_W, &d_Lrr, &d_Phi, &d_Spi, &d_Lc, &d_descII,
+          &d_descRR, &d_descC, &d_syrk, &d_spi_desc, &d_descGG, &d_gx, &d_gx_ptr, &d_trow,
+          &d_pos, &d_ridx, &d_ridx_off, &d_pidx, &d_pidx_off, &d_rabs, &d_pabs, &d_pcid,
+          &d_sub_cids, &d_c_ptr, &d_c_sub, &d_c_loc, &d_c_copies, &d_ifc_gamma, &d_ifc_delta,
+          &d_gamma_ptr, &d_gamma_copies, &d_gamma_gdof, &d_int_gdof, &d_ifc_gdof,
+          &d_trsv_rr_fwd, &d_trsv_rr_bwd, &d_trsv_rr_off, &d_trsv_II_fwd, &d_trsv_II_bwd,
+          &d_trsv_II_off, &d_trsv_c_fwd, &d_trsv_c_bwd, &d_trsv_c_off, &d_work_i, &d_status,
+          &d_vG, &d_vG2, &d_vR, &d_vR2, &d_vP, &d_vI, &d_vI2, &d_vc, &d_gam_r, &d_gam_z,
+          &d_gam_p, &d_gam_q, &d_gam_x, &d_sc, &d_part, &d_alphas, &d_betas, &d_descRRvec,
+          &d_descIIvec, &d_descCvec};
+}
+
+// Host analysis after bddc_setup / adapt: layout, index maps, uploads of the
+// substructure matrices.  Matrices and vectors are (re)allocated.
+void Solver::build(const Problem &P, hipStream_t st) {
+  free_all();
+  stream = st;
+  const int ns = (int)P.subs.size();
+  L = Layout();
+  L.nsub = ns;
+  L.n_glob = P.n_glob;
+  L.nI.resize(ns);
+  L.nG.resize(ns);
+  L.nr.resize(ns);
+  L.np.resize(ns);
+  // coarse numbering: corner dofs first (ascending), then explicit variables
+  // glob by glob
+  std::vector<int64_t> corner_cid(P.n_glob, -1);
+  int64_t nc = 0;
+  for (int64_t g : P.corner_gdofs) corner_cid[g] = nc++;
+  std::vector<int64_t> glob_cid0(P.globs.size(), -1);
+  for (size_t gi = 0; gi < P.globs.size(); ++gi) {
+    glob_cid0[gi] = nc;
+    nc += P.cov[gi].m;
+  }
+  L.n_coarse = nc;
+  // per substructure pi dofs: (interface position, coarse id), sorted by coarse id
+  std::vector<std::vector<std::pair<int, int>>> pis(ns);
+  std::vector<std::vector<int>> rpos(ns);
+  for (int s = 0; s < ns; ++s) {
+    const Sub &S = P.subs[s];
+    auto &pi = pis[s];
+    for (size_t k = 0; k < S.corner_pos.size(); ++k)
+      pi.push_back({S.corner_pos[k], (int)corner_cid[S.corner_gdof[k]]});
+    for (size_t a = 0; a < S.glob_ids.size(); ++a) {
+      const int gi = S.glob_ids[a];
+      const GlobCov &c = P.cov[gi];
+      for (int k = 0; k < c.m; ++k) pi.push_back({S.glob_pos[a][c.perm[k]], (int)(glob_cid0[gi] + k)});
+    }
+    std::sort(pi.begin(), pi.end(), [](auto &x, auto &y) { return x.second < y.second; });
+    std::vector<char> isp(S.nG, 0);
+    for (auto &x : pi) isp[x.first] = 1;
+    for (int t = 0; t < S.nG; ++t)
+      if (!isp[t]) rpos[s].push_back(t);
+    L.nI[s] = S.nI;
+    L.nG[s] = S.nG;
+    L.np[s] = (int)pi.size();
+    L.nr[s] = (int)rpos[s].size();
+  }
+  auto offsets = [&](const std::vector<int> &a, const std::vector<int> &b,
+                     std::vector<int64_t> &off) {
+    off.resize(ns);
+    int64_t o = 0;
+    for (int s = 0; s < ns; ++s) {
+      off[s] = o;
+      o += (int64_t)a[s] * (b.empty() ? 1 : b[s]);
+    }
+    return o;
+  };
+  L.sumI = offsets(L.nI, {}, L.offI);
+  L.sumG = offsets(L.nG, {}, L.offG);
+  L.sumR = offsets(L.nr, {}, L.offR);
+  L.sumP = offsets(L.np, {}, L.offP);
+  L.sII = offsets(L.nI, L.nI, L.offII);
+  L.sIG = offsets(L.nI, L.nG, L.offIG);
+  L.sGG = offsets(L.nG, L.nG, L.offGG);
+  L.sRR = offsets(L.nr, L.nr, L.offRR);
+  L.sRP = offsets(L.nr, L.np, L.offRP);
+  L.sPP = offsets(L.np, L.np, L.offPP);
+  for (int s = 0; s < ns; ++s) {
+    L.max_nI = std::max(L.max_nI, L.nI[s]);
+    L.max_nG = std::max(L.max_nG, L.nG[s]);
+    L.max_nr = std::max(L.max_nr, L.nr[s]);
+    L.max_np = std::max(L.max_np, L.np[s]);
+  }
+  // CSR stack
+  std::vector<int> row_sub, row_loc, col;
+  std::vector<int64_t> rowptr(1, 0);
+  std::vector<double> val;
+  for (int s = 0; s < ns; ++s) {
+    const Csr &A = P.subs[s].A;
+    for (int r = 0; r < A.n; ++r) {
+      row_sub.push_back(s);
+      row_loc.push_back(r);
+      rowptr.push_back(rowptr.back() + (A.ptr[r + 1] - A.ptr[r]));
+    }
+    col.insert(col.end(), A.col.begin(), A.col.end());
+    val.insert(val.end(), A.val.begin(), A.val.end());
+  }
+  n_rows = (int64_t)row_sub.size();
+  nnz = (int64_t)val.size();
+  d_row_sub = upload(alloc, st, row_sub);
+  d_row_loc = upload(alloc, st, row_loc);
+  d_rowptr = upload(alloc, st, rowptr);
+  d_col = upload(alloc, st, col);
+  d_val = upload(alloc, st, val);
+  d_nI = upload(alloc, st, L.nI);
+  d_nG = upload(alloc, st, L.nG);
+  d_nr = upload(alloc, st, L.nr);
+  d_np = upload(alloc, st, L.np);
+  d_offI = upload(alloc, st, L.offI);
+  d_offG = upload(alloc, st, L.offG);
+  d_offR = upload(alloc, st, L.offR);
+  d_offP = upload(alloc, st, L.offP);
+  d_offII = upload(alloc, st, L.offII);
+  d_offIG = upload(alloc, st, L.offIG);
+  d_offGG = upload(alloc, st, L.offGG);
+  d_offRR = upload(alloc, st, L.offRR);
+  d_offRP = upload(alloc, st, L.offRP);
+  d_offPP = upload(alloc, st, L.offPP);
+  // interface maps: global interface dof numbering gamma (ascending global)
+  std::vector<int64_t> gam_of(P.n_glob, -1);
+  std::vector<int> mult(P.n_glob, 0);
+  for (int s = 0; s < ns; ++s)
+    for (int t = 0; t < L.nG[s]; ++t) mult[P.subs[s].gdof[L.nI[s] + t]]++;
+  std::vector<int64_t> gamma_gdof;
+  for (int64_t g = 0; g < P.n_glob; ++g)
+    if (mult[g] > 0) {
+      gam_of[g] = (int64_t)gamma_gdof.size();
+      gamma_gdof.push_back(g);
+    }
+  L.n_gamma = (int64_t)gamma_gdof.size();
+  std::vector<int64_t> ifc_gamma(L.sumG), ifc_gdof(L.sumG), int_gdof(L.sumI);
+  std::vector<double> ifc_delta(L.sumG);
+  std::vector<int> gptr(L.n_gamma + 1, 0);
+  for (int s = 0; s < ns; ++s)
+    for (int t = 0; t < L.nG[s]; ++t) {
+      const int64_t g = P.subs[s].gdof[L.nI[s] + t];
+      ifc_gamma[L.offG[s] + t] = gam_of[g];
+      ifc_gdof[L.offG[s] + t] = g;
+      ifc_delta[L.offG[s] + t] = P.subs[s].delta[t];
+      gptr[gam_of[g] + 1]++;
+    }
+  for (int64_t k = 0; k < L.n_gamma; ++k) gptr[k + 1] += gptr[k];
+  std::vector<int64_t> gcopies(gptr[L.n_gamma]);
+  {
+    std::vector<int> fill(gptr.begin(), gptr.end() - 1);
+    for (int s = 0; s < ns; ++s)  // substructures ascending: fixed summation order
+      for (int t = 0; t < L.nG[s]; ++t) gcopies[fill[ifc_gamma[L.offG[s] + t]]++] = L.offG[s] + t;
+  }
+  for (int s = 0; s < ns; ++s)
+    for (int t = 0; t < L.nI[s]; ++t) int_gdof[L.offI[s] + t] = P.subs[s].gdof[t];
+  d_ifc_gamma = upload(alloc, st, ifc_gamma);
+  d_ifc_gdof = upload(alloc, st, ifc_gdof);
+  d_ifc_delta = upload(alloc, st, ifc_delta);
+  d_gamma_ptr = upload(alloc, st, gptr);
+  d_gamma_copies = upload(alloc, st, gcopies);
+  d_gamma_gdof = upload(alloc, st, gamma_gdof);
+  d_int_gdof = upload(alloc, st, int_gdof);
+  // transforms
+  std::vector<GlobXf> gx;
+  std::vector<int> gx_ptr(ns + 1, 0), gk_glob, gk_k;
+  std::vector<double> trow, wmat;
+  std::vector<int> pos;
+  int64_t scr = 0, scrS = 0;
+  for (int s = 0; s < ns; ++s) {
+    const Sub &S = P.subs[s];
+    for (size_t a = 0; a < S.glob_ids.size(); ++a) {
+      const int gi = S.glob_ids[a];
+      const GlobCov &c = P.cov[gi];
+      if (c.m == 0) continue;
+      GlobXf x;
+      x.sub = s;
+      x.m = c.m;
+      x.ng = c.n;
+      x.trow_off = (int64_t)trow.size();
+      trow.insert(trow.end(), c.trow.begin(), c.trow.end());
+      for (int k = 0; k < c.m; ++k)
+        for (int t = 0; t < c.n; ++t)
+          wmat.push_back(c.trow[(size_t)k * c.n + t] - (t == c.perm[k] ? 1.0 : 0.0));
+      x.pos_off = (int64_t)pos.size();
+      for (int t = 0; t < c.n; ++t) pos.push_back((int)(L.offG[s] + S.glob_pos[a][t]));
+      x.piv_off = (int64_t)pos.size();
+      for (int k = 0; k < c.m; ++k) pos.push_back((int)(L.offG[s] + S.glob_pos[a][c.perm[k]]));
+      x.scr_off = scr;
+      scr += c.m;
+      x.scrS_off = scrS;
+      scrS += (int64_t)c.m * S.nG;
+      for (int k = 0; k < c.m; ++k) gk_glob.push_back((int)gx.size()), gk_k.push_back(k);
+      gx.push_back(x);
+      gx_ptr[s + 1]++;
+    }
+  }
+  for (int s = 0; s < ns; ++s) gx_ptr[s + 1] += gx_ptr[s];
+  n_gx = (int)gx.size();
+  n_gk = (int)gk_glob.size();
+  d_gx = upload(alloc, st, gx);
+  d_gx_ptr = upload(alloc, st, gx_ptr);
+  d_trow = upload(alloc, st, trow);
+  d_wmat = upload(alloc, st, wmat);
+  d_pos = upload(alloc, st, pos);
+  d_gk_glob = upload(alloc, st, gk_glob);
+  d_gk_k = upload(alloc, st, gk_k);
+  d_scr = alloc0(alloc, st, sizeof(double) * (size_t)std::max<int64_t>(scr, 1));
+  scrS_elems = scrS;
+  // r / pi index maps (local interface positions and absolute positions)
+  std::vector<int> ridx, pidx, rabs, pabs, pcid, sub_cids;
+  std::vector<int64_t> ridx_off(ns), pidx_off(ns);
+  for (int s = 0; s < ns; ++s) {
+    ridx_off[s] = (int64_t)ridx.size();
+    for (int t : rpos[s]) ridx.push_back(t), rabs.push_back((int)(L.offG[s] + t));
+    pidx_off[s] = (int64_t)pidx.size();
+    for (auto &x : pis[s]) {
+      pidx.push_back(x.first);
+      pabs.push_back((int)(L.offG[s] + x.first));
+      pcid.push_back(x.second);
+      sub_cids.push_back(x.second);
+    }
+  }
+  d_ridx = upload(alloc, st, ridx);
+  d_ridx_off = upload(alloc, st, ridx_off);
+  d_pidx = upload(alloc, st, pidx);
+  d_pidx_off = upload(alloc, st, pidx_off);
+  d_rabs = upload(alloc, st, rabs);
+  d_pabs = upload(alloc, st, pabs);
+  d_pcid = upload(alloc, st, pcid);
+  d_sub_cids = upload(alloc, st, sub_cids);
+  // coarse copies
+  std::vector<int> cptr(nc + 1, 0), csub, cloc;
+  std::vector<int64_t> ccopies;
+  for (int s = 0; s < ns; ++s)
+    for (auto &x : pis[s]) cptr[x.second + 1]++;
+  for (int64_t a = 0; a < nc; ++a) cptr[a + 1] += cptr[a];
+  csub.resize(cptr[nc]);
+  cloc.resize(cptr[nc]);
+  ccopies.resize(cptr[nc]);
+  {
+    std::vector<int> fill(cptr.begin(), cptr.end() - 1);
+    for (int s = 0; s < ns; ++s)
+      for (int l = 0; l < L.np[s]; ++l) {
+        const int a = pis[s][l].second;
+        const int k = fill[a]++;
+        csub[k] = s;
+        cloc[k] = l;
+        ccopies[k] = L.offP[s] + l;
+      }
+  }
+  d_c_ptr = upload(alloc, st, cptr);
+  d_c_sub = upload(alloc, st, csub);
+  d_c_loc = upload(alloc, st, cloc);
+  d_c_copies = upload(alloc, st, ccopies);
+  // descriptors
+  std::vector<MatDesc> dII(ns), dRR(ns), dGG(ns), dIIv(ns), dRRv(ns);
+  std::vector<GemmDesc> syrk(ns), spi(ns);
+  for (int s = 0; s < ns; ++s) {
+    dII[s] = MatDesc{L.offII[s], L.offIG[s], L.nI[s], L.nG[s], std::max(1, L.nI[s]), std::max(1, L.nI[s])};
+    dRR[s] = MatDesc{L.offRR[s], L.offRP[s], L.nr[s], L.np[s], std::max(1, L.nr[s]), std::max(1, L.nr[s])};
+    dGG[s] = MatDesc{L.offGG[s], 0, L.nG[s], 0, std::max(1, L.nG[s]), 1};
+    dIIv[s] = MatDesc{L.offII[s], L.offI[s], L.nI[s], 1, std::max(1, L.nI[s]), (int)L.sumI};
+    dRRv[s] = MatDesc{L.offRR[s], L.offR[s], L.nr[s], 1, std::max(1, L.nr[s]), (int)L.sumR};
+    syrk[s] = GemmDesc{L.offIG[s], L.offIG[s], L.offGG[s], L.nG[s], L.nG[s], L.nI[s],
+                       std::max(1, L.nI[s]), std::max(1, L.nI[s]), std::max(1, L.nG[s])};
+    spi[s] = GemmDesc{L.offRP[s], L.offRP[s], L.offPP[s], L.np[s], L.np[s], L.nr[s],
+                      std::max(1, L.nr[s]), std::max(1, L.nr[s]), std::max(1, L.np[s])};
+  }
+  h_descII = dII;
+  h_descRR = dRR;
+  h_descGG = dGG;
+  d_descII = upload(alloc, st, dII);
+  d_descRR = upload(alloc, st, dRR);
+  d_descGG = upload(alloc, st, dGG);
+  d_descIIvec = upload(alloc, st, dIIv);
+  d_descRRvec = upload(alloc, st, dRRv);
+  d_syrk = upload(alloc, st, syrk);
+  d_spi_desc = upload(alloc, st, spi);
+  MatDesc dc{0, 0, (int)nc, 0, (int)std::max<int64_t>(1, nc), (int)std::max<int64_t>(1, nc)};
+  h_descC = {dc};
+  d_descC = upload(alloc, st, h_descC);
+  MatDesc dcv{0, 0, (int)nc, 1, (int)std::max<int64_t>(1, nc), (int)std::max<int64_t>(1, nc)};
+  d_descCvec = upload(alloc, st, std::vector<MatDesc>{dcv});
+  // trsv plans
+  auto plan = [&](const std::vector<int> &n, DBuf &f, DBuf &b, DBuf &o, TrsvPlan &p) {
+    std::vector<int> fw, bw, off;
+    int total;
+    make_trsv_orders(n, fw, bw, off, total);
+    f = upload(alloc, st, fw);
+    b = upload(alloc, st, bw);
+    o = upload(alloc, st, off);
+    p.batch = (int)n.size();
+    p.total_blocks = total;
+    p.d_order_fwd = f.as<int>();
+    p.d_order_bwd = b.as<int>();
+    p.d_flag_off = o.as<int>();
+    return total;
+  };
+  int w1 = plan(L.nr, d_trsv_rr_fwd, d_trsv_rr_bwd, d_trsv_rr_off, plan_rr);
+  int w2 = plan(L.nI, d_trsv_II_fwd, d_trsv_II_bwd, d_trsv_II_off, plan_II);
+  int w3 = plan({(int)nc}, d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, plan_c);
+  d_work_i = alloc0(alloc, st, sizeof(int) * (size_t)(4 + std::max({w1, w2, w3})));
+  d_status = alloc0(alloc, st, sizeof(int) * (size_t)(ns + 2));
+  // matrices
+  d_AII = alloc0(alloc, st, sizeof(double) * (size_t)L.sII);
+  d_AIG = alloc0(alloc, st, sizeof(double) * (size_t)L.sIG);
+  d_S = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
+  d_W = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
+  d_Lrr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
+  d_Phi = alloc0(alloc, st, sizeof(double) * (size_t)L.sRP);
+  d_Spi = alloc0(alloc, st, sizeof(double) * (size_t)L.sPP);
+  d_Lc = alloc0(alloc, st, sizeof(double) * (size_t)(nc * nc));
+  // work vectors (nrhs up to kMaxRhs)
+  const size_t R = kMaxRhs;
+  d_vG = alloc0(alloc, st, sizeof(double) * L.sumG * R);
+  d_vG2 = alloc0(alloc, st, sizeof(double) * L.sumG * R);
+  d_vR = alloc0(alloc, st, sizeof(double) * L.sumR * R);
+  d_vR2 = alloc0(alloc, st, sizeof(double) * L.sumR * R);
+  d_vP = alloc0(alloc, st, sizeof(double) * L.sumP * R);
+  d_vI = alloc0(alloc, st, sizeof(double) * L.sumI * R);
+  d_vI2 = alloc0(alloc, st, sizeof(double) * L.sumI * R);
+  d_vc = alloc0(alloc, st, sizeof(double) * nc * R);
+  d_gam_r = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
+  d_gam_z = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
+  d_gam_p = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
+  d_gam_q = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
+  d_gam_x = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
+  d_sc = alloc0(alloc, st, sizeof(double) * 16);
+  d_part = alloc0(alloc, st, sizeof(double) * 1024);
+  d_alphas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
+  d_betas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
+  HIPCHK(hipStreamSynchronize(st));
+  factored = false;
+}
+
+void Solver::factor() {
+  hipStream_t st = stream;
+  const int ns = L.nsub;
+  auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(hipMemsetAsync(d_status.p, 0, d_status.bytes, st));
+  HIPCHK(hipMemsetAsync(d_AII.p, 0, d_AII.bytes, st));
+  HIPCHK(hipMemsetAsync(d_AIG.p, 0, d_AIG.bytes, st));
+  HIPCHK(hipMemsetAsync(d_S.p, 0, d_S.bytes, st));
+  scatter_dense_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
+      d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
+      d_val.as<double>(), n_rows, d_nI.as<int>(), d_nG.as<int>(), d_offII.as<int64_t>(),
+      d_offIG.as<int64_t>(), d_offGG.as<int64_t>(), d_AII.as<double>(), d_AIG.as<double>(),
+      d_S.as<double>());
+  HIPCHK(hipGetLastError());
+  int *status = d_status.as<int>();
+  // Dirichlet factors and Schur complements
+  HIPCHK(DenseOps<double>::potrf(st, d_AII.as<double>(), d_descII.as<MatDesc>(), h_descII.data(), ns,
+                                 status));
+  HIPCHK(DenseOps<double>::trsm(st, d_AII.as<double>(), d_AIG.as<double>(), d_descII.as<MatDesc>(),
+                                h_descII.data(), ns, false));
+  HIPCHK(DenseOps<double>::gemm(st, d_AIG.as<double>(), d_AIG.as<double>(), d_S.as<double>(),
+                                d_syrk.as<GemmDesc>(), ns, L.max_nG, L.max_nG, true, false, -1.0,
+                                1.0, true));
+  HIPCHK(symmetrize_lower<double>(st, d_S.as<double>(), d_descGG.as<MatDesc>(), ns, L.max_nG));
+  // transformed Schur complements Sbar = T^T S T in the work pool
+  HIPCHK(hipMemcpyAsync(d_W.p, d_S.p, sizeof(double) * L.sGG, hipMemcpyDeviceToDevice, st));
+  if (n_gx > 0 && L.max_nG > 0) {
+    DBuf scrS;
+    scrS.bytes = sizeof(double) * (size_t)scrS_elems;
+    scrS.p = alloc.get(scrS.bytes);
+    for (int rows = 0; rows < 2; ++rows) {
+      xform_copy_pivots_kernel<<<dim3(nblocks(L.max_nG), n_gx), TPB, 0, st>>>(
+          d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_gx.as<GlobXf>(), n_gx,
+          d_pos.as<int>(), d_offG.as<int64_t>(), scrS.as<double>(), rows);
+      HIPCHK(hipGetLastError());
+      if (!rows)
+        xform_cols_kernel<<<dim3(nblocks(L.max_nG), ns), TPB, 0, st>>>(
+            d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_gx.as<GlobXf>(),
+            d_gx_ptr.as<int>(), d_wmat.as<double>(), d_pos.as<int>(), d_offG.as<int64_t>(),
+            scrS.as<double>());
+      else
+        xform_rows_kernel<<<dim3(nblocks(L.max_nG, 4), ns), TPB, 0, st>>>(
+            d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_gx.as<GlobXf>(),
+            d_gx_ptr.as<int>(), d_wmat.as<double>(), d_pos.as<int>(), d_offG.as<int64_t>(),
+            scrS.as<double>());
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    release(scrS);
+  }
+  // split into rr, r-pi, pi-pi
+  auto gather = [&](DBuf &dst, const DBuf &dstoff, const DBuf &ldd, const DBuf &ri, const DBuf &rio,
+                    const DBuf &nrow, const DBuf &ci, const DBuf &cio, const DBuf &ncol, int64_t maxe,
+                    double scale) {
+    if (maxe <= 0) return;
+    gather_block_kernel<<<dim3(nblocks(maxe), ns), TPB, 0, st>>>(
+        d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), dst.as<double>(),
+        dstoff.as<int64_t>(), ldd.as<int>(), ri.as<int>(), rio.as<int64_t>(), nrow.as<int>(),
+        ci.as<int>(), cio.as<int64_t>(), ncol.as<int>(), scale);
+    HIPCHK(hipGetLastError());
+  };
+  gather(d_Lrr, d_offRR, d_nr, d_ridx, d_ridx_off, d_nr, d_ridx, d_ridx_off, d_nr,
+         (int64_t)L.max_nr * L.max_nr, 1.0);
+  gather(d_Phi, d_offRP, d_nr, d_ridx, d_ridx_off, d_nr, d_pidx, d_pidx_off, d_np,
+         (int64_t)L.max_nr * L.max_np, 1.0);
+  gather(d_Spi, d_offPP, d_np, d_pidx, d_pidx_off, d_np, d_pidx, d_pidx_off, d_np,
+         (int64_t)L.max_np * L.max_np, 1.0);
+  // constrained local factor and coarse basis
+  HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), d_descRR.as<MatDesc>(), h_descRR.data(),
+                                 ns, status));
+  HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
+                                h_descRR.data(), ns, false));
+  HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
+                                d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
+                                -1.0, 1.0, false));
+  HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
+                                h_descRR.data(), ns, true));
+  if (L.sRP > 0) {
+    axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
+                                                 L.sRP);
+    HIPCHK(hipGetLastError());
+  }
+  // coarse problem
+  const int64_t nc = L.n_coarse;
+  if (nc > 0) {
+    coarse_assemble_kernel<<<nblocks(nc * nc), TPB, 0, st>>>(
+        (int)nc, d_c_ptr.as<int>(), d_c_sub.as<int>(), d_c_loc.as<int>(), d_offPP.as<int64_t>(),
+        d_np.as<int>(), d_Spi.as<double>(), d_sub_cids.as<int>(), d_offP.as<int64_t>(),
+        d_Lc.as<double>());
+    HIPCHK(hipGetLastError());
+    HIPCHK(DenseOps<double>::potrf(st, d_Lc.as<double>(), d_descC.as<MatDesc>(), h_descC.data(), 1,
+                                   status + ns));
+  }
+  std::vector<int> hs(ns + 2, 0);
+  HIPCHK(hipMemcpyAsync(hs.data(), d_status.p, sizeof(int) * (ns + 2), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  factor_seconds = std::chrono::duration<double>(t1 - t0).count();
+  for (int s = 0; s < ns; ++s)
+    if (hs[s]) throw NotSpdError("substructure " + std::to_string(s) + ": non-positive pivot at column " +
+                                 std::to_string(hs[s] - 1));
+  if (hs[ns]) throw SingularCoarseError("coarse problem: non-positive pivot at column " +
+                                        std::to_string(hs[ns] - 1));
+  // flop count (dense, executed)
+  double fl = 0;
+  for (int s = 0; s < ns; ++s) {
+    const double ni = L.nI[s], ng = L.nG[s], nr = L.nr[s], np = L.np[s];
+    fl += ni * ni * ni / 3 + ni * ni * ng + ng * ng * ni + nr * nr * nr / 3 + 2 * nr * nr * np +
+          nr * np * np;
+  }
+  fl += (double)nc * nc * nc / 3;
+  factor_flops = fl;
+  factored = true;
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner and PCG (one right-hand side per call of the internals)
+
+void Solver::trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, double *x, bool t, int nrhs) {
+  HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), plan, t, nrhs,
+                              d_work_i.as<int>(), d_status.as<int>() + L.nsub + 1));
+}
+
+// interface residual (gamma vector, nrhs = 1) -> z on gamma.  Interior values
+// are not produced here.
+void Solver::apply_gamma(const double *r, double *z) {
+  double *vG = d_vG.as<double>();
+  gather_kernel<<<nblocks(L.sumG), TPB, 0, stream>>>(r, L.n_gamma, d_ifc_gamma.as<int64_t>(),
+                                                     d_ifc_delta.as<double>(), vG, L.sumG, L.sumG, 1);
+  HIPCHK(hipGetLastError());
+  apply_local(vG, z);
+}
+
+void Solver::apply_Tt_vec(double *b) {
+  if (!n_gx) return;
+  vec_pivots_kernel<<<nblocks(n_gx), TPB, 0, stream>>>(b, d_gx.as<GlobXf>(), n_gx, d_pos.as<int>(),
+                                                       d_scr.as<double>());
+  apply_Tt_kernel<<<nblocks((int64_t)n_gx * 64), TPB, 0, stream>>>(
+      b, d_gx.as<GlobXf>(), n_gx, d_wmat.as<double>(), d_pos.as<int>(), d_scr.as<double>());
+  HIPCHK(hipGetLastError());
+}
+
+void Solver::apply_T_vec(double *x) {
+  if (!n_gx) return;
+  apply_T_dots_kernel<<<nblocks((int64_t)n_gk * 64), TPB, 0, stream>>>(
+      x, d_gx.as<GlobXf>(), d_gk_glob.as<int>(), d_gk_k.as<int>(), n_gk, d_trow.as<double>(),
+      d_pos.as<int>(), d_scr.as<double>());
+  apply_T_store_kernel<<<nblocks(n_gk), TPB, 0, stream>>>(x, d_gx.as<GlobXf>(), d_gk_glob.as<int>(),
+                                                          d_gk_k.as<int>(), n_gk, d_pos.as<int>(),
+                                                          d_scr.as<double>());
+  HIPCHK(hipGetLastError());
+}
+
+// q = sum_i R_i^T S_i R_i p on gamma vectors
+void Solver::schur_gamma(const double *p, double *q) {
+  hipStream_t st = stream;
+  double *vG = d_vG.as<double>(), *vG2 = d_vG2.as<double>();
+  gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(p, L.n_gamma, d_ifc_gamma.as<int64_t>(), nullptr, vG,
+                                                 L.sumG, L.sumG, 1);
+  if (L.max_nG > 0)
+    gemv_t_kernel<<<dim3(nblocks((int64_t)L.max_nG * 64), L.nsub), TPB, 0, st>>>(
+        d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_nG.as<int>(), vG,
+        d_offG.as<int64_t>(), vG2, d_offG.as<int64_t>(), 1.0, 0.0);
+  reduce_copies_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(vG2, L.sumG, d_gamma_ptr.as<int>(),
+                                                           d_gamma_copies.as<int64_t>(), nullptr, q,
+                                                           L.n_gamma, L.n_gamma, 1, 1.0, 0.0);
+  HIPCHK(hipGetLastError());
+}
+
+void Solver::dot(const double *a, const double *b, int64_t n, double *out) {
+  dot_partial_kernel<<<DOT_BLOCKS, TPB, 0, stream>>>(a, b, n, d_part.as<double>());
+  dot_final_kernel<<<1, TPB, 0, stream>>>(d_part.as<double>(), DOT_BLOCKS, out);
+  HIPCHK(hipGetLastError());
+}
+
+// interior Dirichlet solve in every substructure: vI <- A_II^-1 vI
+void Solver::interior_solve(double *vI) {
+  trsv(plan_II, d_AII, d_descIIvec, vI, false, 1);
+  trsv(plan_II, d_AII, d_descIIvec, vI, true, 1);
+}
+
+// z = M r for global vectors (Algorithm 2): the interior part of r enters
+// through E^T, i.e. the substructure right-hand side has b_I = r_I, which is
+// condensed onto the interface before the interface solve; the result is
+// extended harmonically.
+void Solver::apply_global(const double *r, double *z) {
+  if (!factored) throw StateError("bddc_apply before bddc_factor");
+  hipStream_t st = stream;
+  double *vI = d_vI.as<double>(), *vG = d_vG.as<double>();
+  double *gr = d_gam_r.as<double>(), *gz = d_gam_z.as<double>();
+  // condensation of the interior right-hand side: r_G - sum A_GI A_II^-1 r_I
+  gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(r, L.n_glob, d_int_gdof.as<int64_t>(), nullptr, vI,
+                                                 L.sumI, L.sumI, 1);
+  interior_solve(vI);
+  spmv_coupling_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
+      d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
+      d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(), vI,
+      nullptr, nullptr, vG, 0, 1, L.sumI, L.sumG);
+  // gamma residual: r_gamma - sum over copies of (A_GI A_II^-1 r_I), where
+  // the interior part enters through E^T with weight 1 in its substructure and
+  // the condensed part is weighted like the interface entries
+  gather_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(r, L.n_glob, d_gamma_gdof.as<int64_t>(), nullptr, gr,
+                                                    L.n_gamma, L.n_gamma, 1);
+  HIPCHK(hipGetLastError());
+  apply_gamma_condensed(gr, vG, gz);
+  harmonic_extension(gz, z);
+}
+
+// as apply_gamma, but the local right-hand sides receive the condensed
+// interior contribution -A_GI A_II^-1 r_I (already in vG_cond, unweighted)
+void Solver::apply_gamma_condensed(const double *r, const double *vG_cond, double *z) {
+  hipStream_t st = stream;
+  // vG2 = delta . R_i r - vG_cond
+  double *vG2 = d_vG2.as<double>();
+  gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(r, L.n_gamma, d_ifc_gamma.as<int64_t>(),
+                                                 d_ifc_delta.as<double>(), vG2, L.sumG, L.sumG, 1);
+  axpby_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(vG2, vG_cond, -1.0, 1.0, L.sumG);
+  HIPCHK(hipGetLastError());
+  apply_local(vG2, z);
+}
+
+// everything of apply_gamma after the weighted gather; b (sum-nG stack) is
+// consumed
+void Solver::apply_local(double *b, double *z) {
+  hipStream_t st = stream;
+  const int ns = L.nsub;
+  double *vG = b, *vR = d_vR.as<double>(), *vR2 = d_vR2.as<double>();
+  double *vP = d_vP.as<double>(), *vc = d_vc.as<double>();
+  apply_Tt_vec(vG);
+  gather32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vG, L.sumG, d_rabs.as<int>(), vR, L.sumR, L.sumR, 1);
+  gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vG, L.sumG, d_pabs.as<int>(), vP, L.sumP, L.sumP, 1);
+  HIPCHK(hipGetLastError());
+  if (L.max_np > 0)
+    gemv_t_kernel<<<dim3(nblocks((int64_t)L.max_np * 64), ns), TPB, 0, st>>>(
+        d_Phi.as<double>(), d_offRP.as<int64_t>(), d_nr.as<int>(), d_np.as<int>(), vR,
+        d_offR.as<int64_t>(), vP, d_offP.as<int64_t>(), 1.0, 1.0);
+  HIPCHK(hipMemcpyAsync(vR2, vR, sizeof(double) * L.sumR, hipMemcpyDeviceToDevice, st));
+  trsv(plan_rr, d_Lrr, d_descRRvec, vR2, false, 1);
+  trsv(plan_rr, d_Lrr, d_descRRvec, vR2, true, 1);
+  if (L.n_coarse > 0) {
+    reduce_copies_kernel<<<nblocks(L.n_coarse), TPB, 0, st>>>(vP, L.sumP, d_c_ptr.as<int>(),
+                                                              d_c_copies.as<int64_t>(), nullptr, vc,
+                                                              L.n_coarse, L.n_coarse, 1, 1.0, 0.0);
+    trsv(plan_c, d_Lc, d_descCvec, vc, false, 1);
+    trsv(plan_c, d_Lc, d_descCvec, vc, true, 1);
+    gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vc, L.n_coarse, d_pcid.as<int>(), vP, L.sumP,
+                                                     L.sumP, 1);
+    if (L.max_nr > 0)
+      gemv_n_kernel<<<dim3(nblocks(L.max_nr), ns), TPB, 0, st>>>(
+          d_Phi.as<double>(), d_offRP.as<int64_t>(), d_nr.as<int>(), d_np.as<int>(), vP,
+          d_offP.as<int64_t>(), vR2, d_offR.as<int64_t>(), 1.0, 1.0);
+  }
+  scatter32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vR2, L.sumR, d_rabs.as<int>(), vG, L.sumG, L.sumR, 1);
+  scatter32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vP, L.sumP, d_pabs.as<int>(), vG, L.sumG, L.sumP, 1);
+  apply_T_vec(vG);
+  reduce_copies_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(vG, L.sumG, d_gamma_ptr.as<int>(),
+                                                           d_gamma_copies.as<int64_t>(),
+                                                           d_ifc_delta.as<double>(), z, L.n_gamma,
+                                                           L.n_gamma, 1, 1.0, 0.0);
+  HIPCHK(hipGetLastError());
+}
+
+// global z from interface values zg: z_G = zg, z_I = -A_II^-1 A_IG zg
+void Solver::harmonic_extension(const double *zg, double *z) {
+  hipStream_t st = stream;
+  double *vI = d_vI.as<double>(), *vG = d_vG.as<double>();
+  scatter_gamma(zg, z);
+  gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(zg, L.n_gamma, d_ifc_gamma.as<int64_t>(), nullptr, vG,
+                                                 L.sumG, L.sumG, 1);
+  spmv_coupling_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
+      d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
+      d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(),
+      nullptr, vG, vI, nullptr, 1, 1, L.sumI, L.sumG);
+  HIPCHK(hipGetLastError());
+  interior_solve(vI);
+  axpby_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(vI, vI, 0.0, -1.0, L.sumI);
+  scatter_interior(vI, z);
+}
+
+void Solver::scatter_gamma(const double *zg, double *z) {
+  // z[gamma_gdof[k]] = zg[k]
+  scatter64(zg, d_gamma_gdof.as<int64_t>(), L.n_gamma, z);
+}
+
+void Solver::scatter_interior(const double *vI, double *z) {
+  scatter64(vI, d_int_gdof.as<int64_t>(), L.sumI, z);
+}
+
+namespace {
+__global__ void scatter64_kernel(const double *src, const int64_t *idx, int64_t n, double *dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[idx[i]] = src[i];
+}
+}  // namespace
+
+void Solver::scatter64(const double *src, const int64_t *idx, int64_t n, double *dst) {
+  if (n <= 0) return;
+  scatter64_kernel<<<nblocks(n), TPB, 0, stream>>>(src, idx, n, dst);
+  HIPCHK(hipGetLastError());
+}
+
+// PCG on the reduced problem (Remark after Lemma 1: zero interface start,
+// interior Dirichlet solves, residuals vanish in the interiors).
+PcgResult Solver::pcg(const double *f, double *u, double rtol, int maxit) {
+  if (!factored) throw StateError("bddc_pcg_solve before bddc_factor");
+  maxit = std::min(maxit, kMaxIt);
+  hipStream_t st = stream;
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t ng = L.n_gamma;
+  double *vI = d_vI.as<double>(), *vG = d_vG.as<double>();
+  double *r = d_gam_r.as<double>(), *z = d_gam_z.as<double>(), *p = d_gam_p.as<double>();
+  double *q = d_gam_q.as<double>(), *x = d_gam_x.as<double>();
+  double *sc = d_sc.as<double>();
+  // u0: interior solves with zero interface
+  gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(f, L.n_glob, d_int_gdof.as<int64_t>(), nullptr, vI,
+                                                 L.sumI, L.sumI, 1);
+  interior_solve(vI);
+  // r0 = f_G - sum A_GI u0_I
+  spmv_coupling_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
+      d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
+      d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(), vI,
+      nullptr, nullptr, vG, 0, 1, L.sumI, L.sumG);
+  gather_kernel<<<nblocks(ng), TPB, 0, st>>>(f, L.n_glob, d_gamma_gdof.as<int64_t>(), nullptr, r, ng,
+                                             ng, 1);
+  reduce_copies_kernel<<<nblocks(ng), TPB, 0, st>>>(vG, L.sumG, d_gamma_ptr.as<int>(),
+                                                    d_gamma_copies.as<int64_t>(), nullptr, r, ng, ng,
+                                                    1, -1.0, 1.0);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * ng, st));
+  dot(r, r, ng, sc + 2);
+  double rr0;
+  HIPCHK(hipMemcpyAsync(&rr0, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  PcgResult res;
+  const double r0 = std::sqrt(rr0);
+  int it = 0;
+  bool conv = (r0 == 0.0);
+  double rel = 0.0;
+  res.history.push_back(1.0);
+  if (!conv) {
+    apply_gamma(r, z);
+    HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * ng, hipMemcpyDeviceToDevice, st));
+    dot(r, z, ng, sc + 0);
+    for (it = 1; it <= maxit; ++it) {
+      schur_gamma(p, q);
+      dot(p, q, ng, sc + 1);
+      pcg_alpha_kernel<<<1, 1, 0, st>>>(sc, d_alphas.as<double>(), it - 1);
+      pcg_update_kernel<<<nblocks(ng), TPB, 0, st>>>(x, r, p, q, sc, ng);
+      dot(r, r, ng, sc + 2);
+      double rr;
+      HIPCHK(hipMemcpyAsync(&rr, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      rel = std::sqrt(rr) / r0;
+      res.history.push_back(rel);
+      if (!std::isfinite(rel)) break;
+      if (rel <= rtol) {
+        conv = true;
+        break;
+      }
+      apply_gamma(r, z);
+      dot(r, z, ng, sc + 5);
+      pcg_beta_kernel<<<1, 1, 0, st>>>(sc, d_betas.as<double>(), it - 1);
+      pcg_dir_kernel<<<nblocks(ng), TPB, 0, st>>>(p, z, sc, ng);
+      HIPCHK(hipGetLastError());
+    }
+    if (it > maxit) it = maxit;
+  }
+  // u: interface from x, interiors A_II^-1 (f_I - A_IG x)
+  scatter_gamma(x, u);
+  gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(x, ng, d_ifc_gamma.as<int64_t>(), nullptr, vG, L.sumG,
+                                                 L.sumG, 1);
+  spmv_coupling_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
+      d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
+      d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(),
+      nullptr, vG, d_vI2.as<double>(), nullptr, 1, 1, L.sumI, L.sumG);
+  gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(f, L.n_glob, d_int_gdof.as<int64_t>(), nullptr, vI,
+                                                 L.sumI, L.sumI, 1);
+  axpby_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(vI, d_vI2.as<double>(), -1.0, 1.0, L.sumI);
+  HIPCHK(hipGetLastError());
+  interior_solve(vI);
+  scatter_interior(vI, u);
+  // Lanczos coefficients
+  const int na = conv ? it : std::max(0, it - 1);
+  res.alphas.resize(na);
+  res.betas.resize(std::max(0, na - 1));
+  if (na > 0)
+    HIPCHK(hipMemcpyAsync(res.alphas.data(), d_alphas.p, sizeof(double) * na, hipMemcpyDeviceToHost, st));
+  if (na > 1)
+    HIPCHK(hipMemcpyAsync(res.betas.data(), d_betas.p, sizeof(double) * (na - 1), hipMemcpyDeviceToHost, st));
+  int herr[2];
+  HIPCHK(hipMemcpyAsync(herr, d_status.as<int>() + L.nsub + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (herr[0]) throw DeviceError("triangular solve wait bound exceeded");
+  res.iters = it;
+  res.converged = conv;
+  res.relres = rel;
+  lanczos_extremes(res.alphas, res.betas, res.lmin, res.lmax);
+  res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  last_history = res.history;
+  return res;
+}
+
+double Solver::apply_bytes() const {
+  double b = 0;
+  for (int s = 0; s < L.nsub; ++s) {
+    const double nr = L.nr[s], np = L.np[s], ng = L.nG[s];
+    b += 8.0 * (nr * nr + 2 * nr * np) + 8.0 * 6 * ng;  // two triangle sweeps, Phi twice, vectors
+  }
+  b += 8.0 * (double)L.n_coarse * L.n_coarse;
+  return b;
+}
+
+double Solver::iter_bytes() const {
+  double b = apply_bytes();
+  for (int s = 0; s < L.nsub; ++s) b += 8.0 * (double)L.nG[s] * L.nG[s];
+  return b;
+}
+
+// extreme eigenvalues of the CG-Lanczos tridiagonal matrix by Sturm
+// bisection: diag_j = 1/a_j + b_{j-1}/a_{j-1}, off_j = sqrt(b_j)/a_j
+void lanczos_extremes(const std::vector<double> &a, const std::vector<double> &b, double &lmin,
+                      double &lmax) {
+  const int k = (int)a.size();
+  if (k == 0) {
+    lmin = lmax = NAN;
+    return;
+  }
+  std::vector<double> d(k), e2(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    d[j] = 1.0 / a[j] + (j > 0 ? b[j - 1] / a[j - 1] : 0.0);
+    if (j < k - 1) {
+      const double o = std::sqrt(b[j]) / a[j];
+      e2[j] = o * o;
+    }
+  }
+  double lo = d[0], hi = d[0];
+  for (int j = 0; j < k; ++j) {
+    const double r = (j > 0 ? std::sqrt(e2[j - 1]) : 0) + (j < k - 1 ? std::sqrt(e2[j]) : 0);
+    lo = std::min(lo, d[j] - r);
+    hi = std::max(hi, d[j] + r);
+  }
+  auto count_below = [&](double x) {  // eigenvalues < x
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) ++c;
+    for (int j = 1; j < k; ++j) {
+      if (q == 0) q = 1e-300;
+      q = d[j] - x - e2[j - 1] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  auto kth = [&](int idx) {  // idx-th smallest (0-based)
+    double a0 = lo, b0 = hi;
+    for (int it = 0; it < 200 && b0 - a0 > 1e-15 * std::max(std::fabs(a0), std::fabs(b0)); ++it) {
+      const double m = 0.5 * (a0 + b0);
+      if (count_below(m) > idx)
+        b0 = m;
+      else
+        a0 = m;
+    }
+    return 0.5 * (a0 + b0);
+  };
+  lmin = kth(0);
+  lmax = kth(k - 1);
+}
+
+}  // namespace bddc
