@@ -52,7 +52,9 @@ typedef enum {
 
 /* Library-wide options.  Zero-initialize and set what you need. */
 typedef struct {
-  int device;                        /* HIP device ordinal */
+  int device;                        /* HIP device ordinal; < 0: host-only context
+                                        (setup analysis and inspection only; factor,
+                                        adapt, apply and solve return BDDC_ERR_STATE) */
   void *hip_stream;                  /* hipStream_t to run on; NULL: library stream */
   int factor_precision;              /* 64 (default, 0 means 64) or 32: substructure
                                         factors and local solves in FP32, PCG,
@@ -177,6 +179,35 @@ bddc_status bddc_get_face_eigs(const bddc_ctx *ctx, int64_t f, int64_t max, doub
 /* Relative residual history ||r_k||_2 / ||r_0||_2, k = 0..iters, of the last
    right-hand side solved by bddc_pcg_solve on this context. */
 bddc_status bddc_pcg_history(const bddc_ctx *ctx, int64_t max, double *out, int64_t *count);
+
+/* Substructure s as built by bddc_setup: n local dofs (interior first, then
+   interface, each ascending in the global numbering), the CSR matrix A_s of
+   the subassembled element matrices (Sec. 2) and the weights of the averaging
+   operator E on the n - n_interior interface dofs.  Pass NULL arrays to query
+   n, n_interior and nnz first; otherwise gdof[n], rowptr[n+1], col[nnz],
+   val[nnz], weights[n - n_interior] are written. */
+bddc_status bddc_get_substructure(const bddc_ctx *ctx, int32_t s, int64_t *n, int64_t *n_interior,
+                                  int64_t *nnz, int64_t *gdof, int64_t *rowptr, int32_t *col,
+                                  double *val, double *weights);
+
+/* Kernel timing.  When on, the main kernels of factor / apply / PCG are
+   bracketed by HIP events on the context's stream; every category keeps the
+   summed time, the number of timed launches and the algorithmic bytes and
+   flops those launches must move / perform (from the operand sizes: e.g. one
+   pass over a dense matrix counts its stored entries once).  Turning timing
+   on clears the statistics.  Timing serializes nothing but adds two event
+   records per timed launch. */
+typedef struct {
+  char name[32];
+  double ms;                 /* summed over launches */
+  int64_t launches;
+  double bytes;              /* summed algorithmic bytes */
+  double flops;              /* summed algorithmic flops */
+} bddc_kernel_stat;
+
+bddc_status bddc_set_timing(bddc_ctx *ctx, int on);
+/* Writes up to max entries; *count receives the number of categories. */
+bddc_status bddc_get_timing(const bddc_ctx *ctx, int max, bddc_kernel_stat *out, int *count);
 
 const char *bddc_last_error(const bddc_ctx *ctx);
 void bddc_destroy(bddc_ctx *ctx);

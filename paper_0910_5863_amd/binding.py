@@ -9,8 +9,10 @@ library is missing or the GPU is absent the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -80,11 +82,28 @@ class bddc_info(C.Structure):
                 ("device_bytes", C.c_size_t)]
 
 
+class bddc_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("ms", C.c_double), ("launches", C.c_int64),
+                ("bytes", C.c_double), ("flops", C.c_double)]
+
+
 SYMBOLS = ["bddc_create", "bddc_setup", "bddc_adapt", "bddc_factor", "bddc_apply",
            "bddc_pcg_solve", "bddc_get_info", "bddc_get_face_rows", "bddc_get_face_eigs",
-           "bddc_pcg_history", "bddc_last_error", "bddc_destroy"]
+           "bddc_pcg_history", "bddc_get_substructure", "bddc_set_timing", "bddc_get_timing", "bddc_last_error",
+           "bddc_destroy"]
 
 _lib = None
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # free device memory through torch before torch itself shuts down
+    for b in list(_live):
+        try:
+            b.close()
+        except Exception:
+            pass
 
 
 def load(path: str = LIB_PATH):
@@ -111,6 +130,12 @@ def load(path: str = LIB_PATH):
     L.bddc_get_face_eigs.argtypes = [P, C.c_int64, C.c_int64, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]
     L.bddc_pcg_history.argtypes = [P, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.bddc_get_substructure.argtypes = [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.bddc_set_timing.argtypes = [P, C.c_int]
+    L.bddc_get_timing.argtypes = [P, C.c_int, C.POINTER(bddc_kernel_stat), C.POINTER(C.c_int)]
     L.bddc_last_error.argtypes = [P]
     L.bddc_last_error.restype = C.c_char_p
     L.bddc_destroy.argtypes = [P]
@@ -176,9 +201,20 @@ def _check(h, code):
 
 
 class BDDC:
-    """One library context on ``device`` using torch's current stream."""
+    """One library context on ``device`` using torch's current stream.
+    ``device < 0`` gives a host-only context (setup analysis, no GPU)."""
 
     def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+        if device < 0:
+            self.torch = None
+            self.device = device
+            opt = bddc_options()
+            opt.device = device
+            self._keep = []
+            self.h = bddc_create(opt)
+            self.n_glob = None
+            _live.add(self)
+            return
         import torch
         self.torch = torch
         self.device = device
@@ -196,17 +232,22 @@ class BDDC:
                 return torch.cuda.caching_allocator_alloc(int(n), device, stream)
 
             def _free(p, user):
-                torch.cuda.caching_allocator_delete(int(p))
+                try:
+                    torch.cuda.caching_allocator_delete(int(p))
+                except Exception:
+                    pass  # interpreter teardown: torch already gone
             fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
             self._keep += [fa, ff]
             opt.alloc, opt.free = fa, ff
         self.h = bddc_create(opt)
         self.n_glob = None
+        _live.add(self)
 
     def close(self):
         if self.h is not None:
             bddc_destroy(self.h)
             self.h = None
+        _live.discard(self)
 
     def __del__(self):
         try:
@@ -286,6 +327,38 @@ class BDDC:
         out = np.zeros(cnt.value)
         _check(self.h, L.bddc_pcg_history(self.h, cnt.value, _ptr(out, C.c_double), C.byref(cnt)))
         return out
+
+    def substructure(self, s):
+        """(gdof, n_interior, scipy CSR matrix, interface weights) of substructure s."""
+        import scipy.sparse as sp
+        L = load()
+        n, ni, nnz = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(self.h, L.bddc_get_substructure(self.h, s, C.byref(n), C.byref(ni), C.byref(nnz),
+                                               None, None, None, None, None))
+        gd = np.zeros(n.value, dtype=np.int64)
+        rp = np.zeros(n.value + 1, dtype=np.int64)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value)
+        w = np.zeros(n.value - ni.value)
+        _check(self.h, L.bddc_get_substructure(self.h, s, C.byref(n), C.byref(ni), C.byref(nnz),
+                                               _ptr(gd, C.c_int64), _ptr(rp, C.c_int64),
+                                               _ptr(col, C.c_int32), _ptr(val, C.c_double),
+                                               _ptr(w, C.c_double)))
+        return gd, ni.value, sp.csr_matrix((val, col, rp), shape=(n.value, n.value)), w
+
+    def set_timing(self, on=True):
+        _check(self.h, load().bddc_set_timing(self.h, 1 if on else 0))
+
+    def timing(self):
+        """{name: dict(ms, launches, bytes, flops)} summed since set_timing."""
+        L = load()
+        cnt = C.c_int()
+        _check(self.h, L.bddc_get_timing(self.h, 0, None, C.byref(cnt)))
+        arr = (bddc_kernel_stat * max(cnt.value, 1))()
+        _check(self.h, L.bddc_get_timing(self.h, cnt.value, arr, C.byref(cnt)))
+        return {arr[i].name.decode(): dict(ms=arr[i].ms, launches=arr[i].launches,
+                                           bytes=arr[i].bytes, flops=arr[i].flops)
+                for i in range(cnt.value)}
 
     def face_eigs(self, f):
         L = load()

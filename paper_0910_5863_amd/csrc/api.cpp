@@ -2,6 +2,7 @@
 // state machine and error reporting around the host setup and device solver.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <memory>
@@ -63,6 +64,11 @@ bddc_status bddc_create(const bddc_options *opt, bddc_ctx **out) {
   if (c->opt.factor_precision == 0) c->opt.factor_precision = 64;
   if (c->opt.factor_precision != 64)
     return BDDC_ERR_ARG;  // FP32 factors are not available in this build
+  if (c->opt.device < 0) {  // host-only context: analysis without a GPU
+    c->S = std::make_unique<Solver>();
+    *out = c.release();
+    return BDDC_OK;
+  }
   bddc_status st = guarded(c.get(), [&] {
     int n = 0;
     check_hip(hipGetDeviceCount(&n), "hipGetDeviceCount");
@@ -95,7 +101,7 @@ bddc_status bddc_setup(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition 
     return fail(c, BDDC_ERR_ARG, "empty mesh or partition");
   if (cons->mode < 0 || cons->mode > 3) return fail(c, BDDC_ERR_ARG, "constraint mode in 0..3");
   return guarded(c, [&] {
-    check_hip(hipSetDevice(c->opt.device), "hipSetDevice");
+    if (c->opt.device >= 0) check_hip(hipSetDevice(c->opt.device), "hipSetDevice");
     Problem &P = c->P;
     P = Problem();
     MeshIn &m = P.mesh;
@@ -135,12 +141,13 @@ bddc_status bddc_setup(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition 
     compute_weights(P);
     build_constraints(P);
     c->adapt = AdaptState();
-    c->S->build(P, c->stream);
+    if (c->opt.device >= 0) c->S->build(P, c->stream);
     c->state = 1;
   });
 }
 
 bddc_status bddc_factor(bddc_ctx *c) {
+  if (c && c->opt.device < 0) return fail(c, BDDC_ERR_STATE, "host-only context (device < 0)");
   if (!c) return BDDC_ERR_ARG;
   if (c->state < 1) return fail(c, BDDC_ERR_STATE, "bddc_factor before bddc_setup");
   return guarded(c, [&] {
@@ -197,6 +204,7 @@ bddc_status bddc_pcg_solve(bddc_ctx *c, int nrhs, const double *f, int64_t ldf, 
 }
 
 bddc_status bddc_adapt(bddc_ctx *c, double tau, bddc_adapt_info *info) {
+  if (c && c->opt.device < 0) return fail(c, BDDC_ERR_STATE, "host-only context (device < 0)");
   if (!c) return BDDC_ERR_ARG;
   if (c->state < 1) return fail(c, BDDC_ERR_STATE, "bddc_adapt before bddc_setup");
   if (!(tau > 0)) return fail(c, BDDC_ERR_ARG, "tau must be positive");
@@ -225,6 +233,20 @@ bddc_status bddc_get_info(const bddc_ctx *c, bddc_info *o) {
   if (c->state < 1) return BDDC_ERR_STATE;
   const Problem &P = c->P;
   const Layout &L = c->S->L;
+  if (c->opt.device < 0) {
+    o->n_glob = P.n_glob;
+    o->n_sub = (int64_t)P.subs.size();
+    o->n_corners = (int64_t)P.corner_nodes.size();
+    o->n_edges = (int64_t)P.edge_ids.size();
+    o->n_faces = (int64_t)P.face_ids.size();
+    o->nc = count_nc(P);
+    for (const Sub &S : P.subs) {
+      o->n_iface_total += S.nG;
+      o->max_interior = std::max<int64_t>(o->max_interior, S.nI);
+      o->max_iface = std::max<int64_t>(o->max_iface, S.nG);
+    }
+    return BDDC_OK;
+  }
   o->n_glob = P.n_glob;
   o->n_sub = (int64_t)P.subs.size();
   o->n_corners = (int64_t)P.corner_nodes.size();
@@ -290,10 +312,62 @@ bddc_status bddc_pcg_history(const bddc_ctx *c, int64_t max, double *out, int64_
   return BDDC_OK;
 }
 
+bddc_status bddc_get_substructure(const bddc_ctx *c, int32_t s, int64_t *n, int64_t *n_interior,
+                                  int64_t *nnz, int64_t *gdof, int64_t *rowptr, int32_t *col,
+                                  double *val, double *weights) {
+  if (!c || !n || !n_interior || !nnz) return BDDC_ERR_ARG;
+  if (c->state < 1) return BDDC_ERR_STATE;
+  if (s < 0 || s >= (int32_t)c->P.subs.size()) return BDDC_ERR_ARG;
+  const Sub &S = c->P.subs[s];
+  *n = S.nI + S.nG;
+  *n_interior = S.nI;
+  *nnz = (int64_t)S.A.val.size();
+  if (gdof)
+    for (int64_t i = 0; i < *n; ++i) gdof[i] = S.gdof[i];
+  if (rowptr)
+    for (int64_t i = 0; i <= *n; ++i) rowptr[i] = S.A.ptr[i];
+  if (col)
+    for (int64_t k = 0; k < *nnz; ++k) col[k] = S.A.col[k];
+  if (val)
+    for (int64_t k = 0; k < *nnz; ++k) val[k] = S.A.val[k];
+  if (weights)
+    for (int t = 0; t < S.nG; ++t) weights[t] = S.delta[t];
+  return BDDC_OK;
+}
+
+bddc_status bddc_set_timing(bddc_ctx *c, int on) {
+  if (!c) return BDDC_ERR_ARG;
+  if (c->opt.device < 0) return fail(c, BDDC_ERR_STATE, "host-only context (device < 0)");
+  return guarded(c, [&] {
+    c->S->timer.reset();
+    c->S->timer.on = on != 0;
+  });
+}
+
+bddc_status bddc_get_timing(const bddc_ctx *c, int max, bddc_kernel_stat *out, int *count) {
+  if (!c || !count) return BDDC_ERR_ARG;
+  const Timer &t = c->S->timer;
+  *count = (int)t.names.size();
+  if (out)
+    for (int i = 0; i < std::min(max, *count); ++i) {
+      std::memset(out[i].name, 0, sizeof(out[i].name));
+      std::strncpy(out[i].name, t.names[i].c_str(), sizeof(out[i].name) - 1);
+      out[i].ms = t.stats[i].ms;
+      out[i].launches = t.stats[i].launches;
+      out[i].bytes = t.stats[i].bytes;
+      out[i].flops = t.stats[i].flops;
+    }
+  return BDDC_OK;
+}
+
 const char *bddc_last_error(const bddc_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 void bddc_destroy(bddc_ctx *c) {
   if (!c) return;
+  if (c->opt.device < 0) {
+    delete c;
+    return;
+  }
   (void)hipSetDevice(c->opt.device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   c->S.reset();

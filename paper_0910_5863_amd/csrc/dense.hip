@@ -173,24 +173,20 @@ __global__ __launch_bounds__(256) void chol_update_kernel(T *pool, const MatDesc
                             d.lda, T(-1), T(1), t * BM, 0);
 }
 
-// Factor the diagonal block of column k in LDS; row tiles below solve
-// X <- X L_kk^{-T}.  Every work-group of the column factors the diagonal
-// block itself (64^3/3 flops) instead of waiting for another launch.
+// Factor the diagonal block of block column k in LDS, in place: one
+// work-group per entry.  status[e] receives (column+1) of the first
+// non-positive pivot.
 template <class T>
-__global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc *desc, int k,
-                                                         int tm, int *status, int batch) {
+__global__ __launch_bounds__(256) void chol_diag_kernel(T *pool, const MatDesc *desc, int k,
+                                                        int *status, int batch) {
   __shared__ T D[NB][NB + 1];
-  __shared__ T X[NB][NB + 1];
   __shared__ int s_fail;
-  int e, t;
-  if (!xcd_remap(gridDim.x, tm, batch, e, t)) return;
+  const int e = blockIdx.x;
+  if (e >= batch) return;
   const MatDesc d = desc[e];
   const int kb = k * NB;
   if (kb >= d.n) return;
   const int w = min(NB, d.n - kb);
-  const int r0 = kb + t * NB;
-  if (r0 >= d.n) return;
-  const int nr = min(NB, d.n - r0);
   T *A = pool + d.a_off;
   const int64_t lda = d.lda;
   const int tid = threadIdx.x;
@@ -218,16 +214,35 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc 
     }
     __syncthreads();
   }
-  if (t == 0) {
-    if (tid == 0 && s_fail && status) atomicCAS(&status[e], 0, s_fail);
-    for (int i = tid; i < w * w; i += 256) {
-      const int r = i % w, c = i / w;
-      if (r >= c) A[(kb + r) + (kb + c) * lda] = D[r][c];
-    }
-    return;
+  if (tid == 0 && s_fail && status) atomicCAS(&status[e], 0, s_fail);
+  for (int i = tid; i < w * w; i += 256) {
+    const int r = i % w, c = i / w;
+    if (r >= c) A[(kb + r) + (kb + c) * lda] = D[r][c];
   }
+}
+
+// Row tiles below the diagonal of block column k (tile t >= 1): X <- X L_kk^{-T}
+// with the factored diagonal block read from global memory.
+template <class T>
+__global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc *desc, int k,
+                                                         int tm, int batch) {
+  __shared__ T D[NB][NB + 1];
+  __shared__ T X[NB][NB + 1];
+  int e, t;
+  if (!xcd_remap(gridDim.x, tm, batch, e, t)) return;
+  const MatDesc d = desc[e];
+  const int kb = k * NB;
+  if (kb >= d.n) return;
+  const int w = min(NB, d.n - kb);
+  const int r0 = kb + (t + 1) * NB;
+  if (r0 >= d.n) return;
+  const int nr = min(NB, d.n - r0);
+  T *A = pool + d.a_off;
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x;
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i % NB, c = i / NB;
+    D[r][c] = (r < w && c < w && r >= c) ? A[(kb + r) + (kb + c) * lda] : T(0);
     X[r][c] = (r < nr && c < w) ? A[(r0 + r) + (kb + c) * lda] : T(0);
   }
   __syncthreads();
@@ -526,9 +541,10 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
   const int nblk = (maxn + NB - 1) / NB;
   for (int k = 0; k < nblk; ++k) {
     const int tm = nblk - k;  // row tiles of block column k (for the largest entry)
-    const int nwg = grid_round(batch * tm);
-    if (k > 0) chol_update_kernel<T><<<nwg, 256, 0, st>>>(pool, d_desc, k, tm, batch);
-    chol_panel_kernel<T><<<nwg, 256, 0, st>>>(pool, d_desc, k, tm, status, batch);
+    if (k > 0) chol_update_kernel<T><<<grid_round(batch * tm), 256, 0, st>>>(pool, d_desc, k, tm, batch);
+    chol_diag_kernel<T><<<batch, 256, 0, st>>>(pool, d_desc, k, status, batch);
+    if (tm > 1)
+      chol_panel_kernel<T><<<grid_round(batch * (tm - 1)), 256, 0, st>>>(pool, d_desc, k, tm - 1, batch);
   }
   return hipGetLastError();
 }

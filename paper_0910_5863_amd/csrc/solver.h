@@ -50,6 +50,39 @@ struct PcgResult {
 void lanczos_extremes(const std::vector<double> &a, const std::vector<double> &b, double &lmin,
                       double &lmax);
 
+// Per-category kernel timing with HIP events on the solver's stream.  Each
+// timed launch also records the algorithmic bytes and flops it must move /
+// perform (from the operand sizes), so achieved rates can be derived.
+struct KernelStat {
+  double ms = 0, bytes = 0, flops = 0;
+  int64_t launches = 0;
+};
+
+class Timer {
+ public:
+  bool on = false;
+  std::vector<std::string> names;
+  std::vector<KernelStat> stats;
+  void begin(hipStream_t st, const char *name, double bytes, double flops);
+  void end(hipStream_t st);
+  void collect();  // after a synchronization: resolve pending event pairs
+  void reset();
+  ~Timer();
+
+ private:
+  struct Pending {
+    int idx;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int cur = -1;
+  hipEvent_t cur_a = nullptr;
+  double cur_bytes = 0, cur_flops = 0;
+  hipEvent_t get_event();
+};
+
 class Solver {
  public:
   static constexpr int kMaxRhs = 1;
@@ -61,10 +94,14 @@ class Solver {
   bool factored = false;
   double factor_seconds = 0, factor_flops = 0;
   std::vector<double> last_history;
+  Timer timer;
 
   ~Solver();
   void build(const Problem &P, hipStream_t st);
   void factor();
+  void factor_schur();
+  void check_status(bool all);
+  bool schur_ready = false;
   void apply_global(const double *r, double *z);
   PcgResult pcg(const double *f, double *u, double rtol, int maxit);
   void free_all();
@@ -92,6 +129,7 @@ class Solver {
   std::vector<DBuf *> all_buffers();
 
   int64_t n_rows = 0, nnz = 0;
+  double bytes_S = 0, bytes_Lrr_tri = 0;
   int n_gx = 0;
   TrsvPlan plan_rr, plan_II, plan_c;
   std::vector<MatDesc> h_descII, h_descRR, h_descGG, h_descC;

@@ -434,6 +434,75 @@ __global__ void pcg_dir_kernel(double *p, const double *z, const double *sc, int
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// timing
+
+hipEvent_t Timer::get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+void Timer::begin(hipStream_t st, const char *name, double bytes, double flops) {
+  if (!on) return;
+  int idx = -1;
+  for (size_t i = 0; i < names.size(); ++i)
+    if (names[i] == name) idx = (int)i;
+  if (idx < 0) {
+    idx = (int)names.size();
+    names.push_back(name);
+    stats.push_back(KernelStat());
+  }
+  cur = idx;
+  cur_a = get_event();
+  cur_bytes = bytes;
+  cur_flops = flops;
+  HIPCHK(hipEventRecord(cur_a, st));
+}
+
+void Timer::end(hipStream_t st) {
+  if (!on || cur < 0) return;
+  hipEvent_t b = get_event();
+  HIPCHK(hipEventRecord(b, st));
+  pending.push_back({cur, cur_a, b, cur_bytes, cur_flops});
+  cur = -1;
+}
+
+void Timer::collect() {
+  for (auto &p : pending) {
+    float ms = 0;
+    HIPCHK(hipEventSynchronize(p.b));
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    KernelStat &k = stats[p.idx];
+    k.ms += ms;
+    k.bytes += p.bytes;
+    k.flops += p.flops;
+    k.launches += 1;
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pending.clear();
+}
+
+void Timer::reset() {
+  collect();
+  names.clear();
+  stats.clear();
+}
+
+Timer::~Timer() {
+  for (auto &p : pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+// ---------------------------------------------------------------------------
 // host side
 
 template <class T>
@@ -766,7 +835,7 @@ void Solver::build(const Problem &P, hipStream_t st) {
   int w2 = plan(L.nI, d_trsv_II_fwd, d_trsv_II_bwd, d_trsv_II_off, plan_II);
   int w3 = plan({(int)nc}, d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, plan_c);
   d_work_i = alloc0(alloc, st, sizeof(int) * (size_t)(4 + std::max({w1, w2, w3})));
-  d_status = alloc0(alloc, st, sizeof(int) * (size_t)(ns + 2));
+  d_status = alloc0(alloc, st, sizeof(int) * (size_t)(2 * ns + 2));
   // matrices
   d_AII = alloc0(alloc, st, sizeof(double) * (size_t)L.sII);
   d_AIG = alloc0(alloc, st, sizeof(double) * (size_t)L.sIG);
@@ -795,14 +864,22 @@ void Solver::build(const Problem &P, hipStream_t st) {
   d_part = alloc0(alloc, st, sizeof(double) * 1024);
   d_alphas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
   d_betas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
+  bytes_S = 0;
+  bytes_Lrr_tri = 0;
+  for (int s = 0; s < ns; ++s) {
+    bytes_S += 8.0 * (double)L.nG[s] * L.nG[s];
+    bytes_Lrr_tri += 8.0 * 0.5 * (double)L.nr[s] * (L.nr[s] + 1);
+  }
   HIPCHK(hipStreamSynchronize(st));
   factored = false;
+  schur_ready = false;
 }
 
-void Solver::factor() {
+// Dirichlet factors A_II = L L^T and Schur complements S_i (original basis);
+// independent of the constraints.
+void Solver::factor_schur() {
   hipStream_t st = stream;
   const int ns = L.nsub;
-  auto t0 = std::chrono::steady_clock::now();
   HIPCHK(hipMemsetAsync(d_status.p, 0, d_status.bytes, st));
   HIPCHK(hipMemsetAsync(d_AII.p, 0, d_AII.bytes, st));
   HIPCHK(hipMemsetAsync(d_AIG.p, 0, d_AIG.bytes, st));
@@ -815,14 +892,39 @@ void Solver::factor() {
   HIPCHK(hipGetLastError());
   int *status = d_status.as<int>();
   // Dirichlet factors and Schur complements
+  double fl_potrf = 0, fl_trsm = 0, fl_syrk = 0;
+  for (int s = 0; s < ns; ++s) {
+    const double ni = L.nI[s], ng = L.nG[s];
+    fl_potrf += ni * ni * ni / 3;
+    fl_trsm += ni * ni * ng;
+    fl_syrk += ng * ng * ni;
+  }
+  timer.begin(st, "factor_potrf_interior", 8.0 * L.sII, fl_potrf);
   HIPCHK(DenseOps<double>::potrf(st, d_AII.as<double>(), d_descII.as<MatDesc>(), h_descII.data(), ns,
                                  status));
+  timer.end(st);
+  timer.begin(st, "factor_trsm_interior", 8.0 * (L.sII / 2 + 2 * L.sIG), fl_trsm);
   HIPCHK(DenseOps<double>::trsm(st, d_AII.as<double>(), d_AIG.as<double>(), d_descII.as<MatDesc>(),
                                 h_descII.data(), ns, false));
+  timer.end(st);
+  timer.begin(st, "factor_syrk_schur", 8.0 * (L.sIG + L.sGG), fl_syrk);
   HIPCHK(DenseOps<double>::gemm(st, d_AIG.as<double>(), d_AIG.as<double>(), d_S.as<double>(),
                                 d_syrk.as<GemmDesc>(), ns, L.max_nG, L.max_nG, true, false, -1.0,
                                 1.0, true));
+  timer.end(st);
   HIPCHK(symmetrize_lower<double>(st, d_S.as<double>(), d_descGG.as<MatDesc>(), ns, L.max_nG));
+  check_status(false);
+  schur_ready = true;
+}
+
+void Solver::factor() {
+  hipStream_t st = stream;
+  const int ns = L.nsub;
+  auto t0 = std::chrono::steady_clock::now();
+  factor_schur();
+  int *status = d_status.as<int>();
+  double fl_rr = 0;
+  for (int s = 0; s < ns; ++s) fl_rr += (double)L.nr[s] * L.nr[s] * L.nr[s] / 3;
   // transformed Schur complements Sbar = T^T S T in the work pool
   HIPCHK(hipMemcpyAsync(d_W.p, d_S.p, sizeof(double) * L.sGG, hipMemcpyDeviceToDevice, st));
   if (n_gx > 0 && L.max_nG > 0) {
@@ -867,8 +969,10 @@ void Solver::factor() {
   gather(d_Spi, d_offPP, d_np, d_pidx, d_pidx_off, d_np, d_pidx, d_pidx_off, d_np,
          (int64_t)L.max_np * L.max_np, 1.0);
   // constrained local factor and coarse basis
+  timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
   HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), d_descRR.as<MatDesc>(), h_descRR.data(),
-                                 ns, status));
+                                 ns, status + ns));
+  timer.end(st);
   HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
                                 h_descRR.data(), ns, false));
   HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
@@ -890,18 +994,11 @@ void Solver::factor() {
         d_Lc.as<double>());
     HIPCHK(hipGetLastError());
     HIPCHK(DenseOps<double>::potrf(st, d_Lc.as<double>(), d_descC.as<MatDesc>(), h_descC.data(), 1,
-                                   status + ns));
+                                   status + 2 * ns));
   }
-  std::vector<int> hs(ns + 2, 0);
-  HIPCHK(hipMemcpyAsync(hs.data(), d_status.p, sizeof(int) * (ns + 2), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  check_status(true);
   auto t1 = std::chrono::steady_clock::now();
   factor_seconds = std::chrono::duration<double>(t1 - t0).count();
-  for (int s = 0; s < ns; ++s)
-    if (hs[s]) throw NotSpdError("substructure " + std::to_string(s) + ": non-positive pivot at column " +
-                                 std::to_string(hs[s] - 1));
-  if (hs[ns]) throw SingularCoarseError("coarse problem: non-positive pivot at column " +
-                                        std::to_string(hs[ns] - 1));
   // flop count (dense, executed)
   double fl = 0;
   for (int s = 0; s < ns; ++s) {
@@ -914,12 +1011,34 @@ void Solver::factor() {
   factored = true;
 }
 
+void Solver::check_status(bool all) {
+  const int ns = L.nsub;
+  std::vector<int> hs(2 * ns + 2, 0);
+  HIPCHK(hipMemcpyAsync(hs.data(), d_status.p, sizeof(int) * (2 * ns + 2), hipMemcpyDeviceToHost,
+                        stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  timer.collect();
+  for (int s = 0; s < ns; ++s) {
+    if (hs[s])
+      throw NotSpdError("substructure " + std::to_string(s) +
+                        ": interior (Dirichlet) matrix, non-positive pivot at column " +
+                        std::to_string(hs[s] - 1) + " of " + std::to_string(L.nI[s]));
+    if (all && hs[ns + s])
+      throw NotSpdError("substructure " + std::to_string(s) +
+                        ": constrained interface matrix, non-positive pivot at column " +
+                        std::to_string(hs[ns + s] - 1) + " of " + std::to_string(L.nr[s]));
+  }
+  if (all && hs[2 * ns])
+    throw SingularCoarseError("coarse problem: non-positive pivot at column " +
+                              std::to_string(hs[2 * ns] - 1) + " of " + std::to_string(L.n_coarse));
+}
+
 // ---------------------------------------------------------------------------
 // preconditioner and PCG (one right-hand side per call of the internals)
 
 void Solver::trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, double *x, bool t, int nrhs) {
   HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), plan, t, nrhs,
-                              d_work_i.as<int>(), d_status.as<int>() + L.nsub + 1));
+                              d_work_i.as<int>(), d_status.as<int>() + 2 * L.nsub + 1));
 }
 
 // interface residual (gamma vector, nrhs = 1) -> z on gamma.  Interior values
@@ -958,10 +1077,13 @@ void Solver::schur_gamma(const double *p, double *q) {
   double *vG = d_vG.as<double>(), *vG2 = d_vG2.as<double>();
   gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(p, L.n_gamma, d_ifc_gamma.as<int64_t>(), nullptr, vG,
                                                  L.sumG, L.sumG, 1);
-  if (L.max_nG > 0)
+  if (L.max_nG > 0) {
+    timer.begin(st, "schur_gemv", bytes_S + 16.0 * L.sumG, 2.0 * (double)L.sGG);
     gemv_t_kernel<<<dim3(nblocks((int64_t)L.max_nG * 64), L.nsub), TPB, 0, st>>>(
         d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_nG.as<int>(), vG,
         d_offG.as<int64_t>(), vG2, d_offG.as<int64_t>(), 1.0, 0.0);
+    timer.end(st);
+  }
   reduce_copies_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(vG2, L.sumG, d_gamma_ptr.as<int>(),
                                                            d_gamma_copies.as<int64_t>(), nullptr, q,
                                                            L.n_gamma, L.n_gamma, 1, 1.0, 0.0);
@@ -1036,14 +1158,20 @@ void Solver::apply_local(double *b, double *z) {
         d_Phi.as<double>(), d_offRP.as<int64_t>(), d_nr.as<int>(), d_np.as<int>(), vR,
         d_offR.as<int64_t>(), vP, d_offP.as<int64_t>(), 1.0, 1.0);
   HIPCHK(hipMemcpyAsync(vR2, vR, sizeof(double) * L.sumR, hipMemcpyDeviceToDevice, st));
+  timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
   trsv(plan_rr, d_Lrr, d_descRRvec, vR2, false, 1);
+  timer.end(st);
+  timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
   trsv(plan_rr, d_Lrr, d_descRRvec, vR2, true, 1);
+  timer.end(st);
   if (L.n_coarse > 0) {
     reduce_copies_kernel<<<nblocks(L.n_coarse), TPB, 0, st>>>(vP, L.sumP, d_c_ptr.as<int>(),
                                                               d_c_copies.as<int64_t>(), nullptr, vc,
                                                               L.n_coarse, L.n_coarse, 1, 1.0, 0.0);
+    timer.begin(st, "trsv_coarse", 8.0 * (double)L.n_coarse * L.n_coarse, 2.0 * L.n_coarse * L.n_coarse);
     trsv(plan_c, d_Lc, d_descCvec, vc, false, 1);
     trsv(plan_c, d_Lc, d_descCvec, vc, true, 1);
+    timer.end(st);
     gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vc, L.n_coarse, d_pcid.as<int>(), vP, L.sumP,
                                                      L.sumP, 1);
     if (L.max_nr > 0)
@@ -1189,7 +1317,7 @@ PcgResult Solver::pcg(const double *f, double *u, double rtol, int maxit) {
   if (na > 1)
     HIPCHK(hipMemcpyAsync(res.betas.data(), d_betas.p, sizeof(double) * (na - 1), hipMemcpyDeviceToHost, st));
   int herr[2];
-  HIPCHK(hipMemcpyAsync(herr, d_status.as<int>() + L.nsub + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(herr, d_status.as<int>() + 2 * L.nsub + 1, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (herr[0]) throw DeviceError("triangular solve wait bound exceeded");
   res.iters = it;
@@ -1198,6 +1326,7 @@ PcgResult Solver::pcg(const double *f, double *u, double rtol, int maxit) {
   lanczos_extremes(res.alphas, res.betas, res.lmin, res.lmax);
   res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   last_history = res.history;
+  timer.collect();
   return res;
 }
 
