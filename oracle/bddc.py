@@ -155,9 +155,13 @@ def projection(D):
     I = sp.identity(n, format="csr")
     if D.shape[0] == 0:
         return I
+    D = sp.csr_matrix(D)
     DDt = (D @ D.T).toarray()
-    X = np.linalg.solve(DDt, D.toarray())
-    P = I - sp.csr_matrix(D.T @ X)
+    Minv = np.linalg.inv(DDt)
+    # (D D^T)^-1 is block diagonal (one block per glob and constraint); drop
+    # the rounding-level entries outside the blocks before the sparse product
+    Minv[np.abs(Minv) < 1e-13 * np.abs(Minv).max()] = 0.0
+    P = I - D.T @ sp.csr_matrix(Minv) @ D
     P = sp.csr_matrix(P)
     P.data[np.abs(P.data) < 1e-14] = 0.0
     P.eliminate_zeros()
