@@ -64,6 +64,7 @@ typedef struct {
   void *(*alloc)(size_t bytes, void *user);
   void (*free)(void *ptr, void *user);
   void *alloc_user;
+  int verbose;                       /* nonzero: per-phase timings on stderr */
 } bddc_options;
 
 /* Q1 hexahedral mesh (Sec. 2: substructure matrices are subassembled from

@@ -38,7 +38,8 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 class bddc_options(C.Structure):
     _fields_ = [("device", C.c_int), ("hip_stream", C.c_void_p), ("factor_precision", C.c_int),
-                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", C.c_void_p)]
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", C.c_void_p),
+                ("verbose", C.c_int)]
 
 
 class bddc_mesh(C.Structure):
@@ -204,7 +205,8 @@ class BDDC:
     """One library context on ``device`` using torch's current stream.
     ``device < 0`` gives a host-only context (setup analysis, no GPU)."""
 
-    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True,
+                 verbose: bool = False):
         if device < 0:
             self.torch = None
             self.device = device
@@ -226,6 +228,7 @@ class BDDC:
         opt.device = device
         opt.hip_stream = C.c_void_p(stream.cuda_stream)
         opt.factor_precision = 64
+        opt.verbose = 1 if verbose else 0
         self._keep = []
         if torch_allocator:
             def _alloc(n, user):

@@ -34,6 +34,8 @@
 #include <chrono>
 #include <cmath>
 #include <numeric>
+#include <cstdio>
+#include <cstdlib>
 
 #include "adapt.h"
 #include "dense.h"
@@ -70,7 +72,7 @@ __global__ void gather_rc_kernel(const double *src, const int64_t *src_off, cons
   dst[dst_off[e] + i] = src[src_off[e] + ra + (int64_t)cb * lds[e]];
 }
 
-// Ssum = Sh_i + Sh_j + rho Q Q^T ; Xb = Sh_i  (per pair, n x n, ld n)
+// Ssum = Sh_i + Sh_j + rho Q Q^T ; Xb = Sh_j  (per pair, n x n, ld n)
 __global__ void pair_sum_kernel(const double *Sh, const int64_t *off_i, const int64_t *off_j,
                                 const int *ns, double *Ssum, double *Xb, double *BJ,
                                 const int64_t *off_p, const double *Q, const int64_t *q_off,
@@ -84,8 +86,8 @@ __global__ void pair_sum_kernel(const double *Sh, const int64_t *off_i, const in
   double v = si + Sh[off_j[e] + i];
   for (int k = 0; k < nq[e]; ++k) v += rho[e] * Q[q_off[e] + r + k * n] * Q[q_off[e] + c + k * n];
   Ssum[off_p[e] + i] = v;
-  Xb[off_p[e] + i] = si;
-  BJ[off_p[e] + i] = si;
+  Xb[off_p[e] + i] = Sh[off_j[e] + i];
+  BJ[off_p[e] + i] = 0.0;
 }
 
 // compact c x c blocks: M = Dj Si Dj + Di Sj Di, BJ = (Sh_i - Sh_i X)[c,c]
@@ -117,13 +119,33 @@ __global__ void transpose_kernel(const double *src, double *dst, const int64_t *
   dst[off[e] + c + (int64_t)r * m] = src[off[e] + i];
 }
 
+// A <- (A + A^T) / 2 in place (entries a >= b of every entry touch both halves)
+__global__ void symmetrize_kernel(double *A, const int64_t *off, const int *n) {
+  const int e = blockIdx.y;
+  const int64_t m = n[e];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m * m) return;
+  const int r = (int)(i % m), c = (int)(i / m);
+  if (r <= c) return;
+  double *a = A + off[e];
+  const double v = 0.5 * (a[r + (int64_t)c * m] + a[c + (int64_t)r * m]);
+  a[r + (int64_t)c * m] = v;
+  a[c + (int64_t)r * m] = v;
+}
+
 // ---------------------------------------------------------------------------
 // batched LOBPCG: dominant eigenpairs of a symmetric d x d matrix per entry
+
+constexpr int LOB_S = LOB_MAXB / 3;  // block size (columns of X, W and P)
+constexpr int LOCK_MAX = 256;        // eigenvectors locked from earlier rounds
+constexpr int STAGE_ROWS = 256;      // rows of a block staged in LDS per pass
 
 struct LobDesc {
   int64_t a_off;    // d x d matrix (ld d)
   int64_t v_off;    // 6 blocks of d x s: X, AX, W, AW, P, AP (ld d)
   int64_t t_off;    // 2 blocks of d x s scratch
+  int64_t lock_off; // nl locked orthonormal eigenvectors (d x nl, ld d)
+  int nl;
   int d, s;
   int need;         // number of leading eigenpairs that must converge (>= 1)
   double tau;       // threshold: pairs with theta >= tau are needed, plus one below
@@ -149,6 +171,9 @@ __device__ double block_sum(double v, double *red) {
 
 // Symmetric eigen-decomposition of the n x n matrix H (LDS, ld LOB_MAXB+1) by
 // parallel cyclic Jacobi (round-robin pairing): H <- diag, V <- eigenvectors.
+// Sweeps stop when every off-diagonal entry is below 1e-15 sqrt(|h_pp h_qq|)
+// (relative accuracy for semidefinite H), or the off-diagonal mass is below
+// 1e-30 of the total, or after 20 sweeps.
 __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1], int n,
                            int *perm, double *cs, double *sn, double *red) {
   const int tid = threadIdx.x;
@@ -157,15 +182,20 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
   for (int i = tid; i < m; i += blockDim.x) perm[i] = i;
   __syncthreads();
   for (int sweep = 0; sweep < 20; ++sweep) {
-    double off = 0, tot = 0;
+    double off = 0, tot = 0, viol = 0;
     for (int i = tid; i < n * n; i += blockDim.x) {
-      const double h = H[i % n][i / n];
+      const int a = i % n, b = i / n;
+      const double h = H[a][b];
       tot += h * h;
-      if (i % n != i / n) off += h * h;
+      if (a != b) {
+        off += h * h;
+        if (fabs(h) > 1e-15 * sqrt(fabs(H[a][a] * H[b][b]))) viol += 1;
+      }
     }
     off = block_sum(off, red);
     tot = block_sum(tot, red);
-    if (off <= 1e-30 * tot || tot == 0) break;
+    viol = block_sum(viol, red);
+    if (viol == 0 || off <= 1e-30 * tot || tot == 0) break;
     for (int step = 0; step < m - 1; ++step) {
       // pairs (perm[k], perm[m-1-k]), k < m/2
       for (int k = tid; k < m / 2; k += blockDim.x) {
@@ -232,245 +262,320 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
   }
 }
 
-// One work-group per entry.  Basis blocks live in global memory; Gram and
-// projected matrices (at most 48 x 48) in LDS.
+// One work-group per entry.  The basis V = [X W P] is kept orthonormal
+// explicitly: W (the residuals) is orthogonalized against X and P by two
+// passes of block Gram-Schmidt, P (the W and P part of the new Ritz vectors)
+// against the new X, and each block is orthonormalized by the scaled
+// eigen-decomposition of its Gram matrix (columns of a near-dependent block
+// are dropped).  The Rayleigh-Ritz step is then the standard symmetric problem
+// V^T A V, solved in LDS by Jacobi rotations.  Blocks live in global memory;
+// every update of a block is row-owned (one thread writes a whole row), so
+// blocks are updated in place.
 __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc *desc,
                                                      LobOut *out, int maxit, double tol,
                                                      double tol_ind) {
-  __shared__ double G[LOB_MAXB][LOB_MAXB + 1];
-  __shared__ double H[LOB_MAXB][LOB_MAXB + 1];
-  __shared__ double Q[LOB_MAXB][LOB_MAXB + 1];
-  __shared__ double Y[LOB_MAXB][LOB_MAXB + 1];
-  __shared__ double theta[LOB_MAXB], gsc[LOB_MAXB], res[LOB_MAXB];
-  __shared__ double cs[LOB_MAXB], sn[LOB_MAXB], red[8];
+  __shared__ double Hs[LOB_MAXB][LOB_MAXB + 1];  // projected / Gram matrices
+  __shared__ double Qs[LOB_MAXB][LOB_MAXB + 1];  // their eigenvectors
+  __shared__ double Cs[LOB_MAXB][2 * LOB_S + 1]; // Ritz coefficients (X part, P part)
+  __shared__ double Ms[LOB_S][LOB_S + 1];        // orthonormalizing map of a block
+  __shared__ double stage[STAGE_ROWS * LOB_S];    // staged rows, or locked coefficients
+  __shared__ double theta[LOB_MAXB], gsc[LOB_MAXB], dinv[LOB_MAXB], res[LOB_S];
+  __shared__ double cs[LOB_MAXB / 2 + 1], sn[LOB_MAXB / 2 + 1], red[8];
   __shared__ int perm[LOB_MAXB + 2];
-  __shared__ int s_nb, s_keep, s_done;
+  __shared__ int s_keep, s_done;
   const LobDesc D = desc[blockIdx.x];
-  const int d = D.d, s = D.s, tid = threadIdx.x;
+  const int d = D.d, s = D.s, tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
   const double *A = pool + D.a_off;
   double *X = pool + D.v_off, *AX = X + (int64_t)d * s, *W = AX + (int64_t)d * s;
   double *AW = W + (int64_t)d * s, *P = AW + (int64_t)d * s, *AP = P + (int64_t)d * s;
-  double *T1 = pool + D.t_off, *T2 = T1 + (int64_t)d * s;
-  // blocks of the basis: 0 = X, 1 = W, 2 = P
-  auto blk = [&](int b) -> double * { return b == 0 ? X : (b == 1 ? W : P); };
-  auto ablk = [&](int b) -> double * { return b == 0 ? AX : (b == 1 ? AW : AP); };
-  // AX = A X (X holds the initial block)
-  auto matblock = [&](const double *in, double *o) {
-    for (int i = tid; i < d * s; i += blockDim.x) {
-      const int r = i % d, q = i / d;
+  double *T1 = pool + D.t_off;
+  const double *YL = pool + D.lock_off;
+  const int nl = D.nl;
+  int nw = 0, npc = 0;  // columns held in W and P
+
+  // o[a * ldo + b] = U[:, a] . V[:, b]  (one wave per entry)
+  auto dots = [&](const double *U, int nu, const double *V, int nv, double *o, int ldo) {
+    for (int i = wave; i < nu * nv; i += nwave) {
+      const int a = i % nu, b = i / nu;
+      const double *u = U + (int64_t)a * d, *v = V + (int64_t)b * d;
       double acc = 0;
-      for (int c = 0; c < d; ++c) acc += A[r + (int64_t)c * d] * in[c + (int64_t)q * d];
-      o[i] = acc;
+      for (int r = lane; r < d; r += 64) acc += u[r] * v[r];
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (lane == 0) o[a * ldo + b] = acc;
     }
+    __syncthreads();
   };
-  int it = 0, nconv = 0, have_p = 0;
-  bool done = false;
-  // Rayleigh-Ritz on [X] first to get theta and an orthonormal X
-  for (it = 0; it <= maxit; ++it) {
-    const int nb = (it == 0) ? 1 : (have_p ? 3 : 2);
-    if (it == 0) {
-      matblock(X, AX);
-      __syncthreads();
-    } else {
-      // W = AX - X theta (residuals), norms
-      for (int i = tid; i < d * s; i += blockDim.x) {
-        const int q = i / d;
-        W[i] = AX[i] - X[i] * theta[q];
-      }
-      __syncthreads();
-      for (int q = 0; q < s; ++q) {
-        double acc = 0;
-        for (int r = tid; r < d; r += blockDim.x) acc += W[r + (int64_t)q * d] * W[r + (int64_t)q * d];
-        acc = block_sum(acc, red);
-        if (tid == 0) res[q] = sqrt(acc);
-      }
-      __syncthreads();
-      // convergence of the leading pairs that matter: those >= tau and the
-      // first one below (or the 'need' leading ones)
-      // the pairs with theta >= tau must converge to tol; the first one
-      // below tau only sets the indicator and converges to tol_ind
-      if (tid == 0) {
-        int k = 0, ok = 1;
-        for (k = 0; k < s; ++k) {
-          const bool selected = theta[k] >= D.tau;
-          const bool needed = (k < D.need) || (k == 0) || (theta[k - 1] >= D.tau);
-          if (!needed) break;
-          const double t = selected ? tol : tol_ind;
-          if (res[k] > t * fmax(fabs(theta[k]), 1.0)) ok = 0;
-        }
-        nconv = k;
-        s_done = ok;
-      }
-      __syncthreads();
-      if (s_done || it == maxit) {
-        done = s_done;
-        break;
-      }
-      // unit columns in W and P keep the Gram matrix free of scale disparity
-      // as the residuals shrink (otherwise the g^-1/2 basis loses accuracy)
-      for (int q = 0; q < s; ++q) {
-        double pn = 0;
-        if (have_p)
-          for (int r = tid; r < d; r += blockDim.x) pn += P[r + (int64_t)q * d] * P[r + (int64_t)q * d];
-        pn = block_sum(pn, red);
-        if (tid == 0) gsc[q] = (have_p && pn > 0) ? 1.0 / sqrt(pn) : 1.0;
-      }
-      __syncthreads();
-      for (int i = tid; i < d * s; i += blockDim.x) {
-        const int q = i / d;
-        if (res[q] > 0) W[i] /= res[q];
-        if (have_p) {
-          P[i] *= gsc[q];
-          AP[i] *= gsc[q];
+  // V[:, b] -= sum_a U[:, a] c[a * ldc + b] for b < nv (AV -= AU c alongside)
+  auto sub_prod = [&](double *V, double *AV, int nv, const double *U, const double *AU, int nu,
+                      const double *c, int ldc) {
+    for (int r = tid; r < d; r += nt) {
+      double acc[LOB_S], aacc[LOB_S];
+#pragma unroll
+      for (int q = 0; q < LOB_S; ++q) acc[q] = aacc[q] = 0;
+      for (int a = 0; a < nu; ++a) {
+        const double u = U[r + (int64_t)a * d];
+        const double au = AV ? AU[r + (int64_t)a * d] : 0.0;
+#pragma unroll
+        for (int q = 0; q < LOB_S; ++q) {
+          if (q < nv) {
+            acc[q] += u * c[a * ldc + q];
+            aacc[q] += au * c[a * ldc + q];
+          }
         }
       }
-      __syncthreads();
-      matblock(W, AW);
-      __syncthreads();
-    }
-    // Gram G = V^T V and H = V^T A V over the nb blocks
-    const int n = nb * s;
-    for (int i = tid; i < n * n; i += blockDim.x) {
-      const int a = i % n, b = i / n;
-      if (a > b) continue;
-      const double *va = blk(a / s) + (int64_t)(a % s) * d;
-      const double *vb = blk(b / s) + (int64_t)(b % s) * d;
-      const double *ab = ablk(b / s) + (int64_t)(b % s) * d;
-      double g = 0, h = 0;
-      for (int r = 0; r < d; ++r) {
-        g += va[r] * vb[r];
-        h += va[r] * ab[r];
-      }
-      G[a][b] = G[b][a] = g;
-      H[a][b] = h;
-      H[b][a] = h;
-    }
-    __syncthreads();
-    // symmetrize H (A V computed in rounding, V^T A V slightly asymmetric)
-    for (int i = tid; i < n * n; i += blockDim.x) {
-      const int a = i % n, b = i / n;
-      if (a < b) {
-        const double m = 0.5 * (H[a][b] + H[b][a]);
-        H[a][b] = H[b][a] = m;
+#pragma unroll
+      for (int q = 0; q < LOB_S; ++q) {
+        if (q < nv) {
+          V[r + (int64_t)q * d] -= acc[q];
+          if (AV) AV[r + (int64_t)q * d] -= aacc[q];
+        }
       }
     }
     __syncthreads();
-    // G = Q diag(g) Q^T; keep g > 1e-13 g_max; Hh = g^-1/2 Q^T H Q g^-1/2
-    // (Q's columns in Q, eigenvalues on the diagonal of G afterwards)
-    jacobi_eig(G, Q, n, perm, cs, sn, red);
+  };
+  // V[:, 0..kp) = V[:, 0..nv) M  (M in Ms)
+  auto right_mul = [&](double *V, int nv, int kp) {
+    for (int r = tid; r < d; r += nt) {
+      double acc[LOB_S];
+#pragma unroll
+      for (int q = 0; q < LOB_S; ++q) acc[q] = 0;
+      for (int b = 0; b < nv; ++b) {
+        const double v = V[r + (int64_t)b * d];
+#pragma unroll
+        for (int q = 0; q < LOB_S; ++q)
+          if (q < kp) acc[q] += v * Ms[b][q];
+      }
+#pragma unroll
+      for (int q = 0; q < LOB_S; ++q)
+        if (q < kp) V[r + (int64_t)q * d] = acc[q];
+    }
+    __syncthreads();
+  };
+  // orthonormalize the nv columns of V (AV alongside when given): with
+  // Dg = diag(G)^-1/2, Dg G Dg = Q diag(g) Q^T, V <- V Dg Q g^-1/2 over g > thr.
+  // Returns the number of columns kept.
+  auto svqb = [&](double *V, double *AV, int nv, double thr) -> int {
+    if (nv == 0) return 0;
+    dots(V, nv, V, nv, &Hs[0][0], LOB_MAXB + 1);
+    for (int a = tid; a < nv; a += nt) dinv[a] = Hs[a][a] > 0 ? 1.0 / sqrt(Hs[a][a]) : 0.0;
+    __syncthreads();
+    for (int i = tid; i < nv * nv; i += nt) {
+      const int a = i % nv, b = i / nv;
+      Hs[a][b] *= dinv[a] * dinv[b];
+    }
+    __syncthreads();
+    jacobi_eig(Hs, Qs, nv, perm, cs, sn, red);
     if (tid == 0) {
-      double gmax = 0;
-      for (int a = 0; a < n; ++a) gmax = fmax(gmax, G[a][a]);
       int keep = 0;
-      for (int a = 0; a < n; ++a) {
-        if (G[a][a] > 1e-13 * gmax) {
+      for (int a = 0; a < nv; ++a)
+        if (Hs[a][a] > thr) {
           perm[keep] = a;
-          gsc[keep] = 1.0 / sqrt(G[a][a]);
+          gsc[keep] = 1.0 / sqrt(Hs[a][a]);
           ++keep;
         }
-      }
       s_keep = keep;
     }
     __syncthreads();
     const int kp = s_keep;
-    // Y <- H Q_keep g^-1/2   (n x kp)
-    for (int i = tid; i < n * kp; i += blockDim.x) {
-      const int a = i % n, b = i / n;
-      double acc = 0;
-      for (int c = 0; c < n; ++c) acc += H[a][c] * Q[c][perm[b]];
-      Y[a][b] = acc * gsc[b];
+    for (int i = tid; i < nv * kp; i += nt) {
+      const int b = i % nv, q = i / nv;
+      Ms[b][q] = dinv[b] * Qs[b][perm[q]] * gsc[q];
     }
     __syncthreads();
-    // G <- g^-1/2 Q_keep^T Y  (kp x kp), reusing G as the projected matrix
-    for (int i = tid; i < kp * kp; i += blockDim.x) {
-      const int a = i % kp, b = i / kp;
-      double acc = 0;
-      for (int c = 0; c < n; ++c) acc += Q[c][perm[a]] * Y[c][b];
-      G[a][b] = acc * gsc[a];
-    }
-    __syncthreads();
-    // keep the map from projected coordinates back to V: Mv = Q_keep g^-1/2
-    // (n x kp) stored in H (H is free now)
-    for (int i = tid; i < n * kp; i += blockDim.x) {
-      const int a = i % n, b = i / n;
-      H[a][b] = Q[a][perm[b]] * gsc[b];
-    }
-    __syncthreads();
-    // symmetrize, eigen-decompose the projected matrix (eigenvectors in Q)
-    for (int i = tid; i < kp * kp; i += blockDim.x) {
-      const int a = i % kp, b = i / kp;
-      if (a < b) {
-        const double m = 0.5 * (G[a][b] + G[b][a]);
-        G[a][b] = G[b][a] = m;
+    right_mul(V, nv, kp);
+    if (AV) right_mul(AV, nv, kp);
+    return kp;
+  };
+  // V <- V - YL (YL^T V): keep a block orthogonal to the locked vectors
+  auto project_locked = [&](double *V, int nv) {
+    if (nl == 0 || nv == 0) return;
+    dots(YL, nl, V, nv, stage, LOB_S);
+    sub_prod(V, nullptr, nv, YL, nullptr, nl, stage, LOB_S);
+  };
+  // AV = A V for nv columns; V staged through LDS in chunks of rows
+  auto apply_A = [&](const double *V, double *AV, int nv) {
+    for (int r0 = 0; r0 < d; r0 += nt) {
+      const int r = r0 + tid;
+      double acc[LOB_S];
+#pragma unroll
+      for (int q = 0; q < LOB_S; ++q) acc[q] = 0;
+      for (int c0 = 0; c0 < d; c0 += STAGE_ROWS) {
+        const int cn = min(STAGE_ROWS, d - c0);
+        __syncthreads();
+        for (int i = tid; i < cn * LOB_S; i += nt) {
+          const int c = i % cn, q = i / cn;
+          stage[c * LOB_S + q] = q < nv ? V[c0 + c + (int64_t)q * d] : 0.0;
+        }
+        __syncthreads();
+        if (r < d) {
+          for (int c = 0; c < cn; ++c) {
+            const double a = A[r + (int64_t)(c0 + c) * d];
+#pragma unroll
+            for (int q = 0; q < LOB_S; ++q) acc[q] += a * stage[c * LOB_S + q];
+          }
+        }
       }
+      if (r < d)
+        for (int q = 0; q < nv; ++q) AV[r + (int64_t)q * d] = acc[q];
     }
     __syncthreads();
-    jacobi_eig(G, Q, kp, perm, cs, sn, red);
-    // order eigenvalues descending: perm holds the ordering
+  };
+  // column b of V = [X W P] and of A V
+  auto vcol = [&](int b) -> const double * {
+    return b < s ? X + (int64_t)b * d
+                 : (b < s + nw ? W + (int64_t)(b - s) * d : P + (int64_t)(b - s - nw) * d);
+  };
+  auto avcol = [&](int b) -> const double * {
+    return b < s ? AX + (int64_t)b * d
+                 : (b < s + nw ? AW + (int64_t)(b - s) * d : AP + (int64_t)(b - s - nw) * d);
+  };
+  // Rayleigh-Ritz on the current n = s + nw + npc columns: theta, and the
+  // coefficients of the new X (Cs[:, 0..s)) and of the new P (Cs[:, s..2s):
+  // the same vectors without their X rows)
+  auto rayleigh_ritz = [&](int n) {
+    for (int i = wave; i < n * n; i += nwave) {
+      const int a = i % n, b = i / n;
+      if (a > b) continue;
+      const double *va = vcol(a), *vb = vcol(b), *aa = avcol(a), *ab = avcol(b);
+      double h1 = 0, h2 = 0;
+      for (int r = lane; r < d; r += 64) {
+        h1 += va[r] * ab[r];
+        h2 += vb[r] * aa[r];
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        h1 += __shfl_xor(h1, off, 64);
+        h2 += __shfl_xor(h2, off, 64);
+      }
+      if (lane == 0) Hs[a][b] = Hs[b][a] = 0.5 * (h1 + h2);
+    }
+    __syncthreads();
+    jacobi_eig(Hs, Qs, n, perm, cs, sn, red);
     if (tid == 0) {
-      for (int a = 0; a < kp; ++a) perm[a] = a;
-      for (int a = 0; a < kp; ++a)
-        for (int b = a + 1; b < kp; ++b)
-          if (G[perm[b]][perm[b]] > G[perm[a]][perm[a]]) {
-            int t = perm[a];
+      for (int a = 0; a < n; ++a) perm[a] = a;
+      for (int a = 0; a < s; ++a)
+        for (int b = a + 1; b < n; ++b)
+          if (Hs[perm[b]][perm[b]] > Hs[perm[a]][perm[a]]) {
+            const int t = perm[a];
             perm[a] = perm[b];
             perm[b] = t;
           }
-      for (int q = 0; q < s; ++q) theta[q] = (q < kp) ? G[perm[q]][perm[q]] : 0.0;
-      s_nb = nb;
+      for (int q = 0; q < s; ++q) theta[q] = Hs[perm[q]][perm[q]];
     }
     __syncthreads();
-    // coefficients of the new X in V: C = Mv Q[:, top s]  (n x s), in Y
-    for (int i = tid; i < n * s; i += blockDim.x) {
-      const int a = i % n, q = i / n;
-      double acc = 0;
-      if (q < kp)
-        for (int c = 0; c < kp; ++c) acc += H[a][c] * Q[c][perm[q]];
-      Y[a][q] = acc;
+    for (int i = tid; i < n * s; i += nt) {
+      const int b = i % n, q = i / n;
+      const double c = Qs[b][perm[q]];
+      Cs[b][q] = c;
+      Cs[b][LOB_S + q] = b < s ? 0.0 : c;
     }
     __syncthreads();
-    // new X = V C and its A-image into the scratch blocks T1, T2
-    for (int i = tid; i < d * s; i += blockDim.x) {
-      const int r = i % d, q = i / d;
-      double x = 0, ax = 0;
-      for (int b = 0; b < n; ++b) {
-        const double c = Y[b][q];
-        const int bb = b / s, col = b % s;
-        x += c * blk(bb)[r + (int64_t)col * d];
-        ax += c * ablk(bb)[r + (int64_t)col * d];
-      }
-      T1[i] = x;
-      T2[i] = ax;
-    }
-    __syncthreads();
-    if (nb > 1) {
-      // new P = the W and P part of V C; written into the X / AX slots first
-      // (the old X is not read by this pass, the old W and P still are)
-      for (int i = tid; i < d * s; i += blockDim.x) {
-        const int r = i % d, q = i / d;
-        double p = 0, ap = 0;
-        for (int b = s; b < n; ++b) {
-          const double c = Y[b][q];
-          const int bb = b / s, col = b % s;
-          p += c * blk(bb)[r + (int64_t)col * d];
-          ap += c * ablk(bb)[r + (int64_t)col * d];
+  };
+  // X <- V Cx, P <- V Cp and their images (row-owned, in place)
+  auto ritz_update = [&](int n, bool with_p) {
+    for (int pass = 0; pass < 2; ++pass) {
+      double *XO = pass ? AX : X, *PO = pass ? AP : P;
+      for (int r = tid; r < d; r += nt) {
+        double ax[LOB_S], ap[LOB_S];
+#pragma unroll
+        for (int q = 0; q < LOB_S; ++q) ax[q] = ap[q] = 0;
+        for (int b = 0; b < n; ++b) {
+          const double v = (pass ? avcol(b) : vcol(b))[r];
+#pragma unroll
+          for (int q = 0; q < LOB_S; ++q) {
+            ax[q] += v * Cs[b][q];
+            ap[q] += v * Cs[b][LOB_S + q];
+          }
         }
-        X[i] = p;
-        AX[i] = ap;
+#pragma unroll
+        for (int q = 0; q < LOB_S; ++q) {
+          if (q < s) {
+            XO[r + (int64_t)q * d] = ax[q];
+            if (with_p) PO[r + (int64_t)q * d] = ap[q];
+          }
+        }
       }
-      __syncthreads();
-      for (int i = tid; i < d * s; i += blockDim.x) {
-        P[i] = X[i];
-        AP[i] = AX[i];
-      }
-      have_p = 1;
       __syncthreads();
     }
-    for (int i = tid; i < d * s; i += blockDim.x) {
-      X[i] = T1[i];
-      AX[i] = T2[i];
+  };
+
+  int it = 0, nconv = 0;
+  bool done = false;
+  for (int q = tid; q < LOB_MAXB; q += nt) theta[q] = 0;
+  __syncthreads();
+  // start block: orthonormal and orthogonal to the locked vectors
+  int kx = s;
+  for (int pass = 0; pass < 2 && kx == s; ++pass) {
+    project_locked(X, s);
+    kx = svqb(X, nullptr, s, 1e-10);
+  }
+  if (kx == s) {
+    apply_A(X, AX, s);
+    rayleigh_ritz(s);
+    ritz_update(s, false);
+  }
+  for (it = 1; it <= maxit && kx == s; ++it) {
+    // residuals W = A X - X theta and their norms
+    for (int i = tid; i < d * s; i += nt) W[i] = AX[i] - X[i] * theta[i / d];
+    __syncthreads();
+    project_locked(W, s);
+    for (int q = wave; q < s; q += nwave) {
+      double acc = 0;
+      for (int r = lane; r < d; r += 64) acc += W[r + (int64_t)q * d] * W[r + (int64_t)q * d];
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (lane == 0) res[q] = sqrt(acc);
     }
     __syncthreads();
+    // the pairs with theta >= tau must converge to tol; the first one below
+    // tau only sets the indicator and converges to tol_ind
+    if (tid == 0) {
+      int k = 0, ok = 1;
+      for (k = 0; k < s; ++k) {
+        const bool selected = theta[k] >= D.tau;
+        const bool needed = (k < D.need) || (k == 0) || (theta[k - 1] >= D.tau);
+        if (!needed) break;
+        const double t = selected ? tol : tol_ind;
+        if (res[k] > t * fmax(fabs(theta[k]), 1.0)) ok = 0;
+      }
+      nconv = k;
+      s_done = ok;
+    }
+    __syncthreads();
+    if (s_done) {
+      done = true;
+      break;
+    }
+    if (it == maxit) break;
+    // search directions: unit residuals, orthonormal and orthogonal to X, P
+    for (int i = tid; i < d * s; i += nt) {
+      const int q = i / d;
+      W[i] = res[q] > 0 ? W[i] / res[q] : 0.0;
+    }
+    __syncthreads();
+    nw = s;
+    for (int pass = 0; pass < 2 && nw > 0; ++pass) {
+      project_locked(W, nw);
+      dots(X, s, W, nw, &Cs[0][0], 2 * LOB_S + 1);
+      sub_prod(W, nullptr, nw, X, nullptr, s, &Cs[0][0], 2 * LOB_S + 1);
+      if (npc > 0) {
+        dots(P, npc, W, nw, &Cs[0][0], 2 * LOB_S + 1);
+        sub_prod(W, nullptr, nw, P, nullptr, npc, &Cs[0][0], 2 * LOB_S + 1);
+      }
+      nw = svqb(W, nullptr, nw, 1e-10);
+    }
+    if (nw == 0 && npc == 0) break;  // no direction left: stagnation
+    apply_A(W, AW, nw);
+    const int n = s + nw + npc;
+    rayleigh_ritz(n);
+    ritz_update(n, true);
+    // P: orthogonal to the new X, orthonormal
+    npc = s;
+    for (int pass = 0; pass < 2 && npc > 0; ++pass) {
+      dots(X, s, P, npc, &Cs[0][0], 2 * LOB_S + 1);
+      sub_prod(P, AP, npc, X, AX, s, &Cs[0][0], 2 * LOB_S + 1);
+      npc = svqb(P, AP, npc, 1e-10);
+    }
+    nw = 0;
   }
   if (tid == 0) {
     out[blockIdx.x].iters = it;
@@ -479,7 +584,7 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
   }
   // eigenvalues into the first column of T1 for the host
   __syncthreads();
-  for (int q = tid; q < s; q += blockDim.x) T1[q] = theta[q];
+  for (int q = tid; q < s; q += nt) T1[q] = theta[q];
 }
 
 }  // namespace
@@ -555,7 +660,16 @@ void orthonormalize(std::vector<double> &Q, int n, int &k) {
 AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   AdaptResult res;
   hipStream_t stream = S.stream;
+  const auto t_start = std::chrono::steady_clock::now();
+  auto log = [&](const char *what) {
+    if (!S.verbose) return;
+    HIPCHK(hipStreamSynchronize(stream));
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    std::fprintf(stderr, "[bddc adapt %8.3f s] %s\n", el, what);
+    std::fflush(stderr);
+  };
   S.factor_schur();  // Schur complements S_i (original basis) in S.d_S
+  log("schur complements");
   const Layout &L = S.L;
   const int dpn = P.mesh.dpn;
   const int nf = (int)P.face_ids.size();
@@ -661,6 +775,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   }
   const int np = (int)pairs.size();
   res.n_pairs = np;
+  log("pair index data (host)");
   if (np == 0) return res;
 
   // ---- device stage 1: Schur complements of S_i onto each pair's shared dofs
@@ -722,11 +837,25 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   GemmDesc *d_gsh = pool.up(stream, gsh);
   int *d_stat = pool.up(stream, std::vector<int>(3 * np + 2 * nside + 4, 0));
   HIPCHK(DenseOps<double>::potrf(stream, Snn, d_mdn, mdn.data(), nside, d_stat));
+  auto check = [&](int first, int count, const char *what) {
+    std::vector<int> hs(count);
+    HIPCHK(hipMemcpyAsync(hs.data(), d_stat + first, sizeof(int) * count, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    int bad = 0, firstbad = -1;
+    for (int e = 0; e < count; ++e)
+      if (hs[e]) bad++, firstbad = firstbad < 0 ? e : firstbad;
+    if (bad)
+      throw NotSpdError(std::string("adaptive pair problems: ") + what + ": " + std::to_string(bad) +
+                        " factors with a non-positive pivot (first entry " + std::to_string(firstbad) +
+                        "); Assumption 2 may not hold");
+  };
+  check(0, nside, "non-shared interface blocks");
   HIPCHK(DenseOps<double>::trsm(stream, Snn, Sns, d_mdn, mdn.data(), nside, false));
   // Sh gets the Schur complement; Sns and Sh live in different pools
   HIPCHK(DenseOps<double>::gemm(stream, Sns, Sns, Sh, d_gsh, nside, max_ns, max_ns, true, false,
                                 -1.0, 1.0, false));
 
+  log("pair Schur complements");
   // ---- stage 2: parallel sum and the reduced pair matrices
   std::vector<int64_t> off_i(np), off_j(np), off_p(np), q_off(np), off_c(np), c_off(np), off_z(np),
       off_cz(np), off_dd(np);
@@ -785,14 +914,16 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   GemmDesc *d_gbj = pool.up(stream, gbj);
   int *stat2 = d_stat + nside;
   HIPCHK(DenseOps<double>::potrf(stream, Ssum, d_mds, mds.data(), np, stat2));
+  check(nside, np, "sum of the Schur complements");
   HIPCHK(DenseOps<double>::trsm(stream, Ssum, Xb, d_mds, mds.data(), np, false));
   HIPCHK(DenseOps<double>::trsm(stream, Ssum, Xb, d_mds, mds.data(), np, true));
-  // BJ = Sh_i - Sh_i X   (A = Sh pool, B = Xb pool, C = BJf pool)
-  {
-    // the gemm wrapper takes one pool per operand
-    HIPCHK(DenseOps<double>::gemm(stream, Sh, Xb, BJf, d_gbj, np, max_sp, max_sp, false, false,
-                                  -1.0, 1.0, false));
-  }
+  // BJ = Sh_i (Sh_i + Sh_j)^+ Sh_j, the product form of the parallel sum (no
+  // cancellation between the two large terms of Sh_i - Sh_i (..)^+ Sh_i when
+  // the coefficients of i and j differ by orders of magnitude)
+  HIPCHK(DenseOps<double>::gemm(stream, Sh, Xb, BJf, d_gbj, np, max_sp, max_sp, false, false, 1.0,
+                                0.0, false));
+  symmetrize_kernel<<<dim3(nblocks((int64_t)max_sp * max_sp), np), TPB, 0, stream>>>(BJf, d_off_p, d_nsp);
+  HIPCHK(hipGetLastError());
   double *Mc = pool.zeros(stream, tc), *BJc = pool.zeros(stream, tc);
   int *d_call = pool.up(stream, call), *d_nc = pool.up(stream, ncv);
   int64_t *d_c_off = pool.up(stream, c_off), *d_off_c = pool.up(stream, off_c);
@@ -825,14 +956,21 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   int *d_dv = pool.up(stream, dv);
   int *stat3 = stat2 + np;
   HIPCHK(DenseOps<double>::potrf(stream, By, d_mdd, mdd.data(), np, stat3));
+  check(nside + np, np, "jump-space denominator");
   // My <- L^-1 My ; Cp <- My^T ; Cp <- L^-1 Cp   (My's pool is the B operand)
   HIPCHK(DenseOps<double>::trsm(stream, By, My, d_mdd, mdd.data(), np, false));
   transpose_kernel<<<dim3(nblocks((int64_t)max_d * max_d), np), TPB, 0, stream>>>(My, Cp, d_off_dd, d_dv);
   HIPCHK(hipGetLastError());
   HIPCHK(DenseOps<double>::trsm(stream, By, Cp, d_mdd, mdd.data(), np, false));
+  // the two solves leave C' symmetric only to ~kappa(By) eps; LOBPCG's
+  // residuals cannot drop below that asymmetry, so C' is symmetrized
+  symmetrize_kernel<<<dim3(nblocks((int64_t)max_d * max_d), np), TPB, 0, stream>>>(Cp, d_off_dd, d_dv);
+  HIPCHK(hipGetLastError());
 
-  // ---- stage 3: batched LOBPCG on C', with spectral deflation when a block
-  // holds only eigenvalues >= tau (C' <- C' - X Theta X^T, run again)
+  log("reduced pair matrices");
+  // ---- stage 3: batched LOBPCG on C'.  When a block holds only eigenvalues
+  // >= tau, its vectors are locked and the pair runs again on the orthogonal
+  // complement of every locked vector.
   const int s_max = LOB_MAXB / 3;
   std::vector<LobDesc> ld(np);
   int64_t tv = 0, ty = 0;
@@ -849,9 +987,9 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
     off_y[p] = ty;
     ty += (int64_t)dv[p] * dv[p];  // room for every eigenvector of the pair
   }
-  double *LP = pool.zeros(stream, tdd + tv);
+  double *LP = pool.zeros(stream, tdd + tv + ty);
   HIPCHK(hipMemcpyAsync(LP, Cp, sizeof(double) * tdd, hipMemcpyDeviceToDevice, stream));
-  double *Yv = pool.zeros(stream, ty);
+  double *Yv = LP + tdd + tv;  // selected eigenvectors, also the locked block
   for (int p = 0; p < np; ++p) {
     ld[p].v_off = tdd + xoff[p];
     ld[p].t_off = tdd + xoff[p] + (int64_t)6 * dv[p] * ld[p].s;
@@ -864,7 +1002,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   ldb.bytes = sizeof(LobDesc) * np;
   ldb.p = S.alloc.get(ldb.bytes);
   pool.bufs.push_back(ldb);
-  const int maxit = 2000;
+  const int maxit = 1000;
   const double tol = 1e-8, tol_ind = 1e-5;
   std::vector<int> ksel(np, 0), active(np);
   std::vector<std::vector<double>> evs(np);
@@ -872,13 +1010,21 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   for (int round = 0; round < 64 && !active.empty(); ++round) {
     const int na = (int)active.size();
     std::vector<LobDesc> lda(na);
-    std::vector<double> X0all;
+    std::vector<int64_t> x0off(na + 1, 0);
+    for (int a = 0; a < na; ++a) {
+      const int p = active[a];
+      x0off[a + 1] = x0off[a] + (int64_t)dv[p] * std::min(dv[p] - ksel[p], s_max);
+    }
+    std::vector<double> X0all(x0off[na]);
     for (int a = 0; a < na; ++a) {
       const int p = active[a];
       ld[p].s = std::min(dv[p] - ksel[p], s_max);
+      ld[p].lock_off = tdd + tv + off_y[p];
+      ld[p].nl = ksel[p];
+      if (ksel[p] > LOCK_MAX) throw ArgError("more than 256 adaptive rows on one face");
       lda[a] = ld[p];
       // seeded start block (splitmix64 of face, round, column, row)
-      std::vector<double> x0((size_t)dv[p] * ld[p].s);
+      double *x0 = X0all.data() + x0off[a];
       for (int q = 0; q < ld[p].s; ++q)
         for (int r = 0; r < dv[p]; ++r) {
           uint64_t z = 0x9E3779B97F4A7C15ull *
@@ -888,10 +1034,8 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
           z ^= z >> 31;
           x0[(size_t)q * dv[p] + r] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
         }
-      HIPCHK(hipMemcpyAsync(LP + ld[p].v_off, x0.data(), sizeof(double) * x0.size(),
+      HIPCHK(hipMemcpyAsync(LP + ld[p].v_off, x0, sizeof(double) * (x0off[a + 1] - x0off[a]),
                             hipMemcpyHostToDevice, stream));
-      X0all.swap(x0);
-      HIPCHK(hipStreamSynchronize(stream));
     }
     HIPCHK(hipMemcpyAsync(ldb.p, lda.data(), sizeof(LobDesc) * na, hipMemcpyHostToDevice, stream));
     lobpcg_kernel<<<na, 256, 0, stream>>>(LP, ldb.as<LobDesc>(), outb.as<LobOut>(), maxit, tol,
@@ -924,27 +1068,25 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
       ksel[p] += k;
       if (k < s) {
         res.omega = std::max(res.omega, th[a][k]);
-      } else if (ksel[p] < dv[p]) {
-        next.push_back(p);
-        // deflate: C' <- C' - (X Theta) X^T, X Theta built in the T1 scratch
-        std::vector<double> hx((size_t)dv[p] * s);
-        HIPCHK(hipMemcpyAsync(hx.data(), LP + ld[p].v_off, sizeof(double) * hx.size(),
-                              hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
-        for (int q = 0; q < s; ++q)
-          for (int r = 0; r < dv[p]; ++r) hx[(size_t)q * dv[p] + r] *= th[a][q];
-        HIPCHK(hipMemcpyAsync(LP + ld[p].t_off, hx.data(), sizeof(double) * hx.size(),
-                              hipMemcpyHostToDevice, stream));
-        gdef.push_back(GemmDesc{ld[p].t_off, ld[p].v_off, off_dd[p], dv[p], dv[p], s, dv[p], dv[p],
-                                dv[p]});
+      } else if (ksel[p] < dv[p] && lo[a].converged) {
+        next.push_back(p);  // the block held only selected pairs: lock them, go on
       }
     }
-    if (!gdef.empty()) {
-      GemmDesc *d_gdef = pool.up(stream, gdef);
-      int mx = 0;
-      for (auto &g : gdef) mx = std::max(mx, g.M);
-      HIPCHK(DenseOps<double>::gemm(stream, LP, LP, LP, d_gdef, (int)gdef.size(), mx, mx, false, true,
-                                    -1.0, 1.0, false));
+    if (S.verbose) {
+      int mx = 0, nu = 0;
+      std::string bad;
+      for (int a = 0; a < na; ++a) {
+        mx = std::max(mx, lo[a].iters);
+        if (!lo[a].converged) {
+          nu++;
+          if (nu <= 12) bad += " " + std::to_string(pairs[active[a]].f) + "(nconv " +
+                               std::to_string(lo[a].nconv) + ")";
+        }
+      }
+      char buf[200];
+      std::snprintf(buf, sizeof buf, "LOBPCG round %d: %d pairs, max iters %d, unconverged %d, continuing %d;",
+                    round, na, mx, nu, (int)next.size());
+      log((std::string(buf) + bad).c_str());
     }
     active.swap(next);
   }

@@ -84,6 +84,7 @@ bddc_status bddc_create(const bddc_options *opt, bddc_ctx **out) {
     c->S->alloc.alloc = c->opt.alloc;
     c->S->alloc.free = c->opt.free;
     c->S->alloc.user = c->opt.alloc_user;
+    c->S->verbose = c->opt.verbose;
   });
   if (st != BDDC_OK) return st;
   *out = c.release();

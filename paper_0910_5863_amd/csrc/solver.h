@@ -95,6 +95,7 @@ class Solver {
   double factor_seconds = 0, factor_flops = 0;
   std::vector<double> last_history;
   Timer timer;
+  int verbose = 0;
 
   ~Solver();
   void build(const Problem &P, hipStream_t st);
