@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Adaptive BDDC-PCG throughput on one MI355X.
+
+Workload: 3D linear elasticity (Q1 hexahedra, 3 dofs per node) on 48^3
+elements in 4 x 4 x 4 cubic substructures of 12^3 elements; Young's modulus
+1 or 1e6 per horizontal layer (seeded), nu = 0.3, clamped at z = 0, gravity
+load; corner and edge-average constraints plus adaptive face constraints with
+tau = 10 (Algorithm 1); FP64; PCG to a relative residual of 1e-8.
+
+One step is one pass of the whole hot path over the problem:
+bddc_adapt(tau) (Dirichlet factors, Schur complements, face-pair
+eigenproblems, constraint rows) -> bddc_factor (change of variables,
+constrained factors, coarse problem) -> bddc_pcg_solve(f).  The problem
+(substructure matrices, interface analysis) is set up and resident on the
+device before the timed region, and so is the load vector.
+
+The output is one JSON line.  `roofline` describes the kernel with the
+largest summed time in the timed steps, measured per launch with HIP events
+on the library's stream; `cpu_baseline` is the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+TAU = 10.0
+RTOL = 1e-8
+PEAK_FP64_MFMA = 78.6      # TFLOP/s, MI355X dense FP64 matrix
+PEAK_HBM = 8000.0          # GB/s, MI355X HBM3E
+# kernels whose work is a dense contraction on the matrix cores
+MFMA_KERNELS = ("gemm_kernel", "chol_update_kernel", "chol_panel_kernel", "chol_diag_kernel",
+                "trsm_update_kernel<fwd>", "trsm_update_kernel<bwd>", "trsm_diag_kernel<fwd>",
+                "trsm_diag_kernel<bwd>")
+KERNEL_SOURCE = {k: "paper_0910_5863_amd/csrc/dense.hip" for k in MFMA_KERNELS}
+KERNEL_SOURCE.update({"trsv_kernel<fwd>": "paper_0910_5863_amd/csrc/dense.hip",
+                      "trsv_kernel<bwd>": "paper_0910_5863_amd/csrc/dense.hip",
+                      "gemv_t_kernel": "paper_0910_5863_amd/csrc/solver.hip",
+                      "gemv_n_kernel": "paper_0910_5863_amd/csrc/solver.hip",
+                      "lobpcg_kernel": "paper_0910_5863_amd/csrc/adapt.hip"})
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle sample (about 15 s)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the steps, run one plain device copy of this many MiB "
+                         "(a known-size reference for hardware byte counters)")
+    return ap.parse_args()
+
+
+def source_sha(rel):
+    with open(os.path.join(ROOT, rel), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """Per-launch HBM bytes of `kernel` from the committed counter summary
+    (profiles/traffic_<kernel>_elasticity48.txt: FETCH_SIZE + WRITE_SIZE per dispatch,
+    scaled by a copy kernel of known size), or None when there is none or the
+    kernel's source changed since the counters were taken."""
+    safe = kernel.replace("<", "_").replace(">", "")
+    path = os.path.join(ROOT, "profiles", f"traffic_{safe}_elasticity48.txt")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCE:
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_sha(KERNEL_SOURCE[kernel]):
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline():
+    """The oracle's adapt + factor + solve on 4 of the 64 substructures: a
+    24 x 24 x 12-element block split 2 x 2 x 1 into 12^3-element substructures,
+    with the layered-coefficient recipe, clamped bottom and gravity of the
+    workload, tau = 10.  Per-substructure work dominates, so the step time is
+    scaled by 64 / 4."""
+    import numpy as np
+    import meshgen
+    from oracle.solver import OracleBDDC
+    from oracle.adapt import adapt, schur_dense
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    nel = (24, 24, 12)
+    coef = meshgen.coef_layers(nel, 2)
+    p = meshgen.cube_problem(meshgen.ELASTICITY, nel, (2, 2, 1), coef=coef, nu=0.3,
+                             dirichlet_face=("z", 0.0), name="elasticity_24x24x12_2x2x1_layers")
+    o = OracleBDDC(p, "ce")
+    t0 = time.perf_counter()
+    Sd = {s: schur_dense(o.S, o.itf, s) for s in range(o.S.n_sub)}
+    ad = adapt(o.S, o.itf, o.cons, TAU, Sd=Sd)
+    o2 = OracleBDDC(p, "ce", extra_face_rows=ad["rows"])
+    r = o2.solve(rtol=RTOL)
+    dt = time.perf_counter() - t0
+    if not r["converged"]:
+        raise RuntimeError("oracle sample did not converge")
+    scale = 64 / p.n_sub
+    return {"value": 1.0 / (dt * scale), "unit": "solves/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"oracle adapt+factor+solve on 4 of the 64 12^3-element substructures "
+                       f"(24x24x12 elements, 2x2x1, same layer recipe, tau=10): {dt:.2f} s, "
+                       f"{r['iters']} PCG iterations; time scaled by 64/4"),
+            "sample_seconds": dt}
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the substructure sharding across GPUs is a design, not an implementation)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_0910_5863_amd import BDDC
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    p = meshgen.elasticity_layers_48()
+    b = BDDC(device=0)
+    b.setup(p, "ce")
+    f = torch.from_numpy(p.f).to("cuda:0")
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def step(phases):
+        t0 = time.perf_counter()
+        ai = b.adapt(TAU)
+        t1 = time.perf_counter()
+        b.factor()
+        t2 = time.perf_counter()
+        u, info = b.pcg_solve(f, rtol=RTOL, maxit=1000)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if not info[0].converged:
+            raise RuntimeError("PCG did not converge")
+        if ai.unconverged:
+            raise RuntimeError(f"{ai.unconverged} face-pair eigenproblems did not converge")
+        phases.append((t1 - t0, t2 - t1, t3 - t2))
+        return ai, info[0]
+
+    warm = []
+    for _ in range(args.warmup):
+        step(warm)
+    torch.cuda.synchronize()
+    b.set_timing(2)
+    phases = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ai, pinfo = step(phases)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = b.timing()
+    b.set_timing(0)
+
+    # dominant kernel and its roofline
+    name, st = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    avg_s = st["ms"] / st["launches"] / 1e3
+    if name in MFMA_KERNELS:
+        achieved = st["flops"] / st["launches"] / avg_s / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_MFMA}
+    else:
+        achieved = st["bytes"] / st["launches"] / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM}
+    roof["traffic"] = measured_traffic(name)
+    roof["kernel"] = name
+    roof["launches"] = st["launches"]
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["algorithmic_bytes_per_launch"] = st["bytes"] / st["launches"]
+    roof["algorithmic_flops_per_launch"] = st["flops"] / st["launches"]
+    top = sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:8]
+    kernels = []
+    for k, v in top:
+        s_ = v["ms"] / 1e3
+        kernels.append({"kernel": k, "ms_per_step": v["ms"] / args.steps, "launches_per_step":
+                        v["launches"] / args.steps,
+                        "TFLOP/s": v["flops"] / s_ / 1e12 if s_ > 0 else None,
+                        "GB/s": v["bytes"] / s_ / 1e9 if s_ > 0 else None})
+
+    ms_per_step = elapsed / args.steps * 1e3
+    ph = np.array(phases)
+    i = b.info()
+    out = {
+        "metric": "BDDC-PCG solves/s to 1e-8 rel. residual",
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "elasticity48_4x4x4_layers_adaptive_tau10", "n_glob": int(p.n_glob),
+                   "n_sub": int(p.n_sub), "tau": TAU, "rtol": RTOL,
+                   "step": "adapt(tau) + factor + pcg_solve(f), problem set up and resident"},
+        "roofline": roof,
+        "phases_ms": {"adapt": float(ph[:, 0].mean() * 1e3), "factor": float(ph[:, 1].mean() * 1e3),
+                      "pcg_solve": float(ph[:, 2].mean() * 1e3)},
+        "resident_solves_per_s": float(1.0 / ph[:, 2].mean()),
+        "pcg_iters": int(pinfo.iters),
+        "kappa": float(pinfo.kappa),
+        "omega": float(ai.omega),
+        "nc": int(ai.nc),
+        "factor_flops_executed": float(i.factor_flops),
+        "device_gb": i.device_bytes / 1e9,
+        "kernels": kernels,
+        "cpu_baseline": None,
+    }
+    del b
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

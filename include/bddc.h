@@ -145,8 +145,11 @@ bddc_status bddc_setup(bddc_ctx *ctx, const bddc_mesh *mesh, const bddc_partitio
                        const bddc_constraints *cons);
 
 /* Algorithm 1: solve the face-pair eigenproblems on the GPU and add, on every
-   face, the rows of the eigenvectors with lambda >= tau (edge parts dropped).
-   Requires a prior bddc_setup; invalidates factors. */
+   face, the rows of the eigenvectors with lambda >= tau (edge parts dropped)
+   to the constraints chosen at bddc_setup.  Adaptive rows of an earlier call
+   are replaced, so the call may be repeated (e.g. for several tau).
+   Requires a prior bddc_setup; invalidates factors.  The Dirichlet factors
+   and Schur complements it computes are reused by the next bddc_factor. */
 bddc_status bddc_adapt(bddc_ctx *ctx, double tau, bddc_adapt_info *info);
 
 /* Factor: Dirichlet factors A_II, Schur complements, constrained local factors,
@@ -191,13 +194,18 @@ bddc_status bddc_get_substructure(const bddc_ctx *ctx, int32_t s, int64_t *n, in
                                   int64_t *nnz, int64_t *gdof, int64_t *rowptr, int32_t *col,
                                   double *val, double *weights);
 
-/* Kernel timing.  When on, the main kernels of factor / apply / PCG are
-   bracketed by HIP events on the context's stream; every category keeps the
-   summed time, the number of timed launches and the algorithmic bytes and
-   flops those launches must move / perform (from the operand sizes: e.g. one
-   pass over a dense matrix counts its stored entries once).  Turning timing
-   on clears the statistics.  Timing serializes nothing but adds two event
-   records per timed launch. */
+/* Kernel timing with HIP events on the context's stream.
+   mode 1: phases of factor / apply / PCG (e.g. "factor_trsm_interior", which
+           spans many kernel launches) are timed as categories;
+   mode 2: every launch of the main kernels is timed under its kernel name
+           (e.g. "chol_update_kernel"), so that per-launch averages can be set
+           beside a profiler's;
+   mode 0: off.
+   Every entry keeps the summed time, the number of timed intervals and the
+   algorithmic bytes and flops they must move / perform (from the operand
+   sizes: one pass over a dense matrix counts its stored entries once).
+   Setting a mode clears the statistics.  Timing serializes nothing but adds
+   two event records per timed interval. */
 typedef struct {
   char name[32];
   double ms;                 /* summed over launches */
@@ -206,7 +214,7 @@ typedef struct {
   double flops;              /* summed algorithmic flops */
 } bddc_kernel_stat;
 
-bddc_status bddc_set_timing(bddc_ctx *ctx, int on);
+bddc_status bddc_set_timing(bddc_ctx *ctx, int mode);
 /* Writes up to max entries; *count receives the number of categories. */
 bddc_status bddc_get_timing(const bddc_ctx *ctx, int max, bddc_kernel_stat *out, int *count);
 

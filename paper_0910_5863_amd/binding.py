@@ -349,8 +349,9 @@ class BDDC:
                                                _ptr(w, C.c_double)))
         return gd, ni.value, sp.csr_matrix((val, col, rp), shape=(n.value, n.value)), w
 
-    def set_timing(self, on=True):
-        _check(self.h, load().bddc_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, mode=1):
+        """0: off; 1 (or True): phase categories; 2: every kernel launch."""
+        _check(self.h, load().bddc_set_timing(self.h, int(mode)))
 
     def timing(self):
         """{name: dict(ms, launches, bytes, flops)} summed since set_timing."""

@@ -853,7 +853,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   HIPCHK(DenseOps<double>::trsm(stream, Snn, Sns, d_mdn, mdn.data(), nside, false));
   // Sh gets the Schur complement; Sns and Sh live in different pools
   HIPCHK(DenseOps<double>::gemm(stream, Sns, Sns, Sh, d_gsh, nside, max_ns, max_ns, true, false,
-                                -1.0, 1.0, false));
+                                -1.0, 1.0, false, gsh.data()));
 
   log("pair Schur complements");
   // ---- stage 2: parallel sum and the reduced pair matrices
@@ -921,7 +921,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   // cancellation between the two large terms of Sh_i - Sh_i (..)^+ Sh_i when
   // the coefficients of i and j differ by orders of magnitude)
   HIPCHK(DenseOps<double>::gemm(stream, Sh, Xb, BJf, d_gbj, np, max_sp, max_sp, false, false, 1.0,
-                                0.0, false));
+                                0.0, false, gbj.data()));
   symmetrize_kernel<<<dim3(nblocks((int64_t)max_sp * max_sp), np), TPB, 0, stream>>>(BJf, d_off_p, d_nsp);
   HIPCHK(hipGetLastError());
   double *Mc = pool.zeros(stream, tc), *BJc = pool.zeros(stream, tc);
@@ -943,10 +943,10 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
                      std::max(1, ncv[p]), std::max(1, dv[p])};
   }
   GemmDesc *d_g1 = pool.up(stream, g1), *d_g2 = pool.up(stream, g2);
-  HIPCHK(DenseOps<double>::gemm(stream, Mc, Zd, T1, d_g1, np, max_c, max_d, false, false, 1.0, 0.0, false));
-  HIPCHK(DenseOps<double>::gemm(stream, Zd, T1, My, d_g2, np, max_d, max_d, true, false, 1.0, 0.0, false));
-  HIPCHK(DenseOps<double>::gemm(stream, BJc, Zd, T1, d_g1, np, max_c, max_d, false, false, 1.0, 0.0, false));
-  HIPCHK(DenseOps<double>::gemm(stream, Zd, T1, By, d_g2, np, max_d, max_d, true, false, 1.0, 0.0, false));
+  HIPCHK(DenseOps<double>::gemm(stream, Mc, Zd, T1, d_g1, np, max_c, max_d, false, false, 1.0, 0.0, false, g1.data()));
+  HIPCHK(DenseOps<double>::gemm(stream, Zd, T1, My, d_g2, np, max_d, max_d, true, false, 1.0, 0.0, false, g2.data()));
+  HIPCHK(DenseOps<double>::gemm(stream, BJc, Zd, T1, d_g1, np, max_c, max_d, false, false, 1.0, 0.0, false, g1.data()));
+  HIPCHK(DenseOps<double>::gemm(stream, Zd, T1, By, d_g2, np, max_d, max_d, true, false, 1.0, 0.0, false, g2.data()));
   // C' = L^-1 My L^-T with By = L L^T
   std::vector<MatDesc> mdd(np);
   for (int p = 0; p < np; ++p)
@@ -1113,8 +1113,8 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   GemmDesc *d_gz = pool.up(stream, gz), *d_gm = pool.up(stream, gm);
   double *Vtmp = pool.zeros(stream, tj);
   HIPCHK(DenseOps<double>::trsm(stream, By, Yv, d_mdy, mdy.data(), np, true));
-  HIPCHK(DenseOps<double>::gemm(stream, Zd, Yv, Jv, d_gz, np, max_c, max_k, false, false, 1.0, 0.0, false));
-  HIPCHK(DenseOps<double>::gemm(stream, Mc, Jv, Vtmp, d_gm, np, max_c, max_k, false, false, 1.0, 0.0, false));
+  HIPCHK(DenseOps<double>::gemm(stream, Zd, Yv, Jv, d_gz, np, max_c, max_k, false, false, 1.0, 0.0, false, gz.data()));
+  HIPCHK(DenseOps<double>::gemm(stream, Mc, Jv, Vtmp, d_gm, np, max_c, max_k, false, false, 1.0, 0.0, false, gm.data()));
   (void)Vv;
   std::vector<double> hv(tj);
   std::vector<int> hstat(3 * np + 2 * nside + 4);

@@ -35,6 +35,13 @@ bddc_status fail(bddc_ctx *c, int code, const std::string &m) {
 
 template <class F>
 bddc_status guarded(bddc_ctx *c, F f) {
+  // per-launch timing hook for the duration of the call
+  struct Hook {
+    explicit Hook(bddc_ctx *c) {
+      launch_timing() = (c && c->S && c->S->timer.mode == 2) ? &c->S->timer : nullptr;
+    }
+    ~Hook() { launch_timing() = nullptr; }
+  } hook(c);
   try {
     f();
     if (c) c->err.clear();
@@ -212,9 +219,17 @@ bddc_status bddc_adapt(bddc_ctx *c, double tau, bddc_adapt_info *info) {
   return guarded(c, [&] {
     check_hip(hipSetDevice(c->opt.device), "hipSetDevice");
     auto t0 = std::chrono::steady_clock::now();
+    // adaptive rows of an earlier call are replaced, not added to
+    bool had_rows = false;
+    for (int k : c->P.extra_k) had_rows |= k > 0;
+    if (had_rows) {
+      for (auto &r : c->P.extra_rows) r.clear();
+      for (int &k : c->P.extra_k) k = 0;
+      build_constraints(c->P);
+    }
     AdaptResult res = run_adapt(c->P, *c->S, c->adapt, tau);
     build_constraints(c->P);
-    c->S->build(c->P, c->stream);
+    c->S->build(c->P, c->stream, /*keep_schur=*/true);
     c->state = 1;
     if (info) {
       info->omega = res.omega;
@@ -340,14 +355,21 @@ bddc_status bddc_set_timing(bddc_ctx *c, int on) {
   if (!c) return BDDC_ERR_ARG;
   if (c->opt.device < 0) return fail(c, BDDC_ERR_STATE, "host-only context (device < 0)");
   return guarded(c, [&] {
+    if (on < 0 || on > 2) throw ArgError("timing mode must be 0, 1 or 2");
     c->S->timer.reset();
-    c->S->timer.on = on != 0;
+    c->S->timer.mode = on;
   });
 }
 
 bddc_status bddc_get_timing(const bddc_ctx *c, int max, bddc_kernel_stat *out, int *count) {
   if (!c || !count) return BDDC_ERR_ARG;
-  const Timer &t = c->S->timer;
+  if (!c->S) return BDDC_ERR_STATE;
+  Timer &t = c->S->timer;
+  try {
+    t.collect();
+  } catch (const std::exception &) {
+    return BDDC_ERR_DEVICE;
+  }
   *count = (int)t.names.size();
   if (out)
     for (int i = 0; i < std::min(max, *count); ++i) {

@@ -13,6 +13,30 @@ namespace bddc {
 
 constexpr int NB = 64;  // block size of the blocked factorizations and solves
 
+// Per-launch timing.  When a LaunchTiming is installed for the calling
+// thread, every kernel launch of the library is bracketed by events under its
+// kernel name, with the algorithmic bytes and flops of that launch.
+struct LaunchTiming {
+  virtual void launch_begin(hipStream_t st, const char *kernel, double bytes, double flops) = 0;
+  virtual void launch_end(hipStream_t st) = 0;
+  virtual ~LaunchTiming() = default;
+};
+LaunchTiming *&launch_timing();  // the calling thread's slot (nullptr: off)
+
+struct LaunchScope {
+  hipStream_t st;
+  LaunchTiming *t;
+  LaunchScope(hipStream_t s, const char *kernel, double bytes, double flops)
+      : st(s), t(launch_timing()) {
+    if (t) t->launch_begin(st, kernel, bytes, flops);
+  }
+  ~LaunchScope() {
+    if (t) t->launch_end(st);
+  }
+  LaunchScope(const LaunchScope &) = delete;
+  LaunchScope &operator=(const LaunchScope &) = delete;
+};
+
 // One batch entry: an n x n lower-triangular factor (or SPD matrix) at
 // pool + a_off with leading dimension lda, and an n x nrhs right-hand side at
 // pool + b_off with leading dimension ldb.
@@ -37,9 +61,11 @@ template <class T>
 struct DenseOps {
   // C = beta*C + alpha*op(A)*op(B) for every entry; lower != 0 computes only
   // tiles that intersect the lower triangle (i >= j).
+  // h_desc (optional) is the host copy of the descriptors, used only to count
+  // the launch's flops and bytes when per-launch timing is on.
   static hipError_t gemm(hipStream_t st, const T *A, const T *B, T *C, const GemmDesc *d_desc,
                          int batch, int maxM, int maxN, bool transA, bool transB, T alpha,
-                         T beta, bool lower);
+                         T beta, bool lower, const GemmDesc *h_desc = nullptr);
   // In-place lower Cholesky of every entry's A (n x n).  status[e] is set to
   // (column+1) of the first non-positive pivot (left untouched if none).
   static hipError_t potrf(hipStream_t st, T *pool, const MatDesc *d_desc, const MatDesc *h_desc,
@@ -63,6 +89,8 @@ struct TrsvPlan {
   int *d_order_fwd = nullptr;  // (entry, block) pairs in dependency order
   int *d_order_bwd = nullptr;
   int *d_flag_off = nullptr;   // first flag of every entry
+  double tri_elems = 0;        // sum over entries of n (n + 1) / 2 (for timing)
+  double rows = 0;             // sum over entries of n
 };
 
 template <class T>

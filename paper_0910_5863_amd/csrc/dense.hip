@@ -509,18 +509,33 @@ __global__ void zero_ints_kernel(int *p, int n) {
 
 namespace bddc {
 
+LaunchTiming *&launch_timing() {
+  static thread_local LaunchTiming *slot = nullptr;
+  return slot;
+}
+
 namespace {
 inline int grid_round(int n) { return ((n + NXCD - 1) / NXCD) * NXCD; }
+inline int blk(int n, int k) { return std::max(0, std::min(NB, n - k * NB)); }
 }  // namespace
 
 template <class T>
 hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const GemmDesc *d_desc,
                              int batch, int maxM, int maxN, bool transA, bool transB, T alpha,
-                             T beta, bool lower) {
+                             T beta, bool lower, const GemmDesc *h_desc) {
   if (batch <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
   const int tm = (maxM + BM - 1) / BM, tn = (maxN + BN - 1) / BN;
   const int nwg = grid_round(batch * tm * tn);
   dim3 g(nwg), b(256);
+  double fl = 0, by = 0;
+  if (launch_timing() && h_desc)
+    for (int e = 0; e < batch; ++e) {
+      const GemmDesc &q = h_desc[e];
+      const double mn = lower ? 0.5 * (double)q.M * (q.N + 1) : (double)q.M * q.N;
+      fl += 2.0 * mn * q.K;
+      by += sizeof(T) * ((double)q.M * q.K + (double)q.K * q.N + (beta != T(0) ? 2.0 : 1.0) * mn);
+    }
+  LaunchScope ls(st, "gemm_kernel", by, fl);
   if (!transA && !transB)
     gemm_kernel<T, false, false><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
   else if (transA && !transB)
@@ -539,12 +554,37 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
   for (int e = 0; e < batch; ++e) maxn = std::max(maxn, h_desc[e].n);
   if (maxn == 0) return hipSuccess;
   const int nblk = (maxn + NB - 1) / NB;
+  const bool timing = launch_timing() != nullptr;
   for (int k = 0; k < nblk; ++k) {
     const int tm = nblk - k;  // row tiles of block column k (for the largest entry)
-    if (k > 0) chol_update_kernel<T><<<grid_round(batch * tm), 256, 0, st>>>(pool, d_desc, k, tm, batch);
-    chol_diag_kernel<T><<<batch, 256, 0, st>>>(pool, d_desc, k, status, batch);
-    if (tm > 1)
+    // algorithmic work of block column k over the batch: the update of the
+    // column below the diagonal by the k*NB columns to its left, the
+    // factorization of the diagonal block, and the panel solve under it
+    double fu = 0, bu = 0, fd = 0, bd = 0, fp = 0, bp = 0;
+    if (timing)
+      for (int e = 0; e < batch; ++e) {
+        const double nb = blk(h_desc[e].n, k);
+        if (nb == 0) continue;
+        const double m = h_desc[e].n - (double)k * NB, kk = (double)k * NB, below = m - nb;
+        fu += 2.0 * (m * nb - 0.5 * nb * (nb - 1)) * kk;
+        bu += sizeof(T) * (m * kk + nb * kk + 2.0 * m * nb);
+        fd += nb * nb * nb / 3.0;
+        bd += sizeof(T) * nb * nb;
+        fp += below * nb * nb;
+        bp += sizeof(T) * (2.0 * below * nb + 0.5 * nb * nb);
+      }
+    if (k > 0) {
+      LaunchScope ls(st, "chol_update_kernel", bu, fu);
+      chol_update_kernel<T><<<grid_round(batch * tm), 256, 0, st>>>(pool, d_desc, k, tm, batch);
+    }
+    {
+      LaunchScope ls(st, "chol_diag_kernel", bd, fd);
+      chol_diag_kernel<T><<<batch, 256, 0, st>>>(pool, d_desc, k, status, batch);
+    }
+    if (tm > 1) {
+      LaunchScope ls(st, "chol_panel_kernel", bp, fp);
       chol_panel_kernel<T><<<grid_round(batch * (tm - 1)), 256, 0, st>>>(pool, d_desc, k, tm - 1, batch);
+    }
   }
   return hipGetLastError();
 }
@@ -561,9 +601,32 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
   const int nblk = (maxn + NB - 1) / NB;
   const int tn = (maxr + NB - 1) / NB;
   const int nwg = grid_round(batch * tn);
+  const bool timing = launch_timing() != nullptr;
+  // algorithmic work at block row k: the update of the k-th block row of B
+  // by the solved rows (forward: the k*NB above it; backward: the ones below)
+  // and the triangular solve with the diagonal block
+  auto work = [&](int k, double &fu, double &bu, double &fd, double &bd) {
+    fu = bu = fd = bd = 0;
+    if (!timing) return;
+    for (int e = 0; e < batch; ++e) {
+      const double nb = blk(h_desc[e].n, k), r = h_desc[e].nrhs;
+      if (nb == 0) continue;
+      const double other = transpose ? h_desc[e].n - (double)k * NB - nb : (double)k * NB;
+      fu += 2.0 * nb * r * other;
+      bu += sizeof(T) * (nb * other + other * r + 2.0 * nb * r);
+      fd += nb * nb * r;
+      bd += sizeof(T) * (0.5 * nb * nb + 2.0 * nb * r);
+    }
+  };
+  double fu, bu, fd, bd;
   if (!transpose) {
     for (int k = 0; k < nblk; ++k) {
-      if (k > 0) trsm_update_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+      work(k, fu, bu, fd, bd);
+      if (k > 0) {
+        LaunchScope ls(st, "trsm_update_kernel<fwd>", bu, fu);
+        trsm_update_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+      }
+      LaunchScope ls(st, "trsm_diag_kernel<fwd>", bd, fd);
       trsm_diag_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
     }
   } else {
@@ -571,7 +634,12 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
     // top; walking k downwards from the largest still visits every entry's
     // blocks bottom-up
     for (int k = nblk - 1; k >= 0; --k) {
-      trsm_update_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+      work(k, fu, bu, fd, bd);
+      {
+        LaunchScope ls(st, "trsm_update_kernel<bwd>", bu, fu);
+        trsm_update_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+      }
+      LaunchScope ls(st, "trsm_diag_kernel<bwd>", bd, fd);
       trsm_diag_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
     }
   }
@@ -595,6 +663,10 @@ hipError_t trsv_blocked(hipStream_t st, const T *apool, T *xpool, const MatDesc 
   const int nz = 1 + plan.total_blocks;
   zero_ints_kernel<<<(nz + 255) / 256, 256, 0, st>>>(work, nz);
   const int *order = transpose ? plan.d_order_bwd : plan.d_order_fwd;
+  // one pass over the stored triangle, the right-hand sides read and written
+  LaunchScope ls(st, transpose ? "trsv_kernel<bwd>" : "trsv_kernel<fwd>",
+                 sizeof(T) * (plan.tri_elems + 2.0 * nrhs * plan.rows),
+                 2.0 * nrhs * plan.tri_elems);
   if (!transpose)
     trsv_kernel<T, false><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, order,
                                                             plan.d_flag_off, plan.total_blocks,

@@ -58,13 +58,15 @@ struct KernelStat {
   int64_t launches = 0;
 };
 
-class Timer {
+class Timer : public LaunchTiming {
  public:
-  bool on = false;
+  int mode = 0;  // 0: off, 1: phase categories (begin / end), 2: kernel launches
   std::vector<std::string> names;
   std::vector<KernelStat> stats;
   void begin(hipStream_t st, const char *name, double bytes, double flops);
   void end(hipStream_t st);
+  void launch_begin(hipStream_t st, const char *kernel, double bytes, double flops) override;
+  void launch_end(hipStream_t st) override;
   void collect();  // after a synchronization: resolve pending event pairs
   void reset();
   ~Timer();
@@ -81,6 +83,8 @@ class Timer {
   hipEvent_t cur_a = nullptr;
   double cur_bytes = 0, cur_flops = 0;
   hipEvent_t get_event();
+  void record_begin(hipStream_t st, const char *name, double bytes, double flops);
+  void record_end(hipStream_t st);
 };
 
 class Solver {
@@ -98,7 +102,7 @@ class Solver {
   int verbose = 0;
 
   ~Solver();
-  void build(const Problem &P, hipStream_t st);
+  void build(const Problem &P, hipStream_t st, bool keep_schur = false);
   void factor();
   void factor_schur();
   void check_status(bool all);
@@ -134,6 +138,7 @@ class Solver {
   int n_gx = 0;
   TrsvPlan plan_rr, plan_II, plan_c;
   std::vector<MatDesc> h_descII, h_descRR, h_descGG, h_descC;
+  std::vector<GemmDesc> h_syrk, h_spi;
 
   DBuf d_row_sub, d_row_loc, d_rowptr, d_col, d_val, d_nI, d_nG, d_nr, d_np;
   DBuf d_offI, d_offG, d_offR, d_offP, d_offII, d_offIG, d_offGG, d_offRR, d_offRP, d_offPP;

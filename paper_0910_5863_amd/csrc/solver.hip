@@ -448,7 +448,22 @@ hipEvent_t Timer::get_event() {
 }
 
 void Timer::begin(hipStream_t st, const char *name, double bytes, double flops) {
-  if (!on) return;
+  if (mode == 1) record_begin(st, name, bytes, flops);
+}
+
+void Timer::end(hipStream_t st) {
+  if (mode == 1) record_end(st);
+}
+
+void Timer::launch_begin(hipStream_t st, const char *kernel, double bytes, double flops) {
+  if (mode == 2) record_begin(st, kernel, bytes, flops);
+}
+
+void Timer::launch_end(hipStream_t st) {
+  if (mode == 2) record_end(st);
+}
+
+void Timer::record_begin(hipStream_t st, const char *name, double bytes, double flops) {
   int idx = -1;
   for (size_t i = 0; i < names.size(); ++i)
     if (names[i] == name) idx = (int)i;
@@ -464,8 +479,8 @@ void Timer::begin(hipStream_t st, const char *name, double bytes, double flops) 
   HIPCHK(hipEventRecord(cur_a, st));
 }
 
-void Timer::end(hipStream_t st) {
-  if (!on || cur < 0) return;
+void Timer::record_end(hipStream_t st) {
+  if (cur < 0) return;
   hipEvent_t b = get_event();
   HIPCHK(hipEventRecord(b, st));
   pending.push_back({cur, cur_a, b, cur_bytes, cur_flops});
@@ -549,8 +564,17 @@ std::vector<DBuf *> Solver::all_buffers() {
 }
 
 // Host analysis after bddc_setup / adapt: layout, index maps, uploads of the
-// substructure matrices.  Matrices and vectors are (re)allocated.
-void Solver::build(const Problem &P, hipStream_t st) {
+// substructure matrices.  Matrices and vectors are (re)allocated, except the
+// Dirichlet factors and Schur complements when keep_schur is set and they are
+// current: they do not depend on the constraints.
+void Solver::build(const Problem &P, hipStream_t st, bool keep_schur) {
+  DBuf kAII, kAIG, kS;
+  const bool keep = keep_schur && schur_ready;
+  if (keep) {
+    std::swap(kAII, d_AII);
+    std::swap(kAIG, d_AIG);
+    std::swap(kS, d_S);
+  }
   free_all();
   stream = st;
   const int ns = (int)P.subs.size();
@@ -811,6 +835,8 @@ void Solver::build(const Problem &P, hipStream_t st) {
   d_descRRvec = upload(alloc, st, dRRv);
   d_syrk = upload(alloc, st, syrk);
   d_spi_desc = upload(alloc, st, spi);
+  h_syrk = syrk;
+  h_spi = spi;
   MatDesc dc{0, 0, (int)nc, 0, (int)std::max<int64_t>(1, nc), (int)std::max<int64_t>(1, nc)};
   h_descC = {dc};
   d_descC = upload(alloc, st, h_descC);
@@ -829,6 +855,12 @@ void Solver::build(const Problem &P, hipStream_t st) {
     p.d_order_fwd = f.as<int>();
     p.d_order_bwd = b.as<int>();
     p.d_flag_off = o.as<int>();
+    p.tri_elems = 0;
+    p.rows = 0;
+    for (int v : n) {
+      p.tri_elems += 0.5 * (double)v * (v + 1);
+      p.rows += v;
+    }
     return total;
   };
   int w1 = plan(L.nr, d_trsv_rr_fwd, d_trsv_rr_bwd, d_trsv_rr_off, plan_rr);
@@ -837,9 +869,21 @@ void Solver::build(const Problem &P, hipStream_t st) {
   d_work_i = alloc0(alloc, st, sizeof(int) * (size_t)(4 + std::max({w1, w2, w3})));
   d_status = alloc0(alloc, st, sizeof(int) * (size_t)(2 * ns + 2));
   // matrices
-  d_AII = alloc0(alloc, st, sizeof(double) * (size_t)L.sII);
-  d_AIG = alloc0(alloc, st, sizeof(double) * (size_t)L.sIG);
-  d_S = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
+  const bool kept = keep && kAII.bytes == std::max<size_t>(sizeof(double) * (size_t)L.sII, 8) &&
+                    kAIG.bytes == std::max<size_t>(sizeof(double) * (size_t)L.sIG, 8) &&
+                    kS.bytes == std::max<size_t>(sizeof(double) * (size_t)L.sGG, 8);
+  if (kept) {
+    d_AII = kAII;
+    d_AIG = kAIG;
+    d_S = kS;
+  } else {
+    release(kAII);
+    release(kAIG);
+    release(kS);
+    d_AII = alloc0(alloc, st, sizeof(double) * (size_t)L.sII);
+    d_AIG = alloc0(alloc, st, sizeof(double) * (size_t)L.sIG);
+    d_S = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
+  }
   d_W = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
   d_Lrr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
   d_Phi = alloc0(alloc, st, sizeof(double) * (size_t)L.sRP);
@@ -872,7 +916,7 @@ void Solver::build(const Problem &P, hipStream_t st) {
   }
   HIPCHK(hipStreamSynchronize(st));
   factored = false;
-  schur_ready = false;
+  schur_ready = kept;
 }
 
 // Dirichlet factors A_II = L L^T and Schur complements S_i (original basis);
@@ -910,7 +954,7 @@ void Solver::factor_schur() {
   timer.begin(st, "factor_syrk_schur", 8.0 * (L.sIG + L.sGG), fl_syrk);
   HIPCHK(DenseOps<double>::gemm(st, d_AIG.as<double>(), d_AIG.as<double>(), d_S.as<double>(),
                                 d_syrk.as<GemmDesc>(), ns, L.max_nG, L.max_nG, true, false, -1.0,
-                                1.0, true));
+                                1.0, true, h_syrk.data()));
   timer.end(st);
   HIPCHK(symmetrize_lower<double>(st, d_S.as<double>(), d_descGG.as<MatDesc>(), ns, L.max_nG));
   check_status(false);
@@ -921,7 +965,14 @@ void Solver::factor() {
   hipStream_t st = stream;
   const int ns = L.nsub;
   auto t0 = std::chrono::steady_clock::now();
-  factor_schur();
+  if (schur_ready) {
+    HIPCHK(hipMemsetAsync(d_status.p, 0, d_status.bytes, st));
+  } else {
+    factor_schur();
+  }
+  // one factor consumes the Schur complements: the next factor (or adapt)
+  // recomputes them from the substructure matrices
+  schur_ready = false;
   int *status = d_status.as<int>();
   double fl_rr = 0;
   for (int s = 0; s < ns; ++s) fl_rr += (double)L.nr[s] * L.nr[s] * L.nr[s] / 3;
@@ -977,7 +1028,7 @@ void Solver::factor() {
                                 h_descRR.data(), ns, false));
   HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
                                 d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
-                                -1.0, 1.0, false));
+                                -1.0, 1.0, false, h_spi.data()));
   HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
                                 h_descRR.data(), ns, true));
   if (L.sRP > 0) {
@@ -1079,6 +1130,7 @@ void Solver::schur_gamma(const double *p, double *q) {
                                                  L.sumG, L.sumG, 1);
   if (L.max_nG > 0) {
     timer.begin(st, "schur_gemv", bytes_S + 16.0 * L.sumG, 2.0 * (double)L.sGG);
+    LaunchScope ls(st, "gemv_t_kernel", bytes_S + 16.0 * L.sumG, 2.0 * (double)L.sGG);
     gemv_t_kernel<<<dim3(nblocks((int64_t)L.max_nG * 64), L.nsub), TPB, 0, st>>>(
         d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_nG.as<int>(), vG,
         d_offG.as<int64_t>(), vG2, d_offG.as<int64_t>(), 1.0, 0.0);
@@ -1153,10 +1205,12 @@ void Solver::apply_local(double *b, double *z) {
   gather32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vG, L.sumG, d_rabs.as<int>(), vR, L.sumR, L.sumR, 1);
   gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vG, L.sumG, d_pabs.as<int>(), vP, L.sumP, L.sumP, 1);
   HIPCHK(hipGetLastError());
-  if (L.max_np > 0)
+  if (L.max_np > 0) {
+    LaunchScope ls(st, "gemv_t_kernel", 8.0 * ((double)L.sRP + L.sumR + 2.0 * L.sumP), 2.0 * (double)L.sRP);
     gemv_t_kernel<<<dim3(nblocks((int64_t)L.max_np * 64), ns), TPB, 0, st>>>(
         d_Phi.as<double>(), d_offRP.as<int64_t>(), d_nr.as<int>(), d_np.as<int>(), vR,
         d_offR.as<int64_t>(), vP, d_offP.as<int64_t>(), 1.0, 1.0);
+  }
   HIPCHK(hipMemcpyAsync(vR2, vR, sizeof(double) * L.sumR, hipMemcpyDeviceToDevice, st));
   timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
   trsv(plan_rr, d_Lrr, d_descRRvec, vR2, false, 1);
@@ -1174,10 +1228,12 @@ void Solver::apply_local(double *b, double *z) {
     timer.end(st);
     gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vc, L.n_coarse, d_pcid.as<int>(), vP, L.sumP,
                                                      L.sumP, 1);
-    if (L.max_nr > 0)
+    if (L.max_nr > 0) {
+      LaunchScope ls(st, "gemv_n_kernel", 8.0 * ((double)L.sRP + L.sumP + 2.0 * L.sumR), 2.0 * (double)L.sRP);
       gemv_n_kernel<<<dim3(nblocks(L.max_nr), ns), TPB, 0, st>>>(
           d_Phi.as<double>(), d_offRP.as<int64_t>(), d_nr.as<int>(), d_np.as<int>(), vP,
           d_offP.as<int64_t>(), vR2, d_offR.as<int64_t>(), 1.0, 1.0);
+    }
   }
   scatter32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vR2, L.sumR, d_rabs.as<int>(), vG, L.sumG, L.sumR, 1);
   scatter32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vP, L.sumP, d_pabs.as<int>(), vG, L.sumG, L.sumP, 1);

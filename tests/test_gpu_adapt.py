@@ -80,3 +80,32 @@ def test_adapt_eigenvalues_rows_and_solve(name):
     assert np.linalg.norm(uu - ref["u"]) / np.linalg.norm(ref["u"]) < 1e-8
     assert abs(pinfo[0].iters - ref["iters"]) <= max(2, int(0.05 * ref["iters"]))
     b.close()
+
+
+def test_adapt_replaces_rows_and_reuses_schur():
+    """A second bddc_adapt replaces the rows of the first: adapting at tau = 2
+    and then at tau = 10 gives the constraints, indicator and solution of a
+    single adaptation at tau = 10 on a fresh context."""
+    BDDC = _gpu()
+    p, tau, o, ad, o2 = oracle_for("layers8")
+    ref = BDDC()
+    ref.setup(p, "ce")
+    i_ref = ref.adapt(tau)
+    ref.factor()
+    f = torch.from_numpy(p.f)
+    u_ref, _ = ref.pcg_solve(f)
+    b = BDDC()
+    b.setup(p, "ce")
+    i2 = b.adapt(2.0)
+    assert i2.nc > i_ref.nc
+    i10 = b.adapt(tau)
+    assert i10.nc == i_ref.nc == o2.cons.Nc()
+    assert i10.omega == i_ref.omega
+    b.factor()
+    u, info = b.pcg_solve(f)
+    assert info[0].iters > 0
+    assert torch.equal(u.cpu(), u_ref.cpu())
+    # a second factor recomputes the Schur complements it consumed
+    b.factor()
+    u2, _ = b.pcg_solve(f)
+    assert torch.equal(u2.cpu(), u_ref.cpu())
