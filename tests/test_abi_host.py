@@ -1,0 +1,106 @@
+"""The C ABI on the CPU (no GPU needed): the library loads and exports every
+function include/bddc.h declares; a host-only context (device < 0) runs the
+setup analysis, whose results equal the oracle's -- glob and corner counts,
+the constraint count Nc, every substructure matrix A_i (Sec. 2: subassembled
+from element matrices) with its local dof numbering, and the weights of the
+averaging operator E (Sec. 7: diagonal entries of the substructure matrices);
+and calls out of order or with bad arguments return their documented status.
+No compute call is made."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen
+from paper_0910_5863_amd import BDDC, BddcError, binding, load
+
+HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "bddc.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bddc_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = load()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(binding.SYMBOLS)
+
+
+CASES = {
+    "poisson16": (lambda: meshgen.poisson_16(), "ce"),
+    "elast6x3_cef": (lambda: meshgen.small_elasticity_layers(6, 3, contrast=1e3), "cef"),
+    "kmeans_elast": (lambda: meshgen.small_kmeans(meshgen.ELASTICITY, 8, 4, contrast=1e3), "ce"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_host_analysis_matches_oracle(name):
+    from oracle.fem import Substructures
+    from oracle.interface import Interface
+    from oracle.cov import Constraints
+    make, mode = CASES[name]
+    p = make()
+    S = Substructures(p)
+    itf = Interface(S)
+    cons = Constraints(itf, mode)
+    b = BDDC(device=-1)
+    b.setup(p, mode)
+    info = b.info()
+    c = itf.counts()
+    assert info.n_glob == p.n_glob == S.n_glob
+    assert info.n_sub == p.n_sub
+    assert (info.n_corners, info.n_edges, info.n_faces) == (c["corners"], c["edges"], c["faces"])
+    assert info.nc == cons.Nc()
+    for s in range(p.n_sub):
+        gdof, n_int, A, w = b.substructure(s)
+        # local order: interior dofs first, then interface dofs, each ascending
+        g = S.gdof[s]
+        interior, iface = g[itf.interior[s]], g[itf.iface[s]]
+        assert n_int == interior.size
+        assert np.array_equal(gdof, np.concatenate([np.sort(interior), np.sort(iface)]))
+        # same matrix up to the local permutation
+        loc = {int(v): k for k, v in enumerate(g)}
+        perm = np.array([loc[int(v)] for v in gdof])
+        Ao = S.A[s][perm][:, perm].toarray()
+        scale = np.abs(Ao).max()
+        assert np.abs(A.toarray() - Ao).max() <= 1e-14 * scale
+        # weights of E on the interface dofs
+        dl = itf.delta[s][perm[n_int:]]
+        assert np.allclose(w, dl, rtol=1e-14, atol=0)
+    b.close()
+
+
+def test_host_only_context_rejects_device_calls():
+    p = meshgen.poisson_16()
+    b = BDDC(device=-1)
+    with pytest.raises(BddcError) as e:
+        b.factor()
+    assert e.value.code == 2          # BDDC_ERR_STATE: before setup
+    b.setup(p, "ce")
+    for call in (b.factor, lambda: b.adapt(10.0)):
+        with pytest.raises(BddcError) as e:
+            call()
+        assert e.value.code == 2      # host-only context
+    with pytest.raises(BddcError) as e:
+        b.substructure(p.n_sub)       # no such substructure
+    assert e.value.code == 1          # BDDC_ERR_ARG
+    b.close()
+
+
+def test_bad_setup_arguments():
+    p = meshgen.poisson_16()
+    b = BDDC(device=-1)
+    bad = meshgen.poisson_16()
+    bad.elem_sub = bad.elem_sub.copy()
+    bad.elem_sub[0] = p.n_sub          # out of range
+    with pytest.raises(BddcError) as e:
+        b.setup(bad, "ce")
+    assert e.value.code == 1
+    b.close()
