@@ -49,9 +49,9 @@ struct Layout {
   int64_t n_glob = 0;
   std::vector<int> nI, nG, nr, np;
   std::vector<int64_t> offI, offG, offR, offP;         // vector stacks
-  std::vector<int64_t> offII, offIG, offGG, offRR, offRP, offPP;  // matrix pools
+  std::vector<int64_t> offGG, offRR, offRP, offPP;  // matrix pools
   int64_t sumI = 0, sumG = 0, sumR = 0, sumP = 0;
-  int64_t sII = 0, sIG = 0, sGG = 0, sRR = 0, sRP = 0, sPP = 0;
+  int64_t sGG = 0, sRR = 0, sRP = 0, sPP = 0;
   int64_t n_gamma = 0;  // global interface dofs
   int64_t n_coarse = 0;
   int max_nI = 0, max_nG = 0, max_nr = 0, max_np = 0;

@@ -1,0 +1,443 @@
+// Multifrontal elimination of the substructure interiors on the device
+// (structure in multifrontal.h / multifrontal.cpp).
+//
+// Factorization, deepest fronts first, all substructures batched per depth:
+//   assemble   U <- the rows of the substructure matrices owned by each front
+//   pull       U, C += the children's contribution blocks (each parent entry
+//              sums its children in a fixed order: deterministic, no atomics)
+//   potrf      F11 = L11 L11^T                     (MFMA, dense.hip)
+//   trsm       F12 <- L11^-1 F12                    (MFMA)
+//   gemm       C <- C - F12^T F12, lower triangle   (MFMA)
+// and at the top the interface Schur complements S_i pull the contributions
+// of their top fronts.  Solves run front by front: forward (deepest first)
+// with update vectors pulled by the parents, backward (top first) reading
+// the already solved ancestors.
+#include "multifrontal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "solver.h"
+
+namespace bddc {
+
+#define HIPCHK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess)                                                            \
+      throw DeviceError(std::string(#x) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int TB = 64;  // block size of the in-front triangular solves
+
+// one-sided symmetric read of a contribution block stored in its lower triangle
+__device__ __forceinline__ double csym(const double *C, int b, int i, int j) {
+  return i >= j ? C[i + (int64_t)j * b] : C[j + (int64_t)i * b];
+}
+
+__global__ void mf_assemble_kernel(const int64_t *dst, const double *val, int64_t nnz, double *U) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const int64_t d = dst[k];
+  if (d >= 0) U[d] = val[k];
+}
+
+// Fronts ids[blockIdx.y]: U += the children's contributions (U holds the
+// assembled rows already); the lower triangle of C = the children's
+// contributions (zero for a leaf), so C needs no clearing.
+__global__ void mf_pull_kernel(const MfFront *F, const int *ids, const int *child_ids,
+                               const int *pmap, double *U, double *C) {
+  const MfFront f = F[ids[blockIdx.y]];
+  const int p = f.p, b = f.b, fs = p + b;
+  const int64_t nu = f.n_child > 0 ? (int64_t)p * fs : 0, ntot = nu + (int64_t)b * b;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ntot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int pr, pc;
+    const bool in_u = e < nu;
+    if (in_u) {
+      pr = (int)(e % p);
+      pc = (int)(e / p);
+    } else {
+      const int64_t e2 = e - nu;
+      const int r = (int)(e2 % b), c = (int)(e2 / b);
+      if (r < c) continue;
+      pr = p + r;
+      pc = p + c;
+    }
+    double acc = 0;
+    for (int ci = 0; ci < f.n_child; ++ci) {
+      const MfFront ch = F[child_ids[f.child_ptr + ci]];
+      const int i = pmap[ch.pmap_off + pr], j = pmap[ch.pmap_off + pc];
+      if (i >= 0 && j >= 0) acc += csym(C + ch.c_off, ch.b, i, j);
+    }
+    if (in_u)
+      U[f.u_off + e] += acc;
+    else
+      C[f.c_off + (e - nu)] = acc;
+  }
+}
+
+// S_s (lower) += the contributions of substructure s's top fronts
+__global__ void mf_root_pull_kernel(const MfFront *F, const int *root_ptr, const int *root_ids,
+                                    const int *pmap, const double *C, double *S,
+                                    const int64_t *offGG, const int *nG) {
+  const int s = blockIdx.y;
+  const int ng = nG[s];
+  const int r0 = root_ptr[s], r1 = root_ptr[s + 1];
+  if (r0 == r1) return;
+  const int64_t nn = (int64_t)ng * ng;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % ng), c = (int)(e / ng);
+    if (r < c) continue;
+    double acc = 0;
+    for (int ri = r0; ri < r1; ++ri) {
+      const MfFront ch = F[root_ids[ri]];
+      const int i = pmap[ch.pmap_off + r], j = pmap[ch.pmap_off + c];
+      if (i >= 0 && j >= 0) acc += csym(C + ch.c_off, ch.b, i, j);
+    }
+    S[offGG[s] + e] += acc;
+  }
+}
+
+// z <- L^-1 z, L (n x n lower, column-major, ld) in global memory, z in LDS.
+// Blocks of TB: the diagonal block by wave 0 (lockstep, shuffles), the rows
+// below by the whole work-group.
+__device__ void lower_solve(const double *L, int ld, int n, double *z) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int jb = 0; jb < n; jb += TB) {
+    const int nb = min(TB, n - jb);
+    if (wave == 0) {
+      double zi = lane < nb ? z[jb + lane] : 0.0;
+      for (int k = 0; k < nb; ++k) {
+        const double zk = __shfl(zi, k, 64) / L[(jb + k) + (int64_t)(jb + k) * ld];
+        if (lane == k)
+          zi = zk;
+        else if (lane > k && lane < nb)
+          zi -= L[(jb + lane) + (int64_t)(jb + k) * ld] * zk;
+      }
+      if (lane < nb) z[jb + lane] = zi;
+    }
+    __syncthreads();
+    for (int r = jb + nb + tid; r < n; r += blockDim.x) {
+      double acc = 0;
+      for (int k = 0; k < nb; ++k) acc += L[r + (int64_t)(jb + k) * ld] * z[jb + k];
+      z[r] -= acc;
+    }
+    __syncthreads();
+  }
+}
+
+// x <- L^-T x (same storage)
+__device__ void upper_solve(const double *L, int ld, int n, double *x) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  const int nblk = (n + TB - 1) / TB;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int jb = bi * TB, nb = min(TB, n - jb);
+    // rows of the block minus the contributions of the solved rows below it
+    for (int i = wave; i < nb; i += nwave) {
+      double acc = 0;
+      const double *col = L + (int64_t)(jb + i) * ld;
+      for (int m = jb + nb + lane; m < n; m += 64) acc += col[m] * x[m];
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (lane == 0) x[jb + i] -= acc;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double xi = lane < nb ? x[jb + lane] : 0.0;
+      for (int k = nb - 1; k >= 0; --k) {
+        const double xk = __shfl(xi, k, 64) / L[(jb + k) + (int64_t)(jb + k) * ld];
+        if (lane == k)
+          xi = xk;
+        else if (lane < k)
+          xi -= L[(jb + k) + (int64_t)(jb + lane) * ld] * xk;
+      }
+      if (lane < nb) x[jb + lane] = xi;
+    }
+    __syncthreads();
+  }
+}
+
+// forward solve of one depth: one work-group per front
+__global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int *ids,
+                                                     const int *child_ids, const int *pmap,
+                                                     const int64_t *piv, const double *U,
+                                                     double *upd, double *vI) {
+  extern __shared__ double z[];
+  const MfFront f = F[ids[blockIdx.x]];
+  const int p = f.p, b = f.b, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwave = blockDim.x >> 6;
+  // right-hand side at the pivots plus the children's updates
+  for (int j = tid; j < p; j += blockDim.x) {
+    double v = vI[piv[f.piv_off + j]];
+    for (int ci = 0; ci < f.n_child; ++ci) {
+      const MfFront ch = F[child_ids[f.child_ptr + ci]];
+      const int k = pmap[ch.pmap_off + j];
+      if (k >= 0) v += upd[ch.upd_off + k];
+    }
+    z[j] = v;
+  }
+  __syncthreads();
+  const double *Uf = U + f.u_off;
+  lower_solve(Uf, p, p, z);
+  for (int j = tid; j < p; j += blockDim.x) vI[piv[f.piv_off + j]] = z[j];
+  // update for the parent: children's updates at the boundary minus F12^T z
+  for (int i = wave; i < b; i += nwave) {
+    const double *w = Uf + (int64_t)(p + i) * p;
+    double acc = 0;
+    for (int j = lane; j < p; j += 64) acc += w[j] * z[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) {
+      double v = -acc;
+      for (int ci = 0; ci < f.n_child; ++ci) {
+        const MfFront ch = F[child_ids[f.child_ptr + ci]];
+        const int k = pmap[ch.pmap_off + p + i];
+        if (k >= 0) v += upd[ch.upd_off + k];
+      }
+      upd[f.upd_off + i] = v;
+    }
+  }
+}
+
+// backward solve of one depth: x_p = L11^-T (y_p - F12 x_b); interface
+// boundary values are zero (pure interior solve)
+__global__ __launch_bounds__(256) void mf_bwd_kernel(const MfFront *F, const int *ids,
+                                                     const int64_t *piv, const int64_t *bnd,
+                                                     const double *U, double *vI) {
+  extern __shared__ double sm[];
+  const MfFront f = F[ids[blockIdx.x]];
+  const int p = f.p, b = f.b, tid = threadIdx.x;
+  double *x = sm, *xb = sm + p;
+  for (int i = tid; i < b; i += blockDim.x) {
+    const int64_t g = bnd[f.bnd_off + i];
+    xb[i] = g >= 0 ? vI[g] : 0.0;
+  }
+  __syncthreads();
+  const double *Uf = U + f.u_off;
+  for (int j = tid; j < p; j += blockDim.x) {
+    double acc = 0;
+    for (int i = 0; i < b; ++i) acc += Uf[j + (int64_t)(p + i) * p] * xb[i];
+    x[j] = vI[piv[f.piv_off + j]] - acc;
+  }
+  __syncthreads();
+  upper_solve(Uf, p, p, x);
+  for (int j = tid; j < p; j += blockDim.x) vI[piv[f.piv_off + j]] = x[j];
+}
+
+template <class T>
+DBuf upload(DevAlloc &A, hipStream_t st, const std::vector<T> &v) {
+  DBuf b;
+  b.bytes = std::max<size_t>(v.size() * sizeof(T), 8);
+  b.p = A.get(b.bytes);
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return b;
+}
+
+DBuf zeros(DevAlloc &A, hipStream_t st, size_t bytes) {
+  DBuf b;
+  b.bytes = std::max<size_t>(bytes, 8);
+  b.p = A.get(b.bytes);
+  HIPCHK(hipMemsetAsync(b.p, 0, b.bytes, st));
+  return b;
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + TPB - 1) / TPB); }
+
+}  // namespace
+
+void MfDevice::release(DevAlloc &A) {
+  for (DBuf *b : {&d_fronts_, &d_child_, &d_piv_, &d_bnd_, &d_pmap_, &d_asm_, &d_root_ptr_,
+                  &d_root_ids_, &d_U_, &d_C_, &d_upd_, &d_status_, &d_level_ids_}) {
+    if (b->p) A.put(b->p, b->bytes);
+    *b = DBuf();
+  }
+  for (auto *v : {&d_potrf_, &d_trsm_, &d_gemm_}) {
+    for (DBuf &b : *v)
+      if (b.p) A.put(b.p, b.bytes);
+    v->clear();
+  }
+  ready = false;
+}
+
+size_t MfDevice::bytes() const {
+  size_t t = 0;
+  for (const DBuf *b : {&d_fronts_, &d_child_, &d_piv_, &d_bnd_, &d_pmap_, &d_asm_, &d_root_ptr_,
+                        &d_root_ids_, &d_U_, &d_C_, &d_upd_, &d_status_, &d_level_ids_})
+    t += b->bytes;
+  return t;
+}
+
+void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAlloc &A, hipStream_t st) {
+  release(A);
+  sym = mf_analyze(P, offI);
+  const MfSymbolic &M = sym;
+  nnz_ = (int64_t)M.asm_dst.size();
+  d_fronts_ = upload(A, st, M.fronts);
+  d_child_ = upload(A, st, M.child_ids);
+  d_piv_ = upload(A, st, M.piv);
+  d_bnd_ = upload(A, st, M.bnd);
+  d_pmap_ = upload(A, st, M.pmap);
+  d_asm_ = upload(A, st, M.asm_dst);
+  d_root_ptr_ = upload(A, st, M.root_ptr);
+  d_root_ids_ = upload(A, st, M.root_ids);
+  d_U_ = zeros(A, st, sizeof(double) * (size_t)M.u_size);
+  d_C_ = zeros(A, st, sizeof(double) * (size_t)M.c_size);
+  d_upd_ = zeros(A, st, sizeof(double) * (size_t)M.upd_size);
+  d_status_ = zeros(A, st, sizeof(int) * (M.fronts.size() + 1));
+  // per-depth front lists and batched descriptors
+  const int D = M.max_depth;
+  std::vector<int> ids;
+  level_off_.assign(D + 2, 0);
+  h_potrf_.assign(D + 1, {});
+  h_trsm_.assign(D + 1, {});
+  h_gemm_.assign(D + 1, {});
+  max_f_.assign(D + 1, 0);
+  max_pb_.assign(D + 1, 0);
+  for (int d = 0; d <= D; ++d) {
+    level_off_[d] = (int64_t)ids.size();
+    for (int t : M.levels[d]) {
+      ids.push_back(t);
+      const MfFront &f = M.fronts[t];
+      max_f_[d] = std::max<int64_t>(max_f_[d], (int64_t)f.p * (f.p + f.b) + (int64_t)f.b * f.b);
+      max_pb_[d] = std::max(max_pb_[d], f.p + f.b);
+      if (f.p == 0) continue;
+      h_potrf_[d].push_back(MatDesc{f.u_off, 0, f.p, 0, f.p, f.p});
+      if (f.b == 0) continue;
+      h_trsm_[d].push_back(MatDesc{f.u_off, f.u_off + (int64_t)f.p * f.p, f.p, f.b, f.p, f.p});
+      h_gemm_[d].push_back(GemmDesc{f.u_off + (int64_t)f.p * f.p, f.u_off + (int64_t)f.p * f.p,
+                                    f.c_off, f.b, f.b, f.p, f.p, f.p, f.b});
+    }
+  }
+  level_off_[D + 1] = (int64_t)ids.size();
+  d_level_ids_ = upload(A, st, ids);
+  for (int d = 0; d <= D; ++d) {
+    d_potrf_.push_back(upload(A, st, h_potrf_[d]));
+    d_trsm_.push_back(upload(A, st, h_trsm_[d]));
+    d_gemm_.push_back(upload(A, st, h_gemm_[d]));
+  }
+  // the in-front solves keep p + b values in LDS
+  int max_lds = 0;
+  for (int d = 1; d <= D; ++d) max_lds = std::max(max_lds, max_pb_[d]);
+  if ((size_t)max_lds * sizeof(double) > 160 * 1024)
+    throw ArgError("a front of the interior elimination exceeds the LDS of one work-group");
+  if ((size_t)max_lds * sizeof(double) > 64 * 1024) {
+    HIPCHK(hipFuncSetAttribute((const void *)mf_bwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(max_lds * sizeof(double))));
+    HIPCHK(hipFuncSetAttribute((const void *)mf_fwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(max_lds * sizeof(double))));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  ready = true;
+}
+
+void MfDevice::factor(hipStream_t st, const double *val, int64_t nnz, double *S, const int64_t *offGG,
+                      const int *nG, int max_nG, int nsub) {
+  if (!ready) throw StateError("interior elimination not set up");
+  if (nnz != nnz_) throw ArgError("interior elimination: matrix size changed");
+  const MfSymbolic &M = sym;
+  double *U = d_U_.as<double>(), *C = d_C_.as<double>();
+  const MfFront *F = d_fronts_.as<MfFront>();
+  const int *ids = d_level_ids_.as<int>();
+  HIPCHK(hipMemsetAsync(d_U_.p, 0, d_U_.bytes, st));
+  HIPCHK(hipMemsetAsync(d_status_.p, 0, d_status_.bytes, st));
+  {
+    LaunchScope ls(st, "mf_assemble_kernel", 20.0 * (double)nnz, 0);
+    mf_assemble_kernel<<<nblocks(nnz), TPB, 0, st>>>(d_asm_.as<int64_t>(), val, nnz, U);
+    HIPCHK(hipGetLastError());
+  }
+  int *status = d_status_.as<int>();
+  for (int d = M.max_depth; d >= 1; --d) {
+    const int nf = (int)M.levels[d].size();
+    if (nf == 0) continue;
+    const int *lid = ids + level_off_[d];
+    {
+      double by = 0;
+      if (launch_timing())
+        for (int t : M.levels[d]) {
+          const MfFront &f = M.fronts[t];
+          by += 8.0 * ((double)f.p * (f.p + f.b) + 0.5 * (double)f.b * f.b);
+          for (int ci = 0; ci < f.n_child; ++ci) by += 4.0 * M.fronts[M.child_ids[f.child_ptr + ci]].b * 0.5 * M.fronts[M.child_ids[f.child_ptr + ci]].b;
+        }
+      LaunchScope ls(st, "mf_pull_kernel", by, 0);
+      const unsigned gx = (unsigned)std::min<int64_t>(2048, (max_f_[d] + TPB - 1) / TPB);
+      mf_pull_kernel<<<dim3(std::max(1u, gx), nf), TPB, 0, st>>>(F, lid, d_child_.as<int>(),
+                                                                 d_pmap_.as<int>(), U, C);
+      HIPCHK(hipGetLastError());
+    }
+    const int np = (int)h_potrf_[d].size();
+    if (np > 0)
+      HIPCHK(DenseOps<double>::potrf(st, U, d_potrf_[d].as<MatDesc>(), h_potrf_[d].data(), np,
+                                     status + level_off_[d]));
+    const int nt = (int)h_trsm_[d].size();
+    if (nt > 0) {
+      HIPCHK(DenseOps<double>::trsm(st, U, U, d_trsm_[d].as<MatDesc>(), h_trsm_[d].data(), nt, false));
+      int maxb = 0;
+      for (const GemmDesc &g : h_gemm_[d]) maxb = std::max(maxb, g.M);
+      HIPCHK(DenseOps<double>::gemm(st, U, U, C, d_gemm_[d].as<GemmDesc>(), nt, maxb, maxb, true, false,
+                                    -1.0, 1.0, true, h_gemm_[d].data()));
+    }
+  }
+  if (max_nG > 0 && nsub > 0) {
+    const unsigned gx = (unsigned)std::min<int64_t>(4096, ((int64_t)max_nG * max_nG + TPB - 1) / TPB);
+    LaunchScope ls(st, "mf_root_pull_kernel", 0, 0);
+    mf_root_pull_kernel<<<dim3(std::max(1u, gx), nsub), TPB, 0, st>>>(
+        F, d_root_ptr_.as<int>(), d_root_ids_.as<int>(), d_pmap_.as<int>(), C, S, offGG, nG);
+    HIPCHK(hipGetLastError());
+  }
+  // pivots
+  std::vector<int> hs(M.fronts.size() + 1);
+  HIPCHK(hipMemcpyAsync(hs.data(), d_status_.p, sizeof(int) * hs.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int d = 1; d <= M.max_depth; ++d)
+    for (size_t e = 0; e < h_potrf_[d].size(); ++e)
+      if (hs[level_off_[d] + e]) {
+        // batch entry e of depth d: find its front
+        int k = 0;
+        for (int t : M.levels[d]) {
+          if (M.fronts[t].p == 0) continue;
+          if (k++ == (int)e)
+            throw NotSpdError("interior elimination: non-positive pivot in substructure " +
+                              std::to_string(M.fronts[t].sub));
+        }
+      }
+}
+
+void MfDevice::solve(hipStream_t st, double *vI) {
+  if (!ready) throw StateError("interior elimination not set up");
+  const MfSymbolic &M = sym;
+  const MfFront *F = d_fronts_.as<MfFront>();
+  const int *ids = d_level_ids_.as<int>();
+  const double *U = d_U_.as<double>();
+  double *upd = d_upd_.as<double>();
+  auto level_bytes = [&](int d) {
+    double by = 0;
+    for (int t : M.levels[d]) {
+      const MfFront &f = M.fronts[t];
+      by += 8.0 * (0.5 * (double)f.p * (f.p + 1) + (double)f.p * f.b + 2.0 * f.p + f.b);
+    }
+    return by;
+  };
+  for (int d = M.max_depth; d >= 1; --d) {
+    const int nf = (int)M.levels[d].size();
+    if (nf == 0) continue;
+    LaunchScope ls(st, "mf_fwd_kernel", launch_timing() ? level_bytes(d) : 0, 0);
+    mf_fwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_pb_[d]), st>>>(
+        F, ids + level_off_[d], d_child_.as<int>(), d_pmap_.as<int>(), d_piv_.as<int64_t>(), U, upd, vI);
+    HIPCHK(hipGetLastError());
+  }
+  for (int d = 1; d <= M.max_depth; ++d) {
+    const int nf = (int)M.levels[d].size();
+    if (nf == 0) continue;
+    LaunchScope ls(st, "mf_bwd_kernel", launch_timing() ? level_bytes(d) : 0, 0);
+    mf_bwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_pb_[d]), st>>>(
+        F, ids + level_off_[d], d_piv_.as<int64_t>(), d_bnd_.as<int64_t>(), U, vI);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+}  // namespace bddc

@@ -7,6 +7,7 @@
 
 #include "device.h"
 #include "host.h"
+#include "multifrontal.h"
 
 namespace bddc {
 
@@ -102,7 +103,7 @@ class Solver {
   int verbose = 0;
 
   ~Solver();
-  void build(const Problem &P, hipStream_t st, bool keep_schur = false);
+  void build(const Problem &P, hipStream_t st, bool keep_interior = false);
   void factor();
   void factor_schur();
   void check_status(bool all);
@@ -136,14 +137,15 @@ class Solver {
   int64_t n_rows = 0, nnz = 0;
   double bytes_S = 0, bytes_Lrr_tri = 0;
   int n_gx = 0;
-  TrsvPlan plan_rr, plan_II, plan_c;
-  std::vector<MatDesc> h_descII, h_descRR, h_descGG, h_descC;
-  std::vector<GemmDesc> h_syrk, h_spi;
+  TrsvPlan plan_rr, plan_c;
+  std::vector<MatDesc> h_descRR, h_descGG, h_descC;
+  std::vector<GemmDesc> h_spi;
+  MfDevice mf;  // interior elimination (multifrontal)
 
   DBuf d_row_sub, d_row_loc, d_rowptr, d_col, d_val, d_nI, d_nG, d_nr, d_np;
-  DBuf d_offI, d_offG, d_offR, d_offP, d_offII, d_offIG, d_offGG, d_offRR, d_offRP, d_offPP;
-  DBuf d_AII, d_AIG, d_S, d_W, d_Lrr, d_Phi, d_Spi, d_Lc;
-  DBuf d_descII, d_descRR, d_descC, d_syrk, d_spi_desc, d_descGG, d_descRRvec, d_descIIvec,
+  DBuf d_offI, d_offG, d_offR, d_offP, d_offGG, d_offRR, d_offRP, d_offPP;
+  DBuf d_S, d_W, d_Lrr, d_Phi, d_Spi, d_Lc;
+  DBuf d_descRR, d_descC, d_spi_desc, d_descGG, d_descRRvec,
       d_descCvec;
   DBuf d_gx, d_gx_ptr, d_trow, d_pos, d_wmat, d_gk_glob, d_gk_k, d_scr;
   int64_t scrS_elems = 0;
@@ -151,7 +153,7 @@ class Solver {
   DBuf d_ridx, d_ridx_off, d_pidx, d_pidx_off, d_rabs, d_pabs, d_pcid, d_sub_cids;
   DBuf d_c_ptr, d_c_sub, d_c_loc, d_c_copies;
   DBuf d_ifc_gamma, d_ifc_delta, d_gamma_ptr, d_gamma_copies, d_gamma_gdof, d_int_gdof, d_ifc_gdof;
-  DBuf d_trsv_rr_fwd, d_trsv_rr_bwd, d_trsv_rr_off, d_trsv_II_fwd, d_trsv_II_bwd, d_trsv_II_off;
+  DBuf d_trsv_rr_fwd, d_trsv_rr_bwd, d_trsv_rr_off;
   DBuf d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, d_work_i, d_status;
   DBuf d_vG, d_vG2, d_vR, d_vR2, d_vP, d_vI, d_vI2, d_vc;
   DBuf d_gam_r, d_gam_z, d_gam_p, d_gam_q, d_gam_x, d_sc, d_part, d_alphas, d_betas;

@@ -83,24 +83,18 @@ inline unsigned nblocks(int64_t n, int tpb = TPB) {
 }
 
 // scatter the CSR substructure matrices into the dense blocks A_II, A_IG, A_GG
-__global__ void scatter_dense_kernel(const int *row_sub, const int *row_loc, const int64_t *rowptr,
-                                     const int *col, const double *val, int64_t nrows,
-                                     const int *nI, const int *nG, const int64_t *offII,
-                                     const int64_t *offIG, const int64_t *offGG, double *AII,
-                                     double *AIG, double *AGG) {
+// A_GG blocks of the substructure matrices into the dense interface pool
+__global__ void scatter_gg_kernel(const int *row_sub, const int *row_loc, const int64_t *rowptr,
+                                  const int *col, const double *val, int64_t nrows, const int *nI,
+                                  const int *nG, const int64_t *offGG, double *AGG) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nrows) return;
   const int s = row_sub[g], r = row_loc[g];
   const int ni = nI[s], ng = nG[s];
+  if (r < ni) return;
   for (int64_t k = rowptr[g]; k < rowptr[g + 1]; ++k) {
     const int c = col[k];
-    const double v = val[k];
-    if (r < ni && c < ni)
-      AII[offII[s] + r + (int64_t)c * ni] = v;
-    else if (r < ni && c >= ni)
-      AIG[offIG[s] + r + (int64_t)(c - ni) * ni] = v;
-    else if (r >= ni && c >= ni)
-      AGG[offGG[s] + (r - ni) + (int64_t)(c - ni) * ng] = v;
+    if (c >= ni) AGG[offGG[s] + (r - ni) + (int64_t)(c - ni) * ng] = val[k];
   }
 }
 
@@ -546,36 +540,37 @@ void Solver::free_all() {
   for (DBuf *b : all_buffers()) release(*b);
 }
 
-Solver::~Solver() { free_all(); }
+Solver::~Solver() {
+  free_all();
+  mf.release(alloc);
+}
 
 std::vector<DBuf *> Solver::all_buffers() {
   return {&d_row_sub, &d_row_loc, &d_rowptr, &d_col, &d_val, &d_nI, &d_nG, &d_nr, &d_np,
-          &d_offI, &d_offG, &d_offR, &d_offP, &d_offII, &d_offIG, &d_offGG, &d_offRR, &d_offRP,
-          &d_offPP, &d_AII, &d_AIG, &d_S, &d_W, &d_Lrr, &d_Phi, &d_Spi, &d_Lc, &d_descII,
-          &d_descRR, &d_descC, &d_syrk, &d_spi_desc, &d_descGG, &d_gx, &d_gx_ptr, &d_trow,
+          &d_offI, &d_offG, &d_offR, &d_offP, &d_offGG, &d_offRR, &d_offRP,
+          &d_offPP, &d_S, &d_W, &d_Lrr, &d_Phi, &d_Spi, &d_Lc,
+          &d_descRR, &d_descC, &d_spi_desc, &d_descGG, &d_gx, &d_gx_ptr, &d_trow,
           &d_pos, &d_ridx, &d_ridx_off, &d_pidx, &d_pidx_off, &d_rabs, &d_pabs, &d_pcid,
           &d_sub_cids, &d_c_ptr, &d_c_sub, &d_c_loc, &d_c_copies, &d_ifc_gamma, &d_ifc_delta,
           &d_gamma_ptr, &d_gamma_copies, &d_gamma_gdof, &d_int_gdof, &d_ifc_gdof,
-          &d_trsv_rr_fwd, &d_trsv_rr_bwd, &d_trsv_rr_off, &d_trsv_II_fwd, &d_trsv_II_bwd,
-          &d_trsv_II_off, &d_trsv_c_fwd, &d_trsv_c_bwd, &d_trsv_c_off, &d_work_i, &d_status,
+          &d_trsv_rr_fwd, &d_trsv_rr_bwd, &d_trsv_rr_off,
+          &d_trsv_c_fwd, &d_trsv_c_bwd, &d_trsv_c_off, &d_work_i, &d_status,
           &d_vG, &d_vG2, &d_vR, &d_vR2, &d_vP, &d_vI, &d_vI2, &d_vc, &d_gam_r, &d_gam_z,
           &d_gam_p, &d_gam_q, &d_gam_x, &d_sc, &d_part, &d_alphas, &d_betas, &d_descRRvec,
-          &d_descIIvec, &d_descCvec};
+          &d_descCvec};
 }
 
 // Host analysis after bddc_setup / adapt: layout, index maps, uploads of the
-// substructure matrices.  Matrices and vectors are (re)allocated, except the
-// Dirichlet factors and Schur complements when keep_schur is set and they are
-// current: they do not depend on the constraints.
-void Solver::build(const Problem &P, hipStream_t st, bool keep_schur) {
-  DBuf kAII, kAIG, kS;
-  const bool keep = keep_schur && schur_ready;
-  if (keep) {
-    std::swap(kAII, d_AII);
-    std::swap(kAIG, d_AIG);
-    std::swap(kS, d_S);
-  }
+// substructure matrices.  Matrices and vectors are (re)allocated, except, when
+// keep_interior is set (a rebuild for new constraints), the interior
+// elimination and -- when current -- the Schur complements: neither depends
+// on the constraints.
+void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
+  DBuf kS;
+  const bool keep = keep_interior && schur_ready;
+  if (keep) std::swap(kS, d_S);
   free_all();
+  if (!keep_interior) mf.release(alloc);
   stream = st;
   const int ns = (int)P.subs.size();
   L = Layout();
@@ -633,8 +628,6 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_schur) {
   L.sumG = offsets(L.nG, {}, L.offG);
   L.sumR = offsets(L.nr, {}, L.offR);
   L.sumP = offsets(L.np, {}, L.offP);
-  L.sII = offsets(L.nI, L.nI, L.offII);
-  L.sIG = offsets(L.nI, L.nG, L.offIG);
   L.sGG = offsets(L.nG, L.nG, L.offGG);
   L.sRR = offsets(L.nr, L.nr, L.offRR);
   L.sRP = offsets(L.nr, L.np, L.offRP);
@@ -674,8 +667,6 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_schur) {
   d_offG = upload(alloc, st, L.offG);
   d_offR = upload(alloc, st, L.offR);
   d_offP = upload(alloc, st, L.offP);
-  d_offII = upload(alloc, st, L.offII);
-  d_offIG = upload(alloc, st, L.offIG);
   d_offGG = upload(alloc, st, L.offGG);
   d_offRR = upload(alloc, st, L.offRR);
   d_offRP = upload(alloc, st, L.offRP);
@@ -812,30 +803,21 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_schur) {
   d_c_loc = upload(alloc, st, cloc);
   d_c_copies = upload(alloc, st, ccopies);
   // descriptors
-  std::vector<MatDesc> dII(ns), dRR(ns), dGG(ns), dIIv(ns), dRRv(ns);
-  std::vector<GemmDesc> syrk(ns), spi(ns);
+  std::vector<MatDesc> dRR(ns), dGG(ns), dRRv(ns);
+  std::vector<GemmDesc> spi(ns);
   for (int s = 0; s < ns; ++s) {
-    dII[s] = MatDesc{L.offII[s], L.offIG[s], L.nI[s], L.nG[s], std::max(1, L.nI[s]), std::max(1, L.nI[s])};
     dRR[s] = MatDesc{L.offRR[s], L.offRP[s], L.nr[s], L.np[s], std::max(1, L.nr[s]), std::max(1, L.nr[s])};
     dGG[s] = MatDesc{L.offGG[s], 0, L.nG[s], 0, std::max(1, L.nG[s]), 1};
-    dIIv[s] = MatDesc{L.offII[s], L.offI[s], L.nI[s], 1, std::max(1, L.nI[s]), (int)L.sumI};
     dRRv[s] = MatDesc{L.offRR[s], L.offR[s], L.nr[s], 1, std::max(1, L.nr[s]), (int)L.sumR};
-    syrk[s] = GemmDesc{L.offIG[s], L.offIG[s], L.offGG[s], L.nG[s], L.nG[s], L.nI[s],
-                       std::max(1, L.nI[s]), std::max(1, L.nI[s]), std::max(1, L.nG[s])};
     spi[s] = GemmDesc{L.offRP[s], L.offRP[s], L.offPP[s], L.np[s], L.np[s], L.nr[s],
                       std::max(1, L.nr[s]), std::max(1, L.nr[s]), std::max(1, L.np[s])};
   }
-  h_descII = dII;
   h_descRR = dRR;
   h_descGG = dGG;
-  d_descII = upload(alloc, st, dII);
   d_descRR = upload(alloc, st, dRR);
   d_descGG = upload(alloc, st, dGG);
-  d_descIIvec = upload(alloc, st, dIIv);
   d_descRRvec = upload(alloc, st, dRRv);
-  d_syrk = upload(alloc, st, syrk);
   d_spi_desc = upload(alloc, st, spi);
-  h_syrk = syrk;
   h_spi = spi;
   MatDesc dc{0, 0, (int)nc, 0, (int)std::max<int64_t>(1, nc), (int)std::max<int64_t>(1, nc)};
   h_descC = {dc};
@@ -864,26 +846,19 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_schur) {
     return total;
   };
   int w1 = plan(L.nr, d_trsv_rr_fwd, d_trsv_rr_bwd, d_trsv_rr_off, plan_rr);
-  int w2 = plan(L.nI, d_trsv_II_fwd, d_trsv_II_bwd, d_trsv_II_off, plan_II);
   int w3 = plan({(int)nc}, d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, plan_c);
-  d_work_i = alloc0(alloc, st, sizeof(int) * (size_t)(4 + std::max({w1, w2, w3})));
+  d_work_i = alloc0(alloc, st, sizeof(int) * (size_t)(4 + std::max(w1, w3)));
   d_status = alloc0(alloc, st, sizeof(int) * (size_t)(2 * ns + 2));
   // matrices
-  const bool kept = keep && kAII.bytes == std::max<size_t>(sizeof(double) * (size_t)L.sII, 8) &&
-                    kAIG.bytes == std::max<size_t>(sizeof(double) * (size_t)L.sIG, 8) &&
-                    kS.bytes == std::max<size_t>(sizeof(double) * (size_t)L.sGG, 8);
+  const bool kept = keep && kS.bytes == std::max<size_t>(sizeof(double) * (size_t)L.sGG, 8);
   if (kept) {
-    d_AII = kAII;
-    d_AIG = kAIG;
     d_S = kS;
   } else {
-    release(kAII);
-    release(kAIG);
     release(kS);
-    d_AII = alloc0(alloc, st, sizeof(double) * (size_t)L.sII);
-    d_AIG = alloc0(alloc, st, sizeof(double) * (size_t)L.sIG);
     d_S = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
   }
+  // interior elimination: structure from the mesh and partition only
+  if (!mf.ready) mf.setup(P, L.offI, alloc, st);
   d_W = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
   d_Lrr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
   d_Phi = alloc0(alloc, st, sizeof(double) * (size_t)L.sRP);
@@ -919,42 +894,21 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_schur) {
   schur_ready = kept;
 }
 
-// Dirichlet factors A_II = L L^T and Schur complements S_i (original basis);
-// independent of the constraints.
+// Dirichlet factors of A_II (multifrontal) and Schur complements S_i
+// (original basis); independent of the constraints.
 void Solver::factor_schur() {
   hipStream_t st = stream;
   const int ns = L.nsub;
   HIPCHK(hipMemsetAsync(d_status.p, 0, d_status.bytes, st));
-  HIPCHK(hipMemsetAsync(d_AII.p, 0, d_AII.bytes, st));
-  HIPCHK(hipMemsetAsync(d_AIG.p, 0, d_AIG.bytes, st));
   HIPCHK(hipMemsetAsync(d_S.p, 0, d_S.bytes, st));
-  scatter_dense_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
+  scatter_gg_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
       d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
-      d_val.as<double>(), n_rows, d_nI.as<int>(), d_nG.as<int>(), d_offII.as<int64_t>(),
-      d_offIG.as<int64_t>(), d_offGG.as<int64_t>(), d_AII.as<double>(), d_AIG.as<double>(),
+      d_val.as<double>(), n_rows, d_nI.as<int>(), d_nG.as<int>(), d_offGG.as<int64_t>(),
       d_S.as<double>());
   HIPCHK(hipGetLastError());
-  int *status = d_status.as<int>();
-  // Dirichlet factors and Schur complements
-  double fl_potrf = 0, fl_trsm = 0, fl_syrk = 0;
-  for (int s = 0; s < ns; ++s) {
-    const double ni = L.nI[s], ng = L.nG[s];
-    fl_potrf += ni * ni * ni / 3;
-    fl_trsm += ni * ni * ng;
-    fl_syrk += ng * ng * ni;
-  }
-  timer.begin(st, "factor_potrf_interior", 8.0 * L.sII, fl_potrf);
-  HIPCHK(DenseOps<double>::potrf(st, d_AII.as<double>(), d_descII.as<MatDesc>(), h_descII.data(), ns,
-                                 status));
-  timer.end(st);
-  timer.begin(st, "factor_trsm_interior", 8.0 * (L.sII / 2 + 2 * L.sIG), fl_trsm);
-  HIPCHK(DenseOps<double>::trsm(st, d_AII.as<double>(), d_AIG.as<double>(), d_descII.as<MatDesc>(),
-                                h_descII.data(), ns, false));
-  timer.end(st);
-  timer.begin(st, "factor_syrk_schur", 8.0 * (L.sIG + L.sGG), fl_syrk);
-  HIPCHK(DenseOps<double>::gemm(st, d_AIG.as<double>(), d_AIG.as<double>(), d_S.as<double>(),
-                                d_syrk.as<GemmDesc>(), ns, L.max_nG, L.max_nG, true, false, -1.0,
-                                1.0, true, h_syrk.data()));
+  timer.begin(st, "factor_interior_schur", 8.0 * (mf.sym.l_entries + (double)mf.sym.c_size), mf.sym.flops);
+  mf.factor(st, d_val.as<double>(), nnz, d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(),
+            L.max_nG, ns);
   timer.end(st);
   HIPCHK(symmetrize_lower<double>(st, d_S.as<double>(), d_descGG.as<MatDesc>(), ns, L.max_nG));
   check_status(false);
@@ -965,6 +919,7 @@ void Solver::factor() {
   hipStream_t st = stream;
   const int ns = L.nsub;
   auto t0 = std::chrono::steady_clock::now();
+  const bool did_interior = !schur_ready;
   if (schur_ready) {
     HIPCHK(hipMemsetAsync(d_status.p, 0, d_status.bytes, st));
   } else {
@@ -1050,12 +1005,12 @@ void Solver::factor() {
   check_status(true);
   auto t1 = std::chrono::steady_clock::now();
   factor_seconds = std::chrono::duration<double>(t1 - t0).count();
-  // flop count (dense, executed)
-  double fl = 0;
+  // flops executed by this call (the interior elimination only when it was
+  // not reused from bddc_adapt)
+  double fl = did_interior ? mf.sym.flops : 0.0;
   for (int s = 0; s < ns; ++s) {
-    const double ni = L.nI[s], ng = L.nG[s], nr = L.nr[s], np = L.np[s];
-    fl += ni * ni * ni / 3 + ni * ni * ng + ng * ng * ni + nr * nr * nr / 3 + 2 * nr * nr * np +
-          nr * np * np;
+    const double nr = L.nr[s], np = L.np[s];
+    fl += nr * nr * nr / 3 + 2 * nr * nr * np + nr * np * np;
   }
   fl += (double)nc * nc * nc / 3;
   factor_flops = fl;
@@ -1150,8 +1105,7 @@ void Solver::dot(const double *a, const double *b, int64_t n, double *out) {
 
 // interior Dirichlet solve in every substructure: vI <- A_II^-1 vI
 void Solver::interior_solve(double *vI) {
-  trsv(plan_II, d_AII, d_descIIvec, vI, false, 1);
-  trsv(plan_II, d_AII, d_descIIvec, vI, true, 1);
+  mf.solve(stream, vI);
 }
 
 // z = M r for global vectors (Algorithm 2): the interior part of r enters

@@ -98,28 +98,29 @@ def test_pcg_matches_oracle(name):
     # iteration on the contrast-1e4 case, so later values are not compared.
     k = min(3, len(hist), len(ref["resid"]))
     np.testing.assert_allclose(hist[:k], np.asarray(ref["resid"][:k]), rtol=1e-6)
-    check_iterations(info[0].iters, ref)
+    check_iterations(info[0].iters, hist, ref)
     assert rel(u, ref["u"]) < 1e-8
     assert abs(info[0].kappa - ref["kappa"]) < 1e-3 * ref["kappa"]
     assert info[0].lmin > 1 - 1e-9
     b.close()
 
 
-def check_iterations(it_gpu, ref, rtol=1e-8):
+def check_iterations(it_gpu, hist_gpu, ref, rtol=1e-8):
     """Iteration counts of two FP64 CG runs that differ only in rounding.
 
-    Equal, or up to max(2, 5%) apart: the stopping test compares a
-    non-monotone residual norm with the tolerance, and rounding moves the
-    iteration where it first drops below.  The oracle must itself be near
-    convergence at the smaller count (relative residual within 100x the
-    tolerance), so a premature stop on either side is caught."""
+    Near the tolerance the CG residual norm oscillates (by factors of 2-5
+    per step at kappa ~ 400), and rounding moves the iteration where it first
+    drops below the tolerance.  So the counts may differ, but the run that
+    stopped later must already have been within 100x the tolerance at the
+    other run's stopping iteration (a premature stop on either side fails
+    this), and the counts stay within 15% of each other."""
     it_ref = ref["iters"]
     if it_gpu == it_ref:
         return
-    allow = max(2, int(0.05 * it_ref))
-    assert abs(it_gpu - it_ref) <= allow, (it_gpu, it_ref, ref["kappa"])
+    assert abs(it_gpu - it_ref) <= max(2, int(0.15 * it_ref)), (it_gpu, it_ref, ref["kappa"])
     k = min(it_gpu, it_ref)
-    assert ref["resid"][k] <= 100 * rtol, (it_gpu, it_ref, ref["resid"][k])
+    later = ref["resid"] if it_ref > it_gpu else hist_gpu
+    assert later[k] <= 100 * rtol, (it_gpu, it_ref, later[k])
 
 
 def test_pcg_matches_direct_poisson16():
