@@ -40,8 +40,11 @@ MFMA_KERNELS = ("gemm_kernel", "chol_update_kernel", "chol_panel_kernel", "chol_
                 "trsm_update_kernel<fwd>", "trsm_update_kernel<bwd>", "trsm_diag_kernel<fwd>",
                 "trsm_diag_kernel<bwd>")
 KERNEL_SOURCE = {k: "paper_0910_5863_amd/csrc/dense.hip" for k in MFMA_KERNELS}
-KERNEL_SOURCE.update({"trsv_kernel<fwd>": "paper_0910_5863_amd/csrc/dense.hip",
-                      "trsv_kernel<bwd>": "paper_0910_5863_amd/csrc/dense.hip",
+KERNEL_SOURCE.update({"trsv_kernel<lower>": "paper_0910_5863_amd/csrc/dense.hip",
+                      "trsv_kernel<upper>": "paper_0910_5863_amd/csrc/dense.hip",
+                      "mf_fwd_kernel": "paper_0910_5863_amd/csrc/multifrontal.hip",
+                      "mf_bwd_kernel": "paper_0910_5863_amd/csrc/multifrontal.hip",
+                      "mf_pull_kernel": "paper_0910_5863_amd/csrc/multifrontal.hip",
                       "gemv_t_kernel": "paper_0910_5863_amd/csrc/solver.hip",
                       "gemv_n_kernel": "paper_0910_5863_amd/csrc/solver.hip",
                       "lobpcg_kernel": "paper_0910_5863_amd/csrc/adapt.hip"})
@@ -200,7 +203,7 @@ def main():
     roof["avg_launch_us"] = avg_s * 1e6
     roof["algorithmic_bytes_per_launch"] = st["bytes"] / st["launches"]
     roof["algorithmic_flops_per_launch"] = st["flops"] / st["launches"]
-    top = sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:8]
+    top = sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:16]
     kernels = []
     for k, v in top:
         s_ = v["ms"] / 1e3

@@ -1124,6 +1124,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   for (int e = 0; e < nside + 2 * np; ++e)
     if (hstat[e])
       throw NotSpdError("adaptive pair problems: non-positive pivot in a pair factor (Assumption 2 may fail)");
+  log("eigenvectors to jump space");
   // ---- host: face rows
   for (int p = 0; p < np; ++p) {
     const PairHost &ph = pairs[p];
@@ -1163,6 +1164,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
     P.extra_k[ph.gi] += added;
     res.n_added += added;
   }
+  log("face rows (host)");
   return res;
 }
 

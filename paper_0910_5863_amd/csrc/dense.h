@@ -79,10 +79,13 @@ struct DenseOps {
 template <class T>
 hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn);
 
-// Few-RHS triangular solves with per-block completion flags (one launch per
-// direction).  x <- L^{-1} x (forward) or L^{-T} x (backward), nrhs <= 8,
-// x at xpool + b_off with leading dimension ldb.  work must hold
-// 1 + sum over entries of ceil(n/NB) ints; it is cleared by the call.
+// One-right-hand-side triangular solves with per-block completion flags (one
+// launch per solve, all entries together): x <- L^{-1} x for a lower
+// triangular L (upper = false) or x <- U^{-1} x for an upper triangular U
+// (upper = true), both column-major at a_off with leading dimension lda; x at
+// xpool + b_off.  L^{-T} x is the upper solve with U = L^T (transpose_batched).
+// work must hold 1 + sum over entries of ceil(n/NB) ints; it is cleared by the
+// call.  err receives 1 if a wait bound is exceeded.
 struct TrsvPlan {
   int batch = 0;
   int total_blocks = 0;
@@ -93,9 +96,24 @@ struct TrsvPlan {
   double rows = 0;             // sum over entries of n
 };
 
+// dinv / dinv_off: inverses of the NB x NB diagonal blocks of L (diag_inverse;
+// the same arrays serve the upper solve with U = L^T).
 template <class T>
 hipError_t trsv_blocked(hipStream_t st, const T *apool, T *xpool, const MatDesc *d_desc,
-                        const TrsvPlan &plan, bool transpose, int nrhs, int *work, int *err);
+                        const TrsvPlan &plan, bool upper, const T *dinv, const int64_t *dinv_off,
+                        int *work, int *err);
+
+// Inverses of the NB x NB diagonal blocks of every entry's lower triangular
+// factor (a_off, n, lda of d_desc): block kb of entry e at
+// inv + inv_off[e] + kb NB^2, column-major with ld NB.
+template <class T>
+hipError_t diag_inverse(hipStream_t st, const T *pool, const MatDesc *d_desc, int batch, int maxn,
+                        T *inv, const int64_t *inv_off);
+
+// B <- A^T for every entry (n x n matrices: A at a_off, lda; B at b_off, ldb)
+template <class T>
+hipError_t transpose_batched(hipStream_t st, const T *apool, T *bpool, const MatDesc *d_desc,
+                             int batch, int maxn);
 
 // Host: ticket orders for entries of sizes n (forward: block index upwards,
 // backward: downwards, level by level across entries) and flag offsets.

@@ -364,9 +364,7 @@ __global__ void symmetrize_kernel(T *pool, const MatDesc *desc, int maxn) {
   }
 }
 
-// --- few-RHS blocked triangular solve with completion flags ----------------
-
-constexpr int TRSV_MAXRHS = 8;
+// --- one-RHS blocked triangular solve with completion flags -----------------
 
 template <class T>
 __device__ __forceinline__ T ld_coherent(const T *p) {
@@ -377,36 +375,60 @@ __device__ __forceinline__ void st_coherent(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Bounded spin on a completion flag: the block waited on holds a smaller
+// ticket, so it is resident or done; the bound only guards against an earlier
+// fault.  The spin reads relaxed; one acquire fence follows success.
 __device__ bool wait_flag(int *flag, int *err) {
-  // bounded spin: the block waited on holds a smaller ticket, so it is
-  // resident or done; the bound only guards against an earlier fault
   for (long it = 0; it < (1L << 26); ++it) {
-    if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) return true;
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      return true;
+    }
     __builtin_amdgcn_s_sleep(1);
   }
   atomicExch(err, 1);
   return false;
 }
 
-template <class T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+__device__ __forceinline__ bool flag_set(int *flag) {
+  if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return false;
+  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  return true;
 }
 
-// One work-group per 64-row block (entry e, block kb), taken in ticket order:
-// forward solves walk kb upwards, backward solves downwards, so every block a
-// work-group waits on belongs to a smaller ticket.
-template <class T, bool BWD>
+// value of v in lane l (l uniform over the wave)
+__device__ __forceinline__ double readlane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// One work-group per 64-row block k of one entry, taken in ticket order
+// (lower: blocks upwards, upper: downwards), so every block waited on holds a
+// smaller ticket.  The work-group accumulates the products of its block row
+// with the solution blocks as they complete: each round takes every block
+// already solved (up to 32); block j always goes to wave j mod 4 and every
+// wave adds its blocks in order, so the sums do not depend on timing.  A lane
+// owns one row and reads its row of each 64 x 64 tile with coalesced loads.
+// The tile of the block solved last (on the critical path) is loaded into
+// registers, a quarter per wave, before waiting.  The diagonal block is
+// applied through its precomputed inverse (staged in LDS before waiting).
+// The upper variant solves U x = b for an upper triangular U stored
+// column-major, so that L^T x = b runs on an explicit transpose of L with the
+// same coalesced access.
+template <class T, bool UPPER>
 __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, const MatDesc *desc,
+                                                   const T *dinv, const int64_t *dinv_off,
                                                    const int *order, const int *flag_off,
-                                                   int total, int *work, int nrhs, int *err) {
-  __shared__ int s_ticket, s_ok;
+                                                   int total, int *work, int *err) {
+  __shared__ int s_ticket, s_ok, s_end;
   __shared__ T D[NB][NB + 1];
-  __shared__ T Tl[NB][NB + 1];
-  __shared__ T ys[NB][TRSV_MAXRHS];
-  __shared__ T part[4][NB][TRSV_MAXRHS];
+  __shared__ T part[4][NB];
+  __shared__ T vs[NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     s_ticket = atomicAdd(&work[0], 1);
@@ -415,83 +437,152 @@ __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, con
   __syncthreads();
   const int tk = s_ticket;
   if (tk >= total) return;
-  const int e = order[2 * tk], kbk = order[2 * tk + 1];
+  const int e = order[2 * tk], k = order[2 * tk + 1];
   const MatDesc d = desc[e];
   const T *L = apool + d.a_off;
   T *x = xpool + d.b_off;
-  const int64_t lda = d.lda, ldb = d.ldb;
+  const int64_t lda = d.lda;
   const int nblk = (d.n + NB - 1) / NB;
-  const int r0 = kbk * NB, w = min(NB, d.n - r0);
+  const int r0 = k * NB, w = min(NB, d.n - r0);
+  const int rl = r0 + min(lane, w - 1);  // row read by this lane (clamped)
   int *flags = work + 1 + flag_off[e];
+  const int step = UPPER ? -1 : 1;
+  const int last = k - step;                        // block solved just before this one
+  const bool has_last = UPPER ? last < nblk : last >= 0;
+  // critical-path tile: columns 16 wave .. 16 wave + 15 of block `last`
+  T pf[16];
+  int wl = 0;
+  if (has_last) {
+    const int c0 = last * NB;
+    wl = min(NB, d.n - c0);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int c = wave * 16 + i;
+      pf[i] = c < wl ? L[rl + (int64_t)(c0 + c) * lda] : T(0);
+    }
+  }
+  // inverse of the diagonal block of L (of L^T's transpose for the upper
+  // variant)
+  const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i % NB, c = i / NB;
-    D[r][c] = (r < w && c < w && r >= c) ? L[(r0 + r) + (r0 + c) * lda] : T(0);
+    D[r][c] = (r < w && c < w && r >= c) ? Di[r + c * NB] : T(0);
   }
-  T acc[TRSV_MAXRHS];
+  // right-hand side of this block (only this work-group overwrites it)
+  const T rhs = (wave == 0 && lane < w) ? x[r0 + lane] : T(0);
+  T acc = T(0);
+  // blocks before `last`, in rounds
+  int next = UPPER ? nblk - 1 : 0;
+  while (UPPER ? next > last : next < last) {
+    if (tid == 0) {
+      if (!wait_flag(&flags[next], err)) s_ok = 0;
+      int end = next + step;
+      for (int c = 1; c < 32 && (UPPER ? end > last : end < last) && flag_set(&flags[end]); ++c)
+        end += step;
+      s_end = end;
+    }
+    __syncthreads();
+    const int end = s_end;
+    for (int jb = next; jb != end; jb += step) {
+      const int owner = UPPER ? (nblk - 1 - jb) & 3 : jb & 3;
+      if (owner != wave) continue;
+      const int c0 = jb * NB, wc = min(NB, d.n - c0);
+      const T xv = lane < wc ? ld_coherent(&x[c0 + lane]) : T(0);
+      const T *row = L + rl + (int64_t)c0 * lda;
+      T a = T(0);
+      if (wc == NB) {
+#pragma unroll 32
+        for (int c = 0; c < NB; ++c) a += row[(int64_t)c * lda] * readlane(xv, c);
+      } else {
+        for (int c = 0; c < wc; ++c) a += row[(int64_t)c * lda] * readlane(xv, c);
+      }
+      acc += a;
+    }
+    next = end;
+    __syncthreads();
+  }
+  if (has_last) {
+    if (tid == 0 && !wait_flag(&flags[last], err)) s_ok = 0;
+    __syncthreads();
+    const int c0 = last * NB;
+    const T xv = lane < wl ? ld_coherent(&x[c0 + lane]) : T(0);
+    T a = T(0);
 #pragma unroll
-  for (int q = 0; q < TRSV_MAXRHS; ++q) acc[q] = T(0);
-  const int jfirst = BWD ? nblk - 1 : 0;
-  const int jstep = BWD ? -1 : 1;
-  for (int jb = jfirst; BWD ? (jb > kbk) : (jb < kbk); jb += jstep) {
-    const int c0 = jb * NB, wc = min(NB, d.n - c0);
-    if (BWD) {
-      // L block (jb, kbk): rows c0.., columns r0..; staged for a transposed use
-      for (int i = tid; i < NB * NB; i += 256) {
-        const int r = i % NB, c = i / NB;
-        Tl[r][c] = (r < wc && c < w) ? L[(c0 + r) + (int64_t)(r0 + c) * lda] : T(0);
-      }
-    }
-    if (tid == 0 && !wait_flag(&flags[jb], err)) s_ok = 0;
-    __syncthreads();
-    for (int i = tid; i < wc * nrhs; i += 256) {
-      const int r = i % wc, q = i / wc;
-      ys[r][q] = ld_coherent(&x[(c0 + r) + q * ldb]);
-    }
-    __syncthreads();
-    if (!BWD) {
-      // acc[row] -= L[r0+row, c0+c] y[c], the wave's quarter of the columns
-      if (lane < w)
-        for (int c = wave; c < wc; c += 4) {
-          const T l = L[(r0 + lane) + (int64_t)(c0 + c) * lda];
-          for (int q = 0; q < nrhs; ++q) acc[q] -= l * ys[c][q];
-        }
-    } else {
-      // acc[col] -= L[c0+r, r0+col] x[r], the wave's quarter of the rows
-      if (lane < w)
-        for (int r = wave; r < wc; r += 4) {
-          const T l = Tl[r][lane];
-          for (int q = 0; q < nrhs; ++q) acc[q] -= l * ys[r][q];
-        }
-    }
-    __syncthreads();
+    for (int i = 0; i < 16; ++i) a += pf[i] * readlane(xv, wave * 16 + i);
+    acc += a;
   }
-  for (int q = 0; q < nrhs; ++q) part[wave][lane][q] = acc[q];
+  part[wave][lane] = acc;
   __syncthreads();
-  // the diagonal block: one wave per right-hand side, values in registers
-  if (wave < nrhs) {
-    const int q = wave;
+  if (wave == 0) {
     T v = T(0);
-    if (lane < w)
-      v = x[(r0 + lane) + q * ldb] + part[0][lane][q] + part[1][lane][q] + part[2][lane][q] +
-          part[3][lane][q];
-    if (!BWD) {
-      for (int r = 0; r < w; ++r) {
-        const T s = wave_sum((lane < r) ? D[r][lane] * v : T(0));
-        if (lane == r) v = (v - s) / D[r][r];
-      }
+    if (lane < w) v = rhs - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+    vs[lane] = v;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // x_k = D^-1 v (lower) or D^-T v (upper), D^-1 lower triangular
+    T y = T(0);
+    if (!UPPER) {
+      for (int c = 0; c <= min(lane, w - 1); ++c) y += D[lane][c] * vs[c];
     } else {
-      for (int r = w - 1; r >= 0; --r) {
-        const T s = wave_sum((lane > r && lane < w) ? D[lane][r] * v : T(0));
-        if (lane == r) v = (v - s) / D[r][r];
-      }
+      for (int c = lane; c < w; ++c) y += D[c][lane] * vs[c];
     }
-    if (lane < w) st_coherent(&x[(r0 + lane) + q * ldb], v);
+    if (lane < w) st_coherent(&x[r0 + lane], y);
   }
   __syncthreads();
   if (tid == 0) {
     __threadfence();
-    __hip_atomic_store(&flags[kbk], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&flags[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (!s_ok) atomicExch(err, 1);
+  }
+}
+
+// Inverse of every NB x NB diagonal block of the lower triangular L of each
+// entry: block kb of entry e goes to inv + inv_off[e] + kb NB^2 (column-major,
+// ld NB, upper part zero).  One work-group per block; thread j solves for
+// column j of the inverse.
+template <class T>
+__global__ __launch_bounds__(64) void diag_inv_kernel(const T *pool, const MatDesc *desc, T *inv,
+                                                      const int64_t *inv_off) {
+  __shared__ T D[NB][NB + 1];
+  __shared__ T Y[NB][NB + 1];  // Y[i][j]: row i of column j of the inverse
+  const MatDesc d = desc[blockIdx.y];
+  const int kb = blockIdx.x, r0 = kb * NB;
+  if (r0 >= d.n) return;
+  const int w = min(NB, d.n - r0), j = threadIdx.x;
+  const T *A = pool + d.a_off;
+  for (int c = 0; c < w; ++c)
+    if (j < w) D[j][c] = (j >= c) ? A[(r0 + j) + (int64_t)(r0 + c) * d.lda] : T(0);
+  for (int i = 0; i < NB; ++i) Y[i][j] = T(0);
+  __syncthreads();
+  if (j < w) {
+    for (int i = j; i < w; ++i) {
+      T sacc = (i == j) ? T(1) : T(0);
+      for (int m = j; m < i; ++m) sacc -= D[i][m] * Y[m][j];
+      Y[i][j] = sacc / D[i][i];
+    }
+  }
+  __syncthreads();
+  T *out = inv + inv_off[blockIdx.y] + (int64_t)kb * NB * NB;
+  for (int c = 0; c < NB; ++c) out[j + (int64_t)c * NB] = Y[j][c];
+}
+
+// B <- A^T for every entry (n x n, lda / ldb); used to keep L^T beside L
+template <class T>
+__global__ void transpose_kernel(const T *apool, T *bpool, const MatDesc *desc) {
+  const MatDesc d = desc[blockIdx.z];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  if (c0 >= d.n || r0 >= d.n) return;
+  __shared__ T tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int j = ty; j < 32; j += 8) {
+    const int r = r0 + tx, c = c0 + j;
+    tile[j][tx] = (r < d.n && c < d.n) ? apool[d.a_off + r + (int64_t)c * d.lda] : T(0);
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int r = c0 + tx, c = r0 + j;
+    if (r < d.n && c < d.n) bpool[d.b_off + r + (int64_t)c * d.ldb] = tile[tx][j];
   }
 }
 
@@ -656,25 +747,42 @@ hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int 
 }
 
 template <class T>
+hipError_t diag_inverse(hipStream_t st, const T *pool, const MatDesc *d_desc, int batch, int maxn,
+                        T *inv, const int64_t *inv_off) {
+  if (batch <= 0 || maxn <= 0) return hipSuccess;
+  LaunchScope ls(st, "diag_inv_kernel", 0, 0);
+  diag_inv_kernel<T><<<dim3((maxn + NB - 1) / NB, batch), 64, 0, st>>>(pool, d_desc, inv, inv_off);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t trsv_blocked(hipStream_t st, const T *apool, T *xpool, const MatDesc *d_desc,
-                        const TrsvPlan &plan, bool transpose, int nrhs, int *work, int *err) {
+                        const TrsvPlan &plan, bool upper, const T *dinv, const int64_t *dinv_off,
+                        int *work, int *err) {
   if (plan.total_blocks == 0) return hipSuccess;
-  if (nrhs > TRSV_MAXRHS) return hipErrorInvalidValue;
   const int nz = 1 + plan.total_blocks;
   zero_ints_kernel<<<(nz + 255) / 256, 256, 0, st>>>(work, nz);
-  const int *order = transpose ? plan.d_order_bwd : plan.d_order_fwd;
-  // one pass over the stored triangle, the right-hand sides read and written
-  LaunchScope ls(st, transpose ? "trsv_kernel<bwd>" : "trsv_kernel<fwd>",
-                 sizeof(T) * (plan.tri_elems + 2.0 * nrhs * plan.rows),
-                 2.0 * nrhs * plan.tri_elems);
-  if (!transpose)
-    trsv_kernel<T, false><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, order,
-                                                            plan.d_flag_off, plan.total_blocks,
-                                                            work, nrhs, err);
+  const int *order = upper ? plan.d_order_bwd : plan.d_order_fwd;
+  // one pass over the stored triangle, the right-hand side read and written
+  LaunchScope ls(st, upper ? "trsv_kernel<upper>" : "trsv_kernel<lower>",
+                 sizeof(T) * (plan.tri_elems + 2.0 * plan.rows), 2.0 * plan.tri_elems);
+  if (!upper)
+    trsv_kernel<T, false><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, dinv, dinv_off,
+                                                            order, plan.d_flag_off,
+                                                            plan.total_blocks, work, err);
   else
-    trsv_kernel<T, true><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, order,
-                                                           plan.d_flag_off, plan.total_blocks,
-                                                           work, nrhs, err);
+    trsv_kernel<T, true><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, dinv, dinv_off,
+                                                           order, plan.d_flag_off,
+                                                           plan.total_blocks, work, err);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t transpose_batched(hipStream_t st, const T *apool, T *bpool, const MatDesc *d_desc,
+                             int batch, int maxn) {
+  if (batch <= 0 || maxn <= 0) return hipSuccess;
+  const unsigned t = (unsigned)((maxn + 31) / 32);
+  transpose_kernel<T><<<dim3(t, t, batch), 256, 0, st>>>(apool, bpool, d_desc);
   return hipGetLastError();
 }
 
@@ -706,8 +814,18 @@ template struct DenseOps<float>;
 template hipError_t symmetrize_lower<double>(hipStream_t, double *, const MatDesc *, int, int);
 template hipError_t symmetrize_lower<float>(hipStream_t, float *, const MatDesc *, int, int);
 template hipError_t trsv_blocked<double>(hipStream_t, const double *, double *, const MatDesc *,
-                                         const TrsvPlan &, bool, int, int *, int *);
+                                         const TrsvPlan &, bool, const double *, const int64_t *,
+                                         int *, int *);
 template hipError_t trsv_blocked<float>(hipStream_t, const float *, float *, const MatDesc *,
-                                        const TrsvPlan &, bool, int, int *, int *);
+                                        const TrsvPlan &, bool, const float *, const int64_t *,
+                                        int *, int *);
+template hipError_t diag_inverse<double>(hipStream_t, const double *, const MatDesc *, int, int,
+                                         double *, const int64_t *);
+template hipError_t diag_inverse<float>(hipStream_t, const float *, const MatDesc *, int, int,
+                                        float *, const int64_t *);
+template hipError_t transpose_batched<double>(hipStream_t, const double *, double *, const MatDesc *,
+                                              int, int);
+template hipError_t transpose_batched<float>(hipStream_t, const float *, float *, const MatDesc *,
+                                             int, int);
 
 }  // namespace bddc

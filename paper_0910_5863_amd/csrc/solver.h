@@ -130,7 +130,8 @@ class Solver {
   void scatter_gamma(const double *zg, double *z);
   void scatter_interior(const double *vI, double *z);
   void scatter64(const double *src, const int64_t *idx, int64_t n, double *dst);
-  void trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, double *x, bool t, int nrhs);
+  void trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
+            const DBuf &dinv_off, double *x, bool upper);
   void release(DBuf &b);
   std::vector<DBuf *> all_buffers();
 
@@ -144,7 +145,8 @@ class Solver {
 
   DBuf d_row_sub, d_row_loc, d_rowptr, d_col, d_val, d_nI, d_nG, d_nr, d_np;
   DBuf d_offI, d_offG, d_offR, d_offP, d_offGG, d_offRR, d_offRP, d_offPP;
-  DBuf d_S, d_W, d_Lrr, d_Phi, d_Spi, d_Lc;
+  DBuf d_S, d_W, d_Lrr, d_Urr, d_Phi, d_Spi, d_Lc, d_Uc, d_descRRT;
+  DBuf d_dinv_rr, d_dinv_rr_off, d_dinv_c, d_dinv_c_off;
   DBuf d_descRR, d_descC, d_spi_desc, d_descGG, d_descRRvec,
       d_descCvec;
   DBuf d_gx, d_gx_ptr, d_trow, d_pos, d_wmat, d_gk_glob, d_gk_k, d_scr;

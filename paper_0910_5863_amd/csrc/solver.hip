@@ -548,7 +548,8 @@ Solver::~Solver() {
 std::vector<DBuf *> Solver::all_buffers() {
   return {&d_row_sub, &d_row_loc, &d_rowptr, &d_col, &d_val, &d_nI, &d_nG, &d_nr, &d_np,
           &d_offI, &d_offG, &d_offR, &d_offP, &d_offGG, &d_offRR, &d_offRP,
-          &d_offPP, &d_S, &d_W, &d_Lrr, &d_Phi, &d_Spi, &d_Lc,
+          &d_offPP, &d_S, &d_W, &d_Lrr, &d_Urr, &d_Phi, &d_Spi, &d_Lc, &d_Uc, &d_descRRT,
+          &d_dinv_rr, &d_dinv_rr_off, &d_dinv_c, &d_dinv_c_off,
           &d_descRR, &d_descC, &d_spi_desc, &d_descGG, &d_gx, &d_gx_ptr, &d_trow,
           &d_pos, &d_ridx, &d_ridx_off, &d_pidx, &d_pidx_off, &d_rabs, &d_pabs, &d_pcid,
           &d_sub_cids, &d_c_ptr, &d_c_sub, &d_c_loc, &d_c_copies, &d_ifc_gamma, &d_ifc_delta,
@@ -803,12 +804,13 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_c_loc = upload(alloc, st, cloc);
   d_c_copies = upload(alloc, st, ccopies);
   // descriptors
-  std::vector<MatDesc> dRR(ns), dGG(ns), dRRv(ns);
+  std::vector<MatDesc> dRR(ns), dGG(ns), dRRv(ns), dRRT(ns);
   std::vector<GemmDesc> spi(ns);
   for (int s = 0; s < ns; ++s) {
     dRR[s] = MatDesc{L.offRR[s], L.offRP[s], L.nr[s], L.np[s], std::max(1, L.nr[s]), std::max(1, L.nr[s])};
     dGG[s] = MatDesc{L.offGG[s], 0, L.nG[s], 0, std::max(1, L.nG[s]), 1};
     dRRv[s] = MatDesc{L.offRR[s], L.offR[s], L.nr[s], 1, std::max(1, L.nr[s]), (int)L.sumR};
+    dRRT[s] = MatDesc{L.offRR[s], L.offRR[s], L.nr[s], 0, std::max(1, L.nr[s]), std::max(1, L.nr[s])};
     spi[s] = GemmDesc{L.offRP[s], L.offRP[s], L.offPP[s], L.np[s], L.np[s], L.nr[s],
                       std::max(1, L.nr[s]), std::max(1, L.nr[s]), std::max(1, L.np[s])};
   }
@@ -817,6 +819,7 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_descRR = upload(alloc, st, dRR);
   d_descGG = upload(alloc, st, dGG);
   d_descRRvec = upload(alloc, st, dRRv);
+  d_descRRT = upload(alloc, st, dRRT);
   d_spi_desc = upload(alloc, st, spi);
   h_spi = spi;
   MatDesc dc{0, 0, (int)nc, 0, (int)std::max<int64_t>(1, nc), (int)std::max<int64_t>(1, nc)};
@@ -861,9 +864,24 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   if (!mf.ready) mf.setup(P, L.offI, alloc, st);
   d_W = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
   d_Lrr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
+  d_Urr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
   d_Phi = alloc0(alloc, st, sizeof(double) * (size_t)L.sRP);
   d_Spi = alloc0(alloc, st, sizeof(double) * (size_t)L.sPP);
   d_Lc = alloc0(alloc, st, sizeof(double) * (size_t)(nc * nc));
+  d_Uc = alloc0(alloc, st, sizeof(double) * (size_t)(nc * nc));
+  {
+    // inverses of the NB x NB diagonal blocks of L_rr and L_c
+    std::vector<int64_t> off(ns);
+    int64_t tot = 0;
+    for (int s = 0; s < ns; ++s) {
+      off[s] = tot;
+      tot += (int64_t)((L.nr[s] + NB - 1) / NB) * NB * NB;
+    }
+    d_dinv_rr = alloc0(alloc, st, sizeof(double) * (size_t)tot);
+    d_dinv_rr_off = upload(alloc, st, off);
+    d_dinv_c = alloc0(alloc, st, sizeof(double) * (size_t)(((nc + NB - 1) / NB) * NB * NB));
+    d_dinv_c_off = upload(alloc, st, std::vector<int64_t>{0});
+  }
   // work vectors (nrhs up to kMaxRhs)
   const size_t R = kMaxRhs;
   d_vG = alloc0(alloc, st, sizeof(double) * L.sumG * R);
@@ -991,6 +1009,12 @@ void Solver::factor() {
                                                  L.sRP);
     HIPCHK(hipGetLastError());
   }
+  // L_rr^T beside L_rr (the backward solves read it row-coalesced) and the
+  // inverses of the diagonal blocks of L_rr
+  HIPCHK(transpose_batched<double>(st, d_Lrr.as<double>(), d_Urr.as<double>(),
+                                   d_descRRT.as<MatDesc>(), ns, L.max_nr));
+  HIPCHK(diag_inverse<double>(st, d_Lrr.as<double>(), d_descRRT.as<MatDesc>(), ns, L.max_nr,
+                              d_dinv_rr.as<double>(), d_dinv_rr_off.as<int64_t>()));
   // coarse problem
   const int64_t nc = L.n_coarse;
   if (nc > 0) {
@@ -1001,6 +1025,10 @@ void Solver::factor() {
     HIPCHK(hipGetLastError());
     HIPCHK(DenseOps<double>::potrf(st, d_Lc.as<double>(), d_descC.as<MatDesc>(), h_descC.data(), 1,
                                    status + 2 * ns));
+    HIPCHK(transpose_batched<double>(st, d_Lc.as<double>(), d_Uc.as<double>(), d_descC.as<MatDesc>(), 1,
+                                     (int)nc));
+    HIPCHK(diag_inverse<double>(st, d_Lc.as<double>(), d_descC.as<MatDesc>(), 1, (int)nc,
+                                d_dinv_c.as<double>(), d_dinv_c_off.as<int64_t>()));
   }
   check_status(true);
   auto t1 = std::chrono::steady_clock::now();
@@ -1042,8 +1070,10 @@ void Solver::check_status(bool all) {
 // ---------------------------------------------------------------------------
 // preconditioner and PCG (one right-hand side per call of the internals)
 
-void Solver::trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, double *x, bool t, int nrhs) {
-  HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), plan, t, nrhs,
+void Solver::trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
+                  const DBuf &dinv_off, double *x, bool upper) {
+  HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), plan, upper,
+                              dinv.as<double>(), dinv_off.as<int64_t>(),
                               d_work_i.as<int>(), d_status.as<int>() + 2 * L.nsub + 1));
 }
 
@@ -1167,18 +1197,18 @@ void Solver::apply_local(double *b, double *z) {
   }
   HIPCHK(hipMemcpyAsync(vR2, vR, sizeof(double) * L.sumR, hipMemcpyDeviceToDevice, st));
   timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
-  trsv(plan_rr, d_Lrr, d_descRRvec, vR2, false, 1);
+  trsv(plan_rr, d_Lrr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, false);
   timer.end(st);
   timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
-  trsv(plan_rr, d_Lrr, d_descRRvec, vR2, true, 1);
+  trsv(plan_rr, d_Urr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, true);
   timer.end(st);
   if (L.n_coarse > 0) {
     reduce_copies_kernel<<<nblocks(L.n_coarse), TPB, 0, st>>>(vP, L.sumP, d_c_ptr.as<int>(),
                                                               d_c_copies.as<int64_t>(), nullptr, vc,
                                                               L.n_coarse, L.n_coarse, 1, 1.0, 0.0);
     timer.begin(st, "trsv_coarse", 8.0 * (double)L.n_coarse * L.n_coarse, 2.0 * L.n_coarse * L.n_coarse);
-    trsv(plan_c, d_Lc, d_descCvec, vc, false, 1);
-    trsv(plan_c, d_Lc, d_descCvec, vc, true, 1);
+    trsv(plan_c, d_Lc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, false);
+    trsv(plan_c, d_Uc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, true);
     timer.end(st);
     gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vc, L.n_coarse, d_pcid.as<int>(), vP, L.sumP,
                                                      L.sumP, 1);
