@@ -8,8 +8,26 @@
 
 namespace bddc {
 
+// One face pair (i, j) reduced to the jump space on the shared non-corner
+// dofs (structure only; built from the setup data).
+struct AdaptPair {
+  int f = 0, gi = 0, sub[2] = {0, 0};
+  std::vector<int> pos_s[2], pos_n[2];  // interface positions: shared, not shared
+  std::vector<int> cidx;                // shared-list indices of the non-corner dofs
+  std::vector<double> wi;               // renormalized weight of side i on every c dof
+  std::vector<double> Q;                // rigid traces on s (n_s x nq, orthonormal columns)
+  int nq = 0;
+  double rho = 0;
+  int d = 0;                            // dimension of the jump space
+  std::vector<int> zptr, zrow;          // Z (n_c x d) by columns: rows and values
+  std::vector<double> zval;
+  std::vector<int> face_c;              // c-indices of the face glob dofs (glob order)
+};
+
 struct AdaptState {
   std::vector<std::vector<double>> eigs;  // per face: computed eigenvalues, descending
+  std::vector<AdaptPair> pairs;
+  bool pairs_ready = false;
 };
 
 struct AdaptResult {

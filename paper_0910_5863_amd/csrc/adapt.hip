@@ -109,6 +109,12 @@ __global__ void pair_restrict_kernel(const double *Sss, const int64_t *off_si,
   BJ[off_c[e] + i] = BJfull[off_p[e] + src];
 }
 
+// dst[idx[i]] = val[i]
+__global__ void scatter_values_kernel(const int64_t *idx, const double *val, int64_t n, double *dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[idx[i]] = val[i];
+}
+
 __global__ void transpose_kernel(const double *src, double *dst, const int64_t *off,
                                  const int *n) {
   const int e = blockIdx.y;
@@ -594,19 +600,6 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
 
 namespace {
 
-struct PairHost {
-  int f, gi, sub[2];
-  std::vector<int> pos_s[2], pos_n[2];
-  std::vector<int> cidx;     // indices into the shared list of the non-corner dofs
-  std::vector<double> wi;    // renormalized weight of side i on every c dof
-  std::vector<double> Q;     // rigid traces on s (n_s x nq, orthonormal columns)
-  int nq = 0;
-  double rho = 0;
-  std::vector<double> Z;     // n_c x d, column-major
-  int d = 0;
-  std::vector<int> face_c;   // c-indices of the face glob dofs (glob order)
-};
-
 struct Pool {
   DevAlloc *A;
   std::vector<DBuf> bufs;
@@ -676,103 +669,118 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   st.eigs.assign(nf, {});
   std::vector<char> is_corner(P.n_glob, 0);
   for (int64_t g : P.corner_gdofs) is_corner[g] = 1;
-  std::vector<PairHost> pairs;
-  for (int f = 0; f < nf; ++f) {
-    PairHost ph;
-    ph.f = f;
-    ph.gi = P.face_ids[f];
-    const Glob &gl = P.globs[ph.gi];
-    ph.sub[0] = gl.subs[0];
-    ph.sub[1] = gl.subs[1];
-    const Sub &Si = P.subs[ph.sub[0]], &Sj = P.subs[ph.sub[1]];
-    std::vector<int64_t> gi_(Si.gdof.begin() + Si.nI, Si.gdof.end());
-    std::vector<int64_t> gj_(Sj.gdof.begin() + Sj.nI, Sj.gdof.end());
-    std::vector<int64_t> sh;
-    std::set_intersection(gi_.begin(), gi_.end(), gj_.begin(), gj_.end(), std::back_inserter(sh));
-    const int ns_ = (int)sh.size();
-    for (int a = 0; a < 2; ++a) {
-      const auto &gg = a == 0 ? gi_ : gj_;
-      std::vector<char> in(gg.size(), 0);
-      for (int64_t g : sh) {
-        const int p = (int)(std::lower_bound(gg.begin(), gg.end(), g) - gg.begin());
-        ph.pos_s[a].push_back(p);
-        in[p] = 1;
-      }
-      for (int p = 0; p < (int)gg.size(); ++p)
-        if (!in[p]) ph.pos_n[a].push_back(p);
-    }
-    std::vector<int> c_of(ns_, -1);
-    for (int k = 0; k < ns_; ++k)
-      if (!is_corner[sh[k]]) {
-        c_of[k] = (int)ph.cidx.size();
-        ph.cidx.push_back(k);
-        const double di = Si.diag[Si.nI + ph.pos_s[0][k]], dj = Sj.diag[Sj.nI + ph.pos_s[1][k]];
-        ph.wi.push_back(di / (di + dj));
-      }
-    const int nc = (int)ph.cidx.size();
-    if (nc == 0) continue;
-    // regularization of the parallel sum when both substructures float
-    double rho = 0;
-    for (int k = 0; k < ns_; ++k)
-      rho = std::max({rho, Si.diag[Si.nI + ph.pos_s[0][k]], Sj.diag[Sj.nI + ph.pos_s[1][k]]});
-    ph.rho = rho;
-    if (Si.floating && Sj.floating) {
-      int nq = dpn == 1 ? 1 : 6;
-      ph.Q.assign((size_t)nq * ns_, 0.0);
-      double cen[3] = {0, 0, 0};
-      for (int k = 0; k < ns_; ++k) {
-        const int64_t node = P.glob2full[sh[k]] / dpn;
-        for (int c = 0; c < 3; ++c) cen[c] += P.mesh.xyz[3 * node + c] / ns_;
-      }
-      for (int k = 0; k < ns_; ++k) {
-        const int64_t full = P.glob2full[sh[k]];
-        const int64_t node = full / dpn;
-        const int comp = (int)(full % dpn);
-        if (dpn == 1) {
-          ph.Q[k] = 1.0;
-          continue;
+  // the pair structure depends on the mesh, the partition and the constraints
+  // chosen at setup only (adaptive rows of earlier calls are removed first):
+  // built once, then reused
+  if (!st.pairs_ready) {
+    std::vector<AdaptPair> &pairs = st.pairs;
+    pairs.clear();
+    for (int f = 0; f < nf; ++f) {
+      AdaptPair ph;
+      ph.f = f;
+      ph.gi = P.face_ids[f];
+      const Glob &gl = P.globs[ph.gi];
+      ph.sub[0] = gl.subs[0];
+      ph.sub[1] = gl.subs[1];
+      const Sub &Si = P.subs[ph.sub[0]], &Sj = P.subs[ph.sub[1]];
+      std::vector<int64_t> gi_(Si.gdof.begin() + Si.nI, Si.gdof.end());
+      std::vector<int64_t> gj_(Sj.gdof.begin() + Sj.nI, Sj.gdof.end());
+      std::vector<int64_t> sh;
+      std::set_intersection(gi_.begin(), gi_.end(), gj_.begin(), gj_.end(), std::back_inserter(sh));
+      const int ns_ = (int)sh.size();
+      for (int a = 0; a < 2; ++a) {
+        const auto &gg = a == 0 ? gi_ : gj_;
+        std::vector<char> in(gg.size(), 0);
+        for (int64_t g : sh) {
+          const int p = (int)(std::lower_bound(gg.begin(), gg.end(), g) - gg.begin());
+          ph.pos_s[a].push_back(p);
+          in[p] = 1;
         }
-        const double x = P.mesh.xyz[3 * node] - cen[0], y = P.mesh.xyz[3 * node + 1] - cen[1],
-                     z = P.mesh.xyz[3 * node + 2] - cen[2];
-        ph.Q[(size_t)comp * ns_ + k] = 1.0;
-        const double rot[3][3] = {{0, -z, y}, {z, 0, -x}, {-y, x, 0}};
-        for (int r = 0; r < 3; ++r) ph.Q[(size_t)(3 + r) * ns_ + k] = rot[r][comp];
+        for (int p = 0; p < (int)gg.size(); ++p)
+          if (!in[p]) ph.pos_n[a].push_back(p);
       }
-      orthonormalize(ph.Q, ns_, nq);
-      ph.nq = nq;
+      std::vector<int> c_of(ns_, -1);
+      for (int k = 0; k < ns_; ++k)
+        if (!is_corner[sh[k]]) {
+          c_of[k] = (int)ph.cidx.size();
+          ph.cidx.push_back(k);
+          const double di = Si.diag[Si.nI + ph.pos_s[0][k]], dj = Sj.diag[Sj.nI + ph.pos_s[1][k]];
+          ph.wi.push_back(di / (di + dj));
+        }
+      const int nc = (int)ph.cidx.size();
+      if (nc == 0) continue;
+      // regularization of the parallel sum when both substructures float
+      double rho = 0;
+      for (int k = 0; k < ns_; ++k)
+        rho = std::max({rho, Si.diag[Si.nI + ph.pos_s[0][k]], Sj.diag[Sj.nI + ph.pos_s[1][k]]});
+      ph.rho = rho;
+      if (Si.floating && Sj.floating) {
+        int nq = dpn == 1 ? 1 : 6;
+        ph.Q.assign((size_t)nq * ns_, 0.0);
+        double cen[3] = {0, 0, 0};
+        for (int k = 0; k < ns_; ++k) {
+          const int64_t node = P.glob2full[sh[k]] / dpn;
+          for (int c = 0; c < 3; ++c) cen[c] += P.mesh.xyz[3 * node + c] / ns_;
+        }
+        for (int k = 0; k < ns_; ++k) {
+          const int64_t full = P.glob2full[sh[k]];
+          const int64_t node = full / dpn;
+          const int comp = (int)(full % dpn);
+          if (dpn == 1) {
+            ph.Q[k] = 1.0;
+            continue;
+          }
+          const double x = P.mesh.xyz[3 * node] - cen[0], y = P.mesh.xyz[3 * node + 1] - cen[1],
+                       z = P.mesh.xyz[3 * node + 2] - cen[2];
+          ph.Q[(size_t)comp * ns_ + k] = 1.0;
+          const double rot[3][3] = {{0, -z, y}, {z, 0, -x}, {-y, x, 0}};
+          for (int r = 0; r < 3; ++r) ph.Q[(size_t)(3 + r) * ns_ + k] = rot[r][comp];
+        }
+        orthonormalize(ph.Q, ns_, nq);
+        ph.nq = nq;
+      }
+      // basis of the J space from the change of variables of the shared globs
+      std::vector<std::vector<double>> cols;
+      for (size_t g2 = 0; g2 < P.globs.size(); ++g2) {
+        const Glob &G = P.globs[g2];
+        if (std::find(G.subs.begin(), G.subs.end(), ph.sub[0]) == G.subs.end() ||
+            std::find(G.subs.begin(), G.subs.end(), ph.sub[1]) == G.subs.end())
+          continue;
+        const GlobCov &cv = P.cov[g2];
+        std::vector<int> crow(G.dofs.size());
+        for (size_t t = 0; t < G.dofs.size(); ++t) {
+          const int k = (int)(std::lower_bound(sh.begin(), sh.end(), G.dofs[t]) - sh.begin());
+          crow[t] = c_of[k];
+        }
+        std::vector<char> expl(G.dofs.size(), 0);
+        for (int k = 0; k < cv.m; ++k) expl[cv.perm[k]] = 1;
+        for (size_t t = 0; t < G.dofs.size(); ++t) {
+          if (expl[t]) continue;
+          std::vector<double> col(nc, 0.0);
+          col[crow[t]] = 1.0;
+          for (int k = 0; k < cv.m; ++k) col[crow[cv.perm[k]]] += cv.trow[(size_t)k * cv.n + t];
+          cols.push_back(std::move(col));
+        }
+        if ((int)g2 == ph.gi)
+          for (size_t t = 0; t < G.dofs.size(); ++t) ph.face_c.push_back(crow[t]);
+      }
+      ph.d = (int)cols.size();
+      if (ph.d == 0) continue;
+      // Z is sparse: one unit entry per column plus the explicit averages' rows
+      ph.zptr.assign(1, 0);
+      for (int c = 0; c < ph.d; ++c) {
+        for (int r = 0; r < nc; ++r)
+          if (cols[c][r] != 0.0) {
+            ph.zrow.push_back(r);
+            ph.zval.push_back(cols[c][r]);
+          }
+        ph.zptr.push_back((int)ph.zrow.size());
+      }
+      pairs.push_back(std::move(ph));
     }
-    // basis of the J space from the change of variables of the shared globs
-    std::vector<std::vector<double>> cols;
-    for (size_t g2 = 0; g2 < P.globs.size(); ++g2) {
-      const Glob &G = P.globs[g2];
-      if (std::find(G.subs.begin(), G.subs.end(), ph.sub[0]) == G.subs.end() ||
-          std::find(G.subs.begin(), G.subs.end(), ph.sub[1]) == G.subs.end())
-        continue;
-      const GlobCov &cv = P.cov[g2];
-      std::vector<int> crow(G.dofs.size());
-      for (size_t t = 0; t < G.dofs.size(); ++t) {
-        const int k = (int)(std::lower_bound(sh.begin(), sh.end(), G.dofs[t]) - sh.begin());
-        crow[t] = c_of[k];
-      }
-      std::vector<char> expl(G.dofs.size(), 0);
-      for (int k = 0; k < cv.m; ++k) expl[cv.perm[k]] = 1;
-      for (size_t t = 0; t < G.dofs.size(); ++t) {
-        if (expl[t]) continue;
-        std::vector<double> col(nc, 0.0);
-        col[crow[t]] = 1.0;
-        for (int k = 0; k < cv.m; ++k) col[crow[cv.perm[k]]] += cv.trow[(size_t)k * cv.n + t];
-        cols.push_back(std::move(col));
-      }
-      if ((int)g2 == ph.gi)
-        for (size_t t = 0; t < G.dofs.size(); ++t) ph.face_c.push_back(crow[t]);
-    }
-    ph.d = (int)cols.size();
-    if (ph.d == 0) continue;
-    ph.Z.resize((size_t)nc * ph.d);
-    for (int c = 0; c < ph.d; ++c)
-      std::copy(cols[c].begin(), cols[c].end(), ph.Z.begin() + (size_t)c * nc);
-    pairs.push_back(std::move(ph));
+    st.pairs_ready = true;
   }
+  const std::vector<AdaptPair> &pairs = st.pairs;
   const int np = (int)pairs.size();
   res.n_pairs = np;
   log("pair index data (host)");
@@ -860,12 +868,13 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   std::vector<int64_t> off_i(np), off_j(np), off_p(np), q_off(np), off_c(np), c_off(np), off_z(np),
       off_cz(np), off_dd(np);
   std::vector<int> nsp(np), nqv(np), ncv(np), dv(np);
-  std::vector<double> rho(np), Qall, wall, Zall;
+  std::vector<double> rho(np), Qall, wall, zval;
+  std::vector<int64_t> zdst;
   std::vector<int> call;
   int64_t tp = 0, tc = 0, tz = 0, tdd = 0, tcz = 0;
   int max_c = 0, max_d = 0;
   for (int p = 0; p < np; ++p) {
-    const PairHost &ph = pairs[p];
+    const AdaptPair &ph = pairs[p];
     off_i[p] = off_sh[2 * p];
     off_j[p] = off_sh[2 * p + 1];
     nsp[p] = nsv[2 * p];
@@ -882,8 +891,13 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
     wall.insert(wall.end(), ph.wi.begin(), ph.wi.end());
     off_c[p] = tc;
     tc += (int64_t)ncv[p] * ncv[p];
-    off_z[p] = (int64_t)Zall.size();
-    Zall.insert(Zall.end(), ph.Z.begin(), ph.Z.end());
+    off_z[p] = tz;
+    for (int c = 0; c < ph.d; ++c)
+      for (int k = ph.zptr[c]; k < ph.zptr[c + 1]; ++k) {
+        zdst.push_back(tz + ph.zrow[k] + (int64_t)c * ncv[p]);
+        zval.push_back(ph.zval[k]);
+      }
+    tz += (int64_t)ncv[p] * dv[p];
     off_cz[p] = tcz;
     tcz += (int64_t)ncv[p] * dv[p];
     off_dd[p] = tdd;
@@ -933,7 +947,15 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
       Sh, d_off_ss_i, d_off_ss_j, BJf, d_off_p, d_nsp, d_call, d_c_off, d_nc, d_w, Mc, BJc, d_off_c);
   HIPCHK(hipGetLastError());
   // My = Z^T M Z, By = Z^T BJ Z
-  double *Zd = pool.up(stream, Zall), *T1 = pool.zeros(stream, tcz), *My = pool.zeros(stream, tdd),
+  double *Zd = pool.zeros(stream, tz);
+  {
+    const int64_t *d_zdst = pool.up(stream, zdst);
+    const double *d_zval = pool.up(stream, zval);
+    scatter_values_kernel<<<nblocks((int64_t)zdst.size()), TPB, 0, stream>>>(d_zdst, d_zval,
+                                                                         (int64_t)zdst.size(), Zd);
+    HIPCHK(hipGetLastError());
+  }
+  double *T1 = pool.zeros(stream, tcz), *My = pool.zeros(stream, tdd),
          *By = pool.zeros(stream, tdd), *Cp = pool.zeros(stream, tdd);
   std::vector<GemmDesc> g1(np), g2(np);
   for (int p = 0; p < np; ++p) {
@@ -1127,7 +1149,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   log("eigenvectors to jump space");
   // ---- host: face rows
   for (int p = 0; p < np; ++p) {
-    const PairHost &ph = pairs[p];
+    const AdaptPair &ph = pairs[p];
     const int nc = ncv[p];
     std::vector<double> ev = evs[p];
     std::sort(ev.begin(), ev.end(), [](double x, double y) { return x > y; });

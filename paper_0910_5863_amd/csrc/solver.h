@@ -108,6 +108,7 @@ class Solver {
   void factor_schur();
   void check_status(bool all);
   bool schur_ready = false;
+  bool struct_ready = false;  // mesh / partition part of the layout is current
   void apply_global(const double *r, double *z);
   PcgResult pcg(const double *f, double *u, double rtol, int maxit);
   void free_all();
@@ -134,6 +135,9 @@ class Solver {
             const DBuf &dinv_off, double *x, bool upper);
   void release(DBuf &b);
   std::vector<DBuf *> all_buffers();
+  std::vector<DBuf *> struct_buffers();
+  std::vector<DBuf *> cons_buffers();
+  void build_structure(const Problem &P, hipStream_t st);
 
   int64_t n_rows = 0, nnz = 0;
   double bytes_S = 0, bytes_Lrr_tri = 0;

@@ -545,20 +545,30 @@ Solver::~Solver() {
   mf.release(alloc);
 }
 
-std::vector<DBuf *> Solver::all_buffers() {
-  return {&d_row_sub, &d_row_loc, &d_rowptr, &d_col, &d_val, &d_nI, &d_nG, &d_nr, &d_np,
-          &d_offI, &d_offG, &d_offR, &d_offP, &d_offGG, &d_offRR, &d_offRP,
-          &d_offPP, &d_S, &d_W, &d_Lrr, &d_Urr, &d_Phi, &d_Spi, &d_Lc, &d_Uc, &d_descRRT,
-          &d_dinv_rr, &d_dinv_rr_off, &d_dinv_c, &d_dinv_c_off,
-          &d_descRR, &d_descC, &d_spi_desc, &d_descGG, &d_gx, &d_gx_ptr, &d_trow,
-          &d_pos, &d_ridx, &d_ridx_off, &d_pidx, &d_pidx_off, &d_rabs, &d_pabs, &d_pcid,
-          &d_sub_cids, &d_c_ptr, &d_c_sub, &d_c_loc, &d_c_copies, &d_ifc_gamma, &d_ifc_delta,
-          &d_gamma_ptr, &d_gamma_copies, &d_gamma_gdof, &d_int_gdof, &d_ifc_gdof,
-          &d_trsv_rr_fwd, &d_trsv_rr_bwd, &d_trsv_rr_off,
-          &d_trsv_c_fwd, &d_trsv_c_bwd, &d_trsv_c_off, &d_work_i, &d_status,
-          &d_vG, &d_vG2, &d_vR, &d_vR2, &d_vP, &d_vI, &d_vI2, &d_vc, &d_gam_r, &d_gam_z,
-          &d_gam_p, &d_gam_q, &d_gam_x, &d_sc, &d_part, &d_alphas, &d_betas, &d_descRRvec,
+// buffers that depend only on the mesh and partition (kept when the
+// constraints change) and the ones that depend on the constraints
+std::vector<DBuf *> Solver::struct_buffers() {
+  return {&d_row_sub, &d_row_loc, &d_rowptr, &d_col, &d_val, &d_nI, &d_nG, &d_offI, &d_offG,
+          &d_offGG, &d_S, &d_W, &d_descGG, &d_ifc_gamma, &d_ifc_delta, &d_gamma_ptr,
+          &d_gamma_copies, &d_gamma_gdof, &d_int_gdof, &d_ifc_gdof, &d_vG, &d_vG2, &d_vI, &d_vI2,
+          &d_gam_r, &d_gam_z, &d_gam_p, &d_gam_q, &d_gam_x, &d_sc, &d_part, &d_alphas, &d_betas};
+}
+
+std::vector<DBuf *> Solver::cons_buffers() {
+  return {&d_nr, &d_np, &d_offR, &d_offP, &d_offRR, &d_offRP, &d_offPP, &d_Lrr, &d_Urr, &d_Phi,
+          &d_Spi, &d_Lc, &d_Uc, &d_descRRT, &d_dinv_rr, &d_dinv_rr_off, &d_dinv_c, &d_dinv_c_off,
+          &d_descRR, &d_descC, &d_spi_desc, &d_gx, &d_gx_ptr, &d_trow, &d_pos, &d_wmat,
+          &d_gk_glob, &d_gk_k, &d_scr, &d_ridx, &d_ridx_off, &d_pidx, &d_pidx_off, &d_rabs,
+          &d_pabs, &d_pcid, &d_sub_cids, &d_c_ptr, &d_c_sub, &d_c_loc, &d_c_copies,
+          &d_trsv_rr_fwd, &d_trsv_rr_bwd, &d_trsv_rr_off, &d_trsv_c_fwd, &d_trsv_c_bwd,
+          &d_trsv_c_off, &d_work_i, &d_status, &d_vR, &d_vR2, &d_vP, &d_vc, &d_descRRvec,
           &d_descCvec};
+}
+
+std::vector<DBuf *> Solver::all_buffers() {
+  std::vector<DBuf *> a = struct_buffers(), b = cons_buffers();
+  a.insert(a.end(), b.begin(), b.end());
+  return a;
 }
 
 // Host analysis after bddc_setup / adapt: layout, index maps, uploads of the
@@ -567,20 +577,30 @@ std::vector<DBuf *> Solver::all_buffers() {
 // elimination and -- when current -- the Schur complements: neither depends
 // on the constraints.
 void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
-  DBuf kS;
-  const bool keep = keep_interior && schur_ready;
-  if (keep) std::swap(kS, d_S);
-  free_all();
-  if (!keep_interior) mf.release(alloc);
+  const bool keep_struct = keep_interior && struct_ready;
+  for (DBuf *b : cons_buffers()) release(*b);
+  if (!keep_struct) {
+    for (DBuf *b : struct_buffers()) release(*b);
+    mf.release(alloc);
+    struct_ready = false;
+    schur_ready = false;
+  }
   stream = st;
   const int ns = (int)P.subs.size();
-  L = Layout();
-  L.nsub = ns;
-  L.n_glob = P.n_glob;
-  L.nI.resize(ns);
-  L.nG.resize(ns);
-  L.nr.resize(ns);
-  L.np.resize(ns);
+  if (!keep_struct) {
+    L = Layout();
+    L.nsub = ns;
+    L.n_glob = P.n_glob;
+    L.nI.resize(ns);
+    L.nG.resize(ns);
+    for (int s = 0; s < ns; ++s) {
+      L.nI[s] = P.subs[s].nI;
+      L.nG[s] = P.subs[s].nG;
+    }
+  }
+  L.nr.assign(ns, 0);
+  L.np.assign(ns, 0);
+  L.max_nr = L.max_np = 0;
   // coarse numbering: corner dofs first (ascending), then explicit variables
   // glob by glob
   std::vector<int64_t> corner_cid(P.n_glob, -1);
@@ -610,8 +630,6 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
     for (auto &x : pi) isp[x.first] = 1;
     for (int t = 0; t < S.nG; ++t)
       if (!isp[t]) rpos[s].push_back(t);
-    L.nI[s] = S.nI;
-    L.nG[s] = S.nG;
     L.np[s] = (int)pi.size();
     L.nr[s] = (int)rpos[s].size();
   }
@@ -625,92 +643,23 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
     }
     return o;
   };
-  L.sumI = offsets(L.nI, {}, L.offI);
-  L.sumG = offsets(L.nG, {}, L.offG);
   L.sumR = offsets(L.nr, {}, L.offR);
   L.sumP = offsets(L.np, {}, L.offP);
-  L.sGG = offsets(L.nG, L.nG, L.offGG);
   L.sRR = offsets(L.nr, L.nr, L.offRR);
   L.sRP = offsets(L.nr, L.np, L.offRP);
   L.sPP = offsets(L.np, L.np, L.offPP);
   for (int s = 0; s < ns; ++s) {
-    L.max_nI = std::max(L.max_nI, L.nI[s]);
-    L.max_nG = std::max(L.max_nG, L.nG[s]);
     L.max_nr = std::max(L.max_nr, L.nr[s]);
     L.max_np = std::max(L.max_np, L.np[s]);
   }
-  // CSR stack
-  std::vector<int> row_sub, row_loc, col;
-  std::vector<int64_t> rowptr(1, 0);
-  std::vector<double> val;
-  for (int s = 0; s < ns; ++s) {
-    const Csr &A = P.subs[s].A;
-    for (int r = 0; r < A.n; ++r) {
-      row_sub.push_back(s);
-      row_loc.push_back(r);
-      rowptr.push_back(rowptr.back() + (A.ptr[r + 1] - A.ptr[r]));
-    }
-    col.insert(col.end(), A.col.begin(), A.col.end());
-    val.insert(val.end(), A.val.begin(), A.val.end());
-  }
-  n_rows = (int64_t)row_sub.size();
-  nnz = (int64_t)val.size();
-  d_row_sub = upload(alloc, st, row_sub);
-  d_row_loc = upload(alloc, st, row_loc);
-  d_rowptr = upload(alloc, st, rowptr);
-  d_col = upload(alloc, st, col);
-  d_val = upload(alloc, st, val);
-  d_nI = upload(alloc, st, L.nI);
-  d_nG = upload(alloc, st, L.nG);
   d_nr = upload(alloc, st, L.nr);
   d_np = upload(alloc, st, L.np);
-  d_offI = upload(alloc, st, L.offI);
-  d_offG = upload(alloc, st, L.offG);
   d_offR = upload(alloc, st, L.offR);
   d_offP = upload(alloc, st, L.offP);
-  d_offGG = upload(alloc, st, L.offGG);
   d_offRR = upload(alloc, st, L.offRR);
   d_offRP = upload(alloc, st, L.offRP);
   d_offPP = upload(alloc, st, L.offPP);
-  // interface maps: global interface dof numbering gamma (ascending global)
-  std::vector<int64_t> gam_of(P.n_glob, -1);
-  std::vector<int> mult(P.n_glob, 0);
-  for (int s = 0; s < ns; ++s)
-    for (int t = 0; t < L.nG[s]; ++t) mult[P.subs[s].gdof[L.nI[s] + t]]++;
-  std::vector<int64_t> gamma_gdof;
-  for (int64_t g = 0; g < P.n_glob; ++g)
-    if (mult[g] > 0) {
-      gam_of[g] = (int64_t)gamma_gdof.size();
-      gamma_gdof.push_back(g);
-    }
-  L.n_gamma = (int64_t)gamma_gdof.size();
-  std::vector<int64_t> ifc_gamma(L.sumG), ifc_gdof(L.sumG), int_gdof(L.sumI);
-  std::vector<double> ifc_delta(L.sumG);
-  std::vector<int> gptr(L.n_gamma + 1, 0);
-  for (int s = 0; s < ns; ++s)
-    for (int t = 0; t < L.nG[s]; ++t) {
-      const int64_t g = P.subs[s].gdof[L.nI[s] + t];
-      ifc_gamma[L.offG[s] + t] = gam_of[g];
-      ifc_gdof[L.offG[s] + t] = g;
-      ifc_delta[L.offG[s] + t] = P.subs[s].delta[t];
-      gptr[gam_of[g] + 1]++;
-    }
-  for (int64_t k = 0; k < L.n_gamma; ++k) gptr[k + 1] += gptr[k];
-  std::vector<int64_t> gcopies(gptr[L.n_gamma]);
-  {
-    std::vector<int> fill(gptr.begin(), gptr.end() - 1);
-    for (int s = 0; s < ns; ++s)  // substructures ascending: fixed summation order
-      for (int t = 0; t < L.nG[s]; ++t) gcopies[fill[ifc_gamma[L.offG[s] + t]]++] = L.offG[s] + t;
-  }
-  for (int s = 0; s < ns; ++s)
-    for (int t = 0; t < L.nI[s]; ++t) int_gdof[L.offI[s] + t] = P.subs[s].gdof[t];
-  d_ifc_gamma = upload(alloc, st, ifc_gamma);
-  d_ifc_gdof = upload(alloc, st, ifc_gdof);
-  d_ifc_delta = upload(alloc, st, ifc_delta);
-  d_gamma_ptr = upload(alloc, st, gptr);
-  d_gamma_copies = upload(alloc, st, gcopies);
-  d_gamma_gdof = upload(alloc, st, gamma_gdof);
-  d_int_gdof = upload(alloc, st, int_gdof);
+  if (!keep_struct) build_structure(P, st);
   // transforms
   std::vector<GlobXf> gx;
   std::vector<int> gx_ptr(ns + 1, 0), gk_glob, gk_k;
@@ -804,20 +753,17 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_c_loc = upload(alloc, st, cloc);
   d_c_copies = upload(alloc, st, ccopies);
   // descriptors
-  std::vector<MatDesc> dRR(ns), dGG(ns), dRRv(ns), dRRT(ns);
+  std::vector<MatDesc> dRR(ns), dRRv(ns), dRRT(ns);
   std::vector<GemmDesc> spi(ns);
   for (int s = 0; s < ns; ++s) {
     dRR[s] = MatDesc{L.offRR[s], L.offRP[s], L.nr[s], L.np[s], std::max(1, L.nr[s]), std::max(1, L.nr[s])};
-    dGG[s] = MatDesc{L.offGG[s], 0, L.nG[s], 0, std::max(1, L.nG[s]), 1};
     dRRv[s] = MatDesc{L.offRR[s], L.offR[s], L.nr[s], 1, std::max(1, L.nr[s]), (int)L.sumR};
     dRRT[s] = MatDesc{L.offRR[s], L.offRR[s], L.nr[s], 0, std::max(1, L.nr[s]), std::max(1, L.nr[s])};
     spi[s] = GemmDesc{L.offRP[s], L.offRP[s], L.offPP[s], L.np[s], L.np[s], L.nr[s],
                       std::max(1, L.nr[s]), std::max(1, L.nr[s]), std::max(1, L.np[s])};
   }
   h_descRR = dRR;
-  h_descGG = dGG;
   d_descRR = upload(alloc, st, dRR);
-  d_descGG = upload(alloc, st, dGG);
   d_descRRvec = upload(alloc, st, dRRv);
   d_descRRT = upload(alloc, st, dRRT);
   d_spi_desc = upload(alloc, st, spi);
@@ -853,16 +799,6 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_work_i = alloc0(alloc, st, sizeof(int) * (size_t)(4 + std::max(w1, w3)));
   d_status = alloc0(alloc, st, sizeof(int) * (size_t)(2 * ns + 2));
   // matrices
-  const bool kept = keep && kS.bytes == std::max<size_t>(sizeof(double) * (size_t)L.sGG, 8);
-  if (kept) {
-    d_S = kS;
-  } else {
-    release(kS);
-    d_S = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
-  }
-  // interior elimination: structure from the mesh and partition only
-  if (!mf.ready) mf.setup(P, L.offI, alloc, st);
-  d_W = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
   d_Lrr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
   d_Urr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
   d_Phi = alloc0(alloc, st, sizeof(double) * (size_t)L.sRP);
@@ -884,14 +820,119 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   }
   // work vectors (nrhs up to kMaxRhs)
   const size_t R = kMaxRhs;
-  d_vG = alloc0(alloc, st, sizeof(double) * L.sumG * R);
-  d_vG2 = alloc0(alloc, st, sizeof(double) * L.sumG * R);
   d_vR = alloc0(alloc, st, sizeof(double) * L.sumR * R);
   d_vR2 = alloc0(alloc, st, sizeof(double) * L.sumR * R);
   d_vP = alloc0(alloc, st, sizeof(double) * L.sumP * R);
+  d_vc = alloc0(alloc, st, sizeof(double) * nc * R);
+  bytes_S = 0;
+  bytes_Lrr_tri = 0;
+  for (int s = 0; s < ns; ++s) {
+    bytes_S += 8.0 * (double)L.nG[s] * L.nG[s];
+    bytes_Lrr_tri += 8.0 * 0.5 * (double)L.nr[s] * (L.nr[s] + 1);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  factored = false;
+  struct_ready = true;
+}
+
+// The part of the layout that depends only on the mesh and partition: the
+// stacked substructure matrices, interface numbering and maps, the interface
+// Schur complement pools, work vectors and the interior elimination.
+void Solver::build_structure(const Problem &P, hipStream_t st) {
+  const int ns = L.nsub;
+  auto offsets = [&](const std::vector<int> &a, std::vector<int64_t> &off, bool square) {
+    off.resize(ns);
+    int64_t o = 0;
+    for (int s = 0; s < ns; ++s) {
+      off[s] = o;
+      o += (int64_t)a[s] * (square ? a[s] : 1);
+    }
+    return o;
+  };
+  L.sumI = offsets(L.nI, L.offI, false);
+  L.sumG = offsets(L.nG, L.offG, false);
+  L.sGG = offsets(L.nG, L.offGG, true);
+  L.max_nI = L.max_nG = 0;
+  for (int s = 0; s < ns; ++s) {
+    L.max_nI = std::max(L.max_nI, L.nI[s]);
+    L.max_nG = std::max(L.max_nG, L.nG[s]);
+  }
+  // CSR stack
+  std::vector<int> row_sub, row_loc, col;
+  std::vector<int64_t> rowptr(1, 0);
+  std::vector<double> val;
+  for (int s = 0; s < ns; ++s) {
+    const Csr &A = P.subs[s].A;
+    for (int r = 0; r < A.n; ++r) {
+      row_sub.push_back(s);
+      row_loc.push_back(r);
+      rowptr.push_back(rowptr.back() + (A.ptr[r + 1] - A.ptr[r]));
+    }
+    col.insert(col.end(), A.col.begin(), A.col.end());
+    val.insert(val.end(), A.val.begin(), A.val.end());
+  }
+  n_rows = (int64_t)row_sub.size();
+  nnz = (int64_t)val.size();
+  d_row_sub = upload(alloc, st, row_sub);
+  d_row_loc = upload(alloc, st, row_loc);
+  d_rowptr = upload(alloc, st, rowptr);
+  d_col = upload(alloc, st, col);
+  d_val = upload(alloc, st, val);
+  d_nI = upload(alloc, st, L.nI);
+  d_nG = upload(alloc, st, L.nG);
+  d_offI = upload(alloc, st, L.offI);
+  d_offG = upload(alloc, st, L.offG);
+  d_offGG = upload(alloc, st, L.offGG);
+  // interface maps: global interface dof numbering gamma (ascending global)
+  std::vector<int64_t> gam_of(P.n_glob, -1);
+  std::vector<int> mult(P.n_glob, 0);
+  for (int s = 0; s < ns; ++s)
+    for (int t = 0; t < L.nG[s]; ++t) mult[P.subs[s].gdof[L.nI[s] + t]]++;
+  std::vector<int64_t> gamma_gdof;
+  for (int64_t g = 0; g < P.n_glob; ++g)
+    if (mult[g] > 0) {
+      gam_of[g] = (int64_t)gamma_gdof.size();
+      gamma_gdof.push_back(g);
+    }
+  L.n_gamma = (int64_t)gamma_gdof.size();
+  std::vector<int64_t> ifc_gamma(L.sumG), ifc_gdof(L.sumG), int_gdof(L.sumI);
+  std::vector<double> ifc_delta(L.sumG);
+  std::vector<int> gptr(L.n_gamma + 1, 0);
+  for (int s = 0; s < ns; ++s)
+    for (int t = 0; t < L.nG[s]; ++t) {
+      const int64_t g = P.subs[s].gdof[L.nI[s] + t];
+      ifc_gamma[L.offG[s] + t] = gam_of[g];
+      ifc_gdof[L.offG[s] + t] = g;
+      ifc_delta[L.offG[s] + t] = P.subs[s].delta[t];
+      gptr[gam_of[g] + 1]++;
+    }
+  for (int64_t k = 0; k < L.n_gamma; ++k) gptr[k + 1] += gptr[k];
+  std::vector<int64_t> gcopies(gptr[L.n_gamma]);
+  {
+    std::vector<int> fill(gptr.begin(), gptr.end() - 1);
+    for (int s = 0; s < ns; ++s)  // substructures ascending: fixed summation order
+      for (int t = 0; t < L.nG[s]; ++t) gcopies[fill[ifc_gamma[L.offG[s] + t]]++] = L.offG[s] + t;
+  }
+  for (int s = 0; s < ns; ++s)
+    for (int t = 0; t < L.nI[s]; ++t) int_gdof[L.offI[s] + t] = P.subs[s].gdof[t];
+  d_ifc_gamma = upload(alloc, st, ifc_gamma);
+  d_ifc_gdof = upload(alloc, st, ifc_gdof);
+  d_ifc_delta = upload(alloc, st, ifc_delta);
+  d_gamma_ptr = upload(alloc, st, gptr);
+  d_gamma_copies = upload(alloc, st, gcopies);
+  d_gamma_gdof = upload(alloc, st, gamma_gdof);
+  d_int_gdof = upload(alloc, st, int_gdof);
+  std::vector<MatDesc> dGG(ns);
+  for (int s = 0; s < ns; ++s) dGG[s] = MatDesc{L.offGG[s], 0, L.nG[s], 0, std::max(1, L.nG[s]), 1};
+  h_descGG = dGG;
+  d_descGG = upload(alloc, st, dGG);
+  d_S = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
+  d_W = alloc0(alloc, st, sizeof(double) * (size_t)L.sGG);
+  const size_t R = kMaxRhs;
+  d_vG = alloc0(alloc, st, sizeof(double) * L.sumG * R);
+  d_vG2 = alloc0(alloc, st, sizeof(double) * L.sumG * R);
   d_vI = alloc0(alloc, st, sizeof(double) * L.sumI * R);
   d_vI2 = alloc0(alloc, st, sizeof(double) * L.sumI * R);
-  d_vc = alloc0(alloc, st, sizeof(double) * nc * R);
   d_gam_r = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
   d_gam_z = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
   d_gam_p = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
@@ -901,15 +942,8 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_part = alloc0(alloc, st, sizeof(double) * 1024);
   d_alphas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
   d_betas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
-  bytes_S = 0;
-  bytes_Lrr_tri = 0;
-  for (int s = 0; s < ns; ++s) {
-    bytes_S += 8.0 * (double)L.nG[s] * L.nG[s];
-    bytes_Lrr_tri += 8.0 * 0.5 * (double)L.nr[s] * (L.nr[s] + 1);
-  }
-  HIPCHK(hipStreamSynchronize(st));
-  factored = false;
-  schur_ready = kept;
+  // interior elimination
+  mf.setup(P, L.offI, alloc, st);
 }
 
 // Dirichlet factors of A_II (multifrontal) and Schur complements S_i
