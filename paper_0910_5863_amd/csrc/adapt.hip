@@ -788,6 +788,13 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
 
   // ---- device stage 1: Schur complements of S_i onto each pair's shared dofs
   Pool pool{&S.alloc};
+  // inverses of the diagonal blocks of a batch of factors (written by potrf)
+  auto dinv_for = [&](const std::vector<MatDesc> &md, double *&dv, int64_t *&doff) {
+    std::vector<int64_t> off;
+    const int64_t t = dinv_layout(md.data(), (int)md.size(), off);
+    dv = pool.zeros(stream, t);
+    doff = pool.up(stream, off);
+  };
   const int nside = 2 * np;
   std::vector<int64_t> src_off(nside), off_nn(nside), off_ns(nside), off_sh(nside), off_ss(nside);
   std::vector<int> lds(nside), nn(nside), nsv(nside);
@@ -844,7 +851,10 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   MatDesc *d_mdn = pool.up(stream, mdn);
   GemmDesc *d_gsh = pool.up(stream, gsh);
   int *d_stat = pool.up(stream, std::vector<int>(3 * np + 2 * nside + 4, 0));
-  HIPCHK(DenseOps<double>::potrf(stream, Snn, d_mdn, mdn.data(), nside, d_stat));
+  double *dv_n;
+  int64_t *do_n;
+  dinv_for(mdn, dv_n, do_n);
+  HIPCHK(DenseOps<double>::potrf(stream, Snn, d_mdn, mdn.data(), nside, d_stat, dv_n, do_n));
   auto check = [&](int first, int count, const char *what) {
     std::vector<int> hs(count);
     HIPCHK(hipMemcpyAsync(hs.data(), d_stat + first, sizeof(int) * count, hipMemcpyDeviceToHost, stream));
@@ -858,7 +868,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
                         "); Assumption 2 may not hold");
   };
   check(0, nside, "non-shared interface blocks");
-  HIPCHK(DenseOps<double>::trsm(stream, Snn, Sns, d_mdn, mdn.data(), nside, false));
+  HIPCHK(DenseOps<double>::trsm(stream, Snn, Sns, d_mdn, mdn.data(), nside, false, dv_n, do_n));
   // Sh gets the Schur complement; Sns and Sh live in different pools
   HIPCHK(DenseOps<double>::gemm(stream, Sns, Sns, Sh, d_gsh, nside, max_ns, max_ns, true, false,
                                 -1.0, 1.0, false, gsh.data()));
@@ -927,10 +937,13 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   MatDesc *d_mds = pool.up(stream, mds);
   GemmDesc *d_gbj = pool.up(stream, gbj);
   int *stat2 = d_stat + nside;
-  HIPCHK(DenseOps<double>::potrf(stream, Ssum, d_mds, mds.data(), np, stat2));
+  double *dv_s;
+  int64_t *do_s;
+  dinv_for(mds, dv_s, do_s);
+  HIPCHK(DenseOps<double>::potrf(stream, Ssum, d_mds, mds.data(), np, stat2, dv_s, do_s));
   check(nside, np, "sum of the Schur complements");
-  HIPCHK(DenseOps<double>::trsm(stream, Ssum, Xb, d_mds, mds.data(), np, false));
-  HIPCHK(DenseOps<double>::trsm(stream, Ssum, Xb, d_mds, mds.data(), np, true));
+  HIPCHK(DenseOps<double>::trsm(stream, Ssum, Xb, d_mds, mds.data(), np, false, dv_s, do_s));
+  HIPCHK(DenseOps<double>::trsm(stream, Ssum, Xb, d_mds, mds.data(), np, true, dv_s, do_s));
   // BJ = Sh_i (Sh_i + Sh_j)^+ Sh_j, the product form of the parallel sum (no
   // cancellation between the two large terms of Sh_i - Sh_i (..)^+ Sh_i when
   // the coefficients of i and j differ by orders of magnitude)
@@ -977,13 +990,16 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   int64_t *d_off_dd = pool.up(stream, off_dd);
   int *d_dv = pool.up(stream, dv);
   int *stat3 = stat2 + np;
-  HIPCHK(DenseOps<double>::potrf(stream, By, d_mdd, mdd.data(), np, stat3));
+  double *dv_y;
+  int64_t *do_y;
+  dinv_for(mdd, dv_y, do_y);
+  HIPCHK(DenseOps<double>::potrf(stream, By, d_mdd, mdd.data(), np, stat3, dv_y, do_y));
   check(nside + np, np, "jump-space denominator");
   // My <- L^-1 My ; Cp <- My^T ; Cp <- L^-1 Cp   (My's pool is the B operand)
-  HIPCHK(DenseOps<double>::trsm(stream, By, My, d_mdd, mdd.data(), np, false));
+  HIPCHK(DenseOps<double>::trsm(stream, By, My, d_mdd, mdd.data(), np, false, dv_y, do_y));
   transpose_kernel<<<dim3(nblocks((int64_t)max_d * max_d), np), TPB, 0, stream>>>(My, Cp, d_off_dd, d_dv);
   HIPCHK(hipGetLastError());
-  HIPCHK(DenseOps<double>::trsm(stream, By, Cp, d_mdd, mdd.data(), np, false));
+  HIPCHK(DenseOps<double>::trsm(stream, By, Cp, d_mdd, mdd.data(), np, false, dv_y, do_y));
   // the two solves leave C' symmetric only to ~kappa(By) eps; LOBPCG's
   // residuals cannot drop below that asymmetry, so C' is symmetrized
   symmetrize_kernel<<<dim3(nblocks((int64_t)max_d * max_d), np), TPB, 0, stream>>>(Cp, d_off_dd, d_dv);
@@ -1134,7 +1150,8 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
   MatDesc *d_mdy = pool.up(stream, mdy);
   GemmDesc *d_gz = pool.up(stream, gz), *d_gm = pool.up(stream, gm);
   double *Vtmp = pool.zeros(stream, tj);
-  HIPCHK(DenseOps<double>::trsm(stream, By, Yv, d_mdy, mdy.data(), np, true));
+  // (the factor By of the pair denominators, whose block inverses are dv_y)
+  HIPCHK(DenseOps<double>::trsm(stream, By, Yv, d_mdy, mdy.data(), np, true, dv_y, do_y));
   HIPCHK(DenseOps<double>::gemm(stream, Zd, Yv, Jv, d_gz, np, max_c, max_k, false, false, 1.0, 0.0, false, gz.data()));
   HIPCHK(DenseOps<double>::gemm(stream, Mc, Jv, Vtmp, d_gm, np, max_c, max_k, false, false, 1.0, 0.0, false, gm.data()));
   (void)Vv;

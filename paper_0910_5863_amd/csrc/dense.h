@@ -67,12 +67,17 @@ struct DenseOps {
                          int batch, int maxM, int maxN, bool transA, bool transB, T alpha,
                          T beta, bool lower, const GemmDesc *h_desc = nullptr);
   // In-place lower Cholesky of every entry's A (n x n).  status[e] is set to
-  // (column+1) of the first non-positive pivot (left untouched if none).
+  // (column+1) of the first non-positive pivot (left untouched if none).  The
+  // inverses of the NB x NB diagonal blocks of L are written to dinv: block
+  // kb of entry e at dinv + dinv_off[e] + kb NB^2 (column-major, ld NB; size
+  // from dinv_layout).
   static hipError_t potrf(hipStream_t st, T *pool, const MatDesc *d_desc, const MatDesc *h_desc,
-                          int batch, int *status);
-  // B <- L^{-1} B (forward) or L^{-T} B (backward), L the lower factor at a_off.
+                          int batch, int *status, T *dinv, const int64_t *dinv_off);
+  // B <- L^{-1} B (forward) or L^{-T} B (backward), L the lower factor at a_off
+  // with the inverses of its diagonal blocks in dinv (as written by potrf).
   static hipError_t trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc *d_desc,
-                         const MatDesc *h_desc, int batch, bool transpose);
+                         const MatDesc *h_desc, int batch, bool transpose, const T *dinv,
+                         const int64_t *dinv_off);
 };
 
 // Copy the lower triangle onto the upper one (entries A at a_off, n x n).
@@ -102,6 +107,18 @@ template <class T>
 hipError_t trsv_blocked(hipStream_t st, const T *apool, T *xpool, const MatDesc *d_desc,
                         const TrsvPlan &plan, bool upper, const T *dinv, const int64_t *dinv_off,
                         int *work, int *err);
+
+// Offsets of the diagonal-block inverses of entries of sizes n (one NB x NB
+// block per NB rows); returns the total number of elements.
+inline int64_t dinv_layout(const MatDesc *h_desc, int batch, std::vector<int64_t> &off) {
+  off.resize(batch);
+  int64_t t = 0;
+  for (int e = 0; e < batch; ++e) {
+    off[e] = t;
+    t += (int64_t)((h_desc[e].n + NB - 1) / NB) * NB * NB;
+  }
+  return t;
+}
 
 // Inverses of the NB x NB diagonal blocks of every entry's lower triangular
 // factor (a_off, n, lda of d_desc): block kb of entry e at

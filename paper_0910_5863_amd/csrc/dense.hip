@@ -66,7 +66,7 @@ __device__ __forceinline__ bool xcd_remap(int nwg, int tiles_per_entry, int batc
 
 // C[m0:m0+64, n0:n0+64] = beta*C + alpha*op(A)*op(B), bounds-checked.
 template <class T, bool TA, bool TB>
-__device__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C,
+__device__ void gemm_tile(const T *A, const T *B, T *C,
                           int M, int N, int K, int lda, int ldb, int ldc, T alpha, T beta, int m0,
                           int n0) {
   typedef typename Mfma<T>::v4 v4;
@@ -173,13 +173,16 @@ __global__ __launch_bounds__(256) void chol_update_kernel(T *pool, const MatDesc
                             d.lda, T(-1), T(1), t * BM, 0);
 }
 
-// Factor the diagonal block of block column k in LDS, in place: one
-// work-group per entry.  status[e] receives (column+1) of the first
-// non-positive pivot.
+// Factor the diagonal block of block column k in LDS, in place, and write
+// the inverse of the factored block to dinv (entry e, block k at
+// dinv + dinv_off[e] + k NB^2, ld NB): one work-group per entry.  status[e]
+// receives (column+1) of the first non-positive pivot.
 template <class T>
 __global__ __launch_bounds__(256) void chol_diag_kernel(T *pool, const MatDesc *desc, int k,
-                                                        int *status, int batch) {
+                                                        int *status, int batch, T *dinv,
+                                                        const int64_t *dinv_off) {
   __shared__ T D[NB][NB + 1];
+  __shared__ T Y[NB][NB + 1];
   __shared__ int s_fail;
   const int e = blockIdx.x;
   if (e >= batch) return;
@@ -219,15 +222,30 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(T *pool, const MatDesc *
     const int r = i % w, c = i / w;
     if (r >= c) A[(kb + r) + (kb + c) * lda] = D[r][c];
   }
+  // inverse of the factored block: thread j solves for column j
+  for (int i = tid; i < NB * NB; i += 256) Y[i % NB][i / NB] = T(0);
+  __syncthreads();
+  if (tid < w) {
+    const int j = tid;
+    for (int i = j; i < w; ++i) {
+      T sacc = (i == j) ? T(1) : T(0);
+      for (int m = j; m < i; ++m) sacc -= D[i][m] * Y[m][j];
+      Y[i][j] = sacc / D[i][i];
+    }
+  }
+  __syncthreads();
+  T *out = dinv + dinv_off[e] + (int64_t)k * NB * NB;
+  for (int i = tid; i < NB * NB; i += 256) out[i] = Y[i % NB][i / NB];
 }
 
-// Row tiles below the diagonal of block column k (tile t >= 1): X <- X L_kk^{-T}
-// with the factored diagonal block read from global memory.
+// Row tiles below the diagonal of block column k (tile t >= 1):
+// X <- X L_kk^{-T} = X (L_kk^{-1})^T, an MFMA tile product with the inverse
+// written by chol_diag_kernel (in place: the tile is read whole before it is
+// written).
 template <class T>
 __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc *desc, int k,
-                                                         int tm, int batch) {
-  __shared__ T D[NB][NB + 1];
-  __shared__ T X[NB][NB + 1];
+                                                         int tm, int batch, const T *dinv,
+                                                         const int64_t *dinv_off) {
   int e, t;
   if (!xcd_remap(gridDim.x, tm, batch, e, t)) return;
   const MatDesc d = desc[e];
@@ -237,31 +255,9 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc 
   const int r0 = kb + (t + 1) * NB;
   if (r0 >= d.n) return;
   const int nr = min(NB, d.n - r0);
-  T *A = pool + d.a_off;
-  const int64_t lda = d.lda;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < NB * NB; i += 256) {
-    const int r = i % NB, c = i / NB;
-    D[r][c] = (r < w && c < w && r >= c) ? A[(kb + r) + (kb + c) * lda] : T(0);
-    X[r][c] = (r < nr && c < w) ? A[(r0 + r) + (kb + c) * lda] : T(0);
-  }
-  __syncthreads();
-  // X L^T = B  ->  column by column, right-looking
-  for (int c = 0; c < w; ++c) {
-    const T inv = T(1) / D[c][c];
-    for (int r = tid; r < nr; r += 256) X[r][c] *= inv;
-    __syncthreads();
-    const int m = w - c - 1;
-    for (int i = tid; i < nr * m; i += 256) {
-      const int r = i % nr, s = c + 1 + i / nr;
-      X[r][s] -= X[r][c] * D[s][c];
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < nr * w; i += 256) {
-    const int r = i % nr, c = i / nr;
-    A[(r0 + r) + (kb + c) * lda] = X[r][c];
-  }
+  T *X = pool + d.a_off + r0 + (int64_t)kb * d.lda;
+  const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
+  gemm_tile<T, false, true>(X, Di, X, nr, w, w, d.lda, NB, d.lda, T(1), T(0), 0, 0);
 }
 
 // --- multi-RHS triangular solves -------------------------------------------
@@ -293,12 +289,14 @@ __global__ __launch_bounds__(256) void trsm_update_kernel(const T *apool, T *bpo
   }
 }
 
+// B[kb:kb+w, tile t] <- L_kk^{-1} B (forward) or L_kk^{-T} B (backward): an MFMA
+// tile product with the inverse of the diagonal block (in place: each
+// work-group reads its column tile whole before writing it).
 template <class T, bool BWD>
 __global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool,
                                                         const MatDesc *desc, int k, int tn,
-                                                        int batch) {
-  __shared__ T D[NB][NB + 1];
-  __shared__ T X[NB][NB + 1];
+                                                        int batch, const T *dinv,
+                                                        const int64_t *dinv_off) {
   int e, t;
   if (!xcd_remap(gridDim.x, tn, batch, e, t)) return;
   const MatDesc d = desc[e];
@@ -307,48 +305,9 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool
   const int w = min(NB, d.n - kb);
   const int c0 = t * NB;
   if (c0 >= d.nrhs) return;
-  const int nc = min(NB, d.nrhs - c0);
-  const T *L = apool + d.a_off;
-  T *B = bpool + d.b_off;
-  const int64_t lda = d.lda, ldb = d.ldb;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < w * w; i += 256) {
-    const int r = i % w, c = i / w;
-    D[r][c] = (r >= c) ? L[(kb + r) + (kb + c) * lda] : T(0);
-  }
-  for (int i = tid; i < w * nc; i += 256) {
-    const int r = i % w, c = i / w;
-    X[r][c] = B[(kb + r) + (c0 + c) * ldb];
-  }
-  __syncthreads();
-  if (!BWD) {
-    for (int r = 0; r < w; ++r) {
-      const T inv = T(1) / D[r][r];
-      for (int c = tid; c < nc; c += 256) X[r][c] *= inv;
-      __syncthreads();
-      const int m = w - r - 1;
-      for (int i = tid; i < m * nc; i += 256) {
-        const int rr = r + 1 + i % m, c = i / m;
-        X[rr][c] -= D[rr][r] * X[r][c];
-      }
-      __syncthreads();
-    }
-  } else {
-    for (int r = w - 1; r >= 0; --r) {
-      const T inv = T(1) / D[r][r];
-      for (int c = tid; c < nc; c += 256) X[r][c] *= inv;
-      __syncthreads();
-      for (int i = tid; i < r * nc; i += 256) {
-        const int rr = i % r, c = i / r;
-        X[rr][c] -= D[r][rr] * X[r][c];
-      }
-      __syncthreads();
-    }
-  }
-  for (int i = tid; i < w * nc; i += 256) {
-    const int r = i % w, c = i / w;
-    B[(kb + r) + (c0 + c) * ldb] = X[r][c];
-  }
+  T *B = bpool + d.b_off + kb;
+  const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
+  gemm_tile<T, BWD, false>(Di, B, B, w, d.nrhs, w, NB, d.ldb, d.ldb, T(1), T(0), 0, c0);
 }
 
 template <class T>
@@ -640,7 +599,8 @@ hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const
 
 template <class T>
 hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
-                              const MatDesc *h_desc, int batch, int *status) {
+                              const MatDesc *h_desc, int batch, int *status, T *dinv,
+                              const int64_t *dinv_off) {
   int maxn = 0;
   for (int e = 0; e < batch; ++e) maxn = std::max(maxn, h_desc[e].n);
   if (maxn == 0) return hipSuccess;
@@ -670,11 +630,12 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
     }
     {
       LaunchScope ls(st, "chol_diag_kernel", bd, fd);
-      chol_diag_kernel<T><<<batch, 256, 0, st>>>(pool, d_desc, k, status, batch);
+      chol_diag_kernel<T><<<batch, 256, 0, st>>>(pool, d_desc, k, status, batch, dinv, dinv_off);
     }
     if (tm > 1) {
       LaunchScope ls(st, "chol_panel_kernel", bp, fp);
-      chol_panel_kernel<T><<<grid_round(batch * (tm - 1)), 256, 0, st>>>(pool, d_desc, k, tm - 1, batch);
+      chol_panel_kernel<T><<<grid_round(batch * (tm - 1)), 256, 0, st>>>(pool, d_desc, k, tm - 1,
+                                                                          batch, dinv, dinv_off);
     }
   }
   return hipGetLastError();
@@ -682,7 +643,8 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
 
 template <class T>
 hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc *d_desc,
-                             const MatDesc *h_desc, int batch, bool transpose) {
+                             const MatDesc *h_desc, int batch, bool transpose, const T *dinv,
+                             const int64_t *dinv_off) {
   int maxn = 0, maxr = 0;
   for (int e = 0; e < batch; ++e) {
     maxn = std::max(maxn, h_desc[e].n);
@@ -718,7 +680,8 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
         trsm_update_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
       }
       LaunchScope ls(st, "trsm_diag_kernel<fwd>", bd, fd);
-      trsm_diag_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+      trsm_diag_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
+                                                      dinv_off);
     }
   } else {
     // entries of different sizes: block k of an entry is its k-th from the
@@ -731,7 +694,8 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
         trsm_update_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
       }
       LaunchScope ls(st, "trsm_diag_kernel<bwd>", bd, fd);
-      trsm_diag_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+      trsm_diag_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
+                                                     dinv_off);
     }
   }
   return hipGetLastError();

@@ -90,6 +90,8 @@ class MfDevice {
   std::vector<std::vector<MatDesc>> h_potrf_, h_trsm_;
   std::vector<std::vector<GemmDesc>> h_gemm_;
   std::vector<DBuf> d_potrf_, d_trsm_, d_gemm_;
+  DBuf d_dinv_;                                    // inverses of the L11 diagonal blocks
+  std::vector<DBuf> d_dinv_off_, d_dinv_toff_;     // per depth: for the potrf / trsm entries
   std::vector<int64_t> max_f_;                     // per depth: max p*f + b*b
   std::vector<int> max_pb_;                        // per depth: max p + b
   int64_t nnz_ = 0;

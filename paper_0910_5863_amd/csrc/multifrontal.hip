@@ -252,11 +252,11 @@ inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 
 
 void MfDevice::release(DevAlloc &A) {
   for (DBuf *b : {&d_fronts_, &d_child_, &d_piv_, &d_bnd_, &d_pmap_, &d_asm_, &d_root_ptr_,
-                  &d_root_ids_, &d_U_, &d_C_, &d_upd_, &d_status_, &d_level_ids_}) {
+                  &d_root_ids_, &d_U_, &d_C_, &d_upd_, &d_status_, &d_level_ids_, &d_dinv_}) {
     if (b->p) A.put(b->p, b->bytes);
     *b = DBuf();
   }
-  for (auto *v : {&d_potrf_, &d_trsm_, &d_gemm_}) {
+  for (auto *v : {&d_potrf_, &d_trsm_, &d_gemm_, &d_dinv_off_, &d_dinv_toff_}) {
     for (DBuf &b : *v)
       if (b.p) A.put(b.p, b.bytes);
     v->clear();
@@ -315,10 +315,30 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
   }
   level_off_[D + 1] = (int64_t)ids.size();
   d_level_ids_ = upload(A, st, ids);
+  // inverses of the diagonal blocks of every front's L11, per depth
+  std::vector<std::vector<int64_t>> doff(D + 1);
+  int64_t dtot = 0;
   for (int d = 0; d <= D; ++d) {
+    const int64_t t = dinv_layout(h_potrf_[d].data(), (int)h_potrf_[d].size(), doff[d]);
+    for (auto &o : doff[d]) o += dtot;
+    dtot += t;
+  }
+  d_dinv_ = zeros(A, st, sizeof(double) * (size_t)dtot);
+  // trsm entries are the potrf entries with b > 0: their inverse offsets
+  for (int d = 0; d <= D; ++d) {
+    std::vector<int64_t> toff;
+    size_t e = 0;
+    for (int t : M.levels[d]) {
+      const MfFront &f = M.fronts[t];
+      if (f.p == 0) continue;
+      if (f.b > 0) toff.push_back(doff[d][e]);
+      ++e;
+    }
     d_potrf_.push_back(upload(A, st, h_potrf_[d]));
     d_trsm_.push_back(upload(A, st, h_trsm_[d]));
     d_gemm_.push_back(upload(A, st, h_gemm_[d]));
+    d_dinv_off_.push_back(upload(A, st, doff[d]));
+    d_dinv_toff_.push_back(upload(A, st, toff));
   }
   // the in-front solves keep p + b values in LDS
   int max_lds = 0;
@@ -372,10 +392,12 @@ void MfDevice::factor(hipStream_t st, const double *val, int64_t nnz, double *S,
     const int np = (int)h_potrf_[d].size();
     if (np > 0)
       HIPCHK(DenseOps<double>::potrf(st, U, d_potrf_[d].as<MatDesc>(), h_potrf_[d].data(), np,
-                                     status + level_off_[d]));
+                                     status + level_off_[d], d_dinv_.as<double>(),
+                                     d_dinv_off_[d].as<int64_t>()));
     const int nt = (int)h_trsm_[d].size();
     if (nt > 0) {
-      HIPCHK(DenseOps<double>::trsm(st, U, U, d_trsm_[d].as<MatDesc>(), h_trsm_[d].data(), nt, false));
+      HIPCHK(DenseOps<double>::trsm(st, U, U, d_trsm_[d].as<MatDesc>(), h_trsm_[d].data(), nt, false,
+                                    d_dinv_.as<double>(), d_dinv_toff_[d].as<int64_t>()));
       int maxb = 0;
       for (const GemmDesc &g : h_gemm_[d]) maxb = std::max(maxb, g.M);
       HIPCHK(DenseOps<double>::gemm(st, U, U, C, d_gemm_[d].as<GemmDesc>(), nt, maxb, maxb, true, false,

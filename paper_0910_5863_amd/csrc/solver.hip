@@ -1029,26 +1029,26 @@ void Solver::factor() {
   // constrained local factor and coarse basis
   timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
   HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), d_descRR.as<MatDesc>(), h_descRR.data(),
-                                 ns, status + ns));
+                                 ns, status + ns, d_dinv_rr.as<double>(),
+                                 d_dinv_rr_off.as<int64_t>()));
   timer.end(st);
   HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
-                                h_descRR.data(), ns, false));
+                                h_descRR.data(), ns, false, d_dinv_rr.as<double>(),
+                                d_dinv_rr_off.as<int64_t>()));
   HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
                                 d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
                                 -1.0, 1.0, false, h_spi.data()));
   HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
-                                h_descRR.data(), ns, true));
+                                h_descRR.data(), ns, true, d_dinv_rr.as<double>(),
+                                d_dinv_rr_off.as<int64_t>()));
   if (L.sRP > 0) {
     axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
                                                  L.sRP);
     HIPCHK(hipGetLastError());
   }
-  // L_rr^T beside L_rr (the backward solves read it row-coalesced) and the
-  // inverses of the diagonal blocks of L_rr
+  // L_rr^T beside L_rr: the backward solves read it row-coalesced
   HIPCHK(transpose_batched<double>(st, d_Lrr.as<double>(), d_Urr.as<double>(),
                                    d_descRRT.as<MatDesc>(), ns, L.max_nr));
-  HIPCHK(diag_inverse<double>(st, d_Lrr.as<double>(), d_descRRT.as<MatDesc>(), ns, L.max_nr,
-                              d_dinv_rr.as<double>(), d_dinv_rr_off.as<int64_t>()));
   // coarse problem
   const int64_t nc = L.n_coarse;
   if (nc > 0) {
@@ -1058,11 +1058,10 @@ void Solver::factor() {
         d_Lc.as<double>());
     HIPCHK(hipGetLastError());
     HIPCHK(DenseOps<double>::potrf(st, d_Lc.as<double>(), d_descC.as<MatDesc>(), h_descC.data(), 1,
-                                   status + 2 * ns));
+                                   status + 2 * ns, d_dinv_c.as<double>(),
+                                   d_dinv_c_off.as<int64_t>()));
     HIPCHK(transpose_batched<double>(st, d_Lc.as<double>(), d_Uc.as<double>(), d_descC.as<MatDesc>(), 1,
                                      (int)nc));
-    HIPCHK(diag_inverse<double>(st, d_Lc.as<double>(), d_descC.as<MatDesc>(), 1, (int)nc,
-                                d_dinv_c.as<double>(), d_dinv_c_off.as<int64_t>()));
   }
   check_status(true);
   auto t1 = std::chrono::steady_clock::now();
