@@ -2,8 +2,10 @@
 //
 // GEMM tiles run on the matrix cores: v_mfma_f64_16x16x4f64 in FP64 and
 // v_mfma_f32_16x16x4f32 in FP32 (FP32 accumulate).  A work-group of 256
-// lanes (4 wave64) owns a 64x64 tile of C; each wave owns a 32x32 quadrant
-// as 2x2 MFMA blocks.  Operand tiles are staged through LDS in K-steps of 16.
+// lanes (4 wave64) owns a 64x64, 128x64, 64x128 or 128x128 tile of C; each
+// wave owns a quadrant of 16x16 MFMA blocks.  Operand tiles are staged
+// through LDS in K-steps of 16, the next step loaded into registers while the
+// current one is multiplied.
 // Work-group ids are remapped so that the tiles of one batch entry stay on
 // one XCD (consecutive hardware ids are dealt round-robin to the 8 XCDs),
 // which keeps an entry's shared operand panels in one L2.
@@ -26,7 +28,7 @@ namespace bddc {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BK = 16;  // K-step of the GEMM tiles
 constexpr int NXCD = 8;
 
 template <class T>
@@ -64,74 +66,82 @@ __device__ __forceinline__ bool xcd_remap(int nwg, int tiles_per_entry, int batc
   return entry < batch;
 }
 
-// C[m0:m0+64, n0:n0+64] = beta*C + alpha*op(A)*op(B), bounds-checked.
-template <class T, bool TA, bool TB>
-__device__ void gemm_tile(const T *A, const T *B, T *C,
-                          int M, int N, int K, int lda, int ldb, int ldc, T alpha, T beta, int m0,
-                          int n0) {
+// C[m0:m0+TM, n0:n0+TN] = beta*C + alpha*op(A)*op(B), bounds-checked, with
+// TM = 32 MT and TN = 32 NT: the four waves own 2 x 2 quadrants of MT x NT
+// MFMA blocks of 16 x 16.  Operands go through LDS in K-steps of BK; the next
+// step's operands are loaded into registers while the current one is
+// multiplied.  A or B may alias C (in-place products of one tile): every
+// operand element a work-group reads lies in its own C tile or is read before
+// the tile is written.
+template <class T, bool TA, bool TB, int MT, int NT>
+__device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int lda, int ldb,
+                          int ldc, T alpha, T beta, int m0, int n0) {
   typedef typename Mfma<T>::v4 v4;
-  __shared__ T As[BK][BM + 2];
-  __shared__ T Bs[BK][BN + 2];
+  constexpr int TM = 32 * MT, TN = 32 * NT;
+  constexpr int LA = TM * BK / 256, LB = TN * BK / 256;
+  __shared__ T As[BK][TM + 2];
+  __shared__ T Bs[BK][TN + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
-  v4 acc[2][2];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) acc[x][y] = v4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  v4 acc[MT][NT];
 #pragma unroll
-    for (int it = 0; it < (BM * BK) / 256; ++it) {
+  for (int x = 0; x < MT; ++x)
+#pragma unroll
+    for (int y = 0; y < NT; ++y) acc[x][y] = v4{0, 0, 0, 0};
+  T ra[LA], rb[LB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int it = 0; it < LA; ++it) {
       const int e = tid + it * 256;
-      int r, kk;
-      if (!TA) {
-        r = e % BM;
-        kk = e / BM;
-      } else {
-        kk = e % BK;
-        r = e / BK;
-      }
+      const int r = TA ? e / BK : e % TM, kk = TA ? e % BK : e / TM;
       const int gr = m0 + r, gk = k0 + kk;
-      T v = 0;
-      if (gr < M && gk < K) v = TA ? A[gk + (int64_t)gr * lda] : A[gr + (int64_t)gk * lda];
-      As[kk][r] = v;
+      ra[it] = (gr < M && gk < K) ? (TA ? A[gk + (int64_t)gr * lda] : A[gr + (int64_t)gk * lda]) : T(0);
     }
 #pragma unroll
-    for (int it = 0; it < (BN * BK) / 256; ++it) {
+    for (int it = 0; it < LB; ++it) {
       const int e = tid + it * 256;
-      int c, kk;
-      if (!TB) {
-        kk = e % BK;
-        c = e / BK;
-      } else {
-        c = e % BN;
-        kk = e / BN;
-      }
+      const int c = TB ? e % TN : e / BK, kk = TB ? e / TN : e % BK;
       const int gc = n0 + c, gk = k0 + kk;
-      T v = 0;
-      if (gc < N && gk < K) v = TB ? B[gc + (int64_t)gk * ldb] : B[gk + (int64_t)gc * ldb];
-      Bs[kk][c] = v;
+      rb[it] = (gc < N && gk < K) ? (TB ? B[gc + (int64_t)gk * ldb] : B[gk + (int64_t)gc * ldb]) : T(0);
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();  // the previous step's reads of LDS are done
+#pragma unroll
+    for (int it = 0; it < LA; ++it) {
+      const int e = tid + it * 256;
+      As[TA ? e % BK : e / TM][TA ? e / BK : e % TM] = ra[it];
+    }
+#pragma unroll
+    for (int it = 0; it < LB; ++it) {
+      const int e = tid + it * 256;
+      Bs[TB ? e / TN : e % BK][TB ? e % TN : e / BK] = rb[it];
     }
     __syncthreads();
+    if (k0 + BK < K) gload(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      const int k = kk + (lane >> 4);
-      const int l16 = lane & 15;
-      const T a0 = As[k][wr * 32 + l16], a1 = As[k][wr * 32 + 16 + l16];
-      const T b0 = Bs[k][wc * 32 + l16], b1 = Bs[k][wc * 32 + 16 + l16];
-      acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
-      acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
-      acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
-      acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+      const int k = kk + (lane >> 4), l16 = lane & 15;
+      T a[MT], b[NT];
+#pragma unroll
+      for (int x = 0; x < MT; ++x) a[x] = As[k][wr * 16 * MT + 16 * x + l16];
+#pragma unroll
+      for (int y = 0; y < NT; ++y) b[y] = Bs[k][wc * 16 * NT + 16 * y + l16];
+#pragma unroll
+      for (int x = 0; x < MT; ++x)
+#pragma unroll
+        for (int y = 0; y < NT; ++y) acc[x][y] = Mfma<T>::op(a[x], b[y], acc[x][y]);
     }
-    __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < MT; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < NT; ++y)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int row = m0 + wr * 32 + x * 16 + Mfma<T>::row(lane, j);
-        const int col = n0 + wc * 32 + y * 16 + (lane & 15);
+        const int row = m0 + wr * 16 * MT + 16 * x + Mfma<T>::row(lane, j);
+        const int col = n0 + wc * 16 * NT + 16 * y + (lane & 15);
         if (row < M && col < N) {
           T *c = &C[row + (int64_t)col * ldc];
           const T v = alpha * acc[x][y][j];
@@ -140,19 +150,20 @@ __device__ void gemm_tile(const T *A, const T *B, T *C,
       }
 }
 
-template <class T, bool TA, bool TB>
+template <class T, bool TA, bool TB, int MT, int NT>
 __global__ __launch_bounds__(256) void gemm_kernel(const T *A, const T *B, T *C,
                                                    const GemmDesc *desc, int tm, int tn, T alpha,
                                                    T beta, int lower, int batch) {
+  constexpr int TM = 32 * MT, TN = 32 * NT;
   int e, t;
   if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
   const GemmDesc d = desc[e];
   const int ti = t % tm, tj = t / tm;
-  const int m0 = ti * BM, n0 = tj * BN;
+  const int m0 = ti * TM, n0 = tj * TN;
   if (m0 >= d.M || n0 >= d.N) return;
-  if (lower && m0 + BM - 1 < n0) return;
-  gemm_tile<T, TA, TB>(A + d.a_off, B + d.b_off, C + d.c_off, d.M, d.N, d.K, d.lda, d.ldb, d.ldc,
-                       alpha, beta, m0, n0);
+  if (lower && m0 + TM - 1 < n0) return;
+  gemm_tile<T, TA, TB, MT, NT>(A + d.a_off, B + d.b_off, C + d.c_off, d.M, d.N, d.K, d.lda, d.ldb,
+                               d.ldc, alpha, beta, m0, n0);
 }
 
 // --- Cholesky -------------------------------------------------------------
@@ -167,10 +178,10 @@ __global__ __launch_bounds__(256) void chol_update_kernel(T *pool, const MatDesc
   const int kb = k * NB;
   if (kb >= d.n || k == 0) return;
   const int M = d.n - kb, N = min(NB, d.n - kb), K = kb;
-  if (t * BM >= M) return;
+  if (t * 128 >= M) return;
   T *A = pool + d.a_off;
-  gemm_tile<T, false, true>(A + kb, A + kb, A + kb + (int64_t)kb * d.lda, M, N, K, d.lda, d.lda,
-                            d.lda, T(-1), T(1), t * BM, 0);
+  gemm_tile<T, false, true, 4, 2>(A + kb, A + kb, A + kb + (int64_t)kb * d.lda, M, N, K, d.lda,
+                                  d.lda, d.lda, T(-1), T(1), t * 128, 0);
 }
 
 // Factor the diagonal block of block column k in LDS, in place, and write
@@ -257,7 +268,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc 
   const int nr = min(NB, d.n - r0);
   T *X = pool + d.a_off + r0 + (int64_t)kb * d.lda;
   const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
-  gemm_tile<T, false, true>(X, Di, X, nr, w, w, d.lda, NB, d.lda, T(1), T(0), 0, 0);
+  gemm_tile<T, false, true, 2, 2>(X, Di, X, nr, w, w, d.lda, NB, d.lda, T(1), T(0), 0, 0);
 }
 
 // --- multi-RHS triangular solves -------------------------------------------
@@ -274,18 +285,18 @@ __global__ __launch_bounds__(256) void trsm_update_kernel(const T *apool, T *bpo
   const int kb = k * NB;
   if (kb >= d.n) return;
   const int w = min(NB, d.n - kb);
-  if (t * BN >= d.nrhs) return;
+  if (t * 128 >= d.nrhs) return;
   const T *L = apool + d.a_off;
   T *B = bpool + d.b_off;
   if (!BWD) {
     if (kb == 0) return;
-    gemm_tile<T, false, false>(L + kb, B, B + kb, w, d.nrhs, kb, d.lda, d.ldb, d.ldb, T(-1), T(1),
-                               0, t * BN);
+    gemm_tile<T, false, false, 2, 4>(L + kb, B, B + kb, w, d.nrhs, kb, d.lda, d.ldb, d.ldb, T(-1),
+                                     T(1), 0, t * 128);
   } else {
     const int K = d.n - kb - w;
     if (K <= 0) return;
-    gemm_tile<T, true, false>(L + (kb + w) + (int64_t)kb * d.lda, B + kb + w, B + kb, w, d.nrhs,
-                              K, d.lda, d.ldb, d.ldb, T(-1), T(1), 0, t * BN);
+    gemm_tile<T, true, false, 2, 4>(L + (kb + w) + (int64_t)kb * d.lda, B + kb + w, B + kb, w,
+                                    d.nrhs, K, d.lda, d.ldb, d.ldb, T(-1), T(1), 0, t * 128);
   }
 }
 
@@ -307,7 +318,7 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool
   if (c0 >= d.nrhs) return;
   T *B = bpool + d.b_off + kb;
   const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
-  gemm_tile<T, BWD, false>(Di, B, B, w, d.nrhs, w, NB, d.ldb, d.ldb, T(1), T(0), 0, c0);
+  gemm_tile<T, BWD, false, 2, 2>(Di, B, B, w, d.nrhs, w, NB, d.ldb, d.ldb, T(1), T(0), 0, c0);
 }
 
 template <class T>
@@ -569,14 +580,27 @@ inline int grid_round(int n) { return ((n + NXCD - 1) / NXCD) * NXCD; }
 inline int blk(int n, int k) { return std::max(0, std::min(NB, n - k * NB)); }
 }  // namespace
 
+template <class T, int MT, int NT>
+static void launch_gemm(hipStream_t st, const T *A, const T *B, T *C, const GemmDesc *d_desc,
+                        int batch, int maxM, int maxN, bool transA, bool transB, T alpha, T beta,
+                        bool lower) {
+  const int tm = (maxM + 32 * MT - 1) / (32 * MT), tn = (maxN + 32 * NT - 1) / (32 * NT);
+  const dim3 g(grid_round(batch * tm * tn)), b(256);
+  if (!transA && !transB)
+    gemm_kernel<T, false, false, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+  else if (transA && !transB)
+    gemm_kernel<T, true, false, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+  else if (!transA && transB)
+    gemm_kernel<T, false, true, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+  else
+    gemm_kernel<T, true, true, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+}
+
 template <class T>
 hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const GemmDesc *d_desc,
                              int batch, int maxM, int maxN, bool transA, bool transB, T alpha,
                              T beta, bool lower, const GemmDesc *h_desc) {
   if (batch <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
-  const int tm = (maxM + BM - 1) / BM, tn = (maxN + BN - 1) / BN;
-  const int nwg = grid_round(batch * tm * tn);
-  dim3 g(nwg), b(256);
   double fl = 0, by = 0;
   if (launch_timing() && h_desc)
     for (int e = 0; e < batch; ++e) {
@@ -586,14 +610,11 @@ hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const
       by += sizeof(T) * ((double)q.M * q.K + (double)q.K * q.N + (beta != T(0) ? 2.0 : 1.0) * mn);
     }
   LaunchScope ls(st, "gemm_kernel", by, fl);
-  if (!transA && !transB)
-    gemm_kernel<T, false, false><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
-  else if (transA && !transB)
-    gemm_kernel<T, true, false><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
-  else if (!transA && transB)
-    gemm_kernel<T, false, true><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+  // 128 x 128 tiles for large products, 64 x 64 otherwise
+  if (maxM >= 256 && maxN >= 256)
+    launch_gemm<T, 4, 4>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower);
   else
-    gemm_kernel<T, true, true><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+    launch_gemm<T, 2, 2>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower);
   return hipGetLastError();
 }
 
@@ -607,7 +628,8 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
   const int nblk = (maxn + NB - 1) / NB;
   const bool timing = launch_timing() != nullptr;
   for (int k = 0; k < nblk; ++k) {
-    const int tm = nblk - k;  // row tiles of block column k (for the largest entry)
+    const int tm = nblk - k;  // row blocks of block column k (for the largest entry)
+    const int tu = (maxn - k * NB + 127) / 128;  // 128-row update tiles
     // algorithmic work of block column k over the batch: the update of the
     // column below the diagonal by the k*NB columns to its left, the
     // factorization of the diagonal block, and the panel solve under it
@@ -626,7 +648,7 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
       }
     if (k > 0) {
       LaunchScope ls(st, "chol_update_kernel", bu, fu);
-      chol_update_kernel<T><<<grid_round(batch * tm), 256, 0, st>>>(pool, d_desc, k, tm, batch);
+      chol_update_kernel<T><<<grid_round(batch * tu), 256, 0, st>>>(pool, d_desc, k, tu, batch);
     }
     {
       LaunchScope ls(st, "chol_diag_kernel", bd, fd);
@@ -652,8 +674,9 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
   }
   if (maxn == 0 || maxr == 0) return hipSuccess;
   const int nblk = (maxn + NB - 1) / NB;
-  const int tn = (maxr + NB - 1) / NB;
-  const int nwg = grid_round(batch * tn);
+  const int tn = (maxr + NB - 1) / NB;    // 64-wide column tiles (diagonal step)
+  const int tu = (maxr + 127) / 128;      // 128-wide column tiles (update)
+  const int nwg = grid_round(batch * tn), nwu = grid_round(batch * tu);
   const bool timing = launch_timing() != nullptr;
   // algorithmic work at block row k: the update of the k-th block row of B
   // by the solved rows (forward: the k*NB above it; backward: the ones below)
@@ -677,7 +700,7 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
       work(k, fu, bu, fd, bd);
       if (k > 0) {
         LaunchScope ls(st, "trsm_update_kernel<fwd>", bu, fu);
-        trsm_update_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+        trsm_update_kernel<T, false><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tu, batch);
       }
       LaunchScope ls(st, "trsm_diag_kernel<fwd>", bd, fd);
       trsm_diag_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
@@ -691,7 +714,7 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
       work(k, fu, bu, fd, bd);
       {
         LaunchScope ls(st, "trsm_update_kernel<bwd>", bu, fu);
-        trsm_update_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+        trsm_update_kernel<T, true><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tu, batch);
       }
       LaunchScope ls(st, "trsm_diag_kernel<bwd>", bd, fd);
       trsm_diag_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
