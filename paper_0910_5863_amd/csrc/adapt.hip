@@ -145,6 +145,8 @@ __global__ void symmetrize_kernel(double *A, const int64_t *off, const int *n) {
 constexpr int LOB_S = LOB_MAXB / 3;  // block size (columns of X, W and P)
 constexpr int LOCK_MAX = 256;        // eigenvectors locked from earlier rounds
 constexpr int STAGE_ROWS = 256;      // rows of a block staged in LDS per pass
+constexpr int DOT_ROWS = 64;         // rows per chunk of the block products U^T V
+constexpr int DOT_PER_THREAD = (LOB_MAXB * LOB_MAXB + 255) / 256;
 
 struct LobDesc {
   int64_t a_off;    // d x d matrix (ld d)
@@ -161,6 +163,9 @@ struct LobOut {
   int iters;
   int converged;
   int nconv;
+  // time per phase (wall clock ticks, thread 0): A products, orthonormalization,
+  // Rayleigh-Ritz products, Rayleigh-Ritz eigensolves
+  long long ticks[4];
 };
 
 // y = sum_k x[k] over the work-group
@@ -178,36 +183,45 @@ __device__ double block_sum(double v, double *red) {
 // Symmetric eigen-decomposition of the n x n matrix H (LDS, ld LOB_MAXB+1) by
 // parallel cyclic Jacobi (round-robin pairing): H <- diag, V <- eigenvectors.
 // Sweeps stop when every off-diagonal entry is below 1e-15 sqrt(|h_pp h_qq|)
-// (relative accuracy for semidefinite H), or the off-diagonal mass is below
-// 1e-30 of the total, or after 20 sweeps.
+// (relative accuracy for semidefinite H) or below 1e-17 of the Frobenius norm
+// (rotations preserve it; smaller entries cannot move the eigenpairs), or the
+// off-diagonal mass is below 1e-30 of the total, or after 20 sweeps.
 __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1], int n,
-                           int *perm, double *cs, double *sn, double *red) {
-  const int tid = threadIdx.x;
+                           double *cs, double *sn, double *red) {
+  __shared__ int pp[LOB_MAXB / 2 + 1], qq[LOB_MAXB / 2 + 1];
+  const int tid = threadIdx.x;  // launched with 256 threads
   for (int i = tid; i < n * n; i += blockDim.x) V[i % n][i / n] = (i % n == i / n) ? 1.0 : 0.0;
   const int m = (n + 1) / 2 * 2;  // even number of players (a dummy when n is odd)
-  for (int i = tid; i < m; i += blockDim.x) perm[i] = i;
+  // round-robin schedule: player 0 stays, the others move one place per step,
+  // so at step t position i >= 1 holds player 1 + ((i - 1 - t) mod (m - 1))
+  auto player = [m](int i, int t) {
+    if (i == 0) return 0;
+    const int r = (i - 1 - t) % (m - 1);
+    return 1 + (r < 0 ? r + m - 1 : r);
+  };
   __syncthreads();
+  double tot = 0;
+  for (int i = tid; i < n * n; i += blockDim.x) tot += H[i % n][i / n] * H[i % n][i / n];
+  tot = block_sum(tot, red);
+  const double floor_abs = 1e-17 * sqrt(tot);
   for (int sweep = 0; sweep < 20; ++sweep) {
-    double off = 0, tot = 0, viol = 0;
+    double off = 0, viol = 0;
     for (int i = tid; i < n * n; i += blockDim.x) {
       const int a = i % n, b = i / n;
+      if (a == b) continue;
       const double h = H[a][b];
-      tot += h * h;
-      if (a != b) {
-        off += h * h;
-        if (fabs(h) > 1e-15 * sqrt(fabs(H[a][a] * H[b][b]))) viol += 1;
-      }
+      off += h * h;
+      if (fabs(h) > fmax(1e-15 * sqrt(fabs(H[a][a] * H[b][b])), floor_abs)) viol += 1;
     }
     off = block_sum(off, red);
-    tot = block_sum(tot, red);
     viol = block_sum(viol, red);
     if (viol == 0 || off <= 1e-30 * tot || tot == 0) break;
     for (int step = 0; step < m - 1; ++step) {
-      // pairs (perm[k], perm[m-1-k]), k < m/2
-      for (int k = tid; k < m / 2; k += blockDim.x) {
-        int p = perm[k], q = perm[m - 1 - k];
+      // the step's pairs (player(k), player(m-1-k)), k < m/2, and rotations
+      if (tid < m / 2) {
+        int p = player(tid, step), q = player(m - 1 - tid, step);
         if (p > q) {
-          int t = p;
+          const int t = p;
           p = q;
           q = t;
         }
@@ -218,51 +232,35 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
           c = 1 / sqrt(t * t + 1);
           s = t * c;
         }
-        cs[k] = c;
-        sn[k] = s;
+        pp[tid] = p;
+        qq[tid] = q;
+        cs[tid] = c;
+        sn[tid] = s;
       }
       __syncthreads();
+      // 256 threads: pair slot tid & 31, every 8th column / row from tid >> 5
+      const int k = tid & 31, g = tid >> 5;
+      const bool act = k < m / 2 && qq[min(k, m / 2 - 1)] < n;
+      const int p = act ? pp[k] : 0, q = act ? qq[k] : 0;
+      const double c = act ? cs[k] : 1.0, s = act ? sn[k] : 0.0;
       // rows: H <- J^T H
-      for (int i = tid; i < (m / 2) * n; i += blockDim.x) {
-        const int k = i % (m / 2), col = i / (m / 2);
-        int p = perm[k], q = perm[m - 1 - k];
-        if (p > q) {
-          int t = p;
-          p = q;
-          q = t;
+      if (act)
+        for (int col = g; col < n; col += 8) {
+          const double hp = H[p][col], hq = H[q][col];
+          H[p][col] = c * hp - s * hq;
+          H[q][col] = s * hp + c * hq;
         }
-        if (q >= n) continue;
-        const double c = cs[k], s = sn[k];
-        const double hp = H[p][col], hq = H[q][col];
-        H[p][col] = c * hp - s * hq;
-        H[q][col] = s * hp + c * hq;
-      }
       __syncthreads();
       // columns: H <- H J, V <- V J
-      for (int i = tid; i < (m / 2) * n; i += blockDim.x) {
-        const int k = i % (m / 2), row = i / (m / 2);
-        int p = perm[k], q = perm[m - 1 - k];
-        if (p > q) {
-          int t = p;
-          p = q;
-          q = t;
+      if (act)
+        for (int row = g; row < n; row += 8) {
+          const double hp = H[row][p], hq = H[row][q];
+          H[row][p] = c * hp - s * hq;
+          H[row][q] = s * hp + c * hq;
+          const double vp = V[row][p], vq = V[row][q];
+          V[row][p] = c * vp - s * vq;
+          V[row][q] = s * vp + c * vq;
         }
-        if (q >= n) continue;
-        const double c = cs[k], s = sn[k];
-        const double hp = H[row][p], hq = H[row][q];
-        H[row][p] = c * hp - s * hq;
-        H[row][q] = s * hp + c * hq;
-        const double vp = V[row][p], vq = V[row][q];
-        V[row][p] = c * vp - s * vq;
-        V[row][q] = s * vp + c * vq;
-      }
-      __syncthreads();
-      // rotate the round-robin schedule (player 0 fixed)
-      if (tid == 0) {
-        const int last = perm[m - 1];
-        for (int k = m - 1; k > 1; --k) perm[k] = perm[k - 1];
-        perm[1] = last;
-      }
       __syncthreads();
     }
   }
@@ -285,6 +283,8 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
   __shared__ double Cs[LOB_MAXB][2 * LOB_S + 1]; // Ritz coefficients (X part, P part)
   __shared__ double Ms[LOB_S][LOB_S + 1];        // orthonormalizing map of a block
   __shared__ double stage[STAGE_ROWS * LOB_S];    // staged rows, or locked coefficients
+  __shared__ double su[DOT_ROWS][LOB_MAXB + 1];   // row chunks of block products
+  __shared__ double sv[DOT_ROWS][LOB_MAXB + 1];
   __shared__ double theta[LOB_MAXB], gsc[LOB_MAXB], dinv[LOB_MAXB], res[LOB_S];
   __shared__ double cs[LOB_MAXB / 2 + 1], sn[LOB_MAXB / 2 + 1], red[8];
   __shared__ int perm[LOB_MAXB + 2];
@@ -299,6 +299,7 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
   const double *YL = pool + D.lock_off;
   const int nl = D.nl;
   int nw = 0, npc = 0;  // columns held in W and P
+  long long ticks[4] = {0, 0, 0, 0};  // phase timing (see LobOut)
 
   // o[a * ldo + b] = U[:, a] . V[:, b]  (one wave per entry)
   auto dots = [&](const double *U, int nu, const double *V, int nv, double *o, int ldo) {
@@ -311,6 +312,47 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
       if (lane == 0) o[a * ldo + b] = acc;
     }
     __syncthreads();
+  };
+  // o[a * ldo + b] = u_a . v_b for nu, nv <= LOB_MAXB columns given by
+  // accessors: the rows go through LDS in chunks, each thread owns a few
+  // entries and sums them in row order (no atomics, fixed order)
+  auto block_dot = [&](auto ucol, int nu, auto vcol2, int nv, double *o, int ldo) {
+    const int ne = nu * nv;
+    double acc[DOT_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < DOT_PER_THREAD; ++q) acc[q] = 0;
+    for (int c0 = 0; c0 < d; c0 += DOT_ROWS) {
+      const int cn = min(DOT_ROWS, d - c0);
+      __syncthreads();
+      for (int i = tid; i < DOT_ROWS * nu; i += nt) {
+        const int r = i % DOT_ROWS, a = i / DOT_ROWS;
+        su[r][a] = r < cn ? ucol(a)[c0 + r] : 0.0;
+      }
+      for (int i = tid; i < DOT_ROWS * nv; i += nt) {
+        const int r = i % DOT_ROWS, b = i / DOT_ROWS;
+        sv[r][b] = r < cn ? vcol2(b)[c0 + r] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < DOT_PER_THREAD; ++q) {
+        const int e = tid + q * nt;
+        if (e < ne) {
+          const int a = e % nu, b = e / nu;
+          double t = 0;
+          for (int r = 0; r < cn; ++r) t += su[r][a] * sv[r][b];
+          acc[q] += t;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < DOT_PER_THREAD; ++q) {
+      const int e = tid + q * nt;
+      if (e < ne) o[(e % nu) * ldo + e / nu] = acc[q];
+    }
+    __syncthreads();
+  };
+  auto cols = [d](const double *base) {
+    return [base, d](int a) { return base + (int64_t)a * d; };
   };
   // V[:, b] -= sum_a U[:, a] c[a * ldc + b] for b < nv (AV -= AU c alongside)
   auto sub_prod = [&](double *V, double *AV, int nv, const double *U, const double *AU, int nu,
@@ -363,7 +405,7 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
   // Returns the number of columns kept.
   auto svqb = [&](double *V, double *AV, int nv, double thr) -> int {
     if (nv == 0) return 0;
-    dots(V, nv, V, nv, &Hs[0][0], LOB_MAXB + 1);
+    block_dot(cols(V), nv, cols(V), nv, &Hs[0][0], LOB_MAXB + 1);
     for (int a = tid; a < nv; a += nt) dinv[a] = Hs[a][a] > 0 ? 1.0 / sqrt(Hs[a][a]) : 0.0;
     __syncthreads();
     for (int i = tid; i < nv * nv; i += nt) {
@@ -371,7 +413,7 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
       Hs[a][b] *= dinv[a] * dinv[b];
     }
     __syncthreads();
-    jacobi_eig(Hs, Qs, nv, perm, cs, sn, red);
+    jacobi_eig(Hs, Qs, nv, cs, sn, red);
     if (tid == 0) {
       int keep = 0;
       for (int a = 0; a < nv; ++a)
@@ -440,23 +482,19 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
   // coefficients of the new X (Cs[:, 0..s)) and of the new P (Cs[:, s..2s):
   // the same vectors without their X rows)
   auto rayleigh_ritz = [&](int n) {
-    for (int i = wave; i < n * n; i += nwave) {
+    // H = V^T A V, symmetrized
+    block_dot(vcol, n, avcol, n, &Hs[0][0], LOB_MAXB + 1);
+    for (int i = tid; i < n * n; i += nt) {
       const int a = i % n, b = i / n;
-      if (a > b) continue;
-      const double *va = vcol(a), *vb = vcol(b), *aa = avcol(a), *ab = avcol(b);
-      double h1 = 0, h2 = 0;
-      for (int r = lane; r < d; r += 64) {
-        h1 += va[r] * ab[r];
-        h2 += vb[r] * aa[r];
+      if (a < b) {
+        const double h = 0.5 * (Hs[a][b] + Hs[b][a]);
+        Hs[a][b] = Hs[b][a] = h;
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        h1 += __shfl_xor(h1, off, 64);
-        h2 += __shfl_xor(h2, off, 64);
-      }
-      if (lane == 0) Hs[a][b] = Hs[b][a] = 0.5 * (h1 + h2);
     }
     __syncthreads();
-    jacobi_eig(Hs, Qs, n, perm, cs, sn, red);
+    const long long tj = wall_clock64();
+    jacobi_eig(Hs, Qs, n, cs, sn, red);
+    ticks[3] += wall_clock64() - tj;
     if (tid == 0) {
       for (int a = 0; a < n; ++a) perm[a] = a;
       for (int a = 0; a < s; ++a)
@@ -516,8 +554,12 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
     kx = svqb(X, nullptr, s, 1e-10);
   }
   if (kx == s) {
+    long long t0 = wall_clock64();
     apply_A(X, AX, s);
+    ticks[0] += wall_clock64() - t0;
+    t0 = wall_clock64();
     rayleigh_ritz(s);
+    ticks[2] += wall_clock64() - t0;
     ritz_update(s, false);
   }
   for (it = 1; it <= maxit && kx == s; ++it) {
@@ -558,35 +600,44 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
       W[i] = res[q] > 0 ? W[i] / res[q] : 0.0;
     }
     __syncthreads();
+    long long to = wall_clock64();
     nw = s;
     for (int pass = 0; pass < 2 && nw > 0; ++pass) {
       project_locked(W, nw);
-      dots(X, s, W, nw, &Cs[0][0], 2 * LOB_S + 1);
+      block_dot(cols(X), s, cols(W), nw, &Cs[0][0], 2 * LOB_S + 1);
       sub_prod(W, nullptr, nw, X, nullptr, s, &Cs[0][0], 2 * LOB_S + 1);
       if (npc > 0) {
-        dots(P, npc, W, nw, &Cs[0][0], 2 * LOB_S + 1);
+        block_dot(cols(P), npc, cols(W), nw, &Cs[0][0], 2 * LOB_S + 1);
         sub_prod(W, nullptr, nw, P, nullptr, npc, &Cs[0][0], 2 * LOB_S + 1);
       }
       nw = svqb(W, nullptr, nw, 1e-10);
     }
+    ticks[1] += wall_clock64() - to;
     if (nw == 0 && npc == 0) break;  // no direction left: stagnation
+    long long t1 = wall_clock64();
     apply_A(W, AW, nw);
+    ticks[0] += wall_clock64() - t1;
     const int n = s + nw + npc;
+    t1 = wall_clock64();
     rayleigh_ritz(n);
+    ticks[2] += wall_clock64() - t1;
     ritz_update(n, true);
     // P: orthogonal to the new X, orthonormal
+    to = wall_clock64();
     npc = s;
     for (int pass = 0; pass < 2 && npc > 0; ++pass) {
-      dots(X, s, P, npc, &Cs[0][0], 2 * LOB_S + 1);
+      block_dot(cols(X), s, cols(P), npc, &Cs[0][0], 2 * LOB_S + 1);
       sub_prod(P, AP, npc, X, AX, s, &Cs[0][0], 2 * LOB_S + 1);
       npc = svqb(P, AP, npc, 1e-10);
     }
+    ticks[1] += wall_clock64() - to;
     nw = 0;
   }
   if (tid == 0) {
     out[blockIdx.x].iters = it;
     out[blockIdx.x].converged = done ? 1 : 0;
     out[blockIdx.x].nconv = nconv;
+    for (int q = 0; q < 4; ++q) out[blockIdx.x].ticks[q] = ticks[q];
   }
   // eigenvalues into the first column of T1 for the host
   __syncthreads();
@@ -1121,9 +1172,15 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
                                std::to_string(lo[a].nconv) + ")";
         }
       }
-      char buf[200];
-      std::snprintf(buf, sizeof buf, "LOBPCG round %d: %d pairs, max iters %d, unconverged %d, continuing %d;",
-                    round, na, mx, nu, (int)next.size());
+      long long tk[4] = {0, 0, 0, 0};
+      for (int a = 0; a < na; ++a)
+        for (int q = 0; q < 4; ++q) tk[q] = std::max(tk[q], lo[a].ticks[q]);
+      char buf[320];
+      std::snprintf(buf, sizeof buf,
+                    "LOBPCG round %d: %d pairs, max iters %d, unconverged %d, continuing %d; max ms: "
+                    "A %.2f, orth %.2f, RR %.2f (eig %.2f);",
+                    round, na, mx, nu, (int)next.size(), tk[0] * 1e-5, tk[1] * 1e-5, tk[2] * 1e-5,
+                    tk[3] * 1e-5);
       log((std::string(buf) + bad).c_str());
     }
     active.swap(next);
