@@ -361,14 +361,24 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
       double acc[LOB_S], aacc[LOB_S];
 #pragma unroll
       for (int q = 0; q < LOB_S; ++q) acc[q] = aacc[q] = 0;
-      for (int a = 0; a < nu; ++a) {
-        const double u = U[r + (int64_t)a * d];
-        const double au = AV ? AU[r + (int64_t)a * d] : 0.0;
+      // eight columns of U (and A U) loaded per batch
+      for (int a0 = 0; a0 < nu; a0 += 8) {
+        double u8[8], au8[8];
 #pragma unroll
-        for (int q = 0; q < LOB_S; ++q) {
-          if (q < nv) {
-            acc[q] += u * c[a * ldc + q];
-            aacc[q] += au * c[a * ldc + q];
+        for (int t = 0; t < 8; ++t) {
+          u8[t] = a0 + t < nu ? U[r + (int64_t)(a0 + t) * d] : 0.0;
+          au8[t] = (AV && a0 + t < nu) ? AU[r + (int64_t)(a0 + t) * d] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (a0 + t >= nu) break;
+          const double *ca = c + (a0 + t) * ldc;
+#pragma unroll
+          for (int q = 0; q < LOB_S; ++q) {
+            if (q < nv) {
+              acc[q] += u8[t] * ca[q];
+              aacc[q] += au8[t] * ca[q];
+            }
           }
         }
       }
@@ -385,11 +395,15 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
   // V[:, 0..kp) = V[:, 0..nv) M  (M in Ms)
   auto right_mul = [&](double *V, int nv, int kp) {
     for (int r = tid; r < d; r += nt) {
-      double acc[LOB_S];
+      double acc[LOB_S], vr[LOB_S];
 #pragma unroll
       for (int q = 0; q < LOB_S; ++q) acc[q] = 0;
-      for (int b = 0; b < nv; ++b) {
-        const double v = V[r + (int64_t)b * d];
+#pragma unroll
+      for (int b = 0; b < LOB_S; ++b) vr[b] = b < nv ? V[r + (int64_t)b * d] : 0.0;
+#pragma unroll
+      for (int b = 0; b < LOB_S; ++b) {
+        if (b >= nv) break;
+        const double v = vr[b];
 #pragma unroll
         for (int q = 0; q < LOB_S; ++q)
           if (q < kp) acc[q] += v * Ms[b][q];
@@ -435,6 +449,54 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
     if (AV) right_mul(AV, nv, kp);
     return kp;
   };
+  // orthonormalization of a well-conditioned block: V <- V L^-T with
+  // V^T V = L L^T (Cholesky in LDS).  Returns false (V untouched) if a pivot
+  // falls below 1e-8 of its diagonal entry (condition above 1e4: the caller
+  // then uses the eigen-decomposition, which drops dependent columns).
+  auto cholqr = [&](double *V, double *AV, int nv) -> bool {
+    if (nv == 0) return true;
+    block_dot(cols(V), nv, cols(V), nv, &Hs[0][0], LOB_MAXB + 1);
+    if (tid == 0) {
+      int ok = 1;
+      for (int j = 0; j < nv && ok; ++j) {
+        double dj = Hs[j][j];
+        for (int k = 0; k < j; ++k) dj -= Hs[j][k] * Hs[j][k];
+        if (!(dj > 1e-8 * Hs[j][j])) {
+          ok = 0;
+          break;
+        }
+        dj = sqrt(dj);
+        Hs[j][j] = dj;
+        for (int i = j + 1; i < nv; ++i) {
+          double v = Hs[i][j];
+          for (int k = 0; k < j; ++k) v -= Hs[i][k] * Hs[j][k];
+          Hs[i][j] = v / dj;
+        }
+      }
+      s_keep = ok;
+    }
+    __syncthreads();
+    if (!s_keep) return false;
+    // columns of L^-1 (thread j), then Ms = L^-T
+    if (tid < nv) {
+      const int j = tid;
+      for (int i = 0; i < nv; ++i) Qs[i][j] = 0.0;
+      for (int i = j; i < nv; ++i) {
+        double y = (i == j) ? 1.0 : 0.0;
+        for (int m = j; m < i; ++m) y -= Hs[i][m] * Qs[m][j];
+        Qs[i][j] = y / Hs[i][i];
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nv * nv; i += nt) {
+      const int b = i % nv, q = i / nv;
+      Ms[b][q] = q >= b ? Qs[q][b] : 0.0;
+    }
+    __syncthreads();
+    right_mul(V, nv, nv);
+    if (AV) right_mul(AV, nv, nv);
+    return true;
+  };
   // V <- V - YL (YL^T V): keep a block orthogonal to the locked vectors
   auto project_locked = [&](double *V, int nv) {
     if (nl == 0 || nv == 0) return;
@@ -457,10 +519,18 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
         }
         __syncthreads();
         if (r < d) {
-          for (int c = 0; c < cn; ++c) {
-            const double a = A[r + (int64_t)(c0 + c) * d];
+          // eight loads of A in flight per thread
+          for (int c = 0; c < cn; c += 8) {
+            double a8[8];
 #pragma unroll
-            for (int q = 0; q < LOB_S; ++q) acc[q] += a * stage[c * LOB_S + q];
+            for (int u = 0; u < 8; ++u) a8[u] = c + u < cn ? A[r + (int64_t)(c0 + c + u) * d] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              if (c + u < cn) {
+#pragma unroll
+                for (int q = 0; q < LOB_S; ++q) acc[q] += a8[u] * stage[(c + u) * LOB_S + q];
+              }
+            }
           }
         }
       }
@@ -551,7 +621,7 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
   int kx = s;
   for (int pass = 0; pass < 2 && kx == s; ++pass) {
     project_locked(X, s);
-    kx = svqb(X, nullptr, s, 1e-10);
+    if (pass == 0 || !cholqr(X, nullptr, s)) kx = svqb(X, nullptr, s, 1e-10);
   }
   if (kx == s) {
     long long t0 = wall_clock64();
@@ -610,7 +680,7 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
         block_dot(cols(P), npc, cols(W), nw, &Cs[0][0], 2 * LOB_S + 1);
         sub_prod(W, nullptr, nw, P, nullptr, npc, &Cs[0][0], 2 * LOB_S + 1);
       }
-      nw = svqb(W, nullptr, nw, 1e-10);
+      if (!cholqr(W, nullptr, nw)) nw = svqb(W, nullptr, nw, 1e-10);
     }
     ticks[1] += wall_clock64() - to;
     if (nw == 0 && npc == 0) break;  // no direction left: stagnation
@@ -628,7 +698,7 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
     for (int pass = 0; pass < 2 && npc > 0; ++pass) {
       block_dot(cols(X), s, cols(P), npc, &Cs[0][0], 2 * LOB_S + 1);
       sub_prod(P, AP, npc, X, AX, s, &Cs[0][0], 2 * LOB_S + 1);
-      npc = svqb(P, AP, npc, 1e-10);
+      if (!cholqr(P, AP, npc)) npc = svqb(P, AP, npc, 1e-10);
     }
     ticks[1] += wall_clock64() - to;
     nw = 0;
@@ -1127,9 +1197,12 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
                             hipMemcpyHostToDevice, stream));
     }
     HIPCHK(hipMemcpyAsync(ldb.p, lda.data(), sizeof(LobDesc) * na, hipMemcpyHostToDevice, stream));
-    lobpcg_kernel<<<na, 256, 0, stream>>>(LP, ldb.as<LobDesc>(), outb.as<LobOut>(), maxit, tol,
-                                          tol_ind);
-    HIPCHK(hipGetLastError());
+    {
+      LaunchScope ls(stream, "lobpcg_kernel", 0, 0);
+      lobpcg_kernel<<<na, 256, 0, stream>>>(LP, ldb.as<LobDesc>(), outb.as<LobOut>(), maxit, tol,
+                                            tol_ind);
+      HIPCHK(hipGetLastError());
+    }
     std::vector<LobOut> lo(na);
     HIPCHK(hipMemcpyAsync(lo.data(), outb.p, sizeof(LobOut) * na, hipMemcpyDeviceToHost, stream));
     std::vector<std::vector<double>> th(na);
@@ -1140,6 +1213,17 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
                             hipMemcpyDeviceToHost, stream));
     }
     HIPCHK(hipStreamSynchronize(stream));
+    if (LaunchTiming *lt = launch_timing()) {
+      // algorithmic work: per iteration one pass over the pair matrix C'
+      // (d x d) multiplying the s-column search block
+      double by = 0, fl = 0;
+      for (int a = 0; a < na; ++a) {
+        const double dd = dv[active[a]], it = lo[a].iters;
+        by += it * 8.0 * dd * dd;
+        fl += it * 2.0 * dd * dd * ld[active[a]].s;
+      }
+      lt->launch_amend(by, fl);
+    }
     std::vector<int> next;
     std::vector<GemmDesc> gdef;
     for (int a = 0; a < na; ++a) {

@@ -19,6 +19,8 @@ constexpr int NB = 64;  // block size of the blocked factorizations and solves
 struct LaunchTiming {
   virtual void launch_begin(hipStream_t st, const char *kernel, double bytes, double flops) = 0;
   virtual void launch_end(hipStream_t st) = 0;
+  // sets the work of the last timed launch (when it is known only afterwards)
+  virtual void launch_amend(double bytes, double flops) = 0;
   virtual ~LaunchTiming() = default;
 };
 LaunchTiming *&launch_timing();  // the calling thread's slot (nullptr: off)

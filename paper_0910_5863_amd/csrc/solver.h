@@ -68,6 +68,7 @@ class Timer : public LaunchTiming {
   void end(hipStream_t st);
   void launch_begin(hipStream_t st, const char *kernel, double bytes, double flops) override;
   void launch_end(hipStream_t st) override;
+  void launch_amend(double bytes, double flops) override;
   void collect();  // after a synchronization: resolve pending event pairs
   void reset();
   ~Timer();

@@ -457,6 +457,13 @@ void Timer::launch_end(hipStream_t st) {
   if (mode == 2) record_end(st);
 }
 
+void Timer::launch_amend(double bytes, double flops) {
+  if (mode == 2 && !pending.empty()) {
+    pending.back().bytes = bytes;
+    pending.back().flops = flops;
+  }
+}
+
 void Timer::record_begin(hipStream_t st, const char *name, double bytes, double flops) {
   int idx = -1;
   for (size_t i = 0; i < names.size(); ++i)
