@@ -142,15 +142,21 @@ __global__ void symmetrize_kernel(double *A, const int64_t *off, const int *n) {
 // ---------------------------------------------------------------------------
 // batched LOBPCG: dominant eigenpairs of a symmetric d x d matrix per entry
 
-constexpr int LOB_S = LOB_MAXB / 3;  // block size (columns of X, W and P)
-constexpr int LOCK_MAX = 256;        // eigenvectors locked from earlier rounds
-constexpr int STAGE_ROWS = 256;      // rows of a block staged in LDS per pass
-constexpr int DOT_ROWS = 64;         // rows per chunk of the block products U^T V
-constexpr int DOT_PER_THREAD = (LOB_MAXB * LOB_MAXB + 255) / 256;
+constexpr int LOB_NT = 512;                // threads per work-group (8 waves)
+constexpr int LOB_NWAVE = LOB_NT / 64;
+constexpr int LOB_S = LOB_MAXB / 3;        // block size (columns of X, W and P)
+constexpr int LOCK_MAX = 256;              // eigenvectors locked from earlier rounds
+constexpr int STAGE_ROWS = 256;            // rows of a block staged in LDS per pass
+constexpr int DOT_ROWS = 64;               // rows per chunk of the block products U^T V
+constexpr int DOT_LD = 2 * LOB_MAXB / LOB_NWAVE;  // staged columns per wave and chunk
+constexpr int JAC_NB = (LOB_MAXB / 2) * (LOB_MAXB / 2) / LOB_NT + 1;  // 2 x 2 blocks per thread
+constexpr int JAC_NV = LOB_MAXB * (LOB_MAXB / 2) / LOB_NT + 1;        // V row pairs per thread
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct LobDesc {
   int64_t a_off;    // d x d matrix (ld d)
-  int64_t v_off;    // 6 blocks of d x s: X, AX, W, AW, P, AP (ld d)
+  int64_t v_off;    // V = [X P W] (d x 3s), then A V (d x 3s), ld d
   int64_t t_off;    // 2 blocks of d x s scratch
   int64_t lock_off; // nl locked orthonormal eigenvectors (d x nl, ld d)
   int nl;
@@ -180,18 +186,84 @@ __device__ double block_sum(double v, double *red) {
   return t;
 }
 
+// the same value, opaque to the optimizer: arithmetic on it is not moved out
+// of the region that uses it (keeps loop-invariant address computations from
+// being hoisted out of the iteration loop and held in registers throughout)
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// value of v in lane l of the wave (l uniform)
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Row tiles of tall-skinny products on the matrix cores (v_mfma_f64_16x16x4f64:
+// lane l holds A[l%16][l/16] and B[l/16][l%16]; entry j of its result is row
+// l/16 + 4j, column l%16).  For rows r0..r0+15 of U (global, column-major,
+// ld d): acc0 += U[r0:r0+16, 0:nk] C0[0:nk, 0:16] and, when TWO, acc1 likewise
+// with C1; C0, C1 in LDS with rows ldc apart, columns from n0 (n1) on read as
+// zero, rows of U past d read as zero.
+template <bool TWO>
+__device__ __forceinline__ void tile_mul(const double *U, int d, int r0, int nk, const double *C0,
+                                         int n0, const double *C1, int n1, int ldc, v4d &acc0,
+                                         v4d &acc1) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+  const bool rv = r0 + i < d;
+  const double *u = U + r0 + i;
+#pragma unroll 4
+  for (int k = 0; k < nk; k += 4) {
+    const int kk = k + kq;
+    const bool kv = kk < nk;
+    const double a = (rv && kv) ? u[(int64_t)kk * d] : 0.0;
+    const double b0 = (kv && i < n0) ? C0[kk * ldc + i] : 0.0;
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+    if (TWO) {
+      const double b1 = (kv && i < n1) ? C1[kk * ldc + i] : 0.0;
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+    }
+  }
+}
+
+// Out[r0 + row, col] = acc (or -= acc when SUB) for the rows < d and columns
+// < ncol of the tile (Out column-major, ld d)
+template <bool SUB>
+__device__ __forceinline__ void tile_store(double *Out, int d, int r0, int ncol, const v4d &acc) {
+  const int lane = threadIdx.x & 63, c = lane & 15, rq = lane >> 4;
+  if (c >= ncol) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = r0 + rq + 4 * j;
+    if (row < d) {
+      double *o = Out + row + (int64_t)c * d;
+      *o = SUB ? *o - acc[j] : acc[j];
+    }
+  }
+}
+
 // Symmetric eigen-decomposition of the n x n matrix H (LDS, ld LOB_MAXB+1) by
 // parallel cyclic Jacobi (round-robin pairing): H <- diag, V <- eigenvectors.
+// A step applies the m/2 disjoint rotations of one round together: every
+// 2 x 2 block of H on the rows of one pair and the columns of another is
+// rotated on both sides by one thread, and each pair of V's columns likewise.
+// The blocks partition H, so each thread reads its entries and writes them
+// back with no other thread touching them in between.
 // Sweeps stop when every off-diagonal entry is below 1e-15 sqrt(|h_pp h_qq|)
 // (relative accuracy for semidefinite H) or below 1e-17 of the Frobenius norm
 // (rotations preserve it; smaller entries cannot move the eigenpairs), or the
 // off-diagonal mass is below 1e-30 of the total, or after 20 sweeps.
+// Launched with LOB_NT threads.
 __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1], int n,
                            double *cs, double *sn, double *red) {
   __shared__ int pp[LOB_MAXB / 2 + 1], qq[LOB_MAXB / 2 + 1];
-  const int tid = threadIdx.x;  // launched with 256 threads
-  for (int i = tid; i < n * n; i += blockDim.x) V[i % n][i / n] = (i % n == i / n) ? 1.0 : 0.0;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n * n; i += LOB_NT) V[i % n][i / n] = (i % n == i / n) ? 1.0 : 0.0;
   const int m = (n + 1) / 2 * 2;  // even number of players (a dummy when n is odd)
+  const int half = m / 2;
   // round-robin schedule: player 0 stays, the others move one place per step,
   // so at step t position i >= 1 holds player 1 + ((i - 1 - t) mod (m - 1))
   auto player = [m](int i, int t) {
@@ -201,12 +273,12 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
   };
   __syncthreads();
   double tot = 0;
-  for (int i = tid; i < n * n; i += blockDim.x) tot += H[i % n][i / n] * H[i % n][i / n];
+  for (int i = tid; i < n * n; i += LOB_NT) tot += H[i % n][i / n] * H[i % n][i / n];
   tot = block_sum(tot, red);
   const double floor_abs = 1e-17 * sqrt(tot);
   for (int sweep = 0; sweep < 20; ++sweep) {
     double off = 0, viol = 0;
-    for (int i = tid; i < n * n; i += blockDim.x) {
+    for (int i = tid; i < n * n; i += LOB_NT) {
       const int a = i % n, b = i / n;
       if (a == b) continue;
       const double h = H[a][b];
@@ -217,8 +289,9 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
     viol = block_sum(viol, red);
     if (viol == 0 || off <= 1e-30 * tot || tot == 0) break;
     for (int step = 0; step < m - 1; ++step) {
-      // the step's pairs (player(k), player(m-1-k)), k < m/2, and rotations
-      if (tid < m / 2) {
+      // the step's pairs (player(k), player(m-1-k)), k < m/2, and rotations;
+      // a pair with the dummy (q = n) keeps c = 1, s = 0
+      if (tid < half) {
         int p = player(tid, step), q = player(m - 1 - tid, step);
         if (p > q) {
           const int t = p;
@@ -238,191 +311,198 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
         sn[tid] = s;
       }
       __syncthreads();
-      // 256 threads: pair slot tid & 31, every 8th column / row from tid >> 5
-      const int k = tid & 31, g = tid >> 5;
-      const bool act = k < m / 2 && qq[min(k, m / 2 - 1)] < n;
-      const int p = act ? pp[k] : 0, q = act ? qq[k] : 0;
-      const double c = act ? cs[k] : 1.0, s = act ? sn[k] : 0.0;
-      // rows: H <- J^T H
-      if (act)
-        for (int col = g; col < n; col += 8) {
-          const double hp = H[p][col], hq = H[q][col];
-          H[p][col] = c * hp - s * hq;
-          H[q][col] = s * hp + c * hq;
+      double hb[JAC_NB][4], vb[JAC_NV][2];
+#pragma unroll
+      for (int u = 0; u < JAC_NB; ++u) {
+        const int e = tid + u * LOB_NT;
+        if (e < half * half) {
+          const int pk = pp[e % half], qk = qq[e % half], pl = pp[e / half], ql = qq[e / half];
+          hb[u][0] = H[pk][pl];
+          hb[u][1] = ql < n ? H[pk][ql] : 0.0;
+          hb[u][2] = qk < n ? H[qk][pl] : 0.0;
+          hb[u][3] = (qk < n && ql < n) ? H[qk][ql] : 0.0;
         }
-      __syncthreads();
-      // columns: H <- H J, V <- V J
-      if (act)
-        for (int row = g; row < n; row += 8) {
-          const double hp = H[row][p], hq = H[row][q];
-          H[row][p] = c * hp - s * hq;
-          H[row][q] = s * hp + c * hq;
-          const double vp = V[row][p], vq = V[row][q];
-          V[row][p] = c * vp - s * vq;
-          V[row][q] = s * vp + c * vq;
+      }
+#pragma unroll
+      for (int u = 0; u < JAC_NV; ++u) {
+        const int e = tid + u * LOB_NT;
+        if (e < n * half) {
+          const int row = e % n, pl = pp[e / n], ql = qq[e / n];
+          vb[u][0] = V[row][pl];
+          vb[u][1] = ql < n ? V[row][ql] : 0.0;
         }
+      }
+#pragma unroll
+      for (int u = 0; u < JAC_NB; ++u) {
+        const int e = tid + u * LOB_NT;
+        if (e < half * half) {
+          const int k = e % half, l = e / half;
+          const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
+          const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+          // rows (J_k^T B), then columns (. J_l)
+          const double rpp = ck * hb[u][0] - sk * hb[u][2], rpq = ck * hb[u][1] - sk * hb[u][3];
+          const double rqp = sk * hb[u][0] + ck * hb[u][2], rqq = sk * hb[u][1] + ck * hb[u][3];
+          H[pk][pl] = cl * rpp - sl * rpq;
+          if (ql < n) H[pk][ql] = sl * rpp + cl * rpq;
+          if (qk < n) H[qk][pl] = cl * rqp - sl * rqq;
+          if (qk < n && ql < n) H[qk][ql] = sl * rqp + cl * rqq;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < JAC_NV; ++u) {
+        const int e = tid + u * LOB_NT;
+        if (e < n * half) {
+          const int row = e % n, l = e / n;
+          const int pl = pp[l], ql = qq[l];
+          const double cl = cs[l], sl = sn[l];
+          V[row][pl] = cl * vb[u][0] - sl * vb[u][1];
+          if (ql < n) V[row][ql] = sl * vb[u][0] + cl * vb[u][1];
+        }
+      }
       __syncthreads();
     }
   }
 }
 
-// One work-group per entry.  The basis V = [X W P] is kept orthonormal
+// One work-group per entry.  The basis V = [X P W] is kept orthonormal
 // explicitly: W (the residuals) is orthogonalized against X and P by two
-// passes of block Gram-Schmidt, P (the W and P part of the new Ritz vectors)
-// against the new X, and each block is orthonormalized by the scaled
-// eigen-decomposition of its Gram matrix (columns of a near-dependent block
-// are dropped).  The Rayleigh-Ritz step is then the standard symmetric problem
-// V^T A V, solved in LDS by Jacobi rotations.  Blocks live in global memory;
-// every update of a block is row-owned (one thread writes a whole row), so
-// blocks are updated in place.
-__global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc *desc,
-                                                     LobOut *out, int maxit, double tol,
-                                                     double tol_ind) {
+// passes of block Gram-Schmidt and orthonormalized by Cholesky QR (or, for a
+// near-dependent block, by the scaled eigen-decomposition of its Gram matrix,
+// which drops columns).  The Rayleigh-Ritz step is the standard symmetric
+// problem V^T A V, solved in LDS by Jacobi rotations; the new P is formed in
+// coefficient space (its coefficients orthonormalized against those of the
+// new X), so X and P leave the update already orthonormal.  Block products
+// U^T V run on the matrix cores.  Blocks live in global memory; every update
+// of a block is row-owned (one thread writes a whole row), so blocks are
+// updated in place.
+__global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobDesc *desc,
+                                                        LobOut *out, int maxit, double tol,
+                                                        double tol_ind) {
   __shared__ double Hs[LOB_MAXB][LOB_MAXB + 1];  // projected / Gram matrices
   __shared__ double Qs[LOB_MAXB][LOB_MAXB + 1];  // their eigenvectors
-  __shared__ double Cs[LOB_MAXB][2 * LOB_S + 1]; // Ritz coefficients (X part, P part)
-  __shared__ double Ms[LOB_S][LOB_S + 1];        // orthonormalizing map of a block
-  __shared__ double stage[STAGE_ROWS * LOB_S];    // staged rows, or locked coefficients
+  __shared__ __align__(16) double Cs[LOB_MAXB][2 * LOB_S];  // Ritz coefficients (X part, P part)
+  __shared__ __align__(16) double Ms[LOB_S][LOB_S];         // orthonormalizing map of a block
+  __shared__ __align__(16) double stage[STAGE_ROWS * LOB_S];  // staged rows, or locked coefficients
   __shared__ double su[DOT_ROWS][LOB_MAXB + 1];   // row chunks of block products
   __shared__ double sv[DOT_ROWS][LOB_MAXB + 1];
   __shared__ double theta[LOB_MAXB], gsc[LOB_MAXB], dinv[LOB_MAXB], res[LOB_S];
-  __shared__ double cs[LOB_MAXB / 2 + 1], sn[LOB_MAXB / 2 + 1], red[8];
+  __shared__ double cs[LOB_MAXB / 2 + 1], sn[LOB_MAXB / 2 + 1], red[LOB_NWAVE];
   __shared__ int perm[LOB_MAXB + 2];
   __shared__ int s_keep, s_done;
   const LobDesc D = desc[blockIdx.x];
-  const int d = D.d, s = D.s, tid = threadIdx.x, nt = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+  const int d_ = D.d, d = d_, s = D.s, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const double *A = pool + D.a_off;
-  double *X = pool + D.v_off, *AX = X + (int64_t)d * s, *W = AX + (int64_t)d * s;
-  double *AW = W + (int64_t)d * s, *P = AW + (int64_t)d * s, *AP = P + (int64_t)d * s;
+  // V = [X P W] and A V, each with contiguous columns: X (s columns), P (npc),
+  // then W (nw), so that [X P] and V are plain column blocks
+  double *V = pool + D.v_off, *AV = V + (int64_t)3 * d * s;
+  double *X = V, *AX = AV, *P = V + (int64_t)d * s, *AP = AV + (int64_t)d * s;
   double *T1 = pool + D.t_off;
   const double *YL = pool + D.lock_off;
   const int nl = D.nl;
   int nw = 0, npc = 0;  // columns held in W and P
+  double *W = P, *AW = AP;  // W follows the npc columns of P
   long long ticks[4] = {0, 0, 0, 0};  // phase timing (see LobOut)
 
-  // o[a * ldo + b] = U[:, a] . V[:, b]  (one wave per entry)
-  auto dots = [&](const double *U, int nu, const double *V, int nv, double *o, int ldo) {
-    for (int i = wave; i < nu * nv; i += nwave) {
-      const int a = i % nu, b = i / nu;
-      const double *u = U + (int64_t)a * d, *v = V + (int64_t)b * d;
-      double acc = 0;
-      for (int r = lane; r < d; r += 64) acc += u[r] * v[r];
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-      if (lane == 0) o[a * ldo + b] = acc;
-    }
-    __syncthreads();
-  };
   // o[a * ldo + b] = u_a . v_b for nu, nv <= LOB_MAXB columns given by
-  // accessors: the rows go through LDS in chunks, each thread owns a few
-  // entries and sums them in row order (no atomics, fixed order)
-  auto block_dot = [&](auto ucol, int nu, auto vcol2, int nv, double *o, int ldo) {
-    const int ne = nu * nv;
-    double acc[DOT_PER_THREAD];
+  // accessors: chunks of DOT_ROWS rows are staged in LDS (the next chunk
+  // loaded into registers while the current one is multiplied) and each wave
+  // accumulates up to two 16 x 16 tiles of U^T V with v_mfma_f64_16x16x4f64,
+  // always in the same order
+  auto block_dot = [&](const double *U, int nu, const double *Vb, int nv, double *o, int ldo) {
+    const int d = opaque(d_);
+    const int tu = (nu + 15) >> 4, tv = (nv + 15) >> 4, ntile = tu * tv;
+    const int cu = 16 * tu, ncol = cu + 16 * tv;  // staged columns (zero past nu, nv)
+    // thread: row `lane` of the chunk, columns wave + LOB_NWAVE q (uniform per wave)
+    double pre[DOT_LD];
+    auto fetch = [&](int c0) {
+      const int r = c0 + lane;
 #pragma unroll
-    for (int q = 0; q < DOT_PER_THREAD; ++q) acc[q] = 0;
+      for (int q = 0; q < DOT_LD; ++q) {
+        const int j = wave + LOB_NWAVE * q;
+        double v = 0;
+        if (r < d) {
+          if (j < cu) {
+            if (j < nu) v = U[r + (int64_t)j * d];
+          } else if (j < ncol && j - cu < nv) {
+            v = Vb[r + (int64_t)(j - cu) * d];
+          }
+        }
+        pre[q] = v;
+      }
+    };
+    v4d acc[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
     for (int c0 = 0; c0 < d; c0 += DOT_ROWS) {
-      const int cn = min(DOT_ROWS, d - c0);
+      __syncthreads();  // the previous chunk's reads of su, sv are done
+#pragma unroll
+      for (int q = 0; q < DOT_LD; ++q) {
+        const int j = wave + LOB_NWAVE * q;
+        if (j < cu)
+          su[lane][j] = pre[q];
+        else if (j < ncol)
+          sv[lane][j - cu] = pre[q];
+      }
       __syncthreads();
-      for (int i = tid; i < DOT_ROWS * nu; i += nt) {
-        const int r = i % DOT_ROWS, a = i / DOT_ROWS;
-        su[r][a] = r < cn ? ucol(a)[c0 + r] : 0.0;
-      }
-      for (int i = tid; i < DOT_ROWS * nv; i += nt) {
-        const int r = i % DOT_ROWS, b = i / DOT_ROWS;
-        sv[r][b] = r < cn ? vcol2(b)[c0 + r] : 0.0;
-      }
-      __syncthreads();
+      if (c0 + DOT_ROWS < d) fetch(c0 + DOT_ROWS);
+      const int kn = min(DOT_ROWS, d - c0);  // rows past kn are zero
 #pragma unroll
-      for (int q = 0; q < DOT_PER_THREAD; ++q) {
-        const int e = tid + q * nt;
-        if (e < ne) {
-          const int a = e % nu, b = e / nu;
-          double t = 0;
-          for (int r = 0; r < cn; ++r) t += su[r][a] * sv[r][b];
-          acc[q] += t;
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < DOT_PER_THREAD; ++q) {
-      const int e = tid + q * nt;
-      if (e < ne) o[(e % nu) * ldo + e / nu] = acc[q];
-    }
-    __syncthreads();
-  };
-  auto cols = [d](const double *base) {
-    return [base, d](int a) { return base + (int64_t)a * d; };
-  };
-  // V[:, b] -= sum_a U[:, a] c[a * ldc + b] for b < nv (AV -= AU c alongside)
-  auto sub_prod = [&](double *V, double *AV, int nv, const double *U, const double *AU, int nu,
-                      const double *c, int ldc) {
-    for (int r = tid; r < d; r += nt) {
-      double acc[LOB_S], aacc[LOB_S];
-#pragma unroll
-      for (int q = 0; q < LOB_S; ++q) acc[q] = aacc[q] = 0;
-      // eight columns of U (and A U) loaded per batch
-      for (int a0 = 0; a0 < nu; a0 += 8) {
-        double u8[8], au8[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          u8[t] = a0 + t < nu ? U[r + (int64_t)(a0 + t) * d] : 0.0;
-          au8[t] = (AV && a0 + t < nu) ? AU[r + (int64_t)(a0 + t) * d] : 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          if (a0 + t >= nu) break;
-          const double *ca = c + (a0 + t) * ldc;
-#pragma unroll
-          for (int q = 0; q < LOB_S; ++q) {
-            if (q < nv) {
-              acc[q] += u8[t] * ca[q];
-              aacc[q] += au8[t] * ca[q];
-            }
+      for (int t = 0; t < 2; ++t) {
+        const int tile = wave + t * LOB_NWAVE;
+        if (tile < ntile) {
+          const int a0 = (tile % tu) * 16 + (lane & 15), b0 = (tile / tu) * 16 + (lane & 15);
+          for (int kk = 0; kk < kn; kk += 4) {
+            const int k = kk + (lane >> 4);
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(su[k][a0], sv[k][b0], acc[t], 0, 0, 0);
           }
         }
       }
+    }
 #pragma unroll
-      for (int q = 0; q < LOB_S; ++q) {
-        if (q < nv) {
-          V[r + (int64_t)q * d] -= acc[q];
-          if (AV) AV[r + (int64_t)q * d] -= aacc[q];
+    for (int t = 0; t < 2; ++t) {
+      const int tile = wave + t * LOB_NWAVE;
+      if (tile < ntile) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int a = (tile % tu) * 16 + (lane >> 4) + 4 * j, b = (tile / tu) * 16 + (lane & 15);
+          if (a < nu && b < nv) o[a * ldo + b] = acc[t][j];
         }
       }
     }
     __syncthreads();
   };
-  // V[:, 0..kp) = V[:, 0..nv) M  (M in Ms)
-  auto right_mul = [&](double *V, int nv, int kp) {
-    for (int r = tid; r < d; r += nt) {
-      double acc[LOB_S], vr[LOB_S];
-#pragma unroll
-      for (int q = 0; q < LOB_S; ++q) acc[q] = 0;
-#pragma unroll
-      for (int b = 0; b < LOB_S; ++b) vr[b] = b < nv ? V[r + (int64_t)b * d] : 0.0;
-#pragma unroll
-      for (int b = 0; b < LOB_S; ++b) {
-        if (b >= nv) break;
-        const double v = vr[b];
-#pragma unroll
-        for (int q = 0; q < LOB_S; ++q)
-          if (q < kp) acc[q] += v * Ms[b][q];
-      }
-#pragma unroll
-      for (int q = 0; q < LOB_S; ++q)
-        if (q < kp) V[r + (int64_t)q * d] = acc[q];
+  const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
+  // V[:, b] -= sum_a U[:, a] c[a * ldc + b] for b < nv (c in LDS); one wave
+  // per 16-row tile
+  auto sub_prod = [&](double *V, int nv, const double *U, int nu, const double *c, int ldc) {
+    const int d = opaque(d_);
+    for (int r0 = 16 * wave; r0 < d; r0 += 16 * LOB_NWAVE) {
+      v4d acc = zero4, unused = zero4;
+      tile_mul<false>(U, d, r0, nu, c, nv, nullptr, 0, ldc, acc, unused);
+      tile_store<true>(V, d, r0, nv, acc);
     }
     __syncthreads();
   };
-  // orthonormalize the nv columns of V (AV alongside when given): with
-  // Dg = diag(G)^-1/2, Dg G Dg = Q diag(g) Q^T, V <- V Dg Q g^-1/2 over g > thr.
-  // Returns the number of columns kept.
-  auto svqb = [&](double *V, double *AV, int nv, double thr) -> int {
-    if (nv == 0) return 0;
-    block_dot(cols(V), nv, cols(V), nv, &Hs[0][0], LOB_MAXB + 1);
-    for (int a = tid; a < nv; a += nt) dinv[a] = Hs[a][a] > 0 ? 1.0 / sqrt(Hs[a][a]) : 0.0;
+  // V[:, 0..kp) = V[:, 0..nv) M  (M in Ms), in place: each wave reads its
+  // rows before writing them
+  auto right_mul = [&](double *V, int nv, int kp) {
+    const int d = opaque(d_);
+    for (int r0 = 16 * wave; r0 < d; r0 += 16 * LOB_NWAVE) {
+      v4d acc = zero4, unused = zero4;
+      tile_mul<false>(V, d, r0, nv, &Ms[0][0], kp, nullptr, 0, LOB_S, acc, unused);
+      tile_store<false>(V, d, r0, kp, acc);
+    }
     __syncthreads();
-    for (int i = tid; i < nv * nv; i += nt) {
+  };
+  // Gram matrix G (nv x nv, in Hs) -> Ms = Dg Q g^-1/2 over the eigenvalues
+  // g > thr of Dg G Dg = Q diag(g) Q^T, Dg = diag(G)^-1/2 (so that the
+  // columns times Ms are orthonormal).  Returns the number of columns kept.
+  auto gram_eig = [&](int nv, double thr) -> int {
+    for (int a = tid; a < nv; a += LOB_NT) dinv[a] = Hs[a][a] > 0 ? 1.0 / sqrt(Hs[a][a]) : 0.0;
+    __syncthreads();
+    for (int i = tid; i < nv * nv; i += LOB_NT) {
       const int a = i % nv, b = i / nv;
       Hs[a][b] *= dinv[a] * dinv[b];
     }
@@ -440,121 +520,120 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
     }
     __syncthreads();
     const int kp = s_keep;
-    for (int i = tid; i < nv * kp; i += nt) {
+    for (int i = tid; i < nv * kp; i += LOB_NT) {
       const int b = i % nv, q = i / nv;
       Ms[b][q] = dinv[b] * Qs[b][perm[q]] * gsc[q];
     }
     __syncthreads();
-    right_mul(V, nv, kp);
-    if (AV) right_mul(AV, nv, kp);
     return kp;
   };
-  // orthonormalization of a well-conditioned block: V <- V L^-T with
-  // V^T V = L L^T (Cholesky in LDS).  Returns false (V untouched) if a pivot
-  // falls below 1e-8 of its diagonal entry (condition above 1e4: the caller
-  // then uses the eigen-decomposition, which drops dependent columns).
-  auto cholqr = [&](double *V, double *AV, int nv) -> bool {
+  // Gram matrix G = L L^T (nv <= LOB_S, in Hs) -> Ms = L^-T.  The Cholesky
+  // factorization runs in wave 0 with row i of G in the registers of lane i,
+  // column by column; lane j then forms column j of L^-1.  Returns false when a
+  // pivot falls below 1e-8 of its diagonal entry (condition above 1e4: the
+  // caller then uses gram_eig).
+  auto chol_inv = [&](int nv) -> bool {
+    if (wave == 0) {
+      double g[LOB_S];
+#pragma unroll
+      for (int k = 0; k < LOB_S; ++k) g[k] = (lane < nv && k < nv) ? Hs[lane][k] : 0.0;
+      bool ok = true;
+#pragma unroll
+      for (int j = 0; j < LOB_S; ++j) {
+        if (j < nv) {
+          const double djj = lane_value(g[j], j);
+          ok = ok && djj > 1e-8 * Hs[j][j];
+          const double r = ok ? sqrt(djj) : 1.0;
+          g[j] = lane == j ? r : (lane > j ? g[j] / r : 0.0);
+#pragma unroll
+          for (int k = j + 1; k < LOB_S; ++k)
+            if (k < nv) {
+              const double lkj = lane_value(g[j], k);
+              if (lane >= k) g[k] -= g[j] * lkj;
+            }
+        }
+      }
+      if (ok) {
+        double y[LOB_S];  // column `lane` of L^-1
+#pragma unroll
+        for (int i = 0; i < LOB_S; ++i) {
+          double acc = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+          for (int mm = 0; mm < i; ++mm) acc -= lane_value(g[mm], i) * y[mm];
+          y[i] = i < nv ? acc / lane_value(g[i], i) : 0.0;
+        }
+        if (lane < nv)
+#pragma unroll
+          for (int q = 0; q < LOB_S; ++q)
+            if (q < nv) Ms[lane][q] = y[q];  // (L^-T)[lane][q] = (L^-1)[q][lane]
+      }
+      if (lane == 0) s_keep = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return s_keep != 0;
+  };
+  // orthonormalize the nv columns of V by the eigen-decomposition of their
+  // Gram matrix (dependent columns dropped); returns the number kept
+  auto svqb = [&](double *V, int nv, double thr) -> int {
+    if (nv == 0) return 0;
+    block_dot(V, nv, V, nv, &Hs[0][0], LOB_MAXB + 1);
+    const int kp = gram_eig(nv, thr);
+    right_mul(V, nv, kp);
+    return kp;
+  };
+  // V <- V L^-T with V^T V = L L^T; false (V untouched) if ill-conditioned
+  auto cholqr = [&](double *V, int nv) -> bool {
     if (nv == 0) return true;
-    block_dot(cols(V), nv, cols(V), nv, &Hs[0][0], LOB_MAXB + 1);
-    if (tid == 0) {
-      int ok = 1;
-      for (int j = 0; j < nv && ok; ++j) {
-        double dj = Hs[j][j];
-        for (int k = 0; k < j; ++k) dj -= Hs[j][k] * Hs[j][k];
-        if (!(dj > 1e-8 * Hs[j][j])) {
-          ok = 0;
-          break;
-        }
-        dj = sqrt(dj);
-        Hs[j][j] = dj;
-        for (int i = j + 1; i < nv; ++i) {
-          double v = Hs[i][j];
-          for (int k = 0; k < j; ++k) v -= Hs[i][k] * Hs[j][k];
-          Hs[i][j] = v / dj;
-        }
-      }
-      s_keep = ok;
-    }
-    __syncthreads();
-    if (!s_keep) return false;
-    // columns of L^-1 (thread j), then Ms = L^-T
-    if (tid < nv) {
-      const int j = tid;
-      for (int i = 0; i < nv; ++i) Qs[i][j] = 0.0;
-      for (int i = j; i < nv; ++i) {
-        double y = (i == j) ? 1.0 : 0.0;
-        for (int m = j; m < i; ++m) y -= Hs[i][m] * Qs[m][j];
-        Qs[i][j] = y / Hs[i][i];
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < nv * nv; i += nt) {
-      const int b = i % nv, q = i / nv;
-      Ms[b][q] = q >= b ? Qs[q][b] : 0.0;
-    }
-    __syncthreads();
+    block_dot(V, nv, V, nv, &Hs[0][0], LOB_MAXB + 1);
+    if (!chol_inv(nv)) return false;
     right_mul(V, nv, nv);
-    if (AV) right_mul(AV, nv, nv);
     return true;
   };
   // V <- V - YL (YL^T V): keep a block orthogonal to the locked vectors
   auto project_locked = [&](double *V, int nv) {
     if (nl == 0 || nv == 0) return;
-    dots(YL, nl, V, nv, stage, LOB_S);
-    sub_prod(V, nullptr, nv, YL, nullptr, nl, stage, LOB_S);
+    for (int a0 = 0; a0 < nl; a0 += LOB_MAXB)
+      block_dot(YL + (int64_t)a0 * d, min(LOB_MAXB, nl - a0), V, nv, stage + a0 * LOB_S, LOB_S);
+    sub_prod(V, nv, YL, nl, stage, LOB_S);
   };
-  // AV = A V for nv columns; V staged through LDS in chunks of rows
-  auto apply_A = [&](const double *V, double *AV, int nv) {
-    for (int r0 = 0; r0 < d; r0 += nt) {
-      const int r = r0 + tid;
-      double acc[LOB_S];
-#pragma unroll
-      for (int q = 0; q < LOB_S; ++q) acc[q] = 0;
+  // AV = A V for nv columns: V staged through LDS in chunks of STAGE_ROWS
+  // rows, each wave accumulating up to four 16-row tiles of A V
+  auto apply_A = [&](const double *Vin, double *AVo, int nv) {
+    const int d = opaque(d_);
+    const int nrt = (d + 15) >> 4;
+    for (int tg = 0; tg < nrt; tg += 4 * LOB_NWAVE) {
+      v4d acc[4] = {zero4, zero4, zero4, zero4}, unused = zero4;
       for (int c0 = 0; c0 < d; c0 += STAGE_ROWS) {
         const int cn = min(STAGE_ROWS, d - c0);
         __syncthreads();
-        for (int i = tid; i < cn * LOB_S; i += nt) {
+        for (int i = tid; i < cn * LOB_S; i += LOB_NT) {
           const int c = i % cn, q = i / cn;
-          stage[c * LOB_S + q] = q < nv ? V[c0 + c + (int64_t)q * d] : 0.0;
+          stage[c * LOB_S + q] = q < nv ? Vin[c0 + c + (int64_t)q * d] : 0.0;
         }
         __syncthreads();
-        if (r < d) {
-          // eight loads of A in flight per thread
-          for (int c = 0; c < cn; c += 8) {
-            double a8[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a8[u] = c + u < cn ? A[r + (int64_t)(c0 + c + u) * d] : 0.0;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              if (c + u < cn) {
-#pragma unroll
-                for (int q = 0; q < LOB_S; ++q) acc[q] += a8[u] * stage[(c + u) * LOB_S + q];
-              }
-            }
-          }
+        for (int t = 0; t < 4; ++t) {
+          const int tile = tg + wave + LOB_NWAVE * t;
+          if (tile < nrt)
+            tile_mul<false>(A + (int64_t)c0 * d, d, 16 * tile, cn, stage, nv, nullptr, 0, LOB_S,
+                            acc[t], unused);
         }
       }
-      if (r < d)
-        for (int q = 0; q < nv; ++q) AV[r + (int64_t)q * d] = acc[q];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int tile = tg + wave + LOB_NWAVE * t;
+        if (tile < nrt) tile_store<false>(AVo, d, 16 * tile, nv, acc[t]);
+      }
     }
     __syncthreads();
   };
-  // column b of V = [X W P] and of A V
-  auto vcol = [&](int b) -> const double * {
-    return b < s ? X + (int64_t)b * d
-                 : (b < s + nw ? W + (int64_t)(b - s) * d : P + (int64_t)(b - s - nw) * d);
-  };
-  auto avcol = [&](int b) -> const double * {
-    return b < s ? AX + (int64_t)b * d
-                 : (b < s + nw ? AW + (int64_t)(b - s) * d : AP + (int64_t)(b - s - nw) * d);
-  };
-  // Rayleigh-Ritz on the current n = s + nw + npc columns: theta, and the
-  // coefficients of the new X (Cs[:, 0..s)) and of the new P (Cs[:, s..2s):
+  // Rayleigh-Ritz on the current n = s + npc + nw columns: theta, and the
+  // coefficients of the new X (Cs[:, 0..s)) and of the new P (Cs[:, LOB_S..):
   // the same vectors without their X rows)
   auto rayleigh_ritz = [&](int n) {
     // H = V^T A V, symmetrized
-    block_dot(vcol, n, avcol, n, &Hs[0][0], LOB_MAXB + 1);
-    for (int i = tid; i < n * n; i += nt) {
+    block_dot(V, n, AV, n, &Hs[0][0], LOB_MAXB + 1);
+    for (int i = tid; i < n * n; i += LOB_NT) {
       const int a = i % n, b = i / n;
       if (a < b) {
         const double h = 0.5 * (Hs[a][b] + Hs[b][a]);
@@ -565,19 +644,21 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
     const long long tj = wall_clock64();
     jacobi_eig(Hs, Qs, n, cs, sn, red);
     ticks[3] += wall_clock64() - tj;
-    if (tid == 0) {
-      for (int a = 0; a < n; ++a) perm[a] = a;
-      for (int a = 0; a < s; ++a)
-        for (int b = a + 1; b < n; ++b)
-          if (Hs[perm[b]][perm[b]] > Hs[perm[a]][perm[a]]) {
-            const int t = perm[a];
-            perm[a] = perm[b];
-            perm[b] = t;
-          }
-      for (int q = 0; q < s; ++q) theta[q] = Hs[perm[q]][perm[q]];
+    // the s largest eigenvalues, descending (ties by index; NaN last)
+    for (int a = tid; a < n; a += LOB_NT) {
+      const double la = isnan(Hs[a][a]) ? -INFINITY : Hs[a][a];
+      int rank = 0;
+      for (int b = 0; b < n; ++b) {
+        const double lb = isnan(Hs[b][b]) ? -INFINITY : Hs[b][b];
+        rank += (lb > la || (lb == la && b < a)) ? 1 : 0;
+      }
+      if (rank < s) {
+        perm[rank] = a;
+        theta[rank] = Hs[a][a];
+      }
     }
     __syncthreads();
-    for (int i = tid; i < n * s; i += nt) {
+    for (int i = tid; i < n * s; i += LOB_NT) {
       const int b = i % n, q = i / n;
       const double c = Qs[b][perm[q]];
       Cs[b][q] = c;
@@ -585,43 +666,71 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
     }
     __syncthreads();
   };
-  // X <- V Cx, P <- V Cp and their images (row-owned, in place)
-  auto ritz_update = [&](int n, bool with_p) {
+  // P coefficients (Cs[:, LOB_S..)) made orthogonal to the X coefficients
+  // (orthonormal) by two Gram-Schmidt passes, then orthonormal; returns the
+  // number of P columns kept
+  auto orth_pcoef = [&](int n) -> int {
     for (int pass = 0; pass < 2; ++pass) {
-      double *XO = pass ? AX : X, *PO = pass ? AP : P;
-      for (int r = tid; r < d; r += nt) {
-        double ax[LOB_S], ap[LOB_S];
-#pragma unroll
-        for (int q = 0; q < LOB_S; ++q) ax[q] = ap[q] = 0;
-        for (int b = 0; b < n; ++b) {
-          const double v = (pass ? avcol(b) : vcol(b))[r];
-#pragma unroll
-          for (int q = 0; q < LOB_S; ++q) {
-            ax[q] += v * Cs[b][q];
-            ap[q] += v * Cs[b][LOB_S + q];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < LOB_S; ++q) {
-          if (q < s) {
-            XO[r + (int64_t)q * d] = ax[q];
-            if (with_p) PO[r + (int64_t)q * d] = ap[q];
-          }
-        }
+      for (int i = tid; i < s * s; i += LOB_NT) {
+        const int a = i % s, q = i / s;
+        double t = 0;
+        for (int b = 0; b < n; ++b) t += Cs[b][a] * Cs[b][LOB_S + q];
+        Ms[a][q] = t;
+      }
+      __syncthreads();
+      for (int i = tid; i < n * s; i += LOB_NT) {
+        const int b = i % n, q = i / n;
+        double t = 0;
+        for (int a = 0; a < s; ++a) t += Cs[b][a] * Ms[a][q];
+        Cs[b][LOB_S + q] -= t;
       }
       __syncthreads();
     }
+    for (int i = tid; i < s * s; i += LOB_NT) {
+      const int a = i % s, q = i / s;
+      double t = 0;
+      for (int b = 0; b < n; ++b) t += Cs[b][LOB_S + a] * Cs[b][LOB_S + q];
+      Hs[a][q] = t;
+    }
+    __syncthreads();
+    const int kp = chol_inv(s) ? s : gram_eig(s, 1e-10);
+    // Cp <- Cp Ms through Qs (free once the Ritz coefficients are in Cs)
+    for (int i = tid; i < n * kp; i += LOB_NT) {
+      const int b = i % n, q = i / n;
+      double t = 0;
+      for (int a = 0; a < s; ++a) t += Cs[b][LOB_S + a] * Ms[a][q];
+      Qs[b][q] = t;
+    }
+    __syncthreads();
+    for (int i = tid; i < n * kp; i += LOB_NT) Cs[i % n][LOB_S + i / n] = Qs[i % n][i / n];
+    __syncthreads();
+    return kp;
+  };
+  // X <- V Cx, P <- V Cp (kp columns) and their images, in place: each wave
+  // reads all columns of its rows before writing them
+  auto ritz_update = [&](int n, int kp) {
+    const int d = opaque(d_);
+    for (int pass = 0; pass < 2; ++pass) {
+      double *B = pass ? AV : V;
+      for (int r0 = 16 * wave; r0 < d; r0 += 16 * LOB_NWAVE) {
+        v4d ax = zero4, ap = zero4;
+        tile_mul<true>(B, d, r0, n, &Cs[0][0], s, &Cs[0][LOB_S], kp, 2 * LOB_S, ax, ap);
+        tile_store<false>(B, d, r0, s, ax);
+        tile_store<false>(B + (int64_t)s * d, d, r0, kp, ap);
+      }
+    }
+    __syncthreads();
   };
 
   int it = 0, nconv = 0;
   bool done = false;
-  for (int q = tid; q < LOB_MAXB; q += nt) theta[q] = 0;
+  for (int q = tid; q < LOB_MAXB; q += LOB_NT) theta[q] = 0;
   __syncthreads();
   // start block: orthonormal and orthogonal to the locked vectors
   int kx = s;
   for (int pass = 0; pass < 2 && kx == s; ++pass) {
     project_locked(X, s);
-    if (pass == 0 || !cholqr(X, nullptr, s)) kx = svqb(X, nullptr, s, 1e-10);
+    if (pass == 0 || !cholqr(X, s)) kx = svqb(X, s, 1e-10);
   }
   if (kx == s) {
     long long t0 = wall_clock64();
@@ -630,14 +739,16 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
     t0 = wall_clock64();
     rayleigh_ritz(s);
     ticks[2] += wall_clock64() - t0;
-    ritz_update(s, false);
+    ritz_update(s, 0);
   }
   for (it = 1; it <= maxit && kx == s; ++it) {
     // residuals W = A X - X theta and their norms
-    for (int i = tid; i < d * s; i += nt) W[i] = AX[i] - X[i] * theta[i / d];
+    W = P + (int64_t)npc * d;
+    AW = AP + (int64_t)npc * d;
+    for (int i = tid; i < d * s; i += LOB_NT) W[i] = AX[i] - X[i] * theta[i / d];
     __syncthreads();
     project_locked(W, s);
-    for (int q = wave; q < s; q += nwave) {
+    for (int q = wave; q < s; q += LOB_NWAVE) {
       double acc = 0;
       for (int r = lane; r < d; r += 64) acc += W[r + (int64_t)q * d] * W[r + (int64_t)q * d];
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -664,43 +775,34 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
       break;
     }
     if (it == maxit) break;
-    // search directions: unit residuals, orthonormal and orthogonal to X, P
-    for (int i = tid; i < d * s; i += nt) {
+    // search directions: unit residuals, orthogonal to X and P, orthonormal
+    for (int i = tid; i < d * s; i += LOB_NT) {
       const int q = i / d;
       W[i] = res[q] > 0 ? W[i] / res[q] : 0.0;
     }
     __syncthreads();
     long long to = wall_clock64();
     nw = s;
-    for (int pass = 0; pass < 2 && nw > 0; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
       project_locked(W, nw);
-      block_dot(cols(X), s, cols(W), nw, &Cs[0][0], 2 * LOB_S + 1);
-      sub_prod(W, nullptr, nw, X, nullptr, s, &Cs[0][0], 2 * LOB_S + 1);
-      if (npc > 0) {
-        block_dot(cols(P), npc, cols(W), nw, &Cs[0][0], 2 * LOB_S + 1);
-        sub_prod(W, nullptr, nw, P, nullptr, npc, &Cs[0][0], 2 * LOB_S + 1);
-      }
-      if (!cholqr(W, nullptr, nw)) nw = svqb(W, nullptr, nw, 1e-10);
+      block_dot(X, s + npc, W, nw, &Cs[0][0], 2 * LOB_S);
+      sub_prod(W, nw, X, s + npc, &Cs[0][0], 2 * LOB_S);
     }
+    if (!cholqr(W, nw)) nw = svqb(W, nw, 1e-10);
     ticks[1] += wall_clock64() - to;
     if (nw == 0 && npc == 0) break;  // no direction left: stagnation
     long long t1 = wall_clock64();
     apply_A(W, AW, nw);
     ticks[0] += wall_clock64() - t1;
-    const int n = s + nw + npc;
+    const int n = s + npc + nw;
     t1 = wall_clock64();
     rayleigh_ritz(n);
     ticks[2] += wall_clock64() - t1;
-    ritz_update(n, true);
-    // P: orthogonal to the new X, orthonormal
     to = wall_clock64();
-    npc = s;
-    for (int pass = 0; pass < 2 && npc > 0; ++pass) {
-      block_dot(cols(X), s, cols(P), npc, &Cs[0][0], 2 * LOB_S + 1);
-      sub_prod(P, AP, npc, X, AX, s, &Cs[0][0], 2 * LOB_S + 1);
-      if (!cholqr(P, AP, npc)) npc = svqb(P, AP, npc, 1e-10);
-    }
+    const int kp = orth_pcoef(n);
     ticks[1] += wall_clock64() - to;
+    ritz_update(n, kp);
+    npc = kp;
     nw = 0;
   }
   if (tid == 0) {
@@ -711,7 +813,7 @@ __global__ __launch_bounds__(256) void lobpcg_kernel(double *pool, const LobDesc
   }
   // eigenvalues into the first column of T1 for the host
   __syncthreads();
-  for (int q = tid; q < s; q += nt) T1[q] = theta[q];
+  for (int q = tid; q < s; q += LOB_NT) T1[q] = theta[q];
 }
 
 }  // namespace
@@ -1199,7 +1301,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
     HIPCHK(hipMemcpyAsync(ldb.p, lda.data(), sizeof(LobDesc) * na, hipMemcpyHostToDevice, stream));
     {
       LaunchScope ls(stream, "lobpcg_kernel", 0, 0);
-      lobpcg_kernel<<<na, 256, 0, stream>>>(LP, ldb.as<LobDesc>(), outb.as<LobOut>(), maxit, tol,
+      lobpcg_kernel<<<na, LOB_NT, 0, stream>>>(LP, ldb.as<LobDesc>(), outb.as<LobOut>(), maxit, tol,
                                             tol_ind);
       HIPCHK(hipGetLastError());
     }

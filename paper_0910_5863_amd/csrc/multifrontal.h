@@ -92,6 +92,7 @@ class MfDevice {
   std::vector<DBuf> d_potrf_, d_trsm_, d_gemm_;
   DBuf d_dinv_;                                    // inverses of the L11 diagonal blocks
   std::vector<DBuf> d_dinv_off_, d_dinv_toff_;     // per depth: for the potrf / trsm entries
+  DBuf d_dinv_front_;                              // per front: offset of its inverses
   std::vector<int64_t> max_f_;                     // per depth: max p*f + b*b
   std::vector<int> max_pb_;                        // per depth: max p + b
   int64_t nnz_ = 0;

@@ -105,24 +105,23 @@ __global__ void mf_root_pull_kernel(const MfFront *F, const int *root_ptr, const
   }
 }
 
-// z <- L^-1 z, L (n x n lower, column-major, ld) in global memory, z in LDS.
-// Blocks of TB: the diagonal block by wave 0 (lockstep, shuffles), the rows
-// below by the whole work-group.
-__device__ void lower_solve(const double *L, int ld, int n, double *z) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int jb = 0; jb < n; jb += TB) {
+// z <- L^-1 z, L (n x n lower, column-major, ld) in global memory, z in LDS;
+// Di: inverses of L's TB x TB diagonal blocks (block k at Di + k TB^2, ld TB).
+// Per block: the diagonal block is applied through its inverse (a product,
+// no sequential substitution), then the rows below are updated.
+__device__ void lower_solve(const double *L, int ld, int n, const double *Di, double *z,
+                            double *tmp) {
+  const int tid = threadIdx.x;
+  for (int jb = 0, kb = 0; jb < n; jb += TB, ++kb) {
     const int nb = min(TB, n - jb);
-    if (wave == 0) {
-      double zi = lane < nb ? z[jb + lane] : 0.0;
-      for (int k = 0; k < nb; ++k) {
-        const double zk = __shfl(zi, k, 64) / L[(jb + k) + (int64_t)(jb + k) * ld];
-        if (lane == k)
-          zi = zk;
-        else if (lane > k && lane < nb)
-          zi -= L[(jb + lane) + (int64_t)(jb + k) * ld] * zk;
-      }
-      if (lane < nb) z[jb + lane] = zi;
+    const double *D = Di + (int64_t)kb * TB * TB;
+    if (tid < nb) {
+      double y = 0;
+      for (int c = 0; c <= tid; ++c) y += D[tid + c * TB] * z[jb + c];
+      tmp[tid] = y;
     }
+    __syncthreads();
+    if (tid < nb) z[jb + tid] = tmp[tid];
     __syncthreads();
     for (int r = jb + nb + tid; r < n; r += blockDim.x) {
       double acc = 0;
@@ -134,7 +133,8 @@ __device__ void lower_solve(const double *L, int ld, int n, double *z) {
 }
 
 // x <- L^-T x (same storage)
-__device__ void upper_solve(const double *L, int ld, int n, double *x) {
+__device__ void upper_solve(const double *L, int ld, int n, const double *Di, double *x,
+                            double *tmp) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
   const int nblk = (n + TB - 1) / TB;
   for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -148,17 +148,15 @@ __device__ void upper_solve(const double *L, int ld, int n, double *x) {
       if (lane == 0) x[jb + i] -= acc;
     }
     __syncthreads();
-    if (wave == 0) {
-      double xi = lane < nb ? x[jb + lane] : 0.0;
-      for (int k = nb - 1; k >= 0; --k) {
-        const double xk = __shfl(xi, k, 64) / L[(jb + k) + (int64_t)(jb + k) * ld];
-        if (lane == k)
-          xi = xk;
-        else if (lane < k)
-          xi -= L[(jb + k) + (int64_t)(jb + lane) * ld] * xk;
-      }
-      if (lane < nb) x[jb + lane] = xi;
+    // x_block = D^-T x_block
+    const double *D = Di + (int64_t)bi * TB * TB;
+    if (tid < nb) {
+      double y = 0;
+      for (int c = tid; c < nb; ++c) y += D[c + tid * TB] * x[jb + c];
+      tmp[tid] = y;
     }
+    __syncthreads();
+    if (tid < nb) x[jb + tid] = tmp[tid];
     __syncthreads();
   }
 }
@@ -167,8 +165,10 @@ __device__ void upper_solve(const double *L, int ld, int n, double *x) {
 __global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int *ids,
                                                      const int *child_ids, const int *pmap,
                                                      const int64_t *piv, const double *U,
+                                                     const double *dinv, const int64_t *dinv_off,
                                                      double *upd, double *vI) {
   extern __shared__ double z[];
+  __shared__ double tmp[TB];
   const MfFront f = F[ids[blockIdx.x]];
   const int p = f.p, b = f.b, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwave = blockDim.x >> 6;
@@ -184,16 +184,24 @@ __global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int
   }
   __syncthreads();
   const double *Uf = U + f.u_off;
-  lower_solve(Uf, p, p, z);
+  if (p > 0) lower_solve(Uf, p, p, dinv + dinv_off[ids[blockIdx.x]], z, tmp);
   for (int j = tid; j < p; j += blockDim.x) vI[piv[f.piv_off + j]] = z[j];
-  // update for the parent: children's updates at the boundary minus F12^T z
-  for (int i = wave; i < b; i += nwave) {
-    const double *w = Uf + (int64_t)(p + i) * p;
-    double acc = 0;
-    for (int j = lane; j < p; j += 64) acc += w[j] * z[j];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) {
-      double v = -acc;
+  // update for the parent: children's updates at the boundary minus F12^T z,
+  // four columns per wave step (independent sums)
+  for (int i0 = 4 * wave; i0 < b; i0 += 4 * nwave) {
+    double acc[4] = {0, 0, 0, 0};
+    for (int j = lane; j < p; j += 64) {
+      const double zj = z[j];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (i0 + t < b) acc[t] += Uf[j + (int64_t)(p + i0 + t) * p] * zj;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      for (int off = 32; off > 0; off >>= 1) acc[t] += __shfl_xor(acc[t], off, 64);
+    if (lane < 4 && i0 + lane < b) {
+      const int i = i0 + lane;
+      double v = -(lane == 0 ? acc[0] : lane == 1 ? acc[1] : lane == 2 ? acc[2] : acc[3]);
       for (int ci = 0; ci < f.n_child; ++ci) {
         const MfFront ch = F[child_ids[f.child_ptr + ci]];
         const int k = pmap[ch.pmap_off + p + i];
@@ -208,8 +216,10 @@ __global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int
 // boundary values are zero (pure interior solve)
 __global__ __launch_bounds__(256) void mf_bwd_kernel(const MfFront *F, const int *ids,
                                                      const int64_t *piv, const int64_t *bnd,
-                                                     const double *U, double *vI) {
+                                                     const double *U, const double *dinv,
+                                                     const int64_t *dinv_off, double *vI) {
   extern __shared__ double sm[];
+  __shared__ double tmp[TB];
   const MfFront f = F[ids[blockIdx.x]];
   const int p = f.p, b = f.b, tid = threadIdx.x;
   double *x = sm, *xb = sm + p;
@@ -225,7 +235,7 @@ __global__ __launch_bounds__(256) void mf_bwd_kernel(const MfFront *F, const int
     x[j] = vI[piv[f.piv_off + j]] - acc;
   }
   __syncthreads();
-  upper_solve(Uf, p, p, x);
+  if (p > 0) upper_solve(Uf, p, p, dinv + dinv_off[ids[blockIdx.x]], x, tmp);
   for (int j = tid; j < p; j += blockDim.x) vI[piv[f.piv_off + j]] = x[j];
 }
 
@@ -252,7 +262,8 @@ inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 
 
 void MfDevice::release(DevAlloc &A) {
   for (DBuf *b : {&d_fronts_, &d_child_, &d_piv_, &d_bnd_, &d_pmap_, &d_asm_, &d_root_ptr_,
-                  &d_root_ids_, &d_U_, &d_C_, &d_upd_, &d_status_, &d_level_ids_, &d_dinv_}) {
+                  &d_root_ids_, &d_U_, &d_C_, &d_upd_, &d_status_, &d_level_ids_, &d_dinv_,
+                  &d_dinv_front_}) {
     if (b->p) A.put(b->p, b->bytes);
     *b = DBuf();
   }
@@ -339,6 +350,16 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
     d_gemm_.push_back(upload(A, st, h_gemm_[d]));
     d_dinv_off_.push_back(upload(A, st, doff[d]));
     d_dinv_toff_.push_back(upload(A, st, toff));
+  }
+  // per front (global id): offset of its diagonal-block inverses (0 if p = 0)
+  {
+    std::vector<int64_t> fo(M.fronts.size(), 0);
+    for (int d = 0; d <= D; ++d) {
+      size_t e = 0;
+      for (int t : M.levels[d])
+        if (M.fronts[t].p > 0) fo[t] = doff[d][e++];
+    }
+    d_dinv_front_ = upload(A, st, fo);
   }
   // the in-front solves keep p + b values in LDS
   int max_lds = 0;
@@ -449,7 +470,8 @@ void MfDevice::solve(hipStream_t st, double *vI) {
     if (nf == 0) continue;
     LaunchScope ls(st, "mf_fwd_kernel", launch_timing() ? level_bytes(d) : 0, 0);
     mf_fwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_pb_[d]), st>>>(
-        F, ids + level_off_[d], d_child_.as<int>(), d_pmap_.as<int>(), d_piv_.as<int64_t>(), U, upd, vI);
+        F, ids + level_off_[d], d_child_.as<int>(), d_pmap_.as<int>(), d_piv_.as<int64_t>(), U,
+        d_dinv_.as<double>(), d_dinv_front_.as<int64_t>(), upd, vI);
     HIPCHK(hipGetLastError());
   }
   for (int d = 1; d <= M.max_depth; ++d) {
@@ -457,7 +479,8 @@ void MfDevice::solve(hipStream_t st, double *vI) {
     if (nf == 0) continue;
     LaunchScope ls(st, "mf_bwd_kernel", launch_timing() ? level_bytes(d) : 0, 0);
     mf_bwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_pb_[d]), st>>>(
-        F, ids + level_off_[d], d_piv_.as<int64_t>(), d_bnd_.as<int64_t>(), U, vI);
+        F, ids + level_off_[d], d_piv_.as<int64_t>(), d_bnd_.as<int64_t>(), U, d_dinv_.as<double>(),
+        d_dinv_front_.as<int64_t>(), vI);
     HIPCHK(hipGetLastError());
   }
 }
