@@ -206,7 +206,7 @@ class BDDC:
     ``device < 0`` gives a host-only context (setup analysis, no GPU)."""
 
     def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True,
-                 verbose: bool = False):
+                 verbose: bool = False, factor_precision: int = 64):
         if device < 0:
             self.torch = None
             self.device = device
@@ -227,7 +227,7 @@ class BDDC:
         opt = bddc_options()
         opt.device = device
         opt.hip_stream = C.c_void_p(stream.cuda_stream)
-        opt.factor_precision = 64
+        opt.factor_precision = int(factor_precision)
         opt.verbose = 1 if verbose else 0
         self._keep = []
         if torch_allocator:

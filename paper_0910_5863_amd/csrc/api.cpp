@@ -70,8 +70,7 @@ bddc_status bddc_create(const bddc_options *opt, bddc_ctx **out) {
   auto c = std::make_unique<bddc_ctx>();
   if (opt) c->opt = *opt;
   if (c->opt.factor_precision == 0) c->opt.factor_precision = 64;
-  if (c->opt.factor_precision != 64)
-    return BDDC_ERR_ARG;  // FP32 factors are not available in this build
+  if (c->opt.factor_precision != 64 && c->opt.factor_precision != 32) return BDDC_ERR_ARG;
   if (c->opt.device < 0) {  // host-only context: analysis without a GPU
     c->S = std::make_unique<Solver>();
     *out = c.release();
@@ -93,6 +92,7 @@ bddc_status bddc_create(const bddc_options *opt, bddc_ctx **out) {
     c->S->alloc.free = c->opt.free;
     c->S->alloc.user = c->opt.alloc_user;
     c->S->verbose = c->opt.verbose;
+    c->S->factor_precision = c->opt.factor_precision;
   });
   if (st != BDDC_OK) return st;
   *out = c.release();

@@ -102,6 +102,10 @@ class Solver {
   std::vector<double> last_history;
   Timer timer;
   int verbose = 0;
+  // 32: the constrained local factor K_rr = L L^T, the coarse basis solves and
+  // the local triangular solves of the preconditioner in FP32 (FP32 MFMA,
+  // FP32 accumulate); everything else in FP64
+  int factor_precision = 64;
 
   ~Solver();
   void build(const Problem &P, hipStream_t st, bool keep_interior = false);
@@ -134,6 +138,8 @@ class Solver {
   void scatter64(const double *src, const int64_t *idx, int64_t n, double *dst);
   void trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
             const DBuf &dinv_off, double *x, bool upper);
+  void trsv32(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
+              const DBuf &dinv_off, float *x, bool upper);
   void release(DBuf &b);
   std::vector<DBuf *> all_buffers();
   std::vector<DBuf *> struct_buffers();
@@ -152,6 +158,7 @@ class Solver {
   DBuf d_offI, d_offG, d_offR, d_offP, d_offGG, d_offRR, d_offRP, d_offPP;
   DBuf d_S, d_W, d_Lrr, d_Urr, d_Phi, d_Spi, d_Lc, d_Uc, d_descRRT;
   DBuf d_dinv_rr, d_dinv_rr_off, d_dinv_c, d_dinv_c_off;
+  DBuf d_Lrr32, d_Urr32, d_dinv_rr32, d_Phi32, d_vR32;  // FP32 local factor (factor_precision 32)
   DBuf d_descRR, d_descC, d_spi_desc, d_descGG, d_descRRvec,
       d_descCvec;
   DBuf d_gx, d_gx_ptr, d_trow, d_pos, d_wmat, d_gk_glob, d_gk_k, d_scr;

@@ -361,6 +361,13 @@ __global__ void spmv_coupling_kernel(const int *row_sub, const int *row_loc, con
   }
 }
 
+// dst = scale * src with a change of precision
+template <class S, class D>
+__global__ void convert_kernel(const S *src, D *dst, int64_t n, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (D)(scale * (double)src[i]);
+}
+
 __global__ void axpby_kernel(double *y, const double *x, double a, double b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = b * y[i] + a * x[i];
@@ -569,7 +576,7 @@ std::vector<DBuf *> Solver::cons_buffers() {
           &d_pabs, &d_pcid, &d_sub_cids, &d_c_ptr, &d_c_sub, &d_c_loc, &d_c_copies,
           &d_trsv_rr_fwd, &d_trsv_rr_bwd, &d_trsv_rr_off, &d_trsv_c_fwd, &d_trsv_c_bwd,
           &d_trsv_c_off, &d_work_i, &d_status, &d_vR, &d_vR2, &d_vP, &d_vc, &d_descRRvec,
-          &d_descCvec};
+          &d_descCvec, &d_Lrr32, &d_Urr32, &d_dinv_rr32, &d_Phi32, &d_vR32};
 }
 
 std::vector<DBuf *> Solver::all_buffers() {
@@ -806,8 +813,15 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_work_i = alloc0(alloc, st, sizeof(int) * (size_t)(4 + std::max(w1, w3)));
   d_status = alloc0(alloc, st, sizeof(int) * (size_t)(2 * ns + 2));
   // matrices
+  const bool p32 = factor_precision == 32;
   d_Lrr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
-  d_Urr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
+  d_Urr = alloc0(alloc, st, p32 ? 0 : sizeof(double) * (size_t)L.sRR);
+  if (p32) {
+    d_Lrr32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sRR);
+    d_Urr32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sRR);
+    d_Phi32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sRP);
+    d_vR32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sumR * kMaxRhs);
+  }
   d_Phi = alloc0(alloc, st, sizeof(double) * (size_t)L.sRP);
   d_Spi = alloc0(alloc, st, sizeof(double) * (size_t)L.sPP);
   d_Lc = alloc0(alloc, st, sizeof(double) * (size_t)(nc * nc));
@@ -820,7 +834,8 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
       off[s] = tot;
       tot += (int64_t)((L.nr[s] + NB - 1) / NB) * NB * NB;
     }
-    d_dinv_rr = alloc0(alloc, st, sizeof(double) * (size_t)tot);
+    d_dinv_rr = alloc0(alloc, st, p32 ? 0 : sizeof(double) * (size_t)tot);
+    if (p32) d_dinv_rr32 = alloc0(alloc, st, sizeof(float) * (size_t)tot);
     d_dinv_rr_off = upload(alloc, st, off);
     d_dinv_c = alloc0(alloc, st, sizeof(double) * (size_t)(((nc + NB - 1) / NB) * NB * NB));
     d_dinv_c_off = upload(alloc, st, std::vector<int64_t>{0});
@@ -835,7 +850,7 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   bytes_Lrr_tri = 0;
   for (int s = 0; s < ns; ++s) {
     bytes_S += 8.0 * (double)L.nG[s] * L.nG[s];
-    bytes_Lrr_tri += 8.0 * 0.5 * (double)L.nr[s] * (L.nr[s] + 1);
+    bytes_Lrr_tri += (p32 ? 4.0 : 8.0) * 0.5 * (double)L.nr[s] * (L.nr[s] + 1);
   }
   HIPCHK(hipStreamSynchronize(st));
   factored = false;
@@ -1034,28 +1049,62 @@ void Solver::factor() {
   gather(d_Spi, d_offPP, d_np, d_pidx, d_pidx_off, d_np, d_pidx, d_pidx_off, d_np,
          (int64_t)L.max_np * L.max_np, 1.0);
   // constrained local factor and coarse basis
-  timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
-  HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), d_descRR.as<MatDesc>(), h_descRR.data(),
-                                 ns, status + ns, d_dinv_rr.as<double>(),
-                                 d_dinv_rr_off.as<int64_t>()));
-  timer.end(st);
-  HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
-                                h_descRR.data(), ns, false, d_dinv_rr.as<double>(),
-                                d_dinv_rr_off.as<int64_t>()));
-  HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
-                                d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
-                                -1.0, 1.0, false, h_spi.data()));
-  HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
-                                h_descRR.data(), ns, true, d_dinv_rr.as<double>(),
-                                d_dinv_rr_off.as<int64_t>()));
-  if (L.sRP > 0) {
-    axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
-                                                 L.sRP);
+  if (factor_precision == 32) {
+    // FP32: K_rr = L L^T and Phi = -K_rr^-1 K_r,pi on the FP32 matrix cores;
+    // S_pi = K_pi,pi - (L^-1 K_r,pi)^T (L^-1 K_r,pi) accumulated in FP64
+    convert_kernel<double, float><<<nblocks(L.sRR), TPB, 0, st>>>(d_Lrr.as<double>(), d_Lrr32.as<float>(),
+                                                                   L.sRR, 1.0);
+    if (L.sRP > 0)
+      convert_kernel<double, float><<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(),
+                                                                     d_Phi32.as<float>(), L.sRP, 1.0);
     HIPCHK(hipGetLastError());
+    timer.begin(st, "factor_potrf_local", 4.0 * L.sRR, fl_rr);
+    HIPCHK(DenseOps<float>::potrf(st, d_Lrr32.as<float>(), d_descRR.as<MatDesc>(), h_descRR.data(),
+                                  ns, status + ns, d_dinv_rr32.as<float>(),
+                                  d_dinv_rr_off.as<int64_t>()));
+    timer.end(st);
+    HIPCHK(DenseOps<float>::trsm(st, d_Lrr32.as<float>(), d_Phi32.as<float>(), d_descRR.as<MatDesc>(),
+                                 h_descRR.data(), ns, false, d_dinv_rr32.as<float>(),
+                                 d_dinv_rr_off.as<int64_t>()));
+    if (L.sRP > 0)
+      convert_kernel<float, double><<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi32.as<float>(),
+                                                                     d_Phi.as<double>(), L.sRP, 1.0);
+    HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
+                                  d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
+                                  -1.0, 1.0, false, h_spi.data()));
+    HIPCHK(DenseOps<float>::trsm(st, d_Lrr32.as<float>(), d_Phi32.as<float>(), d_descRR.as<MatDesc>(),
+                                 h_descRR.data(), ns, true, d_dinv_rr32.as<float>(),
+                                 d_dinv_rr_off.as<int64_t>()));
+    if (L.sRP > 0)
+      convert_kernel<float, double><<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi32.as<float>(),
+                                                                     d_Phi.as<double>(), L.sRP, -1.0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(transpose_batched<float>(st, d_Lrr32.as<float>(), d_Urr32.as<float>(),
+                                    d_descRRT.as<MatDesc>(), ns, L.max_nr));
+  } else {
+    timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
+    HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), d_descRR.as<MatDesc>(), h_descRR.data(),
+                                   ns, status + ns, d_dinv_rr.as<double>(),
+                                   d_dinv_rr_off.as<int64_t>()));
+    timer.end(st);
+    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
+                                  h_descRR.data(), ns, false, d_dinv_rr.as<double>(),
+                                  d_dinv_rr_off.as<int64_t>()));
+    HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
+                                  d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
+                                  -1.0, 1.0, false, h_spi.data()));
+    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
+                                  h_descRR.data(), ns, true, d_dinv_rr.as<double>(),
+                                  d_dinv_rr_off.as<int64_t>()));
+    if (L.sRP > 0) {
+      axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
+                                                   L.sRP);
+      HIPCHK(hipGetLastError());
+    }
+    // L_rr^T beside L_rr: the backward solves read it row-coalesced
+    HIPCHK(transpose_batched<double>(st, d_Lrr.as<double>(), d_Urr.as<double>(),
+                                     d_descRRT.as<MatDesc>(), ns, L.max_nr));
   }
-  // L_rr^T beside L_rr: the backward solves read it row-coalesced
-  HIPCHK(transpose_batched<double>(st, d_Lrr.as<double>(), d_Urr.as<double>(),
-                                   d_descRRT.as<MatDesc>(), ns, L.max_nr));
   // coarse problem
   const int64_t nc = L.n_coarse;
   if (nc > 0) {
@@ -1115,6 +1164,13 @@ void Solver::trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const D
   HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), plan, upper,
                               dinv.as<double>(), dinv_off.as<int64_t>(),
                               d_work_i.as<int>(), d_status.as<int>() + 2 * L.nsub + 1));
+}
+
+void Solver::trsv32(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
+                    const DBuf &dinv_off, float *x, bool upper) {
+  HIPCHK(trsv_blocked<float>(stream, A.as<float>(), x, desc.as<MatDesc>(), plan, upper,
+                             dinv.as<float>(), dinv_off.as<int64_t>(), d_work_i.as<int>(),
+                             d_status.as<int>() + 2 * L.nsub + 1));
 }
 
 // interface residual (gamma vector, nrhs = 1) -> z on gamma.  Interior values
@@ -1236,12 +1292,27 @@ void Solver::apply_local(double *b, double *z) {
         d_offR.as<int64_t>(), vP, d_offP.as<int64_t>(), 1.0, 1.0);
   }
   HIPCHK(hipMemcpyAsync(vR2, vR, sizeof(double) * L.sumR, hipMemcpyDeviceToDevice, st));
-  timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
-  trsv(plan_rr, d_Lrr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, false);
-  timer.end(st);
-  timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
-  trsv(plan_rr, d_Urr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, true);
-  timer.end(st);
+  if (factor_precision == 32) {
+    // K_rr solves in FP32; the vector enters and leaves in FP64
+    float *x32 = d_vR32.as<float>();
+    convert_kernel<double, float><<<nblocks(L.sumR), TPB, 0, st>>>(vR2, x32, L.sumR, 1.0);
+    HIPCHK(hipGetLastError());
+    timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 8.0 * L.sumR, (double)L.sRR);
+    trsv32(plan_rr, d_Lrr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, false);
+    timer.end(st);
+    timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 8.0 * L.sumR, (double)L.sRR);
+    trsv32(plan_rr, d_Urr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, true);
+    timer.end(st);
+    convert_kernel<float, double><<<nblocks(L.sumR), TPB, 0, st>>>(x32, vR2, L.sumR, 1.0);
+    HIPCHK(hipGetLastError());
+  } else {
+    timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
+    trsv(plan_rr, d_Lrr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, false);
+    timer.end(st);
+    timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
+    trsv(plan_rr, d_Urr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, true);
+    timer.end(st);
+  }
   if (L.n_coarse > 0) {
     reduce_copies_kernel<<<nblocks(L.n_coarse), TPB, 0, st>>>(vP, L.sumP, d_c_ptr.as<int>(),
                                                               d_c_copies.as<int64_t>(), nullptr, vc,
@@ -1414,7 +1485,8 @@ double Solver::apply_bytes() const {
   double b = 0;
   for (int s = 0; s < L.nsub; ++s) {
     const double nr = L.nr[s], np = L.np[s], ng = L.nG[s];
-    b += 8.0 * (nr * nr + 2 * nr * np) + 8.0 * 6 * ng;  // two triangle sweeps, Phi twice, vectors
+    const double fb = factor_precision == 32 ? 4.0 : 8.0;
+    b += fb * nr * nr + 8.0 * 2 * nr * np + 8.0 * 6 * ng;  // two triangle sweeps, Phi twice, vectors
   }
   b += 8.0 * (double)L.n_coarse * L.n_coarse;
   return b;

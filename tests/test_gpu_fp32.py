@@ -1,0 +1,127 @@
+"""Mixed precision (factor_precision = 32): the constrained local factor
+K_rr = L L^T, the coarse-basis solves and the local triangular solves of the
+preconditioner run in FP32 on the matrix cores; the PCG operator (FP64 Schur
+complements), residuals, dot products, averaging and the coarse problem stay
+FP64.
+
+A solve in FP32 has a relative forward error of at most about kappa * u32
+(u32 = 2^-24); the preconditioner is a solve with the partially assembled
+matrix A~ of Algorithm 2, so its output is compared with the FP64 oracle's to
+kappa(A~) * u32, with kappa(A~) computed by the oracle (dense eigenvalues) for
+each case -- the coefficient contrast drives it from 2e3 to 1e7.  The outer PCG is
+FP64 and still stops at ||r_k|| <= 1e-8 ||r_0||: the solution must match the
+FP64 oracle to 1e-7 relative error (the FP64 path is held to 1e-8; the FP32
+preconditioner only changes the Krylov space, not the stopping test).  Where
+kappa(A~) * u32 is small (below 1e-2) the preconditioned spectrum barely moves
+(the condition number estimate stays within 1% of the FP64 one), but the
+rounding noise of an FP32 apply (about 1e-6 relative) is within two orders of
+the 1e-8 stopping tolerance, so the last iterations stall: measured +2 (C1)
+to +4 (adaptive, contrast 1e2); at most 5 more iterations than the FP64
+count are allowed.  Where it
+is not (elasticity with contrast 1e3-1e4: kappa(A~) * u32 = 0.1-0.6), the FP32
+solve is inexact in the directions of the small eigenvalues of the local
+problems and PCG needs more iterations (measured: 85 against 37 at contrast
+1e4): only convergence and the solution error are asserted there, and the
+counts are printed.
+"""
+import numpy as np
+import pytest
+
+import meshgen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0910_5863_amd import BDDC
+    return BDDC
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+CASES = {
+    "poisson16": (lambda: meshgen.poisson_16(), "ce"),
+    "elast8_ce": (lambda: meshgen.small_elasticity_layers(8, 2, contrast=1e4), "ce"),
+    "kmeans_elast": (lambda: meshgen.small_kmeans(meshgen.ELASTICITY, 8, 4, contrast=1e3), "ce"),
+}
+
+_cache = {}
+
+
+def oracle_for(name):
+    if name not in _cache:
+        from oracle.solver import OracleBDDC
+        make, mode = CASES[name]
+        p = make()
+        o = OracleBDDC(p, mode)
+        ev = np.linalg.eigvalsh(o.M.Atil.toarray())
+        tol = ev[-1] / ev[0] * 2.0 ** -24
+        _cache[name] = (p, o, mode, tol, o.solve())
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_apply_and_pcg(name):
+    BDDC = _gpu()
+    p, o, mode, tol, ref = oracle_for(name)
+    b = BDDC(factor_precision=32)
+    b.setup(p, mode)
+    b.factor()
+    r = meshgen.random_vector(p.n_glob, 0)
+    z = b.apply(torch.from_numpy(r)).cpu().numpy()[:, 0]
+    e_apply = rel(z, o.apply(r))
+    assert e_apply < tol, (name, e_apply)
+    u, info = b.pcg_solve(torch.from_numpy(p.f))
+    u = u.cpu().numpy()[:, 0]
+    assert info[0].converged
+    e_u = rel(u, ref["u"])
+    print(f"{name}: apply err {e_apply:.2e}, solution err {e_u:.2e}, "
+          f"iters {info[0].iters} (FP64 oracle {ref['iters']}), kappa {info[0].kappa:.4g}")
+    assert e_u < 1e-7, (name, e_u)
+    if tol < 1e-2:
+        assert info[0].iters <= ref["iters"] + 5
+        assert abs(info[0].kappa - ref["kappa"]) <= 1e-2 * ref["kappa"]
+        assert info[0].lmin > 1 - 1e-3
+    b.close()
+
+
+def test_fp32_adaptive_solve():
+    """Adaptive face constraints (tau = 10) with FP32 local factors: the
+    constraint selection itself runs on the FP64 Schur complements, so Nc
+    equals the FP64 run's; the solve matches the FP64 run to 1e-7.  Contrast
+    1e2 keeps kappa(A~) * u32 small (7e-3), so the condition number estimate
+    stays below tau and at most 5 more iterations are needed."""
+    BDDC = _gpu()
+    p = meshgen.small_elasticity_layers(8, 2, contrast=1e2)
+    f = torch.from_numpy(p.f)
+    res = {}
+    for prec in (64, 32):
+        b = BDDC(factor_precision=prec)
+        b.setup(p, "ce")
+        ai = b.adapt(10.0)
+        b.factor()
+        u, info = b.pcg_solve(f)
+        res[prec] = (ai.nc, u.cpu().numpy()[:, 0], info[0])
+        b.close()
+    assert res[32][0] == res[64][0]
+    assert rel(res[32][1], res[64][1]) < 1e-7
+    assert res[32][2].kappa < 10.0 * (1 + 1e-3)
+    assert res[32][2].iters <= res[64][2].iters + 5
+
+
+def test_fp32_repeat_bitwise_deterministic():
+    BDDC = _gpu()
+    p = meshgen.small_elasticity_layers(8, 2, contrast=1e4)
+    b = BDDC(factor_precision=32)
+    b.setup(p, "ce")
+    b.factor()
+    f = torch.from_numpy(p.f)
+    u1, _ = b.pcg_solve(f)
+    u2, _ = b.pcg_solve(f)
+    assert np.array_equal(u1.cpu().numpy(), u2.cpu().numpy())
+    b.close()
