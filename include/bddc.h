@@ -56,9 +56,12 @@ typedef struct {
                                         (setup analysis and inspection only; factor,
                                         adapt, apply and solve return BDDC_ERR_STATE) */
   void *hip_stream;                  /* hipStream_t to run on; NULL: library stream */
-  int factor_precision;              /* 64 (default, 0 means 64) or 32: substructure
-                                        factors and local solves in FP32, PCG,
-                                        averaging, coarse problem in FP64 */
+  int factor_precision;              /* 64 (default, 0 means 64) or 32: the constrained
+                                        substructure factor L_rr is kept in FP32 and
+                                        the preconditioner's local triangular solves
+                                        run in FP32; the factorizations, Phi, the
+                                        coarse problem, averaging, Schur operator
+                                        and PCG stay FP64 */
   /* optional device allocator (e.g. a framework's caching allocator);
      NULL: hipMalloc / hipFree */
   void *(*alloc)(size_t bytes, void *user);

@@ -102,9 +102,9 @@ class Solver {
   std::vector<double> last_history;
   Timer timer;
   int verbose = 0;
-  // 32: the constrained local factor K_rr = L L^T, the coarse basis solves and
-  // the local triangular solves of the preconditioner in FP32 (FP32 MFMA,
-  // FP32 accumulate); everything else in FP64
+  // 32: the constrained local factor K_rr = L L^T is stored in FP32 and the
+  // preconditioner's local triangular solves run in FP32; the factorization,
+  // the coarse basis and coarse matrix, and everything else stay FP64
   int factor_precision = 64;
 
   ~Solver();
@@ -158,7 +158,8 @@ class Solver {
   DBuf d_offI, d_offG, d_offR, d_offP, d_offGG, d_offRR, d_offRP, d_offPP;
   DBuf d_S, d_W, d_Lrr, d_Urr, d_Phi, d_Spi, d_Lc, d_Uc, d_descRRT;
   DBuf d_dinv_rr, d_dinv_rr_off, d_dinv_c, d_dinv_c_off;
-  DBuf d_Lrr32, d_Urr32, d_dinv_rr32, d_Phi32, d_vR32;  // FP32 local factor (factor_precision 32)
+  DBuf d_Lrr32, d_Urr32, d_dinv_rr32, d_vR32;  // FP32 local factor (factor_precision 32)
+  int64_t dinv_rr_elems = 0;
   DBuf d_descRR, d_descC, d_spi_desc, d_descGG, d_descRRvec,
       d_descCvec;
   DBuf d_gx, d_gx_ptr, d_trow, d_pos, d_wmat, d_gk_glob, d_gk_k, d_scr;

@@ -576,7 +576,7 @@ std::vector<DBuf *> Solver::cons_buffers() {
           &d_pabs, &d_pcid, &d_sub_cids, &d_c_ptr, &d_c_sub, &d_c_loc, &d_c_copies,
           &d_trsv_rr_fwd, &d_trsv_rr_bwd, &d_trsv_rr_off, &d_trsv_c_fwd, &d_trsv_c_bwd,
           &d_trsv_c_off, &d_work_i, &d_status, &d_vR, &d_vR2, &d_vP, &d_vc, &d_descRRvec,
-          &d_descCvec, &d_Lrr32, &d_Urr32, &d_dinv_rr32, &d_Phi32, &d_vR32};
+          &d_descCvec, &d_Lrr32, &d_Urr32, &d_dinv_rr32, &d_vR32};
 }
 
 std::vector<DBuf *> Solver::all_buffers() {
@@ -819,7 +819,6 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   if (p32) {
     d_Lrr32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sRR);
     d_Urr32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sRR);
-    d_Phi32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sRP);
     d_vR32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sumR * kMaxRhs);
   }
   d_Phi = alloc0(alloc, st, sizeof(double) * (size_t)L.sRP);
@@ -834,8 +833,9 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
       off[s] = tot;
       tot += (int64_t)((L.nr[s] + NB - 1) / NB) * NB * NB;
     }
-    d_dinv_rr = alloc0(alloc, st, p32 ? 0 : sizeof(double) * (size_t)tot);
+    d_dinv_rr = alloc0(alloc, st, sizeof(double) * (size_t)tot);
     if (p32) d_dinv_rr32 = alloc0(alloc, st, sizeof(float) * (size_t)tot);
+    dinv_rr_elems = tot;
     d_dinv_rr_off = upload(alloc, st, off);
     d_dinv_c = alloc0(alloc, st, sizeof(double) * (size_t)(((nc + NB - 1) / NB) * NB * NB));
     d_dinv_c_off = upload(alloc, st, std::vector<int64_t>{0});
@@ -1048,59 +1048,38 @@ void Solver::factor() {
          (int64_t)L.max_nr * L.max_np, 1.0);
   gather(d_Spi, d_offPP, d_np, d_pidx, d_pidx_off, d_np, d_pidx, d_pidx_off, d_np,
          (int64_t)L.max_np * L.max_np, 1.0);
-  // constrained local factor and coarse basis
+  // constrained local factor and coarse basis (FP64 in both precisions:
+  // S_pi = K_pi,pi - K_pi,r K_rr^-1 K_r,pi is a difference of nearly equal
+  // terms at high coefficient contrast)
+  timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
+  HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), d_descRR.as<MatDesc>(), h_descRR.data(),
+                                 ns, status + ns, d_dinv_rr.as<double>(),
+                                 d_dinv_rr_off.as<int64_t>()));
+  timer.end(st);
+  HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
+                                h_descRR.data(), ns, false, d_dinv_rr.as<double>(),
+                                d_dinv_rr_off.as<int64_t>()));
+  HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
+                                d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
+                                -1.0, 1.0, false, h_spi.data()));
+  HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
+                                h_descRR.data(), ns, true, d_dinv_rr.as<double>(),
+                                d_dinv_rr_off.as<int64_t>()));
+  if (L.sRP > 0) {
+    axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
+                                                 L.sRP);
+    HIPCHK(hipGetLastError());
+  }
   if (factor_precision == 32) {
-    // FP32: K_rr = L L^T and Phi = -K_rr^-1 K_r,pi on the FP32 matrix cores;
-    // S_pi = K_pi,pi - (L^-1 K_r,pi)^T (L^-1 K_r,pi) accumulated in FP64
+    // the factor used by the preconditioner's local solves, stored in FP32
     convert_kernel<double, float><<<nblocks(L.sRR), TPB, 0, st>>>(d_Lrr.as<double>(), d_Lrr32.as<float>(),
                                                                    L.sRR, 1.0);
-    if (L.sRP > 0)
-      convert_kernel<double, float><<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(),
-                                                                     d_Phi32.as<float>(), L.sRP, 1.0);
-    HIPCHK(hipGetLastError());
-    timer.begin(st, "factor_potrf_local", 4.0 * L.sRR, fl_rr);
-    HIPCHK(DenseOps<float>::potrf(st, d_Lrr32.as<float>(), d_descRR.as<MatDesc>(), h_descRR.data(),
-                                  ns, status + ns, d_dinv_rr32.as<float>(),
-                                  d_dinv_rr_off.as<int64_t>()));
-    timer.end(st);
-    HIPCHK(DenseOps<float>::trsm(st, d_Lrr32.as<float>(), d_Phi32.as<float>(), d_descRR.as<MatDesc>(),
-                                 h_descRR.data(), ns, false, d_dinv_rr32.as<float>(),
-                                 d_dinv_rr_off.as<int64_t>()));
-    if (L.sRP > 0)
-      convert_kernel<float, double><<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi32.as<float>(),
-                                                                     d_Phi.as<double>(), L.sRP, 1.0);
-    HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
-                                  d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
-                                  -1.0, 1.0, false, h_spi.data()));
-    HIPCHK(DenseOps<float>::trsm(st, d_Lrr32.as<float>(), d_Phi32.as<float>(), d_descRR.as<MatDesc>(),
-                                 h_descRR.data(), ns, true, d_dinv_rr32.as<float>(),
-                                 d_dinv_rr_off.as<int64_t>()));
-    if (L.sRP > 0)
-      convert_kernel<float, double><<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi32.as<float>(),
-                                                                     d_Phi.as<double>(), L.sRP, -1.0);
+    convert_kernel<double, float><<<nblocks(dinv_rr_elems), TPB, 0, st>>>(
+        d_dinv_rr.as<double>(), d_dinv_rr32.as<float>(), dinv_rr_elems, 1.0);
     HIPCHK(hipGetLastError());
     HIPCHK(transpose_batched<float>(st, d_Lrr32.as<float>(), d_Urr32.as<float>(),
                                     d_descRRT.as<MatDesc>(), ns, L.max_nr));
   } else {
-    timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
-    HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), d_descRR.as<MatDesc>(), h_descRR.data(),
-                                   ns, status + ns, d_dinv_rr.as<double>(),
-                                   d_dinv_rr_off.as<int64_t>()));
-    timer.end(st);
-    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
-                                  h_descRR.data(), ns, false, d_dinv_rr.as<double>(),
-                                  d_dinv_rr_off.as<int64_t>()));
-    HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
-                                  d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
-                                  -1.0, 1.0, false, h_spi.data()));
-    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
-                                  h_descRR.data(), ns, true, d_dinv_rr.as<double>(),
-                                  d_dinv_rr_off.as<int64_t>()));
-    if (L.sRP > 0) {
-      axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
-                                                   L.sRP);
-      HIPCHK(hipGetLastError());
-    }
     // L_rr^T beside L_rr: the backward solves read it row-coalesced
     HIPCHK(transpose_batched<double>(st, d_Lrr.as<double>(), d_Urr.as<double>(),
                                      d_descRRT.as<MatDesc>(), ns, L.max_nr));

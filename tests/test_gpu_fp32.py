@@ -1,8 +1,8 @@
 """Mixed precision (factor_precision = 32): the constrained local factor
-K_rr = L L^T, the coarse-basis solves and the local triangular solves of the
-preconditioner run in FP32 on the matrix cores; the PCG operator (FP64 Schur
-complements), residuals, dot products, averaging and the coarse problem stay
-FP64.
+K_rr = L L^T is kept in FP32 and the preconditioner's local triangular solves
+run in FP32; the factorizations (so the coarse basis Phi and the coarse
+matrix), the PCG operator (FP64 Schur complements), residuals, dot products
+and averaging stay FP64.
 
 A solve in FP32 has a relative forward error of at most about kappa * u32
 (u32 = 2^-24); the preconditioner is a solve with the partially assembled
