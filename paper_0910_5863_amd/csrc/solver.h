@@ -172,6 +172,16 @@ class Solver {
   DBuf d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, d_work_i, d_status;
   DBuf d_vG, d_vG2, d_vR, d_vR2, d_vP, d_vI, d_vI2, d_vc;
   DBuf d_gam_r, d_gam_z, d_gam_p, d_gam_q, d_gam_x, d_sc, d_part, d_alphas, d_betas;
+  DBuf d_pcg_ctl, d_pcg_hist;  // PCG control words (stop, iterations, converged, maxit), history
+  // one PCG iteration captured as a graph (rebuilt after every build); the
+  // stream it is captured on, two events and pinned words for the lookahead
+  hipGraphExec_t pcg_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t pcg_ev[2] = {nullptr, nullptr};
+  int *pcg_pin = nullptr;
+  bool use_graphs = true;
+  void pcg_iteration();
+  void drop_pcg_graph();
 };
 
 }  // namespace bddc

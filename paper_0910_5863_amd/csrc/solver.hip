@@ -405,31 +405,68 @@ __global__ void dot_final_kernel(const double *part, int nb, double *out) {
 
 // PCG scalar updates on the device.  sc: [0] rz, [1] pq, [2] rr, [3] alpha,
 // [4] beta, [5] rz_new
-__global__ void pcg_alpha_kernel(double *sc, double *alphas, int it) {
+// PCG scalars live on the device: sc[0] = (r, z), sc[1] = (p, q), sc[2] =
+// (r, r), sc[3] = alpha, sc[4] = beta, sc[5] = new (r, z), sc[6] = r0,
+// sc[7] = rtol.  Control words ctl[0] = stop, ctl[1] = iterations done,
+// ctl[2] = converged, ctl[3] = maxit.  Once stop is set, every later
+// iteration leaves x, r and p untouched, so iterations launched ahead of the
+// host's check are harmless.
+__global__ void pcg_init_kernel(double *sc, int *ctl, double r0, double rtol, int maxit) {
+  sc[6] = r0;
+  sc[7] = rtol;
+  ctl[0] = 0;
+  ctl[1] = 0;
+  ctl[2] = 0;
+  ctl[3] = maxit;
+}
+__global__ void pcg_alpha_kernel(double *sc, double *alphas, const int *ctl) {
+  if (ctl[0]) return;
   const double a = sc[0] / sc[1];
   sc[3] = a;
-  alphas[it] = a;
+  alphas[ctl[1]] = a;
 }
-__global__ void pcg_beta_kernel(double *sc, double *betas, int it) {
+// after (r, r): the relative residual of this iteration, and the stop test
+__global__ void pcg_check_kernel(const double *sc, int *ctl, double *hist) {
+  if (ctl[0]) return;
+  const int it = ctl[1] + 1;
+  const double rel = sqrt(sc[2]) / sc[6];
+  hist[it] = rel;
+  ctl[1] = it;
+  if (!isfinite(rel)) {
+    ctl[0] = 1;
+  } else if (rel <= sc[7]) {
+    ctl[0] = 1;
+    ctl[2] = 1;
+  } else if (it >= ctl[3]) {
+    ctl[0] = 1;
+  }
+}
+__global__ void pcg_beta_kernel(double *sc, double *betas, const int *ctl) {
+  if (ctl[0]) return;
   const double b = sc[5] / sc[0];
   sc[4] = b;
-  betas[it] = b;
+  betas[ctl[1] - 1] = b;
   sc[0] = sc[5];
 }
 // x += alpha p ; r -= alpha q
 __global__ void pcg_update_kernel(double *x, double *r, const double *p, const double *q,
-                                  const double *sc, int64_t n) {
+                                  const double *sc, const int *ctl, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || ctl[0]) return;
   const double a = sc[3];
   x[i] += a * p[i];
   r[i] -= a * q[i];
 }
 // p = z + beta p
-__global__ void pcg_dir_kernel(double *p, const double *z, const double *sc, int64_t n) {
+__global__ void pcg_dir_kernel(double *p, const double *z, const double *sc, const int *ctl,
+                               int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || ctl[0]) return;
   p[i] = z[i] + sc[4] * p[i];
+}
+__global__ void copy_kernel(double *dst, const double *src, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 }  // namespace
@@ -551,12 +588,22 @@ void Solver::release(DBuf &b) {
 }
 
 void Solver::free_all() {
+  drop_pcg_graph();
   for (DBuf *b : all_buffers()) release(*b);
+}
+
+void Solver::drop_pcg_graph() {
+  if (pcg_exec) hipGraphExecDestroy(pcg_exec);
+  pcg_exec = nullptr;
 }
 
 Solver::~Solver() {
   free_all();
   mf.release(alloc);
+  for (hipEvent_t &e : pcg_ev)
+    if (e) hipEventDestroy(e);
+  if (cap_stream) hipStreamDestroy(cap_stream);
+  if (pcg_pin) hipHostFree(pcg_pin);
 }
 
 // buffers that depend only on the mesh and partition (kept when the
@@ -565,7 +612,8 @@ std::vector<DBuf *> Solver::struct_buffers() {
   return {&d_row_sub, &d_row_loc, &d_rowptr, &d_col, &d_val, &d_nI, &d_nG, &d_offI, &d_offG,
           &d_offGG, &d_S, &d_W, &d_descGG, &d_ifc_gamma, &d_ifc_delta, &d_gamma_ptr,
           &d_gamma_copies, &d_gamma_gdof, &d_int_gdof, &d_ifc_gdof, &d_vG, &d_vG2, &d_vI, &d_vI2,
-          &d_gam_r, &d_gam_z, &d_gam_p, &d_gam_q, &d_gam_x, &d_sc, &d_part, &d_alphas, &d_betas};
+          &d_gam_r, &d_gam_z, &d_gam_p, &d_gam_q, &d_gam_x, &d_sc, &d_part, &d_alphas, &d_betas,
+          &d_pcg_ctl, &d_pcg_hist};
 }
 
 std::vector<DBuf *> Solver::cons_buffers() {
@@ -592,6 +640,7 @@ std::vector<DBuf *> Solver::all_buffers() {
 // on the constraints.
 void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   const bool keep_struct = keep_interior && struct_ready;
+  drop_pcg_graph();  // it holds the addresses of buffers released here
   for (DBuf *b : cons_buffers()) release(*b);
   if (!keep_struct) {
     for (DBuf *b : struct_buffers()) release(*b);
@@ -964,6 +1013,8 @@ void Solver::build_structure(const Problem &P, hipStream_t st) {
   d_part = alloc0(alloc, st, sizeof(double) * 1024);
   d_alphas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
   d_betas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
+  d_pcg_ctl = alloc0(alloc, st, sizeof(int) * 4);
+  d_pcg_hist = alloc0(alloc, st, sizeof(double) * (kMaxIt + 2));
   // interior elimination
   mf.setup(P, L.offI, alloc, st);
 }
@@ -1270,7 +1321,7 @@ void Solver::apply_local(double *b, double *z) {
         d_Phi.as<double>(), d_offRP.as<int64_t>(), d_nr.as<int>(), d_np.as<int>(), vR,
         d_offR.as<int64_t>(), vP, d_offP.as<int64_t>(), 1.0, 1.0);
   }
-  HIPCHK(hipMemcpyAsync(vR2, vR, sizeof(double) * L.sumR, hipMemcpyDeviceToDevice, st));
+  copy_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vR2, vR, L.sumR);
   if (factor_precision == 32) {
     // K_rr solves in FP32; the vector enters and leaves in FP64
     float *x32 = d_vR32.as<float>();
@@ -1360,6 +1411,28 @@ void Solver::scatter64(const double *src, const int64_t *idx, int64_t n, double 
 
 // PCG on the reduced problem (Remark after Lemma 1: zero interface start,
 // interior Dirichlet solves, residuals vanish in the interiors).
+// One PCG iteration on the interface, all scalars on the device (see
+// pcg_check_kernel); launched eagerly or captured as a graph.
+void Solver::pcg_iteration() {
+  hipStream_t st = stream;
+  const int64_t ng = L.n_gamma;
+  double *r = d_gam_r.as<double>(), *z = d_gam_z.as<double>(), *p = d_gam_p.as<double>();
+  double *q = d_gam_q.as<double>(), *x = d_gam_x.as<double>();
+  double *sc = d_sc.as<double>();
+  int *ctl = d_pcg_ctl.as<int>();
+  schur_gamma(p, q);
+  dot(p, q, ng, sc + 1);
+  pcg_alpha_kernel<<<1, 1, 0, st>>>(sc, d_alphas.as<double>(), ctl);
+  pcg_update_kernel<<<nblocks(ng), TPB, 0, st>>>(x, r, p, q, sc, ctl, ng);
+  dot(r, r, ng, sc + 2);
+  pcg_check_kernel<<<1, 1, 0, st>>>(sc, ctl, d_pcg_hist.as<double>());
+  apply_gamma(r, z);
+  dot(r, z, ng, sc + 5);
+  pcg_beta_kernel<<<1, 1, 0, st>>>(sc, d_betas.as<double>(), ctl);
+  pcg_dir_kernel<<<nblocks(ng), TPB, 0, st>>>(p, z, sc, ctl, ng);
+  HIPCHK(hipGetLastError());
+}
+
 PcgResult Solver::pcg(const double *f, double *u, double rtol, int maxit) {
   if (!factored) throw StateError("bddc_pcg_solve before bddc_factor");
   maxit = std::min(maxit, kMaxIt);
@@ -1396,33 +1469,69 @@ PcgResult Solver::pcg(const double *f, double *u, double rtol, int maxit) {
   bool conv = (r0 == 0.0);
   double rel = 0.0;
   res.history.push_back(1.0);
-  if (!conv) {
+  if (!conv && maxit > 0) {
     apply_gamma(r, z);
-    HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * ng, hipMemcpyDeviceToDevice, st));
+    copy_kernel<<<nblocks(ng), TPB, 0, st>>>(p, z, ng);
     dot(r, z, ng, sc + 0);
-    for (it = 1; it <= maxit; ++it) {
-      schur_gamma(p, q);
-      dot(p, q, ng, sc + 1);
-      pcg_alpha_kernel<<<1, 1, 0, st>>>(sc, d_alphas.as<double>(), it - 1);
-      pcg_update_kernel<<<nblocks(ng), TPB, 0, st>>>(x, r, p, q, sc, ng);
-      dot(r, r, ng, sc + 2);
-      double rr;
-      HIPCHK(hipMemcpyAsync(&rr, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      rel = std::sqrt(rr) / r0;
-      res.history.push_back(rel);
-      if (!std::isfinite(rel)) break;
-      if (rel <= rtol) {
-        conv = true;
-        break;
+    int *ctl = d_pcg_ctl.as<int>();
+    pcg_init_kernel<<<1, 1, 0, st>>>(sc, ctl, r0, rtol, maxit);
+    HIPCHK(hipGetLastError());
+    // per-launch timing records events around launches: then run eagerly
+    const bool graphs = use_graphs && timer.mode == 0;
+    if (graphs && !pcg_exec) {
+      // capture one iteration on a private stream (the caller's stream may
+      // be the legacy default stream, which cannot be captured)
+      if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      stream = cap_stream;
+      HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        pcg_iteration();
+      } catch (...) {
+        hipStreamEndCapture(cap_stream, &g);
+        if (g) hipGraphDestroy(g);
+        stream = st;
+        throw;
       }
-      apply_gamma(r, z);
-      dot(r, z, ng, sc + 5);
-      pcg_beta_kernel<<<1, 1, 0, st>>>(sc, d_betas.as<double>(), it - 1);
-      pcg_dir_kernel<<<nblocks(ng), TPB, 0, st>>>(p, z, sc, ng);
-      HIPCHK(hipGetLastError());
+      stream = st;
+      HIPCHK(hipStreamEndCapture(cap_stream, &g));
+      const hipError_t e = hipGraphInstantiate(&pcg_exec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIPCHK(e);
     }
-    if (it > maxit) it = maxit;
+    if (graphs) {
+      if (!pcg_pin) HIPCHK(hipHostMalloc((void **)&pcg_pin, sizeof(int) * 8, hipHostMallocDefault));
+      for (hipEvent_t &e : pcg_ev)
+        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      // the host checks iteration k while iteration k + 1 runs
+      for (int k = 0; k < maxit; ++k) {
+        HIPCHK(hipGraphLaunch(pcg_exec, st));
+        HIPCHK(hipMemcpyAsync(pcg_pin + 4 * (k & 1), ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(pcg_ev[k & 1], st));
+        if (k > 0) {
+          HIPCHK(hipEventSynchronize(pcg_ev[(k - 1) & 1]));
+          if (pcg_pin[4 * ((k - 1) & 1)]) break;
+        }
+      }
+    } else {
+      for (int k = 0; k < maxit; ++k) {
+        pcg_iteration();
+        int h[4];
+        HIPCHK(hipMemcpyAsync(h, ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (h[0]) break;
+      }
+    }
+    int h[4];
+    HIPCHK(hipMemcpyAsync(h, ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    it = h[1];
+    conv = h[2] != 0;
+    std::vector<double> hist(it + 1);
+    if (it > 0)
+      HIPCHK(hipMemcpy(hist.data(), d_pcg_hist.p, sizeof(double) * (it + 1), hipMemcpyDeviceToHost));
+    for (int k = 1; k <= it; ++k) res.history.push_back(hist[k]);
+    if (it > 0) rel = hist[it];
   }
   // u: interface from x, interiors A_II^-1 (f_I - A_IG x)
   scatter_gamma(x, u);

@@ -180,3 +180,27 @@ def test_repeat_bitwise_deterministic():
     assert np.array_equal(h1, h2)
     assert np.array_equal(u1.cpu().numpy(), u2.cpu().numpy())
     b.close()
+
+
+def test_pcg_graph_matches_eager():
+    """PCG iterations replayed from a captured graph (timing off) against the
+    same iterations launched one by one (phase timing on): same iteration
+    count, history and solution bits, on repeated calls in both orders."""
+    BDDC = _gpu()
+    p = meshgen.small_kmeans(meshgen.ELASTICITY, 8, 4, contrast=1e3)
+    b = BDDC()
+    b.setup(p, "ce")
+    b.factor()
+    f = torch.from_numpy(p.f)
+    runs = []
+    for timing in (0, 1, 0, 1, 0):
+        b.set_timing(timing)
+        u, info = b.pcg_solve(f)
+        runs.append((u.cpu().numpy(), b.pcg_history(), info[0].iters, info[0].kappa))
+    b.set_timing(0)
+    for u, h, it, kappa in runs[1:]:
+        assert it == runs[0][2]
+        assert np.array_equal(h, runs[0][1])
+        assert np.array_equal(u, runs[0][0])
+        assert kappa == runs[0][3]
+    b.close()
