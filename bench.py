@@ -61,7 +61,53 @@ def parse_args():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, run one plain device copy of this many MiB "
                          "(a known-size reference for hardware byte counters)")
+    ap.add_argument("--serving", type=int, default=0, metavar="N",
+                    help="instead of the step benchmark, serve the first N requests of the "
+                         "seeded request stream (Poisson arrivals) and report latency")
+    ap.add_argument("--serving-rate", type=float, default=8.0, help="arrivals per second")
+    ap.add_argument("--serving-workers", type=int, default=4, help="requests in flight at once")
+    ap.add_argument("--serving-precision", type=int, default=32, choices=(32, 64))
     return ap.parse_args()
+
+
+def serving(args):
+    """Requests from the seeded stream (Poisson or elasticity cubes of
+    16^3-48^3 elements in 8-64 substructures, layered contrast 1-1e6), each a
+    full adapt(tau = 10) + factor + PCG solve, submitted at seeded Poisson
+    arrival times to the request server; one JSON line with throughput and
+    arrival-to-result latency percentiles."""
+    import numpy as np
+    import meshgen
+    from paper_0910_5863_amd import Server
+    reqs = meshgen.serving_requests(max(args.serving, 512))[:args.serving]
+    probs = [meshgen.request_problem(r) for r in reqs]  # generated before the clock starts
+    gaps = np.random.default_rng(7).exponential(1.0 / args.serving_rate, len(probs))
+    srv = Server(max_active=args.serving_workers, factor_precision=args.serving_precision)
+    t0 = time.perf_counter()
+    ids = []
+    for p, t in zip(probs, np.cumsum(gaps)):
+        delay = t0 + t - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(p, 10.0))
+    res = [srv.wait(i)[1] for i in ids]
+    elapsed = time.perf_counter() - t0
+    srv.close()
+    failed = [r.error.decode() for r in res if r.state != 2]
+    lat = np.array([r.done_s - r.submit_s for r in res])
+    queue = np.array([r.start_s - r.submit_s for r in res])
+    iters = np.array([r.pcg.iters for r in res])
+    print(json.dumps({
+        "metric": "serving: solves/s and arrival-to-result latency",
+        "value": len(res) / elapsed, "unit": "solves/s", "n_gpus": 1,
+        "requests": len(res), "failed": len(failed), "errors": failed[:3],
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "p50_queue_s": float(np.percentile(queue, 50)), "max_queue_s": float(queue.max()),
+        "arrival_rate_per_s": args.serving_rate, "workers": args.serving_workers,
+        "factor_precision": args.serving_precision, "pcg_iters_median": float(np.median(iters)),
+        "elapsed_s": elapsed, "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": "serving_request_stream_seed5", "tau": 10.0, "rtol": 1e-8},
+    }))
 
 
 def source_sha(rel):
@@ -136,6 +182,9 @@ def main():
               f"(the substructure sharding across GPUs is a design, not an implementation)",
               file=sys.stderr)
         sys.exit(2)
+    if args.serving > 0:
+        serving(args)
+        return
     import numpy as np
     import torch
     import meshgen

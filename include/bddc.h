@@ -224,6 +224,75 @@ bddc_status bddc_get_timing(const bddc_ctx *ctx, int max, bddc_kernel_stat *out,
 const char *bddc_last_error(const bddc_ctx *ctx);
 void bddc_destroy(bddc_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+   Request server: many independent solves (each a full setup -> adapt ->
+   factor -> PCG of the hot path above, on its own mesh) served with
+   continuous admission.  Requests are queued in arrival order; the head of
+   the queue is admitted as soon as a worker is free and its device-memory
+   footprint estimate fits beside those of the requests in flight (a request
+   larger than the whole budget runs alone).  Each admitted request runs on
+   its worker's own non-blocking stream with stream-ordered allocations, so
+   the device work of the requests in flight overlaps, and its memory returns
+   to the pool when it finishes.  Results do not depend on what else runs:
+   every kernel is deterministic and no reduction crosses requests.
+
+   Footprint estimate (bytes, from the mesh and partition before any
+   allocation): 8 * sum over substructures of 6 n_G^2 (Schur complement and
+   its work copy, the interface factor and its transpose, the top fronts'
+   contribution blocks) plus 6 n_G^2 more when tau > 0 (the face-pair Schur
+   complements held during adaptation), plus the CSR matrices and vectors,
+   times 1.15.  n_G counts a substructure's non-Dirichlet dofs on nodes it
+   shares with another substructure.
+
+   All calls are thread-safe.  Errors of a request (bad input, OOM, non-SPD)
+   are reported in its bddc_request_info; the call that returns them
+   succeeds. */
+typedef struct bddc_server bddc_server;
+
+typedef struct {
+  int device;                 /* HIP device ordinal */
+  int factor_precision;       /* 64 or 32 (0 means 64), for every request */
+  int max_active;             /* requests in flight at once (0 means 4) */
+  double hbm_budget_bytes;    /* admission limit on the summed footprint
+                                 estimates (0: 80% of the device's free memory) */
+} bddc_server_options;
+
+typedef struct {
+  int64_t id;
+  int state;                  /* 0 queued, 1 running, 2 done, 3 failed */
+  int status;                 /* bddc_status of a failed request, else 0 */
+  double submit_s, start_s, done_s;  /* seconds since the server was created */
+  double footprint_bytes;     /* the admission estimate */
+  int64_t n_glob;
+  double omega;               /* adaptation indicator (0 without adaptation) */
+  int64_t nc;                 /* rows of D used by the solve */
+  bddc_pcg_info pcg;
+  char error[160];            /* message of a failed request */
+} bddc_request_info;
+
+bddc_status bddc_server_create(const bddc_server_options *opt, bddc_server **out);
+/* Queues one request.  All arrays are host pointers, copied before the call
+   returns.  tau > 0 runs bddc_adapt(tau) before the factorization, tau <= 0
+   solves with the given constraints only.  f: the load in the global
+   numbering of the mesh's non-Dirichlet dofs (ascending node, then
+   component); its length n_glob must match the mesh (checked at setup: a
+   mismatch fails the request).  params may be NULL (defaults of
+   bddc_pcg_solve).  *id receives the request id. */
+bddc_status bddc_server_submit(bddc_server *srv, const bddc_mesh *mesh, const bddc_partition *part,
+                               const bddc_constraints *cons, double tau, const double *f,
+                               int64_t n_glob, const bddc_pcg_params *params, int64_t *id);
+/* Blocks until request id has finished; copies the solution (n_glob host
+   doubles) to u when u != NULL and fills info (may be NULL).  The request's
+   record is kept until bddc_server_release. */
+bddc_status bddc_server_wait(bddc_server *srv, int64_t id, double *u, bddc_request_info *info);
+/* Non-blocking state of request id. */
+bddc_status bddc_server_query(bddc_server *srv, int64_t id, bddc_request_info *info);
+/* Forgets a finished request (its host copy of the solution). */
+bddc_status bddc_server_release(bddc_server *srv, int64_t id);
+/* Finishes every queued request, then stops the workers and frees the
+   server. */
+void bddc_server_destroy(bddc_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,18 @@ class bddc_info(C.Structure):
                 ("device_bytes", C.c_size_t)]
 
 
+class bddc_server_options(C.Structure):
+    _fields_ = [("device", C.c_int), ("factor_precision", C.c_int), ("max_active", C.c_int),
+                ("hbm_budget_bytes", C.c_double)]
+
+
+class bddc_request_info(C.Structure):
+    _fields_ = [("id", C.c_int64), ("state", C.c_int), ("status", C.c_int), ("submit_s", C.c_double),
+                ("start_s", C.c_double), ("done_s", C.c_double), ("footprint_bytes", C.c_double),
+                ("n_glob", C.c_int64), ("omega", C.c_double), ("nc", C.c_int64),
+                ("pcg", bddc_pcg_info), ("error", C.c_char * 160)]
+
+
 class bddc_kernel_stat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("ms", C.c_double), ("launches", C.c_int64),
                 ("bytes", C.c_double), ("flops", C.c_double)]
@@ -90,8 +102,11 @@ class bddc_kernel_stat(C.Structure):
 
 SYMBOLS = ["bddc_create", "bddc_setup", "bddc_adapt", "bddc_factor", "bddc_apply",
            "bddc_pcg_solve", "bddc_get_info", "bddc_get_face_rows", "bddc_get_face_eigs",
-           "bddc_pcg_history", "bddc_get_substructure", "bddc_set_timing", "bddc_get_timing", "bddc_last_error",
-           "bddc_destroy"]
+           "bddc_pcg_history", "bddc_get_substructure", "bddc_set_timing", "bddc_get_timing",
+           "bddc_server_create", "bddc_server_submit", "bddc_server_wait", "bddc_server_query",
+           "bddc_server_release", "bddc_server_destroy", "bddc_last_error", "bddc_destroy"]
+# the last entries have their own return types
+_VOID = ("bddc_server_destroy", "bddc_destroy")
 
 _lib = None
 _live = weakref.WeakSet()
@@ -140,9 +155,19 @@ def load(path: str = LIB_PATH):
     L.bddc_last_error.argtypes = [P]
     L.bddc_last_error.restype = C.c_char_p
     L.bddc_destroy.argtypes = [P]
-    L.bddc_destroy.restype = None
-    for s in SYMBOLS[:-2]:
-        getattr(L, s).restype = C.c_int
+    L.bddc_server_create.argtypes = [C.POINTER(bddc_server_options), C.POINTER(P)]
+    L.bddc_server_submit.argtypes = [P, C.POINTER(bddc_mesh), C.POINTER(bddc_partition),
+                                     C.POINTER(bddc_constraints), C.c_double, C.POINTER(C.c_double),
+                                     C.c_int64, C.POINTER(bddc_pcg_params), C.POINTER(C.c_int64)]
+    L.bddc_server_wait.argtypes = [P, C.c_int64, C.POINTER(C.c_double), C.POINTER(bddc_request_info)]
+    L.bddc_server_query.argtypes = [P, C.c_int64, C.POINTER(bddc_request_info)]
+    L.bddc_server_release.argtypes = [P, C.c_int64]
+    L.bddc_server_destroy.argtypes = [P]
+    for s in SYMBOLS:
+        if s in _VOID:
+            getattr(L, s).restype = None
+        elif s != "bddc_last_error":
+            getattr(L, s).restype = C.c_int
     _lib = L
     return L
 
@@ -199,6 +224,99 @@ def _check(h, code):
     if code != 0:
         msg = bddc_last_error(h) if h is not None else ""
         raise BddcError(code, msg)
+
+
+def _marshal(prob, mode, augment_corners=True, qr_drop_tol=1e-10):
+    """ctypes structures for a meshgen-style problem, and the arrays they point to."""
+    xyz = np.ascontiguousarray(prob.xyz, dtype=np.float64)
+    hex8 = np.ascontiguousarray(prob.hex8, dtype=np.int64)
+    coef = np.ascontiguousarray(prob.coef, dtype=np.float64)
+    dirichlet = np.ascontiguousarray(prob.dirichlet, dtype=np.uint8)
+    elem_sub = np.ascontiguousarray(prob.elem_sub, dtype=np.int32)
+    mesh = bddc_mesh(int(prob.kind), xyz.shape[0], _ptr(xyz, C.c_double), hex8.shape[0],
+                     _ptr(hex8, C.c_int64), _ptr(coef, C.c_double), float(prob.nu),
+                     _ptr(dirichlet, C.c_uint8))
+    part = bddc_partition(int(prob.n_sub), _ptr(elem_sub, C.c_int32))
+    cons = bddc_constraints(MODES[mode] if isinstance(mode, str) else int(mode),
+                            1 if augment_corners else 0, float(qr_drop_tol))
+    return mesh, part, cons, (xyz, hex8, coef, dirichlet, elem_sub)
+
+
+def bddc_server_create(opt):
+    h = C.c_void_p()
+    _check(None, load().bddc_server_create(C.byref(opt), C.byref(h)))
+    return h
+
+
+def bddc_server_submit(h, mesh, part, cons, tau, f, params):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    rid = C.c_int64()
+    _check(None, load().bddc_server_submit(h, C.byref(mesh), C.byref(part), C.byref(cons),
+                                           float(tau), _ptr(f, C.c_double), f.shape[0],
+                                           C.byref(params), C.byref(rid)))
+    return rid.value
+
+
+def bddc_server_wait(h, rid, n_glob):
+    u = np.empty(n_glob, dtype=np.float64)
+    info = bddc_request_info()
+    _check(None, load().bddc_server_wait(h, rid, _ptr(u, C.c_double), C.byref(info)))
+    return u, info
+
+
+def bddc_server_query(h, rid):
+    info = bddc_request_info()
+    _check(None, load().bddc_server_query(h, rid, C.byref(info)))
+    return info
+
+
+def bddc_server_release(h, rid):
+    _check(None, load().bddc_server_release(h, rid))
+
+
+def bddc_server_destroy(h):
+    load().bddc_server_destroy(h)
+
+
+class Server:
+    """Request server on one device (bddc_server_*): submit() queues a full
+    setup -> adapt -> factor -> PCG solve of one problem and returns its id;
+    wait() blocks for its solution (a host array) and record.  Inputs and
+    results are host arrays; device memory is the server's own."""
+
+    def __init__(self, device: int = 0, factor_precision: int = 64, max_active: int = 4,
+                 hbm_budget_bytes: float = 0.0):
+        self.h = bddc_server_create(bddc_server_options(device, factor_precision, max_active,
+                                                        float(hbm_budget_bytes)))
+        self._n = {}
+
+    def submit(self, prob, tau=0.0, mode="ce", rtol=1e-8, maxit=1000):
+        mesh, part, cons, _arrays = _marshal(prob, mode)
+        rid = bddc_server_submit(self.h, mesh, part, cons, tau, prob.f,
+                                 bddc_pcg_params(rtol, maxit))
+        self._n[rid] = int(np.asarray(prob.f).shape[0])
+        return rid
+
+    def wait(self, rid):
+        return bddc_server_wait(self.h, rid, self._n[rid])
+
+    def query(self, rid):
+        return bddc_server_query(self.h, rid)
+
+    def release(self, rid):
+        bddc_server_release(self.h, rid)
+        self._n.pop(rid, None)
+
+    def close(self):
+        if self.h is not None:
+            bddc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BDDC:
@@ -259,18 +377,7 @@ class BDDC:
             pass
 
     def setup(self, prob, mode="ce", augment_corners=True, qr_drop_tol=1e-10):
-        xyz = np.ascontiguousarray(prob.xyz, dtype=np.float64)
-        hex8 = np.ascontiguousarray(prob.hex8, dtype=np.int64)
-        coef = np.ascontiguousarray(prob.coef, dtype=np.float64)
-        dirichlet = np.ascontiguousarray(prob.dirichlet, dtype=np.uint8)
-        elem_sub = np.ascontiguousarray(prob.elem_sub, dtype=np.int32)
-        self._arrays = (xyz, hex8, coef, dirichlet, elem_sub)
-        mesh = bddc_mesh(int(prob.kind), xyz.shape[0], _ptr(xyz, C.c_double), hex8.shape[0],
-                         _ptr(hex8, C.c_int64), _ptr(coef, C.c_double), float(prob.nu),
-                         _ptr(dirichlet, C.c_uint8))
-        part = bddc_partition(int(prob.n_sub), _ptr(elem_sub, C.c_int32))
-        cons = bddc_constraints(MODES[mode] if isinstance(mode, str) else int(mode),
-                                1 if augment_corners else 0, float(qr_drop_tol))
+        mesh, part, cons, self._arrays = _marshal(prob, mode, augment_corners, qr_drop_tol)
         bddc_setup(self.h, mesh, part, cons)
         self.n_glob = self.info().n_glob
 

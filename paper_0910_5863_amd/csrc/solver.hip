@@ -1529,7 +1529,9 @@ PcgResult Solver::pcg(const double *f, double *u, double rtol, int maxit) {
     conv = h[2] != 0;
     std::vector<double> hist(it + 1);
     if (it > 0)
-      HIPCHK(hipMemcpy(hist.data(), d_pcg_hist.p, sizeof(double) * (it + 1), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpyAsync(hist.data(), d_pcg_hist.p, sizeof(double) * (it + 1), hipMemcpyDeviceToHost,
+                            st));
+    HIPCHK(hipStreamSynchronize(st));
     for (int k = 1; k <= it; ++k) res.history.push_back(hist[k]);
     if (it > 0) rel = hist[it];
   }

@@ -1,0 +1,117 @@
+"""Request server (bddc_server_*): continuous admission by footprint, work of
+concurrent requests overlapping on the device, results independent of the
+mix.
+
+Tolerance: 0.  Every kernel is deterministic and no reduction crosses
+requests, so each request's solution must have the same bits whether it runs
+alone or among others, and the same bits as a direct context solve.
+"""
+import numpy as np
+import pytest
+
+import meshgen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0910_5863_amd import BDDC, Server
+    return BDDC, Server
+
+
+def _requests():
+    """Eight small requests in the serving recipe: Poisson and elasticity,
+    8^3-16^3 elements, 2^3 substructures, layered contrast, half of them
+    with adaptive face constraints."""
+    specs = [
+        (meshgen.POISSON, 8, 1e0, 0.0), (meshgen.ELASTICITY, 8, 1e3, 10.0),
+        (meshgen.POISSON, 12, 1e4, 0.0), (meshgen.ELASTICITY, 12, 1e2, 10.0),
+        (meshgen.POISSON, 16, 1e2, 2.0), (meshgen.ELASTICITY, 8, 1e5, 0.0),
+        (meshgen.ELASTICITY, 12, 1e0, 10.0), (meshgen.POISSON, 12, 1e6, 10.0),
+    ]
+    out = []
+    for i, (kind, n, contrast, tau) in enumerate(specs):
+        req = dict(id=i, kind=kind, n=n, s=2, contrast=contrast, seed=1000 + i)
+        out.append((meshgen.request_problem(req), tau))
+    return out
+
+
+def test_server_results_alone_and_in_the_mix():
+    BDDC, Server = _gpu()
+    reqs = _requests()
+    # alone: one request in flight at a time, each waited for before the next
+    alone = []
+    srv = Server(max_active=1)
+    for p, tau in reqs:
+        rid = srv.submit(p, tau)
+        u, info = srv.wait(rid)
+        assert info.state == 2, info.error
+        alone.append((u, info))
+    srv.close()
+    # in the mix: all submitted at once, four workers, a budget that fits
+    # about three of the largest footprints at a time
+    fps = sorted(info.footprint_bytes for _, info in alone)
+    budget = 3.0 * fps[-1]
+    srv = Server(max_active=4, hbm_budget_bytes=budget)
+    ids = [srv.submit(p, tau) for p, tau in reqs]
+    mix = [srv.wait(i) for i in ids]
+    srv.close()
+    for (ua, ia), (um, im) in zip(alone, mix):
+        assert im.state == 2, im.error
+        assert ia.pcg.converged and im.pcg.converged
+        assert ia.pcg.iters == im.pcg.iters
+        assert np.array_equal(ua, um)
+        assert ia.nc == im.nc and ia.omega == im.omega
+    # admission: whenever a request started, the requests then in flight
+    # (itself included) fit in the budget, unless it ran alone
+    for i, (_, im) in enumerate(mix):
+        live = [m for _, m in mix if m.start_s <= im.start_s < m.done_s]
+        if len(live) > 1:
+            assert sum(m.footprint_bytes for m in live) <= budget * (1 + 1e-12)
+    # overlap: some requests were in flight together
+    assert any(sum(1 for _, m in mix if m.start_s <= im.start_s < m.done_s) > 1 for _, im in mix)
+    # the same bits as a direct context solve
+    p, tau = reqs[3]
+    b = BDDC()
+    b.setup(p, "ce")
+    if tau > 0:
+        b.adapt(tau)
+    b.factor()
+    u, _ = b.pcg_solve(torch.from_numpy(p.f))
+    assert np.array_equal(u.cpu().numpy()[:, 0], alone[3][0])
+    b.close()
+
+
+def test_server_solution_solves_the_assembled_system():
+    _, Server = _gpu()
+    from oracle.fem import Substructures
+    p, tau = _requests()[1]
+    srv = Server(max_active=2)
+    u, info = srv.wait(srv.submit(p, tau))
+    srv.close()
+    assert info.state == 2, info.error
+    K = Substructures(p).assembled()
+    r = np.linalg.norm(p.f - K @ u) / np.linalg.norm(p.f)
+    assert r < 1e-7, r
+
+
+def test_server_reports_request_errors():
+    """A load of the wrong length fails that request only (BDDC_ERR_ARG in
+    its record); the next request is served normally."""
+    _, Server = _gpu()
+    from paper_0910_5863_amd import binding
+    p, _ = _requests()[0]
+    srv = Server(max_active=1)
+    mesh, part, cons, _arrays = binding._marshal(p, "ce")
+    f = np.ones(p.f.shape[0] + 1)
+    rid = binding.bddc_server_submit(srv.h, mesh, part, cons, 0.0, f, binding.bddc_pcg_params(0, 0))
+    srv._n[rid] = f.shape[0]
+    u, info = srv.wait(rid)
+    assert info.state == 3 and info.status == 1
+    ok = srv.submit(p)
+    u, info = srv.wait(ok)
+    assert info.state == 2
+    srv.close()
