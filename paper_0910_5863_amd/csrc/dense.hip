@@ -186,8 +186,9 @@ __global__ __launch_bounds__(256) void chol_update_kernel(T *pool, const MatDesc
 
 // Factor the diagonal block of block column k in LDS, in place, and write
 // the inverse of the factored block to dinv (entry e, block k at
-// dinv + dinv_off[e] + k NB^2, ld NB): one work-group per entry.  status[e]
-// receives (column+1) of the first non-positive pivot.
+// dinv + dinv_off[e] + k NB^2, ld NB, zero outside the w x w block): one
+// work-group per entry.  status[e] receives (column+1) of the first
+// non-positive pivot.
 template <class T>
 __global__ __launch_bounds__(256) void chol_diag_kernel(T *pool, const MatDesc *desc, int k,
                                                         int *status, int batch, T *dinv,
@@ -221,28 +222,43 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(T *pool, const MatDesc *
     if (tid == 0) D[c][c] = lcc;
     for (int r = c + 1 + tid; r < w; r += 256) D[r][c] /= lcc;
     __syncthreads();
-    const int m = w - c - 1;
-    for (int i = tid; i < m * m; i += 256) {
-      const int r = c + 1 + i % m, s = c + 1 + i / m;
-      if (r >= s) D[r][s] -= D[r][c] * D[s][c];
+    // trailing update: lane = row r, the four waves take every fourth column
+    const int r = tid & 63;
+    if (r > c && r < w) {
+      const T lrc = D[r][c];
+      for (int s = c + 1 + (tid >> 6); s <= r; s += 4) D[r][s] -= lrc * D[s][c];
     }
     __syncthreads();
   }
-  if (tid == 0 && s_fail && status) atomicCAS(&status[e], 0, s_fail);
   for (int i = tid; i < w * w; i += 256) {
     const int r = i % w, c = i / w;
     if (r >= c) A[(kb + r) + (kb + c) * lda] = D[r][c];
   }
-  // inverse of the factored block: thread j solves for column j
-  for (int i = tid; i < NB * NB; i += 256) Y[i % NB][i / NB] = T(0);
+  if (tid == 0 && s_fail && status) atomicCAS(&status[e], 0, s_fail);
+  // inverse of the factored block: lane j of wave 0 forms column j of L^-1 in
+  // registers by forward substitution against the rows of L broadcast from
+  // LDS (D holds the factor; outside the w x w block it is the identity)
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i % NB, c = i / NB;
+    if (r >= w || c >= w) D[r][c] = (r == c) ? T(1) : T(0);
+  }
   __syncthreads();
-  if (tid < w) {
+  if (tid < 64) {
     const int j = tid;
-    for (int i = j; i < w; ++i) {
-      T sacc = (i == j) ? T(1) : T(0);
-      for (int m = j; m < i; ++m) sacc -= D[i][m] * Y[m][j];
-      Y[i][j] = sacc / D[i][i];
+    T y[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      T s0 = r == j ? T(1) : T(0), s1 = T(0);
+#pragma unroll
+      for (int m = 0; m + 1 < r; m += 2) {
+        s0 -= D[r][m] * y[m];
+        s1 -= D[r][m + 1] * y[m + 1];
+      }
+      if (r & 1) s0 -= D[r][r - 1] * y[r - 1];
+      y[r] = (s0 + s1) / D[r][r];
     }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) Y[r][j] = (r < w && j < w) ? y[r] : T(0);
   }
   __syncthreads();
   T *out = dinv + dinv_off[e] + (int64_t)k * NB * NB;
