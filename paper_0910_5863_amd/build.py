@@ -16,8 +16,12 @@ SRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbddc_mi355x.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# -amdgpu-mfma-vgpr-form: matrix-core accumulators stay in ordinary VGPRs;
+# otherwise the GEMM tiles' loop-carried accumulators were copied into the
+# accumulation registers and back at every K-step, draining the MFMA pipe
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 
 
