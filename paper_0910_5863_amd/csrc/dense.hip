@@ -67,22 +67,31 @@ __device__ __forceinline__ bool xcd_remap(int nwg, int tiles_per_entry, int batc
 }
 
 // C[m0:m0+TM, n0:n0+TN] = beta*C + alpha*op(A)*op(B), bounds-checked, with
-// TM = 32 MT and TN = 32 NT: the four waves own 2 x 2 quadrants of MT x NT
-// MFMA blocks of 16 x 16.  Operands go through LDS in K-steps of BK; the next
-// step's operands are loaded into registers while the current one is
-// multiplied.  A or B may alias C (in-place products of one tile): every
+// TM = 32 MT and TN = 32 NT: in each group of four waves, the waves own 2 x 2
+// quadrants of MT x NT MFMA blocks of 16 x 16.  Operands go through two LDS
+// buffers per group in K-steps of BK: the next step's operands are loaded
+// into registers while the current step is multiplied from one buffer, then
+// stored into the other, so one barrier per step suffices.  With KS > 1 the
+// work-group has KS groups (256 KS threads) that take every KS-th K-step of
+// the same tile; their partial products are summed through LDS in group
+// order (deterministic) -- more waves per tile where a launch has few tiles
+// and long K.  A or B may alias C (in-place products of one tile): every
 // operand element a work-group reads lies in its own C tile or is read before
 // the tile is written.
-template <class T, bool TA, bool TB, int MT, int NT>
+template <class T, bool TA, bool TB, int MT, int NT, int KS = 1>
 __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int lda, int ldb,
                           int ldc, T alpha, T beta, int m0, int n0) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int TM = 32 * MT, TN = 32 * NT;
   constexpr int LA = TM * BK / 256, LB = TN * BK / 256;
-  __shared__ T As[BK][TM + 2];
-  __shared__ T Bs[BK][TN + 2];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int SA = BK * (TM + 2), SB = BK * (TN + 2);      // one buffer of A / B
+  constexpr int PART = 256 * MT * NT * 4;                     // one group's partial tile
+  constexpr int SOPS = KS * 2 * (SA + SB), SRED = (KS - 1) * PART;
+  __shared__ T smem[SOPS > SRED ? SOPS : SRED];
+  const int tid = threadIdx.x % 256, g = threadIdx.x / 256;
+  const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
+  T *As = smem + g * 2 * SA, *Bs = smem + KS * 2 * SA + g * 2 * SB;
   v4 acc[MT][NT];
 #pragma unroll
   for (int x = 0; x < MT; ++x)
@@ -105,34 +114,71 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
       rb[it] = (gc < N && gk < K) ? (TB ? B[gc + (int64_t)gk * ldb] : B[gk + (int64_t)gc * ldb]) : T(0);
     }
   };
-  gload(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    __syncthreads();  // the previous step's reads of LDS are done
+  auto lstore = [&](int buf) {
+    T *as = As + buf * SA, *bs = Bs + buf * SB;
 #pragma unroll
     for (int it = 0; it < LA; ++it) {
       const int e = tid + it * 256;
-      As[TA ? e % BK : e / TM][TA ? e / BK : e % TM] = ra[it];
+      as[(TA ? e % BK : e / TM) * (TM + 2) + (TA ? e / BK : e % TM)] = ra[it];
     }
 #pragma unroll
     for (int it = 0; it < LB; ++it) {
       const int e = tid + it * 256;
-      Bs[TB ? e / TN : e % BK][TB ? e % TN : e / BK] = rb[it];
+      bs[(TB ? e / TN : e % BK) * (TN + 2) + (TB ? e % TN : e / BK)] = rb[it];
     }
+  };
+  const int nsteps = (K + BK - 1) / BK, rounds = (nsteps + KS - 1) / KS;
+  int step = g;  // this group's K-steps: g, g + KS, ...
+  if (step < nsteps) {
+    gload(step * BK);
+    lstore(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int it = 0; it < rounds; ++it, step += KS) {
+    const bool more = step + KS < nsteps;
+    if (more) gload((step + KS) * BK);
+    if (step < nsteps) {
+      const T *as = As + buf * SA, *bs = Bs + buf * SB;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int k = kk + (lane >> 4), l16 = lane & 15;
+        T a[MT], b[NT];
+#pragma unroll
+        for (int x = 0; x < MT; ++x) a[x] = as[k * (TM + 2) + wr * 16 * MT + 16 * x + l16];
+#pragma unroll
+        for (int y = 0; y < NT; ++y) b[y] = bs[k * (TN + 2) + wc * 16 * NT + 16 * y + l16];
+#pragma unroll
+        for (int x = 0; x < MT; ++x)
+#pragma unroll
+          for (int y = 0; y < NT; ++y) acc[x][y] = Mfma<T>::op(a[x], b[y], acc[x][y]);
+      }
+    }
+    // the other buffer was last read before the previous barrier
+    if (more) lstore(buf ^ 1);
     __syncthreads();
-    if (k0 + BK < K) gload(k0 + BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int k = kk + (lane >> 4), l16 = lane & 15;
-      T a[MT], b[NT];
-#pragma unroll
-      for (int x = 0; x < MT; ++x) a[x] = As[k][wr * 16 * MT + 16 * x + l16];
-#pragma unroll
-      for (int y = 0; y < NT; ++y) b[y] = Bs[k][wc * 16 * NT + 16 * y + l16];
+    buf ^= 1;
+  }
+  if (KS > 1) {
+    // partial tiles of groups 1.. through LDS (operand buffers are free now)
+    auto ridx = [&](int x, int y, int j) { return (((wave * MT + x) * NT + y) * 4 + j) * 64 + lane; };
+    if (g > 0) {
 #pragma unroll
       for (int x = 0; x < MT; ++x)
 #pragma unroll
-        for (int y = 0; y < NT; ++y) acc[x][y] = Mfma<T>::op(a[x], b[y], acc[x][y]);
+        for (int y = 0; y < NT; ++y)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) smem[(g - 1) * PART + ridx(x, y, j)] = acc[x][y][j];
     }
+    __syncthreads();
+    if (g > 0) return;
+    for (int q = 0; q < KS - 1; ++q)
+#pragma unroll
+      for (int x = 0; x < MT; ++x)
+#pragma unroll
+        for (int y = 0; y < NT; ++y)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[x][y][j] += smem[q * PART + ridx(x, y, j)];
   }
 #pragma unroll
   for (int x = 0; x < MT; ++x)
@@ -169,19 +215,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T *A, const T *B, T *C,
 // --- Cholesky -------------------------------------------------------------
 
 // Left-looking update of block column k: A[kb:, kb:kb+w] -= A[kb:, :kb] A[kb:kb+w, :kb]^T
-template <class T>
-__global__ __launch_bounds__(256) void chol_update_kernel(T *pool, const MatDesc *desc, int k,
-                                                          int tm, int batch) {
+// MT = 4, KS = 1: 128-row tiles; MT = 2, KS = 2: 64-row tiles with two
+// groups of waves splitting K (for launches with few tiles and long K)
+template <class T, int MT, int KS>
+__global__ __launch_bounds__(256 * KS) void chol_update_kernel(T *pool, const MatDesc *desc, int k,
+                                                               int tm, int batch) {
+  constexpr int TM = 32 * MT;
   int e, t;
   if (!xcd_remap(gridDim.x, tm, batch, e, t)) return;
   const MatDesc d = desc[e];
   const int kb = k * NB;
   if (kb >= d.n || k == 0) return;
   const int M = d.n - kb, N = min(NB, d.n - kb), K = kb;
-  if (t * 128 >= M) return;
+  if (t * TM >= M) return;
   T *A = pool + d.a_off;
-  gemm_tile<T, false, true, 4, 2>(A + kb, A + kb, A + kb + (int64_t)kb * d.lda, M, N, K, d.lda,
-                                  d.lda, d.lda, T(-1), T(1), t * 128, 0);
+  gemm_tile<T, false, true, MT, 2, KS>(A + kb, A + kb, A + kb + (int64_t)kb * d.lda, M, N, K,
+                                       d.lda, d.lda, d.lda, T(-1), T(1), t * TM, 0);
 }
 
 // Factor the diagonal block of block column k in LDS, in place, and write
@@ -664,7 +713,14 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
       }
     if (k > 0) {
       LaunchScope ls(st, "chol_update_kernel", bu, fu);
-      chol_update_kernel<T><<<grid_round(batch * tu), 256, 0, st>>>(pool, d_desc, k, tu, batch);
+      if (batch * tu >= 512) {
+        chol_update_kernel<T, 4, 1><<<grid_round(batch * tu), 256, 0, st>>>(pool, d_desc, k, tu,
+                                                                           batch);
+      } else {
+        const int t64 = (maxn - k * NB + 63) / 64;
+        chol_update_kernel<T, 2, 2><<<grid_round(batch * t64), 512, 0, st>>>(pool, d_desc, k, t64,
+                                                                             batch);
+      }
     }
     {
       LaunchScope ls(st, "chol_diag_kernel", bd, fd);
