@@ -340,28 +340,31 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc 
 
 // forward: B[kb:kb+w, :] -= L[kb:kb+w, :kb] B[:kb, :]
 // backward: B[kb:kb+w, :] -= L[kb+w:n, kb:kb+w]^T B[kb+w:n, :]
-template <class T, bool BWD>
-__global__ __launch_bounds__(256) void trsm_update_kernel(const T *apool, T *bpool,
-                                                          const MatDesc *desc, int k, int tn,
-                                                          int batch) {
+// NT = 4, KS = 1: 128-column tiles; NT = 2, KS = 2: 64-column tiles with two
+// groups of waves splitting K (few right-hand sides, long K)
+template <class T, bool BWD, int NT, int KS>
+__global__ __launch_bounds__(256 * KS) void trsm_update_kernel(const T *apool, T *bpool,
+                                                               const MatDesc *desc, int k, int tn,
+                                                               int batch) {
+  constexpr int TN = 32 * NT;
   int e, t;
   if (!xcd_remap(gridDim.x, tn, batch, e, t)) return;
   const MatDesc d = desc[e];
   const int kb = k * NB;
   if (kb >= d.n) return;
   const int w = min(NB, d.n - kb);
-  if (t * 128 >= d.nrhs) return;
+  if (t * TN >= d.nrhs) return;
   const T *L = apool + d.a_off;
   T *B = bpool + d.b_off;
   if (!BWD) {
     if (kb == 0) return;
-    gemm_tile<T, false, false, 2, 4>(L + kb, B, B + kb, w, d.nrhs, kb, d.lda, d.ldb, d.ldb, T(-1),
-                                     T(1), 0, t * 128);
+    gemm_tile<T, false, false, 2, NT, KS>(L + kb, B, B + kb, w, d.nrhs, kb, d.lda, d.ldb, d.ldb,
+                                          T(-1), T(1), 0, t * TN);
   } else {
     const int K = d.n - kb - w;
     if (K <= 0) return;
-    gemm_tile<T, true, false, 2, 4>(L + (kb + w) + (int64_t)kb * d.lda, B + kb + w, B + kb, w,
-                                    d.nrhs, K, d.lda, d.ldb, d.ldb, T(-1), T(1), 0, t * 128);
+    gemm_tile<T, true, false, 2, NT, KS>(L + (kb + w) + (int64_t)kb * d.lda, B + kb + w, B + kb,
+                                         w, d.nrhs, K, d.lda, d.ldb, d.ldb, T(-1), T(1), 0, t * TN);
   }
 }
 
@@ -749,6 +752,21 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
   const int tn = (maxr + NB - 1) / NB;    // 64-wide column tiles (diagonal step)
   const int tu = (maxr + 127) / 128;      // 128-wide column tiles (update)
   const int nwg = grid_round(batch * tn), nwu = grid_round(batch * tu);
+  // few tiles: 64-wide tiles, two groups of waves per tile splitting K
+  const bool narrow = batch * tu < 512;
+  auto update = [&](bool bwd, int k) {
+    if (!narrow) {
+      if (bwd)
+        trsm_update_kernel<T, true, 4, 1><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tu, batch);
+      else
+        trsm_update_kernel<T, false, 4, 1><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tu, batch);
+    } else {
+      if (bwd)
+        trsm_update_kernel<T, true, 2, 2><<<nwg, 512, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+      else
+        trsm_update_kernel<T, false, 2, 2><<<nwg, 512, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+    }
+  };
   const bool timing = launch_timing() != nullptr;
   // algorithmic work at block row k: the update of the k-th block row of B
   // by the solved rows (forward: the k*NB above it; backward: the ones below)
@@ -772,7 +790,7 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
       work(k, fu, bu, fd, bd);
       if (k > 0) {
         LaunchScope ls(st, "trsm_update_kernel<fwd>", bu, fu);
-        trsm_update_kernel<T, false><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tu, batch);
+        update(false, k);
       }
       LaunchScope ls(st, "trsm_diag_kernel<fwd>", bd, fd);
       trsm_diag_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
@@ -786,7 +804,7 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
       work(k, fu, bu, fd, bd);
       {
         LaunchScope ls(st, "trsm_update_kernel<bwd>", bu, fu);
-        trsm_update_kernel<T, true><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tu, batch);
+        update(true, k);
       }
       LaunchScope ls(st, "trsm_diag_kernel<bwd>", bd, fd);
       trsm_diag_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
