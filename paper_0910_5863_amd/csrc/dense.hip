@@ -527,14 +527,22 @@ __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, con
       const int c0 = jb * NB, wc = min(NB, d.n - c0);
       const T xv = lane < wc ? ld_coherent(&x[c0 + lane]) : T(0);
       const T *row = L + rl + (int64_t)c0 * lda;
-      T a = T(0);
       if (wc == NB) {
-#pragma unroll 32
-        for (int c = 0; c < NB; ++c) a += row[(int64_t)c * lda] * readlane(xv, c);
+        // four independent partial sums, added in a fixed order
+        T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+#pragma unroll
+        for (int c = 0; c < NB; c += 4) {
+          a0 += row[(int64_t)c * lda] * readlane(xv, c);
+          a1 += row[(int64_t)(c + 1) * lda] * readlane(xv, c + 1);
+          a2 += row[(int64_t)(c + 2) * lda] * readlane(xv, c + 2);
+          a3 += row[(int64_t)(c + 3) * lda] * readlane(xv, c + 3);
+        }
+        acc += (a0 + a1) + (a2 + a3);
       } else {
+        T a = T(0);
         for (int c = 0; c < wc; ++c) a += row[(int64_t)c * lda] * readlane(xv, c);
+        acc += a;
       }
-      acc += a;
     }
     next = end;
     __syncthreads();
@@ -544,10 +552,13 @@ __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, con
     __syncthreads();
     const int c0 = last * NB;
     const T xv = lane < wl ? ld_coherent(&x[c0 + lane]) : T(0);
-    T a = T(0);
+    T a0 = T(0), a1 = T(0);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) a += pf[i] * readlane(xv, wave * 16 + i);
-    acc += a;
+    for (int i = 0; i < 16; i += 2) {
+      a0 += pf[i] * readlane(xv, wave * 16 + i);
+      a1 += pf[i + 1] * readlane(xv, wave * 16 + i + 1);
+    }
+    acc += a0 + a1;
   }
   part[wave][lane] = acc;
   __syncthreads();
@@ -559,12 +570,24 @@ __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, con
   __syncthreads();
   if (wave == 0) {
     // x_k = D^-1 v (lower) or D^-T v (upper), D^-1 lower triangular
-    T y = T(0);
-    if (!UPPER) {
-      for (int c = 0; c <= min(lane, w - 1); ++c) y += D[lane][c] * vs[c];
-    } else {
-      for (int c = lane; c < w; ++c) y += D[c][lane] * vs[c];
+    // (D is zero outside its lower triangle and vs beyond w: full-length
+    // sums with four partial sums)
+    T y0 = T(0), y1 = T(0), y2 = T(0), y3 = T(0);
+#pragma unroll 4
+    for (int c = 0; c < NB; c += 4) {
+      if (!UPPER) {
+        y0 += D[lane][c] * vs[c];
+        y1 += D[lane][c + 1] * vs[c + 1];
+        y2 += D[lane][c + 2] * vs[c + 2];
+        y3 += D[lane][c + 3] * vs[c + 3];
+      } else {
+        y0 += D[c][lane] * vs[c];
+        y1 += D[c + 1][lane] * vs[c + 1];
+        y2 += D[c + 2][lane] * vs[c + 2];
+        y3 += D[c + 3][lane] * vs[c + 3];
+      }
     }
+    const T y = (y0 + y1) + (y2 + y3);
     if (lane < w) st_coherent(&x[r0 + lane], y);
   }
   __syncthreads();
