@@ -95,6 +95,8 @@ class MfDevice {
   DBuf d_dinv_front_;                              // per front: offset of its inverses
   std::vector<int64_t> max_f_;                     // per depth: max p*f + b*b
   std::vector<int> max_pb_;                        // per depth: max p + b
+  std::vector<int> max_p_, max_b_;                 // per depth: max p, max b
+  DBuf d_zp_;                                      // solves: z of every front's pivots
   int64_t nnz_ = 0;
 };
 

@@ -161,18 +161,19 @@ __device__ void upper_solve(const double *L, int ld, int n, const double *Di, do
   }
 }
 
-// forward solve of one depth: one work-group per front
+// forward solve of one depth, pivots: one work-group per front; the
+// right-hand side at the pivots (plus the children's updates) goes through
+// L11^-1 and the result z is written to the pivots of vI and to zp
+// (p values per front at piv_off)
 __global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int *ids,
                                                      const int *child_ids, const int *pmap,
                                                      const int64_t *piv, const double *U,
                                                      const double *dinv, const int64_t *dinv_off,
-                                                     double *upd, double *vI) {
+                                                     const double *upd, double *vI, double *zp) {
   extern __shared__ double z[];
   __shared__ double tmp[TB];
   const MfFront f = F[ids[blockIdx.x]];
-  const int p = f.p, b = f.b, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nwave = blockDim.x >> 6;
-  // right-hand side at the pivots plus the children's updates
+  const int p = f.p, tid = threadIdx.x;
   for (int j = tid; j < p; j += blockDim.x) {
     double v = vI[piv[f.piv_off + j]];
     for (int ci = 0; ci < f.n_child; ++ci) {
@@ -183,23 +184,41 @@ __global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int
     z[j] = v;
   }
   __syncthreads();
+  if (p > 0) lower_solve(U + f.u_off, p, p, dinv + dinv_off[ids[blockIdx.x]], z, tmp);
+  for (int j = tid; j < p; j += blockDim.x) {
+    vI[piv[f.piv_off + j]] = z[j];
+    zp[f.piv_off + j] = z[j];
+  }
+}
+
+// forward solve of one depth, boundary: the update each front passes to its
+// parent, its children's updates at the boundary minus F12^T z; work-group
+// (front, 64-column chunk of the boundary), four columns per wave step
+__global__ __launch_bounds__(256) void mf_fupd_kernel(const MfFront *F, const int *ids, int nchunk,
+                                                      const int *child_ids, const int *pmap,
+                                                      const double *U, const double *zp,
+                                                      double *upd) {
+  extern __shared__ double z[];
+  const int fi = blockIdx.x / nchunk, i_lo = (blockIdx.x % nchunk) * 64;
+  const MfFront f = F[ids[fi]];
+  const int p = f.p, b = f.b, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (i_lo >= b) return;
+  for (int j = tid; j < p; j += blockDim.x) z[j] = zp[f.piv_off + j];
+  __syncthreads();
   const double *Uf = U + f.u_off;
-  if (p > 0) lower_solve(Uf, p, p, dinv + dinv_off[ids[blockIdx.x]], z, tmp);
-  for (int j = tid; j < p; j += blockDim.x) vI[piv[f.piv_off + j]] = z[j];
-  // update for the parent: children's updates at the boundary minus F12^T z,
-  // four columns per wave step (independent sums)
-  for (int i0 = 4 * wave; i0 < b; i0 += 4 * nwave) {
+  const int i_hi = min(b, i_lo + 64);
+  for (int i0 = i_lo + 4 * wave; i0 < i_hi; i0 += 16) {
     double acc[4] = {0, 0, 0, 0};
     for (int j = lane; j < p; j += 64) {
       const double zj = z[j];
 #pragma unroll
       for (int t = 0; t < 4; ++t)
-        if (i0 + t < b) acc[t] += Uf[j + (int64_t)(p + i0 + t) * p] * zj;
+        if (i0 + t < i_hi) acc[t] += Uf[j + (int64_t)(p + i0 + t) * p] * zj;
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t)
       for (int off = 32; off > 0; off >>= 1) acc[t] += __shfl_xor(acc[t], off, 64);
-    if (lane < 4 && i0 + lane < b) {
+    if (lane < 4 && i0 + lane < i_hi) {
       const int i = i0 + lane;
       double v = -(lane == 0 ? acc[0] : lane == 1 ? acc[1] : lane == 2 ? acc[2] : acc[3]);
       for (int ci = 0; ci < f.n_child; ++ci) {
@@ -212,30 +231,57 @@ __global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int
   }
 }
 
-// backward solve of one depth: x_p = L11^-T (y_p - F12 x_b); interface
-// boundary values are zero (pure interior solve)
-__global__ __launch_bounds__(256) void mf_bwd_kernel(const MfFront *F, const int *ids,
-                                                     const int64_t *piv, const int64_t *bnd,
-                                                     const double *U, const double *dinv,
-                                                     const int64_t *dinv_off, double *vI) {
-  extern __shared__ double sm[];
-  __shared__ double tmp[TB];
-  const MfFront f = F[ids[blockIdx.x]];
-  const int p = f.p, b = f.b, tid = threadIdx.x;
-  double *x = sm, *xb = sm + p;
+// backward solve of one depth, boundary product: zp <- y_p - F12 x_b for the
+// pivot rows of each front (interface boundary values are zero: pure
+// interior solve); work-group (front, 64-row chunk), lane = row, the four
+// waves take quarters of the boundary and are summed in a fixed order
+__global__ __launch_bounds__(256) void mf_bprod_kernel(const MfFront *F, const int *ids, int nchunk,
+                                                       const int64_t *piv, const int64_t *bnd,
+                                                       const double *U, const double *vI,
+                                                       double *zp) {
+  extern __shared__ double xb[];
+  __shared__ double part[4][64];
+  const int fi = blockIdx.x / nchunk, j_lo = (blockIdx.x % nchunk) * 64;
+  const MfFront f = F[ids[fi]];
+  const int p = f.p, b = f.b, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (j_lo >= p) return;
   for (int i = tid; i < b; i += blockDim.x) {
     const int64_t g = bnd[f.bnd_off + i];
     xb[i] = g >= 0 ? vI[g] : 0.0;
   }
   __syncthreads();
   const double *Uf = U + f.u_off;
-  for (int j = tid; j < p; j += blockDim.x) {
-    double acc = 0;
-    for (int i = 0; i < b; ++i) acc += Uf[j + (int64_t)(p + i) * p] * xb[i];
-    x[j] = vI[piv[f.piv_off + j]] - acc;
+  const int j = j_lo + lane;
+  const int q = (b + 3) / 4, i_lo = wave * q, i_hi = min(b, i_lo + q);
+  double a0 = 0, a1 = 0;
+  if (j < p) {
+    int i = i_lo;
+    for (; i + 1 < i_hi; i += 2) {
+      a0 += Uf[j + (int64_t)(p + i) * p] * xb[i];
+      a1 += Uf[j + (int64_t)(p + i + 1) * p] * xb[i + 1];
+    }
+    if (i < i_hi) a0 += Uf[j + (int64_t)(p + i) * p] * xb[i];
   }
+  part[wave][lane] = a0 + a1;
   __syncthreads();
-  if (p > 0) upper_solve(Uf, p, p, dinv + dinv_off[ids[blockIdx.x]], x, tmp);
+  if (wave == 0 && j < p)
+    zp[f.piv_off + j] =
+        vI[piv[f.piv_off + j]] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
+}
+
+// backward solve of one depth, pivots: x_p = L11^-T zp (zp from
+// mf_bprod_kernel); one work-group per front
+__global__ __launch_bounds__(256) void mf_bwd_kernel(const MfFront *F, const int *ids,
+                                                     const int64_t *piv, const double *U,
+                                                     const double *dinv, const int64_t *dinv_off,
+                                                     const double *zp, double *vI) {
+  extern __shared__ double x[];
+  __shared__ double tmp[TB];
+  const MfFront f = F[ids[blockIdx.x]];
+  const int p = f.p, tid = threadIdx.x;
+  for (int j = tid; j < p; j += blockDim.x) x[j] = zp[f.piv_off + j];
+  __syncthreads();
+  if (p > 0) upper_solve(U + f.u_off, p, p, dinv + dinv_off[ids[blockIdx.x]], x, tmp);
   for (int j = tid; j < p; j += blockDim.x) vI[piv[f.piv_off + j]] = x[j];
 }
 
@@ -263,7 +309,7 @@ inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 
 void MfDevice::release(DevAlloc &A) {
   for (DBuf *b : {&d_fronts_, &d_child_, &d_piv_, &d_bnd_, &d_pmap_, &d_asm_, &d_root_ptr_,
                   &d_root_ids_, &d_U_, &d_C_, &d_upd_, &d_status_, &d_level_ids_, &d_dinv_,
-                  &d_dinv_front_}) {
+                  &d_dinv_front_, &d_zp_}) {
     if (b->p) A.put(b->p, b->bytes);
     *b = DBuf();
   }
@@ -278,7 +324,8 @@ void MfDevice::release(DevAlloc &A) {
 size_t MfDevice::bytes() const {
   size_t t = 0;
   for (const DBuf *b : {&d_fronts_, &d_child_, &d_piv_, &d_bnd_, &d_pmap_, &d_asm_, &d_root_ptr_,
-                        &d_root_ids_, &d_U_, &d_C_, &d_upd_, &d_status_, &d_level_ids_})
+                        &d_root_ids_, &d_U_, &d_C_, &d_upd_, &d_status_, &d_level_ids_, &d_dinv_,
+                        &d_dinv_front_, &d_zp_})
     t += b->bytes;
   return t;
 }
@@ -309,6 +356,8 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
   h_gemm_.assign(D + 1, {});
   max_f_.assign(D + 1, 0);
   max_pb_.assign(D + 1, 0);
+  max_p_.assign(D + 1, 0);
+  max_b_.assign(D + 1, 0);
   for (int d = 0; d <= D; ++d) {
     level_off_[d] = (int64_t)ids.size();
     for (int t : M.levels[d]) {
@@ -316,6 +365,8 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
       const MfFront &f = M.fronts[t];
       max_f_[d] = std::max<int64_t>(max_f_[d], (int64_t)f.p * (f.p + f.b) + (int64_t)f.b * f.b);
       max_pb_[d] = std::max(max_pb_[d], f.p + f.b);
+      max_p_[d] = std::max(max_p_[d], f.p);
+      max_b_[d] = std::max(max_b_[d], f.b);
       if (f.p == 0) continue;
       h_potrf_[d].push_back(MatDesc{f.u_off, 0, f.p, 0, f.p, f.p});
       if (f.b == 0) continue;
@@ -361,17 +412,18 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
     }
     d_dinv_front_ = upload(A, st, fo);
   }
-  // the in-front solves keep p + b values in LDS
+  // z of every front's pivots between the two launches of a depth
+  d_zp_ = zeros(A, st, sizeof(double) * std::max<size_t>(1, M.piv.size()));
+  // the in-front solves keep p values (boundary products: b values) in LDS
   int max_lds = 0;
-  for (int d = 1; d <= D; ++d) max_lds = std::max(max_lds, max_pb_[d]);
-  if ((size_t)max_lds * sizeof(double) > 160 * 1024)
+  for (int d = 1; d <= D; ++d) max_lds = std::max(max_lds, std::max(max_p_[d], max_b_[d]));
+  if ((size_t)max_lds * sizeof(double) > 150 * 1024)
     throw ArgError("a front of the interior elimination exceeds the LDS of one work-group");
-  if ((size_t)max_lds * sizeof(double) > 64 * 1024) {
-    HIPCHK(hipFuncSetAttribute((const void *)mf_bwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(max_lds * sizeof(double))));
-    HIPCHK(hipFuncSetAttribute((const void *)mf_fwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(max_lds * sizeof(double))));
-  }
+  if ((size_t)max_lds * sizeof(double) > 64 * 1024)
+    for (const void *k : {(const void *)mf_bwd_kernel, (const void *)mf_fwd_kernel,
+                          (const void *)mf_fupd_kernel, (const void *)mf_bprod_kernel})
+      HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(max_lds * sizeof(double))));
   HIPCHK(hipStreamSynchronize(st));
   ready = true;
 }
@@ -457,30 +509,57 @@ void MfDevice::solve(hipStream_t st, double *vI) {
   const int *ids = d_level_ids_.as<int>();
   const double *U = d_U_.as<double>();
   double *upd = d_upd_.as<double>();
-  auto level_bytes = [&](int d) {
+  // bytes of the pivot (triangle) and boundary (F12) parts of a depth
+  auto tri_bytes = [&](int d) {
     double by = 0;
     for (int t : M.levels[d]) {
       const MfFront &f = M.fronts[t];
-      by += 8.0 * (0.5 * (double)f.p * (f.p + 1) + (double)f.p * f.b + 2.0 * f.p + f.b);
+      by += 8.0 * (0.5 * (double)f.p * (f.p + 1) + 3.0 * f.p);
     }
     return by;
   };
+  auto f12_bytes = [&](int d) {
+    double by = 0;
+    for (int t : M.levels[d]) {
+      const MfFront &f = M.fronts[t];
+      by += 8.0 * ((double)f.p * f.b + f.p + 2.0 * f.b);
+    }
+    return by;
+  };
+  const bool tm = launch_timing() != nullptr;
+  double *zp = d_zp_.as<double>();
   for (int d = M.max_depth; d >= 1; --d) {
     const int nf = (int)M.levels[d].size();
     if (nf == 0) continue;
-    LaunchScope ls(st, "mf_fwd_kernel", launch_timing() ? level_bytes(d) : 0, 0);
-    mf_fwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_pb_[d]), st>>>(
-        F, ids + level_off_[d], d_child_.as<int>(), d_pmap_.as<int>(), d_piv_.as<int64_t>(), U,
-        d_dinv_.as<double>(), d_dinv_front_.as<int64_t>(), upd, vI);
+    {
+      LaunchScope ls(st, "mf_fwd_kernel", tm ? tri_bytes(d) : 0, 0);
+      mf_fwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
+          F, ids + level_off_[d], d_child_.as<int>(), d_pmap_.as<int>(), d_piv_.as<int64_t>(), U,
+          d_dinv_.as<double>(), d_dinv_front_.as<int64_t>(), upd, vI, zp);
+    }
+    const int nc = (max_b_[d] + 63) / 64;
+    if (nc > 0) {
+      LaunchScope ls(st, "mf_fupd_kernel", tm ? f12_bytes(d) : 0, 0);
+      mf_fupd_kernel<<<nf * nc, TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
+          F, ids + level_off_[d], nc, d_child_.as<int>(), d_pmap_.as<int>(), U, zp, upd);
+    }
     HIPCHK(hipGetLastError());
   }
   for (int d = 1; d <= M.max_depth; ++d) {
     const int nf = (int)M.levels[d].size();
     if (nf == 0) continue;
-    LaunchScope ls(st, "mf_bwd_kernel", launch_timing() ? level_bytes(d) : 0, 0);
-    mf_bwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_pb_[d]), st>>>(
-        F, ids + level_off_[d], d_piv_.as<int64_t>(), d_bnd_.as<int64_t>(), U, d_dinv_.as<double>(),
-        d_dinv_front_.as<int64_t>(), vI);
+    const int nc = (max_p_[d] + 63) / 64;
+    if (nc > 0) {
+      LaunchScope ls(st, "mf_bprod_kernel", tm ? f12_bytes(d) : 0, 0);
+      mf_bprod_kernel<<<nf * nc, TPB, sizeof(double) * std::max(1, max_b_[d]), st>>>(
+          F, ids + level_off_[d], nc, d_piv_.as<int64_t>(), d_bnd_.as<int64_t>(), U, vI, zp);
+    }
+    {
+      LaunchScope ls(st, "mf_bwd_kernel", tm ? tri_bytes(d) : 0, 0);
+      mf_bwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
+          F, ids + level_off_[d], d_piv_.as<int64_t>(), U, d_dinv_.as<double>(),
+          d_dinv_front_.as<int64_t>(), zp, vI);
+    }
     HIPCHK(hipGetLastError());
   }
 }
