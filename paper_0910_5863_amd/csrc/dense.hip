@@ -413,13 +413,31 @@ __device__ __forceinline__ void st_coherent(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Completion flags of the one-right-hand-side solves.  Everything that
+// crosses work-groups in those kernels (the flags and the solved entries of x)
+// is read and written with device-coherent atomic accesses, so a flag needs
+// only ordering, not cache maintenance: the producer waits for its x stores
+// to complete before the flag store (workgroup-scope release: a store-counter
+// wait), and the consumer's x loads are issued after the flag load returned
+// (workgroup-scope acquire).  Agent-scope fences would write back and
+// invalidate the whole L2 of the XCD at every block, evicting the cached
+// factor tiles of every other work-group.
+// (called by a lane of the wave that stored the entries: s_waitcnt vmcnt(0),
+// encoded for gfx9 with expcnt and lgkmcnt left at their maxima, waits until
+// those device-coherent stores are acknowledged)
+__device__ __forceinline__ void flag_publish(int *flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Bounded spin on a completion flag: the block waited on holds a smaller
 // ticket, so it is resident or done; the bound only guards against an earlier
-// fault.  The spin reads relaxed; one acquire fence follows success.
+// fault.
 __device__ bool wait_flag(int *flag, int *err) {
   for (long it = 0; it < (1L << 26); ++it) {
     if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-      __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       return true;
     }
     __builtin_amdgcn_s_sleep(1);
@@ -430,7 +448,7 @@ __device__ bool wait_flag(int *flag, int *err) {
 
 __device__ __forceinline__ bool flag_set(int *flag) {
   if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return false;
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   return true;
 }
 
@@ -592,8 +610,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, con
   }
   __syncthreads();
   if (tid == 0) {
-    __threadfence();
-    __hip_atomic_store(&flags[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    flag_publish(&flags[k]);
     if (!s_ok) atomicExch(err, 1);
   }
 }
