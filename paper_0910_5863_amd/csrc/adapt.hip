@@ -1019,65 +1019,51 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
     doff = pool.up(stream, off);
   };
   const int nside = 2 * np;
-  std::vector<int64_t> src_off(nside), off_nn(nside), off_ns(nside), off_sh(nside), off_ss(nside);
-  std::vector<int> lds(nside), nn(nside), nsv(nside);
-  std::vector<int> idx_s, idx_n;
-  std::vector<int64_t> idx_s_off(nside), idx_n_off(nside);
-  int64_t tnn = 0, tns = 0, tsh = 0;
-  int max_nn = 0, max_ns = 0;
+  // Schur complement of S_a onto the shared dofs s of each pair side, in two
+  // eliminations that the sides of one substructure share: the sides are
+  // grouped three at a time (in pair order); for a group with shared-dof
+  // union U, the rest N of the interface is eliminated once (S_U = S_UU -
+  // S_UN S_NN^-1 S_NU), then each side eliminates U \ s from S_U.  Equal to
+  // eliminating everything but s at once (quotient property of Schur
+  // complements), with far fewer flops.
+  std::vector<int> nsv(nside);
+  std::vector<int64_t> off_sh(nside), off_ss(nside);
+  int64_t tsh = 0;
+  int max_ns = 0;
   for (int p = 0; p < np; ++p)
     for (int a = 0; a < 2; ++a) {
-      const int e = 2 * p + a, sub = pairs[p].sub[a];
-      src_off[e] = L.offGG[sub];
-      lds[e] = L.nG[sub];
-      nn[e] = (int)pairs[p].pos_n[a].size();
+      const int e = 2 * p + a;
       nsv[e] = (int)pairs[p].pos_s[a].size();
-      max_nn = std::max(max_nn, nn[e]);
       max_ns = std::max(max_ns, nsv[e]);
-      off_nn[e] = tnn;
-      tnn += (int64_t)nn[e] * nn[e];
-      off_ns[e] = tns;
-      tns += (int64_t)nn[e] * nsv[e];
       off_sh[e] = tsh;
       off_ss[e] = tsh + (int64_t)nsv[e] * nsv[e];
       tsh += 2 * (int64_t)nsv[e] * nsv[e];
-      idx_s_off[e] = (int64_t)idx_s.size();
-      idx_s.insert(idx_s.end(), pairs[p].pos_s[a].begin(), pairs[p].pos_s[a].end());
-      idx_n_off[e] = (int64_t)idx_n.size();
-      idx_n.insert(idx_n.end(), pairs[p].pos_n[a].begin(), pairs[p].pos_n[a].end());
     }
-  double *Snn = pool.zeros(stream, tnn), *Sns = pool.zeros(stream, tns), *Sh = pool.zeros(stream, tsh);
-  int64_t *d_src_off = pool.up(stream, src_off);
-  int *d_lds = pool.up(stream, lds), *d_nn = pool.up(stream, nn), *d_ns = pool.up(stream, nsv);
-  int *d_idx_s = pool.up(stream, idx_s), *d_idx_n = pool.up(stream, idx_n);
-  int64_t *d_idx_s_off = pool.up(stream, idx_s_off), *d_idx_n_off = pool.up(stream, idx_n_off);
-  int64_t *d_off_nn = pool.up(stream, off_nn), *d_off_ns = pool.up(stream, off_ns);
-  int64_t *d_off_sh = pool.up(stream, off_sh), *d_off_ss = pool.up(stream, off_ss);
-  const double *Sd = S.d_S.as<double>();
-  auto gather = [&](double *dst, const int64_t *doff, const int *ri, const int64_t *rio, const int *nr,
-                    const int *ci, const int64_t *cio, const int *ncl, int64_t maxe) {
-    gather_rc_kernel<<<dim3(nblocks(maxe), nside), TPB, 0, stream>>>(Sd, d_src_off, d_lds, dst, doff, ri,
-                                                                     rio, nr, ci, cio, ncl);
-    HIPCHK(hipGetLastError());
+  struct SideGroup {
+    int sub;
+    std::vector<int> sides, U, N;
   };
-  gather(Snn, d_off_nn, d_idx_n, d_idx_n_off, d_nn, d_idx_n, d_idx_n_off, d_nn, (int64_t)max_nn * max_nn);
-  gather(Sns, d_off_ns, d_idx_n, d_idx_n_off, d_nn, d_idx_s, d_idx_s_off, d_ns, (int64_t)max_nn * max_ns);
-  gather(Sh, d_off_sh, d_idx_s, d_idx_s_off, d_ns, d_idx_s, d_idx_s_off, d_ns, (int64_t)max_ns * max_ns);
-  gather(Sh, d_off_ss, d_idx_s, d_idx_s_off, d_ns, d_idx_s, d_idx_s_off, d_ns, (int64_t)max_ns * max_ns);
-  std::vector<MatDesc> mdn(nside);
-  std::vector<GemmDesc> gsh(nside);
-  for (int e = 0; e < nside; ++e) {
-    mdn[e] = MatDesc{off_nn[e], off_ns[e], nn[e], nsv[e], std::max(1, nn[e]), std::max(1, nn[e])};
-    gsh[e] = GemmDesc{off_ns[e], off_ns[e], off_sh[e], nsv[e], nsv[e], nn[e], std::max(1, nn[e]),
-                      std::max(1, nn[e]), std::max(1, nsv[e])};
+  std::vector<SideGroup> groups;
+  {
+    std::vector<std::vector<int>> by_sub(L.nsub);
+    for (int e = 0; e < nside; ++e) by_sub[pairs[e / 2].sub[e % 2]].push_back(e);
+    for (int sb = 0; sb < L.nsub; ++sb)
+      for (size_t k = 0; k < by_sub[sb].size(); k += 3) {
+        SideGroup g;
+        g.sub = sb;
+        std::vector<char> in(L.nG[sb], 0);
+        for (size_t t = k; t < std::min(by_sub[sb].size(), k + 3); ++t) {
+          const int e = by_sub[sb][t];
+          g.sides.push_back(e);
+          for (int q : pairs[e / 2].pos_s[e % 2]) in[q] = 1;
+        }
+        for (int q = 0; q < L.nG[sb]; ++q) (in[q] ? g.U : g.N).push_back(q);
+        groups.push_back(std::move(g));
+      }
   }
-  MatDesc *d_mdn = pool.up(stream, mdn);
-  GemmDesc *d_gsh = pool.up(stream, gsh);
-  int *d_stat = pool.up(stream, std::vector<int>(3 * np + 2 * nside + 4, 0));
-  double *dv_n;
-  int64_t *do_n;
-  dinv_for(mdn, dv_n, do_n);
-  HIPCHK(DenseOps<double>::potrf(stream, Snn, d_mdn, mdn.data(), nside, d_stat, dv_n, do_n));
+  const int ng = (int)groups.size();
+  const double *Sd = S.d_S.as<double>();
+  int *d_stat = pool.up(stream, std::vector<int>(3 * np + 2 * nside + 2 * ng + 4, 0));
   auto check = [&](int first, int count, const char *what) {
     std::vector<int> hs(count);
     HIPCHK(hipMemcpyAsync(hs.data(), d_stat + first, sizeof(int) * count, hipMemcpyDeviceToHost, stream));
@@ -1090,11 +1076,127 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
                         " factors with a non-positive pivot (first entry " + std::to_string(firstbad) +
                         "); Assumption 2 may not hold");
   };
+  // one gather + Cholesky + TRSM + GEMM pass: for entry e, from the matrix at
+  // src + src_off[e] (ld lds[e]), with index lists n (eliminated) and u (kept)
+  // of it: Out (u x u) = S_uu - S_un S_nn^-1 S_nu
+  auto eliminate = [&](const double *src, const std::vector<int64_t> &src_off,
+                       const std::vector<int> &lds, const std::vector<std::vector<int>> &nidx,
+                       const std::vector<std::vector<int>> &uidx, double *out,
+                       const std::vector<int64_t> &out_off, int *stat) {
+    const int cnt = (int)nidx.size();
+    std::vector<int64_t> o_nn(cnt), o_nu(cnt), io_n(cnt), io_u(cnt);
+    std::vector<int> nn(cnt), nu(cnt), in_all, iu_all;
+    int64_t tnn = 0, tnu = 0;
+    int mnn = 0, mnu = 0;
+    for (int e = 0; e < cnt; ++e) {
+      nn[e] = (int)nidx[e].size();
+      nu[e] = (int)uidx[e].size();
+      mnn = std::max(mnn, nn[e]);
+      mnu = std::max(mnu, nu[e]);
+      o_nn[e] = tnn;
+      tnn += (int64_t)nn[e] * nn[e];
+      o_nu[e] = tnu;
+      tnu += (int64_t)nn[e] * nu[e];
+      io_n[e] = (int64_t)in_all.size();
+      in_all.insert(in_all.end(), nidx[e].begin(), nidx[e].end());
+      io_u[e] = (int64_t)iu_all.size();
+      iu_all.insert(iu_all.end(), uidx[e].begin(), uidx[e].end());
+    }
+    double *Snn = pool.zeros(stream, std::max<int64_t>(tnn, 1));
+    double *Snu = pool.zeros(stream, std::max<int64_t>(tnu, 1));
+    int64_t *d_so = pool.up(stream, src_off), *d_onn = pool.up(stream, o_nn),
+            *d_onu = pool.up(stream, o_nu), *d_oo = pool.up(stream, out_off);
+    int *d_lds = pool.up(stream, lds), *d_nn = pool.up(stream, nn), *d_nu = pool.up(stream, nu);
+    int *d_in = pool.up(stream, in_all.empty() ? std::vector<int>{0} : in_all);
+    int *d_iu = pool.up(stream, iu_all.empty() ? std::vector<int>{0} : iu_all);
+    int64_t *d_ion = pool.up(stream, io_n), *d_iou = pool.up(stream, io_u);
+    auto gather = [&](double *dst, const int64_t *doff, const int *ri, const int64_t *rio,
+                      const int *nr, const int *ci, const int64_t *cio, const int *ncl, int64_t maxe) {
+      if (maxe <= 0) return;
+      gather_rc_kernel<<<dim3(nblocks(maxe), cnt), TPB, 0, stream>>>(src, d_so, d_lds, dst, doff, ri,
+                                                                     rio, nr, ci, cio, ncl);
+      HIPCHK(hipGetLastError());
+    };
+    gather(Snn, d_onn, d_in, d_ion, d_nn, d_in, d_ion, d_nn, (int64_t)mnn * mnn);
+    gather(Snu, d_onu, d_in, d_ion, d_nn, d_iu, d_iou, d_nu, (int64_t)mnn * mnu);
+    gather(out, d_oo, d_iu, d_iou, d_nu, d_iu, d_iou, d_nu, (int64_t)mnu * mnu);
+    std::vector<MatDesc> md(cnt);
+    std::vector<GemmDesc> gd(cnt);
+    for (int e = 0; e < cnt; ++e) {
+      md[e] = MatDesc{o_nn[e], o_nu[e], nn[e], nu[e], std::max(1, nn[e]), std::max(1, nn[e])};
+      gd[e] = GemmDesc{o_nu[e], o_nu[e], out_off[e], nu[e], nu[e], nn[e], std::max(1, nn[e]),
+                       std::max(1, nn[e]), std::max(1, nu[e])};
+    }
+    MatDesc *d_md = pool.up(stream, md);
+    GemmDesc *d_gd = pool.up(stream, gd);
+    double *dv;
+    int64_t *doff;
+    dinv_for(md, dv, doff);
+    HIPCHK(DenseOps<double>::potrf(stream, Snn, d_md, md.data(), cnt, stat, dv, doff));
+    HIPCHK(DenseOps<double>::trsm(stream, Snn, Snu, d_md, md.data(), cnt, false, dv, doff));
+    // Out and Snu live in different pools
+    HIPCHK(DenseOps<double>::gemm(stream, Snu, Snu, out, d_gd, cnt, mnu, mnu, true, false, -1.0, 1.0,
+                                  false, gd.data()));
+  };
+  // level 1: per group, onto U
+  std::vector<int64_t> g_src(ng), g_off(ng);
+  std::vector<int> g_lds(ng);
+  std::vector<std::vector<int>> g_n(ng), g_u(ng);
+  int64_t tsu = 0;
+  for (int g = 0; g < ng; ++g) {
+    g_src[g] = L.offGG[groups[g].sub];
+    g_lds[g] = L.nG[groups[g].sub];
+    g_n[g] = groups[g].N;
+    g_u[g] = groups[g].U;
+    g_off[g] = tsu;
+    tsu += (int64_t)groups[g].U.size() * groups[g].U.size();
+  }
+  double *SU = pool.zeros(stream, std::max<int64_t>(tsu, 1));
+  eliminate(Sd, g_src, g_lds, g_n, g_u, SU, g_off, d_stat + 2 * nside);
+  check(2 * nside, ng, "interface blocks outside the shared dofs");
+  // level 2: per side, onto s (from its group's S_U), and the original S_ss
+  double *Sh = pool.zeros(stream, tsh);
+  std::vector<int64_t> s_src(nside), ss_src(nside);
+  std::vector<int> s_lds(nside), ss_lds(nside);
+  std::vector<std::vector<int>> s_n(nside), s_u(nside), ss_idx(nside);
+  for (int g = 0; g < ng; ++g) {
+    const SideGroup &G = groups[g];
+    std::vector<int> at(L.nG[G.sub], -1);
+    for (size_t t = 0; t < G.U.size(); ++t) at[G.U[t]] = (int)t;
+    for (int e : G.sides) {
+      const std::vector<int> &ps = pairs[e / 2].pos_s[e % 2];
+      std::vector<char> mine(G.U.size(), 0);
+      for (int q : ps) {
+        s_u[e].push_back(at[q]);
+        mine[at[q]] = 1;
+      }
+      for (size_t t = 0; t < G.U.size(); ++t)
+        if (!mine[t]) s_n[e].push_back((int)t);
+      s_src[e] = g_off[g];
+      s_lds[e] = (int)G.U.size();
+      ss_src[e] = L.offGG[G.sub];
+      ss_lds[e] = L.nG[G.sub];
+    }
+  }
+  eliminate(SU, s_src, s_lds, s_n, s_u, Sh, off_sh, d_stat);
   check(0, nside, "non-shared interface blocks");
-  HIPCHK(DenseOps<double>::trsm(stream, Snn, Sns, d_mdn, mdn.data(), nside, false, dv_n, do_n));
-  // Sh gets the Schur complement; Sns and Sh live in different pools
-  HIPCHK(DenseOps<double>::gemm(stream, Sns, Sns, Sh, d_gsh, nside, max_ns, max_ns, true, false,
-                                -1.0, 1.0, false, gsh.data()));
+  {
+    // the original S_ss of every side (for the numerator M)
+    std::vector<int> ss_all;
+    std::vector<int64_t> ss_io(nside);
+    for (int e = 0; e < nside; ++e) {
+      ss_io[e] = (int64_t)ss_all.size();
+      const std::vector<int> &ps = pairs[e / 2].pos_s[e % 2];
+      ss_all.insert(ss_all.end(), ps.begin(), ps.end());
+    }
+    int64_t *d_so = pool.up(stream, ss_src), *d_oo = pool.up(stream, off_ss),
+            *d_io = pool.up(stream, ss_io);
+    int *d_lds = pool.up(stream, ss_lds), *d_ns = pool.up(stream, nsv);
+    int *d_ix = pool.up(stream, ss_all);
+    gather_rc_kernel<<<dim3(nblocks((int64_t)max_ns * max_ns), nside), TPB, 0, stream>>>(
+        Sd, d_so, d_lds, Sh, d_oo, d_ix, d_io, d_ns, d_ix, d_io, d_ns);
+    HIPCHK(hipGetLastError());
+  }
 
   log("pair Schur complements");
   // ---- stage 2: parallel sum and the reduced pair matrices
