@@ -1134,9 +1134,13 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
     dinv_for(md, dv, doff);
     HIPCHK(DenseOps<double>::potrf(stream, Snn, d_md, md.data(), cnt, stat, dv, doff));
     HIPCHK(DenseOps<double>::trsm(stream, Snn, Snu, d_md, md.data(), cnt, false, dv, doff));
-    // Out and Snu live in different pools
+    // Out and Snu live in different pools; the product is symmetric: its
+    // lower triangle is formed and mirrored
     HIPCHK(DenseOps<double>::gemm(stream, Snu, Snu, out, d_gd, cnt, mnu, mnu, true, false, -1.0, 1.0,
-                                  false, gd.data()));
+                                  true, gd.data()));
+    std::vector<MatDesc> mo(cnt);
+    for (int e = 0; e < cnt; ++e) mo[e] = MatDesc{out_off[e], 0, nu[e], 0, std::max(1, nu[e]), 1};
+    HIPCHK(symmetrize_lower<double>(stream, out, pool.up(stream, mo), cnt, mnu));
   };
   // level 1: per group, onto U
   std::vector<int64_t> g_src(ng), g_off(ng);
