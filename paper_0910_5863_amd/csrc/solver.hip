@@ -120,39 +120,39 @@ __global__ void xform_copy_pivots_kernel(const double *pool, const int64_t *offG
   }
 }
 
+// S[:, glob dofs] += (pivot columns) W for one (substructure, glob) per
+// blockIdx.y: the globs of a substructure own disjoint columns, so they run
+// side by side; a thread per row
 __global__ void xform_cols_kernel(double *pool, const int64_t *offGG, const int *nG,
-                                  const GlobXf *gx, const int *gx_ptr, const double *wmat,
-                                  const int *pos, const int64_t *offG, const double *scr) {
-  const int s = blockIdx.y;
-  const int ng = nG[s];
+                                  const GlobXf *gx, const double *wmat, const int *pos,
+                                  const int64_t *offG, const double *scr) {
+  const GlobXf x = gx[blockIdx.y];
+  const int s = x.sub, ng = nG[s];
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= ng) return;
   double *S = pool + offGG[s];
   const int base = (int)offG[s];
-  for (int g = gx_ptr[s]; g < gx_ptr[s + 1]; ++g) {
-    const GlobXf x = gx[g];
-    for (int t = 0; t < x.ng; ++t) {
-      const int q = pos[x.pos_off + t] - base;
-      double acc = 0;
-      for (int k = 0; k < x.m; ++k)
-        acc += wmat[x.trow_off + (int64_t)k * x.ng + t] * scr[x.scrS_off + (int64_t)k * ng + row];
-      S[row + (int64_t)q * ng] += acc;
-    }
+  for (int t = 0; t < x.ng; ++t) {
+    const int q = pos[x.pos_off + t] - base;
+    double acc = 0;
+    for (int k = 0; k < x.m; ++k)
+      acc += wmat[x.trow_off + (int64_t)k * x.ng + t] * scr[x.scrS_off + (int64_t)k * ng + row];
+    S[row + (int64_t)q * ng] += acc;
   }
 }
 
+// S[glob dofs, :] += W^T (pivot rows), one (substructure, glob) per
+// blockIdx.y (disjoint rows); a wave per column, 16 columns per wave
 __global__ void xform_rows_kernel(double *pool, const int64_t *offGG, const int *nG,
-                                  const GlobXf *gx, const int *gx_ptr, const double *wmat,
-                                  const int *pos, const int64_t *offG, const double *scr) {
-  const int s = blockIdx.y;
-  const int ng = nG[s];
+                                  const GlobXf *gx, const double *wmat, const int *pos,
+                                  const int64_t *offG, const double *scr) {
+  const GlobXf x = gx[blockIdx.y];
+  const int s = x.sub, ng = nG[s];
   const int lane = threadIdx.x & 63;
-  const int col = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (col >= ng) return;
-  double *S = pool + offGG[s] + (int64_t)col * ng;
+  const int col0 = (blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 16;
   const int base = (int)offG[s];
-  for (int g = gx_ptr[s]; g < gx_ptr[s + 1]; ++g) {
-    const GlobXf x = gx[g];
+  for (int col = col0; col < min(ng, col0 + 16); ++col) {
+    double *S = pool + offGG[s] + (int64_t)col * ng;
     for (int t = lane; t < x.ng; t += 64) {
       const int q = pos[x.pos_off + t] - base;
       double acc = 0;
@@ -1068,15 +1068,13 @@ void Solver::factor() {
           d_pos.as<int>(), d_offG.as<int64_t>(), scrS.as<double>(), rows);
       HIPCHK(hipGetLastError());
       if (!rows)
-        xform_cols_kernel<<<dim3(nblocks(L.max_nG), ns), TPB, 0, st>>>(
+        xform_cols_kernel<<<dim3(nblocks(L.max_nG), n_gx), TPB, 0, st>>>(
             d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_gx.as<GlobXf>(),
-            d_gx_ptr.as<int>(), d_wmat.as<double>(), d_pos.as<int>(), d_offG.as<int64_t>(),
-            scrS.as<double>());
+            d_wmat.as<double>(), d_pos.as<int>(), d_offG.as<int64_t>(), scrS.as<double>());
       else
-        xform_rows_kernel<<<dim3(nblocks(L.max_nG, 4), ns), TPB, 0, st>>>(
+        xform_rows_kernel<<<dim3(nblocks((L.max_nG + 15) / 16, 4), n_gx), TPB, 0, st>>>(
             d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_gx.as<GlobXf>(),
-            d_gx_ptr.as<int>(), d_wmat.as<double>(), d_pos.as<int>(), d_offG.as<int64_t>(),
-            scrS.as<double>());
+            d_wmat.as<double>(), d_pos.as<int>(), d_offG.as<int64_t>(), scrS.as<double>());
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipStreamSynchronize(st));
