@@ -161,7 +161,7 @@ def cpu_baseline():
     t0 = time.perf_counter()
     Sd = {s: schur_dense(o.S, o.itf, s) for s in range(o.S.n_sub)}
     ad = adapt(o.S, o.itf, o.cons, TAU, Sd=Sd)
-    o2 = OracleBDDC(p, "ce", extra_face_rows=ad["rows"])
+    o2 = OracleBDDC(p, "ce", extra_rows=ad["rows"])
     r = o2.solve(rtol=RTOL)
     dt = time.perf_counter() - t0
     if not r["converged"]:

@@ -13,11 +13,19 @@ Pi projects onto the null space of D^c_ij, the constraints of the globs that
 both substructures share.  E_ij averages the two copies of every shared
 non-corner dof with the weights renormalized over {i, j}.
 
-Eigenvectors with lambda >= tau give rows d = w^T Pi (I-E)^T S^c (I-E) Pi
-(eq. (d-def)); each row is split and only its face part is kept (Remark after
-Proposition 1: adaptive edge rows are dropped).  The condition number
-indicator (eq. (cond-ind)) reported is the largest eigenvalue that was *not*
-selected, maximized over pairs.
+Eigenvectors with lambda >= tau (or, with ``count``, the ``count`` dominant
+ones of every face: the "3eigv" variant of Sec. 7) give rows
+d = w^T Pi (I-E)^T S^c (I-E) Pi (eq. (d-def)).  Each row is split into one row
+over the face and one row over each edge in the face's closure (Sec. 3 after
+Proposition 1), so that D^c D^cT stays block diagonal by glob.  By default the
+edge rows are dropped, as in the computations of the paper (Remark after
+Proposition 1); ``edges=True`` keeps them.  The condition number indicator
+(eq. (cond-ind)) reported is the largest eigenvalue that was *not* selected,
+maximized over pairs.
+
+Reading (paper silent): an edge part whose largest entry is at most
+EDGE_DROP times the largest entry of its whole row d is rounding residue (the
+edge's existing constraints already annihilate it) and gives no row.
 
 Reduction (``reduced=True``, default): interface dofs of i that are not shared
 with j do not enter (I - E); their values are free in the denominator, so they
@@ -32,6 +40,8 @@ import numpy as np
 import scipy.linalg as sla
 
 from .bddc import _splu_spd
+
+EDGE_DROP = 1e-8
 
 
 def schur_dense(S, itf, i):
@@ -187,6 +197,18 @@ class PairProblem:
         c = np.array([self.col[self.i][m[g]] for g in gl["dofs"]])
         return d[:, c]
 
+    def edge_parts(self, d, itf):
+        """[(edge glob index, entries of d on substructure i's copy of that
+        edge's dofs in the glob's dof order)] for every edge glob shared by i
+        and j (the edges of the face's closure), in glob order."""
+        m = {g: k for k, g in enumerate(self.side[self.i]["X"])}
+        out = []
+        for gi, gl in enumerate(itf.globs):
+            if gl["kind"] == "edge" and self.i in gl["subs"] and self.j in gl["subs"]:
+                c = np.array([self.col[self.i][m[g]] for g in gl["dofs"]])
+                out.append((gi, d[:, c]))
+        return out
+
     def other_face_part(self, d, itf):
         gl = itf.globs[self.face_gi]
         m = {g: k for k, g in enumerate(self.side[self.j]["X"])}
@@ -194,12 +216,15 @@ class PairProblem:
         return d[:, c]
 
 
-def adapt(S, itf, cons, tau, reduced=True, Sd=None):
+def adapt(S, itf, cons, tau, reduced=True, Sd=None, count=None, edges=False):
     """Algorithm 1: for every face pair select the eigenvectors with
-    lambda >= tau (Sec. 7: eigenvalues greater or equal to tau were used).
+    lambda >= tau (Sec. 7: eigenvalues greater or equal to tau were used), or
+    the ``count`` largest when count is given (tau is then ignored).
 
-    Returns dict(rows={face glob: rows}, omega=indicator, k={face: count},
-    lam={face: eigenvalues descending})."""
+    Returns dict(rows={glob: rows}, omega=indicator, k={face: count},
+    lam={face: eigenvalues descending}).  rows holds the face rows and, with
+    edges=True, the edge rows; on every glob they are ordered by face, then by
+    eigenvalue (largest first)."""
     if Sd is None:
         Sd = {s: schur_dense(S, itf, s) for s in range(S.n_sub)}
     rows, kcount, lams = {}, {}, {}
@@ -207,15 +232,26 @@ def adapt(S, itf, cons, tau, reduced=True, Sd=None):
     for fg in itf.face_ids:
         pp = PairProblem(S, itf, cons, fg, Sd, reduced=reduced)
         lam, W = pp.solve()
-        sel = lam >= tau
+        if count is None:
+            sel = lam >= tau
+        else:
+            sel = np.zeros(lam.size, dtype=bool)
+            sel[max(0, lam.size - count):] = True
         lams[fg] = lam[::-1].copy()
         kcount[fg] = int(sel.sum())
         unsel = lam[~sel]
         if unsel.size:
             omega = max(omega, float(unsel.max()))
         if sel.any():
-            d = pp.rows(W[:, sel])
+            d = pp.rows(W[:, sel])[::-1]       # largest eigenvalue first
             c = pp.face_part(d, itf)
-            c = c / np.abs(c).max(axis=1, keepdims=True)
-            rows[fg] = c[::-1]                 # largest eigenvalue first
+            rows.setdefault(fg, []).extend(c / np.abs(c).max(axis=1, keepdims=True))
+            if edges:
+                scale = np.abs(d).max(axis=1)
+                for gi, ce in pp.edge_parts(d, itf):
+                    for q in range(ce.shape[0]):
+                        mx = np.abs(ce[q]).max()
+                        if mx > EDGE_DROP * scale[q]:
+                            rows.setdefault(gi, []).append(ce[q] / mx)
+    rows = {g: np.array(r) for g, r in rows.items()}
     return dict(rows=rows, omega=omega, k=kcount, lam=lams)

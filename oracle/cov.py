@@ -95,10 +95,12 @@ class Constraints:
     mode: 'c' (corners only), 'ce' (+ edge averages), 'cef' (+ face averages),
     'all' (every glob dof constrained: H^avg = I, so the constrained space is
     the continuous one and BDDC becomes exact).
-    extra_face_rows: dict glob index -> extra rows over that face (adaptive).
+    extra_rows: dict glob index -> extra rows over that glob (the adaptive
+    face rows, and the adaptive edge rows when they are kept), stacked after
+    the averages.
     """
 
-    def __init__(self, itf, mode="ce", extra_face_rows=None):
+    def __init__(self, itf, mode="ce", extra_rows=None):
         self.itf = itf
         S = itf.S
         dpn = S.prob.dpn
@@ -111,8 +113,8 @@ class Constraints:
             if (gl["kind"] == "edge" and mode in ("ce", "cef")) or \
                (gl["kind"] == "face" and mode == "cef"):
                 rows.append(unit_averages(gl, dpn))
-            if extra_face_rows and k in extra_face_rows:
-                rows.append(np.atleast_2d(extra_face_rows[k]))
+            if extra_rows and k in extra_rows:
+                rows.append(np.atleast_2d(extra_rows[k]))
             rows = [r for r in rows if r.size]
             self.H.append(np.vstack(rows) if rows else np.zeros((0, gl["dofs"].size)))
         self.G = [GlobTransform(H) for H in self.H]

@@ -14,18 +14,18 @@ from .pcg import pcg
 
 
 class OracleBDDC:
-    def __init__(self, prob, mode="ce", extra_face_rows=None, augment_corners=True):
+    def __init__(self, prob, mode="ce", extra_rows=None, augment_corners=True):
         t0 = time.perf_counter()
         self.prob = prob
         self.S = Substructures(prob)
         self.itf = Interface(self.S, augment_corners=augment_corners)
         self.t_setup = time.perf_counter() - t0
         self.mode = mode
-        self.build(extra_face_rows)
+        self.build(extra_rows)
 
-    def build(self, extra_face_rows=None):
+    def build(self, extra_rows=None):
         t0 = time.perf_counter()
-        self.cons = Constraints(self.itf, self.mode, extra_face_rows)
+        self.cons = Constraints(self.itf, self.mode, extra_rows)
         self.M = Algorithm2(self.S, self.itf, self.cons)
         self.K = self.S.assembled()
         self.t_factor = time.perf_counter() - t0

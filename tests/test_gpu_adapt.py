@@ -42,7 +42,7 @@ def oracle_for(name):
         o = OracleBDDC(p, "ce")
         Sd = {s: schur_dense(o.S, o.itf, s) for s in range(o.S.n_sub)}
         ad = adapt(o.S, o.itf, o.cons, tau, Sd=Sd)
-        o2 = OracleBDDC(p, "ce", extra_face_rows=ad["rows"])
+        o2 = OracleBDDC(p, "ce", extra_rows=ad["rows"])
         _cache[name] = (p, tau, o, ad, o2)
     return _cache[name]
 

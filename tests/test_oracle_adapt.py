@@ -106,7 +106,7 @@ def test_two_substructures_corollary_exact(tau):
     ad0 = adapt(o.S, o.itf, o.cons, np.inf)
     assert abs(lmax0 - ad0["omega"]) < 1e-7 * lmax0
     ad = adapt(o.S, o.itf, o.cons, tau)
-    o2 = OracleBDDC(p, "ce", extra_face_rows=ad["rows"])
+    o2 = OracleBDDC(p, "ce", extra_rows=ad["rows"])
     lmax, lmin = _exact_lmax(o2)
     assert lmin > 1 - 1e-9
     assert abs(lmax - ad["omega"]) < 1e-7 * lmax
@@ -118,8 +118,87 @@ def test_adaptivity_reduces_condition_number(layered):
     p, S, itf, cons, Sd = layered
     k0 = OracleBDDC(p, "ce").solve()
     ad = adapt(S, itf, cons, 10.0, Sd=Sd)
-    o = OracleBDDC(p, "ce", extra_face_rows=ad["rows"])
+    o = OracleBDDC(p, "ce", extra_rows=ad["rows"])
     out = o.solve()
     assert out["kappa"] < k0["kappa"]
     assert out["kappa"] < 1.5 * 10.0
     assert out["Nc"] == o.cons.Nc() > 0
+
+
+@pytest.mark.parametrize("case", ["layers", "kmeans"])
+def test_kept_edge_rows_bound_every_pair_problem(case, layered):
+    """Sec. 3 after Proposition 1: splitting each row d into its face part and
+    one row per edge of the face's closure gives constraints at least as
+    strong as d itself, so every pair problem re-solved on the new constraint
+    set has its largest eigenvalue at most the largest unselected one
+    (Corollary with eq. (complement)); hence omega~ <= tau.  Dropping the
+    edge rows (Remark after Proposition 1) loses this: on the layered mesh a
+    re-solved pair exceeds the indicator."""
+    if case == "layers":
+        p, S, itf, cons, Sd = layered
+        tau = 10.0
+    else:
+        p = meshgen.small_kmeans(meshgen.ELASTICITY, 8, 4, contrast=1e3)
+        S = Substructures(p)
+        itf = Interface(S)
+        cons = Constraints(itf, "ce")
+        Sd = {s: schur_dense(S, itf, s) for s in range(S.n_sub)}
+        tau = 5.0
+    ad = adapt(S, itf, cons, tau, Sd=Sd, edges=True)
+    edge_rows = [g for g in ad["rows"] if itf.globs[g]["kind"] == "edge"]
+    assert edge_rows
+    again = adapt(S, itf, Constraints(itf, "ce", ad["rows"]), np.inf, Sd=Sd)
+    assert again["omega"] <= ad["omega"] * (1 + 1e-8) < tau
+    if case == "layers":
+        ad0 = adapt(S, itf, cons, tau, Sd=Sd)
+        assert ad0["omega"] == ad["omega"]
+        again0 = adapt(S, itf, Constraints(itf, "ce", ad0["rows"]), np.inf, Sd=Sd)
+        assert again0["omega"] > 1.1 * ad0["omega"]
+
+
+def test_kept_edge_rows_are_split_parts_of_d(layered):
+    """Each kept edge row is, up to scale, the part of a face row's d on one
+    edge of the closure, and the corresponding face row the part on the face:
+    together with zero corner entries they reassemble d (Proposition 1 gives
+    the other side's copy as the negative)."""
+    p, S, itf, cons, Sd = layered
+    fg = itf.face_ids[0]
+    from oracle.adapt import PairProblem
+    pp = PairProblem(S, itf, cons, fg, Sd)
+    lam, W = pp.solve()
+    d = pp.rows(W[:, -1:])
+    parts = pp.edge_parts(d, itf)
+    assert parts
+    globs = [(fg, pp.face_part(d, itf))] + parts
+    rebuilt = np.zeros_like(d)
+    for s, sign in ((pp.i, 1.0), (pp.j, -1.0)):
+        m = {g: k for k, g in enumerate(pp.side[s]["X"])}
+        for gi, part in globs:
+            c = [pp.col[s][m[g]] for g in itf.globs[gi]["dofs"]]
+            rebuilt[:, c] = sign * part
+    np.testing.assert_allclose(rebuilt, d, rtol=0, atol=1e-10 * np.abs(d).max())
+
+
+def test_three_eigenvectors_match_face_average_count(layered):
+    """Sec. 7: three dominant eigenvectors per face give as many constraints
+    as the arithmetic face averages (three per face in elasticity)."""
+    p, S, itf, cons, Sd = layered
+    ad = adapt(S, itf, cons, np.inf, Sd=Sd, count=3)
+    assert all(k == 3 for k in ad["k"].values())
+    c3 = Constraints(itf, "ce", ad["rows"])
+    assert c3.Nc() == Constraints(itf, "cef").Nc() == cons.Nc() + 3 * len(itf.face_ids)
+    # the indicator is the fourth eigenvalue, maximized over faces
+    assert ad["omega"] == max(l[3] for l in ad["lam"].values())
+
+
+def test_two_substructures_corollary_count():
+    """With two substructures and the k dominant eigenvectors added, the
+    largest eigenvalue of the preconditioned operator is lambda_{k+1}."""
+    p = _two_substructures()
+    o = OracleBDDC(p, "ce")
+    ad = adapt(o.S, o.itf, o.cons, np.inf, count=3)
+    o2 = OracleBDDC(p, "ce", extra_rows=ad["rows"])
+    lmax, lmin = _exact_lmax(o2)
+    lam = ad["lam"][o.itf.face_ids[0]]
+    assert abs(lmax - lam[3]) < 1e-7 * lmax
+    assert lmin > 1 - 1e-9
