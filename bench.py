@@ -67,7 +67,115 @@ def parse_args():
     ap.add_argument("--serving-rate", type=float, default=8.0, help="arrivals per second")
     ap.add_argument("--serving-workers", type=int, default=4, help="requests in flight at once")
     ap.add_argument("--serving-precision", type=int, default=32, choices=(32, 64))
+    ap.add_argument("--variants", choices=("elasticity48", "kmeans64"), default=None,
+                    help="instead of the step benchmark, solve the workload once per constraint "
+                         "set (c, c+e, c+e+f, 3eigv, adaptive tau with and without edge rows) and "
+                         "print one JSON line each: Nc, kappa, iterations, phase times")
+    ap.add_argument("--planar-cubes", type=int, nargs=2, default=None, metavar=("KMIN", "KMAX"),
+                    help="instead of the step benchmark, solve the planar-cubes series (k x k "
+                         "substructures of 8^3 elasticity elements, corners only) for k in "
+                         "KMIN..KMAX and print one JSON line each")
     return ap.parse_args()
+
+
+# constraint sets of the variants table: (label, setup mode, adapt call, edges)
+VARIANTS = [("c", "c", None, False), ("c+e", "ce", None, False), ("c+e+f", "cef", None, False),
+            ("3eigv", "ce", ("count", 3), False), ("adaptive tau=10", "ce", ("tau", 10.0), False),
+            ("adaptive tau=10, edge rows kept", "ce", ("tau", 10.0), True),
+            ("adaptive tau=2", "ce", ("tau", 2.0), False),
+            ("adaptive tau=2, edge rows kept", "ce", ("tau", 2.0), True)]
+
+
+def variants(args):
+    """The structure of the paper's Tables 1/3/5/7 on a synthetic workload:
+    one solve per constraint set, with Nc, the Lanczos condition number
+    estimate, iterations and phase times (setup, adapt, factor, PCG)."""
+    import torch
+    import meshgen
+    from paper_0910_5863_amd import BDDC
+    p = meshgen.elasticity_layers_48() if args.variants == "elasticity48" \
+        else meshgen.elasticity_kmeans_64()
+    f = torch.from_numpy(p.f).to("cuda:0")
+    for label, mode, ad, edges in VARIANTS:
+        b = BDDC(device=0)
+        t0 = time.perf_counter()
+        b.setup(p, mode, adaptive_edges=edges)
+        t1 = time.perf_counter()
+        ai = None
+        if ad is not None:
+            ai = b.adapt_count(ad[1]) if ad[0] == "count" else b.adapt(ad[1])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        b.factor()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        u, info = b.pcg_solve(f, rtol=RTOL, maxit=5000, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        nc = b.info().nc
+        b.close()
+        del b, u
+        torch.cuda.empty_cache()
+        print(json.dumps({
+            "workload": p.name, "variant": label, "nc": int(nc),
+            "omega": None if ai is None else float(ai.omega),
+            "edge_rows": None if ai is None else int(ai.n_added_edge),
+            "kappa": float(info[0].kappa), "iters": int(info[0].iters),
+            "converged": bool(info[0].converged), "setup_s": t1 - t0, "adapt_s": t2 - t1,
+            "factor_s": t3 - t2, "pcg_s": t4 - t3}), flush=True)
+
+
+# the weak-scaling series of Table 9 (SGI Altix 4700, MUMPS, one processor per
+# substructure): substructures, dofs, condition number, iterations, MUMPS
+# analysis s, factorization s, PCG s; printed beside each result as context
+TABLE9 = {2: (4, 7803, 28.3, 13, 0.2, 0.5, 0.8), 3: (9, 16875, 38.0, 26, 0.5, 0.4, 3.6),
+          4: (16, 29403, 42.2, 36, 1, 0.8, 13), 5: (25, 45387, 44.4, 42, 15, 12, 613),
+          6: (36, 64827, 45.7, 44, 14, 10, 524), 7: (49, 87723, 46.5, 46, 16, 12, 579),
+          8: (64, 114075, 47.1, 47, 19, 14, 643)}
+
+
+def planar_cubes(args):
+    """Planar-cubes weak scaling on one GPU: k x k substructures of 8^3
+    elasticity elements, corners only.  Setup (host analysis and upload),
+    factor and PCG solve are timed; factor + solve run three times and the
+    median is reported."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_0910_5863_amd import BDDC
+    for k in range(args.planar_cubes[0], args.planar_cubes[1] + 1):
+        p = meshgen.planar_cubes(k)
+        f = torch.from_numpy(p.f).to("cuda:0")
+        b = BDDC(device=0)
+        t0 = time.perf_counter()
+        b.setup(p, "c")
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        tf, ts = [], []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            b.factor()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            u, info = b.pcg_solve(f, rtol=RTOL, maxit=2000)
+            torch.cuda.synchronize()
+            tf.append(t1 - t0)
+            ts.append(time.perf_counter() - t1)
+        i = b.info()
+        b.close()
+        del b, u
+        torch.cuda.empty_cache()
+        it = int(info[0].iters)
+        ctx = TABLE9.get(k)
+        print(json.dumps({
+            "workload": p.name, "k": k, "n_sub": int(p.n_sub), "dofs_all": int(p.n_nodes * 3),
+            "n_glob": int(p.n_glob), "nc": int(i.nc), "n_coarse": int(i.n_coarse),
+            "kappa": float(info[0].kappa), "iters": it, "setup_s": t_setup,
+            "factor_s": float(np.median(tf)), "pcg_s": float(np.median(ts)),
+            "ms_per_iteration": float(np.median(ts)) / max(it, 1) * 1e3,
+            "paper_table9": None if ctx is None else dict(zip(
+                ("n_sub", "dofs", "kappa", "iters", "analysis_s", "factorization_s", "pcg_s"), ctx)),
+        }), flush=True)
 
 
 def serving(args):
@@ -184,6 +292,13 @@ def main():
         sys.exit(2)
     if args.serving > 0:
         serving(args)
+        return
+    if args.variants or args.planar_cubes:
+        import torch
+        if not torch.cuda.is_available():
+            print("bench.py: no GPU visible", file=sys.stderr)
+            sys.exit(1)
+        variants(args) if args.variants else planar_cubes(args)
         return
     import numpy as np
     import torch

@@ -99,6 +99,16 @@ typedef struct {
                                 corners in its closure (Assumptions 1 and 2) */
   double qr_drop_tol;        /* rows of U with |U_kk| <= tol*|U_11| are dropped
                                 (Sec. 5 after eq. (T)); 0 means 1e-10 */
+  int adaptive_edges;        /* 0: bddc_adapt keeps only the face part of each
+                                adaptive row, as in the paper's computations
+                                (Remark after Proposition 1); nonzero: each row d
+                                is split into its face part and one row per edge
+                                of the face's closure (Sec. 3 after Proposition 1),
+                                and the edge rows are added to those edges'
+                                constraints, so that every pair problem re-solved
+                                on the new constraints stays below tau.  An edge
+                                part whose largest entry is at most 1e-8 times the
+                                largest entry of d is rounding residue and dropped. */
 } bddc_constraints;
 
 typedef struct {
@@ -123,6 +133,8 @@ typedef struct {
   int64_t lobpcg_iters;      /* total LOBPCG iterations over all pairs */
   int64_t unconverged;       /* pairs whose LOBPCG did not converge */
   double seconds;
+  int64_t n_added_edge;      /* adaptive edge rows added (adaptive_edges only; before
+                                the QR drops dependent rows) */
 } bddc_adapt_info;
 
 typedef struct {
@@ -155,6 +167,13 @@ bddc_status bddc_setup(bddc_ctx *ctx, const bddc_mesh *mesh, const bddc_partitio
    and Schur complements it computes are reused by the next bddc_factor. */
 bddc_status bddc_adapt(bddc_ctx *ctx, double tau, bddc_adapt_info *info);
 
+/* The "3eigv" variant of Sec. 7: as bddc_adapt, but every face takes the rows
+   of its rows_per_face dominant eigenvectors (all of them if the face's pair
+   problem has fewer), whatever their eigenvalues; omega is then the largest
+   eigenvalue not taken.  rows_per_face >= 1, else BDDC_ERR_ARG.  With three
+   rows per face in elasticity the count equals that of the face averages. */
+bddc_status bddc_adapt_count(bddc_ctx *ctx, int rows_per_face, bddc_adapt_info *info);
+
 /* Factor: Dirichlet factors A_II, Schur complements, constrained local factors,
    coarse basis and coarse factor, all substructures batched. */
 bddc_status bddc_factor(bddc_ctx *ctx);
@@ -178,6 +197,13 @@ bddc_status bddc_get_info(const bddc_ctx *ctx, bddc_info *info);
    and the face's two substructures through subs[2]. */
 bddc_status bddc_get_face_rows(const bddc_ctx *ctx, int64_t f, int64_t max_rows, double *out,
                                int64_t *dofs, int64_t *rows, int64_t *n_dofs, int32_t *subs);
+
+/* Adaptive rows of one edge glob (after bddc_adapt with adaptive_edges), for
+   inspection: edge index e in [0, n_edges).  Rows of n_dofs entries
+   (row-major, edge dofs in ascending global order), ordered by face, then by
+   eigenvalue (largest first); the edge's global dof ids if dofs != NULL. */
+bddc_status bddc_get_edge_rows(const bddc_ctx *ctx, int64_t e, int64_t max_rows, double *out,
+                               int64_t *dofs, int64_t *rows, int64_t *n_dofs);
 
 /* Eigenvalues of the last bddc_adapt for face f, descending (up to max). */
 bddc_status bddc_get_face_eigs(const bddc_ctx *ctx, int64_t f, int64_t max, double *out,

@@ -281,6 +281,38 @@ def small_kmeans(kind: int, n: int, k: int, seed_part: int = 0, seed_coef: int =
                         dirichlet_face=("z", 0.0), name=f"kmeans{n}_{kk}")
 
 
+def planar_cubes(k: int, H: int = 8):
+    """k x k cubic substructures of H^3 elasticity elements side by side in one
+    layer: the domain [0, k] x [0, k] x [0, 1] with elements of size 1/H,
+    E = 1, nu = 0.3, every dof clamped on the face x = 0 and a unit downward
+    traction on the opposite face x = k (consistent nodal loads of the
+    bilinear face elements).  The material and the load are stand-ins: the
+    weak-scaling experiment fixes one side and loads the opposite one without
+    stating either."""
+    nel = (H * k, H * k, H)
+    xyz, hex8 = grid_mesh(*nel)
+    xyz[:, 0] *= k
+    xyz[:, 1] *= k
+    elem_sub = partition_blocks(nel, (k, k, 1))
+    dpn = 3
+    dirichlet = np.zeros(xyz.shape[0] * dpn, dtype=np.uint8)
+    for c in range(dpn):
+        dirichlet[dpn * _face_nodes(xyz, 0, 0.0) + c] = 1
+    # loaded face x = k: an (ny + 1) x (nz + 1) node grid of squares of side
+    # h; each node carries h^2/4 per square it touches
+    h = 1.0 / H
+    nodes = _face_nodes(xyz, 0, float(k))
+    j = np.rint(xyz[nodes, 1] * H).astype(np.int64)
+    kk = np.rint(xyz[nodes, 2] * H).astype(np.int64)
+    wy = np.where((j == 0) | (j == nel[1]), 0.5 * h, h)
+    wz = np.where((kk == 0) | (kk == nel[2]), 0.5 * h, h)
+    load = np.zeros(xyz.shape[0] * dpn)
+    load[dpn * nodes + 2] = -wy * wz
+    return Problem(name=f"planar_cubes_{k}x{k}_H{H}", kind=ELASTICITY, nel=nel, xyz=xyz,
+                   hex8=hex8, coef=np.ones(hex8.shape[0]), nu=0.3, elem_sub=elem_sub,
+                   n_sub=k * k, dirichlet=dirichlet, load=load)
+
+
 def serving_requests(n_req: int = 512, seed: int = 5):
     """Request stream: type (Poisson/elasticity, p = 0.5), elements per side
     n in {16,24,32,40,48}, substructures per side s in {2,3,4} with n % s == 0,

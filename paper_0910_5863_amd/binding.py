@@ -54,7 +54,8 @@ class bddc_partition(C.Structure):
 
 
 class bddc_constraints(C.Structure):
-    _fields_ = [("mode", C.c_int), ("augment_corners", C.c_int), ("qr_drop_tol", C.c_double)]
+    _fields_ = [("mode", C.c_int), ("augment_corners", C.c_int), ("qr_drop_tol", C.c_double),
+                ("adaptive_edges", C.c_int)]
 
 
 class bddc_pcg_params(C.Structure):
@@ -70,7 +71,7 @@ class bddc_pcg_info(C.Structure):
 class bddc_adapt_info(C.Structure):
     _fields_ = [("omega", C.c_double), ("nc", C.c_int64), ("n_added", C.c_int64),
                 ("n_pairs", C.c_int64), ("lobpcg_iters", C.c_int64), ("unconverged", C.c_int64),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("n_added_edge", C.c_int64)]
 
 
 class bddc_info(C.Structure):
@@ -100,8 +101,9 @@ class bddc_kernel_stat(C.Structure):
                 ("bytes", C.c_double), ("flops", C.c_double)]
 
 
-SYMBOLS = ["bddc_create", "bddc_setup", "bddc_adapt", "bddc_factor", "bddc_apply",
-           "bddc_pcg_solve", "bddc_get_info", "bddc_get_face_rows", "bddc_get_face_eigs",
+SYMBOLS = ["bddc_create", "bddc_setup", "bddc_adapt", "bddc_adapt_count", "bddc_factor",
+           "bddc_apply", "bddc_pcg_solve", "bddc_get_info", "bddc_get_face_rows",
+           "bddc_get_edge_rows", "bddc_get_face_eigs",
            "bddc_pcg_history", "bddc_get_substructure", "bddc_set_timing", "bddc_get_timing",
            "bddc_server_create", "bddc_server_submit", "bddc_server_wait", "bddc_server_query",
            "bddc_server_release", "bddc_server_destroy", "bddc_last_error", "bddc_destroy"]
@@ -135,6 +137,7 @@ def load(path: str = LIB_PATH):
     L.bddc_setup.argtypes = [P, C.POINTER(bddc_mesh), C.POINTER(bddc_partition),
                              C.POINTER(bddc_constraints)]
     L.bddc_adapt.argtypes = [P, C.c_double, C.POINTER(bddc_adapt_info)]
+    L.bddc_adapt_count.argtypes = [P, C.c_int, C.POINTER(bddc_adapt_info)]
     L.bddc_factor.argtypes = [P]
     L.bddc_apply.argtypes = [P, C.c_int, P, C.c_int64, P, C.c_int64]
     L.bddc_pcg_solve.argtypes = [P, C.c_int, P, C.c_int64, P, C.c_int64,
@@ -143,6 +146,9 @@ def load(path: str = LIB_PATH):
     L.bddc_get_face_rows.argtypes = [P, C.c_int64, C.c_int64, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    L.bddc_get_edge_rows.argtypes = [P, C.c_int64, C.c_int64, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]
     L.bddc_get_face_eigs.argtypes = [P, C.c_int64, C.c_int64, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]
     L.bddc_pcg_history.argtypes = [P, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -194,6 +200,12 @@ def bddc_adapt(h, tau):
     return info
 
 
+def bddc_adapt_count(h, rows_per_face):
+    info = bddc_adapt_info()
+    _check(h, load().bddc_adapt_count(h, int(rows_per_face), C.byref(info)))
+    return info
+
+
 def bddc_factor(h):
     _check(h, load().bddc_factor(h))
 
@@ -226,7 +238,7 @@ def _check(h, code):
         raise BddcError(code, msg)
 
 
-def _marshal(prob, mode, augment_corners=True, qr_drop_tol=1e-10):
+def _marshal(prob, mode, augment_corners=True, qr_drop_tol=1e-10, adaptive_edges=False):
     """ctypes structures for a meshgen-style problem, and the arrays they point to."""
     xyz = np.ascontiguousarray(prob.xyz, dtype=np.float64)
     hex8 = np.ascontiguousarray(prob.hex8, dtype=np.int64)
@@ -238,7 +250,8 @@ def _marshal(prob, mode, augment_corners=True, qr_drop_tol=1e-10):
                      _ptr(dirichlet, C.c_uint8))
     part = bddc_partition(int(prob.n_sub), _ptr(elem_sub, C.c_int32))
     cons = bddc_constraints(MODES[mode] if isinstance(mode, str) else int(mode),
-                            1 if augment_corners else 0, float(qr_drop_tol))
+                            1 if augment_corners else 0, float(qr_drop_tol),
+                            1 if adaptive_edges else 0)
     return mesh, part, cons, (xyz, hex8, coef, dirichlet, elem_sub)
 
 
@@ -376,13 +389,18 @@ class BDDC:
         except Exception:
             pass
 
-    def setup(self, prob, mode="ce", augment_corners=True, qr_drop_tol=1e-10):
-        mesh, part, cons, self._arrays = _marshal(prob, mode, augment_corners, qr_drop_tol)
+    def setup(self, prob, mode="ce", augment_corners=True, qr_drop_tol=1e-10,
+              adaptive_edges=False):
+        mesh, part, cons, self._arrays = _marshal(prob, mode, augment_corners, qr_drop_tol,
+                                                  adaptive_edges)
         bddc_setup(self.h, mesh, part, cons)
         self.n_glob = self.info().n_glob
 
     def adapt(self, tau):
         return bddc_adapt(self.h, tau)
+
+    def adapt_count(self, rows_per_face):
+        return bddc_adapt_count(self.h, rows_per_face)
 
     def factor(self):
         bddc_factor(self.h)
@@ -429,6 +447,16 @@ class BDDC:
         _check(self.h, L.bddc_get_face_rows(self.h, f, rows.value, _ptr(out, C.c_double),
                                             _ptr(dofs, C.c_int64), C.byref(rows), C.byref(nd), subs))
         return out, dofs, (subs[0], subs[1])
+
+    def edge_rows(self, e):
+        L = load()
+        rows, nd = C.c_int64(), C.c_int64()
+        _check(self.h, L.bddc_get_edge_rows(self.h, e, 0, None, None, C.byref(rows), C.byref(nd)))
+        out = np.zeros((rows.value, nd.value))
+        dofs = np.zeros(nd.value, dtype=np.int64)
+        _check(self.h, L.bddc_get_edge_rows(self.h, e, rows.value, _ptr(out, C.c_double),
+                                            _ptr(dofs, C.c_int64), C.byref(rows), C.byref(nd)))
+        return out, dofs
 
     def pcg_history(self):
         L = load()

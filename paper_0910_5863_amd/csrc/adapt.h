@@ -22,6 +22,8 @@ struct AdaptPair {
   std::vector<int> zptr, zrow;          // Z (n_c x d) by columns: rows and values
   std::vector<double> zval;
   std::vector<int> face_c;              // c-indices of the face glob dofs (glob order)
+  std::vector<int> edge_gi;             // edge globs of the face's closure (ascending)
+  std::vector<std::vector<int>> edge_c; // their c-indices (glob order)
 };
 
 struct AdaptState {
@@ -32,11 +34,13 @@ struct AdaptState {
 
 struct AdaptResult {
   double omega = 0;
-  int64_t n_added = 0, n_pairs = 0, iters = 0, unconverged = 0;
+  int64_t n_added = 0, n_added_edge = 0, n_pairs = 0, iters = 0, unconverged = 0;
 };
 
-// Solves the face-pair eigenproblems with the current constraints, appends
-// the selected rows to P.extra_rows / P.extra_k of every face.
-AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau);
+// Solves the face-pair eigenproblems with the current constraints and
+// appends the selected rows to P.extra_rows / P.extra_k of every face (and of
+// the edges of its closure when P.adapt_edges).  count == 0 selects the
+// eigenvalues >= tau; count > 0 the count dominant ones of every face.
+AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int count = 0);
 
 }  // namespace bddc

@@ -163,6 +163,7 @@ struct LobDesc {
   int d, s;
   int need;         // number of leading eigenpairs that must converge (>= 1)
   double tau;       // threshold: pairs with theta >= tau are needed, plus one below
+  int take;         // > 0: the first `take` pairs are selected whatever tau says
 };
 
 struct LobOut {
@@ -760,8 +761,9 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
     if (tid == 0) {
       int k = 0, ok = 1;
       for (k = 0; k < s; ++k) {
-        const bool selected = theta[k] >= D.tau;
-        const bool needed = (k < D.need) || (k == 0) || (theta[k - 1] >= D.tau);
+        const bool selected = D.take > 0 ? k < D.take : theta[k] >= D.tau;
+        const bool needed = (k < D.need) || (k == 0) ||
+                            (D.take > 0 ? k <= D.take : theta[k - 1] >= D.tau);
         if (!needed) break;
         const double t = selected ? tol : tol_ind;
         if (res[k] > t * fmax(fabs(theta[k]), 1.0)) ok = 0;
@@ -873,7 +875,7 @@ void orthonormalize(std::vector<double> &Q, int n, int &k) {
 
 }  // namespace
 
-AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
+AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int count) {
   AdaptResult res;
   hipStream_t stream = S.stream;
   const auto t_start = std::chrono::steady_clock::now();
@@ -986,6 +988,10 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
         }
         if ((int)g2 == ph.gi)
           for (size_t t = 0; t < G.dofs.size(); ++t) ph.face_c.push_back(crow[t]);
+        if (G.kind == GLOB_EDGE) {
+          ph.edge_gi.push_back((int)g2);
+          ph.edge_c.push_back(crow);
+        }
       }
       ph.d = (int)cols.size();
       if (ph.d == 0) continue;
@@ -1386,6 +1392,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
     for (int a = 0; a < na; ++a) {
       const int p = active[a];
       ld[p].s = std::min(dv[p] - ksel[p], s_max);
+      ld[p].take = count > 0 ? std::min(count - ksel[p], ld[p].s) : 0;
       ld[p].lock_off = tdd + tv + off_y[p];
       ld[p].nl = ksel[p];
       if (ksel[p] > LOCK_MAX) throw ArgError("more than 256 adaptive rows on one face");
@@ -1440,7 +1447,10 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
       res.iters += lo[a].iters;
       if (!lo[a].converged) res.unconverged++;
       int k = 0;
-      while (k < s && th[a][k] >= tau) ++k;
+      if (count > 0)
+        k = std::min(count - ksel[p], s);
+      else
+        while (k < s && th[a][k] >= tau) ++k;
       evs[p].insert(evs[p].end(), th[a].begin(), th[a].end());
       // keep the selected eigenvectors
       if (k > 0)
@@ -1513,7 +1523,38 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
     if (hstat[e])
       throw NotSpdError("adaptive pair problems: non-positive pivot in a pair factor (Assumption 2 may fail)");
   log("eigenvectors to jump space");
-  // ---- host: face rows
+  // ---- host: face rows, and edge rows when they are kept.  Pi_G acts glob
+  // by glob: each part of v is projected onto the null space of its glob's
+  // constraint rows chosen at setup (orthonormalized once per glob).
+  std::vector<std::vector<double>> hq(P.globs.size());
+  std::vector<int> hm(P.globs.size(), -1);
+  auto glob_basis = [&](int gi) -> int {
+    if (hm[gi] < 0) {
+      const GlobCov &cv = P.cov[gi];
+      hm[gi] = cv.m;
+      if (cv.m > 0) {
+        hq[gi] = cv.hrow;
+        orthonormalize(hq[gi], (int)P.globs[gi].dofs.size(), hm[gi]);
+      }
+    }
+    return hm[gi];
+  };
+  // r = v[cidx], projected; returns max |r|
+  auto glob_part = [&](const double *v, const std::vector<int> &cidx, int gi, std::vector<double> &r) {
+    const int n = (int)cidx.size(), m = glob_basis(gi);
+    const std::vector<double> &H = hq[gi];
+    r.resize(n);
+    for (int t = 0; t < n; ++t) r[t] = v[cidx[t]];
+    for (int a = 0; a < m; ++a) {
+      double dt = 0;
+      for (int t = 0; t < n; ++t) dt += H[(size_t)a * n + t] * r[t];
+      for (int t = 0; t < n; ++t) r[t] -= dt * H[(size_t)a * n + t];
+    }
+    double mx = 0;
+    for (double x : r) mx = std::max(mx, std::fabs(x));
+    return mx;
+  };
+  constexpr double EDGE_DROP = 1e-8;  // edge parts below this (relative to d) are rounding residue
   for (int p = 0; p < np; ++p) {
     const AdaptPair &ph = pairs[p];
     const int nc = ncv[p];
@@ -1522,35 +1563,33 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau) {
     st.eigs[ph.f] = ev;
     const int k = ksel[p];
     if (k == 0) continue;
-    const Glob &gl = P.globs[ph.gi];
-    const GlobCov &cv = P.cov[ph.gi];
-    const int nfd = (int)gl.dofs.size();
-    std::vector<double> Hq;
-    int m = cv.m;
-    if (m > 0) {
-      Hq = cv.hrow;
-      orthonormalize(Hq, nfd, m);
-    }
-    std::vector<double> rows;
+    const int ne = P.adapt_edges ? (int)ph.edge_gi.size() : 0;
+    std::vector<double> rf;
+    std::vector<std::vector<double>> re(ne);
+    std::vector<double> mxe(ne);
     for (int q = 0; q < k; ++q) {
-      std::vector<double> r(nfd);
-      for (int t = 0; t < nfd; ++t) r[t] = hv[off_jv[p] + (size_t)q * nc + ph.face_c[t]];
-      // project onto the null space of the face's existing constraint rows
-      for (int a = 0; a < m; ++a) {
-        double dt = 0;
-        for (int t = 0; t < nfd; ++t) dt += Hq[(size_t)a * nfd + t] * r[t];
-        for (int t = 0; t < nfd; ++t) r[t] -= dt * Hq[(size_t)a * nfd + t];
+      const double *v = hv.data() + off_jv[p] + (size_t)q * nc;
+      const double mxf = glob_part(v, ph.face_c, ph.gi, rf);
+      double scale = mxf;
+      for (int e = 0; e < ne; ++e) {
+        mxe[e] = glob_part(v, ph.edge_c[e], ph.edge_gi[e], re[e]);
+        scale = std::max(scale, mxe[e]);
       }
-      double mx = 0;
-      for (double v : r) mx = std::max(mx, std::fabs(v));
-      if (mx == 0) continue;
-      for (double &v : r) v /= mx;
-      rows.insert(rows.end(), r.begin(), r.end());
+      if (mxf > 0) {
+        for (double &x : rf) x /= mxf;
+        P.extra_rows[ph.gi].insert(P.extra_rows[ph.gi].end(), rf.begin(), rf.end());
+        P.extra_k[ph.gi] += 1;
+        res.n_added += 1;
+      }
+      for (int e = 0; e < ne; ++e) {
+        if (!(mxe[e] > EDGE_DROP * scale)) continue;
+        for (double &x : re[e]) x /= mxe[e];
+        const int gi = ph.edge_gi[e];
+        P.extra_rows[gi].insert(P.extra_rows[gi].end(), re[e].begin(), re[e].end());
+        P.extra_k[gi] += 1;
+        res.n_added_edge += 1;
+      }
     }
-    const int added = (int)(rows.size() / nfd);
-    P.extra_rows[ph.gi].insert(P.extra_rows[ph.gi].end(), rows.begin(), rows.end());
-    P.extra_k[ph.gi] += added;
-    res.n_added += added;
   }
   log("face rows (host)");
   return res;

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -145,6 +146,7 @@ bddc_status bddc_setup(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition 
     P.n_glob = ng;
     P.mode = cons->mode;
     P.drop_tol = cons->qr_drop_tol > 0 ? cons->qr_drop_tol : 1e-10;
+    P.adapt_edges = cons->adaptive_edges != 0;
     assemble_substructures(P);
     classify_interface(P, cons->augment_corners != 0);
     compute_weights(P);
@@ -212,11 +214,7 @@ bddc_status bddc_pcg_solve(bddc_ctx *c, int nrhs, const double *f, int64_t ldf, 
   return BDDC_OK;
 }
 
-bddc_status bddc_adapt(bddc_ctx *c, double tau, bddc_adapt_info *info) {
-  if (c && c->opt.device < 0) return fail(c, BDDC_ERR_STATE, "host-only context (device < 0)");
-  if (!c) return BDDC_ERR_ARG;
-  if (c->state < 1) return fail(c, BDDC_ERR_STATE, "bddc_adapt before bddc_setup");
-  if (!(tau > 0)) return fail(c, BDDC_ERR_ARG, "tau must be positive");
+static bddc_status adapt_impl(bddc_ctx *c, double tau, int count, bddc_adapt_info *info) {
   return guarded(c, [&] {
     check_hip(hipSetDevice(c->opt.device), "hipSetDevice");
     auto t0 = std::chrono::steady_clock::now();
@@ -228,7 +226,7 @@ bddc_status bddc_adapt(bddc_ctx *c, double tau, bddc_adapt_info *info) {
       for (int &k : c->P.extra_k) k = 0;
       build_constraints(c->P);
     }
-    AdaptResult res = run_adapt(c->P, *c->S, c->adapt, tau);
+    AdaptResult res = run_adapt(c->P, *c->S, c->adapt, tau, count);
     auto ta = std::chrono::steady_clock::now();
     build_constraints(c->P);
     auto tb = std::chrono::steady_clock::now();
@@ -248,8 +246,25 @@ bddc_status bddc_adapt(bddc_ctx *c, double tau, bddc_adapt_info *info) {
       info->lobpcg_iters = res.iters;
       info->unconverged = res.unconverged;
       info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      info->n_added_edge = res.n_added_edge;
     }
   });
+}
+
+bddc_status bddc_adapt(bddc_ctx *c, double tau, bddc_adapt_info *info) {
+  if (c && c->opt.device < 0) return fail(c, BDDC_ERR_STATE, "host-only context (device < 0)");
+  if (!c) return BDDC_ERR_ARG;
+  if (c->state < 1) return fail(c, BDDC_ERR_STATE, "bddc_adapt before bddc_setup");
+  if (!(tau > 0)) return fail(c, BDDC_ERR_ARG, "tau must be positive");
+  return adapt_impl(c, tau, 0, info);
+}
+
+bddc_status bddc_adapt_count(bddc_ctx *c, int rows_per_face, bddc_adapt_info *info) {
+  if (c && c->opt.device < 0) return fail(c, BDDC_ERR_STATE, "host-only context (device < 0)");
+  if (!c) return BDDC_ERR_ARG;
+  if (c->state < 1) return fail(c, BDDC_ERR_STATE, "bddc_adapt_count before bddc_setup");
+  if (rows_per_face < 1) return fail(c, BDDC_ERR_ARG, "rows_per_face must be >= 1");
+  return adapt_impl(c, HUGE_VAL, rows_per_face, info);
 }
 
 bddc_status bddc_get_info(const bddc_ctx *c, bddc_info *o) {
@@ -303,6 +318,26 @@ bddc_status bddc_get_face_rows(const bddc_ctx *c, int64_t f, int64_t max_rows, d
   *rows = k;
   *n_dofs = n;
   if (subs) subs[0] = g.subs[0], subs[1] = g.subs[1];
+  if (dofs)
+    for (int t = 0; t < n; ++t) dofs[t] = g.dofs[t];
+  if (out)
+    for (int64_t r = 0; r < std::min<int64_t>(k, max_rows); ++r)
+      for (int t = 0; t < n; ++t) out[r * n + t] = P.extra_rows[gi][(size_t)r * n + t];
+  return BDDC_OK;
+}
+
+bddc_status bddc_get_edge_rows(const bddc_ctx *c, int64_t e, int64_t max_rows, double *out,
+                               int64_t *dofs, int64_t *rows, int64_t *n_dofs) {
+  if (!c || !rows || !n_dofs) return BDDC_ERR_ARG;
+  if (c->state < 1) return BDDC_ERR_STATE;
+  const Problem &P = c->P;
+  if (e < 0 || e >= (int64_t)P.edge_ids.size()) return BDDC_ERR_ARG;
+  const int gi = P.edge_ids[e];
+  const Glob &g = P.globs[gi];
+  const int n = (int)g.dofs.size();
+  const int k = (gi < (int)P.extra_k.size()) ? P.extra_k[gi] : 0;
+  *rows = k;
+  *n_dofs = n;
   if (dofs)
     for (int t = 0; t < n; ++t) dofs[t] = g.dofs[t];
   if (out)

@@ -82,6 +82,7 @@ struct Problem {
   // constraints
   int mode = 1;
   double drop_tol = 1e-10;
+  bool adapt_edges = false;                      // keep the edge parts of adaptive rows
   std::vector<std::vector<double>> extra_rows;   // per glob: adaptive rows (k x n)
   std::vector<int> extra_k;
   std::vector<GlobCov> cov;

@@ -109,3 +109,103 @@ def test_adapt_replaces_rows_and_reuses_schur():
     b.factor()
     u2, _ = b.pcg_solve(f)
     assert torch.equal(u2.cpu(), u_ref.cpu())
+
+
+def _same_span(a, b, tol=1e-6):
+    """Row spaces of a and b agree: equal numerical rank (singular values
+    above tol of the largest) and principal-angle cosines within tol of one."""
+    sa, va = np.linalg.svd(a)[1:]
+    sb, vb = np.linalg.svd(b)[1:]
+    ra, rb = int(np.sum(sa > tol * sa[0])), int(np.sum(sb > tol * sb[0]))
+    assert ra == rb, (sa / sa[0], sb / sb[0])
+    cos = np.linalg.svd(va[:ra] @ vb[:rb].T)[1]
+    assert cos.min() > 1 - tol, cos
+
+
+EDGE_CASES = {
+    "layers6x2": (lambda: meshgen.small_elasticity_layers(6, 2, contrast=1e4), 10.0),
+    "kmeans_elast": (lambda: meshgen.small_kmeans(meshgen.ELASTICITY, 8, 4, contrast=1e3), 5.0),
+}
+
+
+@pytest.mark.parametrize("name", list(EDGE_CASES))
+def test_adapt_keeps_edge_rows(name):
+    """adaptive_edges: every selected row is split into a face row and one
+    row per edge of the face's closure (Sec. 3 after Proposition 1).  The
+    edge rows, Nc, omega and the solution match the oracle's; edge rows are
+    compared per edge as row spaces, since eigenvectors of repeated
+    eigenvalues, and hence their rows, are not unique."""
+    BDDC = _gpu()
+    from oracle.solver import OracleBDDC
+    from oracle.adapt import adapt, schur_dense
+    make, tau = EDGE_CASES[name]
+    p = make()
+    o = OracleBDDC(p, "ce")
+    Sd = {s: schur_dense(o.S, o.itf, s) for s in range(o.S.n_sub)}
+    ad = adapt(o.S, o.itf, o.cons, tau, Sd=Sd, edges=True)
+    o2 = OracleBDDC(p, "ce", extra_rows=ad["rows"])
+    b = BDDC()
+    b.setup(p, "ce", adaptive_edges=True)
+    info = b.adapt(tau)
+    assert info.unconverged == 0
+    assert abs(info.omega - ad["omega"]) <= 1e-6 * max(1.0, ad["omega"])
+    n_edge_rows = sum(len(r) for g, r in ad["rows"].items() if o.itf.globs[g]["kind"] == "edge")
+    assert n_edge_rows > 0 and info.n_added_edge == n_edge_rows
+    assert info.nc == o2.cons.Nc()
+    for e, gi in enumerate(o.itf.edge_ids):
+        rows, dofs = b.edge_rows(e)
+        assert np.array_equal(dofs, o.itf.globs[gi]["dofs"])
+        ref = ad["rows"].get(gi)
+        assert rows.shape[0] == (0 if ref is None else len(ref))
+        if rows.shape[0]:
+            _same_span(rows, ref)
+    for f, gi in enumerate(o.itf.face_ids):
+        rows, _, _ = b.face_rows(f)
+        ref = ad["rows"].get(gi)
+        assert rows.shape[0] == (0 if ref is None else len(ref))
+        if rows.shape[0]:
+            _same_span(rows, ref)
+    b.factor()
+    u, pinfo = b.pcg_solve(torch.from_numpy(p.f))
+    ref = o2.solve()
+    uu = u.cpu().numpy()[:, 0]
+    assert np.linalg.norm(uu - ref["u"]) / np.linalg.norm(ref["u"]) < 1e-8
+    assert abs(pinfo[0].iters - ref["iters"]) <= 2
+    b.close()
+
+
+@pytest.mark.parametrize("name", ["layers8", "kmeans_poisson"])
+def test_adapt_three_dominant_eigenvectors(name):
+    """bddc_adapt_count(3), the "3eigv" variant of Sec. 7: three rows per
+    face from the dominant eigenvectors whatever their eigenvalues; Nc, the
+    indicator (the largest fourth eigenvalue), the rows and the solution
+    match the oracle's count mode."""
+    BDDC = _gpu()
+    from oracle.solver import OracleBDDC
+    from oracle.adapt import adapt, schur_dense
+    make, _ = CASES[name]
+    p = make()
+    o = OracleBDDC(p, "ce")
+    Sd = {s: schur_dense(o.S, o.itf, s) for s in range(o.S.n_sub)}
+    ad = adapt(o.S, o.itf, o.cons, np.inf, Sd=Sd, count=3)
+    o2 = OracleBDDC(p, "ce", extra_rows=ad["rows"])
+    b = BDDC()
+    b.setup(p, "ce")
+    info = b.adapt_count(3)
+    assert info.unconverged == 0
+    assert info.n_added == 3 * len(o.itf.face_ids)
+    assert info.nc == o2.cons.Nc()
+    assert abs(info.omega - ad["omega"]) <= 1e-6 * max(1.0, ad["omega"])
+    for f, gi in enumerate(o.itf.face_ids):
+        lam_ref = ad["lam"][gi]
+        np.testing.assert_allclose(b.face_eigs(f)[:4], lam_ref[:4], rtol=1e-6)
+        rows, _, _ = b.face_rows(f)
+        assert rows.shape[0] == 3
+        _same_span(rows, ad["rows"][gi])
+    b.factor()
+    u, pinfo = b.pcg_solve(torch.from_numpy(p.f))
+    ref = o2.solve()
+    uu = u.cpu().numpy()[:, 0]
+    assert np.linalg.norm(uu - ref["u"]) / np.linalg.norm(ref["u"]) < 1e-8
+    assert abs(pinfo[0].iters - ref["iters"]) <= 2
+    b.close()
