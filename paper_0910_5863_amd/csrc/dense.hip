@@ -78,6 +78,8 @@ __device__ __forceinline__ bool xcd_remap(int nwg, int tiles_per_entry, int batc
 // and long K.  A or B may alias C (in-place products of one tile): every
 // operand element a work-group reads lies in its own C tile or is read before
 // the tile is written.
+// With KS = 1 the epilogue stages C through the operand buffers: a caller
+// that uses the LDS again after gemm_tile must synchronize first.
 template <class T, bool TA, bool TB, int MT, int NT, int KS = 1>
 __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int lda, int ldb,
                           int ldc, T alpha, T beta, int m0, int n0) {
@@ -87,6 +89,7 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
   constexpr int SA = BK * (TM + 2), SB = BK * (TN + 2);      // one buffer of A / B
   constexpr int PART = 256 * MT * NT * 4;                     // one group's partial tile
   constexpr int SOPS = KS * 2 * (SA + SB), SRED = (KS - 1) * PART;
+  static_assert(KS > 1 || SOPS >= 4 * (16 * MT + 1) * 16, "epilogue staging exceeds the operand buffers");
   __shared__ T smem[SOPS > SRED ? SOPS : SRED];
   const int tid = threadIdx.x % 256, g = threadIdx.x / 256;
   const int lane = tid & 63, wave = tid >> 6;
@@ -180,20 +183,54 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[x][y][j] += smem[q * PART + ridx(x, y, j)];
   }
+  if (KS == 1) {
+    // each wave stages one 16-column strip of its quadrant at a time in LDS
+    // (its own slot; the operand buffers are free after the last barrier)
+    // and writes C a column at a time: lanes on consecutive rows, so every
+    // access covers whole cache lines of the column-major C (the MFMA layout
+    // spreads a register over 16 columns)
+    constexpr int SR = 16 * MT + 1;  // strip rows + pad
+    T *stg = smem + wave * SR * 16;
+    const int r0 = m0 + wr * 16 * MT;
 #pragma unroll
-  for (int x = 0; x < MT; ++x)
+    for (int y = 0; y < NT; ++y) {
 #pragma unroll
-    for (int y = 0; y < NT; ++y)
+      for (int x = 0; x < MT; ++x)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = m0 + wr * 16 * MT + 16 * x + Mfma<T>::row(lane, j);
-        const int col = n0 + wc * 16 * NT + 16 * y + (lane & 15);
+        for (int j = 0; j < 4; ++j)
+          stg[16 * x + Mfma<T>::row(lane, j) + (lane & 15) * SR] = alpha * acc[x][y][j];
+      __builtin_amdgcn_wave_barrier();
+      __asm__ volatile("" ::: "memory");
+      const int c0 = n0 + wc * 16 * NT + 16 * y;
+#pragma unroll
+      for (int it = 0; it < MT * 4; ++it) {
+        const int i = lane + 64 * it, r = i % (16 * MT), c = i / (16 * MT);
+        const int row = r0 + r, col = c0 + c;
         if (row < M && col < N) {
-          T *c = &C[row + (int64_t)col * ldc];
-          const T v = alpha * acc[x][y][j];
-          *c = (beta == T(0)) ? v : v + beta * (*c);
+          T *cp = &C[row + (int64_t)col * ldc];
+          const T v = stg[r + c * SR];
+          *cp = (beta == T(0)) ? v : v + beta * (*cp);
         }
       }
+      __builtin_amdgcn_wave_barrier();
+      __asm__ volatile("" ::: "memory");
+    }
+  } else {
+#pragma unroll
+    for (int x = 0; x < MT; ++x)
+#pragma unroll
+      for (int y = 0; y < NT; ++y)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = m0 + wr * 16 * MT + 16 * x + Mfma<T>::row(lane, j);
+          const int col = n0 + wc * 16 * NT + 16 * y + (lane & 15);
+          if (row < M && col < N) {
+            T *c = &C[row + (int64_t)col * ldc];
+            const T v = alpha * acc[x][y][j];
+            *c = (beta == T(0)) ? v : v + beta * (*c);
+          }
+        }
+  }
 }
 
 template <class T, bool TA, bool TB, int MT, int NT>
