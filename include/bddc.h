@@ -68,6 +68,14 @@ typedef struct {
   void (*free)(void *ptr, void *user);
   void *alloc_user;
   int verbose;                       /* nonzero: per-phase timings on stderr */
+  int autotune;                      /* nonzero: the first batched GEMM of each shape
+                                        (element type, transposes, batch size, largest
+                                        M, N, K) times every tile shape whose result is
+                                        bitwise the default one's and keeps the fastest
+                                        for the rest of the process; the trials save
+                                        and restore the product's output, so results
+                                        do not depend on this switch.  The first call
+                                        of a shape costs a few extra products. */
 } bddc_options;
 
 /* Q1 hexahedral mesh (Sec. 2: substructure matrices are subassembled from
@@ -150,6 +158,7 @@ typedef struct {
   double apply_bytes;        /* bytes the PCG-internal apply streams per RHS */
   double pcg_iter_bytes;     /* bytes one PCG iteration streams per RHS */
   size_t device_bytes;       /* device memory held by the context */
+  int64_t autotune_entries;  /* GEMM shapes tuned so far in this process */
 } bddc_info;
 
 bddc_status bddc_create(const bddc_options *opt, bddc_ctx **ctx);

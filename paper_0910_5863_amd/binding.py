@@ -39,7 +39,7 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 class bddc_options(C.Structure):
     _fields_ = [("device", C.c_int), ("hip_stream", C.c_void_p), ("factor_precision", C.c_int),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", C.c_void_p),
-                ("verbose", C.c_int)]
+                ("verbose", C.c_int), ("autotune", C.c_int)]
 
 
 class bddc_mesh(C.Structure):
@@ -81,7 +81,7 @@ class bddc_info(C.Structure):
                 ("max_interior", C.c_int64), ("max_iface", C.c_int64),
                 ("factor_flops", C.c_double), ("factor_seconds", C.c_double),
                 ("apply_bytes", C.c_double), ("pcg_iter_bytes", C.c_double),
-                ("device_bytes", C.c_size_t)]
+                ("device_bytes", C.c_size_t), ("autotune_entries", C.c_int64)]
 
 
 class bddc_server_options(C.Structure):
@@ -337,7 +337,7 @@ class BDDC:
     ``device < 0`` gives a host-only context (setup analysis, no GPU)."""
 
     def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True,
-                 verbose: bool = False, factor_precision: int = 64):
+                 verbose: bool = False, factor_precision: int = 64, autotune: bool = False):
         if device < 0:
             self.torch = None
             self.device = device
@@ -360,6 +360,7 @@ class BDDC:
         opt.hip_stream = C.c_void_p(stream.cuda_stream)
         opt.factor_precision = int(factor_precision)
         opt.verbose = 1 if verbose else 0
+        opt.autotune = 1 if autotune else 0
         self._keep = []
         if torch_allocator:
             def _alloc(n, user):

@@ -38,11 +38,16 @@ bddc_status fail(bddc_ctx *c, int code, const std::string &m) {
 template <class F>
 bddc_status guarded(bddc_ctx *c, F f) {
   // per-launch timing hook for the duration of the call
+  // and the GEMM autotuning switch
   struct Hook {
     explicit Hook(bddc_ctx *c) {
       launch_timing() = (c && c->S && c->S->timer.mode == 2) ? &c->S->timer : nullptr;
+      autotune_enabled() = c && c->opt.autotune != 0;
     }
-    ~Hook() { launch_timing() = nullptr; }
+    ~Hook() {
+      launch_timing() = nullptr;
+      autotune_enabled() = false;
+    }
   } hook(c);
   try {
     f();
@@ -302,6 +307,7 @@ bddc_status bddc_get_info(const bddc_ctx *c, bddc_info *o) {
   o->apply_bytes = c->S->apply_bytes();
   o->pcg_iter_bytes = c->S->iter_bytes();
   o->device_bytes = c->S->alloc.held;
+  o->autotune_entries = autotune_entries();
   return BDDC_OK;
 }
 

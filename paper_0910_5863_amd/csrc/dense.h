@@ -25,6 +25,15 @@ struct LaunchTiming {
 };
 LaunchTiming *&launch_timing();  // the calling thread's slot (nullptr: off)
 
+// GEMM tile autotuning.  When on for the calling thread, the first
+// DenseOps::gemm call of each shape signature (element type, transposes,
+// lower, batch size, largest M, N and K) times every tile shape whose result
+// is bitwise the default one's, and that signature uses the fastest from
+// then on (a table shared by the process).  Calls under stream capture use
+// the table but never tune.
+bool &autotune_enabled();   // the calling thread's switch (default off)
+int64_t autotune_entries();  // signatures tuned so far in this process
+
 struct LaunchScope {
   hipStream_t st;
   LaunchTiming *t;

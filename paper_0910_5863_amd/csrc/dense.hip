@@ -22,6 +22,9 @@
 #include <climits>
 #include <vector>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include "dense.h"
 
 namespace bddc {
@@ -80,7 +83,10 @@ __device__ __forceinline__ bool xcd_remap(int nwg, int tiles_per_entry, int batc
 // the tile is written.
 // With KS = 1 the epilogue stages C through the operand buffers: a caller
 // that uses the LDS again after gemm_tile must synchronize first.
-template <class T, bool TA, bool TB, int MT, int NT, int KS = 1>
+// TAG tells the callers apart: each kernel uses instantiations of its own, so
+// that no LDS array is reached from two kernels (such an array is addressed
+// through a per-kernel lookup table, which costs registers).
+template <class T, bool TA, bool TB, int MT, int NT, int KS = 1, int TAG = 0>
 __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int lda, int ldb,
                           int ldc, T alpha, T beta, int m0, int n0) {
   typedef typename Mfma<T>::v4 v4;
@@ -245,8 +251,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T *A, const T *B, T *C,
   const int m0 = ti * TM, n0 = tj * TN;
   if (m0 >= d.M || n0 >= d.N) return;
   if (lower && m0 + TM - 1 < n0) return;
-  gemm_tile<T, TA, TB, MT, NT>(A + d.a_off, B + d.b_off, C + d.c_off, d.M, d.N, d.K, d.lda, d.ldb,
-                               d.ldc, alpha, beta, m0, n0);
+  gemm_tile<T, TA, TB, MT, NT, 1, 0>(A + d.a_off, B + d.b_off, C + d.c_off, d.M, d.N, d.K, d.lda,
+                                     d.ldb, d.ldc, alpha, beta, m0, n0);
 }
 
 // --- Cholesky -------------------------------------------------------------
@@ -266,8 +272,8 @@ __global__ __launch_bounds__(256 * KS) void chol_update_kernel(T *pool, const Ma
   const int M = d.n - kb, N = min(NB, d.n - kb), K = kb;
   if (t * TM >= M) return;
   T *A = pool + d.a_off;
-  gemm_tile<T, false, true, MT, 2, KS>(A + kb, A + kb, A + kb + (int64_t)kb * d.lda, M, N, K,
-                                       d.lda, d.lda, d.lda, T(-1), T(1), t * TM, 0);
+  gemm_tile<T, false, true, MT, 2, KS, 1>(A + kb, A + kb, A + kb + (int64_t)kb * d.lda, M, N, K,
+                                          d.lda, d.lda, d.lda, T(-1), T(1), t * TM, 0);
 }
 
 // Factor the diagonal block of block column k in LDS, in place, and write
@@ -370,7 +376,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc 
   const int nr = min(NB, d.n - r0);
   T *X = pool + d.a_off + r0 + (int64_t)kb * d.lda;
   const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
-  gemm_tile<T, false, true, 2, 2>(X, Di, X, nr, w, w, d.lda, NB, d.lda, T(1), T(0), 0, 0);
+  gemm_tile<T, false, true, 2, 2, 1, 2>(X, Di, X, nr, w, w, d.lda, NB, d.lda, T(1), T(0), 0, 0);
 }
 
 // --- multi-RHS triangular solves -------------------------------------------
@@ -395,13 +401,14 @@ __global__ __launch_bounds__(256 * KS) void trsm_update_kernel(const T *apool, T
   T *B = bpool + d.b_off;
   if (!BWD) {
     if (kb == 0) return;
-    gemm_tile<T, false, false, 2, NT, KS>(L + kb, B, B + kb, w, d.nrhs, kb, d.lda, d.ldb, d.ldb,
-                                          T(-1), T(1), 0, t * TN);
+    gemm_tile<T, false, false, 2, NT, KS, 3>(L + kb, B, B + kb, w, d.nrhs, kb, d.lda, d.ldb, d.ldb,
+                                             T(-1), T(1), 0, t * TN);
   } else {
     const int K = d.n - kb - w;
     if (K <= 0) return;
-    gemm_tile<T, true, false, 2, NT, KS>(L + (kb + w) + (int64_t)kb * d.lda, B + kb + w, B + kb,
-                                         w, d.nrhs, K, d.lda, d.ldb, d.ldb, T(-1), T(1), 0, t * TN);
+    gemm_tile<T, true, false, 2, NT, KS, 3>(L + (kb + w) + (int64_t)kb * d.lda, B + kb + w, B + kb,
+                                            w, d.nrhs, K, d.lda, d.ldb, d.ldb, T(-1), T(1), 0,
+                                            t * TN);
   }
 }
 
@@ -423,7 +430,7 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool
   if (c0 >= d.nrhs) return;
   T *B = bpool + d.b_off + kb;
   const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
-  gemm_tile<T, BWD, false, 2, 2>(Di, B, B, w, d.nrhs, w, NB, d.ldb, d.ldb, T(1), T(0), 0, c0);
+  gemm_tile<T, BWD, false, 2, 2, 1, 4>(Di, B, B, w, d.nrhs, w, NB, d.ldb, d.ldb, T(1), T(0), 0, c0);
 }
 
 template <class T>
@@ -725,6 +732,97 @@ inline int grid_round(int n) { return ((n + NXCD - 1) / NXCD) * NXCD; }
 inline int blk(int n, int k) { return std::max(0, std::min(NB, n - k * NB)); }
 }  // namespace
 
+#define HIP_RETURN_IF(x)            \
+  do {                              \
+    hipError_t e_ = (x);            \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
+// --- GEMM tile autotuning ---------------------------------------------------
+// A shape signature (element size, transposes, lower, batch, largest M, N, K)
+// maps to the tile shape measured fastest on its first call.  Every candidate
+// accumulates each entry of C over K in the same order (KS = 1, MFMA K-steps
+// ascending), so they give the same bits and the choice changes only time.
+struct TuneKey {
+  int elem;
+  bool ta, tb, lower;
+  int batch, maxM, maxN, maxK;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(elem, ta, tb, lower, batch, maxM, maxN, maxK) <
+           std::tie(o.elem, o.ta, o.tb, o.lower, o.batch, o.maxM, o.maxN, o.maxK);
+  }
+};
+constexpr int N_TILE_SHAPES = 4;  // 128 x 128, 64 x 64, 128 x 64, 64 x 128
+
+std::mutex &tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+std::map<TuneKey, int> &tune_table() {
+  static std::map<TuneKey, int> t;
+  return t;
+}
+int tune_lookup(const TuneKey &k) {
+  std::lock_guard<std::mutex> g(tune_mutex());
+  auto it = tune_table().find(k);
+  return it == tune_table().end() ? -1 : it->second;
+}
+void tune_store(const TuneKey &k, int shape) {
+  std::lock_guard<std::mutex> g(tune_mutex());
+  tune_table().emplace(k, shape);
+}
+
+// Times every tile shape on the call's own operands: C (the span the batch
+// writes, which also covers A or B where they alias it) is saved first and
+// restored before each further trial and before the final launch by the
+// caller, so the call's result is that of one product.  Returns the fastest
+// shape (the default one on ties), or -1 after a HIP error.
+template <class T, class Launch>
+int tune_gemm(hipStream_t st, T *C, const GemmDesc *h, int batch, int dflt, Launch &launch) {
+  int64_t lo = INT64_MAX, hi = 0;
+  for (int e = 0; e < batch; ++e) {
+    if (h[e].M <= 0 || h[e].N <= 0) continue;
+    lo = std::min(lo, h[e].c_off);
+    hi = std::max(hi, h[e].c_off + (int64_t)h[e].ldc * (h[e].N - 1) + h[e].M);
+  }
+  if (hi <= lo) return dflt;
+  const size_t bytes = sizeof(T) * (size_t)(hi - lo);
+  void *save = nullptr;
+  if (hipMallocAsync(&save, bytes, st) != hipSuccess) return dflt;  // no room: keep the default
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return -1;
+  if (hipEventCreate(&ev[1]) != hipSuccess) return -1;
+  float best = 0;
+  int pick = dflt;
+  bool ok = hipMemcpyAsync(save, C + lo, bytes, hipMemcpyDeviceToDevice, st) == hipSuccess;
+  for (int q = 0; q < N_TILE_SHAPES && ok; ++q) {
+    const int shape = (dflt + q) % N_TILE_SHAPES;  // the default first
+    if (q > 0) ok = hipMemcpyAsync(C + lo, save, bytes, hipMemcpyDeviceToDevice, st) == hipSuccess;
+    ok = ok && hipEventRecord(ev[0], st) == hipSuccess;
+    if (ok) launch(shape);
+    ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(ev[1], st) == hipSuccess &&
+         hipEventSynchronize(ev[1]) == hipSuccess;
+    float ms = 0;
+    ok = ok && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess;
+    if (ok && (q == 0 || ms < best)) best = ms, pick = shape;
+  }
+  ok = ok && hipMemcpyAsync(C + lo, save, bytes, hipMemcpyDeviceToDevice, st) == hipSuccess;
+  ok = hipFreeAsync(save, st) == hipSuccess && ok;
+  ok = hipEventDestroy(ev[0]) == hipSuccess && ok;
+  ok = hipEventDestroy(ev[1]) == hipSuccess && ok;
+  return ok ? pick : -1;
+}
+
+bool &autotune_enabled() {
+  static thread_local bool on = false;
+  return on;
+}
+
+int64_t autotune_entries() {
+  std::lock_guard<std::mutex> g(tune_mutex());
+  return (int64_t)tune_table().size();
+}
+
 template <class T, int MT, int NT>
 static void launch_gemm(hipStream_t st, const T *A, const T *B, T *C, const GemmDesc *d_desc,
                         int batch, int maxM, int maxN, bool transA, bool transB, T alpha, T beta,
@@ -755,11 +853,33 @@ hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const
       by += sizeof(T) * ((double)q.M * q.K + (double)q.K * q.N + (beta != T(0) ? 2.0 : 1.0) * mn);
     }
   LaunchScope ls(st, "gemm_kernel", by, fl);
-  // 128 x 128 tiles for large products, 64 x 64 otherwise
-  if (maxM >= 256 && maxN >= 256)
-    launch_gemm<T, 4, 4>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower);
-  else
-    launch_gemm<T, 2, 2>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower);
+  auto launch = [&](int shape) {
+    switch (shape) {
+      case 0: launch_gemm<T, 4, 4>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower); break;
+      case 1: launch_gemm<T, 2, 2>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower); break;
+      case 2: launch_gemm<T, 4, 2>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower); break;
+      default: launch_gemm<T, 2, 4>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower); break;
+    }
+  };
+  // 128 x 128 tiles for large products, 64 x 64 otherwise, unless the tuner
+  // has measured this shape
+  int shape = (maxM >= 256 && maxN >= 256) ? 0 : 1;
+  if (autotune_enabled() && h_desc) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_RETURN_IF(hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusNone) {
+      TuneKey key{sizeof(T), transA, transB, lower, batch, maxM, maxN, 0};
+      for (int e = 0; e < batch; ++e) key.maxK = std::max(key.maxK, h_desc[e].K);
+      int found = tune_lookup(key);
+      if (found < 0) {
+        found = tune_gemm(st, C, h_desc, batch, shape, launch);
+        if (found < 0) return hipGetLastError();
+        tune_store(key, found);
+      }
+      shape = found;
+    }
+  }
+  launch(shape);
   return hipGetLastError();
 }
 
