@@ -260,18 +260,32 @@ __device__ __forceinline__ void tile_store(double *Out, int d, int r0, int ncol,
 // Launched with LOB_NT threads.
 __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1], int n,
                            double *cs, double *sn, double *red) {
-  __shared__ int pp[LOB_MAXB / 2 + 1], qq[LOB_MAXB / 2 + 1];
+  // the step's pairs (p | q << 16) and rotations (c, s), one 4-byte and one
+  // 16-byte LDS read per pair
+  __shared__ int pq[LOB_MAXB / 2 + 1];
+  __shared__ double2 rot[LOB_MAXB / 2 + 1];
+  (void)cs;
+  (void)sn;
   const int tid = threadIdx.x;
   for (int i = tid; i < n * n; i += LOB_NT) V[i % n][i / n] = (i % n == i / n) ? 1.0 : 0.0;
   const int m = (n + 1) / 2 * 2;  // even number of players (a dummy when n is odd)
   const int half = m / 2;
-  // round-robin schedule: player 0 stays, the others move one place per step,
-  // so at step t position i >= 1 holds player 1 + ((i - 1 - t) mod (m - 1))
-  auto player = [m](int i, int t) {
-    if (i == 0) return 0;
-    const int r = (i - 1 - t) % (m - 1);
-    return 1 + (r < 0 ? r + m - 1 : r);
-  };
+  // the 2 x 2 blocks (k, l) of H and the (row, l) entries of V a thread
+  // updates are the same at every step (only the players in them change):
+  // indices computed once, outside the step loop
+  int bk[JAC_NB], bl[JAC_NB], vr[JAC_NV], vl[JAC_NV];
+#pragma unroll
+  for (int u = 0; u < JAC_NB; ++u) {
+    const int e = tid + u * LOB_NT;
+    bk[u] = e < half * half ? e % half : -1;
+    bl[u] = e / half;
+  }
+#pragma unroll
+  for (int u = 0; u < JAC_NV; ++u) {
+    const int e = tid + u * LOB_NT;
+    vr[u] = e < n * half ? e % n : -1;
+    vl[u] = e / n;
+  }
   __syncthreads();
   double tot = 0;
   for (int i = tid; i < n * n; i += LOB_NT) tot += H[i % n][i / n] * H[i % n][i / n];
@@ -289,11 +303,16 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
     off = block_sum(off, red);
     viol = block_sum(viol, red);
     if (viol == 0 || off <= 1e-30 * tot || tot == 0) break;
+    // round-robin schedule: player 0 stays at position 0; the player at
+    // position i >= 1 moves down one place per step (from 1 back to m - 1).
+    // Thread k < m/2 pairs positions k and m - 1 - k; at step 0 position i
+    // holds player i.
+    int pa = tid, pb = m - 1 - tid;
     for (int step = 0; step < m - 1; ++step) {
-      // the step's pairs (player(k), player(m-1-k)), k < m/2, and rotations;
-      // a pair with the dummy (q = n) keeps c = 1, s = 0
+      // the step's pairs and rotations; a pair with the dummy (q = n) keeps
+      // c = 1, s = 0
       if (tid < half) {
-        int p = player(tid, step), q = player(m - 1 - tid, step);
+        int p = pa, q = pb;
         if (p > q) {
           const int t = p;
           p = q;
@@ -306,18 +325,27 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
           c = 1 / sqrt(t * t + 1);
           s = t * c;
         }
-        pp[tid] = p;
-        qq[tid] = q;
-        cs[tid] = c;
-        sn[tid] = s;
+        pq[tid] = p | (q << 16);
+        rot[tid] = double2{c, s};
+        if (tid > 0) pa = pa > 1 ? pa - 1 : m - 1;
+        pb = pb > 1 ? pb - 1 : m - 1;
       }
       __syncthreads();
+      // every read of the step before any write (the reads of one thread
+      // then overlap in flight); the blocks partition H and the items
+      // partition the touched entries of V, so no other thread touches
+      // these entries in this step
+      int hk[JAC_NB], hl[JAC_NB], vk[JAC_NV];
+      double2 rk[JAC_NB], rl[JAC_NB], rv[JAC_NV];
       double hb[JAC_NB][4], vb[JAC_NV][2];
 #pragma unroll
       for (int u = 0; u < JAC_NB; ++u) {
-        const int e = tid + u * LOB_NT;
-        if (e < half * half) {
-          const int pk = pp[e % half], qk = qq[e % half], pl = pp[e / half], ql = qq[e / half];
+        if (bk[u] >= 0) {
+          hk[u] = pq[bk[u]];
+          hl[u] = pq[bl[u]];
+          rk[u] = rot[bk[u]];
+          rl[u] = rot[bl[u]];
+          const int pk = hk[u] & 0xffff, qk = hk[u] >> 16, pl = hl[u] & 0xffff, ql = hl[u] >> 16;
           hb[u][0] = H[pk][pl];
           hb[u][1] = ql < n ? H[pk][ql] : 0.0;
           hb[u][2] = qk < n ? H[qk][pl] : 0.0;
@@ -326,20 +354,19 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
       }
 #pragma unroll
       for (int u = 0; u < JAC_NV; ++u) {
-        const int e = tid + u * LOB_NT;
-        if (e < n * half) {
-          const int row = e % n, pl = pp[e / n], ql = qq[e / n];
-          vb[u][0] = V[row][pl];
-          vb[u][1] = ql < n ? V[row][ql] : 0.0;
+        if (vr[u] >= 0) {
+          vk[u] = pq[vl[u]];
+          rv[u] = rot[vl[u]];
+          const int pl = vk[u] & 0xffff, ql = vk[u] >> 16;
+          vb[u][0] = V[vr[u]][pl];
+          vb[u][1] = ql < n ? V[vr[u]][ql] : 0.0;
         }
       }
 #pragma unroll
       for (int u = 0; u < JAC_NB; ++u) {
-        const int e = tid + u * LOB_NT;
-        if (e < half * half) {
-          const int k = e % half, l = e / half;
-          const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
-          const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+        if (bk[u] >= 0) {
+          const int pk = hk[u] & 0xffff, qk = hk[u] >> 16, pl = hl[u] & 0xffff, ql = hl[u] >> 16;
+          const double ck = rk[u].x, sk = rk[u].y, cl = rl[u].x, sl = rl[u].y;
           // rows (J_k^T B), then columns (. J_l)
           const double rpp = ck * hb[u][0] - sk * hb[u][2], rpq = ck * hb[u][1] - sk * hb[u][3];
           const double rqp = sk * hb[u][0] + ck * hb[u][2], rqq = sk * hb[u][1] + ck * hb[u][3];
@@ -351,13 +378,11 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
       }
 #pragma unroll
       for (int u = 0; u < JAC_NV; ++u) {
-        const int e = tid + u * LOB_NT;
-        if (e < n * half) {
-          const int row = e % n, l = e / n;
-          const int pl = pp[l], ql = qq[l];
-          const double cl = cs[l], sl = sn[l];
-          V[row][pl] = cl * vb[u][0] - sl * vb[u][1];
-          if (ql < n) V[row][ql] = sl * vb[u][0] + cl * vb[u][1];
+        if (vr[u] >= 0) {
+          const int pl = vk[u] & 0xffff, ql = vk[u] >> 16;
+          const double cl = rv[u].x, sl = rv[u].y;
+          V[vr[u]][pl] = cl * vb[u][0] - sl * vb[u][1];
+          if (ql < n) V[vr[u]][ql] = sl * vb[u][0] + cl * vb[u][1];
         }
       }
       __syncthreads();
