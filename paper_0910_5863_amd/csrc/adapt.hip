@@ -253,8 +253,9 @@ __device__ __forceinline__ void tile_store(double *Out, int d, int r0, int ncol,
 // rotated on both sides by one thread, and each pair of V's columns likewise.
 // The blocks partition H, so each thread reads its entries and writes them
 // back with no other thread touching them in between.
-// Sweeps stop when every off-diagonal entry is below 1e-15 sqrt(|h_pp h_qq|)
-// (relative accuracy for semidefinite H) or below 1e-17 of the Frobenius norm
+// Sweeps stop when every off-diagonal entry is below 1e-13 sqrt(|h_pp h_qq|)
+// (eigenvalues then hold to about 1e-26 relative and eigenvectors to 1e-13,
+// far inside the 1e-8 residual tolerance of the Ritz pairs) or below 1e-17 of the Frobenius norm
 // (rotations preserve it; smaller entries cannot move the eigenpairs), or the
 // off-diagonal mass is below 1e-30 of the total, or after 20 sweeps.
 // Launched with LOB_NT threads.
@@ -298,7 +299,7 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
       if (a == b) continue;
       const double h = H[a][b];
       off += h * h;
-      if (fabs(h) > fmax(1e-15 * sqrt(fabs(H[a][a] * H[b][b])), floor_abs)) viol += 1;
+      if (fabs(h) > fmax(1e-13 * sqrt(fabs(H[a][a] * H[b][b])), floor_abs)) viol += 1;
     }
     off = block_sum(off, red);
     viol = block_sum(viol, red);
@@ -322,7 +323,7 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
         if (q < n && H[p][q] != 0.0) {
           const double theta = (H[q][q] - H[p][p]) / (2 * H[p][q]);
           const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1));
-          c = 1 / sqrt(t * t + 1);
+          c = rsqrt(t * t + 1);
           s = t * c;
         }
         pq[tid] = p | (q << 16);
