@@ -47,6 +47,7 @@ KERNEL_SOURCE.update({"trsv_kernel<lower>": "paper_0910_5863_amd/csrc/dense.hip"
                       "mf_bwd_kernel": "paper_0910_5863_amd/csrc/multifrontal.hip",
                       "mf_pull_kernel": "paper_0910_5863_amd/csrc/multifrontal.hip",
                       "gemv_t_kernel": "paper_0910_5863_amd/csrc/solver.hip",
+                      "symv_kernel": "paper_0910_5863_amd/csrc/solver.hip",
                       "gemv_n_kernel": "paper_0910_5863_amd/csrc/solver.hip",
                       "lobpcg_kernel": "paper_0910_5863_amd/csrc/adapt.hip"})
 

@@ -148,6 +148,7 @@ class Solver {
 
   int64_t n_rows = 0, nnz = 0;
   double bytes_S = 0, bytes_Lrr_tri = 0;
+  double bytes_S_sym = 0, symv_parts = 0;  // symmetric Schur product: panel bytes, partial sums
   int n_gx = 0;
   TrsvPlan plan_rr, plan_c;
   std::vector<MatDesc> h_descRR, h_descGG, h_descC;
@@ -172,6 +173,7 @@ class Solver {
   DBuf d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, d_work_i, d_status;
   DBuf d_vG, d_vG2, d_vR, d_vR2, d_vP, d_vI, d_vI2, d_vc;
   DBuf d_gam_r, d_gam_z, d_gam_p, d_gam_q, d_gam_x, d_sc, d_part, d_alphas, d_betas;
+  DBuf d_symv_part, d_symv_off;  // partial products of the symmetric Schur operator
   DBuf d_pcg_ctl, d_pcg_hist;  // PCG control words (stop, iterations, converged, maxit), history
   // one PCG iteration captured as a graph (rebuilt after every build); the
   // stream it is captured on, two events and pinned words for the lookahead

@@ -295,6 +295,73 @@ __global__ void apply_T_store_kernel(double *xv, const GlobXf *gx, const int *gk
   xv[pos[x.piv_off + k]] = scr[x.scr_off + k];
 }
 
+// y_s = S_s x_s for symmetric S_s (column-major, both triangles stored)
+// reading only the lower triangle, in two launches.  Work-group (J, s) takes
+// the panel of S_s below the diagonal of column block J (columns 64J..64J+63,
+// rows 64J..n-1): its columns give y[c] = sum_{r >= 64J} S[r][c] x[r] for c
+// in the block (the diagonal block read whole), and its rows below the
+// diagonal block give the partial sums a_J[r] = sum_c S[r][c] x[c], which
+// stand for the upper triangle.  symv_reduce_kernel then adds, for r in
+// block J, a_0[r] + ... + a_{J-1}[r] in that order, so the result does not
+// depend on scheduling.  Partials of (s, J) start at off[s] + J n - 32 J (J+1)
+// (panel J holds n - 64 (J+1) rows below its diagonal block).
+constexpr int SYMV_NT = 256;
+__global__ __launch_bounds__(SYMV_NT) void symv_panel_kernel(const double *spool, const int64_t *soff,
+                                                             const int *nG, const double *x,
+                                                             const int64_t *xoff, double *y,
+                                                             double *part, const int64_t *poff) {
+  __shared__ double red[2][4][64];
+  const int s = blockIdx.y, n = nG[s], c0 = 64 * blockIdx.x;
+  if (c0 >= n) return;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const double *A = spool + soff[s];
+  const double *xs = x + xoff[s];
+  const int cg = c0 + 16 * g;  // this wave's 16 columns
+  double xc[16], dacc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    xc[j] = cg + j < n ? xs[cg + j] : 0.0;
+    dacc[j] = 0.0;
+  }
+  double *ps = part + poff[s] + (int64_t)blockIdx.x * n - 32ll * blockIdx.x * (blockIdx.x + 1);
+  int buf = 0;
+  for (int rt = c0; rt < n; rt += 64, buf ^= 1) {
+    const int r = rt + lane;
+    const bool rv = r < n;
+    const double xr = rv ? xs[r] : 0.0;
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double v = (rv && cg + j < n) ? A[r + (int64_t)(cg + j) * n] : 0.0;
+      dacc[j] += v * xr;
+      a += v * xc[j];
+    }
+    if (rt > c0) {  // rows below the diagonal block (uniform per work-group)
+      red[buf][g][lane] = a;
+      __syncthreads();
+      if (g == 0 && rv) ps[r - (c0 + 64)] = ((red[buf][0][lane] + red[buf][1][lane]) + red[buf][2][lane]) + red[buf][3][lane];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    double t = dacc[j];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if (lane == 0 && cg + j < n) y[xoff[s] + cg + j] = t;
+  }
+}
+
+__global__ void symv_reduce_kernel(const int *nG, const int64_t *xoff, double *y, const double *part,
+                                   const int64_t *poff) {
+  const int s = blockIdx.y, n = nG[s];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int J = r / 64;
+  const double *ps = part + poff[s];
+  double acc = y[xoff[s] + r];
+  for (int j = 0; j < J; ++j) acc += ps[(int64_t)j * n - 32ll * j * (j + 1) + (r - 64 * (j + 1))];
+  y[xoff[s] + r] = acc;
+}
+
 // batched GEMV on column-major blocks: y_i = alpha op(A_i) x_i + beta y_i.
 // trans: y[j] = sum_r A[r, j] x[r] (a wave per output, coalesced columns);
 // notrans: y[r] = sum_j A[r, j] x[j] (a thread per output row).
@@ -613,7 +680,7 @@ std::vector<DBuf *> Solver::struct_buffers() {
           &d_offGG, &d_S, &d_W, &d_descGG, &d_ifc_gamma, &d_ifc_delta, &d_gamma_ptr,
           &d_gamma_copies, &d_gamma_gdof, &d_int_gdof, &d_ifc_gdof, &d_vG, &d_vG2, &d_vI, &d_vI2,
           &d_gam_r, &d_gam_z, &d_gam_p, &d_gam_q, &d_gam_x, &d_sc, &d_part, &d_alphas, &d_betas,
-          &d_pcg_ctl, &d_pcg_hist};
+          &d_pcg_ctl, &d_pcg_hist, &d_symv_part, &d_symv_off};
 }
 
 std::vector<DBuf *> Solver::cons_buffers() {
@@ -1002,6 +1069,25 @@ void Solver::build_structure(const Problem &P, hipStream_t st) {
   const size_t R = kMaxRhs;
   d_vG = alloc0(alloc, st, sizeof(double) * L.sumG * R);
   d_vG2 = alloc0(alloc, st, sizeof(double) * L.sumG * R);
+  {
+    // partial sums of the symmetric Schur products: n - 64 (J+1) rows per
+    // column block J below its diagonal block
+    std::vector<int64_t> off(ns);
+    int64_t tot = 0;
+    bytes_S_sym = 0;
+    for (int s = 0; s < ns; ++s) {
+      off[s] = tot;
+      const int64_t n = L.nG[s], nb = (n + 63) / 64;
+      for (int64_t j = 0; j < nb; ++j) {
+        tot += std::max<int64_t>(0, n - 64 * (j + 1));
+        // the panel read: rows 64j.. of its columns (diagonal block whole)
+        bytes_S_sym += 8.0 * (double)std::min<int64_t>(64, n - 64 * j) * (double)(n - 64 * j);
+      }
+    }
+    symv_parts = (double)tot;
+    d_symv_part = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, tot));
+    d_symv_off = upload(alloc, st, off);
+  }
   d_vI = alloc0(alloc, st, sizeof(double) * L.sumI * R);
   d_vI2 = alloc0(alloc, st, sizeof(double) * L.sumI * R);
   d_gam_r = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
@@ -1238,11 +1324,21 @@ void Solver::schur_gamma(const double *p, double *q) {
   gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(p, L.n_gamma, d_ifc_gamma.as<int64_t>(), nullptr, vG,
                                                  L.sumG, L.sumG, 1);
   if (L.max_nG > 0) {
-    timer.begin(st, "schur_gemv", bytes_S + 16.0 * L.sumG, 2.0 * (double)L.sGG);
-    LaunchScope ls(st, "gemv_t_kernel", bytes_S + 16.0 * L.sumG, 2.0 * (double)L.sGG);
-    gemv_t_kernel<<<dim3(nblocks((int64_t)L.max_nG * 64), L.nsub), TPB, 0, st>>>(
-        d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_nG.as<int>(), vG,
-        d_offG.as<int64_t>(), vG2, d_offG.as<int64_t>(), 1.0, 0.0);
+    // lower triangle of each S_s, the partial sums for its upper triangle
+    // written and read once, x read per panel and y written
+    const double by = bytes_S_sym + 2.0 * 8.0 * symv_parts + 16.0 * L.sumG;
+    timer.begin(st, "schur_symv", by, 2.0 * (double)L.sGG);
+    {
+      LaunchScope ls(st, "symv_kernel", bytes_S_sym + 8.0 * symv_parts + 16.0 * L.sumG, 2.0 * (double)L.sGG);
+      symv_panel_kernel<<<dim3((L.max_nG + 63) / 64, L.nsub), SYMV_NT, 0, st>>>(
+          d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), vG, d_offG.as<int64_t>(), vG2,
+          d_symv_part.as<double>(), d_symv_off.as<int64_t>());
+    }
+    {
+      LaunchScope ls(st, "symv_reduce_kernel", 8.0 * symv_parts + 16.0 * L.sumG, (double)symv_parts);
+      symv_reduce_kernel<<<dim3(nblocks(L.max_nG), L.nsub), TPB, 0, st>>>(
+          d_nG.as<int>(), d_offG.as<int64_t>(), vG2, d_symv_part.as<double>(), d_symv_off.as<int64_t>());
+    }
     timer.end(st);
   }
   reduce_copies_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(vG2, L.sumG, d_gamma_ptr.as<int>(),
@@ -1581,9 +1677,9 @@ double Solver::apply_bytes() const {
 }
 
 double Solver::iter_bytes() const {
-  double b = apply_bytes();
-  for (int s = 0; s < L.nsub; ++s) b += 8.0 * (double)L.nG[s] * L.nG[s];
-  return b;
+  // the Schur operator reads the lower triangles (diagonal blocks whole) and
+  // writes and reads its partial sums once
+  return apply_bytes() + bytes_S_sym + 16.0 * symv_parts;
 }
 
 // extreme eigenvalues of the CG-Lanczos tridiagonal matrix by Sturm
