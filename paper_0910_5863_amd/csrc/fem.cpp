@@ -87,22 +87,6 @@ void element_matrix(const MeshIn &m, int64_t e, double *K) {
   }
 }
 
-template <class F>
-static void parallel_for(int n, F f) {
-  int nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
-  nt = std::min(nt, n);
-  if (nt <= 1) {
-    for (int i = 0; i < n; ++i) f(i);
-    return;
-  }
-  std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t)
-    th.emplace_back([&, t]() {
-      for (int i = t; i < n; i += nt) f(i);
-    });
-  for (auto &x : th) x.join();
-}
-
 // Builds, for every substructure: local dof numbering (interior first, then
 // interface, each ascending in global order), the CSR matrix A_i and diag.
 // Requires P.full2glob and the node multiplicities (computed here).

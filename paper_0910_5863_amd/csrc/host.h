@@ -3,8 +3,11 @@
 // bddc_setup (and again after bddc_adapt for the constraints).
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
+#include <exception>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace bddc {
@@ -95,6 +98,31 @@ void assemble_substructures(Problem &P);
 // globs, corners, weights (interface.cpp)
 void classify_interface(Problem &P, bool augment);
 void compute_weights(Problem &P);
+
+// f(i) for i in [0, n) on up to 16 host threads (i = t, t + nt, ...); the
+// first exception a thread throws is rethrown after all have joined
+template <class F>
+void parallel_for(int n, F f) {
+  int nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+  nt = std::min(nt, n);
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::exception_ptr> err(nt);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t]() {
+      try {
+        for (int i = t; i < n; i += nt) f(i);
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+    });
+  for (auto &x : th) x.join();
+  for (auto &e : err)
+    if (e) std::rethrow_exception(e);
+}
 
 // change of variables (qrcp.cpp)
 GlobCov qr_change_of_variables(const std::vector<double> &H, int m, int n, double drop_tol);

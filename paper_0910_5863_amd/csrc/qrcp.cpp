@@ -95,7 +95,8 @@ void build_constraints(Problem &P) {
     P.extra_rows.assign(P.globs.size(), {});
     P.extra_k.assign(P.globs.size(), 0);
   }
-  for (size_t gi = 0; gi < P.globs.size(); ++gi) {
+  // globs are independent: one QR-CP each, on the host threads
+  parallel_for((int)P.globs.size(), [&](int gi) {
     const Glob &g = P.globs[gi];
     const int n = (int)g.dofs.size();
     std::vector<double> H;
@@ -122,7 +123,7 @@ void build_constraints(Problem &P) {
       m += P.extra_k[gi];
     }
     P.cov[gi] = qr_change_of_variables(H, m, n, P.drop_tol);
-  }
+  });
 }
 
 int64_t count_nc(const Problem &P) {

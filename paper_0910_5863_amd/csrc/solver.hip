@@ -132,12 +132,20 @@ __global__ void xform_cols_kernel(double *pool, const int64_t *offGG, const int 
   if (row >= ng) return;
   double *S = pool + offGG[s];
   const int base = (int)offG[s];
-  for (int t = 0; t < x.ng; ++t) {
-    const int q = pos[x.pos_off + t] - base;
-    double acc = 0;
-    for (int k = 0; k < x.m; ++k)
-      acc += wmat[x.trow_off + (int64_t)k * x.ng + t] * scr[x.scrS_off + (int64_t)k * ng + row];
-    S[row + (int64_t)q * ng] += acc;
+  // eight glob columns at a time: each pivot value is loaded once for all
+  // eight (every sum still runs over k in order)
+  for (int t0 = 0; t0 < x.ng; t0 += 8) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < x.m; ++k) {
+      const double sv = scr[x.scrS_off + (int64_t)k * ng + row];
+      const double *w = wmat + x.trow_off + (int64_t)k * x.ng + t0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (t0 + j < x.ng) acc[j] += w[j] * sv;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (t0 + j < x.ng) S[row + (int64_t)(pos[x.pos_off + t0 + j] - base) * ng] += acc[j];
   }
 }
 
@@ -151,14 +159,23 @@ __global__ void xform_rows_kernel(double *pool, const int64_t *offGG, const int 
   const int lane = threadIdx.x & 63;
   const int col0 = (blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 16;
   const int base = (int)offG[s];
-  for (int col = col0; col < min(ng, col0 + 16); ++col) {
-    double *S = pool + offGG[s] + (int64_t)col * ng;
+  const int col1 = min(ng, col0 + 16);
+  // four columns at a time: each weight is loaded once for all four (every
+  // sum still runs over k in order)
+  for (int c0 = col0; c0 < col1; c0 += 4) {
     for (int t = lane; t < x.ng; t += 64) {
+      double acc[4] = {0, 0, 0, 0};
+      for (int k = 0; k < x.m; ++k) {
+        const double w = wmat[x.trow_off + (int64_t)k * x.ng + t];
+        const double *sv = scr + x.scrS_off + (int64_t)k * ng + c0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (c0 + j < col1) acc[j] += w * sv[j];
+      }
       const int q = pos[x.pos_off + t] - base;
-      double acc = 0;
-      for (int k = 0; k < x.m; ++k)
-        acc += wmat[x.trow_off + (int64_t)k * x.ng + t] * scr[x.scrS_off + (int64_t)k * ng + col];
-      S[q] += acc;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (c0 + j < col1) pool[offGG[s] + (int64_t)(c0 + j) * ng + q] += acc[j];
     }
   }
 }
