@@ -230,6 +230,35 @@ __device__ __forceinline__ void tile_mul(const double *U, int d, int r0, int nk,
   }
 }
 
+// Four row tiles at once (rows r0[t]..r0[t]+15, t < nt), sharing the C0
+// operand: acc[t] += U[r0[t]:+16, 0:nk] C0[0:nk, 0:16].  The four tiles'
+// loads of one K-step are independent, so four times as many loads of U are
+// in flight as with one tile at a time (the product is bound by their
+// latency).
+__device__ __forceinline__ void tile_mul4(const double *U, int d, const int (&r0)[4], int nt, int nk,
+                                          const double *C0, int n0, int ldc, v4d (&acc)[4]) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+  const double *u[4];
+  bool rv[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    rv[t] = t < nt && r0[t] + i < d;
+    u[t] = U + (rv[t] ? r0[t] + i : 0);
+  }
+#pragma unroll 4
+  for (int k = 0; k < nk; k += 4) {
+    const int kk = k + kq;
+    const bool kv = kk < nk;
+    double a[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] = (rv[t] && kv) ? u[t][(int64_t)kk * d] : 0.0;
+    const double b0 = (kv && i < n0) ? C0[kk * ldc + i] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < nt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b0, acc[t], 0, 0, 0);
+  }
+}
+
 // Out[r0 + row, col] = acc (or -= acc when SUB) for the rows < d and columns
 // < ncol of the tile (Out column-major, ld d)
 template <bool SUB>
@@ -629,7 +658,7 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
     const int d = opaque(d_);
     const int nrt = (d + 15) >> 4;
     for (int tg = 0; tg < nrt; tg += 4 * LOB_NWAVE) {
-      v4d acc[4] = {zero4, zero4, zero4, zero4}, unused = zero4;
+      v4d acc[4] = {zero4, zero4, zero4, zero4};
       for (int c0 = 0; c0 < d; c0 += STAGE_ROWS) {
         const int cn = min(STAGE_ROWS, d - c0);
         __syncthreads();
@@ -638,13 +667,14 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
           stage[c * LOB_S + q] = q < nv ? Vin[c0 + c + (int64_t)q * d] : 0.0;
         }
         __syncthreads();
+        int r0[4], nt = 0;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int tile = tg + wave + LOB_NWAVE * t;
-          if (tile < nrt)
-            tile_mul<false>(A + (int64_t)c0 * d, d, 16 * tile, cn, stage, nv, nullptr, 0, LOB_S,
-                            acc[t], unused);
+          r0[t] = 16 * tile;
+          if (tile < nrt) nt = t + 1;
         }
+        if (nt > 0) tile_mul4(A + (int64_t)c0 * d, d, r0, nt, cn, stage, nv, LOB_S, acc);
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
