@@ -205,38 +205,18 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 
 // Row tiles of tall-skinny products on the matrix cores (v_mfma_f64_16x16x4f64:
 // lane l holds A[l%16][l/16] and B[l/16][l%16]; entry j of its result is row
-// l/16 + 4j, column l%16).  For rows r0..r0+15 of U (global, column-major,
-// ld d): acc0 += U[r0:r0+16, 0:nk] C0[0:nk, 0:16] and, when TWO, acc1 likewise
-// with C1; C0, C1 in LDS with rows ldc apart, columns from n0 (n1) on read as
-// zero, rows of U past d read as zero.
+// l/16 + 4j, column l%16).  U is global, column-major, ld d; C0, C1 in LDS
+// with rows ldc apart, columns from n0 (n1) on read as zero, rows of U past d
+// read as zero.
+// Up to four row tiles at once (rows r0[t]..r0[t]+15, t < nt), sharing the
+// C operands: acc0[t] += U[r0[t]:+16, 0:nk] C0[0:nk, 0:16] and, when TWO,
+// acc1[t] likewise with C1.  The tiles' loads of one K-step are independent,
+// so four times as many loads of U are in flight as with one tile at a time
+// (these products are bound by their latency).
 template <bool TWO>
-__device__ __forceinline__ void tile_mul(const double *U, int d, int r0, int nk, const double *C0,
-                                         int n0, const double *C1, int n1, int ldc, v4d &acc0,
-                                         v4d &acc1) {
-  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
-  const bool rv = r0 + i < d;
-  const double *u = U + r0 + i;
-#pragma unroll 4
-  for (int k = 0; k < nk; k += 4) {
-    const int kk = k + kq;
-    const bool kv = kk < nk;
-    const double a = (rv && kv) ? u[(int64_t)kk * d] : 0.0;
-    const double b0 = (kv && i < n0) ? C0[kk * ldc + i] : 0.0;
-    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-    if (TWO) {
-      const double b1 = (kv && i < n1) ? C1[kk * ldc + i] : 0.0;
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
-    }
-  }
-}
-
-// Four row tiles at once (rows r0[t]..r0[t]+15, t < nt), sharing the C0
-// operand: acc[t] += U[r0[t]:+16, 0:nk] C0[0:nk, 0:16].  The four tiles'
-// loads of one K-step are independent, so four times as many loads of U are
-// in flight as with one tile at a time (the product is bound by their
-// latency).
 __device__ __forceinline__ void tile_mul4(const double *U, int d, const int (&r0)[4], int nt, int nk,
-                                          const double *C0, int n0, int ldc, v4d (&acc)[4]) {
+                                          const double *C0, int n0, const double *C1, int n1,
+                                          int ldc, v4d (&acc0)[4], v4d (&acc1)[4]) {
   const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
   const double *u[4];
   bool rv[4];
@@ -255,8 +235,27 @@ __device__ __forceinline__ void tile_mul4(const double *U, int d, const int (&r0
     const double b0 = (kv && i < n0) ? C0[kk * ldc + i] : 0.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
-      if (t < nt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b0, acc[t], 0, 0, 0);
+      if (t < nt) acc0[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b0, acc0[t], 0, 0, 0);
+    if (TWO) {
+      const double b1 = (kv && i < n1) ? C1[kk * ldc + i] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nt) acc1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b1, acc1[t], 0, 0, 0);
+    }
   }
+}
+
+// the row tiles a wave takes in group g of a d-row block: 16 (wave + NWAVE
+// (4 g + t)), t < 4; returns how many exist
+__device__ __forceinline__ int wave_tiles(int d, int g, int (&r0)[4]) {
+  const int wave = threadIdx.x >> 6;
+  int nt = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    r0[t] = 16 * (wave + LOB_NWAVE * (4 * g + t));
+    if (r0[t] < d) nt = t + 1;
+  }
+  return nt;
 }
 
 // Out[r0 + row, col] = acc (or -= acc when SUB) for the rows < d and columns
@@ -534,10 +533,14 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
   // per 16-row tile
   auto sub_prod = [&](double *V, int nv, const double *U, int nu, const double *c, int ldc) {
     const int d = opaque(d_);
-    for (int r0 = 16 * wave; r0 < d; r0 += 16 * LOB_NWAVE) {
-      v4d acc = zero4, unused = zero4;
-      tile_mul<false>(U, d, r0, nu, c, nv, nullptr, 0, ldc, acc, unused);
-      tile_store<true>(V, d, r0, nv, acc);
+    for (int g = 0; 16 * LOB_NWAVE * 4 * g < d; ++g) {
+      int r0[4];
+      const int nt = wave_tiles(d, g, r0);
+      v4d acc[4] = {zero4, zero4, zero4, zero4}, unused[4];
+      if (nt > 0) tile_mul4<false>(U, d, r0, nt, nu, c, nv, nullptr, 0, ldc, acc, unused);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nt) tile_store<true>(V, d, r0[t], nv, acc[t]);
     }
     __syncthreads();
   };
@@ -545,10 +548,14 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
   // rows before writing them
   auto right_mul = [&](double *V, int nv, int kp) {
     const int d = opaque(d_);
-    for (int r0 = 16 * wave; r0 < d; r0 += 16 * LOB_NWAVE) {
-      v4d acc = zero4, unused = zero4;
-      tile_mul<false>(V, d, r0, nv, &Ms[0][0], kp, nullptr, 0, LOB_S, acc, unused);
-      tile_store<false>(V, d, r0, kp, acc);
+    for (int g = 0; 16 * LOB_NWAVE * 4 * g < d; ++g) {
+      int r0[4];
+      const int nt = wave_tiles(d, g, r0);
+      v4d acc[4] = {zero4, zero4, zero4, zero4}, unused[4];
+      if (nt > 0) tile_mul4<false>(V, d, r0, nt, nv, &Ms[0][0], kp, nullptr, 0, LOB_S, acc, unused);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nt) tile_store<false>(V, d, r0[t], kp, acc[t]);
     }
     __syncthreads();
   };
@@ -674,7 +681,8 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
           r0[t] = 16 * tile;
           if (tile < nrt) nt = t + 1;
         }
-        if (nt > 0) tile_mul4(A + (int64_t)c0 * d, d, r0, nt, cn, stage, nv, LOB_S, acc);
+        v4d unused[4];
+        if (nt > 0) tile_mul4<false>(A + (int64_t)c0 * d, d, r0, nt, cn, stage, nv, nullptr, 0, LOB_S, acc, unused);
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -769,11 +777,17 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
     const int d = opaque(d_);
     for (int pass = 0; pass < 2; ++pass) {
       double *B = pass ? AV : V;
-      for (int r0 = 16 * wave; r0 < d; r0 += 16 * LOB_NWAVE) {
-        v4d ax = zero4, ap = zero4;
-        tile_mul<true>(B, d, r0, n, &Cs[0][0], s, &Cs[0][LOB_S], kp, 2 * LOB_S, ax, ap);
-        tile_store<false>(B, d, r0, s, ax);
-        tile_store<false>(B + (int64_t)s * d, d, r0, kp, ap);
+      for (int g = 0; 16 * LOB_NWAVE * 4 * g < d; ++g) {
+        int r0[4];
+        const int nt = wave_tiles(d, g, r0);
+        v4d ax[4] = {zero4, zero4, zero4, zero4}, ap[4] = {zero4, zero4, zero4, zero4};
+        if (nt > 0) tile_mul4<true>(B, d, r0, nt, n, &Cs[0][0], s, &Cs[0][LOB_S], kp, 2 * LOB_S, ax, ap);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < nt) {
+            tile_store<false>(B, d, r0[t], s, ax[t]);
+            tile_store<false>(B + (int64_t)s * d, d, r0[t], kp, ap[t]);
+          }
       }
     }
     __syncthreads();
