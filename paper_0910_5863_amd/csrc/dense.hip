@@ -303,36 +303,39 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(T *pool, const MatDesc *
     D[r][c] = (r < w && c < w && r >= c) ? A[(kb + r) + (kb + c) * lda] : T(0);
   }
   __syncthreads();
+  // right-looking, one barrier per column: column c of L goes to Y (wave 0)
+  // while the trailing matrix in D is updated with the unscaled column,
+  // a_rs -= a_rc a_sc / a_cc, so no entry read in a step is written in it
+  // (reads: column c of D; writes: Y's column c, D's columns > c)
   for (int c = 0; c < w; ++c) {
     T piv = D[c][c];
     if (!(piv > T(0))) {
       if (tid == 0 && s_fail == 0) s_fail = kb + c + 1;
       piv = T(1);
     }
-    const T lcc = sqrt(piv);
-    __syncthreads();
-    if (tid == 0) D[c][c] = lcc;
-    for (int r = c + 1 + tid; r < w; r += 256) D[r][c] /= lcc;
-    __syncthreads();
-    // trailing update: lane = row r, the four waves take every fourth column
     const int r = tid & 63;
+    if (tid < 64 && r >= c && r < w) {
+      const T lcc = sqrt(piv);
+      Y[r][c] = r == c ? lcc : D[r][c] / lcc;
+    }
+    // trailing update: lane = row r, the four waves take every fourth column
     if (r > c && r < w) {
-      const T lrc = D[r][c];
-      for (int s = c + 1 + (tid >> 6); s <= r; s += 4) D[r][s] -= lrc * D[s][c];
+      const T a = D[r][c] / piv;
+      for (int s = c + 1 + (tid >> 6); s <= r; s += 4) D[r][s] -= a * D[s][c];
     }
     __syncthreads();
   }
   for (int i = tid; i < w * w; i += 256) {
     const int r = i % w, c = i / w;
-    if (r >= c) A[(kb + r) + (kb + c) * lda] = D[r][c];
+    if (r >= c) A[(kb + r) + (kb + c) * lda] = Y[r][c];
   }
   if (tid == 0 && s_fail && status) atomicCAS(&status[e], 0, s_fail);
   // inverse of the factored block: lane j of wave 0 forms column j of L^-1 in
   // registers by forward substitution against the rows of L broadcast from
-  // LDS (D holds the factor; outside the w x w block it is the identity)
+  // LDS (D receives the factor, and the identity outside the w x w block)
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i % NB, c = i / NB;
-    if (r >= w || c >= w) D[r][c] = (r == c) ? T(1) : T(0);
+    D[r][c] = (r < w && c < w) ? (r >= c ? Y[r][c] : T(0)) : (r == c ? T(1) : T(0));
   }
   __syncthreads();
   if (tid < 64) {
