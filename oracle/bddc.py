@@ -10,7 +10,7 @@ Algorithm 2:   A~ wbar_c = Pibar R^cT T^T E^T r,
 (I - P) is the discrete harmonic extension: interior values are replaced by
 -A_II^{-1} A_IG u_G in each substructure (Sec. 2).  t is the largest diagonal
 entry of R^cT T^T A T R^c (Sec. 4 suggests the largest diagonal entry of A^c;
-reading stated in the design doc); the result does not depend on it.
+the paper does not fix it further); the result does not depend on it.
 """
 from __future__ import annotations
 

@@ -6,7 +6,7 @@ factored by QR with column pivoting, H^avg = Q [U V] K, and the inverse change
 of variables is T = K^{-1} [U^{-1}  -U^{-1} V; 0  I]  (eq. (T)).  Rows whose
 diagonal entry of U is negligible are dropped (Sec. 5, after eq. (T)).
 
-Reading (stated in the design doc): the QR is LAPACK's DGEQP3 through SciPy, as in
+Reading (the paper leaves the details open): the QR is LAPACK's DGEQP3 through SciPy, as in
 the paper; rows with |U_kk| <= 1e-10 |U_11| are dropped.  Position
 convention: the k-th new (explicit) variable of glob g is stored at the local
 position of the dof K selects k-th; the other new variables are the unchanged

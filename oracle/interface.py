@@ -5,7 +5,7 @@ the set of substructures that contain them: a class shared by exactly two
 substructures is a face; a class shared by more than two is an edge, and an
 edge with a single node is a corner (Sec. 2, definition of globs).
 
-Readings where the paper is silent (stated in the design doc):
+Readings where the paper is silent:
 * corners also include the nodes of >2-substructure classes that lie on the
   domain boundary (this reproduces the 7 corners / 6 edges / 12 faces of the
   2x2x2 cube in the sparsity figure), and, for irregular partitions, face nodes

@@ -7,7 +7,9 @@ so every residual vanishes in the interiors and (I - P)^T can be omitted.
 Stopping: ||r_k||_2 <= rtol ||r_0||_2 with rtol = 1e-8 (Sec. 7: relative
 residual tolerance 10^-8).  The condition number is estimated from the
 Lanczos tridiagonal matrix built from the CG coefficients (Sec. 7, captions of
-the result tables); reading of its entries stated in the design doc.
+the result tables): diagonal 1/a_j + b_{j-1}/a_{j-1}, off-diagonal
+sqrt(b_j)/a_j (the standard CG-Lanczos relation; the paper does not print
+it).
 """
 from __future__ import annotations
 
