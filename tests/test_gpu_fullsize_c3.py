@@ -13,7 +13,12 @@ properties that hold at any size:
 - every pair eigenproblem converged, omega < tau, lambda_min >= 1 (Sec. 2);
 - two FP64 solves give the same bits;
 - the FP32 solve satisfies the same residual bound and differs from the
-  FP64 solution by less than 1e-7 relative.
+  FP64 solution by less than 1e-7 relative;
+- with the adaptive edge rows kept (Sec. 3 after Proposition 1), the same
+  residual bound, more constraints than with face rows alone, and a
+  condition number within the soft bound 1.5 tau (the indicator bounds the
+  pair problems; for more than two substructures it is a heuristic for the
+  global kappa).
 
 Residual bound.  PCG stops at ||r_k|| <= 1e-8 ||r_0|| on its recursive
 residual of the interface problem, whose operator is the sum of FP64 Schur
@@ -44,9 +49,9 @@ def _run():
     p = meshgen.elasticity_kmeans_64()
     f = torch.from_numpy(p.f).to("cuda:0")
     out = {"p": p}
-    for prec in (64, 32):
-        b = BDDC(factor_precision=prec)
-        b.setup(p, "ce")
+    for prec in (64, 32, "edges"):
+        b = BDDC(factor_precision=64 if prec == "edges" else prec)
+        b.setup(p, "ce", adaptive_edges=prec == "edges")
         info0 = b.info()
         ai = b.adapt(TAU)
         b.factor()
@@ -89,7 +94,7 @@ def test_c3_structure():
     assert i.n_glob == st["p"].n_glob == 811200
 
 
-@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("prec", [64, 32, "edges"])
 def test_c3_solution(prec):
     st = _oracle()
     r = np.linalg.norm(st["p"].f - st["K"] @ st[prec]["u"])
@@ -101,6 +106,9 @@ def test_c3_solution(prec):
     assert pi.converged and pi.lmin > 1 - 1e-6
     if prec == 64:
         assert np.array_equal(st[64]["u"], st[64]["u2"])
-    else:
+    elif prec == 32:
         u64 = st[64]["u"]
         assert np.linalg.norm(st[32]["u"] - u64) <= 1e-7 * np.linalg.norm(u64)
+    else:
+        assert ai.nc > st[64]["ai"].nc and ai.n_added_edge > 0
+        assert pi.kappa < 1.5 * TAU
