@@ -77,6 +77,14 @@ struct DenseOps {
   static hipError_t gemm(hipStream_t st, const T *A, const T *B, T *C, const GemmDesc *d_desc,
                          int batch, int maxM, int maxN, bool transA, bool transB, T alpha,
                          T beta, bool lower, const GemmDesc *h_desc = nullptr);
+  // C[map(i), j] += (A B^T)[i, j] (map_rows) or C[i, map(j)] += (A B^T)[i, j]
+  // for every entry (op(A) = A, op(B) = B^T), where map(x) =
+  // map[map_off[e] + x]: a product added into scattered rows or columns of C
+  // (every mapped row or column distinct within an entry).
+  static hipError_t gemm_scatter(hipStream_t st, const T *A, const T *B, T *C,
+                                 const GemmDesc *d_desc, const int *map, const int64_t *map_off,
+                                 bool map_rows, int batch, int maxM, int maxN,
+                                 const GemmDesc *h_desc = nullptr);
   // In-place lower Cholesky of every entry's A (n x n).  status[e] is set to
   // (column+1) of the first non-positive pivot (left untouched if none).  The
   // inverses of the NB x NB diagonal blocks of L are written to dinv: block

@@ -86,9 +86,12 @@ __device__ __forceinline__ bool xcd_remap(int nwg, int tiles_per_entry, int batc
 // TAG tells the callers apart: each kernel uses instantiations of its own, so
 // that no LDS array is reached from two kernels (such an array is addressed
 // through a per-kernel lookup table, which costs registers).
+// rmap / cmap (optional): C's row i is row rmap[i] of the storage, column j
+// is column cmap[j].
 template <class T, bool TA, bool TB, int MT, int NT, int KS = 1, int TAG = 0>
 __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int lda, int ldb,
-                          int ldc, T alpha, T beta, int m0, int n0) {
+                          int ldc, T alpha, T beta, int m0, int n0, const int *rmap = nullptr,
+                          const int *cmap = nullptr) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int TM = 32 * MT, TN = 32 * NT;
   constexpr int LA = TM * BK / 256, LB = TN * BK / 256;
@@ -213,7 +216,7 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
         const int i = lane + 64 * it, r = i % (16 * MT), c = i / (16 * MT);
         const int row = r0 + r, col = c0 + c;
         if (row < M && col < N) {
-          T *cp = &C[row + (int64_t)col * ldc];
+          T *cp = &C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc];
           const T v = stg[r + c * SR];
           *cp = (beta == T(0)) ? v : v + beta * (*cp);
         }
@@ -231,7 +234,7 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
           const int row = m0 + wr * 16 * MT + 16 * x + Mfma<T>::row(lane, j);
           const int col = n0 + wc * 16 * NT + 16 * y + (lane & 15);
           if (row < M && col < N) {
-            T *c = &C[row + (int64_t)col * ldc];
+            T *c = &C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc];
             const T v = alpha * acc[x][y][j];
             *c = (beta == T(0)) ? v : v + beta * (*c);
           }
@@ -253,6 +256,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T *A, const T *B, T *C,
   if (lower && m0 + TM - 1 < n0) return;
   gemm_tile<T, TA, TB, MT, NT, 1, 0>(A + d.a_off, B + d.b_off, C + d.c_off, d.M, d.N, d.K, d.lda,
                                      d.ldb, d.ldc, alpha, beta, m0, n0);
+}
+
+// C[map rows or columns] += A B^T per entry (TAG 5: instantiations of its own)
+template <class T, int MT, int NT>
+__global__ __launch_bounds__(256) void gemm_scatter_kernel(const T *A, const T *B, T *C,
+                                                           const GemmDesc *desc, const int *map,
+                                                           const int64_t *map_off, int map_rows,
+                                                           int tm, int tn, int batch) {
+  constexpr int TM = 32 * MT, TN = 32 * NT;
+  int e, t;
+  if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
+  const GemmDesc d = desc[e];
+  const int ti = t % tm, tj = t / tm;
+  const int m0 = ti * TM, n0 = tj * TN;
+  if (m0 >= d.M || n0 >= d.N) return;
+  const int *mp = map + map_off[e];
+  gemm_tile<T, false, true, MT, NT, 1, 5>(A + d.a_off, B + d.b_off, C + d.c_off, d.M, d.N, d.K, d.lda,
+                                          d.ldb, d.ldc, T(1), T(1), m0, n0, map_rows ? mp : nullptr,
+                                          map_rows ? nullptr : mp);
 }
 
 // --- Cholesky -------------------------------------------------------------
@@ -883,6 +905,26 @@ hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const
     }
   }
   launch(shape);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t DenseOps<T>::gemm_scatter(hipStream_t st, const T *A, const T *B, T *C,
+                                     const GemmDesc *d_desc, const int *map, const int64_t *map_off,
+                                     bool map_rows, int batch, int maxM, int maxN,
+                                     const GemmDesc *h_desc) {
+  if (batch <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
+  double fl = 0, by = 0;
+  if (launch_timing() && h_desc)
+    for (int e = 0; e < batch; ++e) {
+      const GemmDesc &q = h_desc[e];
+      fl += 2.0 * q.M * q.N * q.K;
+      by += sizeof(T) * ((double)q.M * q.K + (double)q.K * q.N + 2.0 * q.M * q.N) + 4.0 * (map_rows ? q.M : q.N);
+    }
+  LaunchScope ls(st, "gemm_scatter_kernel", by, fl);
+  const int tm = (maxM + 63) / 64, tn = (maxN + 63) / 64;
+  gemm_scatter_kernel<T, 2, 2><<<grid_round(batch * tm * tn), 256, 0, st>>>(
+      A, B, C, d_desc, map, map_off, map_rows ? 1 : 0, tm, tn, batch);
   return hipGetLastError();
 }
 

@@ -165,6 +165,11 @@ class Solver {
       d_descCvec;
   DBuf d_gx, d_gx_ptr, d_trow, d_pos, d_wmat, d_gk_glob, d_gk_k, d_scr;
   int64_t scrS_elems = 0;
+  // the two passes of T^T S T as scatter products: descriptors (column
+  // pass, row pass), local glob positions and their offsets per record
+  DBuf d_xf_cols, d_xf_rows, d_xf_map, d_xf_map_off;
+  std::vector<GemmDesc> h_xf_cols, h_xf_rows;
+  int xf_max_ng = 0;
   int n_gk = 0;
   DBuf d_ridx, d_ridx_off, d_pidx, d_pidx_off, d_rabs, d_pabs, d_pcid, d_sub_cids;
   DBuf d_c_ptr, d_c_sub, d_c_loc, d_c_copies;

@@ -120,66 +120,6 @@ __global__ void xform_copy_pivots_kernel(const double *pool, const int64_t *offG
   }
 }
 
-// S[:, glob dofs] += (pivot columns) W for one (substructure, glob) per
-// blockIdx.y: the globs of a substructure own disjoint columns, so they run
-// side by side; a thread per row
-__global__ void xform_cols_kernel(double *pool, const int64_t *offGG, const int *nG,
-                                  const GlobXf *gx, const double *wmat, const int *pos,
-                                  const int64_t *offG, const double *scr) {
-  const GlobXf x = gx[blockIdx.y];
-  const int s = x.sub, ng = nG[s];
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= ng) return;
-  double *S = pool + offGG[s];
-  const int base = (int)offG[s];
-  // eight glob columns at a time: each pivot value is loaded once for all
-  // eight (every sum still runs over k in order)
-  for (int t0 = 0; t0 < x.ng; t0 += 8) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < x.m; ++k) {
-      const double sv = scr[x.scrS_off + (int64_t)k * ng + row];
-      const double *w = wmat + x.trow_off + (int64_t)k * x.ng + t0;
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (t0 + j < x.ng) acc[j] += w[j] * sv;
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (t0 + j < x.ng) S[row + (int64_t)(pos[x.pos_off + t0 + j] - base) * ng] += acc[j];
-  }
-}
-
-// S[glob dofs, :] += W^T (pivot rows), one (substructure, glob) per
-// blockIdx.y (disjoint rows); a wave per column, 16 columns per wave
-__global__ void xform_rows_kernel(double *pool, const int64_t *offGG, const int *nG,
-                                  const GlobXf *gx, const double *wmat, const int *pos,
-                                  const int64_t *offG, const double *scr) {
-  const GlobXf x = gx[blockIdx.y];
-  const int s = x.sub, ng = nG[s];
-  const int lane = threadIdx.x & 63;
-  const int col0 = (blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 16;
-  const int base = (int)offG[s];
-  const int col1 = min(ng, col0 + 16);
-  // four columns at a time: each weight is loaded once for all four (every
-  // sum still runs over k in order)
-  for (int c0 = col0; c0 < col1; c0 += 4) {
-    for (int t = lane; t < x.ng; t += 64) {
-      double acc[4] = {0, 0, 0, 0};
-      for (int k = 0; k < x.m; ++k) {
-        const double w = wmat[x.trow_off + (int64_t)k * x.ng + t];
-        const double *sv = scr + x.scrS_off + (int64_t)k * ng + c0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (c0 + j < col1) acc[j] += w * sv[j];
-      }
-      const int q = pos[x.pos_off + t] - base;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (c0 + j < col1) pool[offGG[s] + (int64_t)(c0 + j) * ng + q] += acc[j];
-    }
-  }
-}
-
 // gather a sub-block: dst[a + b*ldd] = src[idx_r[a] + idx_c[b]*lds] per entry
 __global__ void gather_block_kernel(const double *src, const int64_t *src_off, const int *lds,
                                     double *dst, const int64_t *dst_off, const int *ldd,
@@ -704,7 +644,8 @@ std::vector<DBuf *> Solver::cons_buffers() {
   return {&d_nr, &d_np, &d_offR, &d_offP, &d_offRR, &d_offRP, &d_offPP, &d_Lrr, &d_Urr, &d_Phi,
           &d_Spi, &d_Lc, &d_Uc, &d_descRRT, &d_dinv_rr, &d_dinv_rr_off, &d_dinv_c, &d_dinv_c_off,
           &d_descRR, &d_descC, &d_spi_desc, &d_gx, &d_gx_ptr, &d_trow, &d_pos, &d_wmat,
-          &d_gk_glob, &d_gk_k, &d_scr, &d_ridx, &d_ridx_off, &d_pidx, &d_pidx_off, &d_rabs,
+          &d_gk_glob, &d_gk_k, &d_scr, &d_xf_cols, &d_xf_rows, &d_xf_map, &d_xf_map_off,
+          &d_ridx, &d_ridx_off, &d_pidx, &d_pidx_off, &d_rabs,
           &d_pabs, &d_pcid, &d_sub_cids, &d_c_ptr, &d_c_sub, &d_c_loc, &d_c_copies,
           &d_trsv_rr_fwd, &d_trsv_rr_bwd, &d_trsv_rr_off, &d_trsv_c_fwd, &d_trsv_c_bwd,
           &d_trsv_c_off, &d_work_i, &d_status, &d_vR, &d_vR2, &d_vP, &d_vc, &d_descRRvec,
@@ -853,6 +794,27 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_gk_k = upload(alloc, st, gk_k);
   d_scr = alloc0(alloc, st, sizeof(double) * (size_t)std::max<int64_t>(scr, 1));
   scrS_elems = scrS;
+  {
+    // T^T S T: the column pass adds (pivot columns, n_G x m) (W, m x ng) into
+    // the glob's columns, the row pass W^T (pivot rows, m x n_G) into its rows
+    h_xf_cols.clear();
+    h_xf_rows.clear();
+    std::vector<int> xmap;
+    std::vector<int64_t> xmap_off;
+    xf_max_ng = 0;
+    for (const GlobXf &x : gx) {
+      const int n = L.nG[x.sub];
+      xmap_off.push_back((int64_t)xmap.size());
+      for (int t = 0; t < x.ng; ++t) xmap.push_back(pos[x.pos_off + t] - (int)L.offG[x.sub]);
+      h_xf_cols.push_back(GemmDesc{x.scrS_off, x.trow_off, L.offGG[x.sub], n, x.ng, x.m, n, x.ng, n});
+      h_xf_rows.push_back(GemmDesc{x.trow_off, x.scrS_off, L.offGG[x.sub], x.ng, n, x.m, x.ng, n, n});
+      xf_max_ng = std::max(xf_max_ng, x.ng);
+    }
+    d_xf_cols = upload(alloc, st, h_xf_cols);
+    d_xf_rows = upload(alloc, st, h_xf_rows);
+    d_xf_map = upload(alloc, st, xmap);
+    d_xf_map_off = upload(alloc, st, xmap_off);
+  }
   // r / pi index maps (local interface positions and absolute positions)
   std::vector<int> ridx, pidx, rabs, pabs, pcid, sub_cids;
   std::vector<int64_t> ridx_off(ns), pidx_off(ns);
@@ -1171,14 +1133,15 @@ void Solver::factor() {
           d_pos.as<int>(), d_offG.as<int64_t>(), scrS.as<double>(), rows);
       HIPCHK(hipGetLastError());
       if (!rows)
-        xform_cols_kernel<<<dim3(nblocks(L.max_nG), n_gx), TPB, 0, st>>>(
-            d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_gx.as<GlobXf>(),
-            d_wmat.as<double>(), d_pos.as<int>(), d_offG.as<int64_t>(), scrS.as<double>());
+        HIPCHK(DenseOps<double>::gemm_scatter(st, scrS.as<double>(), d_wmat.as<double>(),
+                                              d_W.as<double>(), d_xf_cols.as<GemmDesc>(),
+                                              d_xf_map.as<int>(), d_xf_map_off.as<int64_t>(), false,
+                                              n_gx, L.max_nG, xf_max_ng, h_xf_cols.data()));
       else
-        xform_rows_kernel<<<dim3(nblocks((L.max_nG + 15) / 16, 4), n_gx), TPB, 0, st>>>(
-            d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), d_gx.as<GlobXf>(),
-            d_wmat.as<double>(), d_pos.as<int>(), d_offG.as<int64_t>(), scrS.as<double>());
-      HIPCHK(hipGetLastError());
+        HIPCHK(DenseOps<double>::gemm_scatter(st, d_wmat.as<double>(), scrS.as<double>(),
+                                              d_W.as<double>(), d_xf_rows.as<GemmDesc>(),
+                                              d_xf_map.as<int>(), d_xf_map_off.as<int64_t>(), true,
+                                              n_gx, xf_max_ng, L.max_nG, h_xf_rows.data()));
     }
     HIPCHK(hipStreamSynchronize(st));
     release(scrS);
