@@ -125,18 +125,39 @@ __global__ void transpose_kernel(const double *src, double *dst, const int64_t *
   dst[off[e] + c + (int64_t)r * m] = src[off[e] + i];
 }
 
-// A <- (A + A^T) / 2 in place (entries a >= b of every entry touch both halves)
-__global__ void symmetrize_kernel(double *A, const int64_t *off, const int *n) {
+// A <- (A + A^T) / 2 in place (ld n), by 32 x 32 tile pairs through LDS so
+// that reads and writes run down columns: work-group (bi, bj), bi <= bj,
+// loads tiles (bi, bj) and (bj, bi), averages each entry with its mirror and
+// writes both (a diagonal tile with itself)
+__global__ __launch_bounds__(256) void symmetrize_kernel(double *A, const int64_t *off, const int *n,
+                                                         int nt) {
+  __shared__ double up[32][33], lo[32][33];
+  const int bi = blockIdx.x % nt, bj = blockIdx.x / nt;
+  if (bi > bj) return;
   const int e = blockIdx.y;
-  const int64_t m = n[e];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m * m) return;
-  const int r = (int)(i % m), c = (int)(i / m);
-  if (r <= c) return;
+  const int m = n[e];
+  if (32 * bj >= m) return;
   double *a = A + off[e];
-  const double v = 0.5 * (a[r + (int64_t)c * m] + a[c + (int64_t)r * m]);
-  a[r + (int64_t)c * m] = v;
-  a[c + (int64_t)r * m] = v;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int cl = ty + 8 * q;
+    const int ru = 32 * bi + tx, cu = 32 * bj + cl;  // tile (bi, bj)
+    const int rl = 32 * bj + tx, cw = 32 * bi + cl;  // tile (bj, bi)
+    if (ru < m && cu < m) up[cl][tx] = a[ru + (int64_t)cu * m];
+    if (rl < m && cw < m) lo[cl][tx] = a[rl + (int64_t)cw * m];
+  }
+  __syncthreads();
+  // entry (r, c) of tile (bi, bj) mirrors entry (c, r) of tile (bj, bi):
+  // up[cl][rl'] with lo[rl'][cl] swapped to lo[col][row] = lo[tx'..]
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int cl = ty + 8 * q;
+    const int ru = 32 * bi + tx, cu = 32 * bj + cl;
+    const int rl = 32 * bj + tx, cw = 32 * bi + cl;
+    if (ru < m && cu < m) a[ru + (int64_t)cu * m] = 0.5 * (up[cl][tx] + lo[tx][cl]);
+    if (rl < m && cw < m) a[rl + (int64_t)cw * m] = 0.5 * (lo[cl][tx] + up[tx][cl]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1354,7 +1375,8 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   // the coefficients of i and j differ by orders of magnitude)
   HIPCHK(DenseOps<double>::gemm(stream, Sh, Xb, BJf, d_gbj, np, max_sp, max_sp, false, false, 1.0,
                                 0.0, false, gbj.data()));
-  symmetrize_kernel<<<dim3(nblocks((int64_t)max_sp * max_sp), np), TPB, 0, stream>>>(BJf, d_off_p, d_nsp);
+  symmetrize_kernel<<<dim3(((max_sp + 31) / 32) * ((max_sp + 31) / 32), np), 256, 0, stream>>>(
+      BJf, d_off_p, d_nsp, (max_sp + 31) / 32);
   HIPCHK(hipGetLastError());
   double *Mc = pool.zeros(stream, tc), *BJc = pool.zeros(stream, tc);
   int *d_call = pool.up(stream, call), *d_nc = pool.up(stream, ncv);
@@ -1407,7 +1429,8 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   HIPCHK(DenseOps<double>::trsm(stream, By, Cp, d_mdd, mdd.data(), np, false, dv_y, do_y));
   // the two solves leave C' symmetric only to ~kappa(By) eps; LOBPCG's
   // residuals cannot drop below that asymmetry, so C' is symmetrized
-  symmetrize_kernel<<<dim3(nblocks((int64_t)max_d * max_d), np), TPB, 0, stream>>>(Cp, d_off_dd, d_dv);
+  symmetrize_kernel<<<dim3(((max_d + 31) / 32) * ((max_d + 31) / 32), np), 256, 0, stream>>>(
+      Cp, d_off_dd, d_dv, (max_d + 31) / 32);
   HIPCHK(hipGetLastError());
 
   log("reduced pair matrices");

@@ -458,16 +458,30 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool
   gemm_tile<T, BWD, false, 2, 2, 1, 4>(Di, B, B, w, d.nrhs, w, NB, d.ldb, d.ldb, T(1), T(0), 0, c0);
 }
 
+// Upper triangle <- lower triangle, by 32 x 32 tiles through LDS so that
+// both the reads and the writes run down columns: work-group (bi, bj), bi <=
+// bj, writes tile (bi, bj) from the transpose of tile (bj, bi) (on the
+// diagonal only the entries above it).
 template <class T>
-__global__ void symmetrize_kernel(T *pool, const MatDesc *desc, int maxn) {
+__global__ __launch_bounds__(256) void symmetrize_kernel(T *pool, const MatDesc *desc, int nt) {
+  __shared__ T tl[32][33];
+  const int bi = blockIdx.x % nt, bj = blockIdx.x / nt;
+  if (bi > bj) return;
   const MatDesc d = desc[blockIdx.y];
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = d.n;
-  if (idx >= n * n) return;
-  const int r = (int)(idx % n), c = (int)(idx / n);
-  if (r < c) {
-    T *A = pool + d.a_off;
-    A[r + (int64_t)c * d.lda] = A[c + (int64_t)r * d.lda];
+  const int n = d.n;
+  if (32 * bj >= n) return;
+  T *A = pool + d.a_off;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 32 * bj + tx, c = 32 * bi + ty + 8 * q;  // lower tile (bj, bi)
+    if (r < n && c < n) tl[ty + 8 * q][tx] = A[r + (int64_t)c * d.lda];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 32 * bi + tx, c = 32 * bj + ty + 8 * q;  // upper tile (bi, bj)
+    if (r < n && c < n && r < c) A[r + (int64_t)c * d.lda] = tl[tx][ty + 8 * q];
   }
 }
 
@@ -1059,9 +1073,9 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
 template <class T>
 hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn) {
   if (batch <= 0 || maxn <= 0) return hipSuccess;
-  const int64_t nn = (int64_t)maxn * maxn;
-  dim3 g((unsigned)((nn + 255) / 256), batch);
-  symmetrize_kernel<T><<<g, 256, 0, st>>>(pool, d_desc, maxn);
+  const int nt = (maxn + 31) / 32;
+  dim3 g((unsigned)(nt * nt), batch);
+  symmetrize_kernel<T><<<g, 256, 0, st>>>(pool, d_desc, nt);
   return hipGetLastError();
 }
 
