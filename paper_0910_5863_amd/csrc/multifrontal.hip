@@ -54,17 +54,18 @@ __global__ void mf_pull_kernel(const MfFront *F, const int *ids, const int *chil
                                const int *pmap, double *U, double *C) {
   const MfFront f = F[ids[blockIdx.y]];
   const int p = f.p, b = f.b, fs = p + b;
-  const int64_t nu = f.n_child > 0 ? (int64_t)p * fs : 0, ntot = nu + (int64_t)b * b;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ntot;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  // a front's blocks hold well under 2^31 entries: 32-bit index arithmetic
+  // (a 64-bit division costs several times a 32-bit one)
+  const int nu = f.n_child > 0 ? p * fs : 0, ntot = nu + b * b;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ntot; e += gridDim.x * blockDim.x) {
     int pr, pc;
     const bool in_u = e < nu;
     if (in_u) {
-      pr = (int)(e % p);
-      pc = (int)(e / p);
+      pr = e % p;
+      pc = e / p;
     } else {
-      const int64_t e2 = e - nu;
-      const int r = (int)(e2 % b), c = (int)(e2 / b);
+      const int e2 = e - nu;
+      const int r = e2 % b, c = e2 / b;
       if (r < c) continue;
       pr = p + r;
       pc = p + c;
@@ -90,10 +91,9 @@ __global__ void mf_root_pull_kernel(const MfFront *F, const int *root_ptr, const
   const int ng = nG[s];
   const int r0 = root_ptr[s], r1 = root_ptr[s + 1];
   if (r0 == r1) return;
-  const int64_t nn = (int64_t)ng * ng;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int r = (int)(e % ng), c = (int)(e / ng);
+  const int nn = ng * ng;  // interface blocks hold well under 2^31 entries
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
+    const int r = e % ng, c = e / ng;
     if (r < c) continue;
     double acc = 0;
     for (int ri = r0; ri < r1; ++ri) {
@@ -364,6 +364,9 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
       ids.push_back(t);
       const MfFront &f = M.fronts[t];
       max_f_[d] = std::max<int64_t>(max_f_[d], (int64_t)f.p * (f.p + f.b) + (int64_t)f.b * f.b);
+      // the extend-add kernels index a front's blocks with 32-bit integers
+      if (max_f_[d] >= ((int64_t)1 << 31))
+        throw ArgError("a front holds 2^31 entries or more");
       max_pb_[d] = std::max(max_pb_[d], f.p + f.b);
       max_p_[d] = std::max(max_p_[d], f.p);
       max_b_[d] = std::max(max_b_[d], f.b);
@@ -478,6 +481,8 @@ void MfDevice::factor(hipStream_t st, const double *val, int64_t nnz, double *S,
     }
   }
   if (max_nG > 0 && nsub > 0) {
+    if ((int64_t)max_nG * max_nG >= ((int64_t)1 << 31))  // 32-bit indices in mf_root_pull_kernel
+      throw ArgError("an interface of 46341 dofs or more");
     const unsigned gx = (unsigned)std::min<int64_t>(4096, ((int64_t)max_nG * max_nG + TPB - 1) / TPB);
     LaunchScope ls(st, "mf_root_pull_kernel", 0, 0);
     mf_root_pull_kernel<<<dim3(std::max(1u, gx), nsub), TPB, 0, st>>>(
