@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc 
 
 // forward: B[kb:kb+w, :] -= L[kb:kb+w, :kb] B[:kb, :]
 // backward: B[kb:kb+w, :] -= L[kb+w:n, kb:kb+w]^T B[kb+w:n, :]
-// NT = 4, KS = 1: 128-column tiles; NT = 2, KS = 2: 64-column tiles with two
+// NT = 4, KS = 1: 128-column tiles; NT = 1, KS = 2: 32-column tiles with two
 // groups of waves splitting K (few right-hand sides, long K)
 template <class T, bool BWD, int NT, int KS>
 __global__ __launch_bounds__(256 * KS) void trsm_update_kernel(const T *apool, T *bpool,
@@ -972,7 +972,7 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
       }
     if (k > 0) {
       LaunchScope ls(st, "chol_update_kernel", bu, fu);
-      if (batch * tu >= 512) {
+      if (batch * tu >= 2048) {  // 128-row tiles only when they fill the device several times
         chol_update_kernel<T, 4, 1><<<grid_round(batch * tu), 256, 0, st>>>(pool, d_desc, k, tu,
                                                                            batch);
       } else {
@@ -1008,7 +1008,7 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
   const int tn = (maxr + NB - 1) / NB;    // 64-wide column tiles (diagonal step)
   const int tu = (maxr + 127) / 128;      // 128-wide column tiles (update)
   const int nwg = grid_round(batch * tn), nwu = grid_round(batch * tu);
-  // few tiles: 64-wide tiles, two groups of waves per tile splitting K
+  // few tiles: 32-wide tiles, two groups of waves per tile splitting K
   const bool narrow = batch * tu < 512;
   auto update = [&](bool bwd, int k) {
     if (!narrow) {
@@ -1017,10 +1017,14 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
       else
         trsm_update_kernel<T, false, 4, 1><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tu, batch);
     } else {
+      // 32-column tiles: twice the work-groups of 64-column ones for few
+      // right-hand sides (the same sums, in the same order)
+      const int t32 = (maxr + 31) / 32;
+      const int nw32 = grid_round(batch * t32);
       if (bwd)
-        trsm_update_kernel<T, true, 2, 2><<<nwg, 512, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+        trsm_update_kernel<T, true, 1, 2><<<nw32, 512, 0, st>>>(pool_a, pool_b, d_desc, k, t32, batch);
       else
-        trsm_update_kernel<T, false, 2, 2><<<nwg, 512, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch);
+        trsm_update_kernel<T, false, 1, 2><<<nw32, 512, 0, st>>>(pool_a, pool_b, d_desc, k, t32, batch);
     }
   };
   const bool timing = launch_timing() != nullptr;
