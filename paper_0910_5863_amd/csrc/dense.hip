@@ -827,10 +827,16 @@ int tune_gemm(hipStream_t st, T *C, const GemmDesc *h, int batch, int dflt, Laun
   if (hi <= lo) return dflt;
   const size_t bytes = sizeof(T) * (size_t)(hi - lo);
   void *save = nullptr;
-  if (hipMallocAsync(&save, bytes, st) != hipSuccess) return dflt;  // no room: keep the default
-  hipEvent_t ev[2];
-  if (hipEventCreate(&ev[0]) != hipSuccess) return -1;
-  if (hipEventCreate(&ev[1]) != hipSuccess) return -1;
+  if (hipMallocAsync(&save, bytes, st) != hipSuccess) {
+    (void)hipGetLastError();  // no room for the copy: keep the default shape, untuned
+    return dflt;
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    (void)hipFreeAsync(save, st);
+    return -1;
+  }
   float best = 0;
   int pick = dflt;
   bool ok = hipMemcpyAsync(save, C + lo, bytes, hipMemcpyDeviceToDevice, st) == hipSuccess;
