@@ -71,6 +71,12 @@ def parse_args():
     ap.add_argument("--serving-rate", type=float, default=8.0, help="arrivals per second")
     ap.add_argument("--serving-workers", type=int, default=4, help="requests in flight at once")
     ap.add_argument("--serving-precision", type=int, default=32, choices=(32, 64))
+    ap.add_argument("--serving-problems", type=int, default=0, metavar="K",
+                    help="> 0: the stream cycles over its first K problems, each request with "
+                         "its own seeded load (a load-case stream on fixed geometries)")
+    ap.add_argument("--serving-resident-gib", type=float, default=0.0,
+                    help="> 0: keep factored contexts resident up to this many GiB, so that "
+                         "requests on a problem already factored only solve")
     ap.add_argument("--variants", choices=("elasticity48", "kmeans64"), default=None,
                     help="instead of the step benchmark, solve the workload once per constraint "
                          "set (c, c+e, c+e+f, 3eigv, adaptive tau with and without edge rows) and "
@@ -191,17 +197,26 @@ def serving(args):
     import numpy as np
     import meshgen
     from paper_0910_5863_amd import Server
-    reqs = meshgen.serving_requests(max(args.serving, 512))[:args.serving]
+    K = args.serving_problems
+    reqs = meshgen.serving_requests(max(args.serving, 512))[:(K if K > 0 else args.serving)]
     probs = [meshgen.request_problem(r) for r in reqs]  # generated before the clock starts
+    if K > 0:
+        # request i: problem i mod K, load scaled entrywise by U(0.5, 2) drawn from seed i
+        loads = [probs[i % K].f * np.random.default_rng(i).uniform(0.5, 2.0, probs[i % K].f.shape)
+                 for i in range(args.serving)]
+        probs = [probs[i % K] for i in range(args.serving)]
+    else:
+        loads = [None] * len(probs)
     gaps = np.random.default_rng(7).exponential(1.0 / args.serving_rate, len(probs))
-    srv = Server(max_active=args.serving_workers, factor_precision=args.serving_precision)
+    srv = Server(max_active=args.serving_workers, factor_precision=args.serving_precision,
+                 resident_bytes=args.serving_resident_gib * 2.0**30)
     t0 = time.perf_counter()
     ids = []
-    for p, t in zip(probs, np.cumsum(gaps)):
+    for p, f, t in zip(probs, loads, np.cumsum(gaps)):
         delay = t0 + t - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        ids.append(srv.submit(p, 10.0))
+        ids.append(srv.submit(p, 10.0, f=f))
     res = [srv.wait(i)[1] for i in ids]
     elapsed = time.perf_counter() - t0
     srv.close()
@@ -217,8 +232,11 @@ def serving(args):
         "p50_queue_s": float(np.percentile(queue, 50)), "max_queue_s": float(queue.max()),
         "arrival_rate_per_s": args.serving_rate, "workers": args.serving_workers,
         "factor_precision": args.serving_precision, "pcg_iters_median": float(np.median(iters)),
+        "reused": int(sum(r.reused for r in res)),
         "elapsed_s": elapsed, "higher_is_better": True, "data": "synthetic",
-        "config": {"workload": "serving_request_stream_seed5", "tau": 10.0, "rtol": 1e-8},
+        "config": {"workload": "serving_request_stream_seed5", "tau": 10.0, "rtol": 1e-8,
+                   "problems": K if K > 0 else len(reqs),
+                   "resident_gib": args.serving_resident_gib},
     }))
 
 

@@ -290,6 +290,17 @@ typedef struct {
   int max_active;             /* requests in flight at once (0 means 4) */
   double hbm_budget_bytes;    /* admission limit on the summed footprint
                                  estimates (0: 80% of the device's free memory) */
+  double resident_bytes;      /* > 0: resident factors.  The factored context of
+                                 a finished request stays on the device (its
+                                 footprint counts in the budget); a later request
+                                 on the same problem (mesh, partition,
+                                 constraints and tau equal, any load) skips setup,
+                                 adaptation and factorization, and up to 16 queued
+                                 requests on it are taken by one worker.  Idle
+                                 contexts beyond this many bytes of footprint, or
+                                 in the way of a new request, are destroyed least
+                                 recently used first.  0: every request builds and
+                                 frees its own context. */
 } bddc_server_options;
 
 typedef struct {
@@ -303,6 +314,7 @@ typedef struct {
   int64_t nc;                 /* rows of D used by the solve */
   bddc_pcg_info pcg;
   char error[160];            /* message of a failed request */
+  int reused;                 /* 1: served by a resident factorization */
 } bddc_request_info;
 
 bddc_status bddc_server_create(const bddc_server_options *opt, bddc_server **out);

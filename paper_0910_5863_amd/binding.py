@@ -86,14 +86,14 @@ class bddc_info(C.Structure):
 
 class bddc_server_options(C.Structure):
     _fields_ = [("device", C.c_int), ("factor_precision", C.c_int), ("max_active", C.c_int),
-                ("hbm_budget_bytes", C.c_double)]
+                ("hbm_budget_bytes", C.c_double), ("resident_bytes", C.c_double)]
 
 
 class bddc_request_info(C.Structure):
     _fields_ = [("id", C.c_int64), ("state", C.c_int), ("status", C.c_int), ("submit_s", C.c_double),
                 ("start_s", C.c_double), ("done_s", C.c_double), ("footprint_bytes", C.c_double),
                 ("n_glob", C.c_int64), ("omega", C.c_double), ("nc", C.c_int64),
-                ("pcg", bddc_pcg_info), ("error", C.c_char * 160)]
+                ("pcg", bddc_pcg_info), ("error", C.c_char * 160), ("reused", C.c_int)]
 
 
 class bddc_kernel_stat(C.Structure):
@@ -298,16 +298,18 @@ class Server:
     results are host arrays; device memory is the server's own."""
 
     def __init__(self, device: int = 0, factor_precision: int = 64, max_active: int = 4,
-                 hbm_budget_bytes: float = 0.0):
+                 hbm_budget_bytes: float = 0.0, resident_bytes: float = 0.0):
         self.h = bddc_server_create(bddc_server_options(device, factor_precision, max_active,
-                                                        float(hbm_budget_bytes)))
+                                                        float(hbm_budget_bytes),
+                                                        float(resident_bytes)))
         self._n = {}
 
-    def submit(self, prob, tau=0.0, mode="ce", rtol=1e-8, maxit=1000):
+    def submit(self, prob, tau=0.0, mode="ce", rtol=1e-8, maxit=1000, f=None):
+        """Queues prob with load f (default prob.f)."""
         mesh, part, cons, _arrays = _marshal(prob, mode)
-        rid = bddc_server_submit(self.h, mesh, part, cons, tau, prob.f,
-                                 bddc_pcg_params(rtol, maxit))
-        self._n[rid] = int(np.asarray(prob.f).shape[0])
+        f = prob.f if f is None else np.ascontiguousarray(f, dtype=np.float64)
+        rid = bddc_server_submit(self.h, mesh, part, cons, tau, f, bddc_pcg_params(rtol, maxit))
+        self._n[rid] = int(np.asarray(f).shape[0])
         return rid
 
     def wait(self, rid):

@@ -2,6 +2,11 @@
 // by device-memory footprint, one worker thread and one non-blocking stream
 // per request in flight, stream-ordered allocations (hipMallocAsync /
 // hipFreeAsync) so that no allocation or release synchronizes the device.
+// With resident factors on, the factored context of a problem stays on the
+// device after its request (on a stream of its own); later requests on the
+// same problem skip setup, adaptation and factorization, queued ones are
+// taken together, and idle contexts are evicted least recently used first
+// when the budget needs their memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,10 +41,61 @@ struct Request {
   bddc_pcg_params params{};
   double tau = 0;
   int64_t n_glob = 0;
+  uint64_t key = 0;  // fingerprint of the problem (everything but the load)
   // results
   bddc_request_info info{};
   std::vector<double> u;
 };
+
+// FNV-1a over the bytes of the problem (mesh, partition, constraints, tau)
+uint64_t fnv(uint64_t h, const void *p, size_t n) {
+  const unsigned char *c = (const unsigned char *)p;
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+uint64_t problem_key(const Request &r) {
+  uint64_t h = 1469598103934665603ull;
+  h = fnv(h, &r.mesh.kind, sizeof r.mesh.kind);
+  h = fnv(h, &r.mesh.nu, sizeof r.mesh.nu);
+  h = fnv(h, r.xyz.data(), sizeof(double) * r.xyz.size());
+  h = fnv(h, r.hex8.data(), sizeof(int64_t) * r.hex8.size());
+  h = fnv(h, r.coef.data(), sizeof(double) * r.coef.size());
+  h = fnv(h, r.dirichlet.data(), r.dirichlet.size());
+  h = fnv(h, r.elem_sub.data(), sizeof(int32_t) * r.elem_sub.size());
+  h = fnv(h, &r.n_sub, sizeof r.n_sub);
+  h = fnv(h, &r.cons.mode, sizeof r.cons.mode);
+  h = fnv(h, &r.cons.augment_corners, sizeof r.cons.augment_corners);
+  h = fnv(h, &r.cons.qr_drop_tol, sizeof r.cons.qr_drop_tol);
+  h = fnv(h, &r.cons.adaptive_edges, sizeof r.cons.adaptive_edges);
+  h = fnv(h, &r.tau, sizeof r.tau);
+  return h;
+}
+
+// the same problem (the fingerprint only selects the candidates)
+bool same_problem(const Request &a, const Request &b) {
+  return a.key == b.key && a.n_glob == b.n_glob && a.mesh.kind == b.mesh.kind &&
+         a.mesh.nu == b.mesh.nu &&
+         a.xyz == b.xyz && a.hex8 == b.hex8 && a.coef == b.coef && a.dirichlet == b.dirichlet &&
+         a.elem_sub == b.elem_sub && a.n_sub == b.n_sub && a.cons.mode == b.cons.mode &&
+         a.cons.augment_corners == b.cons.augment_corners &&
+         a.cons.qr_drop_tol == b.cons.qr_drop_tol && a.cons.adaptive_edges == b.cons.adaptive_edges &&
+         a.tau == b.tau;
+}
+
+// A factored context kept on the device for its problem.
+struct Resident {
+  std::unique_ptr<Request> proto;  // a copy of the problem's inputs (the load unused)
+  bddc_ctx *ctx = nullptr;
+  hipStream_t st = nullptr;
+  double footprint = 0;
+  bool busy = true;   // a worker builds or uses it
+  uint64_t last_used = 0;
+  double omega = 0;
+  int64_t nc = 0;
+};
+
+constexpr int kMaxTaken = 16;  // queued requests on one resident problem taken at once
 
 // Footprint estimate from the mesh and partition (see bddc_server_submit).
 double footprint(const Request &r) {
@@ -97,28 +153,95 @@ struct bddc_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> queue;
   std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
-  double reserved = 0;
+  double reserved = 0;   // footprints of the requests in flight and the resident contexts
   int running = 0;
   int64_t next_id = 0;
   bool stopping = false;
   std::vector<std::thread> workers;
+  std::vector<std::unique_ptr<Resident>> resident;
+  uint64_t use_clock = 0;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+  bool keep_resident() const { return opt.resident_bytes > 0; }
 
-  // the head of the queue fits beside the requests in flight (or runs alone)
-  bool head_fits() const {
-    if (queue.empty()) return false;
-    return running == 0 || reserved + queue.front()->info.footprint_bytes <= opt.hbm_budget_bytes;
+  Resident *find_resident(const Request &r) const {
+    for (auto &e : resident)
+      if (same_problem(*e->proto, r)) return e.get();
+    return nullptr;
+  }
+  double idle_resident_bytes() const {
+    double b = 0;
+    for (auto &e : resident)
+      if (!e->busy) b += e->footprint;
+    return b;
   }
 
-  // runs request r; results go to out and u (published by the caller under
-  // the lock, so that queries never read a record being written)
-  void process(const Request &r, bddc_request_info &out, std::vector<double> &u, hipStream_t st);
+  // the head of the queue can start: its problem is resident and idle, or it
+  // fits beside the requests in flight once idle resident contexts are
+  // evicted (or runs alone); a head whose problem is resident but busy waits
+  bool head_admissible() const {
+    if (queue.empty()) return false;
+    const Request &h = *queue.front();
+    if (Resident *e = find_resident(h)) return !e->busy;
+    return running == 0 ||
+           reserved - idle_resident_bytes() + h.info.footprint_bytes <= opt.hbm_budget_bytes;
+  }
+
+  // removes idle resident contexts, least recently used first, while
+  // pred(bytes removed so far) holds.  They are destroyed by the caller
+  // outside the lock; their footprints stay in `reserved` until then
+  // (release_destroyed), so admission never counts memory not yet freed.
+  template <class Pred>
+  void evict_while(Pred pred, std::vector<std::unique_ptr<Resident>> &out) {
+    double freed = 0;
+    while (pred(freed)) {
+      int v = -1;
+      for (int i = 0; i < (int)resident.size(); ++i)
+        if (!resident[i]->busy && (v < 0 || resident[i]->last_used < resident[v]->last_used)) v = i;
+      if (v < 0) return;
+      freed += resident[v]->footprint;
+      out.push_back(std::move(resident[v]));
+      resident.erase(resident.begin() + v);
+    }
+  }
+  // destroys removed resident contexts, then returns their footprints
+  void release_destroyed(std::vector<std::unique_ptr<Resident>> &v);
+
+  // builds a context for r's problem on stream st (setup, adapt, factor);
+  // null on failure, with info.status and info.error set
+  bddc_ctx *build(const Request &r, bddc_request_info &info, hipStream_t st);
+  // solves r on a factored context; results go to info and u (published by
+  // the caller under the lock, so that queries never read a record being
+  // written)
+  void solve(bddc_ctx *c, const Request &r, bddc_request_info &info, std::vector<double> &u,
+             hipStream_t st);
   void worker();
 };
 
-void bddc_server::process(const Request &r, bddc_request_info &info, std::vector<double> &u,
-                          hipStream_t st) {
+void destroy_resident(std::vector<std::unique_ptr<Resident>> &v) {
+  for (auto &e : v) {
+    if (e->ctx) bddc_destroy(e->ctx);
+    if (e->st) {
+      (void)hipStreamSynchronize(e->st);
+      (void)hipStreamDestroy(e->st);
+    }
+  }
+  v.clear();
+}
+
+void bddc_server::release_destroyed(std::vector<std::unique_ptr<Resident>> &v) {
+  if (v.empty()) return;
+  double b = 0;
+  for (auto &e : v) b += e->footprint;
+  destroy_resident(v);
+  {
+    std::lock_guard<std::mutex> lk(m);
+    reserved -= b;
+  }
+  cv_work.notify_all();
+}
+
+bddc_ctx *bddc_server::build(const Request &r, bddc_request_info &info, hipStream_t st) {
   bddc_options o{};
   o.device = opt.device;
   o.hip_stream = st;
@@ -127,7 +250,6 @@ void bddc_server::process(const Request &r, bddc_request_info &info, std::vector
   o.free = async_free;
   o.alloc_user = st;
   bddc_ctx *c = nullptr;
-  double *fd = nullptr, *ud = nullptr;
   auto fail = [&](bddc_status s, const char *what) {
     info.status = s;
     std::snprintf(info.error, sizeof info.error, "%s: %s", what,
@@ -136,7 +258,7 @@ void bddc_server::process(const Request &r, bddc_request_info &info, std::vector
   bddc_status s = bddc_create(&o, &c);
   if (s != BDDC_OK) {
     fail(s, "create");
-    return;
+    return nullptr;
   }
   bddc_partition part{r.n_sub, r.elem_sub.data()};
   s = bddc_setup(c, &r.mesh, &part, &r.cons);
@@ -145,7 +267,8 @@ void bddc_server::process(const Request &r, bddc_request_info &info, std::vector
   if (s != BDDC_OK) {
     fail(s, "setup");
   } else if (inf.n_glob != r.n_glob) {
-    info.status = BDDC_ERR_ARG;
+    s = BDDC_ERR_ARG;
+    info.status = s;
     std::snprintf(info.error, sizeof info.error, "load has %lld entries, the mesh %lld dofs",
                   (long long)r.n_glob, (long long)inf.n_glob);
   } else {
@@ -158,75 +281,179 @@ void bddc_server::process(const Request &r, bddc_request_info &info, std::vector
       info.nc = ai.nc;
     }
     if (s == BDDC_OK && (s = bddc_factor(c)) != BDDC_OK) fail(s, "factor");
-    if (s == BDDC_OK) {
-      const size_t nb = sizeof(double) * (size_t)r.n_glob;
-      fd = (double *)async_alloc(nb, st);
-      ud = (double *)async_alloc(nb, st);
-      if (!fd || !ud || hipMemcpyAsync(fd, r.f.data(), nb, hipMemcpyHostToDevice, st) != hipSuccess) {
-        info.status = BDDC_ERR_OOM;
-        std::snprintf(info.error, sizeof info.error, "load / solution buffers");
-      } else if ((s = bddc_pcg_solve(c, 1, fd, r.n_glob, ud, r.n_glob, &r.params, &info.pcg)) !=
-                 BDDC_OK) {
-        fail(s, "pcg");
-      } else {
-        u.resize(r.n_glob);
-        if (hipMemcpyAsync(u.data(), ud, nb, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
-          info.status = BDDC_ERR_DEVICE;
-          std::snprintf(info.error, sizeof info.error, "copy of the solution");
-        }
-      }
+  }
+  if (s != BDDC_OK) {
+    bddc_destroy(c);
+    (void)hipStreamSynchronize(st);
+    return nullptr;
+  }
+  return c;
+}
+
+void bddc_server::solve(bddc_ctx *c, const Request &r, bddc_request_info &info,
+                        std::vector<double> &u, hipStream_t st) {
+  const size_t nb = sizeof(double) * (size_t)r.n_glob;
+  double *fd = (double *)async_alloc(nb, st), *ud = (double *)async_alloc(nb, st);
+  bddc_status s;
+  if (!fd || !ud || hipMemcpyAsync(fd, r.f.data(), nb, hipMemcpyHostToDevice, st) != hipSuccess) {
+    info.status = BDDC_ERR_OOM;
+    std::snprintf(info.error, sizeof info.error, "load / solution buffers");
+  } else if ((s = bddc_pcg_solve(c, 1, fd, r.n_glob, ud, r.n_glob, &r.params, &info.pcg)) != BDDC_OK) {
+    info.status = s;
+    std::snprintf(info.error, sizeof info.error, "pcg: %s", bddc_last_error(c));
+  } else {
+    u.resize(r.n_glob);
+    if (hipMemcpyAsync(u.data(), ud, nb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      info.status = BDDC_ERR_DEVICE;
+      std::snprintf(info.error, sizeof info.error, "copy of the solution");
     }
   }
   if (fd) async_free(fd, st);
   if (ud) async_free(ud, st);
-  bddc_destroy(c);
   (void)hipStreamSynchronize(st);
 }
 
 void bddc_server::worker() {
   (void)hipSetDevice(opt.device);
-  hipStream_t st = nullptr;
-  const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  hipStream_t wst = nullptr;
+  const bool have_stream = hipStreamCreateWithFlags(&wst, hipStreamNonBlocking) == hipSuccess;
   for (;;) {
-    Request *r = nullptr;
+    std::vector<Request *> batch;
+    Resident *res = nullptr;
+    bool fresh = true;  // the context is built for this batch
+    std::vector<std::unique_ptr<Resident>> victims;
     {
       std::unique_lock<std::mutex> lk(m);
-      cv_work.wait(lk, [&] { return head_fits() || (stopping && queue.empty()); });
+      cv_work.wait(lk, [&] { return head_admissible() || (stopping && queue.empty()); });
       if (queue.empty()) break;
-      r = queue.front();
-      queue.pop_front();
-      reserved += r->info.footprint_bytes;
+      Request *h = queue.front();
+      res = find_resident(*h);
+      if (res) {
+        // resident and idle: take the queued requests on this problem
+        res->busy = true;
+        fresh = false;
+        for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < kMaxTaken;) {
+          if (same_problem(**it, *h)) {
+            batch.push_back(*it);
+            it = queue.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      } else {
+        queue.pop_front();
+        batch.push_back(h);
+        const double fp = h->info.footprint_bytes;
+        evict_while([&](double freed) { return reserved - freed + fp > opt.hbm_budget_bytes; },
+                    victims);
+        reserved += fp;
+        if (keep_resident()) {
+          // registered now, so requests on the same problem wait for it
+          // instead of factoring it again
+          auto e = std::make_unique<Resident>();
+          e->proto = std::make_unique<Request>(*h);
+          e->proto->f.clear();
+          e->proto->mesh.xyz = e->proto->xyz.data();  // its own copies
+          e->proto->mesh.hex8 = e->proto->hex8.data();
+          e->proto->mesh.coef = e->proto->coef.data();
+          e->proto->mesh.dirichlet = e->proto->dirichlet.data();
+          e->footprint = fp;
+          res = e.get();
+          resident.push_back(std::move(e));
+        }
+      }
       running++;
-      r->info.state = 1;
-      r->info.start_s = now();
+      for (Request *r : batch) {
+        r->info.state = 1;
+        r->info.start_s = now();
+      }
     }
-    cv_work.notify_all();  // the new head may fit beside this one
-    bddc_request_info res;
-    std::vector<double> u;
+    cv_work.notify_all();  // the new head may be admissible too
+    release_destroyed(victims);
+    std::vector<bddc_request_info> out(batch.size());
+    std::vector<std::vector<double>> us(batch.size());
     {
       std::lock_guard<std::mutex> lk(m);
-      res = r->info;
+      for (size_t i = 0; i < batch.size(); ++i) out[i] = batch[i]->info;
     }
-    if (have_stream) {
-      process(*r, res, u, st);
-    } else {
-      res.status = BDDC_ERR_DEVICE;
-      std::snprintf(res.error, sizeof res.error, "stream creation failed");
+    bddc_ctx *c = res ? res->ctx : nullptr;
+    hipStream_t st = (res && !fresh) ? res->st : wst;
+    bool ok = true;
+    if (fresh) {
+      // a resident context gets a stream of its own (any worker may use it later)
+      bool stream_ok = have_stream;
+      if (res) {
+        stream_ok = hipStreamCreateWithFlags(&res->st, hipStreamNonBlocking) == hipSuccess;
+        if (!stream_ok) res->st = nullptr;
+        st = res->st;
+      }
+      if (!stream_ok) {
+        out[0].status = BDDC_ERR_DEVICE;
+        std::snprintf(out[0].error, sizeof out[0].error, "stream creation failed");
+        ok = false;
+      } else {
+        c = build(*batch[0], out[0], st);
+        ok = c != nullptr;
+        if (ok && res) {
+          res->ctx = c;
+          res->omega = out[0].omega;
+          res->nc = out[0].nc;
+        }
+      }
     }
+    for (size_t i = 0; i < batch.size() && ok; ++i) {
+      if (!fresh) {
+        out[i].omega = res->omega;
+        out[i].nc = res->nc;
+        out[i].reused = 1;
+      }
+      solve(c, *batch[i], out[i], us[i], st);
+    }
+    // a context of its own is freed before its footprint is returned
+    if (!res && c) {
+      bddc_destroy(c);
+      (void)hipStreamSynchronize(st);
+    }
+    std::vector<std::unique_ptr<Resident>> dropped;
     {
       std::lock_guard<std::mutex> lk(m);
-      r->info = res;
-      r->u.swap(u);
-      reserved -= r->info.footprint_bytes;
+      for (size_t i = 0; i < batch.size(); ++i) {
+        Request *r = batch[i];
+        r->info = out[i];
+        if (!ok && i > 0) {
+          r->info.status = out[0].status;
+          std::memcpy(r->info.error, out[0].error, sizeof r->info.error);
+        }
+        r->u.swap(us[i]);
+        r->info.done_s = now();
+        r->info.state = r->info.status == BDDC_OK ? 2 : 3;
+      }
       running--;
-      r->info.done_s = now();
-      r->info.state = r->info.status == BDDC_OK ? 2 : 3;
+      if (res) {
+        if (ok) {
+          res->busy = false;
+          res->last_used = ++use_clock;
+          // keep the idle contexts within their own limit
+          evict_while([&](double freed) { return idle_resident_bytes() > opt.resident_bytes; },
+                      dropped);
+        } else {
+          for (size_t i = 0; i < resident.size(); ++i)
+            if (resident[i].get() == res) {
+              dropped.push_back(std::move(resident[i]));
+              resident.erase(resident.begin() + i);
+              break;
+            }
+        }
+      } else {
+        reserved -= batch[0]->info.footprint_bytes;
+      }
     }
     cv_done.notify_all();
+    release_destroyed(dropped);
     cv_work.notify_all();
   }
-  if (have_stream) (void)hipStreamDestroy(st);
+  if (have_stream) (void)hipStreamDestroy(wst);
 }
 
 extern "C" {
@@ -290,6 +517,7 @@ bddc_status bddc_server_submit(bddc_server *srv, const bddc_mesh *mesh, const bd
   r->n_glob = n_glob;
   r->info.footprint_bytes = footprint(*r);
   r->info.n_glob = n_glob;
+  r->key = problem_key(*r);
   {
     std::lock_guard<std::mutex> lk(srv->m);
     r->id = r->info.id = srv->next_id++;
@@ -340,6 +568,7 @@ void bddc_server_destroy(bddc_server *srv) {
   }
   srv->cv_work.notify_all();
   for (std::thread &t : srv->workers) t.join();
+  destroy_resident(srv->resident);
   delete srv;
 }
 

@@ -104,3 +104,36 @@ def test_bad_setup_arguments():
         b.setup(bad, "ce")
     assert e.value.code == 1
     b.close()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes structure of the binding that the header defines has the
+    header's size and field offsets (gcc compiles the header as C and prints
+    them)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    txt = open(HEADER).read()
+    structs = [v for k, v in vars(binding).items()
+               if isinstance(v, type) and issubclass(v, ctypes.Structure)
+               and re.search(r"}\s*%s\s*;" % k, txt)]
+    assert len(structs) >= 5
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bddc.h"', "int main(void) {"]
+    expect = []
+    for st in structs:
+        lines.append('printf("%%zu\\n", sizeof(%s));' % st.__name__)
+        expect.append(ctypes.sizeof(st))
+        for name, *_ in st._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (st.__name__, name))
+            expect.append(getattr(st, name).offset)
+    lines.append("return 0; }")
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "abi"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == expect

@@ -115,3 +115,48 @@ def test_server_reports_request_errors():
     u, info = srv.wait(ok)
     assert info.state == 2
     srv.close()
+
+
+def test_server_resident_factors():
+    """resident_bytes > 0: requests on one problem with different loads are
+    served by one factored context.  Each solution has the bits of a fresh
+    solve of its load; every request after the first reports reuse; a
+    different problem in between is served normally; with a limit below one
+    footprint the idle context is destroyed and the next request on the
+    problem factors it again."""
+    _, Server = _gpu()
+    p, tau = _requests()[3]
+    rng = np.random.default_rng(7)
+    loads = [p.f] + [p.f * rng.uniform(0.5, 2.0, p.f.shape) for _ in range(5)]
+    other, tau_o = _requests()[0]
+    fresh = []
+    srv = Server(max_active=1)
+    for f in loads:
+        u, info = srv.wait(srv.submit(p, tau, f=f))
+        assert info.state == 2 and info.reused == 0, info.error
+        fresh.append((u, info))
+    u_o, i_o = srv.wait(srv.submit(other, tau_o))
+    srv.close()
+    srv = Server(max_active=2, resident_bytes=1e12)
+    first = srv.wait(srv.submit(p, tau, f=loads[0]))
+    ids = [srv.submit(p, tau, f=f) for f in loads[1:3]]
+    ids.append(srv.submit(other, tau_o))
+    ids += [srv.submit(p, tau, f=f) for f in loads[3:]]
+    got = [first] + [srv.wait(i) for i in ids]
+    srv.close()
+    u_mid, i_mid = got.pop(3)
+    assert i_mid.state == 2 and np.array_equal(u_mid, u_o) and i_mid.reused == 0
+    assert got[0][1].reused == 0
+    for k, ((u, info), (uf, inf_f)) in enumerate(zip(got, fresh)):
+        assert info.state == 2, info.error
+        assert k == 0 or info.reused == 1
+        assert np.array_equal(u, uf)
+        assert info.pcg.iters == inf_f.pcg.iters
+        assert info.nc == inf_f.nc and info.omega == inf_f.omega
+    # a limit below one footprint: nothing stays resident
+    srv = Server(max_active=1, resident_bytes=1.0)
+    a = srv.wait(srv.submit(p, tau, f=loads[1]))
+    b = srv.wait(srv.submit(p, tau, f=loads[2]))
+    srv.close()
+    assert a[1].reused == 0 and b[1].reused == 0
+    assert np.array_equal(a[0], fresh[1][0]) and np.array_equal(b[0], fresh[2][0])
