@@ -62,6 +62,9 @@ def parse_args():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default GEMM tile shapes (the tuner, on by default, "
                          "measures them during the warmup step)")
+    ap.add_argument("--per-substructure-factor", action="store_true",
+                    help="launch the factor's Cholesky, TRSMs and S_pi product once per "
+                         "substructure instead of once for all (the unbatched baseline)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, run one plain device copy of this many MiB "
                          "(a known-size reference for hardware byte counters)")
@@ -331,7 +334,8 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     p = meshgen.elasticity_layers_48()
-    b = BDDC(device=0, autotune=not args.no_autotune)
+    b = BDDC(device=0, autotune=not args.no_autotune,
+             per_substructure_launches=args.per_substructure_factor)
     b.setup(p, "ce")
     f = torch.from_numpy(p.f).to("cuda:0")
     if args.copy_probe_mib > 0:
@@ -424,7 +428,9 @@ def main():
         "config": {"workload": "elasticity48_4x4x4_layers_adaptive_tau10", "n_glob": int(p.n_glob),
                    "n_sub": int(p.n_sub), "tau": TAU, "rtol": RTOL,
                    "step": "adapt(tau) + factor + pcg_solve(f), problem set up and resident",
-                   "gemm_autotune": not args.no_autotune},
+                   "gemm_autotune": not args.no_autotune,
+                   "factor_launches": ("per_substructure" if args.per_substructure_factor
+                                       else "batched")},
         "roofline": roof,
         "phases_ms": {"adapt": float(ph[:, 0].mean() * 1e3), "factor": float(ph[:, 1].mean() * 1e3),
                       "pcg_solve": float(ph[:, 2].mean() * 1e3)},

@@ -76,6 +76,13 @@ typedef struct {
                                         and restore the product's output, so results
                                         do not depend on this switch.  The first call
                                         of a shape costs a few extra products. */
+  int per_substructure_launches;     /* nonzero: bddc_factor runs the Cholesky of
+                                        K_rr, the two TRSMs of Phi and the S_pi
+                                        product once per substructure instead of
+                                        once for all substructures together (a
+                                        baseline for the batched launches; the
+                                        results agree to rounding, not bitwise,
+                                        since tile shapes follow the batch) */
 } bddc_options;
 
 /* Q1 hexahedral mesh (Sec. 2: substructure matrices are subassembled from

@@ -39,7 +39,8 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 class bddc_options(C.Structure):
     _fields_ = [("device", C.c_int), ("hip_stream", C.c_void_p), ("factor_precision", C.c_int),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", C.c_void_p),
-                ("verbose", C.c_int), ("autotune", C.c_int)]
+                ("verbose", C.c_int), ("autotune", C.c_int),
+                ("per_substructure_launches", C.c_int)]
 
 
 class bddc_mesh(C.Structure):
@@ -339,7 +340,8 @@ class BDDC:
     ``device < 0`` gives a host-only context (setup analysis, no GPU)."""
 
     def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True,
-                 verbose: bool = False, factor_precision: int = 64, autotune: bool = False):
+                 verbose: bool = False, factor_precision: int = 64, autotune: bool = False,
+                 per_substructure_launches: bool = False):
         if device < 0:
             self.torch = None
             self.device = device
@@ -363,6 +365,7 @@ class BDDC:
         opt.factor_precision = int(factor_precision)
         opt.verbose = 1 if verbose else 0
         opt.autotune = 1 if autotune else 0
+        opt.per_substructure_launches = 1 if per_substructure_launches else 0
         self._keep = []
         if torch_allocator:
             def _alloc(n, user):

@@ -99,6 +99,7 @@ bddc_status bddc_create(const bddc_options *opt, bddc_ctx **out) {
     c->S->alloc.user = c->opt.alloc_user;
     c->S->verbose = c->opt.verbose;
     c->S->factor_precision = c->opt.factor_precision;
+    c->S->per_sub_launches = c->opt.per_substructure_launches != 0;
   });
   if (st != BDDC_OK) return st;
   *out = c.release();

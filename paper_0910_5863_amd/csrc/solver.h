@@ -187,6 +187,7 @@ class Solver {
   hipEvent_t pcg_ev[2] = {nullptr, nullptr};
   int *pcg_pin = nullptr;
   bool use_graphs = true;
+  bool per_sub_launches = false;  // factor's dense operations one substructure at a time
   void pcg_iteration();
   void drop_pcg_graph();
 };

@@ -1166,20 +1166,30 @@ void Solver::factor() {
   // constrained local factor and coarse basis (FP64 in both precisions:
   // S_pi = K_pi,pi - K_pi,r K_rr^-1 K_r,pi is a difference of nearly equal
   // terms at high coefficient contrast)
+  // all substructures in each launch sequence, or (per_sub_launches) one
+  // substructure per sequence: the same operations entry by entry
+  const int ng = per_sub_launches ? ns : 1, gs = per_sub_launches ? 1 : ns;
+  const MatDesc *dRR = d_descRR.as<MatDesc>();
+  const int64_t *dio = d_dinv_rr_off.as<int64_t>();
   timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
-  HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), d_descRR.as<MatDesc>(), h_descRR.data(),
-                                 ns, status + ns, d_dinv_rr.as<double>(),
-                                 d_dinv_rr_off.as<int64_t>()));
+  for (int g = 0; g < ng; ++g)
+    HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), dRR + g * gs, h_descRR.data() + g * gs,
+                                   gs, status + ns + g * gs, d_dinv_rr.as<double>(), dio + g * gs));
   timer.end(st);
-  HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
-                                h_descRR.data(), ns, false, d_dinv_rr.as<double>(),
-                                d_dinv_rr_off.as<int64_t>()));
-  HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
-                                d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false,
-                                -1.0, 1.0, false, h_spi.data()));
-  HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), d_descRR.as<MatDesc>(),
-                                h_descRR.data(), ns, true, d_dinv_rr.as<double>(),
-                                d_dinv_rr_off.as<int64_t>()));
+  for (int g = 0; g < ng; ++g)
+    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR + g * gs,
+                                  h_descRR.data() + g * gs, gs, false, d_dinv_rr.as<double>(),
+                                  dio + g * gs));
+  for (int g = 0; g < ng; ++g) {
+    const int mm = per_sub_launches ? h_spi[g].M : L.max_np, nn = per_sub_launches ? h_spi[g].N : L.max_np;
+    HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
+                                  d_spi_desc.as<GemmDesc>() + g * gs, gs, mm, nn, true, false, -1.0,
+                                  1.0, false, h_spi.data() + g * gs));
+  }
+  for (int g = 0; g < ng; ++g)
+    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR + g * gs,
+                                  h_descRR.data() + g * gs, gs, true, d_dinv_rr.as<double>(),
+                                  dio + g * gs));
   if (L.sRP > 0) {
     axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
                                                  L.sRP);

@@ -204,3 +204,26 @@ def test_pcg_graph_matches_eager():
         assert np.array_equal(u, runs[0][0])
         assert kappa == runs[0][3]
     b.close()
+
+
+def test_per_substructure_factor_launches():
+    """per_substructure_launches: the factor's dense operations launched one
+    substructure at a time give the oracle's solution (1e-8) and the batched
+    launches' solution to rounding (tile shapes follow the batch size)."""
+    BDDC = _gpu()
+    from oracle.solver import OracleBDDC
+    p = meshgen.small_kmeans(meshgen.ELASTICITY, 8, 4, contrast=1e3)
+    ref = OracleBDDC(p, "ce").solve()
+    f = torch.from_numpy(p.f)
+    out = []
+    for per_sub in (False, True):
+        b = BDDC(per_substructure_launches=per_sub)
+        b.setup(p, "ce")
+        b.factor()
+        u, info = b.pcg_solve(f)
+        out.append((u.cpu().numpy()[:, 0], info[0].iters))
+        b.close()
+    (ub, ib), (us, is_) = out
+    assert np.linalg.norm(us - ref["u"]) / np.linalg.norm(ref["u"]) < 1e-8
+    assert np.linalg.norm(us - ub) / np.linalg.norm(ub) < 1e-12
+    assert abs(is_ - ib) <= 1
