@@ -123,7 +123,8 @@ def test_server_resident_factors():
     solve of its load; every request after the first reports reuse; a
     different problem in between is served normally; with a limit below one
     footprint the idle context is destroyed and the next request on the
-    problem factors it again."""
+    problem factors it again; under a budget that holds one of two problems,
+    each evicts the other's idle context."""
     _, Server = _gpu()
     p, tau = _requests()[3]
     rng = np.random.default_rng(7)
@@ -160,3 +161,16 @@ def test_server_resident_factors():
     srv.close()
     assert a[1].reused == 0 and b[1].reused == 0
     assert np.array_equal(a[0], fresh[1][0]) and np.array_equal(b[0], fresh[2][0])
+    # a budget below the two problems' footprints: each new problem evicts
+    # the idle context of the other, and a problem that stays resident is
+    # reused
+    budget = fresh[0][1].footprint_bytes + i_o.footprint_bytes - 1.0
+    srv = Server(max_active=1, resident_bytes=1e12, hbm_budget_bytes=budget)
+    seq = [(p, tau, loads[1]), (other, tau_o, None), (p, tau, loads[2]), (p, tau, loads[3])]
+    res = [srv.wait(srv.submit(q, t, f=f)) for q, t, f in seq]
+    srv.close()
+    assert [r[1].state for r in res] == [2, 2, 2, 2]
+    assert [r[1].reused for r in res] == [0, 0, 0, 1]
+    assert np.array_equal(res[1][0], u_o)
+    for (u, _), k in zip([res[0], res[2], res[3]], (1, 2, 3)):
+        assert np.array_equal(u, fresh[k][0])
