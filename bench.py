@@ -62,6 +62,9 @@ def parse_args():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default GEMM tile shapes (the tuner, on by default, "
                          "measures them during the warmup step)")
+    ap.add_argument("--factor-precision", type=int, default=64, choices=(32, 64),
+                    help="32: FP32 local factor L_rr and local triangular solves (outer PCG, "
+                         "coarse problem and averaging stay FP64)")
     ap.add_argument("--per-substructure-factor", action="store_true",
                     help="launch the factor's Cholesky, TRSMs and S_pi product once per "
                          "substructure instead of once for all (the unbatched baseline)")
@@ -334,7 +337,7 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     p = meshgen.elasticity_layers_48()
-    b = BDDC(device=0, autotune=not args.no_autotune,
+    b = BDDC(device=0, autotune=not args.no_autotune, factor_precision=args.factor_precision,
              per_substructure_launches=args.per_substructure_factor)
     b.setup(p, "ce")
     f = torch.from_numpy(p.f).to("cuda:0")
@@ -423,12 +426,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.factor_precision == 64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "elasticity48_4x4x4_layers_adaptive_tau10", "n_glob": int(p.n_glob),
                    "n_sub": int(p.n_sub), "tau": TAU, "rtol": RTOL,
                    "step": "adapt(tau) + factor + pcg_solve(f), problem set up and resident",
                    "gemm_autotune": not args.no_autotune,
+                   "factor_precision": args.factor_precision,
                    "factor_launches": ("per_substructure" if args.per_substructure_factor
                                        else "batched")},
         "roofline": roof,
