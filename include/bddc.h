@@ -301,13 +301,18 @@ typedef struct {
                                  a finished request stays on the device (its
                                  footprint counts in the budget); a later request
                                  on the same problem (mesh, partition,
-                                 constraints and tau equal, any load) skips setup,
-                                 adaptation and factorization, and up to 16 queued
-                                 requests on it are taken by one worker.  Idle
+                                 constraints, tau and load length equal byte for
+                                 byte; any load values) skips setup, adaptation
+                                 and factorization, and up to 16 queued requests
+                                 on it are taken by one worker.  A queue head
+                                 whose problem is resident but in use waits for
+                                 it (the requests behind it wait too).  Idle
                                  contexts beyond this many bytes of footprint, or
                                  in the way of a new request, are destroyed least
-                                 recently used first.  0: every request builds and
-                                 frees its own context. */
+                                 recently used first; their footprints count until
+                                 their memory is freed.  Requests on one context
+                                 run one after another.  0: every request builds
+                                 and frees its own context. */
 } bddc_server_options;
 
 typedef struct {
