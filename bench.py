@@ -314,8 +314,8 @@ def cpu_baseline():
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the substructure sharding across GPUs is a design, not an implementation)",
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(sharding the substructures across GPUs is designed, not implemented)",
               file=sys.stderr)
         sys.exit(2)
     if args.serving > 0:
