@@ -216,7 +216,35 @@ class PairProblem:
         return d[:, c]
 
 
-def adapt(S, itf, cons, tau, reduced=True, Sd=None, count=None, edges=False):
+def face_pair(S, itf, cons, fg, Sd, tau, reduced=True, count=None, edges=False):
+    """Algorithm 1 on the face glob fg: the pair's eigenvalues (descending),
+    the number selected, the largest unselected eigenvalue, and the new rows
+    as [(glob index, row)] (face rows, then with edges=True the edge rows)."""
+    pp = PairProblem(S, itf, cons, fg, Sd, reduced=reduced)
+    lam, W = pp.solve()
+    if count is None:
+        sel = lam >= tau
+    else:
+        sel = np.zeros(lam.size, dtype=bool)
+        sel[max(0, lam.size - count):] = True
+    unsel = lam[~sel]
+    out = []
+    if sel.any():
+        d = pp.rows(W[:, sel])[::-1]       # largest eigenvalue first
+        c = pp.face_part(d, itf)
+        out += [(fg, row) for row in c / np.abs(c).max(axis=1, keepdims=True)]
+        if edges:
+            scale = np.abs(d).max(axis=1)
+            for gi, ce in pp.edge_parts(d, itf):
+                for q in range(ce.shape[0]):
+                    mx = np.abs(ce[q]).max()
+                    if mx > EDGE_DROP * scale[q]:
+                        out.append((gi, ce[q] / mx))
+    return dict(lam=lam[::-1].copy(), k=int(sel.sum()),
+                unsel_max=float(unsel.max()) if unsel.size else None, rows=out)
+
+
+def adapt(S, itf, cons, tau, reduced=True, Sd=None, count=None, edges=False, mapper=map):
     """Algorithm 1: for every face pair select the eigenvectors with
     lambda >= tau (Sec. 7: eigenvalues greater or equal to tau were used), or
     the ``count`` largest when count is given (tau is then ignored).
@@ -224,34 +252,22 @@ def adapt(S, itf, cons, tau, reduced=True, Sd=None, count=None, edges=False):
     Returns dict(rows={glob: rows}, omega=indicator, k={face: count},
     lam={face: eigenvalues descending}).  rows holds the face rows and, with
     edges=True, the edge rows; on every glob they are ordered by face, then by
-    eigenvalue (largest first)."""
+    eigenvalue (largest first).  ``mapper`` evaluates the independent pair
+    problems (the built-in map by default; a process pool's map gives the same
+    result)."""
     if Sd is None:
         Sd = {s: schur_dense(S, itf, s) for s in range(S.n_sub)}
+    faces = list(itf.face_ids)
+    res = list(mapper(lambda fg: face_pair(S, itf, cons, fg, Sd, tau, reduced, count, edges),
+                      faces))
     rows, kcount, lams = {}, {}, {}
     omega = 0.0
-    for fg in itf.face_ids:
-        pp = PairProblem(S, itf, cons, fg, Sd, reduced=reduced)
-        lam, W = pp.solve()
-        if count is None:
-            sel = lam >= tau
-        else:
-            sel = np.zeros(lam.size, dtype=bool)
-            sel[max(0, lam.size - count):] = True
-        lams[fg] = lam[::-1].copy()
-        kcount[fg] = int(sel.sum())
-        unsel = lam[~sel]
-        if unsel.size:
-            omega = max(omega, float(unsel.max()))
-        if sel.any():
-            d = pp.rows(W[:, sel])[::-1]       # largest eigenvalue first
-            c = pp.face_part(d, itf)
-            rows.setdefault(fg, []).extend(c / np.abs(c).max(axis=1, keepdims=True))
-            if edges:
-                scale = np.abs(d).max(axis=1)
-                for gi, ce in pp.edge_parts(d, itf):
-                    for q in range(ce.shape[0]):
-                        mx = np.abs(ce[q]).max()
-                        if mx > EDGE_DROP * scale[q]:
-                            rows.setdefault(gi, []).append(ce[q] / mx)
+    for fg, r in zip(faces, res):
+        lams[fg] = r["lam"]
+        kcount[fg] = r["k"]
+        if r["unsel_max"] is not None:
+            omega = max(omega, r["unsel_max"])
+        for gi, row in r["rows"]:
+            rows.setdefault(gi, []).append(row)
     rows = {g: np.array(r) for g, r in rows.items()}
     return dict(rows=rows, omega=omega, k=kcount, lam=lams)

@@ -34,28 +34,36 @@ class OracleBDDC:
         return self.M.apply(r)
 
     def solve(self, f=None, rtol=1e-8, maxit=1000):
-        """PCG on the reduced problem (eq. (reduced-problem)).  Vectors are
-        global, but every residual is kept exactly zero in the interiors, as
-        the Remark after Lemma 1 states it is: the interior rows of R^T A R u
-        are satisfied by the interior Dirichlet solves of the start and by the
-        discrete harmonic search directions, so they are not iterated on."""
+        """PCG on the reduced problem with M_BDDC of Algorithm 2 (see
+        ``reduced_pcg``)."""
         if f is None:
             f = self.prob.f
-        t0 = time.perf_counter()
-        interior = np.flatnonzero(self.itf.mult == 1)
-        u0 = self.M.harm.interior_solve(f)
-        fr = f.copy()
-        fr[interior] = 0.0
-
-        def Aop(v):
-            q = self.K @ v
-            q[interior] = 0.0
-            return q
-
-        out = pcg(Aop, fr, self.M.apply, u0, rtol=rtol, maxit=maxit)
-        out["t_solve"] = time.perf_counter() - t0
+        out = reduced_pcg(self.itf, self.K, self.M.harm, self.M.apply, f, rtol, maxit)
         out["Nc"] = self.cons.Nc()
         return out
+
+
+def reduced_pcg(itf, K, harm, M_apply, f, rtol=1e-8, maxit=1000):
+    """PCG on the reduced problem (eq. (reduced-problem)).  Vectors are
+    global, but every residual is kept exactly zero in the interiors, as the
+    Remark after Lemma 1 states it is: the interior rows of R^T A R u are
+    satisfied by the interior Dirichlet solves of the start and by the discrete
+    harmonic search directions, so they are not iterated on.  K is the
+    assembled R^T A R, harm the interior solves, M_apply the preconditioner."""
+    t0 = time.perf_counter()
+    interior = np.flatnonzero(itf.mult == 1)
+    u0 = harm.interior_solve(f)
+    fr = f.copy()
+    fr[interior] = 0.0
+
+    def Aop(v):
+        q = K @ v
+        q[interior] = 0.0
+        return q
+
+    out = pcg(Aop, fr, M_apply, u0, rtol=rtol, maxit=maxit)
+    out["t_solve"] = time.perf_counter() - t0
+    return out
 
 
 def direct_solve(prob):
