@@ -133,10 +133,17 @@ typedef struct {
 
 typedef struct {
   int iters;                 /* PCG iterations (operator applications) */
-  int converged;
-  double relres;             /* ||r_k|| / ||r_0|| at exit */
+  int converged;             /* the stopping test ||r_k|| <= rtol ||r_0|| was met */
+  double relres;             /* ||r_k|| / ||r_0|| at exit (PCG's own residual) */
   double kappa, lmin, lmax;  /* Lanczos estimates from the CG coefficients */
   double seconds;            /* wall time of the call */
+  double true_relres;        /* ||R^T f - R^T A R u|| / ||r_0|| of the returned u, from
+                                the substructure matrices A_i (eq. (assembled)) */
+  int refinements;           /* correction solves run because true_relres exceeded
+                                rtol after the main solve (at most 3; each solves
+                                A d = f - A u with the same preconditioner) */
+  int refine_iters;          /* PCG iterations of those correction solves (not in
+                                iters, which counts the main solve only) */
 } bddc_pcg_info;
 
 typedef struct {
@@ -336,7 +343,9 @@ bddc_status bddc_server_create(const bddc_server_options *opt, bddc_server **out
    numbering of the mesh's non-Dirichlet dofs (ascending node, then
    component); its length n_glob must match the mesh (checked at setup: a
    mismatch fails the request).  params may be NULL (defaults of
-   bddc_pcg_solve).  *id receives the request id. */
+   bddc_pcg_solve).  *id receives the request id.  Returns BDDC_ERR_OOM,
+   queueing nothing, when the request's footprint estimate alone exceeds the
+   admission budget (it could never be admitted). */
 bddc_status bddc_server_submit(bddc_server *srv, const bddc_mesh *mesh, const bddc_partition *part,
                                const bddc_constraints *cons, double tau, const double *f,
                                int64_t n_glob, const bddc_pcg_params *params, int64_t *id);

@@ -66,7 +66,8 @@ class bddc_pcg_params(C.Structure):
 class bddc_pcg_info(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("relres", C.c_double),
                 ("kappa", C.c_double), ("lmin", C.c_double), ("lmax", C.c_double),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("true_relres", C.c_double), ("refinements", C.c_int),
+                ("refine_iters", C.c_int)]
 
 
 class bddc_adapt_info(C.Structure):

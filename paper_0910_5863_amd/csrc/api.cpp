@@ -210,6 +210,9 @@ bddc_status bddc_pcg_solve(bddc_ctx *c, int nrhs, const double *f, int64_t ldf, 
         o.lmax = res.lmax;
         o.kappa = res.lmax / res.lmin;
         o.seconds = res.seconds;
+        o.true_relres = res.true_relres;
+        o.refinements = res.refinements;
+        o.refine_iters = res.refine_iters;
       }
       all_conv &= res.converged;
     }

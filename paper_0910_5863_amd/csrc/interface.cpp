@@ -18,6 +18,7 @@
 #include <unordered_map>
 
 #include "host.h"
+#include "solver.h"
 
 namespace bddc {
 
@@ -114,18 +115,43 @@ void classify_interface(Problem &P, bool augment) {
     }
   }
 
-  if (augment) {
-    const int need = m.kind == 0 ? 1 : 3;
-    std::map<std::pair<int, int>, std::vector<int64_t>> shared;
-    for (int64_t n = 0; n < m.n_nodes; ++n) {
-      const auto &s = ns[n];
-      if (s.size() < 2) continue;
-      for (size_t a = 0; a < s.size(); ++a)
-        for (size_t b = a + 1; b < s.size(); ++b) shared[{s[a], s[b]}].push_back(n);
+  const int need = m.kind == 0 ? 1 : 3;
+  std::map<std::pair<int, int>, std::vector<int64_t>> shared;
+  for (int64_t n = 0; n < m.n_nodes; ++n) {
+    const auto &s = ns[n];
+    if (s.size() < 2) continue;
+    for (size_t a = 0; a < s.size(); ++a)
+      for (size_t b = a + 1; b < s.size(); ++b) shared[{s[a], s[b]}].push_back(n);
+  }
+  auto pt = [&](int64_t n) {
+    return std::array<double, 3>{m.xyz[3 * n], m.xyz[3 * n + 1], m.xyz[3 * n + 2]};
+  };
+  if (!augment) {
+    // Assumption 2 (Sec. 3): the corners shared by two adjacent substructures
+    // must remove their relative rigid body motions: at least one corner
+    // (scalar) or three non-collinear corners (elasticity) in the closure of
+    // the pair's face, unless neither substructure floats (both carry
+    // Dirichlet dofs, so the pair has no rigid motion).  Without the corner
+    // augmentation a partition that breaks it is rejected here.
+    std::vector<char> fixed(m.n_sub, 0);
+    for (int64_t e = 0; e < m.n_elems; ++e)
+      for (int a = 0; a < 8 && !fixed[m.elem_sub[e]]; ++a)
+        for (int c = 0; c < dpn; ++c)
+          if (m.dirichlet[dpn * m.hex8[8 * e + a] + c]) fixed[m.elem_sub[e]] = 1;
+    for (auto &f : faces) {
+      const int i = f.first[0], j = f.first[1];
+      if (fixed[i] && fixed[j]) continue;
+      std::vector<std::array<double, 3>> cpts;
+      for (int64_t n : shared[{i, j}])
+        if (corner.count(n)) cpts.push_back(pt(n));
+      const int have = noncollinear_count(cpts);
+      if (have < need)
+        throw CornersError("face pair (" + std::to_string(i) + ", " + std::to_string(j) +
+                           ") sees " + std::to_string(have) + " independent corner(s), " +
+                           std::to_string(need) + " needed (Assumption 2); set augment_corners");
     }
-    auto pt = [&](int64_t n) {
-      return std::array<double, 3>{m.xyz[3 * n], m.xyz[3 * n + 1], m.xyz[3 * n + 2]};
-    };
+  }
+  if (augment) {
     for (auto &f : faces) {
       const auto &cl = shared[{f.first[0], f.first[1]}];
       std::vector<std::array<double, 3>> cpts;

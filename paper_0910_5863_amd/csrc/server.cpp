@@ -516,6 +516,8 @@ bddc_status bddc_server_submit(bddc_server *srv, const bddc_mesh *mesh, const bd
   r->tau = tau;
   r->n_glob = n_glob;
   r->info.footprint_bytes = footprint(*r);
+  // a request that alone exceeds the admission budget could never start
+  if (r->info.footprint_bytes > srv->opt.hbm_budget_bytes) return BDDC_ERR_OOM;
   r->info.n_glob = n_glob;
   r->key = problem_key(*r);
   {

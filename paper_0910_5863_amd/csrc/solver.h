@@ -44,6 +44,10 @@ struct PcgResult {
   int iters = 0;
   bool converged = false;
   double relres = 0, lmin = 0, lmax = 0, seconds = 0;
+  double r0 = 0;              // ||r_0||: the reduced problem's initial residual
+  double true_relres = 0;     // ||f - A u|| / ||r_0|| with the assembled A (CSR A_i)
+  int refinements = 0;        // correction solves run because true_relres > rtol
+  int refine_iters = 0;       // PCG iterations of those correction solves
   std::vector<double> alphas, betas;
   std::vector<double> history;  // ||r_k|| / ||r_0||, k = 0..iters
 };
@@ -116,6 +120,14 @@ class Solver {
   bool struct_ready = false;  // mesh / partition part of the layout is current
   void apply_global(const double *r, double *z);
   PcgResult pcg(const double *f, double *u, double rtol, int maxit);
+  // one PCG solve on the explicit Schur operator (pcg adds the true-residual
+  // check and the correction solves); abs_tol > 0 replaces rtol by
+  // abs_tol / ||r_0||
+  PcgResult pcg_once(const double *f, double *u, double rtol, int maxit, double abs_tol = 0);
+  // rt = f - A u over all free dofs with the substructure matrices A_i;
+  // returns ||rt||
+  double true_residual(const double *f, const double *u, double *rt);
+  static constexpr int kMaxRefine = 3;
   void free_all();
 
   // bytes streamed per PCG-internal preconditioner application and per
@@ -178,6 +190,7 @@ class Solver {
   DBuf d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, d_work_i, d_status;
   DBuf d_vG, d_vG2, d_vR, d_vR2, d_vP, d_vI, d_vI2, d_vc;
   DBuf d_gam_r, d_gam_z, d_gam_p, d_gam_q, d_gam_x, d_sc, d_part, d_alphas, d_betas;
+  DBuf d_true_r, d_true_d;  // global vectors: true residual and correction
   DBuf d_symv_part, d_symv_off;  // partial products of the symmetric Schur operator
   DBuf d_pcg_ctl, d_pcg_hist;  // PCG control words (stop, iterations, converged, maxit), history
   // one PCG iteration captured as a graph (rebuilt after every build); the

@@ -106,6 +106,28 @@ def test_bad_setup_arguments():
     b.close()
 
 
+def test_insufficient_corners_rejected_without_augmentation():
+    """Assumption 2 (Sec. 3): without the corner augmentation, a k-means
+    partition whose face pairs see fewer than three non-collinear corners is
+    rejected by bddc_setup with BDDC_ERR_INSUFFICIENT_CORNERS; the same
+    partition with augmentation, and a cube partition without it, are
+    accepted."""
+    # 10^3 elements in 6 k-means parts: two floating face pairs lack corners
+    km = meshgen.small_kmeans(meshgen.ELASTICITY, 10, 6, contrast=1e3)
+    b = BDDC(device=-1)
+    with pytest.raises(BddcError) as e:
+        b.setup(km, "ce", augment_corners=False)
+    assert e.value.code == 7
+    assert "Assumption 2" in str(e.value)
+    b.close()
+    b = BDDC(device=-1)
+    b.setup(km, "ce", augment_corners=True)
+    b.close()
+    b = BDDC(device=-1)
+    b.setup(meshgen.small_elasticity_layers(6, 2, contrast=1e3), "ce", augment_corners=False)
+    b.close()
+
+
 def test_binding_structs_match_the_header(tmp_path):
     """Every ctypes structure of the binding that the header defines has the
     header's size and field offsets (gcc compiles the header as C and prints
