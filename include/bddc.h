@@ -206,6 +206,22 @@ bddc_status bddc_factor(bddc_ctx *ctx);
 bddc_status bddc_apply(bddc_ctx *ctx, int nrhs, const double *r, int64_t ldr, double *z,
                        int64_t ldz);
 
+/* bddc_apply for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+   same kernels and results, but the work vectors of the application (local
+   stacks, coarse vector, front updates of the interior solves, triangular
+   solve counters) live in one static device array of 64 MiB per device
+   instead of the context's buffers, and the call allocates nothing (no
+   hipMalloc, hipFree or allocating library routine).  Arguments as
+   bddc_apply (device vectors owned by the caller; the context must be
+   factored).  The call only enqueues work on the context's stream and
+   returns before it completes.  A problem whose work vectors exceed the
+   array is rejected with BDDC_ERR_ARG and a message giving both sizes.  All
+   calls on one device share the array (each clears the part it uses first):
+   calls that overlap on one device race. */
+bddc_status bddc_apply_noalloc(bddc_ctx *ctx, int nrhs, const double *r, int64_t ldr, double *z,
+                               int64_t ldz);
+
 /* Solve R^T A R u = f by BDDC-PCG.  f, u: device, n_glob x nrhs column-major;
    each column is an independent solve.  info may be NULL, else nrhs entries. */
 bddc_status bddc_pcg_solve(bddc_ctx *ctx, int nrhs, const double *f, int64_t ldf, double *u,

@@ -104,7 +104,8 @@ class bddc_kernel_stat(C.Structure):
 
 
 SYMBOLS = ["bddc_create", "bddc_setup", "bddc_adapt", "bddc_adapt_count", "bddc_factor",
-           "bddc_apply", "bddc_pcg_solve", "bddc_get_info", "bddc_get_face_rows",
+           "bddc_apply", "bddc_apply_noalloc", "bddc_pcg_solve", "bddc_get_info",
+           "bddc_get_face_rows",
            "bddc_get_edge_rows", "bddc_get_face_eigs",
            "bddc_pcg_history", "bddc_get_substructure", "bddc_set_timing", "bddc_get_timing",
            "bddc_server_create", "bddc_server_submit", "bddc_server_wait", "bddc_server_query",
@@ -214,6 +215,10 @@ def bddc_factor(h):
 
 def bddc_apply(h, nrhs, r_ptr, ldr, z_ptr, ldz):
     _check(h, load().bddc_apply(h, nrhs, r_ptr, ldr, z_ptr, ldz))
+
+
+def bddc_apply_noalloc(h, nrhs, r_ptr, ldr, z_ptr, ldz):
+    _check(h, load().bddc_apply_noalloc(h, nrhs, r_ptr, ldr, z_ptr, ldz))
 
 
 def bddc_pcg_solve(h, nrhs, f_ptr, ldf, u_ptr, ldu, params, infos):
@@ -431,6 +436,21 @@ class BDDC:
         zt = self.torch.empty_like(rt)
         bddc_apply(self.h, rt.shape[0], C.c_void_p(rt.data_ptr()), n, C.c_void_p(zt.data_ptr()), n)
         return zt.t()
+
+    def apply_noalloc(self, r, z):
+        """bddc_apply_noalloc: z = M r into the caller's device tensor z, both
+        (n_glob, nrhs) column-major views as returned by apply() (or 1-D);
+        enqueued on the context's stream, nothing allocated by the library."""
+        nr = 1 if r.dim() == 1 else r.shape[1]
+        for t in (r, z):
+            if not t.is_cuda or t.dtype != self.torch.float64 or t.shape[0] != self.n_glob:
+                raise ValueError("r, z: float64 device tensors with n_glob rows")
+            if t.dim() == 2 and (t.stride(0) != 1 or t.shape[1] != nr):
+                raise ValueError("r, z: column-major (n_glob, nrhs) views of one shape")
+        ldr = self.n_glob if nr == 1 else r.stride(1)
+        ldz = self.n_glob if nr == 1 else z.stride(1)
+        bddc_apply_noalloc(self.h, nr, C.c_void_p(r.data_ptr()), ldr, C.c_void_p(z.data_ptr()), ldz)
+        return z
 
     def pcg_solve(self, f, rtol=1e-8, maxit=1000, raise_on_fail=True):
         ft, n = self._dev(f)

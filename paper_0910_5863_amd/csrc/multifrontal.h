@@ -80,7 +80,11 @@ class MfDevice {
   void factor(hipStream_t st, const double *val, int64_t nnz, double *S, const int64_t *offGG,
               const int *nG, int max_nG, int nsub);
   // vI <- A_II^-1 vI on the stack of interiors, every substructure
-  void solve(hipStream_t st, double *vI);
+  // interior solves in place; upd / zp: work vectors of upd_elems() and
+  // zp_elems() doubles (nullptr: the object's own)
+  void solve(hipStream_t st, double *vI, double *upd = nullptr, double *zp = nullptr);
+  int64_t upd_elems() const { return (int64_t)(d_upd_.bytes / sizeof(double)); }
+  int64_t zp_elems() const { return (int64_t)(d_zp_.bytes / sizeof(double)); }
   size_t bytes() const;
 
  private:

@@ -507,13 +507,13 @@ void MfDevice::factor(hipStream_t st, const double *val, int64_t nnz, double *S,
       }
 }
 
-void MfDevice::solve(hipStream_t st, double *vI) {
+void MfDevice::solve(hipStream_t st, double *vI, double *upd_w, double *zp_w) {
   if (!ready) throw StateError("interior elimination not set up");
   const MfSymbolic &M = sym;
   const MfFront *F = d_fronts_.as<MfFront>();
   const int *ids = d_level_ids_.as<int>();
   const double *U = d_U_.as<double>();
-  double *upd = d_upd_.as<double>();
+  double *upd = upd_w ? upd_w : d_upd_.as<double>();
   // bytes of the pivot (triangle) and boundary (F12) parts of a depth
   auto tri_bytes = [&](int d) {
     double by = 0;
@@ -532,7 +532,7 @@ void MfDevice::solve(hipStream_t st, double *vI) {
     return by;
   };
   const bool tm = launch_timing() != nullptr;
-  double *zp = d_zp_.as<double>();
+  double *zp = zp_w ? zp_w : d_zp_.as<double>();
   for (int d = M.max_depth; d >= 1; --d) {
     const int nf = (int)M.levels[d].size();
     if (nf == 0) continue;

@@ -93,6 +93,17 @@ class Timer : public LaunchTiming {
   void record_end(hipStream_t st);
 };
 
+// Work vectors of one preconditioner application: by default the solver's
+// own buffers (own_work); the allocation-free entry point carves them out of
+// a static device array instead (carve_work).
+struct ApplyWork {
+  double *vI = nullptr, *vG = nullptr, *vG2 = nullptr, *gr = nullptr, *gz = nullptr;
+  double *vR = nullptr, *vR2 = nullptr, *vP = nullptr, *vc = nullptr, *scr = nullptr;
+  float *vR32 = nullptr;
+  double *mf_upd = nullptr, *mf_zp = nullptr;
+  int *trsv_work = nullptr, *err = nullptr;
+};
+
 class Solver {
  public:
   static constexpr int kMaxRhs = 1;
@@ -119,6 +130,12 @@ class Solver {
   bool schur_ready = false;
   bool struct_ready = false;  // mesh / partition part of the layout is current
   void apply_global(const double *r, double *z);
+  void apply_global(const double *r, double *z, const ApplyWork &w);
+  ApplyWork own_work();
+  // bytes of a work set for apply_global (segments 256-byte aligned) and the
+  // set laid out from base (device memory of at least work_bytes())
+  size_t work_bytes() const;
+  ApplyWork carve_work(void *base) const;
   PcgResult pcg(const double *f, double *u, double rtol, int maxit);
   // one PCG solve on the explicit Schur operator (pcg adds the true-residual
   // check and the correction solves); abs_tol > 0 replaces rtol by
@@ -137,21 +154,21 @@ class Solver {
 
   // internals (public for the adaptive module)
   void apply_gamma(const double *r, double *z);
-  void apply_gamma_condensed(const double *r, const double *vG_cond, double *z);
-  void apply_local(double *b, double *z);
-  void apply_T_vec(double *x);
-  void apply_Tt_vec(double *b);
+  void apply_gamma_condensed(const double *r, const double *vG_cond, double *z, const ApplyWork &w);
+  void apply_local(double *b, double *z, const ApplyWork &w);
+  void apply_T_vec(double *x, double *scr);
+  void apply_Tt_vec(double *b, double *scr);
   void schur_gamma(const double *p, double *q);
-  void harmonic_extension(const double *zg, double *z);
-  void interior_solve(double *vI);
+  void harmonic_extension(const double *zg, double *z, const ApplyWork &w);
+  void interior_solve(double *vI, const ApplyWork *w = nullptr);
   void dot(const double *a, const double *b, int64_t n, double *out);
   void scatter_gamma(const double *zg, double *z);
   void scatter_interior(const double *vI, double *z);
   void scatter64(const double *src, const int64_t *idx, int64_t n, double *dst);
   void trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
-            const DBuf &dinv_off, double *x, bool upper);
+            const DBuf &dinv_off, double *x, bool upper, const ApplyWork &w);
   void trsv32(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
-              const DBuf &dinv_off, float *x, bool upper);
+              const DBuf &dinv_off, float *x, bool upper, const ApplyWork &w);
   void release(DBuf &b);
   std::vector<DBuf *> all_buffers();
   std::vector<DBuf *> struct_buffers();

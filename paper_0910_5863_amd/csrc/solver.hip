@@ -1304,46 +1304,116 @@ void Solver::check_status(bool all) {
 // preconditioner and PCG (one right-hand side per call of the internals)
 
 void Solver::trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
-                  const DBuf &dinv_off, double *x, bool upper) {
+                  const DBuf &dinv_off, double *x, bool upper, const ApplyWork &w) {
   HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), plan, upper,
-                              dinv.as<double>(), dinv_off.as<int64_t>(),
-                              d_work_i.as<int>(), d_status.as<int>() + 2 * L.nsub + 1));
+                              dinv.as<double>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
+}
+void Solver::trsv32(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
+                    const DBuf &dinv_off, float *x, bool upper, const ApplyWork &w) {
+  HIPCHK(trsv_blocked<float>(stream, A.as<float>(), x, desc.as<MatDesc>(), plan, upper,
+                             dinv.as<float>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
 }
 
-void Solver::trsv32(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
-                    const DBuf &dinv_off, float *x, bool upper) {
-  HIPCHK(trsv_blocked<float>(stream, A.as<float>(), x, desc.as<MatDesc>(), plan, upper,
-                             dinv.as<float>(), dinv_off.as<int64_t>(), d_work_i.as<int>(),
-                             d_status.as<int>() + 2 * L.nsub + 1));
+ApplyWork Solver::own_work() {
+  ApplyWork w;
+  w.vI = d_vI.as<double>();
+  w.vG = d_vG.as<double>();
+  w.vG2 = d_vG2.as<double>();
+  w.gr = d_gam_r.as<double>();
+  w.gz = d_gam_z.as<double>();
+  w.vR = d_vR.as<double>();
+  w.vR2 = d_vR2.as<double>();
+  w.vP = d_vP.as<double>();
+  w.vc = d_vc.as<double>();
+  w.scr = d_scr.as<double>();
+  w.vR32 = d_vR32.as<float>();
+  w.mf_upd = nullptr;  // the interior elimination's own vectors
+  w.mf_zp = nullptr;
+  w.trsv_work = d_work_i.as<int>();
+  w.err = d_status.as<int>() + 2 * L.nsub + 1;
+  return w;
+}
+
+namespace {
+constexpr int kWorkSegments = 15;
+// segment sizes of a work set in the order of ApplyWork's members, in bytes,
+// each rounded up to 256
+std::vector<size_t> work_segments(const Layout &L, int64_t scr, int64_t trsv_ints, int64_t upd,
+                                  int64_t zp, bool fp32) {
+  auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) / 256 * 256; };
+  const size_t d = sizeof(double);
+  return {al(d * L.sumI), al(d * L.sumG), al(d * L.sumG), al(d * L.n_gamma), al(d * L.n_gamma),
+          al(d * L.sumR), al(d * L.sumR), al(d * L.sumP), al(d * L.n_coarse), al(d * scr),
+          al(fp32 ? sizeof(float) * L.sumR : 0), al(d * upd), al(d * zp),
+          al(sizeof(int) * trsv_ints), al(sizeof(int))};
+}
+}  // namespace
+
+size_t Solver::work_bytes() const {
+  size_t t = 0;
+  for (size_t b : work_segments(L, (int64_t)(d_scr.bytes / sizeof(double)),
+                                (int64_t)(d_work_i.bytes / sizeof(int)), mf.upd_elems(),
+                                mf.zp_elems(), factor_precision == 32))
+    t += b;
+  return t;
+}
+
+ApplyWork Solver::carve_work(void *base) const {
+  const auto seg = work_segments(L, (int64_t)(d_scr.bytes / sizeof(double)),
+                                 (int64_t)(d_work_i.bytes / sizeof(int)), mf.upd_elems(),
+                                 mf.zp_elems(), factor_precision == 32);
+  char *p = (char *)base;
+  void *q[kWorkSegments];
+  for (int k = 0; k < kWorkSegments; ++k) {
+    q[k] = p;
+    p += seg[k];
+  }
+  ApplyWork w;
+  w.vI = (double *)q[0];
+  w.vG = (double *)q[1];
+  w.vG2 = (double *)q[2];
+  w.gr = (double *)q[3];
+  w.gz = (double *)q[4];
+  w.vR = (double *)q[5];
+  w.vR2 = (double *)q[6];
+  w.vP = (double *)q[7];
+  w.vc = (double *)q[8];
+  w.scr = (double *)q[9];
+  w.vR32 = (float *)q[10];
+  w.mf_upd = (double *)q[11];
+  w.mf_zp = (double *)q[12];
+  w.trsv_work = (int *)q[13];
+  w.err = (int *)q[14];
+  return w;
 }
 
 // interface residual (gamma vector, nrhs = 1) -> z on gamma.  Interior values
 // are not produced here.
 void Solver::apply_gamma(const double *r, double *z) {
-  double *vG = d_vG.as<double>();
+  const ApplyWork w = own_work();
   gather_kernel<<<nblocks(L.sumG), TPB, 0, stream>>>(r, L.n_gamma, d_ifc_gamma.as<int64_t>(),
-                                                     d_ifc_delta.as<double>(), vG, L.sumG, L.sumG, 1);
+                                                     d_ifc_delta.as<double>(), w.vG, L.sumG, L.sumG, 1);
   HIPCHK(hipGetLastError());
-  apply_local(vG, z);
+  apply_local(w.vG, z, w);
 }
 
-void Solver::apply_Tt_vec(double *b) {
+void Solver::apply_Tt_vec(double *b, double *scr) {
   if (!n_gx) return;
   vec_pivots_kernel<<<nblocks(n_gx), TPB, 0, stream>>>(b, d_gx.as<GlobXf>(), n_gx, d_pos.as<int>(),
-                                                       d_scr.as<double>());
+                                                       scr);
   apply_Tt_kernel<<<nblocks((int64_t)n_gx * 64), TPB, 0, stream>>>(
-      b, d_gx.as<GlobXf>(), n_gx, d_wmat.as<double>(), d_pos.as<int>(), d_scr.as<double>());
+      b, d_gx.as<GlobXf>(), n_gx, d_wmat.as<double>(), d_pos.as<int>(), scr);
   HIPCHK(hipGetLastError());
 }
 
-void Solver::apply_T_vec(double *x) {
+void Solver::apply_T_vec(double *x, double *scr) {
   if (!n_gx) return;
   apply_T_dots_kernel<<<nblocks((int64_t)n_gk * 64), TPB, 0, stream>>>(
       x, d_gx.as<GlobXf>(), d_gk_glob.as<int>(), d_gk_k.as<int>(), n_gk, d_trow.as<double>(),
-      d_pos.as<int>(), d_scr.as<double>());
+      d_pos.as<int>(), scr);
   apply_T_store_kernel<<<nblocks(n_gk), TPB, 0, stream>>>(x, d_gx.as<GlobXf>(), d_gk_glob.as<int>(),
                                                           d_gk_k.as<int>(), n_gk, d_pos.as<int>(),
-                                                          d_scr.as<double>());
+                                                          scr);
   HIPCHK(hipGetLastError());
 }
 
@@ -1384,23 +1454,25 @@ void Solver::dot(const double *a, const double *b, int64_t n, double *out) {
 }
 
 // interior Dirichlet solve in every substructure: vI <- A_II^-1 vI
-void Solver::interior_solve(double *vI) {
-  mf.solve(stream, vI);
+void Solver::interior_solve(double *vI, const ApplyWork *w) {
+  mf.solve(stream, vI, w ? w->mf_upd : nullptr, w ? w->mf_zp : nullptr);
 }
 
 // z = M r for global vectors (Algorithm 2): the interior part of r enters
 // through E^T, i.e. the substructure right-hand side has b_I = r_I, which is
 // condensed onto the interface before the interface solve; the result is
 // extended harmonically.
-void Solver::apply_global(const double *r, double *z) {
+void Solver::apply_global(const double *r, double *z) { apply_global(r, z, own_work()); }
+
+void Solver::apply_global(const double *r, double *z, const ApplyWork &w) {
   if (!factored) throw StateError("bddc_apply before bddc_factor");
   hipStream_t st = stream;
-  double *vI = d_vI.as<double>(), *vG = d_vG.as<double>();
-  double *gr = d_gam_r.as<double>(), *gz = d_gam_z.as<double>();
+  double *vI = w.vI, *vG = w.vG;
+  double *gr = w.gr, *gz = w.gz;
   // condensation of the interior right-hand side: r_G - sum A_GI A_II^-1 r_I
   gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(r, L.n_glob, d_int_gdof.as<int64_t>(), nullptr, vI,
                                                  L.sumI, L.sumI, 1);
-  interior_solve(vI);
+  interior_solve(vI, &w);
   spmv_coupling_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
       d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
       d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(), vI,
@@ -1411,31 +1483,32 @@ void Solver::apply_global(const double *r, double *z) {
   gather_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(r, L.n_glob, d_gamma_gdof.as<int64_t>(), nullptr, gr,
                                                     L.n_gamma, L.n_gamma, 1);
   HIPCHK(hipGetLastError());
-  apply_gamma_condensed(gr, vG, gz);
-  harmonic_extension(gz, z);
+  apply_gamma_condensed(gr, vG, gz, w);
+  harmonic_extension(gz, z, w);
 }
 
 // as apply_gamma, but the local right-hand sides receive the condensed
 // interior contribution -A_GI A_II^-1 r_I (already in vG_cond, unweighted)
-void Solver::apply_gamma_condensed(const double *r, const double *vG_cond, double *z) {
+void Solver::apply_gamma_condensed(const double *r, const double *vG_cond, double *z,
+                                   const ApplyWork &w) {
   hipStream_t st = stream;
   // vG2 = delta . R_i r - vG_cond
-  double *vG2 = d_vG2.as<double>();
+  double *vG2 = w.vG2;
   gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(r, L.n_gamma, d_ifc_gamma.as<int64_t>(),
                                                  d_ifc_delta.as<double>(), vG2, L.sumG, L.sumG, 1);
   axpby_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(vG2, vG_cond, -1.0, 1.0, L.sumG);
   HIPCHK(hipGetLastError());
-  apply_local(vG2, z);
+  apply_local(vG2, z, w);
 }
 
 // everything of apply_gamma after the weighted gather; b (sum-nG stack) is
 // consumed
-void Solver::apply_local(double *b, double *z) {
+void Solver::apply_local(double *b, double *z, const ApplyWork &w) {
   hipStream_t st = stream;
   const int ns = L.nsub;
-  double *vG = b, *vR = d_vR.as<double>(), *vR2 = d_vR2.as<double>();
-  double *vP = d_vP.as<double>(), *vc = d_vc.as<double>();
-  apply_Tt_vec(vG);
+  double *vG = b, *vR = w.vR, *vR2 = w.vR2;
+  double *vP = w.vP, *vc = w.vc;
+  apply_Tt_vec(vG, w.scr);
   gather32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vG, L.sumG, d_rabs.as<int>(), vR, L.sumR, L.sumR, 1);
   gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vG, L.sumG, d_pabs.as<int>(), vP, L.sumP, L.sumP, 1);
   HIPCHK(hipGetLastError());
@@ -1448,23 +1521,23 @@ void Solver::apply_local(double *b, double *z) {
   copy_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vR2, vR, L.sumR);
   if (factor_precision == 32) {
     // K_rr solves in FP32; the vector enters and leaves in FP64
-    float *x32 = d_vR32.as<float>();
+    float *x32 = w.vR32;
     convert_kernel<double, float><<<nblocks(L.sumR), TPB, 0, st>>>(vR2, x32, L.sumR, 1.0);
     HIPCHK(hipGetLastError());
     timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 8.0 * L.sumR, (double)L.sRR);
-    trsv32(plan_rr, d_Lrr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, false);
+    trsv32(plan_rr, d_Lrr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, false, w);
     timer.end(st);
     timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 8.0 * L.sumR, (double)L.sRR);
-    trsv32(plan_rr, d_Urr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, true);
+    trsv32(plan_rr, d_Urr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, true, w);
     timer.end(st);
     convert_kernel<float, double><<<nblocks(L.sumR), TPB, 0, st>>>(x32, vR2, L.sumR, 1.0);
     HIPCHK(hipGetLastError());
   } else {
     timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
-    trsv(plan_rr, d_Lrr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, false);
+    trsv(plan_rr, d_Lrr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, false, w);
     timer.end(st);
     timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
-    trsv(plan_rr, d_Urr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, true);
+    trsv(plan_rr, d_Urr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, true, w);
     timer.end(st);
   }
   if (L.n_coarse > 0) {
@@ -1472,8 +1545,8 @@ void Solver::apply_local(double *b, double *z) {
                                                               d_c_copies.as<int64_t>(), nullptr, vc,
                                                               L.n_coarse, L.n_coarse, 1, 1.0, 0.0);
     timer.begin(st, "trsv_coarse", 8.0 * (double)L.n_coarse * L.n_coarse, 2.0 * L.n_coarse * L.n_coarse);
-    trsv(plan_c, d_Lc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, false);
-    trsv(plan_c, d_Uc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, true);
+    trsv(plan_c, d_Lc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, false, w);
+    trsv(plan_c, d_Uc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, true, w);
     timer.end(st);
     gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vc, L.n_coarse, d_pcid.as<int>(), vP, L.sumP,
                                                      L.sumP, 1);
@@ -1486,7 +1559,7 @@ void Solver::apply_local(double *b, double *z) {
   }
   scatter32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vR2, L.sumR, d_rabs.as<int>(), vG, L.sumG, L.sumR, 1);
   scatter32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vP, L.sumP, d_pabs.as<int>(), vG, L.sumG, L.sumP, 1);
-  apply_T_vec(vG);
+  apply_T_vec(vG, w.scr);
   reduce_copies_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(vG, L.sumG, d_gamma_ptr.as<int>(),
                                                            d_gamma_copies.as<int64_t>(),
                                                            d_ifc_delta.as<double>(), z, L.n_gamma,
@@ -1495,9 +1568,9 @@ void Solver::apply_local(double *b, double *z) {
 }
 
 // global z from interface values zg: z_G = zg, z_I = -A_II^-1 A_IG zg
-void Solver::harmonic_extension(const double *zg, double *z) {
+void Solver::harmonic_extension(const double *zg, double *z, const ApplyWork &w) {
   hipStream_t st = stream;
-  double *vI = d_vI.as<double>(), *vG = d_vG.as<double>();
+  double *vI = w.vI, *vG = w.vG;
   scatter_gamma(zg, z);
   gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(zg, L.n_gamma, d_ifc_gamma.as<int64_t>(), nullptr, vG,
                                                  L.sumG, L.sumG, 1);
@@ -1506,7 +1579,7 @@ void Solver::harmonic_extension(const double *zg, double *z) {
       d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(),
       nullptr, vG, vI, nullptr, 1, 1, L.sumI, L.sumG);
   HIPCHK(hipGetLastError());
-  interior_solve(vI);
+  interior_solve(vI, &w);
   axpby_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(vI, vI, 0.0, -1.0, L.sumI);
   scatter_interior(vI, z);
 }
