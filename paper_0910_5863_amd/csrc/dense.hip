@@ -87,8 +87,8 @@ __device__ __forceinline__ bool xcd_remap(int nwg, int tiles_per_entry, int batc
 // that no LDS array is reached from two kernels (such an array is addressed
 // through a per-kernel lookup table, which costs registers).
 // rmap / cmap (optional): C's row i is row rmap[i] of the storage, column j
-// is column cmap[j].
-template <class T, bool TA, bool TB, int MT, int NT, int KS = 1, int TAG = 0>
+// is column cmap[j].  LW: only entries with row >= column are written.
+template <class T, bool TA, bool TB, int MT, int NT, int KS = 1, int TAG = 0, bool LW = false>
 __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int lda, int ldb,
                           int ldc, T alpha, T beta, int m0, int n0, const int *rmap = nullptr,
                           const int *cmap = nullptr) {
@@ -215,7 +215,7 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
       for (int it = 0; it < MT * 4; ++it) {
         const int i = lane + 64 * it, r = i % (16 * MT), c = i / (16 * MT);
         const int row = r0 + r, col = c0 + c;
-        if (row < M && col < N) {
+        if (row < M && col < N && (!LW || row >= col)) {
           T *cp = &C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc];
           const T v = stg[r + c * SR];
           *cp = (beta == T(0)) ? v : v + beta * (*cp);
@@ -233,7 +233,7 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
         for (int j = 0; j < 4; ++j) {
           const int row = m0 + wr * 16 * MT + 16 * x + Mfma<T>::row(lane, j);
           const int col = n0 + wc * 16 * NT + 16 * y + (lane & 15);
-          if (row < M && col < N) {
+          if (row < M && col < N && (!LW || row >= col)) {
             T *c = &C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc];
             const T v = alpha * acc[x][y][j];
             *c = (beta == T(0)) ? v : v + beta * (*c);
@@ -279,23 +279,57 @@ __global__ __launch_bounds__(256) void gemm_scatter_kernel(const T *A, const T *
 
 // --- Cholesky -------------------------------------------------------------
 
-// Left-looking update of block column k: A[kb:, kb:kb+w] -= A[kb:, :kb] A[kb:kb+w, :kb]^T
+// Update of block column k by the columns of its panel to its left:
+// A[kb:, kb:kb+w] -= A[kb:, c0:kb] A[kb:kb+w, c0:kb]^T with c0 = k0 NB (the
+// panel's first column; the columns before it were applied by the panel
+// updates, chol_syrk_kernel).
 // MT = 4, KS = 1: 128-row tiles; MT = 2, KS = 2: 64-row tiles with two
-// groups of waves splitting K (for launches with few tiles and long K)
+// groups of waves splitting K (for launches with few tiles)
 template <class T, int MT, int KS>
 __global__ __launch_bounds__(256 * KS) void chol_update_kernel(T *pool, const MatDesc *desc, int k,
-                                                               int tm, int batch) {
+                                                               int k0, int tm, int batch) {
   constexpr int TM = 32 * MT;
   int e, t;
   if (!xcd_remap(gridDim.x, tm, batch, e, t)) return;
   const MatDesc d = desc[e];
-  const int kb = k * NB;
-  if (kb >= d.n || k == 0) return;
-  const int M = d.n - kb, N = min(NB, d.n - kb), K = kb;
+  const int kb = k * NB, c0 = k0 * NB;
+  if (kb >= d.n || k <= k0) return;
+  const int M = d.n - kb, N = min(NB, d.n - kb), K = kb - c0;
   if (t * TM >= M) return;
   T *A = pool + d.a_off;
-  gemm_tile<T, false, true, MT, 2, KS, 1>(A + kb, A + kb, A + kb + (int64_t)kb * d.lda, M, N, K,
-                                          d.lda, d.lda, d.lda, T(-1), T(1), t * TM, 0);
+  const T *P = A + kb + (int64_t)c0 * d.lda;
+  gemm_tile<T, false, true, MT, 2, KS, 1>(P, P, A + kb + (int64_t)kb * d.lda, M, N, K, d.lda, d.lda,
+                                          d.lda, T(-1), T(1), t * TM, 0);
+}
+
+// tile (ti, tj), tj <= ti, of the lower triangle from a linear index
+__device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
+  int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  ti = i;
+  tj = t - i * (i + 1) / 2;
+}
+
+// Trailing update after a factored panel of columns [p0, p1):
+// A[p1:, p1:] -= L[p1:, p0:p1] L[p1:, p0:p1]^T, lower triangle only, 128 x 128
+// tiles (tile pairs tj <= ti, tm tile rows for the largest entry); the
+// diagonal tiles write only their lower part.
+template <class T>
+__global__ __launch_bounds__(256) void chol_syrk_kernel(T *pool, const MatDesc *desc, int p0, int p1,
+                                                        int tm, int batch) {
+  int e, t;
+  if (!xcd_remap(gridDim.x, tm * (tm + 1) / 2, batch, e, t)) return;
+  const MatDesc d = desc[e];
+  if (p1 >= d.n) return;
+  int ti, tj;
+  lower_tile(t, ti, tj);
+  const int M = d.n - p1;
+  if (ti * 128 >= M) return;
+  T *A = pool + d.a_off;
+  const T *P = A + p1 + (int64_t)p0 * d.lda;
+  gemm_tile<T, false, true, 4, 4, 1, 6, true>(P, P, A + p1 + (int64_t)p1 * d.lda, M, M, p1 - p0,
+                                              d.lda, d.lda, d.lda, T(-1), T(1), ti * 128, tj * 128);
 }
 
 // Factor the diagonal block of block column k in LDS, in place, and write
@@ -406,14 +440,16 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc 
 
 // --- multi-RHS triangular solves -------------------------------------------
 
-// forward: B[kb:kb+w, :] -= L[kb:kb+w, :kb] B[:kb, :]
-// backward: B[kb:kb+w, :] -= L[kb+w:n, kb:kb+w]^T B[kb+w:n, :]
+// Within a panel of block rows [p0, p1) (columns of L):
+// forward: B[kb:kb+w, :] -= L[kb:kb+w, p0:kb] B[p0:kb, :]
+// backward: B[kb:kb+w, :] -= L[kb+w:q1, kb:kb+w]^T B[kb+w:q1, :], q1 = min(p1, n)
+// (the rows outside the panel were applied by trsm_gemm_kernel).
 // NT = 4, KS = 1: 128-column tiles; NT = 1, KS = 2: 32-column tiles with two
-// groups of waves splitting K (few right-hand sides, long K)
+// groups of waves splitting K (few right-hand sides)
 template <class T, bool BWD, int NT, int KS>
 __global__ __launch_bounds__(256 * KS) void trsm_update_kernel(const T *apool, T *bpool,
-                                                               const MatDesc *desc, int k, int tn,
-                                                               int batch) {
+                                                               const MatDesc *desc, int k, int p0,
+                                                               int p1, int tn, int batch) {
   constexpr int TN = 32 * NT;
   int e, t;
   if (!xcd_remap(gridDim.x, tn, batch, e, t)) return;
@@ -425,11 +461,11 @@ __global__ __launch_bounds__(256 * KS) void trsm_update_kernel(const T *apool, T
   const T *L = apool + d.a_off;
   T *B = bpool + d.b_off;
   if (!BWD) {
-    if (kb == 0) return;
-    gemm_tile<T, false, false, 2, NT, KS, 3>(L + kb, B, B + kb, w, d.nrhs, kb, d.lda, d.ldb, d.ldb,
-                                             T(-1), T(1), 0, t * TN);
+    if (kb <= p0) return;
+    gemm_tile<T, false, false, 2, NT, KS, 3>(L + kb + (int64_t)p0 * d.lda, B + p0, B + kb, w, d.nrhs,
+                                             kb - p0, d.lda, d.ldb, d.ldb, T(-1), T(1), 0, t * TN);
   } else {
-    const int K = d.n - kb - w;
+    const int K = min(p1, d.n) - kb - w;
     if (K <= 0) return;
     gemm_tile<T, true, false, 2, NT, KS, 3>(L + (kb + w) + (int64_t)kb * d.lda, B + kb + w, B + kb,
                                             w, d.nrhs, K, d.lda, d.ldb, d.ldb, T(-1), T(1), 0,
@@ -456,6 +492,36 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool
   T *B = bpool + d.b_off + kb;
   const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
   gemm_tile<T, BWD, false, 2, 2, 1, 4>(Di, B, B, w, d.nrhs, w, NB, d.ldb, d.ldb, T(1), T(0), 0, c0);
+}
+
+// Update of the rows outside a solved panel of block rows [p0, p1):
+// forward: B[p1:n, :] -= L[p1:n, p0:p1] B[p0:p1, :]
+// backward: B[0:p0, :] -= L[p0:q1, 0:p0]^T B[p0:q1, :], q1 = min(p1, n)
+// 128-row tiles (tm for the largest entry) by 32 NT-column tiles (tn).
+template <class T, bool BWD, int NT>
+__global__ __launch_bounds__(256) void trsm_gemm_kernel(const T *apool, T *bpool, const MatDesc *desc,
+                                                        int p0, int p1, int tm, int tn, int batch) {
+  constexpr int TN = 32 * NT;
+  int e, t;
+  if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
+  const MatDesc d = desc[e];
+  const int ti = t % tm, tj = t / tm;
+  if (tj * TN >= d.nrhs) return;
+  const T *L = apool + d.a_off;
+  T *B = bpool + d.b_off;
+  if (!BWD) {
+    if (p1 >= d.n) return;
+    const int M = d.n - p1;
+    if (ti * 128 >= M) return;
+    gemm_tile<T, false, false, 4, NT, 1, 7>(L + p1 + (int64_t)p0 * d.lda, B + p0, B + p1, M, d.nrhs,
+                                            p1 - p0, d.lda, d.ldb, d.ldb, T(-1), T(1), ti * 128,
+                                            tj * TN);
+  } else {
+    const int q1 = min(p1, d.n);
+    if (p0 >= q1 || ti * 128 >= p0) return;
+    gemm_tile<T, true, false, 4, NT, 1, 7>(L + p0, B + p0, B, p0, d.nrhs, q1 - p0, d.lda, d.ldb,
+                                           d.ldb, T(-1), T(1), ti * 128, tj * TN);
+  }
 }
 
 // Upper triangle <- lower triangle, by 32 x 32 tiles through LDS so that
@@ -948,6 +1014,14 @@ hipError_t DenseOps<T>::gemm_scatter(hipStream_t st, const T *A, const T *B, T *
   return hipGetLastError();
 }
 
+// Panels of PB block columns: within a panel each block column is updated
+// by the panel's columns to its left (chol_update_kernel, short K), its
+// diagonal block factored and inverted (chol_diag_kernel) and the rows below
+// solved (chol_panel_kernel); then the whole trailing matrix is updated by
+// the panel at once (chol_syrk_kernel, 128 x 128 tiles, K = PB NB), so most
+// flops run as large tile products with many work-groups.
+constexpr int PB = 4;
+
 template <class T>
 hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
                               const MatDesc *h_desc, int batch, int *status, T *dinv,
@@ -957,49 +1031,72 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
   if (maxn == 0) return hipSuccess;
   const int nblk = (maxn + NB - 1) / NB;
   const bool timing = launch_timing() != nullptr;
-  for (int k = 0; k < nblk; ++k) {
-    const int tm = nblk - k;  // row blocks of block column k (for the largest entry)
-    const int tu = (maxn - k * NB + 127) / 128;  // 128-row update tiles
-    // algorithmic work of block column k over the batch: the update of the
-    // column below the diagonal by the k*NB columns to its left, the
-    // factorization of the diagonal block, and the panel solve under it
-    double fu = 0, bu = 0, fd = 0, bd = 0, fp = 0, bp = 0;
-    if (timing)
-      for (int e = 0; e < batch; ++e) {
-        const double nb = blk(h_desc[e].n, k);
-        if (nb == 0) continue;
-        const double m = h_desc[e].n - (double)k * NB, kk = (double)k * NB, below = m - nb;
-        fu += 2.0 * (m * nb - 0.5 * nb * (nb - 1)) * kk;
-        bu += sizeof(T) * (m * kk + nb * kk + 2.0 * m * nb);
-        fd += nb * nb * nb / 3.0;
-        bd += sizeof(T) * nb * nb;
-        fp += below * nb * nb;
-        bp += sizeof(T) * (2.0 * below * nb + 0.5 * nb * nb);
+  for (int k0 = 0; k0 < nblk; k0 += PB) {
+    const int k1 = std::min(nblk, k0 + PB);
+    for (int k = k0; k < k1; ++k) {
+      const int tm = nblk - k;  // row blocks of block column k (for the largest entry)
+      const int tu = (maxn - k * NB + 127) / 128;  // 128-row update tiles
+      // algorithmic work of block column k over the batch: the update of the
+      // column below the diagonal by the panel's columns to its left, the
+      // factorization of the diagonal block, and the panel solve under it
+      double fu = 0, bu = 0, fd = 0, bd = 0, fp = 0, bp = 0;
+      if (timing)
+        for (int e = 0; e < batch; ++e) {
+          const double nb = blk(h_desc[e].n, k);
+          if (nb == 0) continue;
+          const double m = h_desc[e].n - (double)k * NB, kk = (double)(k - k0) * NB, below = m - nb;
+          fu += 2.0 * (m * nb - 0.5 * nb * (nb - 1)) * kk;
+          bu += sizeof(T) * (m * kk + nb * kk + 2.0 * m * nb);
+          fd += nb * nb * nb / 3.0;
+          bd += sizeof(T) * nb * nb;
+          fp += below * nb * nb;
+          bp += sizeof(T) * (2.0 * below * nb + 0.5 * nb * nb);
+        }
+      if (k > k0) {
+        LaunchScope ls(st, "chol_update_kernel", bu, fu);
+        if (batch * tu >= 2048) {  // 128-row tiles only when they fill the device several times
+          chol_update_kernel<T, 4, 1><<<grid_round(batch * tu), 256, 0, st>>>(pool, d_desc, k, k0,
+                                                                             tu, batch);
+        } else {
+          const int t64 = (maxn - k * NB + 63) / 64;
+          chol_update_kernel<T, 2, 2><<<grid_round(batch * t64), 512, 0, st>>>(pool, d_desc, k, k0,
+                                                                               t64, batch);
+        }
       }
-    if (k > 0) {
-      LaunchScope ls(st, "chol_update_kernel", bu, fu);
-      if (batch * tu >= 2048) {  // 128-row tiles only when they fill the device several times
-        chol_update_kernel<T, 4, 1><<<grid_round(batch * tu), 256, 0, st>>>(pool, d_desc, k, tu,
-                                                                           batch);
-      } else {
-        const int t64 = (maxn - k * NB + 63) / 64;
-        chol_update_kernel<T, 2, 2><<<grid_round(batch * t64), 512, 0, st>>>(pool, d_desc, k, t64,
-                                                                             batch);
+      {
+        LaunchScope ls(st, "chol_diag_kernel", bd, fd);
+        chol_diag_kernel<T><<<batch, 256, 0, st>>>(pool, d_desc, k, status, batch, dinv, dinv_off);
+      }
+      if (tm > 1) {
+        LaunchScope ls(st, "chol_panel_kernel", bp, fp);
+        chol_panel_kernel<T><<<grid_round(batch * (tm - 1)), 256, 0, st>>>(pool, d_desc, k, tm - 1,
+                                                                            batch, dinv, dinv_off);
       }
     }
-    {
-      LaunchScope ls(st, "chol_diag_kernel", bd, fd);
-      chol_diag_kernel<T><<<batch, 256, 0, st>>>(pool, d_desc, k, status, batch, dinv, dinv_off);
-    }
-    if (tm > 1) {
-      LaunchScope ls(st, "chol_panel_kernel", bp, fp);
-      chol_panel_kernel<T><<<grid_round(batch * (tm - 1)), 256, 0, st>>>(pool, d_desc, k, tm - 1,
-                                                                          batch, dinv, dinv_off);
+    const int p0 = k0 * NB, p1 = k1 * NB;
+    if (p1 < maxn) {
+      const int tm = (maxn - p1 + 127) / 128;
+      double fs = 0, bs = 0;
+      if (timing)
+        for (int e = 0; e < batch; ++e) {
+          const double m = h_desc[e].n - (double)p1;
+          if (m <= 0) continue;
+          fs += m * (m + 1) * (p1 - p0);
+          bs += sizeof(T) * (m * (p1 - p0) + m * (m + 1));
+        }
+      LaunchScope ls(st, "chol_syrk_kernel", bs, fs);
+      chol_syrk_kernel<T><<<grid_round(batch * (tm * (tm + 1) / 2)), 256, 0, st>>>(pool, d_desc, p0,
+                                                                                  p1, tm, batch);
     }
   }
   return hipGetLastError();
 }
 
+// Panels of PB block rows, as in potrf: inside a panel, block rows are
+// updated by the panel's solved rows (trsm_update_kernel, short K) and solved
+// with the inverse diagonal blocks (trsm_diag_kernel); then every row outside
+// the panel on the unsolved side is updated by the whole panel at once
+// (trsm_gemm_kernel, 128-row tiles, K = PB NB).
 template <class T>
 hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc *d_desc,
                              const MatDesc *h_desc, int batch, bool transpose, const T *dinv,
@@ -1016,34 +1113,72 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
   const int nwg = grid_round(batch * tn), nwu = grid_round(batch * tu);
   // few tiles: 32-wide tiles, two groups of waves per tile splitting K
   const bool narrow = batch * tu < 512;
-  auto update = [&](bool bwd, int k) {
+  auto update = [&](bool bwd, int k, int p0, int p1) {
     if (!narrow) {
       if (bwd)
-        trsm_update_kernel<T, true, 4, 1><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tu, batch);
+        trsm_update_kernel<T, true, 4, 1><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1, tu,
+                                                              batch);
       else
-        trsm_update_kernel<T, false, 4, 1><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tu, batch);
+        trsm_update_kernel<T, false, 4, 1><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1, tu,
+                                                               batch);
     } else {
       // 32-column tiles: twice the work-groups of 64-column ones for few
       // right-hand sides (the same sums, in the same order)
       const int t32 = (maxr + 31) / 32;
       const int nw32 = grid_round(batch * t32);
       if (bwd)
-        trsm_update_kernel<T, true, 1, 2><<<nw32, 512, 0, st>>>(pool_a, pool_b, d_desc, k, t32, batch);
+        trsm_update_kernel<T, true, 1, 2><<<nw32, 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1,
+                                                               t32, batch);
       else
-        trsm_update_kernel<T, false, 1, 2><<<nw32, 512, 0, st>>>(pool_a, pool_b, d_desc, k, t32, batch);
+        trsm_update_kernel<T, false, 1, 2><<<nw32, 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1,
+                                                                t32, batch);
+    }
+  };
+  // rows outside the panel [p0, p1): below it (forward) or above it (backward)
+  auto panel_gemm = [&](bool bwd, int p0, int p1) {
+    const int rows = bwd ? p0 : maxn - p1;
+    if (rows <= 0) return;
+    const int tm = (rows + 127) / 128;
+    double fg = 0, bg = 0;
+    if (launch_timing())
+      for (int e = 0; e < batch; ++e) {
+        const double n = h_desc[e].n, r = h_desc[e].nrhs;
+        const double m = bwd ? (n > p0 ? p0 : 0) : std::max(0.0, n - p1);
+        const double kk = bwd ? std::max(0.0, std::min((double)p1, n) - p0) : (n > p1 ? p1 - p0 : 0);
+        if (m <= 0 || kk <= 0) continue;
+        fg += 2.0 * m * r * kk;
+        bg += sizeof(T) * (m * kk + kk * r + 2.0 * m * r);
+      }
+    LaunchScope ls(st, bwd ? "trsm_gemm_kernel<bwd>" : "trsm_gemm_kernel<fwd>", bg, fg);
+    if (maxr >= 128) {
+      const int tq = (maxr + 127) / 128;
+      const unsigned g = grid_round(batch * tm * tq);
+      if (bwd)
+        trsm_gemm_kernel<T, true, 4><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch);
+      else
+        trsm_gemm_kernel<T, false, 4><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch);
+    } else {
+      const int tq = (maxr + 63) / 64;
+      const unsigned g = grid_round(batch * tm * tq);
+      if (bwd)
+        trsm_gemm_kernel<T, true, 2><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch);
+      else
+        trsm_gemm_kernel<T, false, 2><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch);
     }
   };
   const bool timing = launch_timing() != nullptr;
   // algorithmic work at block row k: the update of the k-th block row of B
-  // by the solved rows (forward: the k*NB above it; backward: the ones below)
-  // and the triangular solve with the diagonal block
-  auto work = [&](int k, double &fu, double &bu, double &fd, double &bd) {
+  // by the panel's solved rows and the triangular solve with the diagonal
+  // block
+  auto work = [&](int k, int p0, int p1, double &fu, double &bu, double &fd, double &bd) {
     fu = bu = fd = bd = 0;
     if (!timing) return;
     for (int e = 0; e < batch; ++e) {
       const double nb = blk(h_desc[e].n, k), r = h_desc[e].nrhs;
       if (nb == 0) continue;
-      const double other = transpose ? h_desc[e].n - (double)k * NB - nb : (double)k * NB;
+      const double other = transpose
+                               ? std::min((double)p1, (double)h_desc[e].n) - (double)k * NB - nb
+                               : (double)k * NB - p0;
       fu += 2.0 * nb * r * other;
       bu += sizeof(T) * (nb * other + other * r + 2.0 * nb * r);
       fd += nb * nb * r;
@@ -1052,29 +1187,37 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
   };
   double fu, bu, fd, bd;
   if (!transpose) {
-    for (int k = 0; k < nblk; ++k) {
-      work(k, fu, bu, fd, bd);
-      if (k > 0) {
-        LaunchScope ls(st, "trsm_update_kernel<fwd>", bu, fu);
-        update(false, k);
+    for (int k0 = 0; k0 < nblk; k0 += PB) {
+      const int k1 = std::min(nblk, k0 + PB), p0 = k0 * NB, p1 = k1 * NB;
+      for (int k = k0; k < k1; ++k) {
+        work(k, p0, p1, fu, bu, fd, bd);
+        if (k > k0) {
+          LaunchScope ls(st, "trsm_update_kernel<fwd>", bu, fu);
+          update(false, k, p0, p1);
+        }
+        LaunchScope ls(st, "trsm_diag_kernel<fwd>", bd, fd);
+        trsm_diag_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
+                                                        dinv_off);
       }
-      LaunchScope ls(st, "trsm_diag_kernel<fwd>", bd, fd);
-      trsm_diag_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
-                                                      dinv_off);
+      panel_gemm(false, p0, p1);
     }
   } else {
     // entries of different sizes: block k of an entry is its k-th from the
-    // top; walking k downwards from the largest still visits every entry's
-    // blocks bottom-up
-    for (int k = nblk - 1; k >= 0; --k) {
-      work(k, fu, bu, fd, bd);
-      {
-        LaunchScope ls(st, "trsm_update_kernel<bwd>", bu, fu);
-        update(true, k);
+    // top; walking the panels and their blocks downwards from the largest
+    // still visits every entry's blocks bottom-up
+    for (int k0 = ((nblk - 1) / PB) * PB; k0 >= 0; k0 -= PB) {
+      const int k1 = std::min(nblk, k0 + PB), p0 = k0 * NB, p1 = k1 * NB;
+      for (int k = k1 - 1; k >= k0; --k) {
+        work(k, p0, p1, fu, bu, fd, bd);
+        if (k < k1 - 1) {
+          LaunchScope ls(st, "trsm_update_kernel<bwd>", bu, fu);
+          update(true, k, p0, p1);
+        }
+        LaunchScope ls(st, "trsm_diag_kernel<bwd>", bd, fd);
+        trsm_diag_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
+                                                       dinv_off);
       }
-      LaunchScope ls(st, "trsm_diag_kernel<bwd>", bd, fd);
-      trsm_diag_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
-                                                     dinv_off);
+      panel_gemm(true, p0, p1);
     }
   }
   return hipGetLastError();
