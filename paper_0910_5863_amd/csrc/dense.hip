@@ -203,6 +203,19 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
     const int r0 = m0 + wr * 16 * MT;
 #pragma unroll
     for (int y = 0; y < NT; ++y) {
+      const int c0 = n0 + wc * 16 * NT + 16 * y;
+      // the strip's C values are all requested before the accumulators are
+      // staged, so their latencies overlap each other and the staging instead
+      // of one load-then-store round trip per element
+      T cv[MT * 4];
+#pragma unroll
+      for (int it = 0; it < MT * 4; ++it) {
+        const int i = lane + 64 * it, r = i % (16 * MT), c = i / (16 * MT);
+        const int row = r0 + r, col = c0 + c;
+        cv[it] = (beta != T(0) && row < M && col < N)
+                     ? C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc]
+                     : T(0);
+      }
 #pragma unroll
       for (int x = 0; x < MT; ++x)
 #pragma unroll
@@ -210,7 +223,6 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
           stg[16 * x + Mfma<T>::row(lane, j) + (lane & 15) * SR] = alpha * acc[x][y][j];
       __builtin_amdgcn_wave_barrier();
       __asm__ volatile("" ::: "memory");
-      const int c0 = n0 + wc * 16 * NT + 16 * y;
 #pragma unroll
       for (int it = 0; it < MT * 4; ++it) {
         const int i = lane + 64 * it, r = i % (16 * MT), c = i / (16 * MT);
@@ -218,7 +230,7 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
         if (row < M && col < N && (!LW || row >= col)) {
           T *cp = &C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc];
           const T v = stg[r + c * SR];
-          *cp = (beta == T(0)) ? v : v + beta * (*cp);
+          *cp = (beta == T(0)) ? v : v + beta * cv[it];
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -1020,7 +1032,7 @@ hipError_t DenseOps<T>::gemm_scatter(hipStream_t st, const T *A, const T *B, T *
 // solved (chol_panel_kernel); then the whole trailing matrix is updated by
 // the panel at once (chol_syrk_kernel, 128 x 128 tiles, K = PB NB), so most
 // flops run as large tile products with many work-groups.
-constexpr int PB = 4;
+constexpr int PB = 8;
 
 template <class T>
 hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
