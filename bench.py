@@ -1,11 +1,16 @@
 #!/usr/bin/env python3
 """Adaptive BDDC-PCG throughput on one MI355X.
 
-Workload: 3D linear elasticity (Q1 hexahedra, 3 dofs per node) on 48^3
-elements in 4 x 4 x 4 cubic substructures of 12^3 elements; Young's modulus
-1 or 1e6 per horizontal layer (seeded), nu = 0.3, clamped at z = 0, gravity
-load; corner and edge-average constraints plus adaptive face constraints with
-tau = 10 (Algorithm 1); FP64; PCG to a relative residual of 1e-8.
+Workload (default, --workload kmeans64): 3D linear elasticity (Q1
+hexahedra, 3 dofs per node) on 64^3 elements split by seeded k-means into 64
+uneven substructures; E = 1 with 5% of the elements (seeded) at E = 1e5,
+nu = 0.3, clamped at z = 0, gravity load; corner and edge-average
+constraints plus the adaptive constraints of the face-pair eigenproblems with
+tau = 10 (Algorithm 1), the edge parts of the adaptive rows kept as edge rows
+(Sec. 3 after Proposition 1); FP64; PCG to a relative residual of 1e-8.
+--workload elasticity48: 48^3 elements in 4 x 4 x 4 cubic substructures of
+12^3, Young's modulus 1 or 1e6 per horizontal layer (seeded), adaptive face
+rows with the edge parts dropped.
 
 One step is one pass of the whole hot path over the problem:
 bddc_adapt(tau) (Dirichlet factors, Schur complements, face-pair
@@ -18,7 +23,8 @@ The output is one JSON line.  `value` comes from the timed steps, run with
 no instrumentation.  `roofline` describes the kernel with the largest summed
 time over the same number of steps run again with every launch bracketed by
 HIP events on the library's stream; `cpu_baseline` is the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+(its full run on the same workload, scaled to this host by a calibration
+task timed here).
 """
 from __future__ import annotations
 
@@ -34,12 +40,15 @@ sys.path.insert(0, ROOT)
 
 TAU = 10.0
 RTOL = 1e-8
+WORKLOAD_C3 = "elasticity64_kmeans64_inclusions_adaptive_tau10_edge_rows_kept"
+WORKLOAD_C2 = "elasticity48_4x4x4_layers_adaptive_tau10"
 PEAK_FP64_MFMA = 78.6      # TFLOP/s, MI355X dense FP64 matrix
 PEAK_HBM = 8000.0          # GB/s, MI355X HBM3E
 # kernels whose work is a dense contraction on the matrix cores
 MFMA_KERNELS = ("gemm_kernel", "chol_update_kernel", "chol_panel_kernel", "chol_diag_kernel",
-                "trsm_update_kernel<fwd>", "trsm_update_kernel<bwd>", "trsm_diag_kernel<fwd>",
-                "trsm_diag_kernel<bwd>")
+                "chol_syrk_kernel", "trsm_update_kernel<fwd>", "trsm_update_kernel<bwd>",
+                "trsm_diag_kernel<fwd>", "trsm_diag_kernel<bwd>", "trsm_gemm_kernel<fwd>",
+                "trsm_gemm_kernel<bwd>")
 KERNEL_SOURCE = {k: "paper_0910_5863_amd/csrc/dense.hip" for k in MFMA_KERNELS}
 KERNEL_SOURCE.update({"trsv_kernel<lower>": "paper_0910_5863_amd/csrc/dense.hip",
                       "trsv_kernel<upper>": "paper_0910_5863_amd/csrc/dense.hip",
@@ -57,6 +66,10 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=("kmeans64", "elasticity48"), default="kmeans64",
+                    help="kmeans64 (default): 64^3 elasticity elements in 64 uneven k-means "
+                         "substructures with stiff inclusions, adaptive edge rows kept; "
+                         "elasticity48: 48^3 elements in 4x4x4 cubes with layered coefficients")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle sample (about 15 s)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -251,13 +264,13 @@ def source_sha(rel):
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, tag):
     """Per-launch HBM bytes of `kernel` from the committed counter summary
-    (profiles/traffic_<kernel>_elasticity48.txt: FETCH_SIZE + WRITE_SIZE per dispatch,
+    (profiles/traffic_<kernel>_<tag>.txt: FETCH_SIZE + WRITE_SIZE per dispatch,
     scaled by a copy kernel of known size), or None when there is none or the
     kernel's source changed since the counters were taken."""
     safe = kernel.replace("<", "_").replace(">", "")
-    path = os.path.join(ROOT, "profiles", f"traffic_{safe}_elasticity48.txt")
+    path = os.path.join(ROOT, "profiles", f"traffic_{safe}_{tag}.txt")
     if not os.path.exists(path) or kernel not in KERNEL_SOURCE:
         return None
     vals = {}
@@ -274,41 +287,42 @@ def measured_traffic(kernel):
         return None
 
 
-def cpu_baseline():
-    """The oracle's adapt + factor + solve on 4 of the 64 substructures: a
-    24 x 24 x 12-element block split 2 x 2 x 1 into 12^3-element substructures,
-    with the layered-coefficient recipe, clamped bottom and gravity of the
-    workload, tau = 10.  Per-substructure work dominates, so the step time is
-    scaled by 64 / 4."""
-    import numpy as np
+def cpu_baseline(workload):
+    """The FP64 CPU oracle on this workload.  The oracle's full run (Schur
+    complements, every face-pair eigenproblem, Algorithm 2 by blocks, PCG to
+    1e-8) on the whole mesh was timed when its reference results were written
+    (tests/golden/<workload>.json: wall time with its worker processes, CPU
+    time summed over them, and one calibration task).  Here, on this host, the
+    calibration task alone is the sample: one substructure's dense Schur
+    complement on one thread.  The ratio of the two calibration times scales
+    the recorded full run to this host."""
     import meshgen
-    from oracle.solver import OracleBDDC
-    from oracle.adapt import adapt, schur_dense
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
-    nel = (24, 24, 12)
-    coef = meshgen.coef_layers(nel, 2)
-    p = meshgen.cube_problem(meshgen.ELASTICITY, nel, (2, 2, 1), coef=coef, nu=0.3,
-                             dirichlet_face=("z", 0.0), name="elasticity_24x24x12_2x2x1_layers")
-    o = OracleBDDC(p, "ce")
-    t0 = time.perf_counter()
-    Sd = {s: schur_dense(o.S, o.itf, s) for s in range(o.S.n_sub)}
-    ad = adapt(o.S, o.itf, o.cons, TAU, Sd=Sd)
-    o2 = OracleBDDC(p, "ce", extra_rows=ad["rows"])
-    r = o2.solve(rtol=RTOL)
-    dt = time.perf_counter() - t0
-    if not r["converged"]:
-        raise RuntimeError("oracle sample did not converge")
-    scale = 64 / p.n_sub
-    return {"value": 1.0 / (dt * scale), "unit": "solves/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": (f"oracle adapt+factor+solve on 4 of the 64 12^3-element substructures "
-                       f"(24x24x12 elements, 2x2x1, same layer recipe, tau=10): {dt:.2f} s, "
-                       f"{r['iters']} PCG iterations; time scaled by 64/4"),
-            "sample_seconds": dt}
+    from threadpoolctl import threadpool_limits
+    from oracle.fem import Substructures
+    from oracle.interface import Interface
+    from oracle.adapt import schur_dense
+    with open(os.path.join(ROOT, "tests", "golden", f"{workload}.json")) as fh:
+        g = json.load(fh)
+    o = g["oracle"]
+    cal = o["calibration"]
+    p = meshgen.elasticity_kmeans_64() if workload == "kmeans64" else meshgen.elasticity_layers_48()
+    S = Substructures(p)
+    itf = Interface(S)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        schur_dense(S, itf, cal["substructure"])
+        t = time.perf_counter() - t0
+    ratio = t / cal["seconds"]
+    step = o["step_s"] * ratio
+    return {"value": 1.0 / step, "unit": "solves/s", "cores": int(o["workers"]), "kind": "oracle",
+            "sample": (f"calibration task on this host: the dense Schur complement of substructure "
+                       f"{cal['substructure']} on one thread, {t:.2f} s against {cal['seconds']:.2f} s "
+                       f"on the host of the oracle's full run ({o['cpu']}, {o['workers']} worker "
+                       f"processes, one BLAS thread each); that run's step of {o['step_s']:.0f} s "
+                       f"(adapt, factor, PCG to 1e-8 in {g['pcg']['iters']} iterations) is scaled "
+                       f"by the ratio {ratio:.3f}"),
+            "value_1core": 1.0 / (o["step_cpu_s"] * ratio),
+            "sample_seconds": t}
 
 
 def main():
@@ -336,10 +350,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
-    p = meshgen.elasticity_layers_48()
+    c3 = args.workload == "kmeans64"
+    p = meshgen.elasticity_kmeans_64() if c3 else meshgen.elasticity_layers_48()
     b = BDDC(device=0, autotune=not args.no_autotune, factor_precision=args.factor_precision,
              per_substructure_launches=args.per_substructure_factor)
-    b.setup(p, "ce")
+    b.setup(p, "ce", adaptive_edges=c3)
     f = torch.from_numpy(p.f).to("cuda:0")
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
@@ -397,7 +412,7 @@ def main():
         achieved = st["bytes"] / st["launches"] / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM}
-    roof["traffic"] = measured_traffic(name)
+    roof["traffic"] = measured_traffic(name, args.workload)
     roof["kernel"] = name
     roof["launches"] = st["launches"]
     roof["avg_launch_us"] = avg_s * 1e6
@@ -428,7 +443,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.factor_precision == 64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "elasticity48_4x4x4_layers_adaptive_tau10", "n_glob": int(p.n_glob),
+        "config": {"workload": (WORKLOAD_C3 if c3 else WORKLOAD_C2), "n_glob": int(p.n_glob),
                    "n_sub": int(p.n_sub), "tau": TAU, "rtol": RTOL,
                    "step": "adapt(tau) + factor + pcg_solve(f), problem set up and resident",
                    "gemm_autotune": not args.no_autotune,
@@ -450,7 +465,7 @@ def main():
     }
     del b
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
 
