@@ -140,10 +140,15 @@ typedef struct {
   double true_relres;        /* ||R^T f - R^T A R u|| / ||r_0|| of the returned u, from
                                 the substructure matrices A_i (eq. (assembled)) */
   int refinements;           /* correction solves run because true_relres exceeded
-                                rtol after the main solve (at most 3; each solves
-                                A d = f - A u with the same preconditioner) */
+                                both rtol and twice residual_floor after the main
+                                solve (at most 3, stopping when the true residual
+                                stops halving; each solves A d = f - A u with the
+                                same preconditioner) */
   int refine_iters;          /* PCG iterations of those correction solves (not in
                                 iters, which counts the main solve only) */
+  double residual_floor;     /* eps || |A| |u| || / ||r_0||: the rounding scale of
+                                evaluating the product A u in FP64; true_relres
+                                cannot be shown below about this level */
 } bddc_pcg_info;
 
 typedef struct {
@@ -177,8 +182,21 @@ typedef struct {
 
 bddc_status bddc_create(const bddc_options *opt, bddc_ctx **ctx);
 
-/* Build substructure matrices, interface globs, weights and constraints
-   (host), and upload the substructure matrices (device). */
+/* Sec. 2 (the substructure matrices A_i assembled from the elements of each
+   substructure, the restriction R, the globs: faces, edges and corners,
+   Assumptions 1 and 2), Sec. 5 (constraint rows H^avg per glob, QR with
+   column pivoting, the change of variables T of eq. (T)) and Sec. 7 (weights
+   of E from the diagonals of A_i, arithmetic edge averages).  Builds all of
+   these on the host from the caller's mesh, partition and constraint choice
+   (all host arrays, copied before the call returns; nothing is retained) and
+   uploads the substructure matrices to the device.  Dirichlet dofs (mesh
+   dirichlet flags) are eliminated after the globs are classified.  Errors:
+   BDDC_ERR_ARG for inconsistent inputs (sizes, out-of-range substructure or
+   node ids), BDDC_ERR_INSUFFICIENT_CORNERS when augment_corners = 0 and a
+   pair of adjacent substructures with a floating member sees fewer than one
+   (scalar) or three non-collinear (elasticity) corners (Assumption 2),
+   BDDC_ERR_OOM / BDDC_ERR_DEVICE from the upload.  Invalidates earlier
+   adaptation and factors. */
 bddc_status bddc_setup(bddc_ctx *ctx, const bddc_mesh *mesh, const bddc_partition *part,
                        const bddc_constraints *cons);
 
@@ -197,8 +215,17 @@ bddc_status bddc_adapt(bddc_ctx *ctx, double tau, bddc_adapt_info *info);
    rows per face in elasticity the count equals that of the face averages. */
 bddc_status bddc_adapt_count(bddc_ctx *ctx, int rows_per_face, bddc_adapt_info *info);
 
-/* Factor: Dirichlet factors A_II, Schur complements, constrained local factors,
-   coarse basis and coarse factor, all substructures batched. */
+/* The factorization steps of Algorithm 2 (Sec. 5, with the primal assembly
+   of the coarse problem of the Remark after it): Dirichlet factors A_II and
+   Schur complements S_i (reused from bddc_adapt when it ran last), T_i^T
+   S_i T_i split into the remaining (r) and coarse (pi) dofs, the constrained
+   local factor K_rr = L L^T, the coarse basis Phi_i = -K_rr^-1 K_r,pi, S_pi^i,
+   the assembled coarse matrix and its Cholesky factor; all substructures in
+   each batched launch.  Requires bddc_setup; device memory is the
+   context's.  Errors: BDDC_ERR_STATE before setup, BDDC_ERR_NOT_SPD naming
+   the substructure and pivot of a non-positive pivot in A_II or K_rr,
+   BDDC_ERR_SINGULAR_COARSE for the coarse factor, BDDC_ERR_OOM /
+   BDDC_ERR_DEVICE. */
 bddc_status bddc_factor(bddc_ctx *ctx);
 
 /* z = M_BDDC r (Algorithm 2) for nrhs columns.  r, z: device, n_glob x nrhs,
@@ -222,8 +249,18 @@ bddc_status bddc_apply(bddc_ctx *ctx, int nrhs, const double *r, int64_t ldr, do
 bddc_status bddc_apply_noalloc(bddc_ctx *ctx, int nrhs, const double *r, int64_t ldr, double *z,
                                int64_t ldz);
 
-/* Solve R^T A R u = f by BDDC-PCG.  f, u: device, n_glob x nrhs column-major;
-   each column is an independent solve.  info may be NULL, else nrhs entries. */
+/* Solve R^T A R u = f (Sec. 2, eq. (assembled)) by PCG on the reduced problem
+   with the BDDC preconditioner of Algorithm 2 (Sec. 2: zero interface start
+   with interior Dirichlet solves, so (I - P)^T is not needed; Sec. 7: stop
+   at ||r_k||_2 <= rtol ||r_0||_2, condition number from the Lanczos
+   coefficients of CG).  f, u: device, n_glob x nrhs column-major, owned by
+   the caller (u written); each column is an independent solve.  After the
+   stop the true residual of the assembled system is computed with the A_i
+   (bddc_pcg_info.true_relres, residual_floor, refinements).  params may be
+   NULL (rtol 1e-8, maxit 1000).  info may be NULL, else nrhs entries.
+   Errors: BDDC_ERR_STATE before bddc_factor, BDDC_ERR_ARG for bad vectors or
+   leading dimensions, BDDC_ERR_NO_CONVERGENCE when a column stops at maxit or
+   on a breakdown (its info entry still filled), BDDC_ERR_DEVICE. */
 bddc_status bddc_pcg_solve(bddc_ctx *ctx, int nrhs, const double *f, int64_t ldf, double *u,
                            int64_t ldu, const bddc_pcg_params *params, bddc_pcg_info *info);
 
