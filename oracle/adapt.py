@@ -173,9 +173,14 @@ class PairProblem:
         self.B = Pi @ Sden @ Pi
         self.Snum = Snum
 
-    def solve(self, null_tol=1e-10):
+    def solve(self, null_tol=1e-12):
         """All eigenpairs of C w = lambda B w in the factor space modulo
-        null(B).  Returns (lambdas ascending, W columns)."""
+        null(B) (eq. (eig-nullspace)): null(B) is spanned by the eigenvectors
+        of B whose eigenvalues are at most null_tol times the largest; the
+        default 1e-12 keeps genuine small eigenvalues of a stiff pair (down to
+        about 1e-11 of the largest at the 64^3 k-means size) out of the null
+        space, where rounding leaves the rigid-body directions near 1e-14.
+        Returns (lambdas ascending, W columns)."""
         ev, V = np.linalg.eigh(0.5 * (self.B + self.B.T))
         keep = ev > null_tol * ev.max()
         Vp = V[:, keep]
