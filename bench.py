@@ -100,6 +100,10 @@ def parse_args():
                     help="instead of the step benchmark, solve the workload once per constraint "
                          "set (c, c+e, c+e+f, 3eigv, adaptive tau with and without edge rows) and "
                          "print one JSON line each: Nc, kappa, iterations, phase times")
+    ap.add_argument("--tau-sweep", action="store_true",
+                    help="instead of the step benchmark, the 64^3 k-means workload at tau = 2, "
+                         "10, 100 with FP64 and FP32 local factors: one JSON line each with "
+                         "iterations, kappa, phase times and the error against the FP64 oracle")
     ap.add_argument("--planar-cubes", type=int, nargs=2, default=None, metavar=("KMIN", "KMAX"),
                     help="instead of the step benchmark, solve the planar-cubes series (k x k "
                          "substructures of 8^3 elasticity elements, corners only) for k in "
@@ -205,6 +209,49 @@ def planar_cubes(args):
             "paper_table9": None if ctx is None else dict(zip(
                 ("n_sub", "dofs", "kappa", "iters", "analysis_s", "factorization_s", "pcg_s"), ctx)),
         }), flush=True)
+
+
+def tau_sweep(args):
+    """Precision and tau on the 64^3 k-means workload (edge rows kept): for
+    tau in {2, 10, 100} and FP64 / FP32 local factors, a fresh context, one
+    untimed adapt + factor + solve (GEMM tuning), then the timed one.  The
+    error is max |u - u_oracle| / max |u_oracle| against the oracle's solution
+    of the same system (tests/golden/kmeans64.npz; the solution does not
+    depend on tau or on the preconditioner)."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_0910_5863_amd import BDDC
+    p = meshgen.elasticity_kmeans_64()
+    uref = np.load(os.path.join(ROOT, "tests", "golden", "kmeans64.npz"))["u"]
+    f = torch.from_numpy(p.f).to("cuda:0")
+    for tau in (2.0, 10.0, 100.0):
+        for prec in (64, 32):
+            b = BDDC(device=0, autotune=True, factor_precision=prec)
+            b.setup(p, "ce", adaptive_edges=True)
+            for rep in range(2):
+                t0 = time.perf_counter()
+                ai = b.adapt(tau)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                b.factor()
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                u, info = b.pcg_solve(f, rtol=RTOL, maxit=3000)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+            uu = u.cpu().numpy()[:, 0]
+            i = b.info()
+            b.close()
+            del b, u
+            torch.cuda.empty_cache()
+            print(json.dumps({
+                "workload": WORKLOAD_C3, "tau": tau, "factor_precision": prec, "nc": int(ai.nc),
+                "omega": float(ai.omega), "iters": int(info[0].iters), "kappa": float(info[0].kappa),
+                "true_relres": float(info[0].true_relres), "fp32_fallbacks": int(i.fp32_fallbacks),
+                "max_rel_error_vs_oracle": float(np.abs(uu - uref).max() / np.abs(uref).max()),
+                "adapt_s": t1 - t0, "factor_s": t2 - t1, "pcg_s": t3 - t2, "step_s": t3 - t0}),
+                flush=True)
 
 
 def serving(args):
@@ -335,12 +382,17 @@ def main():
     if args.serving > 0:
         serving(args)
         return
-    if args.variants or args.planar_cubes:
+    if args.variants or args.planar_cubes or args.tau_sweep:
         import torch
         if not torch.cuda.is_available():
             print("bench.py: no GPU visible", file=sys.stderr)
             sys.exit(1)
-        variants(args) if args.variants else planar_cubes(args)
+        if args.tau_sweep:
+            tau_sweep(args)
+        elif args.variants:
+            variants(args)
+        else:
+            planar_cubes(args)
         return
     import numpy as np
     import torch

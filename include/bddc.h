@@ -178,6 +178,9 @@ typedef struct {
   double pcg_iter_bytes;     /* bytes one PCG iteration streams per RHS */
   size_t device_bytes;       /* device memory held by the context */
   int64_t autotune_entries;  /* GEMM shapes tuned so far in this process */
+  int64_t fp32_fallbacks;    /* factor_precision 32: substructures whose FP32 local
+                                factorization met a non-positive pivot and were
+                                factored again in FP64 (stored rounded to FP32) */
 } bddc_info;
 
 bddc_status bddc_create(const bddc_options *opt, bddc_ctx **ctx);

@@ -67,7 +67,7 @@ class bddc_pcg_info(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("relres", C.c_double),
                 ("kappa", C.c_double), ("lmin", C.c_double), ("lmax", C.c_double),
                 ("seconds", C.c_double), ("true_relres", C.c_double), ("refinements", C.c_int),
-                ("refine_iters", C.c_int)]
+                ("refine_iters", C.c_int), ("residual_floor", C.c_double)]
 
 
 class bddc_adapt_info(C.Structure):
@@ -83,7 +83,8 @@ class bddc_info(C.Structure):
                 ("max_interior", C.c_int64), ("max_iface", C.c_int64),
                 ("factor_flops", C.c_double), ("factor_seconds", C.c_double),
                 ("apply_bytes", C.c_double), ("pcg_iter_bytes", C.c_double),
-                ("device_bytes", C.c_size_t), ("autotune_entries", C.c_int64)]
+                ("device_bytes", C.c_size_t), ("autotune_entries", C.c_int64),
+                ("fp32_fallbacks", C.c_int64)]
 
 
 class bddc_server_options(C.Structure):

@@ -159,6 +159,7 @@ bddc_status bddc_pcg_solve(bddc_ctx *c, int nrhs, const double *f, int64_t ldf, 
         o.true_relres = res.true_relres;
         o.refinements = res.refinements;
         o.refine_iters = res.refine_iters;
+        o.residual_floor = res.residual_floor;
       }
       all_conv &= res.converged;
     }
@@ -258,6 +259,7 @@ bddc_status bddc_get_info(const bddc_ctx *c, bddc_info *o) {
   o->pcg_iter_bytes = c->S->iter_bytes();
   o->device_bytes = c->S->alloc.held;
   o->autotune_entries = autotune_entries();
+  o->fp32_fallbacks = c->S ? c->S->fp32_fallbacks : 0;
   return BDDC_OK;
 }
 

@@ -46,6 +46,7 @@ struct PcgResult {
   double relres = 0, lmin = 0, lmax = 0, seconds = 0;
   double r0 = 0;              // ||r_0||: the reduced problem's initial residual
   double true_relres = 0;     // ||f - A u|| / ||r_0|| with the assembled A (CSR A_i)
+  double residual_floor = 0;  // eps || |A| |u| || / ||r_0||: rounding scale of that product
   int refinements = 0;        // correction solves run because true_relres > rtol
   int refine_iters = 0;       // PCG iterations of those correction solves
   std::vector<double> alphas, betas;
@@ -126,6 +127,9 @@ class Solver {
   void build(const Problem &P, hipStream_t st, bool keep_interior = false);
   void factor();
   void factor_schur();
+  void factor_local_fp32(int *status);
+  int fp32_fallbacks = 0;  // substructures whose FP32 local factor fell back to FP64
+  std::vector<int64_t> h_dinv_rr_off;
   void check_status(bool all);
   bool schur_ready = false;
   bool struct_ready = false;  // mesh / partition part of the layout is current
@@ -142,8 +146,8 @@ class Solver {
   // abs_tol / ||r_0||
   PcgResult pcg_once(const double *f, double *u, double rtol, int maxit, double abs_tol = 0);
   // rt = f - A u over all free dofs with the substructure matrices A_i;
-  // returns ||rt||
-  double true_residual(const double *f, const double *u, double *rt);
+  // returns ||rt|| and, in *floor, eps || |A| |u| ||
+  double true_residual(const double *f, const double *u, double *rt, double *floor);
   static constexpr int kMaxRefine = 3;
   void free_all();
 
@@ -189,6 +193,9 @@ class Solver {
   DBuf d_S, d_W, d_Lrr, d_Urr, d_Phi, d_Spi, d_Lc, d_Uc, d_descRRT;
   DBuf d_dinv_rr, d_dinv_rr_off, d_dinv_c, d_dinv_c_off;
   DBuf d_Lrr32, d_Urr32, d_dinv_rr32, d_vR32;  // FP32 local factor (factor_precision 32)
+  DBuf d_Phi32, d_rscale;  // FP32 coarse-basis work block; diag(K_rr)^-1/2 per remaining dof
+  DBuf d_PhiF, d_krrphi_desc;  // FP64 copy of the FP32 basis; K_rr Phi product descriptors
+  std::vector<GemmDesc> h_krrphi;
   int64_t dinv_rr_elems = 0;
   DBuf d_descRR, d_descC, d_spi_desc, d_descGG, d_descRRvec,
       d_descCvec;
@@ -208,6 +215,7 @@ class Solver {
   DBuf d_vG, d_vG2, d_vR, d_vR2, d_vP, d_vI, d_vI2, d_vc;
   DBuf d_gam_r, d_gam_z, d_gam_p, d_gam_q, d_gam_x, d_sc, d_part, d_alphas, d_betas;
   DBuf d_true_r, d_true_d;  // global vectors: true residual and correction
+  DBuf d_abs_I, d_abs_G;    // |A_i| |u_i| on the local stacks (rounding scale)
   DBuf d_symv_part, d_symv_off;  // partial products of the symmetric Schur operator
   DBuf d_pcg_ctl, d_pcg_hist;  // PCG control words (stop, iterations, converged, maxit), history
   // one PCG iteration captured as a graph (rebuilt after every build); the

@@ -25,6 +25,8 @@
 //            solve per substructure.
 #include <hip/hip_runtime.h>
 
+#include <limits>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -386,24 +388,31 @@ __global__ void spmv_coupling_kernel(const int *row_sub, const int *row_loc, con
 }
 
 // y_i = A_i x_i for every substructure (all local rows), x and y split into
-// the interior stack (local rows < nI) and the interface stack
+// the interior stack (local rows < nI) and the interface stack; a receives
+// |A_i| |x_i| (the scale of the rounding in y)
 __global__ void spmv_local_kernel(const int *row_sub, const int *row_loc, const int64_t *rowptr,
                                   const int *col, const double *val, int64_t nrows, const int *nI,
                                   const int64_t *offI, const int64_t *offG, const double *xI,
-                                  const double *xG, double *yI, double *yG) {
+                                  const double *xG, double *yI, double *yG, double *aI,
+                                  double *aG) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nrows) return;
   const int s = row_sub[g], r = row_loc[g];
   const int ni = nI[s];
-  double acc = 0;
+  double acc = 0, aacc = 0;
   for (int64_t k = rowptr[g]; k < rowptr[g + 1]; ++k) {
     const int c = col[k];
-    acc += val[k] * (c < ni ? xI[offI[s] + c] : xG[offG[s] + (c - ni)]);
+    const double t = val[k] * (c < ni ? xI[offI[s] + c] : xG[offG[s] + (c - ni)]);
+    acc += t;
+    aacc += fabs(t);
   }
-  if (r < ni)
+  if (r < ni) {
     yI[offI[s] + r] = acc;
-  else
+    aI[offI[s] + r] = aacc;
+  } else {
     yG[offG[s] + (r - ni)] = acc;
+    aG[offG[s] + (r - ni)] = aacc;
+  }
 }
 
 // rt = f - (assembled product): interior dofs take their one substructure's
@@ -421,6 +430,54 @@ __global__ void residual_gamma_kernel(const double *f, const int64_t *gamma_gdof
   double acc = 0;
   for (int k = ptr[g]; k < ptr[g + 1]; ++k) acc += yG[copies[k]];
   rt[gamma_gdof[g]] = f[gamma_gdof[g]] - acc;
+}
+
+// Symmetric diagonal scaling of the constrained local matrices (FP32 factor):
+// s = diag(K_rr)^{-1/2} per remaining dof (1 where the diagonal is not
+// positive: the factorization reports that pivot).
+__global__ void rscale_kernel(const double *K, const int64_t *offRR, const int *nr,
+                              const int64_t *offR, double *sc) {
+  const int sub = blockIdx.y;
+  const int n = nr[sub];
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const double d = K[offRR[sub] + a + (int64_t)a * n];
+  sc[offR[sub] + a] = d > 0 ? 1.0 / sqrt(d) : 1.0;
+}
+
+// dst (FP32) = diag(rs) src diag(cs) for each substructure's n_r x ncol block
+// (column-major, ld n_r; cs == nullptr: no column scaling)
+__global__ void scale_f32_kernel(const double *src, float *dst, const int64_t *off, const int *nr,
+                                 const int *ncol, const double *rs, const double *cs,
+                                 const int64_t *offR) {
+  const int sub = blockIdx.y;
+  const int64_t n = nr[sub], m = ncol[sub];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * m) return;
+  const int a = (int)(i % n), b = (int)(i / n);
+  const double v = src[off[sub] + i] * rs[offR[sub] + a] * (cs ? cs[offR[sub] + b] : 1.0);
+  dst[off[sub] + i] = (float)v;
+}
+
+// dst (FP64) = alpha diag(rs) src (+ dst when accumulate) for each
+// substructure's n_r x ncol block (rs == nullptr: no scaling)
+__global__ void unscale_f64_kernel(const float *src, double *dst, const int64_t *off, const int *nr,
+                                   const int *ncol, const double *rs, const int64_t *offR,
+                                   double alpha, int accumulate) {
+  const int sub = blockIdx.y;
+  const int64_t n = nr[sub], m = ncol[sub];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * m) return;
+  const int a = (int)(i % n);
+  const double v = alpha * (rs ? rs[offR[sub] + a] : 1.0) * (double)src[off[sub] + i];
+  dst[off[sub] + i] = accumulate ? dst[off[sub] + i] + v : v;
+}
+
+// y = (D) x elementwise with a change of precision (d: per-element scale)
+template <class S, class D>
+__global__ void convert_scaled_kernel(const S *src, D *dst, const double *d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (D)(d[i] * (double)src[i]);
 }
 
 // dst = scale * src with a change of precision
@@ -503,9 +560,13 @@ __global__ void pcg_check_kernel(const double *sc, int *ctl, double *hist) {
     ctl[0] = 1;
   }
 }
-__global__ void pcg_beta_kernel(double *sc, double *betas, const int *ctl) {
+// beta = (r, z) / (r_old, z_old) (Fletcher-Reeves), or with flexible set
+// ((r, z) - (r, z_old)) / (r_old, z_old) (Polak-Ribiere, sc[11] = (r, z_old)):
+// the form that tolerates a preconditioner that is not exactly symmetric
+// positive definite, as with FP32 local factors
+__global__ void pcg_beta_kernel(double *sc, double *betas, const int *ctl, int flexible) {
   if (ctl[0]) return;
-  const double b = sc[5] / sc[0];
+  const double b = (flexible ? sc[5] - sc[11] : sc[5]) / sc[0];
   sc[4] = b;
   betas[ctl[1] - 1] = b;
   sc[0] = sc[5];
@@ -525,6 +586,10 @@ __global__ void pcg_dir_kernel(double *p, const double *z, const double *sc, con
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || ctl[0]) return;
   p[i] = z[i] + sc[4] * p[i];
+}
+__global__ void fill_kernel(double *dst, double v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
 }
 __global__ void copy_kernel(double *dst, const double *src, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -675,7 +740,8 @@ std::vector<DBuf *> Solver::struct_buffers() {
           &d_offGG, &d_S, &d_W, &d_descGG, &d_ifc_gamma, &d_ifc_delta, &d_gamma_ptr,
           &d_gamma_copies, &d_gamma_gdof, &d_int_gdof, &d_ifc_gdof, &d_vG, &d_vG2, &d_vI, &d_vI2,
           &d_gam_r, &d_gam_z, &d_gam_p, &d_gam_q, &d_gam_x, &d_sc, &d_part, &d_alphas, &d_betas,
-          &d_pcg_ctl, &d_pcg_hist, &d_symv_part, &d_symv_off, &d_true_r, &d_true_d};
+          &d_pcg_ctl, &d_pcg_hist, &d_symv_part, &d_symv_off, &d_true_r, &d_true_d, &d_abs_I,
+          &d_abs_G};
 }
 
 std::vector<DBuf *> Solver::cons_buffers() {
@@ -687,7 +753,8 @@ std::vector<DBuf *> Solver::cons_buffers() {
           &d_pabs, &d_pcid, &d_sub_cids, &d_c_ptr, &d_c_sub, &d_c_loc, &d_c_copies,
           &d_trsv_rr_fwd, &d_trsv_rr_bwd, &d_trsv_rr_off, &d_trsv_c_fwd, &d_trsv_c_bwd,
           &d_trsv_c_off, &d_work_i, &d_status, &d_vR, &d_vR2, &d_vP, &d_vc, &d_descRRvec,
-          &d_descCvec, &d_Lrr32, &d_Urr32, &d_dinv_rr32, &d_vR32};
+          &d_descCvec, &d_Lrr32, &d_Urr32, &d_dinv_rr32, &d_vR32, &d_Phi32, &d_rscale, &d_PhiF,
+          &d_krrphi_desc};
 }
 
 std::vector<DBuf *> Solver::all_buffers() {
@@ -915,6 +982,15 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_descRRT = upload(alloc, st, dRRT);
   d_spi_desc = upload(alloc, st, spi);
   h_spi = spi;
+  if (factor_precision == 32) {
+    // K_rr Phi per substructure (the Galerkin coarse matrix of the FP32 basis)
+    std::vector<GemmDesc> kp(ns);
+    for (int s = 0; s < ns; ++s)
+      kp[s] = GemmDesc{L.offRR[s], L.offRP[s], L.offRP[s], L.nr[s], L.np[s], L.nr[s],
+                       std::max(1, L.nr[s]), std::max(1, L.nr[s]), std::max(1, L.nr[s])};
+    d_krrphi_desc = upload(alloc, st, kp);
+    h_krrphi = kp;
+  }
   MatDesc dc{0, 0, (int)nc, 0, (int)std::max<int64_t>(1, nc), (int)std::max<int64_t>(1, nc)};
   h_descC = {dc};
   d_descC = upload(alloc, st, h_descC);
@@ -953,6 +1029,9 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
     d_Lrr32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sRR);
     d_Urr32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sRR);
     d_vR32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sumR * kMaxRhs);
+    d_Phi32 = alloc0(alloc, st, sizeof(float) * (size_t)L.sRP);
+    d_PhiF = alloc0(alloc, st, sizeof(double) * (size_t)std::max<int64_t>(1, L.sRP));
+    d_rscale = alloc0(alloc, st, sizeof(double) * (size_t)std::max<int64_t>(1, L.sumR));
   }
   d_Phi = alloc0(alloc, st, sizeof(double) * (size_t)L.sRP);
   d_Spi = alloc0(alloc, st, sizeof(double) * (size_t)L.sPP);
@@ -970,6 +1049,7 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
     if (p32) d_dinv_rr32 = alloc0(alloc, st, sizeof(float) * (size_t)tot);
     dinv_rr_elems = tot;
     d_dinv_rr_off = upload(alloc, st, off);
+    h_dinv_rr_off = off;
     d_dinv_c = alloc0(alloc, st, sizeof(double) * (size_t)(((nc + NB - 1) / NB) * NB * NB));
     d_dinv_c_off = upload(alloc, st, std::vector<int64_t>{0});
   }
@@ -1120,6 +1200,8 @@ void Solver::build_structure(const Problem &P, hipStream_t st) {
   d_pcg_hist = alloc0(alloc, st, sizeof(double) * (kMaxIt + 2));
   d_true_r = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, L.n_glob));
   d_true_d = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, L.n_glob));
+  d_abs_I = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, L.sumI));
+  d_abs_G = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, L.sumG));
   // interior elimination
   mf.setup(P, L.offI, alloc, st);
 }
@@ -1211,40 +1293,34 @@ void Solver::factor() {
   const int ng = per_sub_launches ? ns : 1, gs = per_sub_launches ? 1 : ns;
   const MatDesc *dRR = d_descRR.as<MatDesc>();
   const int64_t *dio = d_dinv_rr_off.as<int64_t>();
-  timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
-  for (int g = 0; g < ng; ++g)
-    HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), dRR + g * gs, h_descRR.data() + g * gs,
-                                   gs, status + ns + g * gs, d_dinv_rr.as<double>(), dio + g * gs));
-  timer.end(st);
-  for (int g = 0; g < ng; ++g)
-    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR + g * gs,
-                                  h_descRR.data() + g * gs, gs, false, d_dinv_rr.as<double>(),
-                                  dio + g * gs));
-  for (int g = 0; g < ng; ++g) {
-    const int mm = per_sub_launches ? h_spi[g].M : L.max_np, nn = per_sub_launches ? h_spi[g].N : L.max_np;
-    HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
-                                  d_spi_desc.as<GemmDesc>() + g * gs, gs, mm, nn, true, false, -1.0,
-                                  1.0, false, h_spi.data() + g * gs));
-  }
-  for (int g = 0; g < ng; ++g)
-    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR + g * gs,
-                                  h_descRR.data() + g * gs, gs, true, d_dinv_rr.as<double>(),
-                                  dio + g * gs));
-  if (L.sRP > 0) {
-    axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
-                                                 L.sRP);
-    HIPCHK(hipGetLastError());
-  }
+  fp32_fallbacks = 0;
   if (factor_precision == 32) {
-    // the factor used by the preconditioner's local solves, stored in FP32
-    convert_kernel<double, float><<<nblocks(L.sRR), TPB, 0, st>>>(d_Lrr.as<double>(), d_Lrr32.as<float>(),
-                                                                   L.sRR, 1.0);
-    convert_kernel<double, float><<<nblocks(dinv_rr_elems), TPB, 0, st>>>(
-        d_dinv_rr.as<double>(), d_dinv_rr32.as<float>(), dinv_rr_elems, 1.0);
-    HIPCHK(hipGetLastError());
-    HIPCHK(transpose_batched<float>(st, d_Lrr32.as<float>(), d_Urr32.as<float>(),
-                                    d_descRRT.as<MatDesc>(), ns, L.max_nr));
+    factor_local_fp32(status);
   } else {
+    timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
+    for (int g = 0; g < ng; ++g)
+      HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), dRR + g * gs, h_descRR.data() + g * gs,
+                                     gs, status + ns + g * gs, d_dinv_rr.as<double>(), dio + g * gs));
+    timer.end(st);
+    for (int g = 0; g < ng; ++g)
+      HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR + g * gs,
+                                    h_descRR.data() + g * gs, gs, false, d_dinv_rr.as<double>(),
+                                    dio + g * gs));
+    for (int g = 0; g < ng; ++g) {
+      const int mm = per_sub_launches ? h_spi[g].M : L.max_np, nn = per_sub_launches ? h_spi[g].N : L.max_np;
+      HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
+                                    d_spi_desc.as<GemmDesc>() + g * gs, gs, mm, nn, true, false, -1.0,
+                                    1.0, false, h_spi.data() + g * gs));
+    }
+    for (int g = 0; g < ng; ++g)
+      HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR + g * gs,
+                                    h_descRR.data() + g * gs, gs, true, d_dinv_rr.as<double>(),
+                                    dio + g * gs));
+    if (L.sRP > 0) {
+      axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
+                                                   L.sRP);
+      HIPCHK(hipGetLastError());
+    }
     // L_rr^T beside L_rr: the backward solves read it row-coalesced
     HIPCHK(transpose_batched<double>(st, d_Lrr.as<double>(), d_Urr.as<double>(),
                                      d_descRRT.as<MatDesc>(), ns, L.max_nr));
@@ -1276,6 +1352,115 @@ void Solver::factor() {
   fl += (double)nc * nc * nc / 3;
   factor_flops = fl;
   factored = true;
+}
+
+// The constrained local factorization in FP32 on the matrix cores (FP32
+// accumulate): K_rr is scaled symmetrically, S K_rr S with S = diag(K_rr)^-1/2,
+// converted and factored, Lt Lt^T = S K_rr S.  A substructure whose FP32
+// factorization meets a non-positive pivot is factored again in FP64 from
+// the unscaled K_rr (kept in FP64) and stored rounded with unit scaling; the
+// count is reported.  The coarse basis runs through the FP32 factor, Phi =
+// -S Lt^-T Lt^-1 S K_r,pi (FP32 TRSMs) with one FP64-residual refinement
+// step, and S_pi is its Galerkin product in FP64 (below).  The coarse matrix
+// and its factor stay FP64.
+void Solver::factor_local_fp32(int *status) {
+  hipStream_t st = stream;
+  const int ns = L.nsub;
+  const MatDesc *dRR = d_descRR.as<MatDesc>();
+  const int64_t *dio = d_dinv_rr_off.as<int64_t>();
+  double *sc = d_rscale.as<double>();
+  float *L32 = d_Lrr32.as<float>(), *P32 = d_Phi32.as<float>();
+  if (L.max_nr == 0) return;
+  rscale_kernel<<<dim3(nblocks(L.max_nr), ns), TPB, 0, st>>>(d_Lrr.as<double>(), d_offRR.as<int64_t>(),
+                                                             d_nr.as<int>(), d_offR.as<int64_t>(), sc);
+  scale_f32_kernel<<<dim3(nblocks((int64_t)L.max_nr * L.max_nr), ns), TPB, 0, st>>>(
+      d_Lrr.as<double>(), L32, d_offRR.as<int64_t>(), d_nr.as<int>(), d_nr.as<int>(), sc, sc,
+      d_offR.as<int64_t>());
+  HIPCHK(hipGetLastError());
+  double fl = 0;
+  for (int q = 0; q < ns; ++q) fl += (double)L.nr[q] * L.nr[q] * L.nr[q] / 3;
+  timer.begin(st, "factor_potrf_local", 4.0 * L.sRR, fl);
+  HIPCHK(DenseOps<float>::potrf(st, L32, dRR, h_descRR.data(), ns, status + ns,
+                                d_dinv_rr32.as<float>(), dio));
+  timer.end(st);
+  std::vector<int> hs(ns);
+  HIPCHK(hipMemcpyAsync(hs.data(), status + ns, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int q = 0; q < ns; ++q) {
+    if (!hs[q]) continue;
+    // FP64 fallback for this substructure: its pivot flag is cleared first,
+    // so that a failure here is reported as NOT_SPD
+    ++fp32_fallbacks;
+    HIPCHK(hipMemsetAsync(status + ns + q, 0, sizeof(int), st));
+    HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), dRR + q, &h_descRR[q], 1, status + ns + q,
+                                   d_dinv_rr.as<double>(), dio + q));
+    const int64_t n = L.nr[q], nb = (n + NB - 1) / NB;
+    const int64_t o = h_descRR[q].a_off;
+    convert_kernel<double, float><<<nblocks(n * n), TPB, 0, st>>>(d_Lrr.as<double>() + o, L32 + o,
+                                                                   n * n, 1.0);
+    convert_kernel<double, float><<<nblocks(nb * NB * NB), TPB, 0, st>>>(
+        d_dinv_rr.as<double>() + h_dinv_rr_off[q], d_dinv_rr32.as<float>() + h_dinv_rr_off[q],
+        nb * NB * NB, 1.0);
+    fill_kernel<<<nblocks(n), TPB, 0, st>>>(sc + L.offR[q], 1.0, n);
+    HIPCHK(hipGetLastError());
+  }
+  if (L.max_np > 0) {
+    double *PhiF = d_PhiF.as<double>(), *Krp = d_Phi.as<double>();
+    const int64_t mx = (int64_t)L.max_nr * L.max_np;
+    // K_rr^-1 X ~ S Lt^-T Lt^-1 S X in FP32: PhiF (+)= alpha of that, X in Krp
+    auto solve32 = [&](double alpha, int accumulate) {
+      scale_f32_kernel<<<dim3(nblocks(mx), ns), TPB, 0, st>>>(Krp, P32, d_offRP.as<int64_t>(),
+                                                              d_nr.as<int>(), d_np.as<int>(), sc,
+                                                              nullptr, d_offR.as<int64_t>());
+      HIPCHK(hipGetLastError());
+      HIPCHK(DenseOps<float>::trsm(st, L32, P32, dRR, h_descRR.data(), ns, false,
+                                   d_dinv_rr32.as<float>(), dio));
+      HIPCHK(DenseOps<float>::trsm(st, L32, P32, dRR, h_descRR.data(), ns, true,
+                                   d_dinv_rr32.as<float>(), dio));
+      unscale_f64_kernel<<<dim3(nblocks(mx), ns), TPB, 0, st>>>(P32, PhiF, d_offRP.as<int64_t>(),
+                                                                d_nr.as<int>(), d_np.as<int>(), sc,
+                                                                d_offR.as<int64_t>(), alpha, accumulate);
+      HIPCHK(hipGetLastError());
+    };
+    // Krp = K_r,pi (again) and Krp += K_rr PhiF: the FP64 residual of K_rr Phi = -K_r,pi
+    auto residual = [&]() {
+      gather_block_kernel<<<dim3(nblocks(mx), ns), TPB, 0, st>>>(
+          d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), Krp, d_offRP.as<int64_t>(),
+          d_nr.as<int>(), d_ridx.as<int>(), d_ridx_off.as<int64_t>(), d_nr.as<int>(), d_pidx.as<int>(),
+          d_pidx_off.as<int64_t>(), d_np.as<int>(), 1.0);
+      HIPCHK(hipGetLastError());
+      HIPCHK(DenseOps<double>::gemm(st, d_Lrr.as<double>(), PhiF, Krp, d_krrphi_desc.as<GemmDesc>(),
+                                    ns, L.max_nr, L.max_np, false, false, 1.0, 1.0, false,
+                                    h_krrphi.data()));
+    };
+    // Phi_0 = -K_rr^-1 K_r,pi by the FP32 factor; one step of refinement with
+    // the FP64 residual W_0 = K_r,pi + K_rr Phi_0: Phi_1 = Phi_0 - K_rr^-1 W_0
+    solve32(-1.0, 0);
+    residual();
+    solve32(-1.0, 1);
+    // S_pi as the Galerkin product [Phi; I]^T K [Phi; I] in FP64 (K_rr, K_r,pi
+    // and K_pi,pi unrounded): symmetric positive definite for any basis, and
+    // off the exact Schur complement only by (Phi - Phi_exact)^T K_rr (Phi -
+    // Phi_exact).  The shorter form K_pi,pi - K_pi,r K_rr^-1 K_r,pi with an
+    // FP32 solve loses its small eigenvalues to cancellation at high
+    // coefficient contrast (an indefinite coarse matrix at the 64^3 k-means
+    // size; without the refinement step the basis costs 76 PCG iterations
+    // there instead of 30).  S_pi += K_pi,r Phi; W = K_r,pi + K_rr Phi;
+    // S_pi += Phi^T W.
+    gather_block_kernel<<<dim3(nblocks(mx), ns), TPB, 0, st>>>(
+        d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), Krp, d_offRP.as<int64_t>(),
+        d_nr.as<int>(), d_ridx.as<int>(), d_ridx_off.as<int64_t>(), d_nr.as<int>(), d_pidx.as<int>(),
+        d_pidx_off.as<int64_t>(), d_np.as<int>(), 1.0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(DenseOps<double>::gemm(st, Krp, PhiF, d_Spi.as<double>(), d_spi_desc.as<GemmDesc>(), ns,
+                                  L.max_np, L.max_np, true, false, 1.0, 1.0, false, h_spi.data()));
+    HIPCHK(DenseOps<double>::gemm(st, d_Lrr.as<double>(), PhiF, Krp, d_krrphi_desc.as<GemmDesc>(), ns,
+                                  L.max_nr, L.max_np, false, false, 1.0, 1.0, false, h_krrphi.data()));
+    HIPCHK(DenseOps<double>::gemm(st, PhiF, Krp, d_Spi.as<double>(), d_spi_desc.as<GemmDesc>(), ns,
+                                  L.max_np, L.max_np, true, false, 1.0, 1.0, false, h_spi.data()));
+    HIPCHK(hipMemcpyAsync(Krp, PhiF, sizeof(double) * L.sRP, hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHK(transpose_batched<float>(st, L32, d_Urr32.as<float>(), d_descRRT.as<MatDesc>(), ns, L.max_nr));
 }
 
 void Solver::check_status(bool all) {
@@ -1520,9 +1705,11 @@ void Solver::apply_local(double *b, double *z, const ApplyWork &w) {
   }
   copy_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vR2, vR, L.sumR);
   if (factor_precision == 32) {
-    // K_rr solves in FP32; the vector enters and leaves in FP64
+    // K_rr solves in FP32 with the scaled factor (K_rr = S^-1 Lt Lt^T S^-1):
+    // the vector enters and leaves in FP64, scaled by S on both sides
     float *x32 = w.vR32;
-    convert_kernel<double, float><<<nblocks(L.sumR), TPB, 0, st>>>(vR2, x32, L.sumR, 1.0);
+    const double *rsc = d_rscale.as<double>();
+    convert_scaled_kernel<double, float><<<nblocks(L.sumR), TPB, 0, st>>>(vR2, x32, rsc, L.sumR);
     HIPCHK(hipGetLastError());
     timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 8.0 * L.sumR, (double)L.sRR);
     trsv32(plan_rr, d_Lrr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, false, w);
@@ -1530,7 +1717,7 @@ void Solver::apply_local(double *b, double *z, const ApplyWork &w) {
     timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 8.0 * L.sumR, (double)L.sRR);
     trsv32(plan_rr, d_Urr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, true, w);
     timer.end(st);
-    convert_kernel<float, double><<<nblocks(L.sumR), TPB, 0, st>>>(x32, vR2, L.sumR, 1.0);
+    convert_scaled_kernel<float, double><<<nblocks(L.sumR), TPB, 0, st>>>(x32, vR2, rsc, L.sumR);
     HIPCHK(hipGetLastError());
   } else {
     timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
@@ -1623,14 +1810,16 @@ void Solver::pcg_iteration() {
   pcg_update_kernel<<<nblocks(ng), TPB, 0, st>>>(x, r, p, q, sc, ctl, ng);
   dot(r, r, ng, sc + 2);
   pcg_check_kernel<<<1, 1, 0, st>>>(sc, ctl, d_pcg_hist.as<double>());
+  const int flexible = factor_precision == 32 ? 1 : 0;
+  if (flexible) dot(r, z, ng, sc + 11);
   apply_gamma(r, z);
   dot(r, z, ng, sc + 5);
-  pcg_beta_kernel<<<1, 1, 0, st>>>(sc, d_betas.as<double>(), ctl);
+  pcg_beta_kernel<<<1, 1, 0, st>>>(sc, d_betas.as<double>(), ctl, flexible);
   pcg_dir_kernel<<<nblocks(ng), TPB, 0, st>>>(p, z, sc, ctl, ng);
   HIPCHK(hipGetLastError());
 }
 
-double Solver::true_residual(const double *f, const double *u, double *rt) {
+double Solver::true_residual(const double *f, const double *u, double *rt, double *floor) {
   hipStream_t st = stream;
   double *vI = d_vI.as<double>(), *vI2 = d_vI2.as<double>();
   double *vG = d_vG.as<double>(), *vG2 = d_vG2.as<double>();
@@ -1644,7 +1833,7 @@ double Solver::true_residual(const double *f, const double *u, double *rt) {
     spmv_local_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
         d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
         d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(), vI,
-        vG, vI2, vG2);
+        vG, vI2, vG2, d_abs_I.as<double>(), d_abs_G.as<double>());
   }
   residual_interior_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(f, d_int_gdof.as<int64_t>(), vI2, rt,
                                                             L.sumI);
@@ -1654,39 +1843,60 @@ double Solver::true_residual(const double *f, const double *u, double *rt) {
   HIPCHK(hipGetLastError());
   double *sc = d_sc.as<double>();
   dot(rt, rt, L.n_glob, sc + 8);
-  double rr;
-  HIPCHK(hipMemcpyAsync(&rr, sc + 8, sizeof(double), hipMemcpyDeviceToHost, st));
+  // the rounding scale of the product: | |A| |u| | over the free dofs, the
+  // interface rows summed over their copies (PCG's q is free here)
+  double *aG = d_gam_q.as<double>();
+  reduce_copies_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(d_abs_G.as<double>(), L.sumG,
+                                                           d_gamma_ptr.as<int>(),
+                                                           d_gamma_copies.as<int64_t>(), nullptr,
+                                                           aG, L.n_gamma, L.n_gamma, 1, 1.0, 0.0);
+  HIPCHK(hipGetLastError());
+  dot(d_abs_I.as<double>(), d_abs_I.as<double>(), L.sumI, sc + 9);
+  dot(aG, aG, L.n_gamma, sc + 10);
+  double h[3];
+  HIPCHK(hipMemcpyAsync(h, sc + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  return std::sqrt(rr);
+  if (floor) *floor = std::numeric_limits<double>::epsilon() * std::sqrt(h[1] + h[2]);
+  return std::sqrt(h[0]);
 }
 
 // PCG to ||r_k|| <= rtol ||r_0|| (Sec. 7), on the interface with the explicit
 // Schur complements; then the residual of the assembled system R^T A R u =
-// R^T f is computed once with the substructure matrices A_i.  The explicit
-// operator carries the rounding of the Schur complements (amplified by the
-// coefficient contrast), so the true residual can sit above the recursive
-// one; while it exceeds rtol ||r_0|| and keeps falling, a correction
-// A d = f - A u is solved by the same PCG to the remaining absolute
-// tolerance and added to u.
+// R^T f is computed once with the substructure matrices A_i, with the
+// rounding scale of that product, eps || |A| |u| ||: a residual at that
+// level is as small as FP64 evaluation can show (with a coefficient contrast
+// of 1e6 it exceeds 1e-8 ||r_0|| even for the exact solution rounded to
+// FP64).  The explicit operator carries the rounding of the Schur
+// complements, so the true residual can sit above the recursive one; while it
+// exceeds both rtol ||r_0|| and twice that rounding scale, and keeps halving,
+// a correction A d = f - A u is solved by the same PCG to half the absolute
+// tolerance and added to u.  Below twice the rounding scale the computed
+// residual is mostly the rounding of the product itself, and a correction
+// solved from it adds that noise to the solution (measured: at 48^3 with
+// contrast 1e6 one such correction moved the solution from 7e-9 to 1.2e-8 of
+// the oracle's).
 PcgResult Solver::pcg(const double *f, double *u, double rtol, int maxit) {
   auto t0 = std::chrono::steady_clock::now();
   PcgResult res = pcg_once(f, u, rtol, maxit);
   if (res.r0 == 0.0) return res;
   double *rt = d_true_r.as<double>(), *du = d_true_d.as<double>();
-  double rn = true_residual(f, u, rt);
+  double fl = 0;
+  double rn = true_residual(f, u, rt, &fl);
   res.true_relres = rn / res.r0;
+  res.residual_floor = fl / res.r0;
   const double target = rtol * res.r0;
-  while (res.converged && rn > target && res.refinements < kMaxRefine) {
+  while (res.converged && rn > target && rn > 2.0 * fl && res.refinements < kMaxRefine) {
     // half the target, so that the rounding of the update leaves room
     PcgResult c = pcg_once(rt, du, rtol, maxit, 0.5 * target);
     ++res.refinements;
     res.refine_iters += c.iters;
     axpby_kernel<<<nblocks(L.n_glob), TPB, 0, stream>>>(u, du, 1.0, 1.0, L.n_glob);
     HIPCHK(hipGetLastError());
-    const double rn_new = true_residual(f, u, rt);
+    const double rn_new = true_residual(f, u, rt, &fl);
     const bool stalled = rn_new > 0.5 * rn;
     rn = rn_new;
     res.true_relres = rn / res.r0;
+    res.residual_floor = fl / res.r0;
     if (stalled) break;
   }
   last_history = res.history;

@@ -90,12 +90,16 @@ def check_edge_rows(g, b):
         assert rows.shape[0] == n, (e, rows.shape[0], n)
 
 
-def check_solution(g, arrays, u, pinfo):
+def check_solution(g, arrays, u, pinfo, same_preconditioner=True):
+    """same_preconditioner=False (FP32 local factors): the preconditioner is
+    not the oracle's FP64 one, so iterations and kappa are not compared; the
+    solution and the true residual are."""
     p = g["pcg"]
     assert pinfo.converged
-    assert abs(pinfo.iters - p["iters"]) <= 2, (pinfo.iters, p["iters"])
-    assert abs(pinfo.kappa - p["kappa"]) <= 1e-2 * p["kappa"], (pinfo.kappa, p["kappa"])
-    assert pinfo.lmin > 1 - 1e-9
+    if same_preconditioner:
+        assert abs(pinfo.iters - p["iters"]) <= 2, (pinfo.iters, p["iters"])
+        assert abs(pinfo.kappa - p["kappa"]) <= 1e-2 * p["kappa"], (pinfo.kappa, p["kappa"])
+        assert pinfo.lmin > 1 - 1e-9
     # the true residual of the assembled system to 1e-8 of r_0, or to the
     # rounding scale of evaluating it in FP64 (eps || |A| |u| ||) where that is
     # larger (coefficient contrast 1e6: about 3e-8 of r_0 even for the oracle's
