@@ -78,9 +78,11 @@ def parse_args():
     ap.add_argument("--factor-precision", type=int, default=64, choices=(32, 64),
                     help="32: FP32 local factor L_rr and local triangular solves (outer PCG, "
                          "coarse problem and averaging stay FP64)")
-    ap.add_argument("--per-substructure-factor", action="store_true",
-                    help="launch the factor's Cholesky, TRSMs and S_pi product once per "
-                         "substructure instead of once for all (the unbatched baseline)")
+    ap.add_argument("--per-substructure", action="store_true",
+                    help="the unbatched baseline: every dense operation of adapt and factor "
+                         "one launch sequence per entry (interior fronts one substructure at a "
+                         "time, LOBPCG one face pair per launch), the PCG's Schur products and "
+                         "local solves one substructure per launch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, run one plain device copy of this many MiB "
                          "(a known-size reference for hardware byte counters)")
@@ -405,7 +407,7 @@ def main():
     c3 = args.workload == "kmeans64"
     p = meshgen.elasticity_kmeans_64() if c3 else meshgen.elasticity_layers_48()
     b = BDDC(device=0, autotune=not args.no_autotune, factor_precision=args.factor_precision,
-             per_substructure_launches=args.per_substructure_factor)
+             per_substructure_launches=args.per_substructure)
     b.setup(p, "ce", adaptive_edges=c3)
     f = torch.from_numpy(p.f).to("cuda:0")
     if args.copy_probe_mib > 0:
@@ -500,8 +502,7 @@ def main():
                    "step": "adapt(tau) + factor + pcg_solve(f), problem set up and resident",
                    "gemm_autotune": not args.no_autotune,
                    "factor_precision": args.factor_precision,
-                   "factor_launches": ("per_substructure" if args.per_substructure_factor
-                                       else "batched")},
+                   "launches": "per_substructure" if args.per_substructure else "batched"},
         "roofline": roof,
         "phases_ms": {"adapt": float(ph[:, 0].mean() * 1e3), "factor": float(ph[:, 1].mean() * 1e3),
                       "pcg_solve": float(ph[:, 2].mean() * 1e3)},

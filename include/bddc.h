@@ -76,13 +76,20 @@ typedef struct {
                                         and restore the product's output, so results
                                         do not depend on this switch.  The first call
                                         of a shape costs a few extra products. */
-  int per_substructure_launches;     /* nonzero: bddc_factor runs the Cholesky of
-                                        K_rr, the two TRSMs of Phi and the S_pi
-                                        product once per substructure instead of
-                                        once for all substructures together (a
-                                        baseline for the batched launches; the
-                                        results agree to rounding, not bitwise,
-                                        since tile shapes follow the batch) */
+  int per_substructure_launches;     /* nonzero: the unbatched baseline.  Every
+                                        batched dense operation (Cholesky, TRSM,
+                                        GEMM of the interior fronts, the pair
+                                        eliminations, reduced pair matrices, K_rr,
+                                        Phi, S_pi) runs one launch sequence per
+                                        entry; the interior fronts of one
+                                        substructure at a time (those of a depth
+                                        batched), LOBPCG one face pair per
+                                        launch, the PCG's Schur products and
+                                        local triangular solves one substructure
+                                        per launch.  Data-movement kernels stay
+                                        batched.  Results agree with the batched
+                                        ones to rounding (tile shapes follow the
+                                        batch); the GEMM tuner is not used */
 } bddc_options;
 
 /* Q1 hexahedral mesh (Sec. 2: substructure matrices are subassembled from

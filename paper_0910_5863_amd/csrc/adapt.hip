@@ -1507,8 +1507,15 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
     HIPCHK(hipMemcpyAsync(ldb.p, lda.data(), sizeof(LobDesc) * na, hipMemcpyHostToDevice, stream));
     {
       LaunchScope ls(stream, "lobpcg_kernel", 0, 0);
-      lobpcg_kernel<<<na, LOB_NT, 0, stream>>>(LP, ldb.as<LobDesc>(), outb.as<LobOut>(), maxit, tol,
-                                            tol_ind);
+      if (per_entry_launches()) {
+        // unbatched baseline: one face pair per launch
+        for (int a = 0; a < na; ++a)
+          lobpcg_kernel<<<1, LOB_NT, 0, stream>>>(LP, ldb.as<LobDesc>() + a, outb.as<LobOut>() + a,
+                                                  maxit, tol, tol_ind);
+      } else {
+        lobpcg_kernel<<<na, LOB_NT, 0, stream>>>(LP, ldb.as<LobDesc>(), outb.as<LobOut>(), maxit, tol,
+                                                 tol_ind);
+      }
       HIPCHK(hipGetLastError());
     }
     std::vector<LobOut> lo(na);

@@ -32,18 +32,20 @@ inline bddc_status fail(bddc_ctx *c, int code, const std::string &m) {
 }
 
 // runs f, turning exceptions into status codes and the context's message;
-// the per-launch timing hook and the GEMM autotuning switch hold for the
-// duration of the call
+// the per-launch timing hook, the GEMM autotuning switch and the unbatched
+// (per-substructure) launch switch hold for the duration of the call
 template <class F>
 bddc_status guarded(bddc_ctx *c, F f) {
   struct Hook {
     explicit Hook(bddc_ctx *c) {
       launch_timing() = (c && c->S && c->S->timer.mode == 2) ? &c->S->timer : nullptr;
       autotune_enabled() = c && c->opt.autotune != 0;
+      per_entry_launches() = c && c->opt.per_substructure_launches != 0;
     }
     ~Hook() {
       launch_timing() = nullptr;
       autotune_enabled() = false;
+      per_entry_launches() = false;
     }
   } hook(c);
   try {

@@ -32,6 +32,18 @@ LaunchTiming *&launch_timing();  // the calling thread's slot (nullptr: off)
 // then on (a table shared by the process).  Calls under stream capture use
 // the table but never tune.
 bool &autotune_enabled();   // the calling thread's switch (default off)
+
+// Unbatched launches (the per-substructure baseline).  When on for the
+// calling thread, every DenseOps call with more than one entry runs as one
+// launch sequence per entry, the same operations entry by entry, and the GEMM
+// tuner is not consulted.  Callers that batch by a coarser unit (the fronts
+// of one substructure) switch it off around their calls (PerEntryOff).
+bool &per_entry_launches();  // the calling thread's switch (default off)
+struct PerEntryOff {
+  bool saved;
+  PerEntryOff() : saved(per_entry_launches()) { per_entry_launches() = false; }
+  ~PerEntryOff() { per_entry_launches() = saved; }
+};
 int64_t autotune_entries();  // signatures tuned so far in this process
 
 struct LaunchScope {

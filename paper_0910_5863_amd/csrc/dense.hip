@@ -941,6 +941,11 @@ bool &autotune_enabled() {
   return on;
 }
 
+bool &per_entry_launches() {
+  static thread_local bool on = false;
+  return on;
+}
+
 int64_t autotune_entries() {
   std::lock_guard<std::mutex> g(tune_mutex());
   return (int64_t)tune_table().size();
@@ -967,6 +972,13 @@ hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const
                              int batch, int maxM, int maxN, bool transA, bool transB, T alpha,
                              T beta, bool lower, const GemmDesc *h_desc) {
   if (batch <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
+  if (per_entry_launches() && batch > 1 && h_desc) {
+    for (int e = 0; e < batch; ++e)
+      if (h_desc[e].M > 0 && h_desc[e].N > 0)
+        HIP_RETURN_IF(gemm(st, A, B, C, d_desc + e, 1, h_desc[e].M, h_desc[e].N, transA, transB, alpha,
+                           beta, lower, h_desc + e));
+    return hipSuccess;
+  }
   double fl = 0, by = 0;
   if (launch_timing() && h_desc)
     for (int e = 0; e < batch; ++e) {
@@ -987,7 +999,7 @@ hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const
   // 128 x 128 tiles for large products, 64 x 64 otherwise, unless the tuner
   // has measured this shape
   int shape = (maxM >= 256 && maxN >= 256) ? 0 : 1;
-  if (autotune_enabled() && h_desc) {
+  if (autotune_enabled() && h_desc && !per_entry_launches()) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIP_RETURN_IF(hipStreamIsCapturing(st, &cs));
     if (cs == hipStreamCaptureStatusNone) {
@@ -1012,6 +1024,13 @@ hipError_t DenseOps<T>::gemm_scatter(hipStream_t st, const T *A, const T *B, T *
                                      bool map_rows, int batch, int maxM, int maxN,
                                      const GemmDesc *h_desc) {
   if (batch <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
+  if (per_entry_launches() && batch > 1 && h_desc) {
+    for (int e = 0; e < batch; ++e)
+      if (h_desc[e].M > 0 && h_desc[e].N > 0)
+        HIP_RETURN_IF(gemm_scatter(st, A, B, C, d_desc + e, map, map_off + e, map_rows, 1,
+                                   h_desc[e].M, h_desc[e].N, h_desc + e));
+    return hipSuccess;
+  }
   double fl = 0, by = 0;
   if (launch_timing() && h_desc)
     for (int e = 0; e < batch; ++e) {
@@ -1038,6 +1057,12 @@ template <class T>
 hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
                               const MatDesc *h_desc, int batch, int *status, T *dinv,
                               const int64_t *dinv_off) {
+  if (per_entry_launches() && batch > 1) {
+    for (int e = 0; e < batch; ++e)
+      HIP_RETURN_IF(potrf(st, pool, d_desc + e, h_desc + e, 1, status ? status + e : nullptr, dinv,
+                          dinv_off + e));
+    return hipSuccess;
+  }
   int maxn = 0;
   for (int e = 0; e < batch; ++e) maxn = std::max(maxn, h_desc[e].n);
   if (maxn == 0) return hipSuccess;
@@ -1113,6 +1138,11 @@ template <class T>
 hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc *d_desc,
                              const MatDesc *h_desc, int batch, bool transpose, const T *dinv,
                              const int64_t *dinv_off) {
+  if (per_entry_launches() && batch > 1) {
+    for (int e = 0; e < batch; ++e)
+      HIP_RETURN_IF(trsm(st, pool_a, pool_b, d_desc + e, h_desc + e, 1, transpose, dinv, dinv_off + e));
+    return hipSuccess;
+  }
   int maxn = 0, maxr = 0;
   for (int e = 0; e < batch; ++e) {
     maxn = std::max(maxn, h_desc[e].n);

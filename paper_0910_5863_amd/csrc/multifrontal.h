@@ -101,6 +101,11 @@ class MfDevice {
   std::vector<int> max_pb_;                        // per depth: max p + b
   std::vector<int> max_p_, max_b_;                 // per depth: max p, max b
   DBuf d_zp_;                                      // solves: z of every front's pivots
+  // per depth and substructure: [begin, end) of its fronts in the level list,
+  // in the potrf entries and in the trsm / gemm entries (fronts of a depth
+  // are ordered by substructure); used by the unbatched launches
+  std::vector<std::vector<int>> lvl_lo_, pot_lo_, trs_lo_;
+  int nsub_ = 0;
   int64_t nnz_ = 0;
 };
 

@@ -86,8 +86,8 @@ __global__ void mf_pull_kernel(const MfFront *F, const int *ids, const int *chil
 // S_s (lower) += the contributions of substructure s's top fronts
 __global__ void mf_root_pull_kernel(const MfFront *F, const int *root_ptr, const int *root_ids,
                                     const int *pmap, const double *C, double *S,
-                                    const int64_t *offGG, const int *nG) {
-  const int s = blockIdx.y;
+                                    const int64_t *offGG, const int *nG, int s0) {
+  const int s = blockIdx.y + s0;
   const int ng = nG[s];
   const int r0 = root_ptr[s], r1 = root_ptr[s + 1];
   if (r0 == r1) return;
@@ -380,6 +380,28 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
   }
   level_off_[D + 1] = (int64_t)ids.size();
   d_level_ids_ = upload(A, st, ids);
+  // per-substructure ranges of every depth's lists
+  nsub_ = (int)P.subs.size();
+  lvl_lo_.assign(D + 1, std::vector<int>(nsub_ + 1, 0));
+  pot_lo_ = lvl_lo_;
+  trs_lo_ = lvl_lo_;
+  for (int d = 0; d <= D; ++d) {
+    std::vector<int> nl(nsub_, 0), npo(nsub_, 0), ntr(nsub_, 0);
+    int last = -1;
+    for (int t : M.levels[d]) {
+      const MfFront &f = M.fronts[t];
+      if (f.sub < last) throw ArgError("interior elimination: fronts of a depth not ordered by substructure");
+      last = f.sub;
+      nl[f.sub]++;
+      if (f.p > 0) npo[f.sub]++;
+      if (f.p > 0 && f.b > 0) ntr[f.sub]++;
+    }
+    for (int q = 0; q < nsub_; ++q) {
+      lvl_lo_[d][q + 1] = lvl_lo_[d][q] + nl[q];
+      pot_lo_[d][q + 1] = pot_lo_[d][q] + npo[q];
+      trs_lo_[d][q + 1] = trs_lo_[d][q] + ntr[q];
+    }
+  }
   // inverses of the diagonal blocks of every front's L11, per depth
   std::vector<std::vector<int64_t>> doff(D + 1);
   int64_t dtot = 0;
@@ -447,15 +469,17 @@ void MfDevice::factor(hipStream_t st, const double *val, int64_t nnz, double *S,
     HIPCHK(hipGetLastError());
   }
   int *status = d_status_.as<int>();
-  for (int d = M.max_depth; d >= 1; --d) {
-    const int nf = (int)M.levels[d].size();
-    if (nf == 0) continue;
-    const int *lid = ids + level_off_[d];
+  // one depth of fronts: level entries [l0, l1), potrf entries [p0, p1), trsm /
+  // gemm entries [t0, t1)
+  auto depth = [&](int d, int l0, int l1, int p0, int p1, int t0, int t1) {
+    const int nf = l1 - l0;
+    if (nf == 0) return;
+    const int *lid = ids + level_off_[d] + l0;
     {
       double by = 0;
       if (launch_timing())
-        for (int t : M.levels[d]) {
-          const MfFront &f = M.fronts[t];
+        for (int k = l0; k < l1; ++k) {
+          const MfFront &f = M.fronts[M.levels[d][k]];
           by += 8.0 * ((double)f.p * (f.p + f.b) + 0.5 * (double)f.b * f.b);
           for (int ci = 0; ci < f.n_child; ++ci) by += 4.0 * M.fronts[M.child_ids[f.child_ptr + ci]].b * 0.5 * M.fronts[M.child_ids[f.child_ptr + ci]].b;
         }
@@ -465,29 +489,44 @@ void MfDevice::factor(hipStream_t st, const double *val, int64_t nnz, double *S,
                                                                  d_pmap_.as<int>(), U, C);
       HIPCHK(hipGetLastError());
     }
-    const int np = (int)h_potrf_[d].size();
+    const int np = p1 - p0;
     if (np > 0)
-      HIPCHK(DenseOps<double>::potrf(st, U, d_potrf_[d].as<MatDesc>(), h_potrf_[d].data(), np,
-                                     status + level_off_[d], d_dinv_.as<double>(),
-                                     d_dinv_off_[d].as<int64_t>()));
-    const int nt = (int)h_trsm_[d].size();
+      HIPCHK(DenseOps<double>::potrf(st, U, d_potrf_[d].as<MatDesc>() + p0, h_potrf_[d].data() + p0, np,
+                                     status + level_off_[d] + p0, d_dinv_.as<double>(),
+                                     d_dinv_off_[d].as<int64_t>() + p0));
+    const int nt = t1 - t0;
     if (nt > 0) {
-      HIPCHK(DenseOps<double>::trsm(st, U, U, d_trsm_[d].as<MatDesc>(), h_trsm_[d].data(), nt, false,
-                                    d_dinv_.as<double>(), d_dinv_toff_[d].as<int64_t>()));
+      HIPCHK(DenseOps<double>::trsm(st, U, U, d_trsm_[d].as<MatDesc>() + t0, h_trsm_[d].data() + t0, nt,
+                                    false, d_dinv_.as<double>(), d_dinv_toff_[d].as<int64_t>() + t0));
       int maxb = 0;
-      for (const GemmDesc &g : h_gemm_[d]) maxb = std::max(maxb, g.M);
-      HIPCHK(DenseOps<double>::gemm(st, U, U, C, d_gemm_[d].as<GemmDesc>(), nt, maxb, maxb, true, false,
-                                    -1.0, 1.0, true, h_gemm_[d].data()));
+      for (int k = t0; k < t1; ++k) maxb = std::max(maxb, h_gemm_[d][k].M);
+      HIPCHK(DenseOps<double>::gemm(st, U, U, C, d_gemm_[d].as<GemmDesc>() + t0, nt, maxb, maxb, true,
+                                    false, -1.0, 1.0, true, h_gemm_[d].data() + t0));
     }
-  }
-  if (max_nG > 0 && nsub > 0) {
+  };
+  auto root_pull = [&](int s0, int count) {
+    if (max_nG <= 0 || count <= 0) return;
     if ((int64_t)max_nG * max_nG >= ((int64_t)1 << 31))  // 32-bit indices in mf_root_pull_kernel
       throw ArgError("an interface of 46341 dofs or more");
     const unsigned gx = (unsigned)std::min<int64_t>(4096, ((int64_t)max_nG * max_nG + TPB - 1) / TPB);
     LaunchScope ls(st, "mf_root_pull_kernel", 0, 0);
-    mf_root_pull_kernel<<<dim3(std::max(1u, gx), nsub), TPB, 0, st>>>(
-        F, d_root_ptr_.as<int>(), d_root_ids_.as<int>(), d_pmap_.as<int>(), C, S, offGG, nG);
+    mf_root_pull_kernel<<<dim3(std::max(1u, gx), count), TPB, 0, st>>>(
+        F, d_root_ptr_.as<int>(), d_root_ids_.as<int>(), d_pmap_.as<int>(), C, S, offGG, nG, s0);
     HIPCHK(hipGetLastError());
+  };
+  if (per_entry_launches() && nsub > 1) {
+    // unbatched: one substructure at a time, its fronts of a depth batched
+    PerEntryOff off;
+    for (int q = 0; q < nsub; ++q) {
+      for (int d = M.max_depth; d >= 1; --d)
+        depth(d, lvl_lo_[d][q], lvl_lo_[d][q + 1], pot_lo_[d][q], pot_lo_[d][q + 1], trs_lo_[d][q],
+              trs_lo_[d][q + 1]);
+      root_pull(q, 1);
+    }
+  } else {
+    for (int d = M.max_depth; d >= 1; --d)
+      depth(d, 0, (int)M.levels[d].size(), 0, (int)h_potrf_[d].size(), 0, (int)h_trsm_[d].size());
+    root_pull(0, nsub);
   }
   // pivots
   std::vector<int> hs(M.fronts.size() + 1);
@@ -533,39 +572,52 @@ void MfDevice::solve(hipStream_t st, double *vI, double *upd_w, double *zp_w) {
   };
   const bool tm = launch_timing() != nullptr;
   double *zp = zp_w ? zp_w : d_zp_.as<double>();
-  for (int d = M.max_depth; d >= 1; --d) {
-    const int nf = (int)M.levels[d].size();
-    if (nf == 0) continue;
+  // forward and backward sweeps over the fronts [l0, l1) of each depth
+  auto fwd = [&](int d, int l0, int l1) {
+    const int nf = l1 - l0;
+    if (nf == 0) return;
+    const int *lid = ids + level_off_[d] + l0;
     {
       LaunchScope ls(st, "mf_fwd_kernel", tm ? tri_bytes(d) : 0, 0);
       mf_fwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
-          F, ids + level_off_[d], d_child_.as<int>(), d_pmap_.as<int>(), d_piv_.as<int64_t>(), U,
+          F, lid, d_child_.as<int>(), d_pmap_.as<int>(), d_piv_.as<int64_t>(), U,
           d_dinv_.as<double>(), d_dinv_front_.as<int64_t>(), upd, vI, zp);
     }
     const int nc = (max_b_[d] + 63) / 64;
     if (nc > 0) {
       LaunchScope ls(st, "mf_fupd_kernel", tm ? f12_bytes(d) : 0, 0);
       mf_fupd_kernel<<<nf * nc, TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
-          F, ids + level_off_[d], nc, d_child_.as<int>(), d_pmap_.as<int>(), U, zp, upd);
+          F, lid, nc, d_child_.as<int>(), d_pmap_.as<int>(), U, zp, upd);
     }
     HIPCHK(hipGetLastError());
-  }
-  for (int d = 1; d <= M.max_depth; ++d) {
-    const int nf = (int)M.levels[d].size();
-    if (nf == 0) continue;
+  };
+  auto bwd = [&](int d, int l0, int l1) {
+    const int nf = l1 - l0;
+    if (nf == 0) return;
+    const int *lid = ids + level_off_[d] + l0;
     const int nc = (max_p_[d] + 63) / 64;
     if (nc > 0) {
       LaunchScope ls(st, "mf_bprod_kernel", tm ? f12_bytes(d) : 0, 0);
       mf_bprod_kernel<<<nf * nc, TPB, sizeof(double) * std::max(1, max_b_[d]), st>>>(
-          F, ids + level_off_[d], nc, d_piv_.as<int64_t>(), d_bnd_.as<int64_t>(), U, vI, zp);
+          F, lid, nc, d_piv_.as<int64_t>(), d_bnd_.as<int64_t>(), U, vI, zp);
     }
     {
       LaunchScope ls(st, "mf_bwd_kernel", tm ? tri_bytes(d) : 0, 0);
       mf_bwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
-          F, ids + level_off_[d], d_piv_.as<int64_t>(), U, d_dinv_.as<double>(),
-          d_dinv_front_.as<int64_t>(), zp, vI);
+          F, lid, d_piv_.as<int64_t>(), U, d_dinv_.as<double>(), d_dinv_front_.as<int64_t>(), zp,
+          vI);
     }
     HIPCHK(hipGetLastError());
+  };
+  if (per_entry_launches() && nsub_ > 1) {
+    // unbatched: one substructure at a time
+    for (int q = 0; q < nsub_; ++q) {
+      for (int d = M.max_depth; d >= 1; --d) fwd(d, lvl_lo_[d][q], lvl_lo_[d][q + 1]);
+      for (int d = 1; d <= M.max_depth; ++d) bwd(d, lvl_lo_[d][q], lvl_lo_[d][q + 1]);
+    }
+  } else {
+    for (int d = M.max_depth; d >= 1; --d) fwd(d, 0, (int)M.levels[d].size());
+    for (int d = 1; d <= M.max_depth; ++d) bwd(d, 0, (int)M.levels[d].size());
   }
 }
 

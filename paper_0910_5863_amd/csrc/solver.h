@@ -225,7 +225,12 @@ class Solver {
   hipEvent_t pcg_ev[2] = {nullptr, nullptr};
   int *pcg_pin = nullptr;
   bool use_graphs = true;
-  bool per_sub_launches = false;  // factor's dense operations one substructure at a time
+  // unbatched baseline: the PCG's Schur products and local triangular solves
+  // one substructure at a time (the dense operations follow the calling
+  // thread's per_entry_launches switch)
+  bool per_sub_launches = false;
+  std::vector<TrsvPlan> sub_plans;  // per substructure (per_sub_launches)
+  std::vector<DBuf> sub_plan_bufs;
   void pcg_iteration();
   void drop_pcg_graph();
 };

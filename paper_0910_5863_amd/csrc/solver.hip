@@ -268,9 +268,9 @@ constexpr int SYMV_NT = 256;
 __global__ __launch_bounds__(SYMV_NT) void symv_panel_kernel(const double *spool, const int64_t *soff,
                                                              const int *nG, const double *x,
                                                              const int64_t *xoff, double *y,
-                                                             double *part, const int64_t *poff) {
+                                                             double *part, const int64_t *poff, int s0) {
   __shared__ double red[2][4][64];
-  const int s = blockIdx.y, n = nG[s], c0 = 64 * blockIdx.x;
+  const int s = blockIdx.y + s0, n = nG[s], c0 = 64 * blockIdx.x;
   if (c0 >= n) return;
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const double *A = spool + soff[s];
@@ -310,8 +310,8 @@ __global__ __launch_bounds__(SYMV_NT) void symv_panel_kernel(const double *spool
 }
 
 __global__ void symv_reduce_kernel(const int *nG, const int64_t *xoff, double *y, const double *part,
-                                   const int64_t *poff) {
-  const int s = blockIdx.y, n = nG[s];
+                                   const int64_t *poff, int s0) {
+  const int s = blockIdx.y + s0, n = nG[s];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int J = r / 64;
@@ -717,6 +717,9 @@ void Solver::release(DBuf &b) {
 void Solver::free_all() {
   drop_pcg_graph();
   for (DBuf *b : all_buffers()) release(*b);
+  for (DBuf &b : sub_plan_bufs) release(b);
+  sub_plan_bufs.clear();
+  sub_plans.clear();
 }
 
 void Solver::drop_pcg_graph() {
@@ -1018,6 +1021,32 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
     return total;
   };
   int w1 = plan(L.nr, d_trsv_rr_fwd, d_trsv_rr_bwd, d_trsv_rr_off, plan_rr);
+  // per_sub_launches: one plan per substructure (its blocks only; flags from 0)
+  for (DBuf &b : sub_plan_bufs) release(b);
+  sub_plan_bufs.clear();
+  sub_plans.clear();
+  if (per_sub_launches)
+    for (int q = 0; q < ns; ++q) {
+      const int nb = (L.nr[q] + NB - 1) / NB;
+      std::vector<int> fw, bw, off(ns, 0);
+      for (int k = 0; k < nb; ++k) {
+        fw.push_back(q), fw.push_back(k);
+        bw.push_back(q), bw.push_back(nb - 1 - k);
+      }
+      TrsvPlan pq;
+      pq.batch = 1;
+      pq.total_blocks = nb;
+      sub_plan_bufs.push_back(upload(alloc, st, fw.empty() ? std::vector<int>{0} : fw));
+      sub_plan_bufs.push_back(upload(alloc, st, bw.empty() ? std::vector<int>{0} : bw));
+      sub_plan_bufs.push_back(upload(alloc, st, off));
+      const size_t k = sub_plan_bufs.size();
+      pq.d_order_fwd = sub_plan_bufs[k - 3].as<int>();
+      pq.d_order_bwd = sub_plan_bufs[k - 2].as<int>();
+      pq.d_flag_off = sub_plan_bufs[k - 1].as<int>();
+      pq.tri_elems = 0.5 * (double)L.nr[q] * (L.nr[q] + 1);
+      pq.rows = L.nr[q];
+      sub_plans.push_back(pq);
+    }
   int w3 = plan({(int)nc}, d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, plan_c);
   d_work_i = alloc0(alloc, st, sizeof(int) * (size_t)(4 + std::max(w1, w3)));
   d_status = alloc0(alloc, st, sizeof(int) * (size_t)(2 * ns + 2));
@@ -1285,12 +1314,10 @@ void Solver::factor() {
          (int64_t)L.max_nr * L.max_np, 1.0);
   gather(d_Spi, d_offPP, d_np, d_pidx, d_pidx_off, d_np, d_pidx, d_pidx_off, d_np,
          (int64_t)L.max_np * L.max_np, 1.0);
-  // constrained local factor and coarse basis (FP64 in both precisions:
-  // S_pi = K_pi,pi - K_pi,r K_rr^-1 K_r,pi is a difference of nearly equal
-  // terms at high coefficient contrast)
-  // all substructures in each launch sequence, or (per_sub_launches) one
-  // substructure per sequence: the same operations entry by entry
-  const int ng = per_sub_launches ? ns : 1, gs = per_sub_launches ? 1 : ns;
+  // constrained local factor and coarse basis (FP64, or FP32 local factors
+  // with an FP64 Galerkin coarse matrix: factor_local_fp32); all substructures
+  // in each launch sequence, or with per_substructure_launches one sequence
+  // per substructure (the dense operations follow per_entry_launches)
   const MatDesc *dRR = d_descRR.as<MatDesc>();
   const int64_t *dio = d_dinv_rr_off.as<int64_t>();
   fp32_fallbacks = 0;
@@ -1298,24 +1325,16 @@ void Solver::factor() {
     factor_local_fp32(status);
   } else {
     timer.begin(st, "factor_potrf_local", 8.0 * L.sRR, fl_rr);
-    for (int g = 0; g < ng; ++g)
-      HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), dRR + g * gs, h_descRR.data() + g * gs,
-                                     gs, status + ns + g * gs, d_dinv_rr.as<double>(), dio + g * gs));
+    HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), dRR, h_descRR.data(), ns, status + ns,
+                                   d_dinv_rr.as<double>(), dio));
     timer.end(st);
-    for (int g = 0; g < ng; ++g)
-      HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR + g * gs,
-                                    h_descRR.data() + g * gs, gs, false, d_dinv_rr.as<double>(),
-                                    dio + g * gs));
-    for (int g = 0; g < ng; ++g) {
-      const int mm = per_sub_launches ? h_spi[g].M : L.max_np, nn = per_sub_launches ? h_spi[g].N : L.max_np;
-      HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
-                                    d_spi_desc.as<GemmDesc>() + g * gs, gs, mm, nn, true, false, -1.0,
-                                    1.0, false, h_spi.data() + g * gs));
-    }
-    for (int g = 0; g < ng; ++g)
-      HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR + g * gs,
-                                    h_descRR.data() + g * gs, gs, true, d_dinv_rr.as<double>(),
-                                    dio + g * gs));
+    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR, h_descRR.data(), ns,
+                                  false, d_dinv_rr.as<double>(), dio));
+    HIPCHK(DenseOps<double>::gemm(st, d_Phi.as<double>(), d_Phi.as<double>(), d_Spi.as<double>(),
+                                  d_spi_desc.as<GemmDesc>(), ns, L.max_np, L.max_np, true, false, -1.0,
+                                  1.0, false, h_spi.data()));
+    HIPCHK(DenseOps<double>::trsm(st, d_Lrr.as<double>(), d_Phi.as<double>(), dRR, h_descRR.data(), ns,
+                                  true, d_dinv_rr.as<double>(), dio));
     if (L.sRP > 0) {
       axpby_kernel<<<nblocks(L.sRP), TPB, 0, st>>>(d_Phi.as<double>(), d_Phi.as<double>(), 0.0, -1.0,
                                                    L.sRP);
@@ -1490,11 +1509,24 @@ void Solver::check_status(bool all) {
 
 void Solver::trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
                   const DBuf &dinv_off, double *x, bool upper, const ApplyWork &w) {
+  // the substructures' local solves one at a time (per_sub_launches)
+  if (&plan == &plan_rr && !sub_plans.empty()) {
+    for (const TrsvPlan &pq : sub_plans)
+      HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), pq, upper,
+                                  dinv.as<double>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
+    return;
+  }
   HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), plan, upper,
                               dinv.as<double>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
 }
 void Solver::trsv32(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
                     const DBuf &dinv_off, float *x, bool upper, const ApplyWork &w) {
+  if (&plan == &plan_rr && !sub_plans.empty()) {
+    for (const TrsvPlan &pq : sub_plans)
+      HIPCHK(trsv_blocked<float>(stream, A.as<float>(), x, desc.as<MatDesc>(), pq, upper,
+                                 dinv.as<float>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
+    return;
+  }
   HIPCHK(trsv_blocked<float>(stream, A.as<float>(), x, desc.as<MatDesc>(), plan, upper,
                              dinv.as<float>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
 }
@@ -1613,16 +1645,23 @@ void Solver::schur_gamma(const double *p, double *q) {
     // written and read once, x read per panel and y written
     const double by = bytes_S_sym + 2.0 * 8.0 * symv_parts + 16.0 * L.sumG;
     timer.begin(st, "schur_symv", by, 2.0 * (double)L.sGG);
-    {
-      LaunchScope ls(st, "symv_kernel", bytes_S_sym + 8.0 * symv_parts + 16.0 * L.sumG, 2.0 * (double)L.sGG);
-      symv_panel_kernel<<<dim3((L.max_nG + 63) / 64, L.nsub), SYMV_NT, 0, st>>>(
-          d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), vG, d_offG.as<int64_t>(), vG2,
-          d_symv_part.as<double>(), d_symv_off.as<int64_t>());
-    }
-    {
-      LaunchScope ls(st, "symv_reduce_kernel", 8.0 * symv_parts + 16.0 * L.sumG, (double)symv_parts);
-      symv_reduce_kernel<<<dim3(nblocks(L.max_nG), L.nsub), TPB, 0, st>>>(
-          d_nG.as<int>(), d_offG.as<int64_t>(), vG2, d_symv_part.as<double>(), d_symv_off.as<int64_t>());
+    // all substructures in one launch, or (per_sub_launches) one at a time
+    const int groups = per_sub_launches ? L.nsub : 1, gsz = per_sub_launches ? 1 : L.nsub;
+    for (int q = 0; q < groups; ++q) {
+      const int mg = per_sub_launches ? L.nG[q] : L.max_nG;
+      if (mg == 0) continue;
+      {
+        LaunchScope ls(st, "symv_kernel", bytes_S_sym + 8.0 * symv_parts + 16.0 * L.sumG, 2.0 * (double)L.sGG);
+        symv_panel_kernel<<<dim3((mg + 63) / 64, gsz), SYMV_NT, 0, st>>>(
+            d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), vG, d_offG.as<int64_t>(), vG2,
+            d_symv_part.as<double>(), d_symv_off.as<int64_t>(), q * gsz);
+      }
+      {
+        LaunchScope ls(st, "symv_reduce_kernel", 8.0 * symv_parts + 16.0 * L.sumG, (double)symv_parts);
+        symv_reduce_kernel<<<dim3(nblocks(mg), gsz), TPB, 0, st>>>(
+            d_nG.as<int>(), d_offG.as<int64_t>(), vG2, d_symv_part.as<double>(), d_symv_off.as<int64_t>(),
+            q * gsz);
+      }
     }
     timer.end(st);
   }

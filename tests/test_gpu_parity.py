@@ -75,6 +75,9 @@ def test_apply_matches_oracle(name):
         z_ref = o.apply(r)
         z = b.apply(torch.from_numpy(r)).cpu().numpy()[:, 0]
         assert rel(z, z_ref) < tol, (name, seed, rel(z, z_ref))
+        # element by element, relative to the largest entry
+        emax = float(np.abs(z - z_ref).max() / np.abs(z_ref).max())
+        assert emax < tol, (name, seed, emax)
     b.close()
 
 
@@ -206,24 +209,33 @@ def test_pcg_graph_matches_eager():
     b.close()
 
 
-def test_per_substructure_factor_launches():
-    """per_substructure_launches: the factor's dense operations launched one
-    substructure at a time give the oracle's solution (1e-8) and the batched
-    launches' solution to rounding (tile shapes follow the batch size)."""
+def test_per_substructure_launches():
+    """per_substructure_launches (the unbatched baseline): adapt (interior
+    fronts one substructure at a time, pair eliminations and reduced pair
+    matrices per entry, LOBPCG per face pair), factor and PCG (Schur products
+    and local solves per substructure) give the oracle's adaptive solution
+    (1e-8), the batched run's constraint count and indicator, and its solution
+    to rounding (tile shapes follow the batch size)."""
     BDDC = _gpu()
     from oracle.solver import OracleBDDC
+    from oracle.adapt import adapt
     p = meshgen.small_kmeans(meshgen.ELASTICITY, 8, 4, contrast=1e3)
-    ref = OracleBDDC(p, "ce").solve()
+    o = OracleBDDC(p, "ce")
+    ad = adapt(o.S, o.itf, o.cons, 5.0)
+    ref = OracleBDDC(p, "ce", extra_rows=ad["rows"]).solve()
     f = torch.from_numpy(p.f)
     out = []
     for per_sub in (False, True):
         b = BDDC(per_substructure_launches=per_sub)
         b.setup(p, "ce")
+        ai = b.adapt(5.0)
         b.factor()
         u, info = b.pcg_solve(f)
-        out.append((u.cpu().numpy()[:, 0], info[0].iters))
+        out.append((u.cpu().numpy()[:, 0], info[0].iters, ai.nc, ai.omega))
         b.close()
-    (ub, ib), (us, is_) = out
+    (ub, ib, nb, wb), (us, is_, ns, ws) = out
+    assert ns == nb == ref["Nc"]
+    assert abs(ws - wb) <= 1e-8 * wb and abs(ws - ad["omega"]) <= 1e-6 * ad["omega"]
     assert np.linalg.norm(us - ref["u"]) / np.linalg.norm(ref["u"]) < 1e-8
     assert np.linalg.norm(us - ub) / np.linalg.norm(ub) < 1e-12
     assert abs(is_ - ib) <= 1
