@@ -106,6 +106,13 @@ def parse_args():
                     help="instead of the step benchmark, the 64^3 k-means workload at tau = 2, "
                          "10, 100 with FP64 and FP32 local factors: one JSON line each with "
                          "iterations, kappa, phase times and the error against the FP64 oracle")
+    ap.add_argument("--nrhs", type=int, default=0, metavar="K",
+                    help="instead of the step benchmark, factor the workload once and solve K "
+                         "loads (the mesh's load scaled entrywise by U(0.5, 2), seeded per load) "
+                         "one call per load and as one call of K columns (block PCG, 8 columns "
+                         "per block): one JSON line with both rates, per-kernel figures of one "
+                         "preconditioner application with 1 and with 8 columns, and whether "
+                         "every block column has the bits of its single solve")
     ap.add_argument("--planar-cubes", type=int, nargs=2, default=None, metavar=("KMIN", "KMAX"),
                     help="instead of the step benchmark, solve the planar-cubes series (k x k "
                          "substructures of 8^3 elasticity elements, corners only) for k in "
@@ -308,6 +315,74 @@ def serving(args):
     }))
 
 
+def multi_rhs(args):
+    """K loads on one factored problem: one solve per call against one call
+    with K columns (blocks of 8 solved by a lock-step block PCG, every factor
+    read once per application for the block)."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_0910_5863_amd import BDDC
+    K = args.nrhs
+    c3 = args.workload == "kmeans64"
+    p = meshgen.elasticity_kmeans_64() if c3 else meshgen.elasticity_layers_48()
+    b = BDDC(device=0, autotune=not args.no_autotune, factor_precision=args.factor_precision)
+    b.setup(p, "ce", adaptive_edges=c3)
+    b.adapt(TAU)
+    b.factor()
+    F = np.stack([p.f * np.random.default_rng(100 + j).uniform(0.5, 2.0, p.f.shape)
+                  for j in range(K)], axis=1)
+    Fd = torch.from_numpy(F).to("cuda:0")
+    cols = [Fd[:, j].contiguous() for j in range(K)]
+    b.pcg_solve(cols[0])  # warm: graphs of the single iteration
+    b.pcg_solve(Fd[:, :min(K, 8)])  # and of the block widths used
+    if K % 8:
+        b.pcg_solve(Fd[:, :K % 8])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    singles = [b.pcg_solve(c) for c in cols]
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Ub, infos = b.pcg_solve(Fd)
+    torch.cuda.synchronize()
+    t_block = time.perf_counter() - t0
+    Ub = Ub.cpu().numpy()
+    same = all(np.array_equal(Ub[:, j], singles[j][0].cpu().numpy()[:, 0]) and
+               infos[j].iters == singles[j][1][0].iters for j in range(K))
+    # one preconditioner application with 1 and with 8 columns, every launch
+    # timed with HIP events on the library's stream
+    per = {}
+    R = torch.from_numpy(np.stack([p.f] * 8, axis=1)).to("cuda:0")
+    for m in (1, 8):
+        b.apply(R[:, :m])
+        torch.cuda.synchronize()
+        b.set_timing(2)
+        b.apply(R[:, :m])
+        torch.cuda.synchronize()
+        st = b.timing()
+        b.set_timing(0)
+        per[m] = {k: {"ms": v["ms"], "GB/s": v["bytes"] / (v["ms"] / 1e3) / 1e9 if v["ms"] > 0 else None,
+                      "launches": v["launches"]}
+                  for k, v in sorted(st.items(), key=lambda kv: -kv[1]["ms"])[:8]}
+    it = [int(i.iters) for i in infos]
+    print(json.dumps({
+        "metric": "BDDC-PCG solves/s to 1e-8 rel. residual, K loads on one factored problem",
+        "value": K / t_block, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "nrhs": K, "block_width": 8,
+        "single_calls_solves_per_s": K / t_single, "speedup": t_single / t_block,
+        "block_columns_bitwise_equal_to_single_solves": bool(same),
+        "iters_min": min(it), "iters_max": max(it),
+        "apply_kernels_1_column": per[1], "apply_kernels_8_columns": per[8],
+        "dtype": "f64" if args.factor_precision == 64 else "f32+f64", "data": "synthetic",
+        "config": {"workload": WORKLOAD_C3 if c3 else WORKLOAD_C2, "n_glob": int(p.n_glob),
+                   "tau": TAU, "rtol": RTOL,
+                   "loads": "f * U(0.5, 2) entrywise, seeds 100..100+K-1",
+                   "timed": "pcg_solve only (adapt and factor once before)"},
+    }), flush=True)
+    b.close()
+
+
 def source_sha(rel):
     with open(os.path.join(ROOT, rel), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
@@ -384,12 +459,14 @@ def main():
     if args.serving > 0:
         serving(args)
         return
-    if args.variants or args.planar_cubes or args.tau_sweep:
+    if args.variants or args.planar_cubes or args.tau_sweep or args.nrhs > 0:
         import torch
         if not torch.cuda.is_available():
             print("bench.py: no GPU visible", file=sys.stderr)
             sys.exit(1)
-        if args.tau_sweep:
+        if args.nrhs > 0:
+            multi_rhs(args)
+        elif args.tau_sweep:
             tau_sweep(args)
         elif args.variants:
             variants(args)

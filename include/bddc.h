@@ -239,7 +239,10 @@ bddc_status bddc_adapt_count(bddc_ctx *ctx, int rows_per_face, bddc_adapt_info *
 bddc_status bddc_factor(bddc_ctx *ctx);
 
 /* z = M_BDDC r (Algorithm 2) for nrhs columns.  r, z: device, n_glob x nrhs,
-   column-major with leading dimensions ldr, ldz >= n_glob. */
+   column-major with leading dimensions ldr, ldz >= n_glob.  The columns are
+   applied in blocks of up to 8: within a block every factor (interior
+   fronts, K_rr, Phi, coarse factor) is read once for all its columns.  A
+   column's result has the same bits whatever nrhs is. */
 bddc_status bddc_apply(bddc_ctx *ctx, int nrhs, const double *r, int64_t ldr, double *z,
                        int64_t ldz);
 
@@ -264,8 +267,14 @@ bddc_status bddc_apply_noalloc(bddc_ctx *ctx, int nrhs, const double *r, int64_t
    with interior Dirichlet solves, so (I - P)^T is not needed; Sec. 7: stop
    at ||r_k||_2 <= rtol ||r_0||_2, condition number from the Lanczos
    coefficients of CG).  f, u: device, n_glob x nrhs column-major, owned by
-   the caller (u written); each column is an independent solve.  After the
-   stop the true residual of the assembled system is computed with the A_i
+   the caller (u written); each column is an independent solve.  Columns are
+   solved in blocks of up to 8 by a block PCG in lock step: every
+   application of the Schur operator and of the preconditioner reads each
+   factor once for the whole block, every column keeps its own scalars and
+   stop test, and a column that has stopped is left untouched while the
+   others go on.  A column's result (solution, iterations, history, kappa)
+   has the same bits whatever nrhs is.  After the stop the true residual of
+   the assembled system is computed with the A_i, column by column
    (bddc_pcg_info.true_relres, residual_floor, refinements).  params may be
    NULL (rtol 1e-8, maxit 1000).  info may be NULL, else nrhs entries.
    Errors: BDDC_ERR_STATE before bddc_factor, BDDC_ERR_ARG for bad vectors or
@@ -380,9 +389,14 @@ typedef struct {
                                  contexts beyond this many bytes of footprint, or
                                  in the way of a new request, are destroyed least
                                  recently used first; their footprints count until
-                                 their memory is freed.  Requests on one context
-                                 run one after another.  0: every request builds
-                                 and frees its own context. */
+                                 their memory is freed.  The requests taken on
+                                 one context are solved as blocks: those with
+                                 equal PCG parameters, up to 8 per block, in one
+                                 bddc_pcg_solve call with nrhs > 1 (each
+                                 request's result has the same bits as when
+                                 solved alone); each block's results are
+                                 published when it finishes.  0: every request
+                                 builds and frees its own context. */
 } bddc_server_options;
 
 typedef struct {
@@ -397,6 +411,7 @@ typedef struct {
   bddc_pcg_info pcg;
   char error[160];            /* message of a failed request */
   int reused;                 /* 1: served by a resident factorization */
+  int batch;                  /* right-hand sides of the block PCG that solved it */
 } bddc_request_info;
 
 bddc_status bddc_server_create(const bddc_server_options *opt, bddc_server **out);

@@ -96,7 +96,8 @@ class bddc_request_info(C.Structure):
     _fields_ = [("id", C.c_int64), ("state", C.c_int), ("status", C.c_int), ("submit_s", C.c_double),
                 ("start_s", C.c_double), ("done_s", C.c_double), ("footprint_bytes", C.c_double),
                 ("n_glob", C.c_int64), ("omega", C.c_double), ("nc", C.c_int64),
-                ("pcg", bddc_pcg_info), ("error", C.c_char * 160), ("reused", C.c_int)]
+                ("pcg", bddc_pcg_info), ("error", C.c_char * 160), ("reused", C.c_int),
+                ("batch", C.c_int)]
 
 
 class bddc_kernel_stat(C.Structure):

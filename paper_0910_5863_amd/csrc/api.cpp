@@ -129,7 +129,12 @@ bddc_status bddc_apply(bddc_ctx *c, int nrhs, const double *r, int64_t ldr, doub
   if (ldr < c->P.n_glob || ldz < c->P.n_glob) return fail(c, BDDC_ERR_ARG, "leading dimension < n_glob");
   return guarded(c, [&] {
     check_hip(hipSetDevice(c->opt.device), "hipSetDevice");
-    for (int q = 0; q < nrhs; ++q) c->S->apply_global(r + q * ldr, z + q * ldz);
+    // blocks of up to Solver::kMaxRhs columns, each reading the factors once
+    const ApplyWork w = c->S->own_work();
+    for (int q0 = 0; q0 < nrhs; q0 += Solver::kMaxRhs) {
+      const int m = std::min(Solver::kMaxRhs, nrhs - q0);
+      c->S->apply_global(r + q0 * ldr, ldr, z + q0 * ldz, ldz, m, w);
+    }
     check_hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   });
 }
@@ -145,8 +150,15 @@ bddc_status bddc_pcg_solve(bddc_ctx *c, int nrhs, const double *f, int64_t ldf, 
   bool all_conv = true;
   bddc_status st = guarded(c, [&] {
     check_hip(hipSetDevice(c->opt.device), "hipSetDevice");
+    // blocks of up to Solver::kMaxRhs columns solved in lock step
+    std::vector<PcgResult> all;
+    for (int q0 = 0; q0 < nrhs; q0 += Solver::kMaxRhs) {
+      const int m = std::min(Solver::kMaxRhs, nrhs - q0);
+      std::vector<PcgResult> b = c->S->pcg_block(f + q0 * ldf, ldf, u + q0 * ldu, ldu, m, rtol, maxit);
+      all.insert(all.end(), b.begin(), b.end());
+    }
     for (int q = 0; q < nrhs; ++q) {
-      PcgResult res = c->S->pcg(f + q * ldf, u + q * ldu, rtol, maxit);
+      const PcgResult &res = all[q];
       if (info) {
         bddc_pcg_info &o = info[q];
         o.iters = res.iters;

@@ -115,13 +115,16 @@ struct DenseOps {
 template <class T>
 hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn);
 
-// One-right-hand-side triangular solves with per-block completion flags (one
-// launch per solve, all entries together): x <- L^{-1} x for a lower
-// triangular L (upper = false) or x <- U^{-1} x for an upper triangular U
-// (upper = true), both column-major at a_off with leading dimension lda; x at
-// xpool + b_off.  L^{-T} x is the upper solve with U = L^T (transpose_batched).
-// work must hold 1 + sum over entries of ceil(n/NB) ints; it is cleared by the
-// call.  err receives 1 if a wait bound is exceeded.
+// Triangular solves with per-block completion flags (one launch per solve,
+// all entries together): x <- L^{-1} x for a lower triangular L (upper =
+// false) or x <- U^{-1} x for an upper triangular U (upper = true), both
+// column-major at a_off with leading dimension lda; x at xpool + b_off, with
+// m right-hand sides (1 <= m <= kTrsvMaxCols) at column stride ldx, which
+// share every load of the factor.  A column gets the same bits for every m.
+// L^{-T} x is the upper solve with U = L^T (transpose_batched).  work must
+// hold 1 + sum over entries of ceil(n/NB) ints; it is cleared by the call.
+// err receives 1 if a wait bound is exceeded.
+constexpr int kTrsvMaxCols = 8;
 struct TrsvPlan {
   int batch = 0;
   int total_blocks = 0;
@@ -137,7 +140,7 @@ struct TrsvPlan {
 template <class T>
 hipError_t trsv_blocked(hipStream_t st, const T *apool, T *xpool, const MatDesc *d_desc,
                         const TrsvPlan &plan, bool upper, const T *dinv, const int64_t *dinv_off,
-                        int *work, int *err);
+                        int *work, int *err, int m = 1, int64_t ldx = 0);
 
 // Offsets of the diagonal-block inverses of entries of sizes n (one NB x NB
 // block per NB rows); returns the total number of elements.

@@ -637,15 +637,21 @@ __device__ __forceinline__ float readlane(float v, int l) {
 // The upper variant solves U x = b for an upper triangular U stored
 // column-major, so that L^T x = b runs on an explicit transpose of L with the
 // same coalesced access.
-template <class T, bool UPPER>
+// Several right-hand sides (m <= M columns of x, column stride ldx) share
+// every load of the factor: each tile element is multiplied into all columns
+// while in registers.  The operations on one column, and their order, are
+// the same for every M, so a column solved in a block has the bits it has
+// when solved alone.
+template <class T, bool UPPER, int M>
 __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, const MatDesc *desc,
                                                    const T *dinv, const int64_t *dinv_off,
                                                    const int *order, const int *flag_off,
-                                                   int total, int *work, int *err) {
+                                                   int total, int *work, int *err, int m,
+                                                   int64_t ldx) {
   __shared__ int s_ticket, s_ok, s_end;
   __shared__ T D[NB][NB + 1];
-  __shared__ T part[4][NB];
-  __shared__ T vs[NB];
+  __shared__ T part[4][M][NB];
+  __shared__ T vs[M][NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     s_ticket = atomicAdd(&work[0], 1);
@@ -685,9 +691,14 @@ __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, con
     const int r = i % NB, c = i / NB;
     D[r][c] = (r < w && c < w && r >= c) ? Di[r + c * NB] : T(0);
   }
-  // right-hand side of this block (only this work-group overwrites it)
-  const T rhs = (wave == 0 && lane < w) ? x[r0 + lane] : T(0);
-  T acc = T(0);
+  // right-hand sides of this block (only this work-group overwrites them)
+  for (int i = tid; i < M * NB; i += 256) {
+    const int q = i / NB, l = i % NB;
+    vs[q][l] = (q < m && l < w) ? x[r0 + l + q * ldx] : T(0);
+  }
+  T acc[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) acc[q] = T(0);
   // blocks before `last`, in rounds
   int next = UPPER ? nblk - 1 : 0;
   while (UPPER ? next > last : next < last) {
@@ -704,23 +715,36 @@ __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, con
       const int owner = UPPER ? (nblk - 1 - jb) & 3 : jb & 3;
       if (owner != wave) continue;
       const int c0 = jb * NB, wc = min(NB, d.n - c0);
-      const T xv = lane < wc ? ld_coherent(&x[c0 + lane]) : T(0);
+      T xv[M];
+#pragma unroll
+      for (int q = 0; q < M; ++q) xv[q] = (q < m && lane < wc) ? ld_coherent(&x[c0 + lane + q * ldx]) : T(0);
       const T *row = L + rl + (int64_t)c0 * lda;
       if (wc == NB) {
-        // four independent partial sums, added in a fixed order
-        T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+        // four independent partial sums per column, added in a fixed order
+        T a0[M], a1[M], a2[M], a3[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) a0[q] = a1[q] = a2[q] = a3[q] = T(0);
 #pragma unroll
         for (int c = 0; c < NB; c += 4) {
-          a0 += row[(int64_t)c * lda] * readlane(xv, c);
-          a1 += row[(int64_t)(c + 1) * lda] * readlane(xv, c + 1);
-          a2 += row[(int64_t)(c + 2) * lda] * readlane(xv, c + 2);
-          a3 += row[(int64_t)(c + 3) * lda] * readlane(xv, c + 3);
+          const T l0 = row[(int64_t)c * lda], l1 = row[(int64_t)(c + 1) * lda];
+          const T l2 = row[(int64_t)(c + 2) * lda], l3 = row[(int64_t)(c + 3) * lda];
+#pragma unroll
+          for (int q = 0; q < M; ++q) {
+            a0[q] += l0 * readlane(xv[q], c);
+            a1[q] += l1 * readlane(xv[q], c + 1);
+            a2[q] += l2 * readlane(xv[q], c + 2);
+            a3[q] += l3 * readlane(xv[q], c + 3);
+          }
         }
-        acc += (a0 + a1) + (a2 + a3);
+#pragma unroll
+        for (int q = 0; q < M; ++q) acc[q] += (a0[q] + a1[q]) + (a2[q] + a3[q]);
       } else {
-        T a = T(0);
-        for (int c = 0; c < wc; ++c) a += row[(int64_t)c * lda] * readlane(xv, c);
-        acc += a;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          T a = T(0);
+          for (int c = 0; c < wc; ++c) a += row[(int64_t)c * lda] * readlane(xv[q], c);
+          acc[q] += a;
+        }
       }
     }
     next = end;
@@ -730,45 +754,52 @@ __global__ __launch_bounds__(256) void trsv_kernel(const T *apool, T *xpool, con
     if (tid == 0 && !wait_flag(&flags[last], err)) s_ok = 0;
     __syncthreads();
     const int c0 = last * NB;
-    const T xv = lane < wl ? ld_coherent(&x[c0 + lane]) : T(0);
-    T a0 = T(0), a1 = T(0);
 #pragma unroll
-    for (int i = 0; i < 16; i += 2) {
-      a0 += pf[i] * readlane(xv, wave * 16 + i);
-      a1 += pf[i + 1] * readlane(xv, wave * 16 + i + 1);
+    for (int q = 0; q < M; ++q) {
+      const T xv = (q < m && lane < wl) ? ld_coherent(&x[c0 + lane + q * ldx]) : T(0);
+      T a0 = T(0), a1 = T(0);
+#pragma unroll
+      for (int i = 0; i < 16; i += 2) {
+        a0 += pf[i] * readlane(xv, wave * 16 + i);
+        a1 += pf[i + 1] * readlane(xv, wave * 16 + i + 1);
+      }
+      acc[q] += a0 + a1;
     }
-    acc += a0 + a1;
   }
-  part[wave][lane] = acc;
+#pragma unroll
+  for (int q = 0; q < M; ++q) part[wave][q][lane] = acc[q];
   __syncthreads();
-  if (wave == 0) {
-    T v = T(0);
-    if (lane < w) v = rhs - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
-    vs[lane] = v;
+  for (int i = tid; i < M * NB; i += 256) {
+    const int q = i / NB, l = i % NB;
+    vs[q][l] = l < w ? vs[q][l] - (part[0][q][l] + part[1][q][l] + part[2][q][l] + part[3][q][l])
+                     : T(0);
   }
   __syncthreads();
-  if (wave == 0) {
-    // x_k = D^-1 v (lower) or D^-T v (upper), D^-1 lower triangular
-    // (D is zero outside its lower triangle and vs beyond w: full-length
-    // sums with four partial sums)
+  // x_k = D^-1 v (lower) or D^-T v (upper), D^-1 lower triangular (D is zero
+  // outside its lower triangle and v beyond w: full-length sums with four
+  // partial sums); column q on wave q mod 4
+  for (int q = wave; q < M; q += 4) {
     T y0 = T(0), y1 = T(0), y2 = T(0), y3 = T(0);
 #pragma unroll 4
     for (int c = 0; c < NB; c += 4) {
       if (!UPPER) {
-        y0 += D[lane][c] * vs[c];
-        y1 += D[lane][c + 1] * vs[c + 1];
-        y2 += D[lane][c + 2] * vs[c + 2];
-        y3 += D[lane][c + 3] * vs[c + 3];
+        y0 += D[lane][c] * vs[q][c];
+        y1 += D[lane][c + 1] * vs[q][c + 1];
+        y2 += D[lane][c + 2] * vs[q][c + 2];
+        y3 += D[lane][c + 3] * vs[q][c + 3];
       } else {
-        y0 += D[c][lane] * vs[c];
-        y1 += D[c + 1][lane] * vs[c + 1];
-        y2 += D[c + 2][lane] * vs[c + 2];
-        y3 += D[c + 3][lane] * vs[c + 3];
+        y0 += D[c][lane] * vs[q][c];
+        y1 += D[c + 1][lane] * vs[q][c + 1];
+        y2 += D[c + 2][lane] * vs[q][c + 2];
+        y3 += D[c + 3][lane] * vs[q][c + 3];
       }
     }
     const T y = (y0 + y1) + (y2 + y3);
-    if (lane < w) st_coherent(&x[r0 + lane], y);
+    if (q < m && lane < w) st_coherent(&x[r0 + lane + q * ldx], y);
   }
+  // every wave that stored waits for its stores before the barrier, so the
+  // flag below is published after all of them
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   __syncthreads();
   if (tid == 0) {
     flag_publish(&flags[k]);
@@ -1283,26 +1314,50 @@ hipError_t diag_inverse(hipStream_t st, const T *pool, const MatDesc *d_desc, in
   return hipGetLastError();
 }
 
+template <class T, bool UPPER, int M>
+static void launch_trsv(hipStream_t st, const T *apool, T *xpool, const MatDesc *d_desc,
+                        const TrsvPlan &plan, const T *dinv, const int64_t *dinv_off,
+                        const int *order, int *work, int *err, int m, int64_t ldx) {
+  trsv_kernel<T, UPPER, M><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, dinv, dinv_off,
+                                                              order, plan.d_flag_off,
+                                                              plan.total_blocks, work, err, m, ldx);
+}
+
+template <class T, bool UPPER>
+static hipError_t launch_trsv_cols(hipStream_t st, const T *apool, T *xpool,
+                                   const MatDesc *d_desc, const TrsvPlan &plan, const T *dinv,
+                                   const int64_t *dinv_off, const int *order, int *work, int *err,
+                                   int m, int64_t ldx) {
+  if (m == 1)
+    launch_trsv<T, UPPER, 1>(st, apool, xpool, d_desc, plan, dinv, dinv_off, order, work, err, m, ldx);
+  else if (m == 2)
+    launch_trsv<T, UPPER, 2>(st, apool, xpool, d_desc, plan, dinv, dinv_off, order, work, err, m, ldx);
+  else if (m <= 4)
+    launch_trsv<T, UPPER, 4>(st, apool, xpool, d_desc, plan, dinv, dinv_off, order, work, err, m, ldx);
+  else if (m <= kTrsvMaxCols)
+    launch_trsv<T, UPPER, 8>(st, apool, xpool, d_desc, plan, dinv, dinv_off, order, work, err, m, ldx);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 template <class T>
 hipError_t trsv_blocked(hipStream_t st, const T *apool, T *xpool, const MatDesc *d_desc,
                         const TrsvPlan &plan, bool upper, const T *dinv, const int64_t *dinv_off,
-                        int *work, int *err) {
-  if (plan.total_blocks == 0) return hipSuccess;
+                        int *work, int *err, int m, int64_t ldx) {
+  if (plan.total_blocks == 0 || m == 0) return hipSuccess;
+  if (m < 0 || m > kTrsvMaxCols) return hipErrorInvalidValue;
   const int nz = 1 + plan.total_blocks;
   zero_ints_kernel<<<(nz + 255) / 256, 256, 0, st>>>(work, nz);
   const int *order = upper ? plan.d_order_bwd : plan.d_order_fwd;
-  // one pass over the stored triangle, the right-hand side read and written
+  // one pass over the stored triangle, the right-hand sides read and written
   LaunchScope ls(st, upper ? "trsv_kernel<upper>" : "trsv_kernel<lower>",
-                 sizeof(T) * (plan.tri_elems + 2.0 * plan.rows), 2.0 * plan.tri_elems);
+                 sizeof(T) * (plan.tri_elems + 2.0 * plan.rows * m), 2.0 * plan.tri_elems * m);
   if (!upper)
-    trsv_kernel<T, false><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, dinv, dinv_off,
-                                                            order, plan.d_flag_off,
-                                                            plan.total_blocks, work, err);
-  else
-    trsv_kernel<T, true><<<plan.total_blocks, 256, 0, st>>>(apool, xpool, d_desc, dinv, dinv_off,
-                                                           order, plan.d_flag_off,
-                                                           plan.total_blocks, work, err);
-  return hipGetLastError();
+    return launch_trsv_cols<T, false>(st, apool, xpool, d_desc, plan, dinv, dinv_off, order, work,
+                                      err, m, ldx);
+  return launch_trsv_cols<T, true>(st, apool, xpool, d_desc, plan, dinv, dinv_off, order, work, err,
+                                   m, ldx);
 }
 
 template <class T>
@@ -1343,10 +1398,10 @@ template hipError_t symmetrize_lower<double>(hipStream_t, double *, const MatDes
 template hipError_t symmetrize_lower<float>(hipStream_t, float *, const MatDesc *, int, int);
 template hipError_t trsv_blocked<double>(hipStream_t, const double *, double *, const MatDesc *,
                                          const TrsvPlan &, bool, const double *, const int64_t *,
-                                         int *, int *);
+                                         int *, int *, int, int64_t);
 template hipError_t trsv_blocked<float>(hipStream_t, const float *, float *, const MatDesc *,
                                         const TrsvPlan &, bool, const float *, const int64_t *,
-                                        int *, int *);
+                                        int *, int *, int, int64_t);
 template hipError_t diag_inverse<double>(hipStream_t, const double *, const MatDesc *, int, int,
                                          double *, const int64_t *);
 template hipError_t diag_inverse<float>(hipStream_t, const float *, const MatDesc *, int, int,

@@ -80,11 +80,15 @@ class MfDevice {
   void factor(hipStream_t st, const double *val, int64_t nnz, double *S, const int64_t *offGG,
               const int *nG, int max_nG, int nsub);
   // vI <- A_II^-1 vI on the stack of interiors, every substructure
-  // interior solves in place; upd / zp: work vectors of upd_elems() and
-  // zp_elems() doubles (nullptr: the object's own)
-  void solve(hipStream_t st, double *vI, double *upd = nullptr, double *zp = nullptr);
-  int64_t upd_elems() const { return (int64_t)(d_upd_.bytes / sizeof(double)); }
-  int64_t zp_elems() const { return (int64_t)(d_zp_.bytes / sizeof(double)); }
+  // interior solves in place, for m <= kMaxCols columns (column q at
+  // vI + q ldI); upd / zp: work vectors of m upd_elems() and m zp_elems()
+  // doubles (nullptr: the object's own).  A column gets the same bits for
+  // every m.
+  static constexpr int kMaxCols = 8;
+  void solve(hipStream_t st, double *vI, double *upd = nullptr, double *zp = nullptr, int m = 1,
+             int64_t ldI = 0);
+  int64_t upd_elems() const { return upd_n_; }  // per column
+  int64_t zp_elems() const { return zp_n_; }
   size_t bytes() const;
 
  private:
@@ -107,6 +111,7 @@ class MfDevice {
   std::vector<std::vector<int>> lvl_lo_, pot_lo_, trs_lo_;
   int nsub_ = 0;
   int64_t nnz_ = 0;
+  int64_t upd_n_ = 1, zp_n_ = 1;  // solve work per column
 };
 
 }  // namespace bddc

@@ -161,6 +161,21 @@ __device__ void upper_solve(const double *L, int ld, int n, const double *Di, do
   }
 }
 
+// Several right-hand sides: work-group -> (logical block b, column q).  The
+// m columns of a logical block are consecutive logical ids; with m > 1 the
+// grid is padded to a multiple of 8 and logical ids are laid out so that
+// consecutive ones run on one XCD (work-groups go to the 8 XCDs in turn), so
+// the columns of a front read its factor through one L2.  Column q's vectors
+// sit at vI + q ldI, upd + q upd_n, zp + q zp_n.
+__device__ __forceinline__ bool col_block(int nlog, int m, int &b, int &q) {
+  int id = blockIdx.x;
+  if (m > 1) id = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  if (id >= nlog * m) return false;
+  b = id / m;
+  q = id % m;
+  return true;
+}
+
 // forward solve of one depth, pivots: one work-group per front; the
 // right-hand side at the pivots (plus the children's updates) goes through
 // L11^-1 and the result z is written to the pivots of vI and to zp
@@ -169,10 +184,17 @@ __global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int
                                                      const int *child_ids, const int *pmap,
                                                      const int64_t *piv, const double *U,
                                                      const double *dinv, const int64_t *dinv_off,
-                                                     const double *upd, double *vI, double *zp) {
+                                                     const double *upd, double *vI, double *zp,
+                                                     int nf, int m, int64_t ldI, int64_t upd_n,
+                                                     int64_t zp_n) {
   extern __shared__ double z[];
   __shared__ double tmp[TB];
-  const MfFront f = F[ids[blockIdx.x]];
+  int fi, q;
+  if (!col_block(nf, m, fi, q)) return;
+  upd += q * upd_n;
+  vI += q * ldI;
+  zp += q * zp_n;
+  const MfFront f = F[ids[fi]];
   const int p = f.p, tid = threadIdx.x;
   for (int j = tid; j < p; j += blockDim.x) {
     double v = vI[piv[f.piv_off + j]];
@@ -184,7 +206,7 @@ __global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int
     z[j] = v;
   }
   __syncthreads();
-  if (p > 0) lower_solve(U + f.u_off, p, p, dinv + dinv_off[ids[blockIdx.x]], z, tmp);
+  if (p > 0) lower_solve(U + f.u_off, p, p, dinv + dinv_off[ids[fi]], z, tmp);
   for (int j = tid; j < p; j += blockDim.x) {
     vI[piv[f.piv_off + j]] = z[j];
     zp[f.piv_off + j] = z[j];
@@ -197,9 +219,14 @@ __global__ __launch_bounds__(256) void mf_fwd_kernel(const MfFront *F, const int
 __global__ __launch_bounds__(256) void mf_fupd_kernel(const MfFront *F, const int *ids, int nchunk,
                                                       const int *child_ids, const int *pmap,
                                                       const double *U, const double *zp,
-                                                      double *upd) {
+                                                      double *upd, int nf, int m, int64_t upd_n,
+                                                      int64_t zp_n) {
   extern __shared__ double z[];
-  const int fi = blockIdx.x / nchunk, i_lo = (blockIdx.x % nchunk) * 64;
+  int lb, q;
+  if (!col_block(nf * nchunk, m, lb, q)) return;
+  upd += q * upd_n;
+  zp += q * zp_n;
+  const int fi = lb / nchunk, i_lo = (lb % nchunk) * 64;
   const MfFront f = F[ids[fi]];
   const int p = f.p, b = f.b, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (i_lo >= b) return;
@@ -238,10 +265,15 @@ __global__ __launch_bounds__(256) void mf_fupd_kernel(const MfFront *F, const in
 __global__ __launch_bounds__(256) void mf_bprod_kernel(const MfFront *F, const int *ids, int nchunk,
                                                        const int64_t *piv, const int64_t *bnd,
                                                        const double *U, const double *vI,
-                                                       double *zp) {
+                                                       double *zp, int nf, int m, int64_t ldI,
+                                                       int64_t zp_n) {
   extern __shared__ double xb[];
   __shared__ double part[4][64];
-  const int fi = blockIdx.x / nchunk, j_lo = (blockIdx.x % nchunk) * 64;
+  int lb, col;
+  if (!col_block(nf * nchunk, m, lb, col)) return;
+  vI += col * ldI;
+  zp += col * zp_n;
+  const int fi = lb / nchunk, j_lo = (lb % nchunk) * 64;
   const MfFront f = F[ids[fi]];
   const int p = f.p, b = f.b, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (j_lo >= p) return;
@@ -274,14 +306,19 @@ __global__ __launch_bounds__(256) void mf_bprod_kernel(const MfFront *F, const i
 __global__ __launch_bounds__(256) void mf_bwd_kernel(const MfFront *F, const int *ids,
                                                      const int64_t *piv, const double *U,
                                                      const double *dinv, const int64_t *dinv_off,
-                                                     const double *zp, double *vI) {
+                                                     const double *zp, double *vI, int nf, int m,
+                                                     int64_t ldI, int64_t zp_n) {
   extern __shared__ double x[];
   __shared__ double tmp[TB];
-  const MfFront f = F[ids[blockIdx.x]];
+  int fi, q;
+  if (!col_block(nf, m, fi, q)) return;
+  zp += q * zp_n;
+  vI += q * ldI;
+  const MfFront f = F[ids[fi]];
   const int p = f.p, tid = threadIdx.x;
   for (int j = tid; j < p; j += blockDim.x) x[j] = zp[f.piv_off + j];
   __syncthreads();
-  if (p > 0) upper_solve(U + f.u_off, p, p, dinv + dinv_off[ids[blockIdx.x]], x, tmp);
+  if (p > 0) upper_solve(U + f.u_off, p, p, dinv + dinv_off[ids[fi]], x, tmp);
   for (int j = tid; j < p; j += blockDim.x) vI[piv[f.piv_off + j]] = x[j];
 }
 
@@ -345,7 +382,8 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
   d_root_ids_ = upload(A, st, M.root_ids);
   d_U_ = zeros(A, st, sizeof(double) * (size_t)M.u_size);
   d_C_ = zeros(A, st, sizeof(double) * (size_t)M.c_size);
-  d_upd_ = zeros(A, st, sizeof(double) * (size_t)M.upd_size);
+  upd_n_ = std::max<int64_t>(1, M.upd_size);
+  d_upd_ = zeros(A, st, sizeof(double) * (size_t)upd_n_ * kMaxCols);
   d_status_ = zeros(A, st, sizeof(int) * (M.fronts.size() + 1));
   // per-depth front lists and batched descriptors
   const int D = M.max_depth;
@@ -438,7 +476,8 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
     d_dinv_front_ = upload(A, st, fo);
   }
   // z of every front's pivots between the two launches of a depth
-  d_zp_ = zeros(A, st, sizeof(double) * std::max<size_t>(1, M.piv.size()));
+  zp_n_ = std::max<int64_t>(1, (int64_t)M.piv.size());
+  d_zp_ = zeros(A, st, sizeof(double) * (size_t)zp_n_ * kMaxCols);
   // the in-front solves keep p values (boundary products: b values) in LDS
   int max_lds = 0;
   for (int d = 1; d <= D; ++d) max_lds = std::max(max_lds, std::max(max_p_[d], max_b_[d]));
@@ -546,8 +585,14 @@ void MfDevice::factor(hipStream_t st, const double *val, int64_t nnz, double *S,
       }
 }
 
-void MfDevice::solve(hipStream_t st, double *vI, double *upd_w, double *zp_w) {
+void MfDevice::solve(hipStream_t st, double *vI, double *upd_w, double *zp_w, int m, int64_t ldI) {
   if (!ready) throw StateError("interior elimination not set up");
+  if (m < 1 || m > kMaxCols) throw ArgError("interior solve: bad number of columns");
+  // grid of n logical blocks times m columns (padded to a multiple of 8)
+  auto grid = [m](int64_t n) {
+    const int64_t g = n * m;
+    return (unsigned)(m > 1 ? (g + 7) / 8 * 8 : g);
+  };
   const MfSymbolic &M = sym;
   const MfFront *F = d_fronts_.as<MfFront>();
   const int *ids = d_level_ids_.as<int>();
@@ -579,15 +624,16 @@ void MfDevice::solve(hipStream_t st, double *vI, double *upd_w, double *zp_w) {
     const int *lid = ids + level_off_[d] + l0;
     {
       LaunchScope ls(st, "mf_fwd_kernel", tm ? tri_bytes(d) : 0, 0);
-      mf_fwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
+      mf_fwd_kernel<<<grid(nf), TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
           F, lid, d_child_.as<int>(), d_pmap_.as<int>(), d_piv_.as<int64_t>(), U,
-          d_dinv_.as<double>(), d_dinv_front_.as<int64_t>(), upd, vI, zp);
+          d_dinv_.as<double>(), d_dinv_front_.as<int64_t>(), upd, vI, zp, nf, m, ldI, upd_n_,
+          zp_n_);
     }
     const int nc = (max_b_[d] + 63) / 64;
     if (nc > 0) {
       LaunchScope ls(st, "mf_fupd_kernel", tm ? f12_bytes(d) : 0, 0);
-      mf_fupd_kernel<<<nf * nc, TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
-          F, lid, nc, d_child_.as<int>(), d_pmap_.as<int>(), U, zp, upd);
+      mf_fupd_kernel<<<grid((int64_t)nf * nc), TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
+          F, lid, nc, d_child_.as<int>(), d_pmap_.as<int>(), U, zp, upd, nf, m, upd_n_, zp_n_);
     }
     HIPCHK(hipGetLastError());
   };
@@ -598,14 +644,14 @@ void MfDevice::solve(hipStream_t st, double *vI, double *upd_w, double *zp_w) {
     const int nc = (max_p_[d] + 63) / 64;
     if (nc > 0) {
       LaunchScope ls(st, "mf_bprod_kernel", tm ? f12_bytes(d) : 0, 0);
-      mf_bprod_kernel<<<nf * nc, TPB, sizeof(double) * std::max(1, max_b_[d]), st>>>(
-          F, lid, nc, d_piv_.as<int64_t>(), d_bnd_.as<int64_t>(), U, vI, zp);
+      mf_bprod_kernel<<<grid((int64_t)nf * nc), TPB, sizeof(double) * std::max(1, max_b_[d]), st>>>(
+          F, lid, nc, d_piv_.as<int64_t>(), d_bnd_.as<int64_t>(), U, vI, zp, nf, m, ldI, zp_n_);
     }
     {
       LaunchScope ls(st, "mf_bwd_kernel", tm ? tri_bytes(d) : 0, 0);
-      mf_bwd_kernel<<<nf, TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
+      mf_bwd_kernel<<<grid(nf), TPB, sizeof(double) * std::max(1, max_p_[d]), st>>>(
           F, lid, d_piv_.as<int64_t>(), U, d_dinv_.as<double>(), d_dinv_front_.as<int64_t>(), zp,
-          vI);
+          vI, nf, m, ldI, zp_n_);
     }
     HIPCHK(hipGetLastError());
   };

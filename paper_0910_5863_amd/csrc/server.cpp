@@ -5,8 +5,10 @@
 // With resident factors on, the factored context of a problem stays on the
 // device after its request (on a stream of its own); later requests on the
 // same problem skip setup, adaptation and factorization, queued ones are
-// taken together, and idle contexts are evicted least recently used first
-// when the budget needs their memory.
+// taken together and solved as blocks (one block PCG for up to kBlockRhs
+// loads, reading each factor once per application for all of them), and
+// idle contexts are evicted least recently used first when the budget needs
+// their memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,6 +44,9 @@ struct Request {
   double tau = 0;
   int64_t n_glob = 0;
   uint64_t key = 0;  // fingerprint of the problem (everything but the load)
+  // resident match, resolved once per resident context: the serial of the
+  // matching one (0: none known) and the largest serial already compared
+  uint64_t match = 0, checked_upto = 0;
   // results
   bddc_request_info info{};
   std::vector<double> u;
@@ -85,6 +90,7 @@ bool same_problem(const Request &a, const Request &b) {
 
 // A factored context kept on the device for its problem.
 struct Resident {
+  uint64_t serial = 0;             // unique per resident context, increasing
   std::unique_ptr<Request> proto;  // a copy of the problem's inputs (the load unused)
   bddc_ctx *ctx = nullptr;
   hipStream_t st = nullptr;
@@ -96,6 +102,11 @@ struct Resident {
 };
 
 constexpr int kMaxTaken = 16;  // queued requests on one resident problem taken at once
+constexpr int kBlockRhs = 8;   // loads per block PCG (the library's block width)
+
+bool same_params(const Request &a, const Request &b) {
+  return a.params.rtol == b.params.rtol && a.params.maxit == b.params.maxit;
+}
 
 // Footprint estimate from the mesh and partition (see bddc_server_submit).
 double footprint(const Request &r) {
@@ -164,10 +175,28 @@ struct bddc_server {
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
   bool keep_resident() const { return opt.resident_bytes > 0; }
 
-  Resident *find_resident(const Request &r) const {
-    for (auto &e : resident)
-      if (same_problem(*e->proto, r)) return e.get();
-    return nullptr;
+  uint64_t resident_serial = 0;
+
+  // the resident context of r's problem, or null.  The byte-wise comparison
+  // of the problem runs once per (request, resident context) pair: its
+  // outcome is kept in the request (match, checked_upto), so the wake-ups of
+  // the workers, under the lock, only compare serials.
+  Resident *find_resident(Request &r) const {
+    if (r.match) {
+      for (auto &e : resident)
+        if (e->serial == r.match) return e.get();
+      r.match = 0;  // evicted
+    }
+    uint64_t upto = r.checked_upto;
+    Resident *hit = nullptr;
+    for (auto &e : resident) {
+      if (e->serial <= r.checked_upto) continue;
+      upto = std::max(upto, e->serial);
+      if (!hit && e->proto->key == r.key && same_problem(*e->proto, r)) hit = e.get();
+    }
+    r.checked_upto = upto;
+    if (hit) r.match = hit->serial;
+    return hit;
   }
   double idle_resident_bytes() const {
     double b = 0;
@@ -181,7 +210,7 @@ struct bddc_server {
   // evicted (or runs alone); a head whose problem is resident but busy waits
   bool head_admissible() const {
     if (queue.empty()) return false;
-    const Request &h = *queue.front();
+    Request &h = *queue.front();
     if (Resident *e = find_resident(h)) return !e->busy;
     return running == 0 ||
            reserved - idle_resident_bytes() + h.info.footprint_bytes <= opt.hbm_budget_bytes;
@@ -210,11 +239,12 @@ struct bddc_server {
   // builds a context for r's problem on stream st (setup, adapt, factor);
   // null on failure, with info.status and info.error set
   bddc_ctx *build(const Request &r, bddc_request_info &info, hipStream_t st);
-  // solves r on a factored context; results go to info and u (published by
+  // solves the loads of rs (same PCG parameters, at most kBlockRhs) as one
+  // block on a factored context; results go to infos and us (published by
   // the caller under the lock, so that queries never read a record being
   // written)
-  void solve(bddc_ctx *c, const Request &r, bddc_request_info &info, std::vector<double> &u,
-             hipStream_t st);
+  void solve(bddc_ctx *c, const std::vector<Request *> &rs, std::vector<bddc_request_info *> &infos,
+             std::vector<std::vector<double> *> &us, hipStream_t st);
   void worker();
 };
 
@@ -290,23 +320,50 @@ bddc_ctx *bddc_server::build(const Request &r, bddc_request_info &info, hipStrea
   return c;
 }
 
-void bddc_server::solve(bddc_ctx *c, const Request &r, bddc_request_info &info,
-                        std::vector<double> &u, hipStream_t st) {
-  const size_t nb = sizeof(double) * (size_t)r.n_glob;
+void bddc_server::solve(bddc_ctx *c, const std::vector<Request *> &rs,
+                        std::vector<bddc_request_info *> &infos,
+                        std::vector<std::vector<double> *> &us, hipStream_t st) {
+  const int m = (int)rs.size();
+  const int64_t n = rs[0]->n_glob;
+  const size_t nb = sizeof(double) * (size_t)n * m;
   double *fd = (double *)async_alloc(nb, st), *ud = (double *)async_alloc(nb, st);
-  bddc_status s;
-  if (!fd || !ud || hipMemcpyAsync(fd, r.f.data(), nb, hipMemcpyHostToDevice, st) != hipSuccess) {
-    info.status = BDDC_ERR_OOM;
-    std::snprintf(info.error, sizeof info.error, "load / solution buffers");
-  } else if ((s = bddc_pcg_solve(c, 1, fd, r.n_glob, ud, r.n_glob, &r.params, &info.pcg)) != BDDC_OK) {
-    info.status = s;
-    std::snprintf(info.error, sizeof info.error, "pcg: %s", bddc_last_error(c));
+  auto fail_all = [&](int status, const char *msg) {
+    for (bddc_request_info *i : infos) {
+      i->status = status;
+      std::snprintf(i->error, sizeof i->error, "%s", msg);
+    }
+  };
+  bool copied = fd && ud;
+  for (int q = 0; q < m && copied; ++q)
+    copied = hipMemcpyAsync(fd + q * n, rs[q]->f.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                            st) == hipSuccess;
+  if (!copied) {
+    fail_all(BDDC_ERR_OOM, "load / solution buffers");
   } else {
-    u.resize(r.n_glob);
-    if (hipMemcpyAsync(u.data(), ud, nb, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
-      info.status = BDDC_ERR_DEVICE;
-      std::snprintf(info.error, sizeof info.error, "copy of the solution");
+    std::vector<bddc_pcg_info> pinfo(m);
+    const bddc_status s = bddc_pcg_solve(c, m, fd, n, ud, n, &rs[0]->params, pinfo.data());
+    if (s != BDDC_OK && s != BDDC_ERR_NO_CONVERGENCE) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "pcg: %s", bddc_last_error(c));
+      fail_all(s, msg);
+    } else {
+      bool ok = true;
+      for (int q = 0; q < m && ok; ++q) {
+        us[q]->resize(n);
+        ok = hipMemcpyAsync(us[q]->data(), ud + q * n, sizeof(double) * n, hipMemcpyDeviceToHost,
+                            st) == hipSuccess;
+      }
+      if (ok) ok = hipStreamSynchronize(st) == hipSuccess;
+      if (!ok) fail_all(BDDC_ERR_DEVICE, "copy of the solution");
+      for (int q = 0; q < m && ok; ++q) {
+        infos[q]->pcg = pinfo[q];
+        infos[q]->batch = m;
+        if (!pinfo[q].converged) {
+          infos[q]->status = BDDC_ERR_NO_CONVERGENCE;
+          std::snprintf(infos[q]->error, sizeof infos[q]->error,
+                        "pcg: PCG did not reach the tolerance");
+        }
+      }
     }
   }
   if (fd) async_free(fd, st);
@@ -334,7 +391,7 @@ void bddc_server::worker() {
         res->busy = true;
         fresh = false;
         for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < kMaxTaken;) {
-          if (same_problem(**it, *h)) {
+          if (find_resident(**it) == res) {
             batch.push_back(*it);
             it = queue.erase(it);
           } else {
@@ -352,6 +409,7 @@ void bddc_server::worker() {
           // registered now, so requests on the same problem wait for it
           // instead of factoring it again
           auto e = std::make_unique<Resident>();
+          e->serial = ++resident_serial;
           e->proto = std::make_unique<Request>(*h);
           e->proto->f.clear();
           e->proto->mesh.xyz = e->proto->xyz.data();  // its own copies
@@ -402,13 +460,51 @@ void bddc_server::worker() {
         }
       }
     }
-    for (size_t i = 0; i < batch.size() && ok; ++i) {
-      if (!fresh) {
-        out[i].omega = res->omega;
-        out[i].nc = res->nc;
-        out[i].reused = 1;
+    // the taken requests in blocks of equal PCG parameters (arrival order
+    // within each), each block published as soon as it is solved
+    std::vector<char> published(batch.size(), 0);
+    if (ok) {
+      std::vector<size_t> order(batch.size());
+      for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        const bddc_pcg_params &x = batch[a]->params, &y = batch[b]->params;
+        return x.rtol != y.rtol ? x.rtol < y.rtol : x.maxit < y.maxit;
+      });
+      for (size_t i0 = 0; i0 < order.size();) {
+        size_t i1 = i0 + 1;
+        while (i1 < order.size() && (int)(i1 - i0) < kBlockRhs &&
+               same_params(*batch[order[i1]], *batch[order[i0]]))
+          ++i1;
+        std::vector<Request *> rs;
+        std::vector<bddc_request_info *> infos;
+        std::vector<std::vector<double> *> uv;
+        for (size_t k = i0; k < i1; ++k) {
+          const size_t i = order[k];
+          if (!fresh) {
+            out[i].omega = res->omega;
+            out[i].nc = res->nc;
+            out[i].reused = 1;
+          }
+          rs.push_back(batch[i]);
+          infos.push_back(&out[i]);
+          uv.push_back(&us[i]);
+        }
+        solve(c, rs, infos, uv, st);
+        {
+          std::lock_guard<std::mutex> lk(m);
+          for (size_t k = i0; k < i1; ++k) {
+            const size_t i = order[k];
+            Request *r = batch[i];
+            r->info = out[i];
+            r->u.swap(us[i]);
+            r->info.done_s = now();
+            r->info.state = r->info.status == BDDC_OK ? 2 : 3;
+            published[i] = 1;
+          }
+        }
+        cv_done.notify_all();
+        i0 = i1;
       }
-      solve(c, *batch[i], out[i], us[i], st);
     }
     // a context of its own is freed before its footprint is returned
     if (!res && c) {
@@ -419,6 +515,7 @@ void bddc_server::worker() {
     {
       std::lock_guard<std::mutex> lk(m);
       for (size_t i = 0; i < batch.size(); ++i) {
+        if (published[i]) continue;
         Request *r = batch[i];
         r->info = out[i];
         if (!ok && i > 0) {

@@ -103,11 +103,14 @@ struct ApplyWork {
   float *vR32 = nullptr;
   double *mf_upd = nullptr, *mf_zp = nullptr;
   int *trsv_work = nullptr, *err = nullptr;
+  int cols = 1;  // right-hand sides the vectors hold (each stack at its own length per column)
 };
 
 class Solver {
  public:
-  static constexpr int kMaxRhs = 1;
+  // right-hand sides solved together (block PCG, multi-column applies)
+  static constexpr int kMaxRhs = 8;
+  static_assert(kMaxRhs <= kTrsvMaxCols && kMaxRhs <= MfDevice::kMaxCols, "block width");
   static constexpr int kMaxIt = 5000;
 
   DevAlloc alloc;
@@ -135,16 +138,23 @@ class Solver {
   bool struct_ready = false;  // mesh / partition part of the layout is current
   void apply_global(const double *r, double *z);
   void apply_global(const double *r, double *z, const ApplyWork &w);
+  // m <= w.cols columns at strides ldr, ldz (each factor read once for all)
+  void apply_global(const double *r, int64_t ldr, double *z, int64_t ldz, int m, const ApplyWork &w);
   ApplyWork own_work();
   // bytes of a work set for apply_global (segments 256-byte aligned) and the
   // set laid out from base (device memory of at least work_bytes())
   size_t work_bytes() const;
   ApplyWork carve_work(void *base) const;
   PcgResult pcg(const double *f, double *u, double rtol, int maxit);
-  // one PCG solve on the explicit Schur operator (pcg adds the true-residual
-  // check and the correction solves); abs_tol > 0 replaces rtol by
-  // abs_tol / ||r_0||
-  PcgResult pcg_once(const double *f, double *u, double rtol, int maxit, double abs_tol = 0);
+  // m <= kMaxRhs right-hand sides in one block PCG (f, u at strides ldf,
+  // ldu), then the true-residual check and corrections per column
+  std::vector<PcgResult> pcg_block(const double *f, int64_t ldf, double *u, int64_t ldu, int m,
+                                   double rtol, int maxit);
+  // one block PCG solve on the explicit Schur operator (pcg_block adds the
+  // true-residual check and the correction solves); abs_tol[c] > 0 replaces
+  // rtol[c] by abs_tol[c] / ||r_0||
+  std::vector<PcgResult> pcg_once(const double *f, int64_t ldf, double *u, int64_t ldu, int m,
+                                  const double *rtol, int maxit, const double *abs_tol);
   // rt = f - A u over all free dofs with the substructure matrices A_i;
   // returns ||rt|| and, in *floor, eps || |A| |u| ||
   double true_residual(const double *f, const double *u, double *rt, double *floor);
@@ -157,22 +167,28 @@ class Solver {
   double iter_bytes() const;
 
   // internals (public for the adaptive module)
-  void apply_gamma(const double *r, double *z);
-  void apply_gamma_condensed(const double *r, const double *vG_cond, double *z, const ApplyWork &w);
-  void apply_local(double *b, double *z, const ApplyWork &w);
-  void apply_T_vec(double *x, double *scr);
-  void apply_Tt_vec(double *b, double *scr);
-  void schur_gamma(const double *p, double *q);
-  void harmonic_extension(const double *zg, double *z, const ApplyWork &w);
-  void interior_solve(double *vI, const ApplyWork *w = nullptr);
-  void dot(const double *a, const double *b, int64_t n, double *out);
-  void scatter_gamma(const double *zg, double *z);
-  void scatter_interior(const double *vI, double *z);
-  void scatter64(const double *src, const int64_t *idx, int64_t n, double *dst);
+  // (m: columns of a block, each vector stack at its own length per column)
+  void apply_gamma(const double *r, double *z, int m = 1);
+  void apply_gamma_condensed(const double *r, const double *vG_cond, double *z, const ApplyWork &w,
+                             int m = 1);
+  void apply_local(double *b, double *z, const ApplyWork &w, int m = 1);
+  void apply_T_vec(double *x, double *scr, int m = 1);
+  void apply_Tt_vec(double *b, double *scr, int m = 1);
+  void schur_gamma(const double *p, double *q, int m = 1);
+  void harmonic_extension(const double *zg, double *z, int64_t ldz, const ApplyWork &w, int m = 1);
+  void interior_solve(double *vI, const ApplyWork *w = nullptr, int m = 1);
+  void dot(const double *a, const double *b, int64_t n, double *out, int m = 1, int64_t lda = 0,
+           int64_t ldb = 0);
+  void scatter_gamma(const double *zg, double *z, int64_t ldz, int m = 1);
+  void scatter_interior(const double *vI, double *z, int64_t ldz, int m = 1);
+  void scatter64(const double *src, int64_t lds, const int64_t *idx, int64_t n, double *dst,
+                 int64_t ldd, int m = 1);
   void trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
-            const DBuf &dinv_off, double *x, bool upper, const ApplyWork &w);
+            const DBuf &dinv_off, double *x, bool upper, const ApplyWork &w, int m = 1,
+            int64_t ldx = 0);
   void trsv32(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
-              const DBuf &dinv_off, float *x, bool upper, const ApplyWork &w);
+              const DBuf &dinv_off, float *x, bool upper, const ApplyWork &w, int m = 1,
+              int64_t ldx = 0);
   void release(DBuf &b);
   std::vector<DBuf *> all_buffers();
   std::vector<DBuf *> struct_buffers();
@@ -201,6 +217,7 @@ class Solver {
       d_descCvec;
   DBuf d_gx, d_gx_ptr, d_trow, d_pos, d_wmat, d_gk_glob, d_gk_k, d_scr;
   int64_t scrS_elems = 0;
+  int64_t scr_elems = 1;  // T / T^T vector scratch per column
   // the two passes of T^T S T as scatter products: descriptors (column
   // pass, row pass), local glob positions and their offsets per record
   DBuf d_xf_cols, d_xf_rows, d_xf_map, d_xf_map_off;
@@ -220,7 +237,7 @@ class Solver {
   DBuf d_pcg_ctl, d_pcg_hist;  // PCG control words (stop, iterations, converged, maxit), history
   // one PCG iteration captured as a graph (rebuilt after every build); the
   // stream it is captured on, two events and pinned words for the lookahead
-  hipGraphExec_t pcg_exec = nullptr;
+  hipGraphExec_t pcg_exec[kMaxRhs + 1] = {};  // per block width
   hipStream_t cap_stream = nullptr;
   hipEvent_t pcg_ev[2] = {nullptr, nullptr};
   int *pcg_pin = nullptr;
@@ -231,7 +248,7 @@ class Solver {
   bool per_sub_launches = false;
   std::vector<TrsvPlan> sub_plans;  // per substructure (per_sub_launches)
   std::vector<DBuf> sub_plan_bufs;
-  void pcg_iteration();
+  void pcg_iteration(int m);
   void drop_pcg_graph();
 };
 

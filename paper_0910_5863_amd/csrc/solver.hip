@@ -208,19 +208,24 @@ __global__ void reduce_copies_kernel(const double *src, int64_t lds, const int *
 
 // b <- T^T b on every constrained glob: pivot values to scratch, then one
 // wave per (substructure, glob) adds W^T v to the glob positions.
+// (column q of a block: blockIdx.y, vectors at stride ld, scratch at stride ls)
 __global__ void vec_pivots_kernel(const double *b, const GlobXf *gx, int ngx, const int *pos,
-                                  double *scr) {
+                                  double *scr, int64_t ld, int64_t ls) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ngx) return;
+  b += blockIdx.y * ld;
+  scr += blockIdx.y * ls;
   const GlobXf x = gx[g];
   for (int k = 0; k < x.m; ++k) scr[x.scr_off + k] = b[pos[x.piv_off + k]];
 }
 
 __global__ void apply_Tt_kernel(double *b, const GlobXf *gx, int ngx, const double *wmat,
-                                const int *pos, const double *scr) {
+                                const int *pos, const double *scr, int64_t ld, int64_t ls) {
   const int g = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (g >= ngx) return;
+  b += blockIdx.y * ld;
+  scr += blockIdx.y * ls;
   const GlobXf x = gx[g];
   for (int t = lane; t < x.ng; t += 64) {
     double acc = 0;
@@ -233,10 +238,12 @@ __global__ void apply_Tt_kernel(double *b, const GlobXf *gx, int ngx, const doub
 // per (glob, k)), then stored at the pivots.
 __global__ void apply_T_dots_kernel(const double *xv, const GlobXf *gx, const int *gk_glob,
                                     const int *gk_k, int ngk, const double *trow, const int *pos,
-                                    double *scr) {
+                                    double *scr, int64_t ld, int64_t ls) {
   const int w = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (w >= ngk) return;
+  xv += blockIdx.y * ld;
+  scr += blockIdx.y * ls;
   const GlobXf x = gx[gk_glob[w]];
   const int k = gk_k[w];
   double acc = 0;
@@ -246,9 +253,12 @@ __global__ void apply_T_dots_kernel(const double *xv, const GlobXf *gx, const in
 }
 
 __global__ void apply_T_store_kernel(double *xv, const GlobXf *gx, const int *gk_glob,
-                                     const int *gk_k, int ngk, const int *pos, const double *scr) {
+                                     const int *gk_k, int ngk, const int *pos, const double *scr,
+                                     int64_t ld, int64_t ls) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= ngk) return;
+  xv += blockIdx.y * ld;
+  scr += blockIdx.y * ls;
   const GlobXf x = gx[gk_glob[w]];
   const int k = gk_k[w];
   xv[pos[x.piv_off + k]] = scr[x.scr_off + k];
@@ -264,69 +274,103 @@ __global__ void apply_T_store_kernel(double *xv, const GlobXf *gx, const int *gk
 // block J, a_0[r] + ... + a_{J-1}[r] in that order, so the result does not
 // depend on scheduling.  Partials of (s, J) start at off[s] + J n - 32 J (J+1)
 // (panel J holds n - 64 (J+1) rows below its diagonal block).
-constexpr int SYMV_NT = 256;
+// Eight waves of eight columns each; every element of S loaded is multiplied
+// into all m <= M right-hand sides (x, y at column stride ldx, partials at
+// ldp).  Per column the operations and their order do not depend on M.
+constexpr int SYMV_NT = 512;
+template <int M>
 __global__ __launch_bounds__(SYMV_NT) void symv_panel_kernel(const double *spool, const int64_t *soff,
                                                              const int *nG, const double *x,
-                                                             const int64_t *xoff, double *y,
-                                                             double *part, const int64_t *poff, int s0) {
-  __shared__ double red[2][4][64];
+                                                             const int64_t *xoff, int64_t ldx,
+                                                             double *y, double *part,
+                                                             const int64_t *poff, int64_t ldp,
+                                                             int s0, int m) {
+  __shared__ double xcs[M][64];         // x at the panel's 64 columns
+  __shared__ double red[2][M][8][64];   // row partial sums per wave (double buffered)
   const int s = blockIdx.y + s0, n = nG[s], c0 = 64 * blockIdx.x;
   if (c0 >= n) return;
-  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
   const double *A = spool + soff[s];
   const double *xs = x + xoff[s];
-  const int cg = c0 + 16 * g;  // this wave's 16 columns
-  double xc[16], dacc[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    xc[j] = cg + j < n ? xs[cg + j] : 0.0;
-    dacc[j] = 0.0;
+  for (int i = tid; i < M * 64; i += SYMV_NT) {
+    const int q = i / 64, c = i % 64;
+    xcs[q][c] = (q < m && c0 + c < n) ? xs[c0 + c + q * ldx] : 0.0;
   }
-  double *ps = part + poff[s] + (int64_t)blockIdx.x * n - 32ll * blockIdx.x * (blockIdx.x + 1);
+  __syncthreads();
+  const int cg = c0 + 8 * g;  // this wave's 8 columns
+  double dacc[8][M];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int q = 0; q < M; ++q) dacc[j][q] = 0.0;
+  const int64_t pstart = poff[s] + (int64_t)blockIdx.x * n - 32ll * blockIdx.x * (blockIdx.x + 1);
+  // the combining thread of the row partial sums: column tid / 64, row lane
+  const int cq = tid >> 6;
   int buf = 0;
   for (int rt = c0; rt < n; rt += 64, buf ^= 1) {
     const int r = rt + lane;
     const bool rv = r < n;
-    const double xr = rv ? xs[r] : 0.0;
-    double a = 0.0;
+    double xr[M];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double v = (rv && cg + j < n) ? A[r + (int64_t)(cg + j) * n] : 0.0;
-      dacc[j] += v * xr;
-      a += v * xc[j];
-    }
+    for (int q = 0; q < M; ++q) xr[q] = (rv && q < m) ? xs[r + q * ldx] : 0.0;
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (rv && cg + j < n) ? A[r + (int64_t)(cg + j) * n] : 0.0;
+    double a[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) a[q] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        dacc[j][q] += v[j] * xr[q];
+        a[q] += v[j] * xcs[q][8 * g + j];
+      }
     if (rt > c0) {  // rows below the diagonal block (uniform per work-group)
-      red[buf][g][lane] = a;
+#pragma unroll
+      for (int q = 0; q < M; ++q) red[buf][q][g][lane] = a[q];
       __syncthreads();
-      if (g == 0 && rv) ps[r - (c0 + 64)] = ((red[buf][0][lane] + red[buf][1][lane]) + red[buf][2][lane]) + red[buf][3][lane];
+      if (cq < m && rv) {
+        double t = red[buf][cq][0][lane];
+#pragma unroll
+        for (int w = 1; w < 8; ++w) t += red[buf][cq][w][lane];
+        part[pstart + (r - (c0 + 64)) + cq * ldp] = t;
+      }
     }
   }
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    double t = dacc[j];
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-    if (lane == 0 && cg + j < n) y[xoff[s] + cg + j] = t;
-  }
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      double t = dacc[j][q];
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+      if (lane == 0 && q < m && cg + j < n) y[xoff[s] + cg + j + q * ldx] = t;
+    }
 }
 
-__global__ void symv_reduce_kernel(const int *nG, const int64_t *xoff, double *y, const double *part,
-                                   const int64_t *poff, int s0) {
+__global__ void symv_reduce_kernel(const int *nG, const int64_t *xoff, int64_t ldx, double *y,
+                                   const double *part, const int64_t *poff, int64_t ldp, int s0) {
   const int s = blockIdx.y + s0, n = nG[s];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int J = r / 64;
-  const double *ps = part + poff[s];
-  double acc = y[xoff[s] + r];
+  const double *ps = part + poff[s] + blockIdx.z * ldp;
+  double *yy = y + xoff[s] + r + blockIdx.z * ldx;
+  double acc = *yy;
   for (int j = 0; j < J; ++j) acc += ps[(int64_t)j * n - 32ll * j * (j + 1) + (r - 64 * (j + 1))];
-  y[xoff[s] + r] = acc;
+  *yy = acc;
 }
 
-// batched GEMV on column-major blocks: y_i = alpha op(A_i) x_i + beta y_i.
+// batched GEMV on column-major blocks: y_i = alpha op(A_i) x_i + beta y_i,
+// for m <= M right-hand sides (x, y at column strides ldx, ldy) sharing the
+// loads of A.
 // trans: y[j] = sum_r A[r, j] x[r] (a wave per output, coalesced columns);
 // notrans: y[r] = sum_j A[r, j] x[j] (a thread per output row).
+template <int M>
 __global__ void gemv_t_kernel(const double *apool, const int64_t *aoff, const int *rows,
-                              const int *cols, const double *x, const int64_t *xoff,
-                              double *y, const int64_t *yoff, double alpha, double beta) {
+                              const int *cols, const double *x, const int64_t *xoff, int64_t ldx,
+                              double *y, const int64_t *yoff, int64_t ldy, double alpha,
+                              double beta, int nrhs) {
   const int s = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
@@ -334,18 +378,30 @@ __global__ void gemv_t_kernel(const double *apool, const int64_t *aoff, const in
   const int m = rows[s];
   const double *A = apool + aoff[s] + (int64_t)j * m;
   const double *xx = x + xoff[s];
-  double acc = 0;
-  for (int r = lane; r < m; r += 64) acc += A[r] * xx[r];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) {
-    double *o = y + yoff[s] + j;
-    *o = (beta == 0.0) ? alpha * acc : alpha * acc + beta * (*o);
+  double acc[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) acc[q] = 0;
+  for (int r = lane; r < m; r += 64) {
+    const double a = A[r];
+#pragma unroll
+    for (int q = 0; q < M; ++q)
+      if (q < nrhs) acc[q] += a * xx[r + q * ldx];
+  }
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+    if (lane == 0 && q < nrhs) {
+      double *o = y + yoff[s] + j + q * ldy;
+      *o = (beta == 0.0) ? alpha * acc[q] : alpha * acc[q] + beta * (*o);
+    }
   }
 }
 
+template <int M>
 __global__ void gemv_n_kernel(const double *apool, const int64_t *aoff, const int *rows,
-                              const int *cols, const double *x, const int64_t *xoff, double *y,
-                              const int64_t *yoff, double alpha, double beta) {
+                              const int *cols, const double *x, const int64_t *xoff, int64_t ldx,
+                              double *y, const int64_t *yoff, int64_t ldy, double alpha,
+                              double beta, int nrhs) {
   const int s = blockIdx.y;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int m = rows[s];
@@ -353,10 +409,21 @@ __global__ void gemv_n_kernel(const double *apool, const int64_t *aoff, const in
   const int n = cols[s];
   const double *A = apool + aoff[s];
   const double *xx = x + xoff[s];
-  double acc = 0;
-  for (int j = 0; j < n; ++j) acc += A[r + (int64_t)j * m] * xx[j];
-  double *o = y + yoff[s] + r;
-  *o = (beta == 0.0) ? alpha * acc : alpha * acc + beta * (*o);
+  double acc[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) acc[q] = 0;
+  for (int j = 0; j < n; ++j) {
+    const double a = A[r + (int64_t)j * m];
+#pragma unroll
+    for (int q = 0; q < M; ++q)
+      if (q < nrhs) acc[q] += a * xx[j + q * ldx];
+  }
+#pragma unroll
+  for (int q = 0; q < M; ++q)
+    if (q < nrhs) {
+      double *o = y + yoff[s] + r + q * ldy;
+      *o = (beta == 0.0) ? alpha * acc[q] : alpha * acc[q] + beta * (*o);
+    }
 }
 
 // per-substructure CSR products between interior and interface parts:
@@ -477,7 +544,8 @@ __global__ void unscale_f64_kernel(const float *src, double *dst, const int64_t 
 template <class S, class D>
 __global__ void convert_scaled_kernel(const S *src, D *dst, const double *d, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = (D)(d[i] * (double)src[i]);
+  const int64_t k = i + blockIdx.y * n;  // column blockIdx.y of a block
+  if (i < n) dst[k] = (D)(d[i] * (double)src[k]);
 }
 
 // dst = scale * src with a change of precision
@@ -492,10 +560,16 @@ __global__ void axpby_kernel(double *y, const double *x, double a, double b, int
   if (i < n) y[i] = b * y[i] + a * x[i];
 }
 
-// deterministic dot products: stage 1 partial sums per block (fixed order)
+// deterministic dot products: stage 1 partial sums per block (fixed order);
+// column q of a block (blockIdx.y) at a + q lda, b + q ldb, partials at
+// part + q DOT_BLOCKS, result at out[q * kScStride]
 constexpr int DOT_BLOCKS = 1024;
-__global__ void dot_partial_kernel(const double *a, const double *b, int64_t n, double *part) {
+constexpr int kScStride = 16;  // PCG scalars per column
+__global__ void dot_partial_kernel(const double *a, const double *b, int64_t n, int64_t lda,
+                                   int64_t ldb, double *part) {
   __shared__ double sh[TPB];
+  a += blockIdx.y * lda;
+  b += blockIdx.y * ldb;
   double acc = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -506,11 +580,12 @@ __global__ void dot_partial_kernel(const double *a, const double *b, int64_t n, 
     if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) part[blockIdx.x + blockIdx.y * DOT_BLOCKS] = sh[0];
 }
 
 __global__ void dot_final_kernel(const double *part, int nb, double *out) {
   __shared__ double sh[TPB];
+  part += blockIdx.x * DOT_BLOCKS;
   double acc = 0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[i];
   sh[threadIdx.x] = acc;
@@ -519,73 +594,108 @@ __global__ void dot_final_kernel(const double *part, int nb, double *out) {
     if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = sh[0];
+  if (threadIdx.x == 0) out[blockIdx.x * kScStride] = sh[0];
 }
 
-// PCG scalar updates on the device.  sc: [0] rz, [1] pq, [2] rr, [3] alpha,
-// [4] beta, [5] rz_new
-// PCG scalars live on the device: sc[0] = (r, z), sc[1] = (p, q), sc[2] =
-// (r, r), sc[3] = alpha, sc[4] = beta, sc[5] = new (r, z), sc[6] = r0,
-// sc[7] = rtol.  Control words ctl[0] = stop, ctl[1] = iterations done,
-// ctl[2] = converged, ctl[3] = maxit.  Once stop is set, every later
-// iteration leaves x, r and p untouched, so iterations launched ahead of the
-// host's check are harmless.
-__global__ void pcg_init_kernel(double *sc, int *ctl, double r0, double rtol, int maxit) {
-  sc[6] = r0;
-  sc[7] = rtol;
-  ctl[0] = 0;
-  ctl[1] = 0;
-  ctl[2] = 0;
-  ctl[3] = maxit;
+// PCG scalars live on the device, kScStride per column q at sc + q
+// kScStride: [0] = (r, z), [1] = (p, q), [2] = (r, r), [3] = alpha, [4] =
+// beta, [5] = new (r, z), [6] = r0, [7] = rtol, [11] = (r, z_old).  Control
+// words: ctl[0] = every column stopped; column q at ctl + kCtl0 + 4 q: [0] =
+// stop, [1] = iterations done, [2] = converged, [3] = maxit.  A stopped
+// column's x, r and p are left untouched by every later iteration (the
+// columns of a block run in lock step until the last one stops), and so are
+// iterations launched ahead of the host's check.  The Lanczos coefficients
+// and residual history of column q sit at alphas / betas + q (kMaxIt + 1)
+// and hist + q (kMaxIt + 2).
+constexpr int kCtl0 = 4;
+struct PcgInit {
+  double r0[Solver::kMaxRhs], rtol[Solver::kMaxRhs];
+};
+__global__ void pcg_init_kernel(double *sc, int *ctl, PcgInit in, int m, int maxit) {
+  const int q = threadIdx.x;
+  if (q < m) {
+    sc[q * kScStride + 6] = in.r0[q];
+    sc[q * kScStride + 7] = in.rtol[q];
+    int *c = ctl + kCtl0 + 4 * q;
+    const bool zero = in.r0[q] == 0.0;  // nothing to solve: converged at once
+    c[0] = zero ? 1 : 0;
+    c[1] = 0;
+    c[2] = zero ? 1 : 0;
+    c[3] = maxit;
+  }
+  __syncthreads();
+  if (q == 0) {
+    int all = 1;
+    for (int k = 0; k < m; ++k) all &= ctl[kCtl0 + 4 * k];
+    ctl[0] = all;
+  }
 }
-__global__ void pcg_alpha_kernel(double *sc, double *alphas, const int *ctl) {
-  if (ctl[0]) return;
-  const double a = sc[0] / sc[1];
-  sc[3] = a;
-  alphas[ctl[1]] = a;
+__global__ void pcg_alpha_kernel(double *sc, double *alphas, const int *ctl, int m) {
+  const int q = threadIdx.x;
+  if (q >= m || ctl[kCtl0 + 4 * q]) return;
+  double *c = sc + q * kScStride;
+  const double a = c[0] / c[1];
+  c[3] = a;
+  alphas[q * (Solver::kMaxIt + 1) + ctl[kCtl0 + 4 * q + 1]] = a;
 }
 // after (r, r): the relative residual of this iteration, and the stop test
-__global__ void pcg_check_kernel(const double *sc, int *ctl, double *hist) {
-  if (ctl[0]) return;
-  const int it = ctl[1] + 1;
-  const double rel = sqrt(sc[2]) / sc[6];
-  hist[it] = rel;
-  ctl[1] = it;
-  if (!isfinite(rel)) {
-    ctl[0] = 1;
-  } else if (rel <= sc[7]) {
-    ctl[0] = 1;
-    ctl[2] = 1;
-  } else if (it >= ctl[3]) {
-    ctl[0] = 1;
+__global__ void pcg_check_kernel(const double *sc, int *ctl, double *hist, int m) {
+  const int q = threadIdx.x;
+  if (q < m && !ctl[kCtl0 + 4 * q]) {
+    const double *c = sc + q * kScStride;
+    int *k = ctl + kCtl0 + 4 * q;
+    const int it = k[1] + 1;
+    const double rel = sqrt(c[2]) / c[6];
+    hist[q * (Solver::kMaxIt + 2) + it] = rel;
+    k[1] = it;
+    if (!isfinite(rel)) {
+      k[0] = 1;
+    } else if (rel <= c[7]) {
+      k[0] = 1;
+      k[2] = 1;
+    } else if (it >= k[3]) {
+      k[0] = 1;
+    }
+  }
+  __syncthreads();
+  if (q == 0) {
+    int all = 1;
+    for (int j = 0; j < m; ++j) all &= ctl[kCtl0 + 4 * j];
+    ctl[0] = all;
   }
 }
 // beta = (r, z) / (r_old, z_old) (Fletcher-Reeves), or with flexible set
 // ((r, z) - (r, z_old)) / (r_old, z_old) (Polak-Ribiere, sc[11] = (r, z_old)):
 // the form that tolerates a preconditioner that is not exactly symmetric
 // positive definite, as with FP32 local factors
-__global__ void pcg_beta_kernel(double *sc, double *betas, const int *ctl, int flexible) {
-  if (ctl[0]) return;
-  const double b = (flexible ? sc[5] - sc[11] : sc[5]) / sc[0];
-  sc[4] = b;
-  betas[ctl[1] - 1] = b;
-  sc[0] = sc[5];
+__global__ void pcg_beta_kernel(double *sc, double *betas, const int *ctl, int flexible, int m) {
+  const int q = threadIdx.x;
+  if (q >= m || ctl[kCtl0 + 4 * q]) return;
+  double *c = sc + q * kScStride;
+  const double b = (flexible ? c[5] - c[11] : c[5]) / c[0];
+  c[4] = b;
+  betas[q * (Solver::kMaxIt + 1) + ctl[kCtl0 + 4 * q + 1] - 1] = b;
+  c[0] = c[5];
 }
-// x += alpha p ; r -= alpha q
+// x += alpha p ; r -= alpha q  (column blockIdx.y, vectors at stride n)
 __global__ void pcg_update_kernel(double *x, double *r, const double *p, const double *q,
                                   const double *sc, const int *ctl, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || ctl[0]) return;
-  const double a = sc[3];
-  x[i] += a * p[i];
-  r[i] -= a * q[i];
+  const int c = blockIdx.y;
+  if (i >= n || ctl[kCtl0 + 4 * c]) return;
+  const double a = sc[c * kScStride + 3];
+  const int64_t k = i + c * n;
+  x[k] += a * p[k];
+  r[k] -= a * q[k];
 }
 // p = z + beta p
 __global__ void pcg_dir_kernel(double *p, const double *z, const double *sc, const int *ctl,
                                int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || ctl[0]) return;
-  p[i] = z[i] + sc[4] * p[i];
+  const int c = blockIdx.y;
+  if (i >= n || ctl[kCtl0 + 4 * c]) return;
+  const int64_t k = i + c * n;
+  p[k] = z[k] + sc[c * kScStride + 4] * p[k];
 }
 __global__ void fill_kernel(double *dst, double v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -723,8 +833,10 @@ void Solver::free_all() {
 }
 
 void Solver::drop_pcg_graph() {
-  if (pcg_exec) hipGraphExecDestroy(pcg_exec);
-  pcg_exec = nullptr;
+  for (hipGraphExec_t &e : pcg_exec) {
+    if (e) (void)hipGraphExecDestroy(e);
+    e = nullptr;
+  }
 }
 
 Solver::~Solver() {
@@ -900,7 +1012,8 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_pos = upload(alloc, st, pos);
   d_gk_glob = upload(alloc, st, gk_glob);
   d_gk_k = upload(alloc, st, gk_k);
-  d_scr = alloc0(alloc, st, sizeof(double) * (size_t)std::max<int64_t>(scr, 1));
+  scr_elems = std::max<int64_t>(scr, 1);  // per column
+  d_scr = alloc0(alloc, st, sizeof(double) * (size_t)scr_elems * kMaxRhs);
   scrS_elems = scrS;
   {
     // T^T S T: the column pass adds (pivot columns, n_G x m) (W, m x ng) into
@@ -1211,7 +1324,7 @@ void Solver::build_structure(const Problem &P, hipStream_t st) {
       }
     }
     symv_parts = (double)tot;
-    d_symv_part = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, tot));
+    d_symv_part = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, tot) * R);
     d_symv_off = upload(alloc, st, off);
   }
   d_vI = alloc0(alloc, st, sizeof(double) * L.sumI * R);
@@ -1221,12 +1334,12 @@ void Solver::build_structure(const Problem &P, hipStream_t st) {
   d_gam_p = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
   d_gam_q = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
   d_gam_x = alloc0(alloc, st, sizeof(double) * L.n_gamma * R);
-  d_sc = alloc0(alloc, st, sizeof(double) * 16);
-  d_part = alloc0(alloc, st, sizeof(double) * 1024);
-  d_alphas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
-  d_betas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1));
-  d_pcg_ctl = alloc0(alloc, st, sizeof(int) * 4);
-  d_pcg_hist = alloc0(alloc, st, sizeof(double) * (kMaxIt + 2));
+  d_sc = alloc0(alloc, st, sizeof(double) * kScStride * R);
+  d_part = alloc0(alloc, st, sizeof(double) * DOT_BLOCKS * R);
+  d_alphas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1) * R);
+  d_betas = alloc0(alloc, st, sizeof(double) * (kMaxIt + 1) * R);
+  d_pcg_ctl = alloc0(alloc, st, sizeof(int) * (kCtl0 + 4 * R));
+  d_pcg_hist = alloc0(alloc, st, sizeof(double) * (kMaxIt + 2) * R);
   d_true_r = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, L.n_glob));
   d_true_d = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, L.n_glob));
   d_abs_I = alloc0(alloc, st, sizeof(double) * std::max<int64_t>(1, L.sumI));
@@ -1508,27 +1621,31 @@ void Solver::check_status(bool all) {
 // preconditioner and PCG (one right-hand side per call of the internals)
 
 void Solver::trsv(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
-                  const DBuf &dinv_off, double *x, bool upper, const ApplyWork &w) {
+                  const DBuf &dinv_off, double *x, bool upper, const ApplyWork &w, int m,
+                  int64_t ldx) {
   // the substructures' local solves one at a time (per_sub_launches)
   if (&plan == &plan_rr && !sub_plans.empty()) {
     for (const TrsvPlan &pq : sub_plans)
       HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), pq, upper,
-                                  dinv.as<double>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
+                                  dinv.as<double>(), dinv_off.as<int64_t>(), w.trsv_work, w.err, m,
+                                  ldx));
     return;
   }
   HIPCHK(trsv_blocked<double>(stream, A.as<double>(), x, desc.as<MatDesc>(), plan, upper,
-                              dinv.as<double>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
+                              dinv.as<double>(), dinv_off.as<int64_t>(), w.trsv_work, w.err, m, ldx));
 }
 void Solver::trsv32(const TrsvPlan &plan, const DBuf &A, const DBuf &desc, const DBuf &dinv,
-                    const DBuf &dinv_off, float *x, bool upper, const ApplyWork &w) {
+                    const DBuf &dinv_off, float *x, bool upper, const ApplyWork &w, int m,
+                    int64_t ldx) {
   if (&plan == &plan_rr && !sub_plans.empty()) {
     for (const TrsvPlan &pq : sub_plans)
       HIPCHK(trsv_blocked<float>(stream, A.as<float>(), x, desc.as<MatDesc>(), pq, upper,
-                                 dinv.as<float>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
+                                 dinv.as<float>(), dinv_off.as<int64_t>(), w.trsv_work, w.err, m,
+                                 ldx));
     return;
   }
   HIPCHK(trsv_blocked<float>(stream, A.as<float>(), x, desc.as<MatDesc>(), plan, upper,
-                             dinv.as<float>(), dinv_off.as<int64_t>(), w.trsv_work, w.err));
+                             dinv.as<float>(), dinv_off.as<int64_t>(), w.trsv_work, w.err, m, ldx));
 }
 
 ApplyWork Solver::own_work() {
@@ -1548,6 +1665,7 @@ ApplyWork Solver::own_work() {
   w.mf_zp = nullptr;
   w.trsv_work = d_work_i.as<int>();
   w.err = d_status.as<int>() + 2 * L.nsub + 1;
+  w.cols = kMaxRhs;
   return w;
 }
 
@@ -1568,7 +1686,7 @@ std::vector<size_t> work_segments(const Layout &L, int64_t scr, int64_t trsv_int
 
 size_t Solver::work_bytes() const {
   size_t t = 0;
-  for (size_t b : work_segments(L, (int64_t)(d_scr.bytes / sizeof(double)),
+  for (size_t b : work_segments(L, scr_elems,
                                 (int64_t)(d_work_i.bytes / sizeof(int)), mf.upd_elems(),
                                 mf.zp_elems(), factor_precision == 32))
     t += b;
@@ -1576,7 +1694,7 @@ size_t Solver::work_bytes() const {
 }
 
 ApplyWork Solver::carve_work(void *base) const {
-  const auto seg = work_segments(L, (int64_t)(d_scr.bytes / sizeof(double)),
+  const auto seg = work_segments(L, scr_elems,
                                  (int64_t)(d_work_i.bytes / sizeof(int)), mf.upd_elems(),
                                  mf.zp_elems(), factor_precision == 32);
   char *p = (char *)base;
@@ -1601,260 +1719,325 @@ ApplyWork Solver::carve_work(void *base) const {
   w.mf_zp = (double *)q[12];
   w.trsv_work = (int *)q[13];
   w.err = (int *)q[14];
+  w.cols = 1;
   return w;
 }
 
-// interface residual (gamma vector, nrhs = 1) -> z on gamma.  Interior values
-// are not produced here.
-void Solver::apply_gamma(const double *r, double *z) {
+// interface residuals (gamma vectors, m columns at stride n_gamma) -> z on
+// gamma.  Interior values are not produced here.
+void Solver::apply_gamma(const double *r, double *z, int m) {
   const ApplyWork w = own_work();
   gather_kernel<<<nblocks(L.sumG), TPB, 0, stream>>>(r, L.n_gamma, d_ifc_gamma.as<int64_t>(),
-                                                     d_ifc_delta.as<double>(), w.vG, L.sumG, L.sumG, 1);
+                                                     d_ifc_delta.as<double>(), w.vG, L.sumG, L.sumG, m);
   HIPCHK(hipGetLastError());
-  apply_local(w.vG, z, w);
+  apply_local(w.vG, z, w, m);
 }
 
-void Solver::apply_Tt_vec(double *b, double *scr) {
+void Solver::apply_Tt_vec(double *b, double *scr, int m) {
   if (!n_gx) return;
-  vec_pivots_kernel<<<nblocks(n_gx), TPB, 0, stream>>>(b, d_gx.as<GlobXf>(), n_gx, d_pos.as<int>(),
-                                                       scr);
-  apply_Tt_kernel<<<nblocks((int64_t)n_gx * 64), TPB, 0, stream>>>(
-      b, d_gx.as<GlobXf>(), n_gx, d_wmat.as<double>(), d_pos.as<int>(), scr);
+  vec_pivots_kernel<<<dim3(nblocks(n_gx), m), TPB, 0, stream>>>(b, d_gx.as<GlobXf>(), n_gx, d_pos.as<int>(),
+                                                                scr, L.sumG, scr_elems);
+  apply_Tt_kernel<<<dim3(nblocks((int64_t)n_gx * 64), m), TPB, 0, stream>>>(
+      b, d_gx.as<GlobXf>(), n_gx, d_wmat.as<double>(), d_pos.as<int>(), scr, L.sumG, scr_elems);
   HIPCHK(hipGetLastError());
 }
 
-void Solver::apply_T_vec(double *x, double *scr) {
+void Solver::apply_T_vec(double *x, double *scr, int m) {
   if (!n_gx) return;
-  apply_T_dots_kernel<<<nblocks((int64_t)n_gk * 64), TPB, 0, stream>>>(
+  apply_T_dots_kernel<<<dim3(nblocks((int64_t)n_gk * 64), m), TPB, 0, stream>>>(
       x, d_gx.as<GlobXf>(), d_gk_glob.as<int>(), d_gk_k.as<int>(), n_gk, d_trow.as<double>(),
-      d_pos.as<int>(), scr);
-  apply_T_store_kernel<<<nblocks(n_gk), TPB, 0, stream>>>(x, d_gx.as<GlobXf>(), d_gk_glob.as<int>(),
-                                                          d_gk_k.as<int>(), n_gk, d_pos.as<int>(),
-                                                          scr);
+      d_pos.as<int>(), scr, L.sumG, scr_elems);
+  apply_T_store_kernel<<<dim3(nblocks(n_gk), m), TPB, 0, stream>>>(
+      x, d_gx.as<GlobXf>(), d_gk_glob.as<int>(), d_gk_k.as<int>(), n_gk, d_pos.as<int>(), scr,
+      L.sumG, scr_elems);
   HIPCHK(hipGetLastError());
 }
 
-// q = sum_i R_i^T S_i R_i p on gamma vectors
-void Solver::schur_gamma(const double *p, double *q) {
+namespace {
+// kernel instance for m columns: the smallest of 1, 2, 4, 8 that holds them
+inline int col_tile(int m) { return m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : 8; }
+
+template <int M>
+void symv_launch(dim3 grid, hipStream_t st, const double *S, const int64_t *offGG, const int *nG,
+                 const double *x, const int64_t *offG, int64_t ldx, double *y, double *part,
+                 const int64_t *poff, int64_t ldp, int s0, int m) {
+  symv_panel_kernel<M><<<grid, SYMV_NT, 0, st>>>(S, offGG, nG, x, offG, ldx, y, part, poff, ldp, s0, m);
+}
+template <int M>
+void gemv_launch(bool trans, dim3 grid, hipStream_t st, const double *A, const int64_t *aoff,
+                 const int *rows, const int *cols, const double *x, const int64_t *xoff,
+                 int64_t ldx, double *y, const int64_t *yoff, int64_t ldy, int m) {
+  if (trans)
+    gemv_t_kernel<M><<<grid, TPB, 0, st>>>(A, aoff, rows, cols, x, xoff, ldx, y, yoff, ldy, 1.0, 1.0, m);
+  else
+    gemv_n_kernel<M><<<grid, TPB, 0, st>>>(A, aoff, rows, cols, x, xoff, ldx, y, yoff, ldy, 1.0, 1.0, m);
+}
+}  // namespace
+
+// q = sum_i R_i^T S_i R_i p on gamma vectors (m columns at stride n_gamma)
+void Solver::schur_gamma(const double *p, double *q, int m) {
   hipStream_t st = stream;
   double *vG = d_vG.as<double>(), *vG2 = d_vG2.as<double>();
   gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(p, L.n_gamma, d_ifc_gamma.as<int64_t>(), nullptr, vG,
-                                                 L.sumG, L.sumG, 1);
+                                                 L.sumG, L.sumG, m);
   if (L.max_nG > 0) {
-    // lower triangle of each S_s, the partial sums for its upper triangle
-    // written and read once, x read per panel and y written
-    const double by = bytes_S_sym + 2.0 * 8.0 * symv_parts + 16.0 * L.sumG;
-    timer.begin(st, "schur_symv", by, 2.0 * (double)L.sGG);
+    // lower triangle of each S_s (read once for all columns), the partial
+    // sums for its upper triangle written and read once per column, x read
+    // per panel and y written
+    const int64_t ldp = (int64_t)symv_parts;
+    const double by = bytes_S_sym + m * (2.0 * 8.0 * symv_parts + 16.0 * L.sumG);
+    timer.begin(st, "schur_symv", by, 2.0 * (double)L.sGG * m);
     // all substructures in one launch, or (per_sub_launches) one at a time
     const int groups = per_sub_launches ? L.nsub : 1, gsz = per_sub_launches ? 1 : L.nsub;
-    for (int q = 0; q < groups; ++q) {
-      const int mg = per_sub_launches ? L.nG[q] : L.max_nG;
+    for (int g = 0; g < groups; ++g) {
+      const int mg = per_sub_launches ? L.nG[g] : L.max_nG;
       if (mg == 0) continue;
       {
-        LaunchScope ls(st, "symv_kernel", bytes_S_sym + 8.0 * symv_parts + 16.0 * L.sumG, 2.0 * (double)L.sGG);
-        symv_panel_kernel<<<dim3((mg + 63) / 64, gsz), SYMV_NT, 0, st>>>(
-            d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), vG, d_offG.as<int64_t>(), vG2,
-            d_symv_part.as<double>(), d_symv_off.as<int64_t>(), q * gsz);
+        LaunchScope ls(st, "symv_kernel", bytes_S_sym + m * (8.0 * symv_parts + 16.0 * L.sumG),
+                       2.0 * (double)L.sGG * m);
+        const dim3 grid((mg + 63) / 64, gsz);
+        const double *S = d_S.as<double>();
+        const int64_t *offGG = d_offGG.as<int64_t>(), *offG = d_offG.as<int64_t>();
+        const int *nG = d_nG.as<int>();
+        double *part = d_symv_part.as<double>();
+        const int64_t *poff = d_symv_off.as<int64_t>();
+        switch (col_tile(m)) {
+          case 1: symv_launch<1>(grid, st, S, offGG, nG, vG, offG, L.sumG, vG2, part, poff, ldp, g * gsz, m); break;
+          case 2: symv_launch<2>(grid, st, S, offGG, nG, vG, offG, L.sumG, vG2, part, poff, ldp, g * gsz, m); break;
+          case 4: symv_launch<4>(grid, st, S, offGG, nG, vG, offG, L.sumG, vG2, part, poff, ldp, g * gsz, m); break;
+          default: symv_launch<8>(grid, st, S, offGG, nG, vG, offG, L.sumG, vG2, part, poff, ldp, g * gsz, m);
+        }
       }
       {
-        LaunchScope ls(st, "symv_reduce_kernel", 8.0 * symv_parts + 16.0 * L.sumG, (double)symv_parts);
-        symv_reduce_kernel<<<dim3(nblocks(mg), gsz), TPB, 0, st>>>(
-            d_nG.as<int>(), d_offG.as<int64_t>(), vG2, d_symv_part.as<double>(), d_symv_off.as<int64_t>(),
-            q * gsz);
+        LaunchScope ls(st, "symv_reduce_kernel", m * (8.0 * symv_parts + 16.0 * L.sumG),
+                       (double)symv_parts * m);
+        symv_reduce_kernel<<<dim3(nblocks(mg), gsz, m), TPB, 0, st>>>(
+            d_nG.as<int>(), d_offG.as<int64_t>(), L.sumG, vG2, d_symv_part.as<double>(),
+            d_symv_off.as<int64_t>(), ldp, g * gsz);
       }
     }
     timer.end(st);
   }
   reduce_copies_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(vG2, L.sumG, d_gamma_ptr.as<int>(),
                                                            d_gamma_copies.as<int64_t>(), nullptr, q,
-                                                           L.n_gamma, L.n_gamma, 1, 1.0, 0.0);
+                                                           L.n_gamma, L.n_gamma, m, 1.0, 0.0);
   HIPCHK(hipGetLastError());
 }
 
-void Solver::dot(const double *a, const double *b, int64_t n, double *out) {
-  dot_partial_kernel<<<DOT_BLOCKS, TPB, 0, stream>>>(a, b, n, d_part.as<double>());
-  dot_final_kernel<<<1, TPB, 0, stream>>>(d_part.as<double>(), DOT_BLOCKS, out);
+// out[q kScStride] = (a_q, b_q) for the m columns (at strides lda, ldb)
+void Solver::dot(const double *a, const double *b, int64_t n, double *out, int m, int64_t lda,
+                 int64_t ldb) {
+  dot_partial_kernel<<<dim3(DOT_BLOCKS, m), TPB, 0, stream>>>(a, b, n, lda, ldb, d_part.as<double>());
+  dot_final_kernel<<<m, TPB, 0, stream>>>(d_part.as<double>(), DOT_BLOCKS, out);
   HIPCHK(hipGetLastError());
 }
 
-// interior Dirichlet solve in every substructure: vI <- A_II^-1 vI
-void Solver::interior_solve(double *vI, const ApplyWork *w) {
-  mf.solve(stream, vI, w ? w->mf_upd : nullptr, w ? w->mf_zp : nullptr);
+// interior Dirichlet solve in every substructure: vI <- A_II^-1 vI (m
+// columns at stride sumI)
+void Solver::interior_solve(double *vI, const ApplyWork *w, int m) {
+  mf.solve(stream, vI, w ? w->mf_upd : nullptr, w ? w->mf_zp : nullptr, m, L.sumI);
 }
 
 // z = M r for global vectors (Algorithm 2): the interior part of r enters
 // through E^T, i.e. the substructure right-hand side has b_I = r_I, which is
 // condensed onto the interface before the interface solve; the result is
-// extended harmonically.
+// extended harmonically.  m <= w.cols columns (r, z at strides ldr, ldz)
+// share every read of the factors; a column gets the same bits for every m.
 void Solver::apply_global(const double *r, double *z) { apply_global(r, z, own_work()); }
 
 void Solver::apply_global(const double *r, double *z, const ApplyWork &w) {
+  apply_global(r, L.n_glob, z, L.n_glob, 1, w);
+}
+
+void Solver::apply_global(const double *r, int64_t ldr, double *z, int64_t ldz, int m,
+                          const ApplyWork &w) {
   if (!factored) throw StateError("bddc_apply before bddc_factor");
+  if (m < 1 || m > w.cols) throw ArgError("apply: more columns than the work vectors hold");
   hipStream_t st = stream;
   double *vI = w.vI, *vG = w.vG;
   double *gr = w.gr, *gz = w.gz;
   // condensation of the interior right-hand side: r_G - sum A_GI A_II^-1 r_I
-  gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(r, L.n_glob, d_int_gdof.as<int64_t>(), nullptr, vI,
-                                                 L.sumI, L.sumI, 1);
-  interior_solve(vI, &w);
+  gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(r, ldr, d_int_gdof.as<int64_t>(), nullptr, vI,
+                                                 L.sumI, L.sumI, m);
+  interior_solve(vI, &w, m);
   spmv_coupling_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
       d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
       d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(), vI,
-      nullptr, nullptr, vG, 0, 1, L.sumI, L.sumG);
+      nullptr, nullptr, vG, 0, m, L.sumI, L.sumG);
   // gamma residual: r_gamma - sum over copies of (A_GI A_II^-1 r_I), where
   // the interior part enters through E^T with weight 1 in its substructure and
   // the condensed part is weighted like the interface entries
-  gather_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(r, L.n_glob, d_gamma_gdof.as<int64_t>(), nullptr, gr,
-                                                    L.n_gamma, L.n_gamma, 1);
+  gather_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(r, ldr, d_gamma_gdof.as<int64_t>(), nullptr, gr,
+                                                    L.n_gamma, L.n_gamma, m);
   HIPCHK(hipGetLastError());
-  apply_gamma_condensed(gr, vG, gz, w);
-  harmonic_extension(gz, z, w);
+  apply_gamma_condensed(gr, vG, gz, w, m);
+  harmonic_extension(gz, z, ldz, w, m);
 }
 
 // as apply_gamma, but the local right-hand sides receive the condensed
 // interior contribution -A_GI A_II^-1 r_I (already in vG_cond, unweighted)
 void Solver::apply_gamma_condensed(const double *r, const double *vG_cond, double *z,
-                                   const ApplyWork &w) {
+                                   const ApplyWork &w, int m) {
   hipStream_t st = stream;
   // vG2 = delta . R_i r - vG_cond
   double *vG2 = w.vG2;
   gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(r, L.n_gamma, d_ifc_gamma.as<int64_t>(),
-                                                 d_ifc_delta.as<double>(), vG2, L.sumG, L.sumG, 1);
-  axpby_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(vG2, vG_cond, -1.0, 1.0, L.sumG);
+                                                 d_ifc_delta.as<double>(), vG2, L.sumG, L.sumG, m);
+  axpby_kernel<<<nblocks(L.sumG * m), TPB, 0, st>>>(vG2, vG_cond, -1.0, 1.0, L.sumG * m);
   HIPCHK(hipGetLastError());
-  apply_local(vG2, z, w);
+  apply_local(vG2, z, w, m);
 }
 
-// everything of apply_gamma after the weighted gather; b (sum-nG stack) is
-// consumed
-void Solver::apply_local(double *b, double *z, const ApplyWork &w) {
+// everything of apply_gamma after the weighted gather; b (sum-nG stacks, m
+// columns) is consumed
+void Solver::apply_local(double *b, double *z, const ApplyWork &w, int m) {
   hipStream_t st = stream;
   const int ns = L.nsub;
   double *vG = b, *vR = w.vR, *vR2 = w.vR2;
   double *vP = w.vP, *vc = w.vc;
-  apply_Tt_vec(vG, w.scr);
-  gather32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vG, L.sumG, d_rabs.as<int>(), vR, L.sumR, L.sumR, 1);
-  gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vG, L.sumG, d_pabs.as<int>(), vP, L.sumP, L.sumP, 1);
+  apply_Tt_vec(vG, w.scr, m);
+  gather32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vG, L.sumG, d_rabs.as<int>(), vR, L.sumR, L.sumR, m);
+  gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vG, L.sumG, d_pabs.as<int>(), vP, L.sumP, L.sumP, m);
   HIPCHK(hipGetLastError());
   if (L.max_np > 0) {
-    LaunchScope ls(st, "gemv_t_kernel", 8.0 * ((double)L.sRP + L.sumR + 2.0 * L.sumP), 2.0 * (double)L.sRP);
-    gemv_t_kernel<<<dim3(nblocks((int64_t)L.max_np * 64), ns), TPB, 0, st>>>(
-        d_Phi.as<double>(), d_offRP.as<int64_t>(), d_nr.as<int>(), d_np.as<int>(), vR,
-        d_offR.as<int64_t>(), vP, d_offP.as<int64_t>(), 1.0, 1.0);
+    LaunchScope ls(st, "gemv_t_kernel", 8.0 * ((double)L.sRP + m * (L.sumR + 2.0 * L.sumP)),
+                   2.0 * (double)L.sRP * m);
+    const dim3 grid(nblocks((int64_t)L.max_np * 64), ns);
+    const double *Phi = d_Phi.as<double>();
+    const int64_t *offRP = d_offRP.as<int64_t>(), *offR = d_offR.as<int64_t>(), *offP = d_offP.as<int64_t>();
+    const int *nr = d_nr.as<int>(), *np = d_np.as<int>();
+    switch (col_tile(m)) {
+      case 1: gemv_launch<1>(true, grid, st, Phi, offRP, nr, np, vR, offR, L.sumR, vP, offP, L.sumP, m); break;
+      case 2: gemv_launch<2>(true, grid, st, Phi, offRP, nr, np, vR, offR, L.sumR, vP, offP, L.sumP, m); break;
+      case 4: gemv_launch<4>(true, grid, st, Phi, offRP, nr, np, vR, offR, L.sumR, vP, offP, L.sumP, m); break;
+      default: gemv_launch<8>(true, grid, st, Phi, offRP, nr, np, vR, offR, L.sumR, vP, offP, L.sumP, m);
+    }
   }
-  copy_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vR2, vR, L.sumR);
+  copy_kernel<<<nblocks(L.sumR * m), TPB, 0, st>>>(vR2, vR, L.sumR * m);
   if (factor_precision == 32) {
     // K_rr solves in FP32 with the scaled factor (K_rr = S^-1 Lt Lt^T S^-1):
     // the vector enters and leaves in FP64, scaled by S on both sides
     float *x32 = w.vR32;
     const double *rsc = d_rscale.as<double>();
-    convert_scaled_kernel<double, float><<<nblocks(L.sumR), TPB, 0, st>>>(vR2, x32, rsc, L.sumR);
+    convert_scaled_kernel<double, float><<<dim3(nblocks(L.sumR), m), TPB, 0, st>>>(vR2, x32, rsc, L.sumR);
     HIPCHK(hipGetLastError());
-    timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 8.0 * L.sumR, (double)L.sRR);
-    trsv32(plan_rr, d_Lrr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, false, w);
+    timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 8.0 * L.sumR * m, (double)L.sRR * m);
+    trsv32(plan_rr, d_Lrr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, false, w, m, L.sumR);
     timer.end(st);
-    timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 8.0 * L.sumR, (double)L.sRR);
-    trsv32(plan_rr, d_Urr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, true, w);
+    timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 8.0 * L.sumR * m, (double)L.sRR * m);
+    trsv32(plan_rr, d_Urr32, d_descRRvec, d_dinv_rr32, d_dinv_rr_off, x32, true, w, m, L.sumR);
     timer.end(st);
-    convert_scaled_kernel<float, double><<<nblocks(L.sumR), TPB, 0, st>>>(x32, vR2, rsc, L.sumR);
+    convert_scaled_kernel<float, double><<<dim3(nblocks(L.sumR), m), TPB, 0, st>>>(x32, vR2, rsc, L.sumR);
     HIPCHK(hipGetLastError());
   } else {
-    timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
-    trsv(plan_rr, d_Lrr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, false, w);
+    timer.begin(st, "trsv_local_fwd", bytes_Lrr_tri + 16.0 * L.sumR * m, (double)L.sRR * m);
+    trsv(plan_rr, d_Lrr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, false, w, m, L.sumR);
     timer.end(st);
-    timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 16.0 * L.sumR, (double)L.sRR);
-    trsv(plan_rr, d_Urr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, true, w);
+    timer.begin(st, "trsv_local_bwd", bytes_Lrr_tri + 16.0 * L.sumR * m, (double)L.sRR * m);
+    trsv(plan_rr, d_Urr, d_descRRvec, d_dinv_rr, d_dinv_rr_off, vR2, true, w, m, L.sumR);
     timer.end(st);
   }
   if (L.n_coarse > 0) {
     reduce_copies_kernel<<<nblocks(L.n_coarse), TPB, 0, st>>>(vP, L.sumP, d_c_ptr.as<int>(),
                                                               d_c_copies.as<int64_t>(), nullptr, vc,
-                                                              L.n_coarse, L.n_coarse, 1, 1.0, 0.0);
-    timer.begin(st, "trsv_coarse", 8.0 * (double)L.n_coarse * L.n_coarse, 2.0 * L.n_coarse * L.n_coarse);
-    trsv(plan_c, d_Lc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, false, w);
-    trsv(plan_c, d_Uc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, true, w);
+                                                              L.n_coarse, L.n_coarse, m, 1.0, 0.0);
+    timer.begin(st, "trsv_coarse", 8.0 * (double)L.n_coarse * L.n_coarse,
+                2.0 * L.n_coarse * L.n_coarse * m);
+    trsv(plan_c, d_Lc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, false, w, m, L.n_coarse);
+    trsv(plan_c, d_Uc, d_descCvec, d_dinv_c, d_dinv_c_off, vc, true, w, m, L.n_coarse);
     timer.end(st);
     gather32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vc, L.n_coarse, d_pcid.as<int>(), vP, L.sumP,
-                                                     L.sumP, 1);
+                                                     L.sumP, m);
     if (L.max_nr > 0) {
-      LaunchScope ls(st, "gemv_n_kernel", 8.0 * ((double)L.sRP + L.sumP + 2.0 * L.sumR), 2.0 * (double)L.sRP);
-      gemv_n_kernel<<<dim3(nblocks(L.max_nr), ns), TPB, 0, st>>>(
-          d_Phi.as<double>(), d_offRP.as<int64_t>(), d_nr.as<int>(), d_np.as<int>(), vP,
-          d_offP.as<int64_t>(), vR2, d_offR.as<int64_t>(), 1.0, 1.0);
+      LaunchScope ls(st, "gemv_n_kernel", 8.0 * ((double)L.sRP + m * (L.sumP + 2.0 * L.sumR)),
+                     2.0 * (double)L.sRP * m);
+      const dim3 grid(nblocks(L.max_nr), ns);
+      const double *Phi = d_Phi.as<double>();
+      const int64_t *offRP = d_offRP.as<int64_t>(), *offR = d_offR.as<int64_t>(), *offP = d_offP.as<int64_t>();
+      const int *nr = d_nr.as<int>(), *np = d_np.as<int>();
+      switch (col_tile(m)) {
+        case 1: gemv_launch<1>(false, grid, st, Phi, offRP, nr, np, vP, offP, L.sumP, vR2, offR, L.sumR, m); break;
+        case 2: gemv_launch<2>(false, grid, st, Phi, offRP, nr, np, vP, offP, L.sumP, vR2, offR, L.sumR, m); break;
+        case 4: gemv_launch<4>(false, grid, st, Phi, offRP, nr, np, vP, offP, L.sumP, vR2, offR, L.sumR, m); break;
+        default: gemv_launch<8>(false, grid, st, Phi, offRP, nr, np, vP, offP, L.sumP, vR2, offR, L.sumR, m);
+      }
     }
   }
-  scatter32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vR2, L.sumR, d_rabs.as<int>(), vG, L.sumG, L.sumR, 1);
-  scatter32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vP, L.sumP, d_pabs.as<int>(), vG, L.sumG, L.sumP, 1);
-  apply_T_vec(vG, w.scr);
+  scatter32_kernel<<<nblocks(L.sumR), TPB, 0, st>>>(vR2, L.sumR, d_rabs.as<int>(), vG, L.sumG, L.sumR, m);
+  scatter32_kernel<<<nblocks(L.sumP), TPB, 0, st>>>(vP, L.sumP, d_pabs.as<int>(), vG, L.sumG, L.sumP, m);
+  apply_T_vec(vG, w.scr, m);
   reduce_copies_kernel<<<nblocks(L.n_gamma), TPB, 0, st>>>(vG, L.sumG, d_gamma_ptr.as<int>(),
                                                            d_gamma_copies.as<int64_t>(),
                                                            d_ifc_delta.as<double>(), z, L.n_gamma,
-                                                           L.n_gamma, 1, 1.0, 0.0);
+                                                           L.n_gamma, m, 1.0, 0.0);
   HIPCHK(hipGetLastError());
 }
 
 // global z from interface values zg: z_G = zg, z_I = -A_II^-1 A_IG zg
-void Solver::harmonic_extension(const double *zg, double *z, const ApplyWork &w) {
+void Solver::harmonic_extension(const double *zg, double *z, int64_t ldz, const ApplyWork &w, int m) {
   hipStream_t st = stream;
   double *vI = w.vI, *vG = w.vG;
-  scatter_gamma(zg, z);
+  scatter_gamma(zg, z, ldz, m);
   gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(zg, L.n_gamma, d_ifc_gamma.as<int64_t>(), nullptr, vG,
-                                                 L.sumG, L.sumG, 1);
+                                                 L.sumG, L.sumG, m);
   spmv_coupling_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
       d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
       d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(),
-      nullptr, vG, vI, nullptr, 1, 1, L.sumI, L.sumG);
+      nullptr, vG, vI, nullptr, 1, m, L.sumI, L.sumG);
   HIPCHK(hipGetLastError());
-  interior_solve(vI, &w);
-  axpby_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(vI, vI, 0.0, -1.0, L.sumI);
-  scatter_interior(vI, z);
+  interior_solve(vI, &w, m);
+  axpby_kernel<<<nblocks(L.sumI * m), TPB, 0, st>>>(vI, vI, 0.0, -1.0, L.sumI * m);
+  scatter_interior(vI, z, ldz, m);
 }
 
-void Solver::scatter_gamma(const double *zg, double *z) {
+void Solver::scatter_gamma(const double *zg, double *z, int64_t ldz, int m) {
   // z[gamma_gdof[k]] = zg[k]
-  scatter64(zg, d_gamma_gdof.as<int64_t>(), L.n_gamma, z);
+  scatter64(zg, L.n_gamma, d_gamma_gdof.as<int64_t>(), L.n_gamma, z, ldz, m);
 }
 
-void Solver::scatter_interior(const double *vI, double *z) {
-  scatter64(vI, d_int_gdof.as<int64_t>(), L.sumI, z);
+void Solver::scatter_interior(const double *vI, double *z, int64_t ldz, int m) {
+  scatter64(vI, L.sumI, d_int_gdof.as<int64_t>(), L.sumI, z, ldz, m);
 }
 
 namespace {
-__global__ void scatter64_kernel(const double *src, const int64_t *idx, int64_t n, double *dst) {
+__global__ void scatter64_kernel(const double *src, int64_t lds, const int64_t *idx, int64_t n,
+                                 double *dst, int64_t ldd) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[idx[i]] = src[i];
+  if (i < n) dst[idx[i] + blockIdx.y * ldd] = src[i + blockIdx.y * lds];
 }
 }  // namespace
 
-void Solver::scatter64(const double *src, const int64_t *idx, int64_t n, double *dst) {
+void Solver::scatter64(const double *src, int64_t lds, const int64_t *idx, int64_t n, double *dst,
+                       int64_t ldd, int m) {
   if (n <= 0) return;
-  scatter64_kernel<<<nblocks(n), TPB, 0, stream>>>(src, idx, n, dst);
+  scatter64_kernel<<<dim3(nblocks(n), m), TPB, 0, stream>>>(src, lds, idx, n, dst, ldd);
   HIPCHK(hipGetLastError());
 }
 
 // PCG on the reduced problem (Remark after Lemma 1: zero interface start,
 // interior Dirichlet solves, residuals vanish in the interiors).
-// One PCG iteration on the interface, all scalars on the device (see
-// pcg_check_kernel); launched eagerly or captured as a graph.
-void Solver::pcg_iteration() {
+// One PCG iteration on the interface for m columns in lock step, all scalars
+// on the device (see pcg_check_kernel); launched eagerly or captured as a
+// graph.
+void Solver::pcg_iteration(int m) {
   hipStream_t st = stream;
   const int64_t ng = L.n_gamma;
   double *r = d_gam_r.as<double>(), *z = d_gam_z.as<double>(), *p = d_gam_p.as<double>();
   double *q = d_gam_q.as<double>(), *x = d_gam_x.as<double>();
   double *sc = d_sc.as<double>();
   int *ctl = d_pcg_ctl.as<int>();
-  schur_gamma(p, q);
-  dot(p, q, ng, sc + 1);
-  pcg_alpha_kernel<<<1, 1, 0, st>>>(sc, d_alphas.as<double>(), ctl);
-  pcg_update_kernel<<<nblocks(ng), TPB, 0, st>>>(x, r, p, q, sc, ctl, ng);
-  dot(r, r, ng, sc + 2);
-  pcg_check_kernel<<<1, 1, 0, st>>>(sc, ctl, d_pcg_hist.as<double>());
+  schur_gamma(p, q, m);
+  dot(p, q, ng, sc + 1, m, ng, ng);
+  pcg_alpha_kernel<<<1, 64, 0, st>>>(sc, d_alphas.as<double>(), ctl, m);
+  pcg_update_kernel<<<dim3(nblocks(ng), m), TPB, 0, st>>>(x, r, p, q, sc, ctl, ng);
+  dot(r, r, ng, sc + 2, m, ng, ng);
+  pcg_check_kernel<<<1, 64, 0, st>>>(sc, ctl, d_pcg_hist.as<double>(), m);
   const int flexible = factor_precision == 32 ? 1 : 0;
-  if (flexible) dot(r, z, ng, sc + 11);
-  apply_gamma(r, z);
-  dot(r, z, ng, sc + 5);
-  pcg_beta_kernel<<<1, 1, 0, st>>>(sc, d_betas.as<double>(), ctl, flexible);
-  pcg_dir_kernel<<<nblocks(ng), TPB, 0, st>>>(p, z, sc, ctl, ng);
+  if (flexible) dot(r, z, ng, sc + 11, m, ng, ng);
+  apply_gamma(r, z, m);
+  dot(r, z, ng, sc + 5, m, ng, ng);
+  pcg_beta_kernel<<<1, 64, 0, st>>>(sc, d_betas.as<double>(), ctl, flexible, m);
+  pcg_dir_kernel<<<dim3(nblocks(ng), m), TPB, 0, st>>>(p, z, sc, ctl, ng);
   HIPCHK(hipGetLastError());
 }
 
@@ -1915,82 +2098,109 @@ double Solver::true_residual(const double *f, const double *u, double *rt, doubl
 // contrast 1e6 one such correction moved the solution from 7e-9 to 1.2e-8 of
 // the oracle's).
 PcgResult Solver::pcg(const double *f, double *u, double rtol, int maxit) {
-  auto t0 = std::chrono::steady_clock::now();
-  PcgResult res = pcg_once(f, u, rtol, maxit);
-  if (res.r0 == 0.0) return res;
-  double *rt = d_true_r.as<double>(), *du = d_true_d.as<double>();
-  double fl = 0;
-  double rn = true_residual(f, u, rt, &fl);
-  res.true_relres = rn / res.r0;
-  res.residual_floor = fl / res.r0;
-  const double target = rtol * res.r0;
-  while (res.converged && rn > target && rn > 2.0 * fl && res.refinements < kMaxRefine) {
-    // half the target, so that the rounding of the update leaves room
-    PcgResult c = pcg_once(rt, du, rtol, maxit, 0.5 * target);
-    ++res.refinements;
-    res.refine_iters += c.iters;
-    axpby_kernel<<<nblocks(L.n_glob), TPB, 0, stream>>>(u, du, 1.0, 1.0, L.n_glob);
-    HIPCHK(hipGetLastError());
-    const double rn_new = true_residual(f, u, rt, &fl);
-    const bool stalled = rn_new > 0.5 * rn;
-    rn = rn_new;
-    res.true_relres = rn / res.r0;
-    res.residual_floor = fl / res.r0;
-    if (stalled) break;
-  }
-  last_history = res.history;
-  res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return res;
+  std::vector<PcgResult> r = pcg_block(f, L.n_glob, u, L.n_glob, 1, rtol, maxit);
+  return r[0];
 }
 
-PcgResult Solver::pcg_once(const double *f, double *u, double rtol, int maxit, double abs_tol) {
+// m right-hand sides (f, u at strides ldf, ldu) solved together: one block
+// PCG in lock step (every application of the operator and the preconditioner
+// reads the factors once for all columns), then the true-residual check and
+// the correction solves column by column.  A column's result has the same
+// bits as when solved alone.
+std::vector<PcgResult> Solver::pcg_block(const double *f, int64_t ldf, double *u, int64_t ldu,
+                                         int m, double rtol, int maxit) {
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> rt_in(m, rtol), abs_in(m, 0.0);
+  std::vector<PcgResult> out = pcg_once(f, ldf, u, ldu, m, rt_in.data(), maxit, abs_in.data());
+  double *rt = d_true_r.as<double>(), *du = d_true_d.as<double>();
+  for (int c = 0; c < m; ++c) {
+    PcgResult &res = out[c];
+    if (res.r0 == 0.0) continue;
+    const double *fc = f + c * ldf;
+    double *uc = u + c * ldu;
+    double fl = 0;
+    double rn = true_residual(fc, uc, rt, &fl);
+    res.true_relres = rn / res.r0;
+    res.residual_floor = fl / res.r0;
+    const double target = rtol * res.r0;
+    while (res.converged && rn > target && rn > 2.0 * fl && res.refinements < kMaxRefine) {
+      // half the target, so that the rounding of the update leaves room
+      const double half = 0.5 * target;
+      PcgResult cr = pcg_once(rt, L.n_glob, du, L.n_glob, 1, &rtol, maxit, &half)[0];
+      ++res.refinements;
+      res.refine_iters += cr.iters;
+      axpby_kernel<<<nblocks(L.n_glob), TPB, 0, stream>>>(uc, du, 1.0, 1.0, L.n_glob);
+      HIPCHK(hipGetLastError());
+      const double rn_new = true_residual(fc, uc, rt, &fl);
+      const bool stalled = rn_new > 0.5 * rn;
+      rn = rn_new;
+      res.true_relres = rn / res.r0;
+      res.residual_floor = fl / res.r0;
+      if (stalled) break;
+    }
+  }
+  last_history = out[0].history;
+  const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (PcgResult &res : out) res.seconds = sec;
+  return out;
+}
+
+std::vector<PcgResult> Solver::pcg_once(const double *f, int64_t ldf, double *u, int64_t ldu, int m,
+                                        const double *rtol_in, int maxit, const double *abs_tol) {
   if (!factored) throw StateError("bddc_pcg_solve before bddc_factor");
+  if (m < 1 || m > kMaxRhs) throw ArgError("pcg: bad number of columns");
   maxit = std::min(maxit, kMaxIt);
   hipStream_t st = stream;
   auto t0 = std::chrono::steady_clock::now();
   const int64_t ng = L.n_gamma;
   double *vI = d_vI.as<double>(), *vG = d_vG.as<double>();
   double *r = d_gam_r.as<double>(), *z = d_gam_z.as<double>(), *p = d_gam_p.as<double>();
-  double *q = d_gam_q.as<double>(), *x = d_gam_x.as<double>();
+  double *x = d_gam_x.as<double>();
   double *sc = d_sc.as<double>();
+  int *ctl = d_pcg_ctl.as<int>();
   // u0: interior solves with zero interface
-  gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(f, L.n_glob, d_int_gdof.as<int64_t>(), nullptr, vI,
-                                                 L.sumI, L.sumI, 1);
-  interior_solve(vI);
+  gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(f, ldf, d_int_gdof.as<int64_t>(), nullptr, vI,
+                                                 L.sumI, L.sumI, m);
+  interior_solve(vI, nullptr, m);
   // r0 = f_G - sum A_GI u0_I
   spmv_coupling_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
       d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
       d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(), vI,
-      nullptr, nullptr, vG, 0, 1, L.sumI, L.sumG);
-  gather_kernel<<<nblocks(ng), TPB, 0, st>>>(f, L.n_glob, d_gamma_gdof.as<int64_t>(), nullptr, r, ng,
-                                             ng, 1);
+      nullptr, nullptr, vG, 0, m, L.sumI, L.sumG);
+  gather_kernel<<<nblocks(ng), TPB, 0, st>>>(f, ldf, d_gamma_gdof.as<int64_t>(), nullptr, r, ng,
+                                             ng, m);
   reduce_copies_kernel<<<nblocks(ng), TPB, 0, st>>>(vG, L.sumG, d_gamma_ptr.as<int>(),
                                                     d_gamma_copies.as<int64_t>(), nullptr, r, ng, ng,
-                                                    1, -1.0, 1.0);
+                                                    m, -1.0, 1.0);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * ng, st));
-  dot(r, r, ng, sc + 2);
-  double rr0;
-  HIPCHK(hipMemcpyAsync(&rr0, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * ng * m, st));
+  dot(r, r, ng, sc + 2, m, ng, ng);
+  std::vector<double> hsc((size_t)kScStride * m);
+  HIPCHK(hipMemcpyAsync(hsc.data(), sc, sizeof(double) * hsc.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  PcgResult res;
-  const double r0 = std::sqrt(rr0);
-  res.r0 = r0;
-  if (abs_tol > 0 && r0 > 0) rtol = abs_tol / r0;
-  int it = 0;
-  bool conv = (r0 == 0.0);
-  double rel = 0.0;
-  res.history.push_back(1.0);
-  if (!conv && maxit > 0) {
-    apply_gamma(r, z);
-    copy_kernel<<<nblocks(ng), TPB, 0, st>>>(p, z, ng);
-    dot(r, z, ng, sc + 0);
-    int *ctl = d_pcg_ctl.as<int>();
-    pcg_init_kernel<<<1, 1, 0, st>>>(sc, ctl, r0, rtol, maxit);
+  std::vector<PcgResult> out(m);
+  PcgInit init{};
+  bool any = false;
+  for (int c = 0; c < m; ++c) {
+    const double r0 = std::sqrt(hsc[(size_t)c * kScStride + 2]);
+    out[c].r0 = r0;
+    out[c].history.push_back(1.0);
+    init.r0[c] = r0;
+    init.rtol[c] = (abs_tol[c] > 0 && r0 > 0) ? abs_tol[c] / r0 : rtol_in[c];
+    if (r0 > 0) any = true;
+  }
+  std::vector<int> its(m, 0), convs(m, 0);
+  for (int c = 0; c < m; ++c) convs[c] = out[c].r0 == 0.0;
+  if (any && maxit > 0) {
+    apply_gamma(r, z, m);
+    copy_kernel<<<nblocks(ng * m), TPB, 0, st>>>(p, z, ng * m);
+    dot(r, z, ng, sc + 0, m, ng, ng);
+    pcg_init_kernel<<<1, 64, 0, st>>>(sc, ctl, init, m, maxit);
     HIPCHK(hipGetLastError());
     // per-launch timing records events around launches: then run eagerly
     const bool graphs = use_graphs && timer.mode == 0;
-    if (graphs && !pcg_exec) {
+    hipGraphExec_t &exec = pcg_exec[m];
+    if (graphs && !exec) {
       // capture one iteration on a private stream (the caller's stream may
       // be the legacy default stream, which cannot be captured)
       if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
@@ -1998,7 +2208,7 @@ PcgResult Solver::pcg_once(const double *f, double *u, double rtol, int maxit, d
       stream = cap_stream;
       HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
       try {
-        pcg_iteration();
+        pcg_iteration(m);
       } catch (...) {
         hipStreamEndCapture(cap_stream, &g);
         if (g) hipGraphDestroy(g);
@@ -2007,7 +2217,7 @@ PcgResult Solver::pcg_once(const double *f, double *u, double rtol, int maxit, d
       }
       stream = st;
       HIPCHK(hipStreamEndCapture(cap_stream, &g));
-      const hipError_t e = hipGraphInstantiate(&pcg_exec, g, nullptr, nullptr, 0);
+      const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       hipGraphDestroy(g);
       HIPCHK(e);
     }
@@ -2015,9 +2225,10 @@ PcgResult Solver::pcg_once(const double *f, double *u, double rtol, int maxit, d
       if (!pcg_pin) HIPCHK(hipHostMalloc((void **)&pcg_pin, sizeof(int) * 8, hipHostMallocDefault));
       for (hipEvent_t &e : pcg_ev)
         if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      // the host checks iteration k while iteration k + 1 runs
+      // the host checks iteration k while iteration k + 1 runs (word 0:
+      // every column stopped)
       for (int k = 0; k < maxit; ++k) {
-        HIPCHK(hipGraphLaunch(pcg_exec, st));
+        HIPCHK(hipGraphLaunch(exec, st));
         HIPCHK(hipMemcpyAsync(pcg_pin + 4 * (k & 1), ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(pcg_ev[k & 1], st));
         if (k > 0) {
@@ -2027,60 +2238,73 @@ PcgResult Solver::pcg_once(const double *f, double *u, double rtol, int maxit, d
       }
     } else {
       for (int k = 0; k < maxit; ++k) {
-        pcg_iteration();
-        int h[4];
-        HIPCHK(hipMemcpyAsync(h, ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        pcg_iteration(m);
+        int h = 0;
+        HIPCHK(hipMemcpyAsync(&h, ctl, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (h[0]) break;
+        if (h) break;
       }
     }
-    int h[4];
-    HIPCHK(hipMemcpyAsync(h, ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+    std::vector<int> h((size_t)kCtl0 + 4 * m);
+    HIPCHK(hipMemcpyAsync(h.data(), ctl, sizeof(int) * h.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    it = h[1];
-    conv = h[2] != 0;
-    std::vector<double> hist(it + 1);
-    if (it > 0)
-      HIPCHK(hipMemcpyAsync(hist.data(), d_pcg_hist.p, sizeof(double) * (it + 1), hipMemcpyDeviceToHost,
-                            st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int k = 1; k <= it; ++k) res.history.push_back(hist[k]);
-    if (it > 0) rel = hist[it];
+    for (int c = 0; c < m; ++c) {
+      its[c] = h[kCtl0 + 4 * c + 1];
+      convs[c] = h[kCtl0 + 4 * c + 2] != 0;
+      const int it = its[c];
+      if (it > 0) {
+        std::vector<double> hist(it + 1);
+        HIPCHK(hipMemcpyAsync(hist.data(), d_pcg_hist.as<double>() + (size_t)c * (kMaxIt + 2),
+                              sizeof(double) * (it + 1), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int k = 1; k <= it; ++k) out[c].history.push_back(hist[k]);
+        out[c].relres = hist[it];
+      }
+    }
   }
   // u: interface from x, interiors A_II^-1 (f_I - A_IG x)
-  scatter_gamma(x, u);
+  scatter_gamma(x, u, ldu, m);
   gather_kernel<<<nblocks(L.sumG), TPB, 0, st>>>(x, ng, d_ifc_gamma.as<int64_t>(), nullptr, vG, L.sumG,
-                                                 L.sumG, 1);
+                                                 L.sumG, m);
   spmv_coupling_kernel<<<nblocks(n_rows), TPB, 0, st>>>(
       d_row_sub.as<int>(), d_row_loc.as<int>(), d_rowptr.as<int64_t>(), d_col.as<int>(),
       d_val.as<double>(), n_rows, d_nI.as<int>(), d_offI.as<int64_t>(), d_offG.as<int64_t>(),
-      nullptr, vG, d_vI2.as<double>(), nullptr, 1, 1, L.sumI, L.sumG);
-  gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(f, L.n_glob, d_int_gdof.as<int64_t>(), nullptr, vI,
-                                                 L.sumI, L.sumI, 1);
-  axpby_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(vI, d_vI2.as<double>(), -1.0, 1.0, L.sumI);
+      nullptr, vG, d_vI2.as<double>(), nullptr, 1, m, L.sumI, L.sumG);
+  gather_kernel<<<nblocks(L.sumI), TPB, 0, st>>>(f, ldf, d_int_gdof.as<int64_t>(), nullptr, vI,
+                                                 L.sumI, L.sumI, m);
+  axpby_kernel<<<nblocks(L.sumI * m), TPB, 0, st>>>(vI, d_vI2.as<double>(), -1.0, 1.0, L.sumI * m);
   HIPCHK(hipGetLastError());
-  interior_solve(vI);
-  scatter_interior(vI, u);
+  interior_solve(vI, nullptr, m);
+  scatter_interior(vI, u, ldu, m);
   // Lanczos coefficients
-  const int na = conv ? it : std::max(0, it - 1);
-  res.alphas.resize(na);
-  res.betas.resize(std::max(0, na - 1));
-  if (na > 0)
-    HIPCHK(hipMemcpyAsync(res.alphas.data(), d_alphas.p, sizeof(double) * na, hipMemcpyDeviceToHost, st));
-  if (na > 1)
-    HIPCHK(hipMemcpyAsync(res.betas.data(), d_betas.p, sizeof(double) * (na - 1), hipMemcpyDeviceToHost, st));
+  for (int c = 0; c < m; ++c) {
+    PcgResult &res = out[c];
+    const int it = its[c];
+    const bool conv = convs[c] != 0;
+    const int na = conv ? it : std::max(0, it - 1);
+    res.alphas.resize(na);
+    res.betas.resize(std::max(0, na - 1));
+    if (na > 0)
+      HIPCHK(hipMemcpyAsync(res.alphas.data(), d_alphas.as<double>() + (size_t)c * (kMaxIt + 1),
+                            sizeof(double) * na, hipMemcpyDeviceToHost, st));
+    if (na > 1)
+      HIPCHK(hipMemcpyAsync(res.betas.data(), d_betas.as<double>() + (size_t)c * (kMaxIt + 1),
+                            sizeof(double) * (na - 1), hipMemcpyDeviceToHost, st));
+    res.iters = it;
+    res.converged = conv;
+  }
   int herr[2];
   HIPCHK(hipMemcpyAsync(herr, d_status.as<int>() + 2 * L.nsub + 1, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (herr[0]) throw DeviceError("triangular solve wait bound exceeded");
-  res.iters = it;
-  res.converged = conv;
-  res.relres = rel;
-  lanczos_extremes(res.alphas, res.betas, res.lmin, res.lmax);
-  res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  last_history = res.history;
+  const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (PcgResult &res : out) {
+    lanczos_extremes(res.alphas, res.betas, res.lmin, res.lmax);
+    res.seconds = sec;
+  }
+  last_history = out[0].history;
   timer.collect();
-  return res;
+  return out;
 }
 
 double Solver::apply_bytes() const {

@@ -174,3 +174,36 @@ def test_server_resident_factors():
     assert np.array_equal(res[1][0], u_o)
     for (u, _), k in zip([res[0], res[2], res[3]], (1, 2, 3)):
         assert np.array_equal(u, fresh[k][0])
+
+
+def test_server_blocks_on_a_resident_problem_match_the_oracle():
+    """Requests queued on one resident problem are solved as block PCGs (up
+    to 8 loads each): every served solution matches the oracle's solution of
+    its load to 1e-8 (element-wise, relative to the largest entry) and has
+    the bits of a direct single solve."""
+    BDDC, Server = _gpu()
+    from oracle.solver import OracleBDDC
+    p, tau = _requests()[5]  # elasticity 8^3, contrast 1e5, c+e constraints
+    assert tau == 0.0
+    rng = np.random.default_rng(11)
+    loads = [p.f] + [p.f * rng.uniform(0.5, 2.0, p.f.shape) + rng.standard_normal(p.f.shape)
+                     for _ in range(12)]
+    srv = Server(max_active=1, resident_bytes=1e12)
+    ids = [srv.submit(p, tau, f=f) for f in loads]
+    got = [srv.wait(i) for i in ids]
+    srv.close()
+    o = OracleBDDC(p, "ce")
+    b = BDDC()
+    b.setup(p, "ce")
+    b.factor()
+    for k, ((u, info), f) in enumerate(zip(got, loads)):
+        assert info.state == 2, info.error
+        assert k == 0 or info.reused == 1
+        ref = o.solve(f)["u"]
+        err = float(np.abs(u - ref).max() / np.abs(ref).max())
+        assert err < 1e-8, (k, err)
+        u1, _ = b.pcg_solve(torch.from_numpy(f))
+        assert np.array_equal(u, u1.cpu().numpy()[:, 0]), k
+    b.close()
+    batches = [info.batch for _, info in got]
+    assert max(batches) > 1 and max(batches) <= 8, batches
