@@ -109,6 +109,17 @@ __global__ void pair_restrict_kernel(const double *Sss, const int64_t *off_si,
   BJ[off_c[e] + i] = BJfull[off_p[e] + src];
 }
 
+// segment e: dst[dst_off[e] + i] = src[src_off[e] + i] for i < len[e] (many
+// small copies in one launch)
+__global__ void copy_segments_kernel(const double *src, const int64_t *src_off, double *dst,
+                                     const int64_t *dst_off, const int64_t *len) {
+  const int e = blockIdx.y;
+  const int64_t n = len[e], so = src_off[e], dO = dst_off[e];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[dO + i] = src[so + i];
+}
+
 // dst[idx[i]] = val[i]
 __global__ void scatter_values_kernel(const int64_t *idx, const double *val, int64_t n, double *dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1136,31 +1147,10 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
       off_ss[e] = tsh + (int64_t)nsv[e] * nsv[e];
       tsh += 2 * (int64_t)nsv[e] * nsv[e];
     }
-  struct SideGroup {
-    int sub;
-    std::vector<int> sides, U, N;
-  };
-  std::vector<SideGroup> groups;
-  {
-    std::vector<std::vector<int>> by_sub(L.nsub);
-    for (int e = 0; e < nside; ++e) by_sub[pairs[e / 2].sub[e % 2]].push_back(e);
-    for (int sb = 0; sb < L.nsub; ++sb)
-      for (size_t k = 0; k < by_sub[sb].size(); k += 3) {
-        SideGroup g;
-        g.sub = sb;
-        std::vector<char> in(L.nG[sb], 0);
-        for (size_t t = k; t < std::min(by_sub[sb].size(), k + 3); ++t) {
-          const int e = by_sub[sb][t];
-          g.sides.push_back(e);
-          for (int q : pairs[e / 2].pos_s[e % 2]) in[q] = 1;
-        }
-        for (int q = 0; q < L.nG[sb]; ++q) (in[q] ? g.U : g.N).push_back(q);
-        groups.push_back(std::move(g));
-      }
-  }
-  const int ng = (int)groups.size();
   const double *Sd = S.d_S.as<double>();
-  int *d_stat = pool.up(stream, std::vector<int>(3 * np + 2 * nside + 2 * ng + 4, 0));
+  // status words: [0, 2 nside) the eliminations of the bisection, then the
+  // sums of the Schur complements (np) and the jump-space denominators (np)
+  int *d_stat = pool.up(stream, std::vector<int>(2 * nside + 2 * np + 4, 0));
   auto check = [&](int first, int count, const char *what) {
     std::vector<int> hs(count);
     HIPCHK(hipMemcpyAsync(hs.data(), d_stat + first, sizeof(int) * count, hipMemcpyDeviceToHost, stream));
@@ -1239,48 +1229,131 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
     for (int e = 0; e < cnt; ++e) mo[e] = MatDesc{out_off[e], 0, nu[e], 0, std::max(1, nu[e]), 1};
     HIPCHK(symmetrize_lower<double>(stream, out, pool.up(stream, mo), cnt, mnu));
   };
-  // level 1: per group, onto U
-  std::vector<int64_t> g_src(ng), g_off(ng);
-  std::vector<int> g_lds(ng);
-  std::vector<std::vector<int>> g_n(ng), g_u(ng);
-  int64_t tsu = 0;
-  for (int g = 0; g < ng; ++g) {
-    g_src[g] = L.offGG[groups[g].sub];
-    g_lds[g] = L.nG[groups[g].sub];
-    g_n[g] = groups[g].N;
-    g_u[g] = groups[g].U;
-    g_off[g] = tsu;
-    tsu += (int64_t)groups[g].U.size() * groups[g].U.size();
+  // Schur complement of S_a onto the shared dofs s of each pair side, by
+  // recursive bisection of the sides of each substructure (in pair order): a
+  // node holds a contiguous range of the substructure's sides and the Schur
+  // complement of S_a onto the union U of their shared dofs (interface
+  // positions, ascending); each half of a node's range eliminates the rest of
+  // U from the node's matrix.  The root is S_a itself and a one-side node is
+  // Sh of that side.  Equal to eliminating everything but s at once
+  // (quotient property of Schur complements); at the 64^3 k-means size, 9
+  // sides per substructure on average, it takes about 1.7 times fewer flops
+  // than eliminating onto groups of three sides first.  One batched
+  // elimination per tree depth.
+  struct BNode {
+    int sub, lo, hi;    // sides by_sub[sub][lo..hi)
+    std::vector<int> U;  // interface positions of the node's matrix
+    int64_t off = 0;     // its matrix in the work pool (depth >= 1), ld |U|
+  };
+  std::vector<std::vector<int>> by_sub(L.nsub);
+  for (int e = 0; e < nside; ++e) by_sub[pairs[e / 2].sub[e % 2]].push_back(e);
+  auto union_of = [&](int sb, int lo, int hi) {
+    std::vector<char> in(L.nG[sb], 0);
+    for (int t = lo; t < hi; ++t) {
+      const int e = by_sub[sb][t];
+      for (int q : pairs[e / 2].pos_s[e % 2]) in[q] = 1;
+    }
+    std::vector<int> U;
+    for (int q = 0; q < L.nG[sb]; ++q)
+      if (in[q]) U.push_back(q);
+    return U;
+  };
+  // depth 0: the roots (the matrices S_a in place)
+  std::vector<BNode> parents;
+  for (int sb = 0; sb < L.nsub; ++sb) {
+    if (by_sub[sb].empty()) continue;
+    BNode r;
+    r.sub = sb;
+    r.lo = 0;
+    r.hi = (int)by_sub[sb].size();
+    r.U.resize(L.nG[sb]);
+    std::iota(r.U.begin(), r.U.end(), 0);
+    parents.push_back(std::move(r));
   }
-  double *SU = pool.zeros(stream, std::max<int64_t>(tsu, 1));
-  eliminate(Sd, g_src, g_lds, g_n, g_u, SU, g_off, d_stat + 2 * nside);
-  check(2 * nside, ng, "interface blocks outside the shared dofs");
-  // level 2: per side, onto s (from its group's S_U), and the original S_ss
-  double *Sh = pool.zeros(stream, tsh);
-  std::vector<int64_t> s_src(nside), ss_src(nside);
-  std::vector<int> s_lds(nside), ss_lds(nside);
-  std::vector<std::vector<int>> s_n(nside), s_u(nside), ss_idx(nside);
-  for (int g = 0; g < ng; ++g) {
-    const SideGroup &G = groups[g];
-    std::vector<int> at(L.nG[G.sub], -1);
-    for (size_t t = 0; t < G.U.size(); ++t) at[G.U[t]] = (int)t;
-    for (int e : G.sides) {
-      const std::vector<int> &ps = pairs[e / 2].pos_s[e % 2];
-      std::vector<char> mine(G.U.size(), 0);
-      for (int q : ps) {
-        s_u[e].push_back(at[q]);
-        mine[at[q]] = 1;
+  // the children of every depth, and the work pool: Sh (and the S_ss
+  // copies) first, then the inner nodes' matrices
+  std::vector<std::vector<BNode>> depth_nodes;
+  std::vector<std::vector<int>> depth_parent;
+  int64_t twk = tsh;
+  {
+    std::vector<BNode> cur = parents;
+    while (!cur.empty()) {
+      std::vector<BNode> kids;
+      std::vector<int> par;
+      for (int k = 0; k < (int)cur.size(); ++k) {
+        const BNode &P = cur[k];
+        const int n = P.hi - P.lo;
+        const int mid = P.lo + n / 2;
+        const int cuts[3] = {P.lo, n == 1 ? P.hi : mid, P.hi};
+        for (int h = 0; h < (n == 1 ? 1 : 2); ++h) {
+          BNode c;
+          c.sub = P.sub;
+          c.lo = cuts[h];
+          c.hi = cuts[h + 1];
+          c.U = union_of(c.sub, c.lo, c.hi);
+          if (c.hi - c.lo == 1) {
+            c.off = off_sh[by_sub[c.sub][c.lo]];
+          } else {
+            c.off = twk;
+            twk += (int64_t)c.U.size() * c.U.size();
+          }
+          kids.push_back(std::move(c));
+          par.push_back(k);
+        }
       }
-      for (size_t t = 0; t < G.U.size(); ++t)
-        if (!mine[t]) s_n[e].push_back((int)t);
-      s_src[e] = g_off[g];
-      s_lds[e] = (int)G.U.size();
-      ss_src[e] = L.offGG[G.sub];
-      ss_lds[e] = L.nG[G.sub];
+      depth_nodes.push_back(kids);
+      depth_parent.push_back(par);
+      std::vector<BNode> inner;
+      for (BNode &c : kids)
+        if (c.hi - c.lo > 1) inner.push_back(c);
+      // inner nodes become the next depth's parents; remember the parent
+      // list of this depth for the index maps
+      cur.swap(inner);
     }
   }
-  eliminate(SU, s_src, s_lds, s_n, s_u, Sh, off_sh, d_stat);
-  check(0, nside, "non-shared interface blocks");
+  double *Wk = pool.zeros(stream, twk);
+  double *Sh = Wk;  // Sh of side e at off_sh[e], its S_ss at off_ss[e]
+  {
+    std::vector<BNode> cur = parents;  // parents of the depth being formed
+    int stat_next = 0;
+    for (size_t dpt = 0; dpt < depth_nodes.size(); ++dpt) {
+      const std::vector<BNode> &kids = depth_nodes[dpt];
+      const int cnt = (int)kids.size();
+      std::vector<int64_t> src_off(cnt), out_off(cnt);
+      std::vector<int> lds(cnt);
+      std::vector<std::vector<int>> nidx(cnt), uidx(cnt);
+      for (int c = 0; c < cnt; ++c) {
+        const BNode &P = cur[depth_parent[dpt][c]];
+        const BNode &K = kids[c];
+        std::vector<int> at(L.nG[K.sub], -1);
+        for (size_t t = 0; t < P.U.size(); ++t) at[P.U[t]] = (int)t;
+        std::vector<char> keep(P.U.size(), 0);
+        for (int q : K.U) {
+          uidx[c].push_back(at[q]);
+          keep[at[q]] = 1;
+        }
+        for (size_t t = 0; t < P.U.size(); ++t)
+          if (!keep[t]) nidx[c].push_back((int)t);
+        src_off[c] = dpt == 0 ? L.offGG[K.sub] : P.off;
+        lds[c] = dpt == 0 ? L.nG[K.sub] : (int)P.U.size();
+        out_off[c] = K.off;
+      }
+      eliminate(dpt == 0 ? Sd : Wk, src_off, lds, nidx, uidx, Wk, out_off, d_stat + stat_next);
+      check(stat_next, cnt, "interface blocks outside the shared dofs");
+      stat_next += cnt;
+      std::vector<BNode> inner;
+      for (const BNode &K : kids)
+        if (K.hi - K.lo > 1) inner.push_back(K);
+      cur.swap(inner);
+    }
+  }
+  std::vector<int64_t> ss_src(nside);
+  std::vector<int> ss_lds(nside);
+  for (int e = 0; e < nside; ++e) {
+    const int sb = pairs[e / 2].sub[e % 2];
+    ss_src[e] = L.offGG[sb];
+    ss_lds[e] = L.nG[sb];
+  }
   {
     // the original S_ss of every side (for the numerator M)
     std::vector<int> ss_all;
@@ -1362,12 +1435,12 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   }
   MatDesc *d_mds = pool.up(stream, mds);
   GemmDesc *d_gbj = pool.up(stream, gbj);
-  int *stat2 = d_stat + nside;
+  int *stat2 = d_stat + 2 * nside;
   double *dv_s;
   int64_t *do_s;
   dinv_for(mds, dv_s, do_s);
   HIPCHK(DenseOps<double>::potrf(stream, Ssum, d_mds, mds.data(), np, stat2, dv_s, do_s));
-  check(nside, np, "sum of the Schur complements");
+  check(2 * nside, np, "sum of the Schur complements");
   HIPCHK(DenseOps<double>::trsm(stream, Ssum, Xb, d_mds, mds.data(), np, false, dv_s, do_s));
   HIPCHK(DenseOps<double>::trsm(stream, Ssum, Xb, d_mds, mds.data(), np, true, dv_s, do_s));
   // BJ = Sh_i (Sh_i + Sh_j)^+ Sh_j, the product form of the parallel sum (no
@@ -1421,7 +1494,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   int64_t *do_y;
   dinv_for(mdd, dv_y, do_y);
   HIPCHK(DenseOps<double>::potrf(stream, By, d_mdd, mdd.data(), np, stat3, dv_y, do_y));
-  check(nside + np, np, "jump-space denominator");
+  check(2 * nside + np, np, "jump-space denominator");
   // My <- L^-1 My ; Cp <- My^T ; Cp <- L^-1 Cp   (My's pool is the B operand)
   HIPCHK(DenseOps<double>::trsm(stream, By, My, d_mdd, mdd.data(), np, false, dv_y, do_y));
   transpose_kernel<<<dim3(nblocks((int64_t)max_d * max_d), np), TPB, 0, stream>>>(My, Cp, d_off_dd, d_dv);
@@ -1473,6 +1546,18 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   std::vector<int> ksel(np, 0), active(np);
   std::vector<std::vector<double>> evs(np);
   std::iota(active.begin(), active.end(), 0);
+  // the per-pair pieces of a round (start blocks in, Ritz values out,
+  // selected vectors kept) move as segments of one launch each
+  auto copy_segments = [&](const double *src, double *dst, const std::vector<int64_t> &so,
+                           const std::vector<int64_t> &dO, const std::vector<int64_t> &len) {
+    const int nseg = (int)len.size();
+    if (nseg == 0) return;
+    int64_t mx = 1;
+    for (int64_t l : len) mx = std::max(mx, l);
+    copy_segments_kernel<<<dim3((unsigned)std::min<int64_t>(nblocks(mx), 64), nseg), TPB, 0, stream>>>(
+        src, pool.up(stream, so), dst, pool.up(stream, dO), pool.up(stream, len));
+    HIPCHK(hipGetLastError());
+  };
   for (int round = 0; round < 64 && !active.empty(); ++round) {
     const int na = (int)active.size();
     std::vector<LobDesc> lda(na);
@@ -1501,8 +1586,17 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
           z ^= z >> 31;
           x0[(size_t)q * dv[p] + r] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
         }
-      HIPCHK(hipMemcpyAsync(LP + ld[p].v_off, x0, sizeof(double) * (x0off[a + 1] - x0off[a]),
-                            hipMemcpyHostToDevice, stream));
+    }
+    {
+      // every start block in one transfer, then to its place in LP
+      double *x0d = pool.up(stream, X0all.empty() ? std::vector<double>{0.0} : X0all);
+      std::vector<int64_t> so(na), dO(na), len(na);
+      for (int a = 0; a < na; ++a) {
+        so[a] = x0off[a];
+        dO[a] = ld[active[a]].v_off;
+        len[a] = x0off[a + 1] - x0off[a];
+      }
+      copy_segments(x0d, LP, so, dO, len);
     }
     HIPCHK(hipMemcpyAsync(ldb.p, lda.data(), sizeof(LobDesc) * na, hipMemcpyHostToDevice, stream));
     {
@@ -1521,13 +1615,24 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
     std::vector<LobOut> lo(na);
     HIPCHK(hipMemcpyAsync(lo.data(), outb.p, sizeof(LobOut) * na, hipMemcpyDeviceToHost, stream));
     std::vector<std::vector<double>> th(na);
-    for (int a = 0; a < na; ++a) {
-      const int p = active[a];
-      th[a].resize(ld[p].s);
-      HIPCHK(hipMemcpyAsync(th[a].data(), LP + ld[p].t_off, sizeof(double) * ld[p].s,
-                            hipMemcpyDeviceToHost, stream));
+    {
+      // the Ritz values of every pair gathered, then one transfer
+      std::vector<int64_t> so(na), dO(na), len(na);
+      int64_t tot = 0;
+      for (int a = 0; a < na; ++a) {
+        so[a] = ld[active[a]].t_off;
+        len[a] = ld[active[a]].s;
+        dO[a] = tot;
+        tot += len[a];
+      }
+      double *thd = pool.zeros(stream, std::max<int64_t>(1, tot));
+      copy_segments(LP, thd, so, dO, len);
+      std::vector<double> tall(std::max<int64_t>(1, tot));
+      HIPCHK(hipMemcpyAsync(tall.data(), thd, sizeof(double) * tall.size(), hipMemcpyDeviceToHost,
+                            stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      for (int a = 0; a < na; ++a) th[a].assign(tall.begin() + dO[a], tall.begin() + dO[a] + len[a]);
     }
-    HIPCHK(hipStreamSynchronize(stream));
     if (LaunchTiming *lt = launch_timing()) {
       // algorithmic work: per iteration one pass over the pair matrix C'
       // (d x d) multiplying the s-column search block
@@ -1540,7 +1645,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
       lt->launch_amend(by, fl);
     }
     std::vector<int> next;
-    std::vector<GemmDesc> gdef;
+    std::vector<int64_t> keep_so, keep_do, keep_len;  // selected eigenvectors to keep
     for (int a = 0; a < na; ++a) {
       const int p = active[a];
       const int s = ld[p].s;
@@ -1553,9 +1658,11 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
         while (k < s && th[a][k] >= tau) ++k;
       evs[p].insert(evs[p].end(), th[a].begin(), th[a].end());
       // keep the selected eigenvectors
-      if (k > 0)
-        HIPCHK(hipMemcpyAsync(Yv + off_y[p] + (int64_t)ksel[p] * dv[p], LP + ld[p].v_off,
-                              sizeof(double) * dv[p] * k, hipMemcpyDeviceToDevice, stream));
+      if (k > 0) {
+        keep_so.push_back(ld[p].v_off);
+        keep_do.push_back(tdd + tv + off_y[p] + (int64_t)ksel[p] * dv[p]);
+        keep_len.push_back((int64_t)dv[p] * k);
+      }
       ksel[p] += k;
       if (k < s) {
         res.omega = std::max(res.omega, th[a][k]);
@@ -1563,6 +1670,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
         next.push_back(p);  // the block held only selected pairs: lock them, go on
       }
     }
+    copy_segments(LP, LP, keep_so, keep_do, keep_len);  // (source and target regions are disjoint)
     if (S.verbose) {
       int mx = 0, nu = 0;
       std::string bad;
@@ -1615,11 +1723,11 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   HIPCHK(DenseOps<double>::gemm(stream, Mc, Jv, Vtmp, d_gm, np, max_c, max_k, false, false, 1.0, 0.0, false, gm.data()));
   (void)Vv;
   std::vector<double> hv(tj);
-  std::vector<int> hstat(3 * np + 2 * nside + 4);
+  std::vector<int> hstat(2 * nside + 2 * np + 4);
   HIPCHK(hipMemcpyAsync(hv.data(), Vtmp, sizeof(double) * tj, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipMemcpyAsync(hstat.data(), d_stat, sizeof(int) * hstat.size(), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
-  for (int e = 0; e < nside + 2 * np; ++e)
+  for (int e = 0; e < 2 * nside + 2 * np; ++e)
     if (hstat[e])
       throw NotSpdError("adaptive pair problems: non-positive pivot in a pair factor (Assumption 2 may fail)");
   log("eigenvectors to jump space");
