@@ -69,6 +69,43 @@ __device__ __forceinline__ bool xcd_remap(int nwg, int tiles_per_entry, int batc
   return entry < batch;
 }
 
+// tile (ti, tj), tj <= ti, of the lower triangle from a linear index
+__device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
+  int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  ti = i;
+  tj = t - i * (i + 1) / 2;
+}
+
+// Only the tiles each entry has: the host sums every entry's tile count into
+// off[0..n] (passed by value with the launch), and work-group ids (remapped
+// as in xcd_remap, so an entry's tiles stay on one XCD) are split at those
+// offsets.  A batch of uneven entries then launches no empty work-groups.
+// n = 0: not used (the caller falls back to a grid sized by its largest entry).
+constexpr int kMaxMapEntries = 480;
+struct TileMap {
+  int n;
+  int off[kMaxMapEntries + 1];
+};
+__device__ __forceinline__ bool map_tile(const TileMap &m, int nwg, int &entry, int &tile) {
+  const int b = blockIdx.x;
+  int logical = b;
+  if ((nwg % NXCD) == 0) logical = (b % NXCD) * (nwg / NXCD) + (b / NXCD);
+  if (logical >= m.off[m.n]) return false;
+  int lo = 0, hi = m.n;  // off[lo] <= logical < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (m.off[mid] <= logical)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  entry = lo;
+  tile = logical - m.off[lo];
+  return true;
+}
+
 // C[m0:m0+TM, n0:n0+TN] = beta*C + alpha*op(A)*op(B), bounds-checked, with
 // TM = 32 MT and TN = 32 NT: in each group of four waves, the waves own 2 x 2
 // quadrants of MT x NT MFMA blocks of 16 x 16.  Operands go through two LDS
@@ -254,15 +291,29 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
   }
 }
 
+// map.n > 0: the entry's own tiles only (lower: its lower-triangle tiles,
+// TM = TN and M = N for every entry)
 template <class T, bool TA, bool TB, int MT, int NT>
 __global__ __launch_bounds__(256) void gemm_kernel(const T *A, const T *B, T *C,
                                                    const GemmDesc *desc, int tm, int tn, T alpha,
-                                                   T beta, int lower, int batch) {
+                                                   T beta, int lower, int batch, const TileMap map) {
   constexpr int TM = 32 * MT, TN = 32 * NT;
-  int e, t;
-  if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
+  int e, t, ti, tj;
+  if (map.n > 0) {
+    if (!map_tile(map, gridDim.x, e, t)) return;
+    if (lower) {
+      lower_tile(t, ti, tj);
+    } else {
+      const int tme = (desc[e].M + TM - 1) / TM;
+      ti = t % tme;
+      tj = t / tme;
+    }
+  } else {
+    if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
+    ti = t % tm;
+    tj = t / tm;
+  }
   const GemmDesc d = desc[e];
-  const int ti = t % tm, tj = t / tm;
   const int m0 = ti * TM, n0 = tj * TN;
   if (m0 >= d.M || n0 >= d.N) return;
   if (lower && m0 + TM - 1 < n0) return;
@@ -314,24 +365,16 @@ __global__ __launch_bounds__(256 * KS) void chol_update_kernel(T *pool, const Ma
                                           d.lda, T(-1), T(1), t * TM, 0);
 }
 
-// tile (ti, tj), tj <= ti, of the lower triangle from a linear index
-__device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
-  int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  while (i * (i + 1) / 2 > t) --i;
-  ti = i;
-  tj = t - i * (i + 1) / 2;
-}
-
 // Trailing update after a factored panel of columns [p0, p1):
 // A[p1:, p1:] -= L[p1:, p0:p1] L[p1:, p0:p1]^T, lower triangle only, 128 x 128
 // tiles (tile pairs tj <= ti, tm tile rows for the largest entry); the
 // diagonal tiles write only their lower part.
 template <class T>
 __global__ __launch_bounds__(256) void chol_syrk_kernel(T *pool, const MatDesc *desc, int p0, int p1,
-                                                        int tm, int batch) {
+                                                        int tm, int batch, const TileMap map) {
   int e, t;
-  if (!xcd_remap(gridDim.x, tm * (tm + 1) / 2, batch, e, t)) return;
+  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tm * (tm + 1) / 2, batch, e, t))
+    return;
   const MatDesc d = desc[e];
   if (p1 >= d.n) return;
   int ti, tj;
@@ -512,12 +555,24 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool
 // 128-row tiles (tm for the largest entry) by 32 NT-column tiles (tn).
 template <class T, bool BWD, int NT>
 __global__ __launch_bounds__(256) void trsm_gemm_kernel(const T *apool, T *bpool, const MatDesc *desc,
-                                                        int p0, int p1, int tm, int tn, int batch) {
+                                                        int p0, int p1, int tm, int tn, int batch,
+                                                        const TileMap map) {
   constexpr int TN = 32 * NT;
-  int e, t;
-  if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
+  int e, t, ti, tj;
+  if (map.n > 0) {
+    if (!map_tile(map, gridDim.x, e, t)) return;
+    // the entry's own row tiles: below the panel (forward) or above it
+    const MatDesc q = desc[e];
+    const int rows = BWD ? (p0 < min(p1, q.n) ? p0 : 0) : max(0, q.n - p1);
+    const int tme = max(1, (rows + 127) / 128);
+    ti = t % tme;
+    tj = t / tme;
+  } else {
+    if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
+    ti = t % tm;
+    tj = t / tm;
+  }
   const MatDesc d = desc[e];
-  const int ti = t % tm, tj = t / tm;
   if (tj * TN >= d.nrhs) return;
   const T *L = apool + d.a_off;
   T *B = bpool + d.b_off;
@@ -877,6 +932,18 @@ LaunchTiming *&launch_timing() {
 
 namespace {
 inline int grid_round(int n) { return ((n + NXCD - 1) / NXCD) * NXCD; }
+// the tile map of a launch, cnt(e) tiles for entry e; map.n = 0 (not used)
+// when the batch has more entries than a map holds
+template <class F>
+TileMap tile_map(int batch, F cnt) {
+  TileMap m;
+  m.n = 0;
+  if (batch <= 0 || batch > kMaxMapEntries) return m;
+  m.off[0] = 0;
+  for (int e = 0; e < batch; ++e) m.off[e + 1] = m.off[e] + std::max(0, cnt(e));
+  m.n = batch;
+  return m;
+}
 inline int blk(int n, int k) { return std::max(0, std::min(NB, n - k * NB)); }
 }  // namespace
 
@@ -985,17 +1052,33 @@ int64_t autotune_entries() {
 template <class T, int MT, int NT>
 static void launch_gemm(hipStream_t st, const T *A, const T *B, T *C, const GemmDesc *d_desc,
                         int batch, int maxM, int maxN, bool transA, bool transB, T alpha, T beta,
-                        bool lower) {
-  const int tm = (maxM + 32 * MT - 1) / (32 * MT), tn = (maxN + 32 * NT - 1) / (32 * NT);
-  const dim3 g(grid_round(batch * tm * tn)), b(256);
+                        bool lower, const GemmDesc *h_desc) {
+  constexpr int TM = 32 * MT, TN = 32 * NT;
+  const int tm = (maxM + TM - 1) / TM, tn = (maxN + TN - 1) / TN;
+  // with the host descriptors, each entry's own tiles only (lower: square
+  // tiles of square products, the lower triangle's tiles)
+  TileMap map;
+  map.n = 0;
+  bool can_map = h_desc != nullptr && (!lower || TM == TN);
+  for (int e = 0; can_map && lower && e < batch; ++e) can_map = h_desc[e].M == h_desc[e].N;
+  if (can_map)
+    map = tile_map(batch, [&](int e) {
+      const GemmDesc &q = h_desc[e];
+      if (q.M <= 0 || q.N <= 0) return 0;
+      const int a = (q.M + TM - 1) / TM, b = (q.N + TN - 1) / TN;
+      return lower ? a * (a + 1) / 2 : a * b;
+    });
+  const int nt = map.n > 0 ? map.off[map.n] : batch * tm * tn;
+  if (nt <= 0) return;
+  const dim3 g(grid_round(nt)), b(256);
   if (!transA && !transB)
-    gemm_kernel<T, false, false, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+    gemm_kernel<T, false, false, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch, map);
   else if (transA && !transB)
-    gemm_kernel<T, true, false, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+    gemm_kernel<T, true, false, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch, map);
   else if (!transA && transB)
-    gemm_kernel<T, false, true, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+    gemm_kernel<T, false, true, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch, map);
   else
-    gemm_kernel<T, true, true, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch);
+    gemm_kernel<T, true, true, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch, map);
 }
 
 template <class T>
@@ -1021,10 +1104,10 @@ hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const
   LaunchScope ls(st, "gemm_kernel", by, fl);
   auto launch = [&](int shape) {
     switch (shape) {
-      case 0: launch_gemm<T, 4, 4>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower); break;
-      case 1: launch_gemm<T, 2, 2>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower); break;
-      case 2: launch_gemm<T, 4, 2>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower); break;
-      default: launch_gemm<T, 2, 4>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower); break;
+      case 0: launch_gemm<T, 4, 4>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower, h_desc); break;
+      case 1: launch_gemm<T, 2, 2>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower, h_desc); break;
+      case 2: launch_gemm<T, 4, 2>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower, h_desc); break;
+      default: launch_gemm<T, 2, 4>(st, A, B, C, d_desc, batch, maxM, maxN, transA, transB, alpha, beta, lower, h_desc); break;
     }
   };
   // 128 x 128 tiles for large products, 64 x 64 otherwise, unless the tuner
@@ -1153,8 +1236,13 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
           bs += sizeof(T) * (m * (p1 - p0) + m * (m + 1));
         }
       LaunchScope ls(st, "chol_syrk_kernel", bs, fs);
-      chol_syrk_kernel<T><<<grid_round(batch * (tm * (tm + 1) / 2)), 256, 0, st>>>(pool, d_desc, p0,
-                                                                                  p1, tm, batch);
+      const TileMap map = tile_map(batch, [&](int e) {
+        const int a = (h_desc[e].n - p1 + 127) / 128;
+        return h_desc[e].n > p1 ? a * (a + 1) / 2 : 0;
+      });
+      const int nt = map.n > 0 ? map.off[map.n] : batch * (tm * (tm + 1) / 2);
+      if (nt > 0)
+        chol_syrk_kernel<T><<<grid_round(nt), 256, 0, st>>>(pool, d_desc, p0, p1, tm, batch, map);
     }
   }
   return hipGetLastError();
@@ -1223,20 +1311,28 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
         bg += sizeof(T) * (m * kk + kk * r + 2.0 * m * r);
       }
     LaunchScope ls(st, bwd ? "trsm_gemm_kernel<bwd>" : "trsm_gemm_kernel<fwd>", bg, fg);
-    if (maxr >= 128) {
-      const int tq = (maxr + 127) / 128;
-      const unsigned g = grid_round(batch * tm * tq);
+    const int tw = maxr >= 128 ? 128 : 64;  // right-hand-side columns per tile
+    const int tq = (maxr + tw - 1) / tw;
+    // each entry's own tiles: its row tiles on the unsolved side times its
+    // column tiles
+    const TileMap map = tile_map(batch, [&](int e) {
+      const int n = h_desc[e].n;
+      const int r = bwd ? (p0 < std::min(p1, n) ? p0 : 0) : std::max(0, n - p1);
+      return ((r + 127) / 128) * ((h_desc[e].nrhs + tw - 1) / tw);
+    });
+    const int nt = map.n > 0 ? map.off[map.n] : batch * tm * tq;
+    if (nt <= 0) return;
+    const unsigned g = grid_round(nt);
+    if (tw == 128) {
       if (bwd)
-        trsm_gemm_kernel<T, true, 4><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch);
+        trsm_gemm_kernel<T, true, 4><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch, map);
       else
-        trsm_gemm_kernel<T, false, 4><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch);
+        trsm_gemm_kernel<T, false, 4><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch, map);
     } else {
-      const int tq = (maxr + 63) / 64;
-      const unsigned g = grid_round(batch * tm * tq);
       if (bwd)
-        trsm_gemm_kernel<T, true, 2><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch);
+        trsm_gemm_kernel<T, true, 2><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch, map);
       else
-        trsm_gemm_kernel<T, false, 2><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch);
+        trsm_gemm_kernel<T, false, 2><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch, map);
     }
   };
   const bool timing = launch_timing() != nullptr;
