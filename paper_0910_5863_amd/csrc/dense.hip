@@ -326,12 +326,21 @@ template <class T, int MT, int NT>
 __global__ __launch_bounds__(256) void gemm_scatter_kernel(const T *A, const T *B, T *C,
                                                            const GemmDesc *desc, const int *map,
                                                            const int64_t *map_off, int map_rows,
-                                                           int tm, int tn, int batch) {
+                                                           int tm, int tn, int batch,
+                                                           const TileMap tmap) {
   constexpr int TM = 32 * MT, TN = 32 * NT;
-  int e, t;
-  if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
+  int e, t, ti, tj;
+  if (tmap.n > 0) {
+    if (!map_tile(tmap, gridDim.x, e, t)) return;
+    const int tme = (desc[e].M + TM - 1) / TM;
+    ti = t % tme;
+    tj = t / tme;
+  } else {
+    if (!xcd_remap(gridDim.x, tm * tn, batch, e, t)) return;
+    ti = t % tm;
+    tj = t / tm;
+  }
   const GemmDesc d = desc[e];
-  const int ti = t % tm, tj = t / tm;
   const int m0 = ti * TM, n0 = tj * TN;
   if (m0 >= d.M || n0 >= d.N) return;
   const int *mp = map + map_off[e];
@@ -350,10 +359,11 @@ __global__ __launch_bounds__(256) void gemm_scatter_kernel(const T *A, const T *
 // groups of waves splitting K (for launches with few tiles)
 template <class T, int MT, int KS>
 __global__ __launch_bounds__(256 * KS) void chol_update_kernel(T *pool, const MatDesc *desc, int k,
-                                                               int k0, int tm, int batch) {
+                                                               int k0, int tm, int batch,
+                                                               const TileMap map) {
   constexpr int TM = 32 * MT;
   int e, t;
-  if (!xcd_remap(gridDim.x, tm, batch, e, t)) return;
+  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tm, batch, e, t)) return;
   const MatDesc d = desc[e];
   const int kb = k * NB, c0 = k0 * NB;
   if (kb >= d.n || k <= k0) return;
@@ -478,9 +488,9 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(T *pool, const MatDesc *
 template <class T>
 __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc *desc, int k,
                                                          int tm, int batch, const T *dinv,
-                                                         const int64_t *dinv_off) {
+                                                         const int64_t *dinv_off, const TileMap map) {
   int e, t;
-  if (!xcd_remap(gridDim.x, tm, batch, e, t)) return;
+  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tm, batch, e, t)) return;
   const MatDesc d = desc[e];
   const int kb = k * NB;
   if (kb >= d.n) return;
@@ -504,10 +514,11 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc 
 template <class T, bool BWD, int NT, int KS>
 __global__ __launch_bounds__(256 * KS) void trsm_update_kernel(const T *apool, T *bpool,
                                                                const MatDesc *desc, int k, int p0,
-                                                               int p1, int tn, int batch) {
+                                                               int p1, int tn, int batch,
+                                                               const TileMap map) {
   constexpr int TN = 32 * NT;
   int e, t;
-  if (!xcd_remap(gridDim.x, tn, batch, e, t)) return;
+  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tn, batch, e, t)) return;
   const MatDesc d = desc[e];
   const int kb = k * NB;
   if (kb >= d.n) return;
@@ -535,9 +546,9 @@ template <class T, bool BWD>
 __global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool,
                                                         const MatDesc *desc, int k, int tn,
                                                         int batch, const T *dinv,
-                                                        const int64_t *dinv_off) {
+                                                        const int64_t *dinv_off, const TileMap map) {
   int e, t;
-  if (!xcd_remap(gridDim.x, tn, batch, e, t)) return;
+  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tn, batch, e, t)) return;
   const MatDesc d = desc[e];
   const int kb = k * NB;
   if (kb >= d.n) return;
@@ -1154,8 +1165,16 @@ hipError_t DenseOps<T>::gemm_scatter(hipStream_t st, const T *A, const T *B, T *
     }
   LaunchScope ls(st, "gemm_scatter_kernel", by, fl);
   const int tm = (maxM + 63) / 64, tn = (maxN + 63) / 64;
-  gemm_scatter_kernel<T, 2, 2><<<grid_round(batch * tm * tn), 256, 0, st>>>(
-      A, B, C, d_desc, map, map_off, map_rows ? 1 : 0, tm, tn, batch);
+  TileMap tmap;
+  tmap.n = 0;
+  if (h_desc)
+    tmap = tile_map(batch, [&](int e) {
+      return h_desc[e].M > 0 && h_desc[e].N > 0 ? ((h_desc[e].M + 63) / 64) * ((h_desc[e].N + 63) / 64) : 0;
+    });
+  const int nt = tmap.n > 0 ? tmap.off[tmap.n] : batch * tm * tn;
+  if (nt <= 0) return hipSuccess;
+  gemm_scatter_kernel<T, 2, 2><<<grid_round(nt), 256, 0, st>>>(
+      A, B, C, d_desc, map, map_off, map_rows ? 1 : 0, tm, tn, batch, tmap);
   return hipGetLastError();
 }
 
@@ -1203,15 +1222,26 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
           fp += below * nb * nb;
           bp += sizeof(T) * (2.0 * below * nb + 0.5 * nb * nb);
         }
+      // the tiles of the rows from block k down, per entry (rows of rt each)
+      auto rows_map = [&](int rt, int skip) {
+        return tile_map(batch, [&](int e) {
+          const int m = h_desc[e].n - k * NB;
+          return m > 0 ? (m + rt - 1) / rt - skip : 0;
+        });
+      };
       if (k > k0) {
         LaunchScope ls(st, "chol_update_kernel", bu, fu);
         if (batch * tu >= 2048) {  // 128-row tiles only when they fill the device several times
-          chol_update_kernel<T, 4, 1><<<grid_round(batch * tu), 256, 0, st>>>(pool, d_desc, k, k0,
-                                                                             tu, batch);
+          const TileMap map = rows_map(128, 0);
+          const int nt = map.n > 0 ? map.off[map.n] : batch * tu;
+          if (nt > 0)
+            chol_update_kernel<T, 4, 1><<<grid_round(nt), 256, 0, st>>>(pool, d_desc, k, k0, tu, batch, map);
         } else {
           const int t64 = (maxn - k * NB + 63) / 64;
-          chol_update_kernel<T, 2, 2><<<grid_round(batch * t64), 512, 0, st>>>(pool, d_desc, k, k0,
-                                                                               t64, batch);
+          const TileMap map = rows_map(64, 0);
+          const int nt = map.n > 0 ? map.off[map.n] : batch * t64;
+          if (nt > 0)
+            chol_update_kernel<T, 2, 2><<<grid_round(nt), 512, 0, st>>>(pool, d_desc, k, k0, t64, batch, map);
         }
       }
       {
@@ -1220,8 +1250,11 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
       }
       if (tm > 1) {
         LaunchScope ls(st, "chol_panel_kernel", bp, fp);
-        chol_panel_kernel<T><<<grid_round(batch * (tm - 1)), 256, 0, st>>>(pool, d_desc, k, tm - 1,
-                                                                            batch, dinv, dinv_off);
+        const TileMap map = rows_map(NB, 1);  // the blocks below the diagonal one
+        const int nt = map.n > 0 ? map.off[map.n] : batch * (tm - 1);
+        if (nt > 0)
+          chol_panel_kernel<T><<<grid_round(nt), 256, 0, st>>>(pool, d_desc, k, tm - 1, batch, dinv,
+                                                               dinv_off, map);
       }
     }
     const int p0 = k0 * NB, p1 = k1 * NB;
@@ -1271,29 +1304,57 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
   const int nblk = (maxn + NB - 1) / NB;
   const int tn = (maxr + NB - 1) / NB;    // 64-wide column tiles (diagonal step)
   const int tu = (maxr + 127) / 128;      // 128-wide column tiles (update)
-  const int nwg = grid_round(batch * tn), nwu = grid_round(batch * tu);
+
   // few tiles: 32-wide tiles, two groups of waves per tile splitting K
   const bool narrow = batch * tu < 512;
+  // the column tiles (cw columns each) of the entries that have work at
+  // block row k: below the panel start (forward) or with solved rows of the
+  // panel below block k (backward)
+  auto col_map = [&](int cw, int k, int p0, int p1, int mode) {
+    return tile_map(batch, [&](int e) {
+      const int n = h_desc[e].n, kb = k * NB;
+      if (kb >= n) return 0;
+      if (mode == 1 && kb <= p0) return 0;
+      if (mode == 2 && std::min(p1, n) - kb - std::min(NB, n - kb) <= 0) return 0;
+      return (h_desc[e].nrhs + cw - 1) / cw;
+    });
+  };
   auto update = [&](bool bwd, int k, int p0, int p1) {
     if (!narrow) {
+      const TileMap map = col_map(128, k, p0, p1, bwd ? 2 : 1);
+      const int nt = map.n > 0 ? map.off[map.n] : batch * tu;
+      if (nt <= 0) return;
       if (bwd)
-        trsm_update_kernel<T, true, 4, 1><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1, tu,
-                                                              batch);
+        trsm_update_kernel<T, true, 4, 1><<<grid_round(nt), 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0,
+                                                                         p1, tu, batch, map);
       else
-        trsm_update_kernel<T, false, 4, 1><<<nwu, 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1, tu,
-                                                               batch);
+        trsm_update_kernel<T, false, 4, 1><<<grid_round(nt), 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0,
+                                                                          p1, tu, batch, map);
     } else {
       // 32-column tiles: twice the work-groups of 64-column ones for few
       // right-hand sides (the same sums, in the same order)
       const int t32 = (maxr + 31) / 32;
-      const int nw32 = grid_round(batch * t32);
+      const TileMap map = col_map(32, k, p0, p1, bwd ? 2 : 1);
+      const int nt = map.n > 0 ? map.off[map.n] : batch * t32;
+      if (nt <= 0) return;
       if (bwd)
-        trsm_update_kernel<T, true, 1, 2><<<nw32, 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1,
-                                                               t32, batch);
+        trsm_update_kernel<T, true, 1, 2><<<grid_round(nt), 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0,
+                                                                         p1, t32, batch, map);
       else
-        trsm_update_kernel<T, false, 1, 2><<<nw32, 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1,
-                                                                t32, batch);
+        trsm_update_kernel<T, false, 1, 2><<<grid_round(nt), 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0,
+                                                                          p1, t32, batch, map);
     }
+  };
+  auto diag = [&](bool bwd, int k) {
+    const TileMap map = col_map(NB, k, 0, 0, 0);
+    const int nt = map.n > 0 ? map.off[map.n] : batch * tn;
+    if (nt <= 0) return;
+    if (bwd)
+      trsm_diag_kernel<T, true><<<grid_round(nt), 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
+                                                                dinv_off, map);
+    else
+      trsm_diag_kernel<T, false><<<grid_round(nt), 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
+                                                                 dinv_off, map);
   };
   // rows outside the panel [p0, p1): below it (forward) or above it (backward)
   auto panel_gemm = [&](bool bwd, int p0, int p1) {
@@ -1365,8 +1426,7 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
           update(false, k, p0, p1);
         }
         LaunchScope ls(st, "trsm_diag_kernel<fwd>", bd, fd);
-        trsm_diag_kernel<T, false><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
-                                                        dinv_off);
+        diag(false, k);
       }
       panel_gemm(false, p0, p1);
     }
@@ -1383,8 +1443,7 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
           update(true, k, p0, p1);
         }
         LaunchScope ls(st, "trsm_diag_kernel<bwd>", bd, fd);
-        trsm_diag_kernel<T, true><<<nwg, 256, 0, st>>>(pool_a, pool_b, d_desc, k, tn, batch, dinv,
-                                                       dinv_off);
+        diag(true, k);
       }
       panel_gemm(true, p0, p1);
     }
