@@ -397,18 +397,34 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(T *pool, const MatDesc *
                                               d.lda, d.lda, d.lda, T(-1), T(1), ti * 128, tj * 128);
 }
 
-// Factor the diagonal block of block column k in LDS, in place, and write
-// the inverse of the factored block to dinv (entry e, block k at
-// dinv + dinv_off[e] + k NB^2, ld NB, zero outside the w x w block): one
-// work-group per entry.  status[e] receives (column+1) of the first
-// non-positive pivot.
+// value of v in lane l (l uniform over the wave)
+__device__ __forceinline__ double readlane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Factor the diagonal block of block column k in place and write the inverse
+// of the factored block to dinv (entry e, block k at dinv + dinv_off[e] +
+// k NB^2, ld NB, zero outside the w x w block): one wave per entry.  Lane r
+// holds row r of the block in registers; column c is eliminated right-looking
+// with the entries of column c broadcast from their lanes (readlane), so the
+// column steps need no barrier and no LDS traffic.  Per entry the operations
+// and their order are those of the row-by-row elimination: a = a_rc / a_cc,
+// a_rs -= a a_sc for s > c, then l_rc = a_rc / sqrt(a_cc).  The inverse is
+// formed as before, lane j taking column j by forward substitution against
+// the rows of L broadcast from LDS.  status[e] receives (column+1) of the
+// first non-positive pivot.
 template <class T>
-__global__ __launch_bounds__(256) void chol_diag_kernel(T *pool, const MatDesc *desc, int k,
-                                                        int *status, int batch, T *dinv,
-                                                        const int64_t *dinv_off) {
+__global__ __launch_bounds__(64) void chol_diag_kernel(T *pool, const MatDesc *desc, int k,
+                                                       int *status, int batch, T *dinv,
+                                                       const int64_t *dinv_off) {
   __shared__ T D[NB][NB + 1];
   __shared__ T Y[NB][NB + 1];
-  __shared__ int s_fail;
   const int e = blockIdx.x;
   if (e >= batch) return;
   const MatDesc d = desc[e];
@@ -417,68 +433,57 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(T *pool, const MatDesc *
   const int w = min(NB, d.n - kb);
   T *A = pool + d.a_off;
   const int64_t lda = d.lda;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_fail = 0;
-  for (int i = tid; i < NB * NB; i += 256) {
-    const int r = i % NB, c = i / NB;
-    D[r][c] = (r < w && c < w && r >= c) ? A[(kb + r) + (kb + c) * lda] : T(0);
-  }
-  __syncthreads();
-  // right-looking, one barrier per column: column c of L goes to Y (wave 0)
-  // while the trailing matrix in D is updated with the unscaled column,
-  // a_rs -= a_rc a_sc / a_cc, so no entry read in a step is written in it
-  // (reads: column c of D; writes: Y's column c, D's columns > c)
-  for (int c = 0; c < w; ++c) {
-    T piv = D[c][c];
-    if (!(piv > T(0))) {
-      if (tid == 0 && s_fail == 0) s_fail = kb + c + 1;
-      piv = T(1);
-    }
-    const int r = tid & 63;
-    if (tid < 64 && r >= c && r < w) {
+  const int r = threadIdx.x;
+  T row[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    row[c] = (r < w && c < w && r >= c) ? A[(kb + r) + (int64_t)(kb + c) * lda] : T(0);
+  int fail = 0;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c < w) {  // uniform
+      T piv = readlane(row[c], c);
+      if (!(piv > T(0))) {
+        if (fail == 0) fail = kb + c + 1;
+        piv = T(1);
+      }
       const T lcc = sqrt(piv);
-      Y[r][c] = r == c ? lcc : D[r][c] / lcc;
+      const T a = row[c] / piv;
+      // rows r > c: a_rs -= a a_sc for c < s <= r (entries above the
+      // diagonal, s > r, are updated too and never read)
+#pragma unroll
+      for (int sc = c + 1; sc < NB; ++sc) row[sc] -= a * readlane(row[c], sc);
+      row[c] = r == c ? lcc : row[c] / lcc;
     }
-    // trailing update: lane = row r, the four waves take every fourth column
-    if (r > c && r < w) {
-      const T a = D[r][c] / piv;
-      for (int s = c + 1 + (tid >> 6); s <= r; s += 4) D[r][s] -= a * D[s][c];
-    }
-    __syncthreads();
   }
-  for (int i = tid; i < w * w; i += 256) {
-    const int r = i % w, c = i / w;
-    if (r >= c) A[(kb + r) + (kb + c) * lda] = Y[r][c];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (r < w && c < w && r >= c) A[(kb + r) + (int64_t)(kb + c) * lda] = row[c];
+    // the factor, and the identity outside the w x w block, for the inverse
+    D[r][c] = (r < w && c < w) ? (r >= c ? row[c] : T(0)) : (r == c ? T(1) : T(0));
   }
-  if (tid == 0 && s_fail && status) atomicCAS(&status[e], 0, s_fail);
-  // inverse of the factored block: lane j of wave 0 forms column j of L^-1 in
-  // registers by forward substitution against the rows of L broadcast from
-  // LDS (D receives the factor, and the identity outside the w x w block)
-  for (int i = tid; i < NB * NB; i += 256) {
-    const int r = i % NB, c = i / NB;
-    D[r][c] = (r < w && c < w) ? (r >= c ? Y[r][c] : T(0)) : (r == c ? T(1) : T(0));
-  }
+  if (r == 0 && fail && status) atomicCAS(&status[e], 0, fail);
   __syncthreads();
-  if (tid < 64) {
-    const int j = tid;
+  {
+    const int j = r;
     T y[NB];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      T s0 = r == j ? T(1) : T(0), s1 = T(0);
+    for (int rr = 0; rr < NB; ++rr) {
+      T s0 = rr == j ? T(1) : T(0), s1 = T(0);
 #pragma unroll
-      for (int m = 0; m + 1 < r; m += 2) {
-        s0 -= D[r][m] * y[m];
-        s1 -= D[r][m + 1] * y[m + 1];
+      for (int m = 0; m + 1 < rr; m += 2) {
+        s0 -= D[rr][m] * y[m];
+        s1 -= D[rr][m + 1] * y[m + 1];
       }
-      if (r & 1) s0 -= D[r][r - 1] * y[r - 1];
-      y[r] = (s0 + s1) / D[r][r];
+      if (rr & 1) s0 -= D[rr][rr - 1] * y[rr - 1];
+      y[rr] = (s0 + s1) / D[rr][rr];
     }
 #pragma unroll
-    for (int r = 0; r < NB; ++r) Y[r][j] = (r < w && j < w) ? y[r] : T(0);
+    for (int rr = 0; rr < NB; ++rr) Y[rr][j] = (rr < w && j < w) ? y[rr] : T(0);
   }
   __syncthreads();
   T *out = dinv + dinv_off[e] + (int64_t)k * NB * NB;
-  for (int i = tid; i < NB * NB; i += 256) out[i] = Y[i % NB][i / NB];
+  for (int i = r; i < NB * NB; i += 64) out[i] = Y[i % NB][i / NB];
 }
 
 // Row tiles below the diagonal of block column k (tile t >= 1):
@@ -679,16 +684,6 @@ __device__ __forceinline__ bool flag_set(int *flag) {
   return true;
 }
 
-// value of v in lane l (l uniform over the wave)
-__device__ __forceinline__ double readlane(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float readlane(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
 
 // One work-group per 64-row block k of one entry, taken in ticket order
 // (lower: blocks upwards, upper: downwards), so every block waited on holds a
@@ -1246,7 +1241,7 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
       }
       {
         LaunchScope ls(st, "chol_diag_kernel", bd, fd);
-        chol_diag_kernel<T><<<batch, 256, 0, st>>>(pool, d_desc, k, status, batch, dinv, dinv_off);
+        chol_diag_kernel<T><<<batch, 64, 0, st>>>(pool, d_desc, k, status, batch, dinv, dinv_off);
       }
       if (tm > 1) {
         LaunchScope ls(st, "chol_panel_kernel", bp, fp);
