@@ -1524,10 +1524,15 @@ void Solver::factor_local_fp32(int *status) {
     // so that a failure here is reported as NOT_SPD
     ++fp32_fallbacks;
     HIPCHK(hipMemsetAsync(status + ns + q, 0, sizeof(int), st));
-    HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), dRR + q, &h_descRR[q], 1, status + ns + q,
-                                   d_dinv_rr.as<double>(), dio + q));
     const int64_t n = L.nr[q], nb = (n + NB - 1) / NB;
     const int64_t o = h_descRR[q].a_off;
+    // the FP64 factorization runs in place; K_rr itself is kept aside and put
+    // back afterwards, since the Galerkin product below needs it unfactored
+    const size_t kbytes = sizeof(double) * (size_t)(n * n);
+    void *keep = alloc.get(kbytes);
+    HIPCHK(hipMemcpyAsync(keep, d_Lrr.as<double>() + o, kbytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(DenseOps<double>::potrf(st, d_Lrr.as<double>(), dRR + q, &h_descRR[q], 1, status + ns + q,
+                                   d_dinv_rr.as<double>(), dio + q));
     convert_kernel<double, float><<<nblocks(n * n), TPB, 0, st>>>(d_Lrr.as<double>() + o, L32 + o,
                                                                    n * n, 1.0);
     convert_kernel<double, float><<<nblocks(nb * NB * NB), TPB, 0, st>>>(
@@ -1535,6 +1540,9 @@ void Solver::factor_local_fp32(int *status) {
         nb * NB * NB, 1.0);
     fill_kernel<<<nblocks(n), TPB, 0, st>>>(sc + L.offR[q], 1.0, n);
     HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(d_Lrr.as<double>() + o, keep, kbytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    alloc.put(keep, kbytes);
   }
   if (L.max_np > 0) {
     double *PhiF = d_PhiF.as<double>(), *Krp = d_Phi.as<double>();

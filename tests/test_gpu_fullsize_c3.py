@@ -80,3 +80,37 @@ def test_c3_solution(prec):
           f"refinements {pi.refinements} ({pi.refine_iters} iterations)")
     if prec == 64:
         assert np.array_equal(st[64]["u"], st[64]["u2"])
+
+
+def test_c3_fp32_fallback_keeps_k_rr():
+    """tau = 2 with FP32 local factors: at this size one substructure's FP32
+    factorization meets a non-positive pivot and is factored again in FP64.
+    The coarse matrix is the Galerkin product of the basis with the unfactored
+    K_rr, so the fallback must leave K_rr in place (built from the factor it
+    was indefinite: no coarse factorization).  The FP32 solve then converges
+    and matches the FP64 solve of the same constraints element-wise to 1e-8.
+    (Its preconditioner is inexact, so the bound lambda_min >= 1 of the exact
+    one does not apply: measured 0.047.)"""
+    st = _run()
+    from paper_0910_5863_amd import BDDC
+    p = st["p"]
+    f = torch.from_numpy(p.f).to("cuda:0")
+    out = {}
+    for prec in (64, 32):
+        b = BDDC(factor_precision=prec, autotune=True)
+        b.setup(p, "ce", adaptive_edges=True)
+        b.adapt(2.0)
+        b.factor()
+        u, pinfo = b.pcg_solve(f)
+        out[prec] = (u.cpu().numpy()[:, 0], pinfo[0], b.info().fp32_fallbacks)
+        b.close()
+        del b, u
+        torch.cuda.empty_cache()
+    (u64, i64, _), (u32, i32, nfb) = out[64], out[32]
+    print(f"fp32 at tau 2: {nfb} fallback(s), iterations {i32.iters} (fp64 {i64.iters}), "
+          f"lambda_min {i32.lmin:.6f}")
+    assert nfb >= 1
+    assert i32.converged and i64.converged
+    err = float(np.abs(u32 - u64).max() / np.abs(u64).max())
+    print(f"fp32 against fp64 at tau 2: max-rel difference {err:.2e}")
+    assert err < 1e-8, err
