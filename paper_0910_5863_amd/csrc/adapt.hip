@@ -58,55 +58,111 @@ inline unsigned nblocks(int64_t n, int tpb = TPB) {
   return (unsigned)std::max<int64_t>(1, (n + tpb - 1) / tpb);
 }
 
+// block offsets of a flat launch (seg_entry): entry e gets
+// ceil(count[e] / per_block) blocks; the last value is the grid size
+inline std::vector<int64_t> seg_offsets(const std::vector<int64_t> &count, int64_t per_block) {
+  std::vector<int64_t> off(count.size() + 1, 0);
+  for (size_t e = 0; e < count.size(); ++e)
+    off[e + 1] = off[e] + (std::max<int64_t>(count[e], 0) + per_block - 1) / per_block;
+  if (off.back() > INT32_MAX) throw ArgError("flat launch over more than 2^31 blocks");
+  return off;
+}
+
+// Flat launches over entries of uneven sizes.  Entry e owns the blocks
+// [boff[e], boff[e+1]) of the launch, enough for its own elements at
+// SEG_CHUNK per block (the host's seg_offsets), so no block is launched for
+// the padding of the smaller entries; a block finds its entry by binary
+// search over boff (uniform over the block) and covers SEG_ITEMS elements
+// per thread, coalesced.
+constexpr int SEG_ITEMS = 4;
+constexpr int64_t SEG_CHUNK = (int64_t)TPB * SEG_ITEMS;
+
+__device__ __forceinline__ int seg_entry(const int64_t *boff, int n, int64_t b) {
+  int lo = 0, hi = n;  // boff[lo] <= b < boff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (boff[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 // dst[e] (rows x cols, ld = rows) = src_sub[ridx, cidx] of the source matrix
 __global__ void gather_rc_kernel(const double *src, const int64_t *src_off, const int *lds,
                                  double *dst, const int64_t *dst_off, const int *ridx,
                                  const int64_t *ridx_off, const int *nrow, const int *cidx,
-                                 const int64_t *cidx_off, const int *ncol) {
-  const int e = blockIdx.y;
+                                 const int64_t *cidx_off, const int *ncol, const int64_t *boff,
+                                 int cnt) {
+  const int64_t b = blockIdx.x;
+  const int e = seg_entry(boff, cnt, b);
   const int64_t nr = nrow[e], nc = ncol[e];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nr * nc) return;
-  const int a = (int)(i % nr), b = (int)(i / nr);
-  const int ra = ridx[ridx_off[e] + a], cb = cidx[cidx_off[e] + b];
-  dst[dst_off[e] + i] = src[src_off[e] + ra + (int64_t)cb * lds[e]];
+  const int64_t i0 = (b - boff[e]) * SEG_CHUNK + threadIdx.x;
+  const double *s = src + src_off[e];
+  const int *ri = ridx + ridx_off[e], *ci = cidx + cidx_off[e];
+  const int64_t ld = lds[e];
+  double *d = dst + dst_off[e];
+#pragma unroll
+  for (int it = 0; it < SEG_ITEMS; ++it) {
+    const int64_t i = i0 + (int64_t)it * TPB;
+    if (i < nr * nc) {
+      const int a = (int)(i % nr), c = (int)(i / nr);
+      d[i] = s[ri[a] + (int64_t)ci[c] * ld];
+    }
+  }
 }
 
-// Ssum = Sh_i + Sh_j + rho Q Q^T ; Xb = Sh_j  (per pair, n x n, ld n)
+// Ssum = Sh_i + Sh_j + rho Q Q^T ; Xb = Sh_j  (per pair, n x n, ld n; flat
+// launch, seg_entry)
 __global__ void pair_sum_kernel(const double *Sh, const int64_t *off_i, const int64_t *off_j,
                                 const int *ns, double *Ssum, double *Xb, double *BJ,
                                 const int64_t *off_p, const double *Q, const int64_t *q_off,
-                                const int *nq, const double *rho) {
-  const int e = blockIdx.y;
+                                const int *nq, const double *rho, const int64_t *boff, int cnt) {
+  const int64_t blk = blockIdx.x;
+  const int e = seg_entry(boff, cnt, blk);
   const int64_t n = ns[e];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * n) return;
-  const int r = (int)(i % n), c = (int)(i / n);
-  const double si = Sh[off_i[e] + i];
-  double v = si + Sh[off_j[e] + i];
-  for (int k = 0; k < nq[e]; ++k) v += rho[e] * Q[q_off[e] + r + k * n] * Q[q_off[e] + c + k * n];
-  Ssum[off_p[e] + i] = v;
-  Xb[off_p[e] + i] = Sh[off_j[e] + i];
-  BJ[off_p[e] + i] = 0.0;
+  const int64_t i0 = (blk - boff[e]) * SEG_CHUNK + threadIdx.x;
+  const double *Si = Sh + off_i[e], *Sj = Sh + off_j[e], *Qe = Q + q_off[e];
+  const int kq = nq[e];
+  const double rh = rho[e];
+#pragma unroll
+  for (int it = 0; it < SEG_ITEMS; ++it) {
+    const int64_t i = i0 + (int64_t)it * TPB;
+    if (i >= n * n) break;
+    const int r = (int)(i % n), c = (int)(i / n);
+    double v = Si[i] + Sj[i];
+    for (int k = 0; k < kq; ++k) v += rh * Qe[r + k * n] * Qe[c + k * n];
+    Ssum[off_p[e] + i] = v;
+    Xb[off_p[e] + i] = Sj[i];
+    BJ[off_p[e] + i] = 0.0;
+  }
 }
 
 // compact c x c blocks: M = Dj Si Dj + Di Sj Di, BJ = (Sh_i - Sh_i X)[c,c]
+// (flat launch, seg_entry)
 __global__ void pair_restrict_kernel(const double *Sss, const int64_t *off_si,
                                      const int64_t *off_sj, const double *BJfull,
                                      const int64_t *off_p, const int *ns, const int *cidx,
                                      const int64_t *c_off, const int *nc, const double *wi,
-                                     double *M, double *BJ, const int64_t *off_c) {
-  const int e = blockIdx.y;
+                                     double *M, double *BJ, const int64_t *off_c,
+                                     const int64_t *boff, int cnt) {
+  const int64_t blk = blockIdx.x;
+  const int e = seg_entry(boff, cnt, blk);
   const int64_t m = nc[e], n = ns[e];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m * m) return;
-  const int a = (int)(i % m), b = (int)(i / m);
-  const int ra = cidx[c_off[e] + a], rb = cidx[c_off[e] + b];
-  const double dia = wi[c_off[e] + a], dib = wi[c_off[e] + b];
-  const double dja = 1.0 - dia, djb = 1.0 - dib;
-  const int64_t src = ra + (int64_t)rb * n;
-  M[off_c[e] + i] = dja * Sss[off_si[e] + src] * djb + dia * Sss[off_sj[e] + src] * dib;
-  BJ[off_c[e] + i] = BJfull[off_p[e] + src];
+  const int64_t i0 = (blk - boff[e]) * SEG_CHUNK + threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < SEG_ITEMS; ++it) {
+    const int64_t i = i0 + (int64_t)it * TPB;
+    if (i >= m * m) break;
+    const int a = (int)(i % m), b = (int)(i / m);
+    const int ra = cidx[c_off[e] + a], rb = cidx[c_off[e] + b];
+    const double dia = wi[c_off[e] + a], dib = wi[c_off[e] + b];
+    const double dja = 1.0 - dia, djb = 1.0 - dib;
+    const int64_t src = ra + (int64_t)rb * n;
+    M[off_c[e] + i] = dja * Sss[off_si[e] + src] * djb + dia * Sss[off_sj[e] + src] * dib;
+    BJ[off_c[e] + i] = BJfull[off_p[e] + src];
+  }
 }
 
 // segment e: dst[dst_off[e] + i] = src[src_off[e] + i] for i < len[e] (many
@@ -126,26 +182,43 @@ __global__ void scatter_values_kernel(const int64_t *idx, const double *val, int
   if (i < n) dst[idx[i]] = val[i];
 }
 
+// dst = src^T per entry (m x m, ld m; flat launch, seg_entry)
 __global__ void transpose_kernel(const double *src, double *dst, const int64_t *off,
-                                 const int *n) {
-  const int e = blockIdx.y;
+                                 const int *n, const int64_t *boff, int cnt) {
+  const int64_t blk = blockIdx.x;
+  const int e = seg_entry(boff, cnt, blk);
   const int64_t m = n[e];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m * m) return;
-  const int r = (int)(i % m), c = (int)(i / m);
-  dst[off[e] + c + (int64_t)r * m] = src[off[e] + i];
+  const int64_t i0 = (blk - boff[e]) * SEG_CHUNK + threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < SEG_ITEMS; ++it) {
+    const int64_t i = i0 + (int64_t)it * TPB;
+    if (i >= m * m) break;
+    const int r = (int)(i % m), c = (int)(i / m);
+    dst[off[e] + c + (int64_t)r * m] = src[off[e] + i];
+  }
+}
+
+// tile pair t of a triangle of tiles, t = bj (bj + 1) / 2 + bi, 0 <= bi <= bj
+__device__ __forceinline__ void upper_pair(int64_t t, int &bi, int &bj) {
+  int j = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(j + 1) * (j + 2) / 2 <= t) ++j;
+  while ((int64_t)j * (j + 1) / 2 > t) --j;
+  bj = j;
+  bi = (int)(t - (int64_t)j * (j + 1) / 2);
 }
 
 // A <- (A + A^T) / 2 in place (ld n), by 32 x 32 tile pairs through LDS so
 // that reads and writes run down columns: work-group (bi, bj), bi <= bj,
 // loads tiles (bi, bj) and (bj, bi), averages each entry with its mirror and
-// writes both (a diagonal tile with itself)
+// writes both (a diagonal tile with itself).  Flat launch: one tile pair per
+// block, entry e owning nt (nt + 1) / 2 of them, nt = ceil(n / 32).
 __global__ __launch_bounds__(256) void symmetrize_kernel(double *A, const int64_t *off, const int *n,
-                                                         int nt) {
+                                                         const int64_t *boff, int cnt) {
   __shared__ double up[32][33], lo[32][33];
-  const int bi = blockIdx.x % nt, bj = blockIdx.x / nt;
-  if (bi > bj) return;
-  const int e = blockIdx.y;
+  const int64_t blk = blockIdx.x;
+  const int e = seg_entry(boff, cnt, blk);
+  int bi, bj;
+  upper_pair(blk - boff[e], bi, bj);
   const int m = n[e];
   if (32 * bj >= m) return;
   double *a = A + off[e];
@@ -159,8 +232,7 @@ __global__ __launch_bounds__(256) void symmetrize_kernel(double *A, const int64_
     if (rl < m && cw < m) lo[cl][tx] = a[rl + (int64_t)cw * m];
   }
   __syncthreads();
-  // entry (r, c) of tile (bi, bj) mirrors entry (c, r) of tile (bj, bi):
-  // up[cl][rl'] with lo[rl'][cl] swapped to lo[col][row] = lo[tx'..]
+  // entry (r, c) of tile (bi, bj) mirrors entry (c, r) of tile (bj, bi)
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int cl = ty + 8 * q;
@@ -1197,16 +1269,21 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
     int *d_in = pool.up(stream, in_all.empty() ? std::vector<int>{0} : in_all);
     int *d_iu = pool.up(stream, iu_all.empty() ? std::vector<int>{0} : iu_all);
     int64_t *d_ion = pool.up(stream, io_n), *d_iou = pool.up(stream, io_u);
+    // a flat launch over the entries' own rows x cols elements
     auto gather = [&](double *dst, const int64_t *doff, const int *ri, const int64_t *rio,
-                      const int *nr, const int *ci, const int64_t *cio, const int *ncl, int64_t maxe) {
-      if (maxe <= 0) return;
-      gather_rc_kernel<<<dim3(nblocks(maxe), cnt), TPB, 0, stream>>>(src, d_so, d_lds, dst, doff, ri,
-                                                                     rio, nr, ci, cio, ncl);
+                      const int *nr, const int *ci, const int64_t *cio, const int *ncl,
+                      const std::vector<int> &hr, const std::vector<int> &hc) {
+      std::vector<int64_t> c(cnt);
+      for (int e = 0; e < cnt; ++e) c[e] = (int64_t)hr[e] * hc[e];
+      const std::vector<int64_t> bo = seg_offsets(c, SEG_CHUNK);
+      if (bo.back() == 0) return;
+      gather_rc_kernel<<<(unsigned)bo.back(), TPB, 0, stream>>>(src, d_so, d_lds, dst, doff, ri, rio, nr,
+                                                                ci, cio, ncl, pool.up(stream, bo), cnt);
       HIPCHK(hipGetLastError());
     };
-    gather(Snn, d_onn, d_in, d_ion, d_nn, d_in, d_ion, d_nn, (int64_t)mnn * mnn);
-    gather(Snu, d_onu, d_in, d_ion, d_nn, d_iu, d_iou, d_nu, (int64_t)mnn * mnu);
-    gather(out, d_oo, d_iu, d_iou, d_nu, d_iu, d_iou, d_nu, (int64_t)mnu * mnu);
+    gather(Snn, d_onn, d_in, d_ion, d_nn, d_in, d_ion, d_nn, nn, nn);
+    gather(Snu, d_onu, d_in, d_ion, d_nn, d_iu, d_iou, d_nu, nn, nu);
+    gather(out, d_oo, d_iu, d_iou, d_nu, d_iu, d_iou, d_nu, nu, nu);
     std::vector<MatDesc> md(cnt);
     std::vector<GemmDesc> gd(cnt);
     for (int e = 0; e < cnt; ++e) {
@@ -1227,7 +1304,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
                                   true, gd.data()));
     std::vector<MatDesc> mo(cnt);
     for (int e = 0; e < cnt; ++e) mo[e] = MatDesc{out_off[e], 0, nu[e], 0, std::max(1, nu[e]), 1};
-    HIPCHK(symmetrize_lower<double>(stream, out, pool.up(stream, mo), cnt, mnu));
+    HIPCHK(symmetrize_lower<double>(stream, out, pool.up(stream, mo), cnt, mnu, mo.data()));
   };
   // Schur complement of S_a onto the shared dofs s of each pair side, by
   // recursive bisection of the sides of each substructure (in pair order): a
@@ -1367,9 +1444,14 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
             *d_io = pool.up(stream, ss_io);
     int *d_lds = pool.up(stream, ss_lds), *d_ns = pool.up(stream, nsv);
     int *d_ix = pool.up(stream, ss_all);
-    gather_rc_kernel<<<dim3(nblocks((int64_t)max_ns * max_ns), nside), TPB, 0, stream>>>(
-        Sd, d_so, d_lds, Sh, d_oo, d_ix, d_io, d_ns, d_ix, d_io, d_ns);
-    HIPCHK(hipGetLastError());
+    std::vector<int64_t> c(nside);
+    for (int e = 0; e < nside; ++e) c[e] = (int64_t)nsv[e] * nsv[e];
+    const std::vector<int64_t> bo = seg_offsets(c, SEG_CHUNK);
+    if (bo.back() > 0) {
+      gather_rc_kernel<<<(unsigned)bo.back(), TPB, 0, stream>>>(Sd, d_so, d_lds, Sh, d_oo, d_ix, d_io, d_ns,
+                                                                d_ix, d_io, d_ns, pool.up(stream, bo), nside);
+      HIPCHK(hipGetLastError());
+    }
   }
 
   log("pair Schur complements");
@@ -1423,9 +1505,24 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   int *d_nsp = pool.up(stream, nsp), *d_nq = pool.up(stream, nqv);
   int max_sp = 0;
   for (int p = 0; p < np; ++p) max_sp = std::max(max_sp, nsp[p]);
-  pair_sum_kernel<<<dim3(nblocks((int64_t)max_sp * max_sp), np), TPB, 0, stream>>>(
-      Sh, d_off_i, d_off_j, d_nsp, Ssum, Xb, BJf, d_off_p, d_Q, d_q_off, d_nq, d_rho);
-  HIPCHK(hipGetLastError());
+  // block offsets of the flat launches over the pairs: n x n elements each
+  // (count) or n x n elements in 32 x 32 tile pairs (tri)
+  auto flat = [&](const std::vector<int> &n, bool tri) {
+    std::vector<int64_t> c(np);
+    for (int p = 0; p < np; ++p) {
+      const int64_t t = (n[p] + 31) / 32;
+      c[p] = tri ? t * (t + 1) / 2 : (int64_t)n[p] * n[p];
+    }
+    return seg_offsets(c, tri ? 1 : SEG_CHUNK);
+  };
+  {
+    const std::vector<int64_t> bo = flat(nsp, false);
+    if (bo.back() > 0)
+      pair_sum_kernel<<<(unsigned)bo.back(), TPB, 0, stream>>>(Sh, d_off_i, d_off_j, d_nsp, Ssum, Xb, BJf,
+                                                               d_off_p, d_Q, d_q_off, d_nq, d_rho,
+                                                               pool.up(stream, bo), np);
+    HIPCHK(hipGetLastError());
+  }
   std::vector<MatDesc> mds(np);
   std::vector<GemmDesc> gbj(np);
   for (int p = 0; p < np; ++p) {
@@ -1448,17 +1545,25 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   // the coefficients of i and j differ by orders of magnitude)
   HIPCHK(DenseOps<double>::gemm(stream, Sh, Xb, BJf, d_gbj, np, max_sp, max_sp, false, false, 1.0,
                                 0.0, false, gbj.data()));
-  symmetrize_kernel<<<dim3(((max_sp + 31) / 32) * ((max_sp + 31) / 32), np), 256, 0, stream>>>(
-      BJf, d_off_p, d_nsp, (max_sp + 31) / 32);
-  HIPCHK(hipGetLastError());
+  {
+    const std::vector<int64_t> bo = flat(nsp, true);
+    if (bo.back() > 0)
+      symmetrize_kernel<<<(unsigned)bo.back(), 256, 0, stream>>>(BJf, d_off_p, d_nsp, pool.up(stream, bo), np);
+    HIPCHK(hipGetLastError());
+  }
   double *Mc = pool.zeros(stream, tc), *BJc = pool.zeros(stream, tc);
   int *d_call = pool.up(stream, call), *d_nc = pool.up(stream, ncv);
   int64_t *d_c_off = pool.up(stream, c_off), *d_off_c = pool.up(stream, off_c);
   int64_t *d_off_ss_i = pool.up(stream, off_ss_i), *d_off_ss_j = pool.up(stream, off_ss_j);
   double *d_w = pool.up(stream, wall);
-  pair_restrict_kernel<<<dim3(nblocks((int64_t)max_c * max_c), np), TPB, 0, stream>>>(
-      Sh, d_off_ss_i, d_off_ss_j, BJf, d_off_p, d_nsp, d_call, d_c_off, d_nc, d_w, Mc, BJc, d_off_c);
-  HIPCHK(hipGetLastError());
+  {
+    const std::vector<int64_t> bo = flat(ncv, false);
+    if (bo.back() > 0)
+      pair_restrict_kernel<<<(unsigned)bo.back(), TPB, 0, stream>>>(Sh, d_off_ss_i, d_off_ss_j, BJf, d_off_p,
+                                                                    d_nsp, d_call, d_c_off, d_nc, d_w, Mc,
+                                                                    BJc, d_off_c, pool.up(stream, bo), np);
+    HIPCHK(hipGetLastError());
+  }
   // My = Z^T M Z, By = Z^T BJ Z
   double *Zd = pool.zeros(stream, tz);
   {
@@ -1497,14 +1602,21 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   check(2 * nside + np, np, "jump-space denominator");
   // My <- L^-1 My ; Cp <- My^T ; Cp <- L^-1 Cp   (My's pool is the B operand)
   HIPCHK(DenseOps<double>::trsm(stream, By, My, d_mdd, mdd.data(), np, false, dv_y, do_y));
-  transpose_kernel<<<dim3(nblocks((int64_t)max_d * max_d), np), TPB, 0, stream>>>(My, Cp, d_off_dd, d_dv);
-  HIPCHK(hipGetLastError());
+  {
+    const std::vector<int64_t> bo = flat(dv, false);
+    if (bo.back() > 0)
+      transpose_kernel<<<(unsigned)bo.back(), TPB, 0, stream>>>(My, Cp, d_off_dd, d_dv, pool.up(stream, bo), np);
+    HIPCHK(hipGetLastError());
+  }
   HIPCHK(DenseOps<double>::trsm(stream, By, Cp, d_mdd, mdd.data(), np, false, dv_y, do_y));
   // the two solves leave C' symmetric only to ~kappa(By) eps; LOBPCG's
   // residuals cannot drop below that asymmetry, so C' is symmetrized
-  symmetrize_kernel<<<dim3(((max_d + 31) / 32) * ((max_d + 31) / 32), np), 256, 0, stream>>>(
-      Cp, d_off_dd, d_dv, (max_d + 31) / 32);
-  HIPCHK(hipGetLastError());
+  {
+    const std::vector<int64_t> bo = flat(dv, true);
+    if (bo.back() > 0)
+      symmetrize_kernel<<<(unsigned)bo.back(), 256, 0, stream>>>(Cp, d_off_dd, d_dv, pool.up(stream, bo), np);
+    HIPCHK(hipGetLastError());
+  }
 
   log("reduced pair matrices");
   // ---- stage 3: batched LOBPCG on C'.  When a block holds only eigenvalues

@@ -112,8 +112,11 @@ struct DenseOps {
 };
 
 // Copy the lower triangle onto the upper one (entries A at a_off, n x n).
+// h_desc (optional): the host copy of the descriptors; with it only each
+// entry's own tiles are launched.
 template <class T>
-hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn);
+hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn,
+                            const MatDesc *h_desc = nullptr);
 
 // Triangular solves with per-block completion flags (one launch per solve,
 // all entries together): x <- L^{-1} x for a lower triangular L (upper =
@@ -161,10 +164,11 @@ template <class T>
 hipError_t diag_inverse(hipStream_t st, const T *pool, const MatDesc *d_desc, int batch, int maxn,
                         T *inv, const int64_t *inv_off);
 
-// B <- A^T for every entry (n x n matrices: A at a_off, lda; B at b_off, ldb)
+// B <- A^T for every entry (n x n matrices: A at a_off, lda; B at b_off, ldb);
+// h_desc (optional) as for symmetrize_lower
 template <class T>
 hipError_t transpose_batched(hipStream_t st, const T *apool, T *bpool, const MatDesc *d_desc,
-                             int batch, int maxn);
+                             int batch, int maxn, const MatDesc *h_desc = nullptr);
 
 // Host: ticket orders for entries of sizes n (forward: block index upwards,
 // backward: downwards, level by level across entries) and flag offsets.

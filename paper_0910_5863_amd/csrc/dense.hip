@@ -611,12 +611,24 @@ __global__ __launch_bounds__(256) void trsm_gemm_kernel(const T *apool, T *bpool
 // both the reads and the writes run down columns: work-group (bi, bj), bi <=
 // bj, writes tile (bi, bj) from the transpose of tile (bj, bi) (on the
 // diagonal only the entries above it).
+// With a tile map (map.n > 0) only each entry's own tile pairs are launched:
+// tile t of entry e is the pair (bi, bj) = (tj, ti) of lower_tile(t).
 template <class T>
-__global__ __launch_bounds__(256) void symmetrize_kernel(T *pool, const MatDesc *desc, int nt) {
+__global__ __launch_bounds__(256) void symmetrize_kernel(T *pool, const MatDesc *desc, int nt,
+                                                         const TileMap map) {
   __shared__ T tl[32][33];
-  const int bi = blockIdx.x % nt, bj = blockIdx.x / nt;
-  if (bi > bj) return;
-  const MatDesc d = desc[blockIdx.y];
+  int e, bi, bj;
+  if (map.n > 0) {
+    int t;
+    if (!map_tile(map, gridDim.x, e, t)) return;
+    lower_tile(t, bj, bi);
+  } else {
+    bi = blockIdx.x % nt;
+    bj = blockIdx.x / nt;
+    e = blockIdx.y;
+    if (bi > bj) return;
+  }
+  const MatDesc d = desc[e];
   const int n = d.n;
   if (32 * bj >= n) return;
   T *A = pool + d.a_off;
@@ -899,10 +911,23 @@ __global__ __launch_bounds__(64) void diag_inv_kernel(const T *pool, const MatDe
 }
 
 // B <- A^T for every entry (n x n, lda / ldb); used to keep L^T beside L
+// With a tile map (map.n > 0) only each entry's own nt x nt tiles are
+// launched (tile t: column tile t % nt, row tile t / nt, nt = ceil(n / 32)).
 template <class T>
-__global__ void transpose_kernel(const T *apool, T *bpool, const MatDesc *desc) {
-  const MatDesc d = desc[blockIdx.z];
-  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+__global__ void transpose_kernel(const T *apool, T *bpool, const MatDesc *desc, const TileMap map) {
+  int e, c0, r0;
+  if (map.n > 0) {
+    int t;
+    if (!map_tile(map, gridDim.x, e, t)) return;
+    const int nt = (desc[e].n + 31) / 32;
+    c0 = (t % nt) * 32;
+    r0 = (t / nt) * 32;
+  } else {
+    e = blockIdx.z;
+    c0 = blockIdx.x * 32;
+    r0 = blockIdx.y * 32;
+  }
+  const MatDesc d = desc[e];
   if (c0 >= d.n || r0 >= d.n) return;
   __shared__ T tile[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
@@ -1447,11 +1472,20 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
 }
 
 template <class T>
-hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn) {
+hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn,
+                            const MatDesc *h_desc) {
   if (batch <= 0 || maxn <= 0) return hipSuccess;
   const int nt = (maxn + 31) / 32;
-  dim3 g((unsigned)(nt * nt), batch);
-  symmetrize_kernel<T><<<g, 256, 0, st>>>(pool, d_desc, nt);
+  const TileMap map = h_desc ? tile_map(batch, [&](int e) {
+    const int t = (h_desc[e].n + 31) / 32;
+    return t * (t + 1) / 2;
+  }) : TileMap{0, {}};
+  if (map.n > 0) {
+    if (map.off[map.n] > 0)
+      symmetrize_kernel<T><<<grid_round(map.off[map.n]), 256, 0, st>>>(pool, d_desc, nt, map);
+  } else {
+    symmetrize_kernel<T><<<dim3((unsigned)(nt * nt), batch), 256, 0, st>>>(pool, d_desc, nt, map);
+  }
   return hipGetLastError();
 }
 
@@ -1512,10 +1546,19 @@ hipError_t trsv_blocked(hipStream_t st, const T *apool, T *xpool, const MatDesc 
 
 template <class T>
 hipError_t transpose_batched(hipStream_t st, const T *apool, T *bpool, const MatDesc *d_desc,
-                             int batch, int maxn) {
+                             int batch, int maxn, const MatDesc *h_desc) {
   if (batch <= 0 || maxn <= 0) return hipSuccess;
-  const unsigned t = (unsigned)((maxn + 31) / 32);
-  transpose_kernel<T><<<dim3(t, t, batch), 256, 0, st>>>(apool, bpool, d_desc);
+  const TileMap map = h_desc ? tile_map(batch, [&](int e) {
+    const int t = (h_desc[e].n + 31) / 32;
+    return t * t;
+  }) : TileMap{0, {}};
+  if (map.n > 0) {
+    if (map.off[map.n] > 0)
+      transpose_kernel<T><<<grid_round(map.off[map.n]), 256, 0, st>>>(apool, bpool, d_desc, map);
+  } else {
+    const unsigned t = (unsigned)((maxn + 31) / 32);
+    transpose_kernel<T><<<dim3(t, t, batch), 256, 0, st>>>(apool, bpool, d_desc, map);
+  }
   return hipGetLastError();
 }
 
@@ -1544,8 +1587,10 @@ void make_trsv_orders(const std::vector<int> &n, std::vector<int> &fwd, std::vec
 
 template struct DenseOps<double>;
 template struct DenseOps<float>;
-template hipError_t symmetrize_lower<double>(hipStream_t, double *, const MatDesc *, int, int);
-template hipError_t symmetrize_lower<float>(hipStream_t, float *, const MatDesc *, int, int);
+template hipError_t symmetrize_lower<double>(hipStream_t, double *, const MatDesc *, int, int,
+                                            const MatDesc *);
+template hipError_t symmetrize_lower<float>(hipStream_t, float *, const MatDesc *, int, int,
+                                           const MatDesc *);
 template hipError_t trsv_blocked<double>(hipStream_t, const double *, double *, const MatDesc *,
                                          const TrsvPlan &, bool, const double *, const int64_t *,
                                          int *, int *, int, int64_t);
@@ -1557,8 +1602,8 @@ template hipError_t diag_inverse<double>(hipStream_t, const double *, const MatD
 template hipError_t diag_inverse<float>(hipStream_t, const float *, const MatDesc *, int, int,
                                         float *, const int64_t *);
 template hipError_t transpose_batched<double>(hipStream_t, const double *, double *, const MatDesc *,
-                                              int, int);
+                                              int, int, const MatDesc *);
 template hipError_t transpose_batched<float>(hipStream_t, const float *, float *, const MatDesc *,
-                                             int, int);
+                                             int, int, const MatDesc *);
 
 }  // namespace bddc

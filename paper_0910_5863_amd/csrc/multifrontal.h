@@ -102,6 +102,10 @@ class MfDevice {
   std::vector<DBuf> d_dinv_off_, d_dinv_toff_;     // per depth: for the potrf / trsm entries
   DBuf d_dinv_front_;                              // per front: offset of its inverses
   std::vector<int64_t> max_f_;                     // per depth: max p*f + b*b
+  // per depth: block offsets of the extend-add launch over the depth's
+  // fronts (each front its own blocks), host copy and device copy
+  std::vector<std::vector<int64_t>> h_pull_off_;
+  std::vector<DBuf> d_pull_off_;
   std::vector<int> max_pb_;                        // per depth: max p + b
   std::vector<int> max_p_, max_b_;                 // per depth: max p, max b
   DBuf d_zp_;                                      // solves: z of every front's pivots

@@ -47,17 +47,36 @@ __global__ void mf_assemble_kernel(const int64_t *dst, const double *val, int64_
   if (d >= 0) U[d] = val[k];
 }
 
-// Fronts ids[blockIdx.y]: U += the children's contributions (U holds the
+// Fronts ids[f] of a depth: U += the children's contributions (U holds the
 // assembled rows already); the lower triangle of C = the children's
-// contributions (zero for a leaf), so C needs no clearing.
+// contributions (zero for a leaf), so C needs no clearing.  A flat launch:
+// front f owns the blocks [boff[f], boff[f+1]) (offsets relative to the
+// depth's list, block b of the launch is b + base), PULL_CHUNK elements of its
+// U and C blocks per launch block.
+constexpr int PULL_ITEMS = 4;
+constexpr int PULL_CHUNK = TPB * PULL_ITEMS;
 __global__ void mf_pull_kernel(const MfFront *F, const int *ids, const int *child_ids,
-                               const int *pmap, double *U, double *C) {
-  const MfFront f = F[ids[blockIdx.y]];
+                               const int *pmap, double *U, double *C, const int64_t *boff, int nf,
+                               int64_t base) {
+  const int64_t blk = blockIdx.x + base;
+  int lo = 0, hi = nf;  // boff[lo] <= blk < boff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (boff[mid] <= blk)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const MfFront f = F[ids[lo]];
   const int p = f.p, b = f.b, fs = p + b;
   // a front's blocks hold well under 2^31 entries: 32-bit index arithmetic
   // (a 64-bit division costs several times a 32-bit one)
   const int nu = f.n_child > 0 ? p * fs : 0, ntot = nu + b * b;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ntot; e += gridDim.x * blockDim.x) {
+  const int e0 = (int)(blk - boff[lo]) * PULL_CHUNK + threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < PULL_ITEMS; ++it) {
+    const int e = e0 + it * TPB;
+    if (e >= ntot) break;
     int pr, pc;
     const bool in_u = e < nu;
     if (in_u) {
@@ -350,7 +369,8 @@ void MfDevice::release(DevAlloc &A) {
     if (b->p) A.put(b->p, b->bytes);
     *b = DBuf();
   }
-  for (auto *v : {&d_potrf_, &d_trsm_, &d_gemm_, &d_dinv_off_, &d_dinv_toff_}) {
+  h_pull_off_.clear();
+  for (auto *v : {&d_potrf_, &d_trsm_, &d_gemm_, &d_dinv_off_, &d_dinv_toff_, &d_pull_off_}) {
     for (DBuf &b : *v)
       if (b.p) A.put(b.p, b.bytes);
     v->clear();
@@ -459,6 +479,17 @@ void MfDevice::setup(const Problem &P, const std::vector<int64_t> &offI, DevAllo
       if (f.b > 0) toff.push_back(doff[d][e]);
       ++e;
     }
+    {
+      std::vector<int64_t> bo(M.levels[d].size() + 1, 0);
+      for (size_t k = 0; k < M.levels[d].size(); ++k) {
+        const MfFront &f = M.fronts[M.levels[d][k]];
+        const int64_t ntot = (f.n_child > 0 ? (int64_t)f.p * (f.p + f.b) : 0) + (int64_t)f.b * f.b;
+        bo[k + 1] = bo[k] + (ntot + PULL_CHUNK - 1) / PULL_CHUNK;
+      }
+      if (bo.back() > INT32_MAX) throw ArgError("extend-add: a depth needs 2^31 blocks or more");
+      d_pull_off_.push_back(upload(A, st, bo));
+      h_pull_off_.push_back(std::move(bo));
+    }
     d_potrf_.push_back(upload(A, st, h_potrf_[d]));
     d_trsm_.push_back(upload(A, st, h_trsm_[d]));
     d_gemm_.push_back(upload(A, st, h_gemm_[d]));
@@ -523,9 +554,11 @@ void MfDevice::factor(hipStream_t st, const double *val, int64_t nnz, double *S,
           for (int ci = 0; ci < f.n_child; ++ci) by += 4.0 * M.fronts[M.child_ids[f.child_ptr + ci]].b * 0.5 * M.fronts[M.child_ids[f.child_ptr + ci]].b;
         }
       LaunchScope ls(st, "mf_pull_kernel", by, 0);
-      const unsigned gx = (unsigned)std::min<int64_t>(2048, (max_f_[d] + TPB - 1) / TPB);
-      mf_pull_kernel<<<dim3(std::max(1u, gx), nf), TPB, 0, st>>>(F, lid, d_child_.as<int>(),
-                                                                 d_pmap_.as<int>(), U, C);
+      const std::vector<int64_t> &bo = h_pull_off_[d];
+      const int64_t nb = bo[l1] - bo[l0];
+      if (nb > 0)
+        mf_pull_kernel<<<(unsigned)nb, TPB, 0, st>>>(F, lid, d_child_.as<int>(), d_pmap_.as<int>(), U, C,
+                                                     d_pull_off_[d].as<int64_t>() + l0, nf, bo[l0]);
       HIPCHK(hipGetLastError());
     }
     const int np = p1 - p0;

@@ -225,6 +225,9 @@ class Solver {
   int xf_max_ng = 0;
   int n_gk = 0;
   DBuf d_ridx, d_ridx_off, d_pidx, d_pidx_off, d_rabs, d_pabs, d_pcid, d_sub_cids;
+  // block offsets of the flat gathers of K_rr, K_r,pi and K_pi,pi (host and device)
+  std::vector<int64_t> h_gb_rr, h_gb_rp, h_gb_pp;
+  DBuf d_gb_rr, d_gb_rp, d_gb_pp;
   DBuf d_c_ptr, d_c_sub, d_c_loc, d_c_copies;
   DBuf d_ifc_gamma, d_ifc_delta, d_gamma_ptr, d_gamma_copies, d_gamma_gdof, d_int_gdof, d_ifc_gdof;
   DBuf d_trsv_rr_fwd, d_trsv_rr_bwd, d_trsv_rr_off;

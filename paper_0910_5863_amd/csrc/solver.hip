@@ -122,19 +122,49 @@ __global__ void xform_copy_pivots_kernel(const double *pool, const int64_t *offG
   }
 }
 
-// gather a sub-block: dst[a + b*ldd] = src[idx_r[a] + idx_c[b]*lds] per entry
+// gather a sub-block: dst[a + b*ldd] = src[idx_r[a] + idx_c[b]*lds] per entry.
+// A flat launch: entry s owns the blocks [boff[s], boff[s+1]) (GB_CHUNK of its
+// nrows x ncols elements per block, host offsets from gather_offsets), so the
+// smaller entries launch no padding.
+constexpr int GB_ITEMS = 4;
+constexpr int64_t GB_CHUNK = (int64_t)TPB * GB_ITEMS;
 __global__ void gather_block_kernel(const double *src, const int64_t *src_off, const int *lds,
                                     double *dst, const int64_t *dst_off, const int *ldd,
                                     const int *ridx, const int64_t *ridx_off, const int *nrows,
                                     const int *cidx, const int64_t *cidx_off, const int *ncols,
-                                    double scale) {
-  const int s = blockIdx.y;
+                                    double scale, const int64_t *boff, int cnt) {
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = cnt;  // boff[lo] <= blk < boff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (boff[mid] <= blk)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int s = lo;
   const int64_t nr = nrows[s], nc = ncols[s];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nr * nc) return;
-  const int a = (int)(i % nr), b = (int)(i / nr);
-  const int ra = ridx[ridx_off[s] + a], cb = cidx[cidx_off[s] + b];
-  dst[dst_off[s] + a + (int64_t)b * ldd[s]] = scale * src[src_off[s] + ra + (int64_t)cb * lds[s]];
+  const int64_t i0 = (blk - boff[s]) * GB_CHUNK + threadIdx.x;
+  const double *S = src + src_off[s];
+  const int *ri = ridx + ridx_off[s], *ci = cidx + cidx_off[s];
+  const int64_t ls = lds[s], ld = ldd[s];
+  double *D = dst + dst_off[s];
+#pragma unroll
+  for (int it = 0; it < GB_ITEMS; ++it) {
+    const int64_t i = i0 + (int64_t)it * TPB;
+    if (i >= nr * nc) break;
+    const int a = (int)(i % nr), c = (int)(i / nr);
+    D[a + (int64_t)c * ld] = scale * S[ri[a] + (int64_t)ci[c] * ls];
+  }
+}
+
+// block offsets of gather_block_kernel for entries of rows[s] x cols[s]
+std::vector<int64_t> gather_offsets(const std::vector<int> &rows, const std::vector<int> &cols) {
+  std::vector<int64_t> off(rows.size() + 1, 0);
+  for (size_t s = 0; s < rows.size(); ++s)
+    off[s + 1] = off[s] + ((int64_t)rows[s] * cols[s] + GB_CHUNK - 1) / GB_CHUNK;
+  if (off.back() > INT32_MAX) throw ArgError("a gather of more than 2^31 blocks");
+  return off;
 }
 
 // coarse matrix: S_c[a,b] = sum over substructures holding both a and b
@@ -860,7 +890,8 @@ std::vector<DBuf *> Solver::struct_buffers() {
 }
 
 std::vector<DBuf *> Solver::cons_buffers() {
-  return {&d_nr, &d_np, &d_offR, &d_offP, &d_offRR, &d_offRP, &d_offPP, &d_Lrr, &d_Urr, &d_Phi,
+  return {&d_nr, &d_np, &d_offR, &d_offP, &d_offRR, &d_offRP, &d_offPP, &d_gb_rr, &d_gb_rp, &d_gb_pp,
+          &d_Lrr, &d_Urr, &d_Phi,
           &d_Spi, &d_Lc, &d_Uc, &d_descRRT, &d_dinv_rr, &d_dinv_rr_off, &d_dinv_c, &d_dinv_c_off,
           &d_descRR, &d_descC, &d_spi_desc, &d_gx, &d_gx_ptr, &d_trow, &d_pos, &d_wmat,
           &d_gk_glob, &d_gk_k, &d_scr, &d_xf_cols, &d_xf_rows, &d_xf_map, &d_xf_map_off,
@@ -967,6 +998,12 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_offRR = upload(alloc, st, L.offRR);
   d_offRP = upload(alloc, st, L.offRP);
   d_offPP = upload(alloc, st, L.offPP);
+  h_gb_rr = gather_offsets(L.nr, L.nr);
+  h_gb_rp = gather_offsets(L.nr, L.np);
+  h_gb_pp = gather_offsets(L.np, L.np);
+  d_gb_rr = upload(alloc, st, h_gb_rr);
+  d_gb_rp = upload(alloc, st, h_gb_rp);
+  d_gb_pp = upload(alloc, st, h_gb_pp);
   if (!keep_struct) build_structure(P, st);
   // transforms
   std::vector<GlobXf> gx;
@@ -1364,7 +1401,8 @@ void Solver::factor_schur() {
   mf.factor(st, d_val.as<double>(), nnz, d_S.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(),
             L.max_nG, ns);
   timer.end(st);
-  HIPCHK(symmetrize_lower<double>(st, d_S.as<double>(), d_descGG.as<MatDesc>(), ns, L.max_nG));
+  HIPCHK(symmetrize_lower<double>(st, d_S.as<double>(), d_descGG.as<MatDesc>(), ns, L.max_nG,
+                                  h_descGG.data()));
   check_status(false);
   schur_ready = true;
 }
@@ -1412,21 +1450,18 @@ void Solver::factor() {
   }
   // split into rr, r-pi, pi-pi
   auto gather = [&](DBuf &dst, const DBuf &dstoff, const DBuf &ldd, const DBuf &ri, const DBuf &rio,
-                    const DBuf &nrow, const DBuf &ci, const DBuf &cio, const DBuf &ncol, int64_t maxe,
-                    double scale) {
-    if (maxe <= 0) return;
-    gather_block_kernel<<<dim3(nblocks(maxe), ns), TPB, 0, st>>>(
+                    const DBuf &nrow, const DBuf &ci, const DBuf &cio, const DBuf &ncol,
+                    const std::vector<int64_t> &h_boff, const DBuf &boff, double scale) {
+    if (h_boff.back() <= 0) return;
+    gather_block_kernel<<<(unsigned)h_boff.back(), TPB, 0, st>>>(
         d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), dst.as<double>(),
         dstoff.as<int64_t>(), ldd.as<int>(), ri.as<int>(), rio.as<int64_t>(), nrow.as<int>(),
-        ci.as<int>(), cio.as<int64_t>(), ncol.as<int>(), scale);
+        ci.as<int>(), cio.as<int64_t>(), ncol.as<int>(), scale, boff.as<int64_t>(), ns);
     HIPCHK(hipGetLastError());
   };
-  gather(d_Lrr, d_offRR, d_nr, d_ridx, d_ridx_off, d_nr, d_ridx, d_ridx_off, d_nr,
-         (int64_t)L.max_nr * L.max_nr, 1.0);
-  gather(d_Phi, d_offRP, d_nr, d_ridx, d_ridx_off, d_nr, d_pidx, d_pidx_off, d_np,
-         (int64_t)L.max_nr * L.max_np, 1.0);
-  gather(d_Spi, d_offPP, d_np, d_pidx, d_pidx_off, d_np, d_pidx, d_pidx_off, d_np,
-         (int64_t)L.max_np * L.max_np, 1.0);
+  gather(d_Lrr, d_offRR, d_nr, d_ridx, d_ridx_off, d_nr, d_ridx, d_ridx_off, d_nr, h_gb_rr, d_gb_rr, 1.0);
+  gather(d_Phi, d_offRP, d_nr, d_ridx, d_ridx_off, d_nr, d_pidx, d_pidx_off, d_np, h_gb_rp, d_gb_rp, 1.0);
+  gather(d_Spi, d_offPP, d_np, d_pidx, d_pidx_off, d_np, d_pidx, d_pidx_off, d_np, h_gb_pp, d_gb_pp, 1.0);
   // constrained local factor and coarse basis (FP64, or FP32 local factors
   // with an FP64 Galerkin coarse matrix: factor_local_fp32); all substructures
   // in each launch sequence, or with per_substructure_launches one sequence
@@ -1455,7 +1490,7 @@ void Solver::factor() {
     }
     // L_rr^T beside L_rr: the backward solves read it row-coalesced
     HIPCHK(transpose_batched<double>(st, d_Lrr.as<double>(), d_Urr.as<double>(),
-                                     d_descRRT.as<MatDesc>(), ns, L.max_nr));
+                                     d_descRRT.as<MatDesc>(), ns, L.max_nr, h_descRR.data()));
   }
   // coarse problem
   const int64_t nc = L.n_coarse;
@@ -1469,7 +1504,7 @@ void Solver::factor() {
                                    status + 2 * ns, d_dinv_c.as<double>(),
                                    d_dinv_c_off.as<int64_t>()));
     HIPCHK(transpose_batched<double>(st, d_Lc.as<double>(), d_Uc.as<double>(), d_descC.as<MatDesc>(), 1,
-                                     (int)nc));
+                                     (int)nc, h_descC.data()));
   }
   check_status(true);
   auto t1 = std::chrono::steady_clock::now();
@@ -1564,10 +1599,11 @@ void Solver::factor_local_fp32(int *status) {
     };
     // Krp = K_r,pi (again) and Krp += K_rr PhiF: the FP64 residual of K_rr Phi = -K_r,pi
     auto residual = [&]() {
-      gather_block_kernel<<<dim3(nblocks(mx), ns), TPB, 0, st>>>(
-          d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), Krp, d_offRP.as<int64_t>(),
-          d_nr.as<int>(), d_ridx.as<int>(), d_ridx_off.as<int64_t>(), d_nr.as<int>(), d_pidx.as<int>(),
-          d_pidx_off.as<int64_t>(), d_np.as<int>(), 1.0);
+      if (h_gb_rp.back() > 0)
+        gather_block_kernel<<<(unsigned)h_gb_rp.back(), TPB, 0, st>>>(
+            d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), Krp, d_offRP.as<int64_t>(),
+            d_nr.as<int>(), d_ridx.as<int>(), d_ridx_off.as<int64_t>(), d_nr.as<int>(), d_pidx.as<int>(),
+            d_pidx_off.as<int64_t>(), d_np.as<int>(), 1.0, d_gb_rp.as<int64_t>(), ns);
       HIPCHK(hipGetLastError());
       HIPCHK(DenseOps<double>::gemm(st, d_Lrr.as<double>(), PhiF, Krp, d_krrphi_desc.as<GemmDesc>(),
                                     ns, L.max_nr, L.max_np, false, false, 1.0, 1.0, false,
@@ -1587,10 +1623,11 @@ void Solver::factor_local_fp32(int *status) {
     // size; without the refinement step the basis costs 76 PCG iterations
     // there instead of 30).  S_pi += K_pi,r Phi; W = K_r,pi + K_rr Phi;
     // S_pi += Phi^T W.
-    gather_block_kernel<<<dim3(nblocks(mx), ns), TPB, 0, st>>>(
-        d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), Krp, d_offRP.as<int64_t>(),
-        d_nr.as<int>(), d_ridx.as<int>(), d_ridx_off.as<int64_t>(), d_nr.as<int>(), d_pidx.as<int>(),
-        d_pidx_off.as<int64_t>(), d_np.as<int>(), 1.0);
+    if (h_gb_rp.back() > 0)
+      gather_block_kernel<<<(unsigned)h_gb_rp.back(), TPB, 0, st>>>(
+          d_W.as<double>(), d_offGG.as<int64_t>(), d_nG.as<int>(), Krp, d_offRP.as<int64_t>(),
+          d_nr.as<int>(), d_ridx.as<int>(), d_ridx_off.as<int64_t>(), d_nr.as<int>(), d_pidx.as<int>(),
+          d_pidx_off.as<int64_t>(), d_np.as<int>(), 1.0, d_gb_rp.as<int64_t>(), ns);
     HIPCHK(hipGetLastError());
     HIPCHK(DenseOps<double>::gemm(st, Krp, PhiF, d_Spi.as<double>(), d_spi_desc.as<GemmDesc>(), ns,
                                   L.max_np, L.max_np, true, false, 1.0, 1.0, false, h_spi.data()));
@@ -1600,7 +1637,8 @@ void Solver::factor_local_fp32(int *status) {
                                   L.max_np, L.max_np, true, false, 1.0, 1.0, false, h_spi.data()));
     HIPCHK(hipMemcpyAsync(Krp, PhiF, sizeof(double) * L.sRP, hipMemcpyDeviceToDevice, st));
   }
-  HIPCHK(transpose_batched<float>(st, L32, d_Urr32.as<float>(), d_descRRT.as<MatDesc>(), ns, L.max_nr));
+  HIPCHK(transpose_batched<float>(st, L32, d_Urr32.as<float>(), d_descRRT.as<MatDesc>(), ns, L.max_nr,
+                                  h_descRR.data()));
 }
 
 void Solver::check_status(bool all) {
