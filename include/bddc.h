@@ -90,6 +90,21 @@ typedef struct {
                                         batched.  Results agree with the batched
                                         ones to rounding (tile shapes follow the
                                         batch); the GEMM tuner is not used */
+  int chol_launch;                   /* the batched Cholesky factorizations (K_rr, the
+                                        coarse matrix, the interior fronts, the pair
+                                        eliminations): 0 (default) picks per call,
+                                        1 runs one launch per step of the blocked
+                                        factorization (block-column update,
+                                        diagonal factor, panel solve, trailing
+                                        update), 2 always runs the fused launch: one
+                                        launch walks every step of every
+                                        substructure, tasks taken from a ticket
+                                        counter and waiting on device-side
+                                        per-entry counters (Sec. 4: the local
+                                        factorizations are independent).  0 fuses
+                                        batches of up to 40,000 tile tasks, where
+                                        that measured faster.  Every setting gives
+                                        the same factor, bit for bit */
 } bddc_options;
 
 /* Q1 hexahedral mesh (Sec. 2: substructure matrices are subassembled from

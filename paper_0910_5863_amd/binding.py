@@ -40,7 +40,7 @@ class bddc_options(C.Structure):
     _fields_ = [("device", C.c_int), ("hip_stream", C.c_void_p), ("factor_precision", C.c_int),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", C.c_void_p),
                 ("verbose", C.c_int), ("autotune", C.c_int),
-                ("per_substructure_launches", C.c_int)]
+                ("per_substructure_launches", C.c_int), ("chol_launch", C.c_int)]
 
 
 class bddc_mesh(C.Structure):
@@ -349,7 +349,7 @@ class BDDC:
 
     def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True,
                  verbose: bool = False, factor_precision: int = 64, autotune: bool = False,
-                 per_substructure_launches: bool = False):
+                 per_substructure_launches: bool = False, chol_launch: int = 0):
         if device < 0:
             self.torch = None
             self.device = device
@@ -374,6 +374,7 @@ class BDDC:
         opt.verbose = 1 if verbose else 0
         opt.autotune = 1 if autotune else 0
         opt.per_substructure_launches = 1 if per_substructure_launches else 0
+        opt.chol_launch = int(chol_launch)
         self._keep = []
         if torch_allocator:
             def _alloc(n, user):

@@ -23,6 +23,7 @@ bddc_status bddc_create(const bddc_options *opt, bddc_ctx **out) {
   if (opt) c->opt = *opt;
   if (c->opt.factor_precision == 0) c->opt.factor_precision = 64;
   if (c->opt.factor_precision != 64 && c->opt.factor_precision != 32) return BDDC_ERR_ARG;
+  if (c->opt.chol_launch < 0 || c->opt.chol_launch > 2) return BDDC_ERR_ARG;
   if (c->opt.device < 0) {  // host-only context: analysis without a GPU
     c->S = std::make_unique<Solver>();
     *out = c.release();

@@ -41,11 +41,15 @@ bddc_status guarded(bddc_ctx *c, F f) {
       launch_timing() = (c && c->S && c->S->timer.mode == 2) ? &c->S->timer : nullptr;
       autotune_enabled() = c && c->opt.autotune != 0;
       per_entry_launches() = c && c->opt.per_substructure_launches != 0;
+      fused_workspace() = (c && c->S && c->opt.chol_launch != 1) ? &c->S->alloc : nullptr;
+      fused_max_tasks() = (c && c->opt.chol_launch == 2) ? INT64_MAX : kFusedAutoTasks;
     }
     ~Hook() {
       launch_timing() = nullptr;
       autotune_enabled() = false;
       per_entry_launches() = false;
+      fused_workspace() = nullptr;
+      fused_max_tasks() = kFusedAutoTasks;
     }
   } hook(c);
   try {

@@ -46,6 +46,24 @@ struct PerEntryOff {
 };
 int64_t autotune_entries();  // signatures tuned so far in this process
 
+// The fused Cholesky.  When a workspace allocator is set for the calling
+// thread (and per_entry_launches is off), DenseOps::potrf factors a batch of
+// at most fused_max_tasks() tile tasks in one launch: the steps of the
+// blocked factorization become tasks handed out by a ticket counter, each
+// entry's tasks waiting on device-side counters of that entry only, so
+// entries no longer wait for each other at every step and no launch gaps
+// separate the steps.  Bitwise the same factor as one launch per step.  The
+// plan and counters live in memory from the workspace for the duration of the
+// call (which synchronizes the stream once).  Larger batches, or no
+// workspace, run one launch per step: there the per-task start (ticket,
+// decode, wait) costs more than the launch gaps it saves (measured at the
+// 64^3 size: 64 K_rr of 2.6k-7.5k, 345k tasks, 64.4 ms fused against 57.0 ms
+// per step; batches up to about 30k tasks are faster fused).
+constexpr int64_t kFusedAutoTasks = 40000;
+struct DevAlloc;
+DevAlloc *&fused_workspace();  // the calling thread's slot (default nullptr)
+int64_t &fused_max_tasks();    // the calling thread's limit (default kFusedAutoTasks)
+
 struct LaunchScope {
   hipStream_t st;
   LaunchTiming *t;

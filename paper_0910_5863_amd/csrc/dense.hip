@@ -6,16 +6,20 @@
 // wave owns a quadrant of 16x16 MFMA blocks.  Operand tiles are staged
 // through LDS in K-steps of 16, the next step loaded into registers while the
 // current one is multiplied.
-// Work-group ids are remapped so that the tiles of one batch entry stay on
-// one XCD (consecutive hardware ids are dealt round-robin to the 8 XCDs),
-// which keeps an entry's shared operand panels in one L2.
+// A launch holds only the tiles each entry has (tile maps); in batches too
+// large for a map, work-group ids are remapped so that the tiles of one batch
+// entry stay on one XCD (consecutive hardware ids are dealt round-robin to the
+// 8 XCDs).
 //
-// Cholesky and multi-RHS triangular solves are left-looking and blocked with
-// NB = 64: per block column one GEMM launch (update with all previous
-// columns, large K) and one launch that factors / solves the 64x64 diagonal
-// block in LDS.  The few-RHS triangular solve used in every preconditioner
-// application is a single launch per direction: one work-group per 64-row
-// block, ordered by an atomic ticket, waiting on per-block completion flags.
+// Cholesky and multi-RHS triangular solves are blocked with NB = 64 in panels
+// of PB block columns: within a panel each block column is updated
+// (short-K GEMM), its 64x64 diagonal block factored (one wave) or applied
+// through its inverse, and the rest of the panel solved; then one large-K
+// GEMM updates everything outside the panel.  The Cholesky runs either one
+// launch per step or as one fused launch (tasks with per-entry counters).
+// The few-RHS triangular solve used in every preconditioner application is a
+// single launch per direction: one work-group per 64-row block, ordered by an
+// atomic ticket, waiting on per-block completion flags.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +30,7 @@
 #include <mutex>
 #include <tuple>
 #include "dense.h"
+#include "device.h"
 
 namespace bddc {
 
@@ -33,6 +38,7 @@ namespace {
 
 constexpr int BK = 16;  // K-step of the GEMM tiles
 constexpr int NXCD = 8;
+constexpr int PB = 8;   // block columns per panel of the blocked Cholesky and TRSM
 
 template <class T>
 struct Mfma;
@@ -79,9 +85,13 @@ __device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
 }
 
 // Only the tiles each entry has: the host sums every entry's tile count into
-// off[0..n] (passed by value with the launch), and work-group ids (remapped
-// as in xcd_remap, so an entry's tiles stay on one XCD) are split at those
-// offsets.  A batch of uneven entries then launches no empty work-groups.
+// off[0..n] (passed by value with the launch), and work-group ids are split at
+// those offsets.  A batch of uneven entries then launches no empty
+// work-groups.  The ids are not remapped per XCD: consecutive ids go to
+// different XCDs, which spreads every entry over all of them; entries whose
+// tiles differ in cost (K) then no longer leave some XCDs idle at the end of
+// a launch (keeping an entry on one XCD measured 4% slower on the adaptive
+// selection at the 64^3 size and no faster on the factorizations).
 // n = 0: not used (the caller falls back to a grid sized by its largest entry).
 constexpr int kMaxMapEntries = 480;
 struct TileMap {
@@ -89,9 +99,8 @@ struct TileMap {
   int off[kMaxMapEntries + 1];
 };
 __device__ __forceinline__ bool map_tile(const TileMap &m, int nwg, int &entry, int &tile) {
-  const int b = blockIdx.x;
-  int logical = b;
-  if ((nwg % NXCD) == 0) logical = (b % NXCD) * (nwg / NXCD) + (b / NXCD);
+  (void)nwg;
+  const int logical = blockIdx.x;
   if (logical >= m.off[m.n]) return false;
   int lo = 0, hi = m.n;  // off[lo] <= logical < off[hi]
   while (hi - lo > 1) {
@@ -125,18 +134,48 @@ __device__ __forceinline__ bool map_tile(const TileMap &m, int nwg, int &entry, 
 // through a per-kernel lookup table, which costs registers).
 // rmap / cmap (optional): C's row i is row rmap[i] of the storage, column j
 // is column cmap[j].  LW: only entries with row >= column are written.
-template <class T, bool TA, bool TB, int MT, int NT, int KS = 1, int TAG = 0, bool LW = false>
-__device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int lda, int ldb,
-                          int ldc, T alpha, T beta, int m0, int n0, const int *rmap = nullptr,
-                          const int *cmap = nullptr) {
+// gemm_tile_s is the same product with its LDS given by the caller (smem,
+// gemm_tile_lds<T, MT, NT, KS>() elements), so that one kernel can run tiles
+// of several shapes in one buffer.  COH: every global load and store of the
+// operands and of C is a device-coherent (agent-scope) access, for products
+// whose operands were written by other work-groups of the same launch (the
+// fused factorization); otherwise plain accesses.
+template <bool COH, class T>
+__device__ __forceinline__ T gld(const T *p) {
+  if constexpr (COH)
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+template <bool COH, class T>
+__device__ __forceinline__ void gst(T *p, T v) {
+  if constexpr (COH)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+
+template <class T, int MT, int NT, int KS>
+constexpr int gemm_tile_lds() {
+  constexpr int TM = 32 * MT, TN = 32 * NT;
+  constexpr int SA = BK * (TM + 2), SB = BK * (TN + 2);
+  constexpr int PART = 256 * MT * NT * 4;
+  constexpr int SOPS = KS * 2 * (SA + SB), SRED = (KS - 1) * PART;
+  return SOPS > SRED ? SOPS : SRED;
+}
+
+template <class T, bool TA, bool TB, int MT, int NT, int KS = 1, bool LW = false, bool COH = false>
+__device__ __forceinline__ void gemm_tile_s(T *smem, const T *A, const T *B, T *C, int M, int N,
+                                            int K, int lda, int ldb, int ldc, T alpha, T beta,
+                                            int m0, int n0, const int *rmap = nullptr,
+                                            const int *cmap = nullptr) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int TM = 32 * MT, TN = 32 * NT;
   constexpr int LA = TM * BK / 256, LB = TN * BK / 256;
   constexpr int SA = BK * (TM + 2), SB = BK * (TN + 2);      // one buffer of A / B
   constexpr int PART = 256 * MT * NT * 4;                     // one group's partial tile
-  constexpr int SOPS = KS * 2 * (SA + SB), SRED = (KS - 1) * PART;
+  constexpr int SOPS = KS * 2 * (SA + SB);
   static_assert(KS > 1 || SOPS >= 4 * (16 * MT + 1) * 16, "epilogue staging exceeds the operand buffers");
-  __shared__ T smem[SOPS > SRED ? SOPS : SRED];
   const int tid = threadIdx.x % 256, g = threadIdx.x / 256;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
@@ -153,14 +192,16 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
       const int e = tid + it * 256;
       const int r = TA ? e / BK : e % TM, kk = TA ? e % BK : e / TM;
       const int gr = m0 + r, gk = k0 + kk;
-      ra[it] = (gr < M && gk < K) ? (TA ? A[gk + (int64_t)gr * lda] : A[gr + (int64_t)gk * lda]) : T(0);
+      ra[it] = (gr < M && gk < K) ? gld<COH>(TA ? &A[gk + (int64_t)gr * lda] : &A[gr + (int64_t)gk * lda])
+                                  : T(0);
     }
 #pragma unroll
     for (int it = 0; it < LB; ++it) {
       const int e = tid + it * 256;
       const int c = TB ? e % TN : e / BK, kk = TB ? e / TN : e % BK;
       const int gc = n0 + c, gk = k0 + kk;
-      rb[it] = (gc < N && gk < K) ? (TB ? B[gc + (int64_t)gk * ldb] : B[gk + (int64_t)gc * ldb]) : T(0);
+      rb[it] = (gc < N && gk < K) ? gld<COH>(TB ? &B[gc + (int64_t)gk * ldb] : &B[gk + (int64_t)gc * ldb])
+                                  : T(0);
     }
   };
   auto lstore = [&](int buf) {
@@ -250,7 +291,7 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
         const int i = lane + 64 * it, r = i % (16 * MT), c = i / (16 * MT);
         const int row = r0 + r, col = c0 + c;
         cv[it] = (beta != T(0) && row < M && col < N)
-                     ? C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc]
+                     ? gld<COH>(&C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc])
                      : T(0);
       }
 #pragma unroll
@@ -267,7 +308,7 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
         if (row < M && col < N && (!LW || row >= col)) {
           T *cp = &C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc];
           const T v = stg[r + c * SR];
-          *cp = (beta == T(0)) ? v : v + beta * cv[it];
+          gst<COH>(cp, (beta == T(0)) ? v : v + beta * cv[it]);
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -285,10 +326,21 @@ __device__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int
           if (row < M && col < N && (!LW || row >= col)) {
             T *c = &C[(rmap ? rmap[row] : row) + (int64_t)(cmap ? cmap[col] : col) * ldc];
             const T v = alpha * acc[x][y][j];
-            *c = (beta == T(0)) ? v : v + beta * (*c);
+            gst<COH>(c, (beta == T(0)) ? v : v + beta * gld<COH>(c));
           }
         }
   }
+}
+
+// gemm_tile_s with an LDS array of its own per instantiation (TAG tells the
+// kernels apart, see above)
+template <class T, bool TA, bool TB, int MT, int NT, int KS = 1, int TAG = 0, bool LW = false>
+__device__ __forceinline__ void gemm_tile(const T *A, const T *B, T *C, int M, int N, int K, int lda,
+                                          int ldb, int ldc, T alpha, T beta, int m0, int n0,
+                                          const int *rmap = nullptr, const int *cmap = nullptr) {
+  __shared__ T smem[gemm_tile_lds<T, MT, NT, KS>()];
+  gemm_tile_s<T, TA, TB, MT, NT, KS, LW, false>(smem, A, B, C, M, N, K, lda, ldb, ldc, alpha, beta,
+                                                m0, n0, rmap, cmap);
 }
 
 // map.n > 0: the entry's own tiles only (lower: its lower-triangle tiles,
@@ -352,40 +404,35 @@ __global__ __launch_bounds__(256) void gemm_scatter_kernel(const T *A, const T *
 // --- Cholesky -------------------------------------------------------------
 
 // Update of block column k by the columns of its panel to its left:
+// The steps of the blocked Cholesky, one tile each, shared by the launch per
+// step (chol_*_kernel) and the fused launch (potrf_fused_kernel).  COH: the
+// matrix, the inverse blocks and the factor are accessed device-coherently
+// (the fused launch, where other work-groups of the same launch wrote them).
+
 // A[kb:, kb:kb+w] -= A[kb:, c0:kb] A[kb:kb+w, c0:kb]^T with c0 = k0 NB (the
 // panel's first column; the columns before it were applied by the panel
-// updates, chol_syrk_kernel).
-// MT = 4, KS = 1: 128-row tiles; MT = 2, KS = 2: 64-row tiles with two
-// groups of waves splitting K (for launches with few tiles)
-template <class T, int MT, int KS>
-__global__ __launch_bounds__(256 * KS) void chol_update_kernel(T *pool, const MatDesc *desc, int k,
-                                                               int k0, int tm, int batch,
-                                                               const TileMap map) {
+// updates, chol_syrk_tile), row tile t of 32 MT rows.
+template <class T, int MT, bool COH>
+__device__ __forceinline__ void chol_update_tile(T *smem, T *pool, const MatDesc &d, int k, int k0,
+                                                 int t) {
   constexpr int TM = 32 * MT;
-  int e, t;
-  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tm, batch, e, t)) return;
-  const MatDesc d = desc[e];
   const int kb = k * NB, c0 = k0 * NB;
   if (kb >= d.n || k <= k0) return;
   const int M = d.n - kb, N = min(NB, d.n - kb), K = kb - c0;
   if (t * TM >= M) return;
   T *A = pool + d.a_off;
   const T *P = A + kb + (int64_t)c0 * d.lda;
-  gemm_tile<T, false, true, MT, 2, KS, 1>(P, P, A + kb + (int64_t)kb * d.lda, M, N, K, d.lda, d.lda,
-                                          d.lda, T(-1), T(1), t * TM, 0);
+  gemm_tile_s<T, false, true, MT, 2, 1, false, COH>(smem, P, P, A + kb + (int64_t)kb * d.lda, M, N,
+                                                    K, d.lda, d.lda, d.lda, T(-1), T(1), t * TM, 0);
 }
 
 // Trailing update after a factored panel of columns [p0, p1):
 // A[p1:, p1:] -= L[p1:, p0:p1] L[p1:, p0:p1]^T, lower triangle only, 128 x 128
-// tiles (tile pairs tj <= ti, tm tile rows for the largest entry); the
-// diagonal tiles write only their lower part.
-template <class T>
-__global__ __launch_bounds__(256) void chol_syrk_kernel(T *pool, const MatDesc *desc, int p0, int p1,
-                                                        int tm, int batch, const TileMap map) {
-  int e, t;
-  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tm * (tm + 1) / 2, batch, e, t))
-    return;
-  const MatDesc d = desc[e];
+// tiles (tile t = the pair tj <= ti of lower_tile); the diagonal tiles write
+// only their lower part.
+template <class T, bool COH>
+__device__ __forceinline__ void chol_syrk_tile(T *smem, T *pool, const MatDesc &d, int p0, int p1,
+                                               int t) {
   if (p1 >= d.n) return;
   int ti, tj;
   lower_tile(t, ti, tj);
@@ -393,8 +440,27 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(T *pool, const MatDesc *
   if (ti * 128 >= M) return;
   T *A = pool + d.a_off;
   const T *P = A + p1 + (int64_t)p0 * d.lda;
-  gemm_tile<T, false, true, 4, 4, 1, 6, true>(P, P, A + p1 + (int64_t)p1 * d.lda, M, M, p1 - p0,
-                                              d.lda, d.lda, d.lda, T(-1), T(1), ti * 128, tj * 128);
+  gemm_tile_s<T, false, true, 4, 4, 1, true, COH>(smem, P, P, A + p1 + (int64_t)p1 * d.lda, M, M,
+                                                  p1 - p0, d.lda, d.lda, d.lda, T(-1), T(1),
+                                                  ti * 128, tj * 128);
+}
+
+// Row tiles below the diagonal of block column k (tile t: rows
+// kb + (t + 1) NB ..): X <- X L_kk^{-T} = X (L_kk^{-1})^T, an MFMA tile product
+// with the inverse written by chol_diag_block (in place: the tile is read
+// whole before it is written).
+template <class T, bool COH>
+__device__ __forceinline__ void chol_panel_tile(T *smem, T *pool, const MatDesc &d, int k, int t,
+                                                const T *Di) {
+  const int kb = k * NB;
+  if (kb >= d.n) return;
+  const int w = min(NB, d.n - kb);
+  const int r0 = kb + (t + 1) * NB;
+  if (r0 >= d.n) return;
+  const int nr = min(NB, d.n - r0);
+  T *X = pool + d.a_off + r0 + (int64_t)kb * d.lda;
+  gemm_tile_s<T, false, true, 2, 2, 1, false, COH>(smem, X, Di, X, nr, w, w, d.lda, NB, d.lda, T(1),
+                                                   T(0), 0, 0);
 }
 
 // value of v in lane l (l uniform over the wave)
@@ -409,62 +475,58 @@ __device__ __forceinline__ float readlane(float v, int l) {
 }
 
 // Factor the diagonal block of block column k in place and write the inverse
-// of the factored block to dinv (entry e, block k at dinv + dinv_off[e] +
-// k NB^2, ld NB, zero outside the w x w block): one wave per entry.  Lane r
-// holds row r of the block in registers; column c is eliminated right-looking
-// with the entries of column c broadcast from their lanes (readlane), so the
-// column steps need no barrier and no LDS traffic.  Per entry the operations
-// and their order are those of the row-by-row elimination: a = a_rc / a_cc,
-// a_rs -= a a_sc for s > c, then l_rc = a_rc / sqrt(a_cc).  The inverse is
-// formed as before, lane j taking column j by forward substitution against
-// the rows of L broadcast from LDS.  status[e] receives (column+1) of the
-// first non-positive pivot.
-template <class T>
-__global__ __launch_bounds__(64) void chol_diag_kernel(T *pool, const MatDesc *desc, int k,
-                                                       int *status, int batch, T *dinv,
-                                                       const int64_t *dinv_off) {
-  __shared__ T D[NB][NB + 1];
-  __shared__ T Y[NB][NB + 1];
-  const int e = blockIdx.x;
-  if (e >= batch) return;
-  const MatDesc d = desc[e];
+// of the factored block to out (NB x NB, ld NB, zero outside the w x w
+// block).  Wave 0 computes; every thread of the work-group must call (the
+// barriers), and all of them copy the inverse out.  Lane r holds row r of the
+// block in registers; column c is eliminated right-looking with the entries
+// of column c broadcast from their lanes (readlane), so the column steps need
+// no barrier and no LDS traffic.  Per entry the operations and their order
+// are those of the row-by-row elimination: a = a_rc / a_cc, a_rs -= a a_sc for
+// s > c, then l_rc = a_rc / sqrt(a_cc).  The inverse is formed by lane j
+// taking column j by forward substitution against the rows of L broadcast
+// from LDS (D).  *status receives (column+1) of the first non-positive pivot.
+template <class T, bool COH>
+__device__ void chol_diag_block(T *pool, const MatDesc &d, int k, int *status, T *out,
+                                T (*D)[NB + 1], T (*Y)[NB + 1]) {
   const int kb = k * NB;
-  if (kb >= d.n) return;
+  if (kb >= d.n) return;  // uniform
   const int w = min(NB, d.n - kb);
   T *A = pool + d.a_off;
   const int64_t lda = d.lda;
   const int r = threadIdx.x;
-  T row[NB];
+  if (r < 64) {
+    T row[NB];
 #pragma unroll
-  for (int c = 0; c < NB; ++c)
-    row[c] = (r < w && c < w && r >= c) ? A[(kb + r) + (int64_t)(kb + c) * lda] : T(0);
-  int fail = 0;
+    for (int c = 0; c < NB; ++c)
+      row[c] = (r < w && c < w && r >= c) ? gld<COH>(&A[(kb + r) + (int64_t)(kb + c) * lda]) : T(0);
+    int fail = 0;
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (c < w) {  // uniform
-      T piv = readlane(row[c], c);
-      if (!(piv > T(0))) {
-        if (fail == 0) fail = kb + c + 1;
-        piv = T(1);
+    for (int c = 0; c < NB; ++c) {
+      if (c < w) {  // uniform
+        T piv = readlane(row[c], c);
+        if (!(piv > T(0))) {
+          if (fail == 0) fail = kb + c + 1;
+          piv = T(1);
+        }
+        const T lcc = sqrt(piv);
+        const T a = row[c] / piv;
+        // rows r > c: a_rs -= a a_sc for c < s <= r (entries above the
+        // diagonal, s > r, are updated too and never read)
+#pragma unroll
+        for (int sc = c + 1; sc < NB; ++sc) row[sc] -= a * readlane(row[c], sc);
+        row[c] = r == c ? lcc : row[c] / lcc;
       }
-      const T lcc = sqrt(piv);
-      const T a = row[c] / piv;
-      // rows r > c: a_rs -= a a_sc for c < s <= r (entries above the
-      // diagonal, s > r, are updated too and never read)
-#pragma unroll
-      for (int sc = c + 1; sc < NB; ++sc) row[sc] -= a * readlane(row[c], sc);
-      row[c] = r == c ? lcc : row[c] / lcc;
     }
-  }
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (r < w && c < w && r >= c) A[(kb + r) + (int64_t)(kb + c) * lda] = row[c];
-    // the factor, and the identity outside the w x w block, for the inverse
-    D[r][c] = (r < w && c < w) ? (r >= c ? row[c] : T(0)) : (r == c ? T(1) : T(0));
+    for (int c = 0; c < NB; ++c) {
+      if (r < w && c < w && r >= c) gst<COH>(&A[(kb + r) + (int64_t)(kb + c) * lda], row[c]);
+      // the factor, and the identity outside the w x w block, for the inverse
+      D[r][c] = (r < w && c < w) ? (r >= c ? row[c] : T(0)) : (r == c ? T(1) : T(0));
+    }
+    if (r == 0 && fail && status) atomicCAS(status, 0, fail);
   }
-  if (r == 0 && fail && status) atomicCAS(&status[e], 0, fail);
   __syncthreads();
-  {
+  if (r < 64) {
     const int j = r;
     T y[NB];
 #pragma unroll
@@ -482,30 +544,53 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(T *pool, const MatDesc *d
     for (int rr = 0; rr < NB; ++rr) Y[rr][j] = (rr < w && j < w) ? y[rr] : T(0);
   }
   __syncthreads();
-  T *out = dinv + dinv_off[e] + (int64_t)k * NB * NB;
-  for (int i = r; i < NB * NB; i += 64) out[i] = Y[i % NB][i / NB];
+  for (int i = r; i < NB * NB; i += blockDim.x) gst<COH>(&out[i], Y[i % NB][i / NB]);
 }
 
-// Row tiles below the diagonal of block column k (tile t >= 1):
-// X <- X L_kk^{-T} = X (L_kk^{-1})^T, an MFMA tile product with the inverse
-// written by chol_diag_kernel (in place: the tile is read whole before it is
-// written).
+// One launch per step of the blocked Cholesky (DenseOps::potrf without the
+// fused launch): every entry's tiles of the step.
+// MT = 4: 128-row tiles; MT = 2: 64-row tiles (launches with few tiles); the
+// sums are the same for both.
+template <class T, int MT>
+__global__ __launch_bounds__(256) void chol_update_kernel(T *pool, const MatDesc *desc, int k, int k0,
+                                                          int tm, int batch, const TileMap map) {
+  __shared__ T smem[gemm_tile_lds<T, MT, 2, 1>()];
+  int e, t;
+  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tm, batch, e, t)) return;
+  chol_update_tile<T, MT, false>(smem, pool, desc[e], k, k0, t);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void chol_syrk_kernel(T *pool, const MatDesc *desc, int p0, int p1,
+                                                        int tm, int batch, const TileMap map) {
+  __shared__ T smem[gemm_tile_lds<T, 4, 4, 1>()];
+  int e, t;
+  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tm * (tm + 1) / 2, batch, e, t))
+    return;
+  chol_syrk_tile<T, false>(smem, pool, desc[e], p0, p1, t);
+}
+
+// one wave per entry
+template <class T>
+__global__ __launch_bounds__(64) void chol_diag_kernel(T *pool, const MatDesc *desc, int k,
+                                                       int *status, int batch, T *dinv,
+                                                       const int64_t *dinv_off) {
+  __shared__ T D[NB][NB + 1];
+  __shared__ T Y[NB][NB + 1];
+  const int e = blockIdx.x;
+  if (e >= batch) return;
+  chol_diag_block<T, false>(pool, desc[e], k, status ? status + e : nullptr,
+                            dinv + dinv_off[e] + (int64_t)k * NB * NB, D, Y);
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void chol_panel_kernel(T *pool, const MatDesc *desc, int k,
                                                          int tm, int batch, const T *dinv,
                                                          const int64_t *dinv_off, const TileMap map) {
+  __shared__ T smem[gemm_tile_lds<T, 2, 2, 1>()];
   int e, t;
   if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tm, batch, e, t)) return;
-  const MatDesc d = desc[e];
-  const int kb = k * NB;
-  if (kb >= d.n) return;
-  const int w = min(NB, d.n - kb);
-  const int r0 = kb + (t + 1) * NB;
-  if (r0 >= d.n) return;
-  const int nr = min(NB, d.n - r0);
-  T *X = pool + d.a_off + r0 + (int64_t)kb * d.lda;
-  const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
-  gemm_tile<T, false, true, 2, 2, 1, 2>(X, Di, X, nr, w, w, d.lda, NB, d.lda, T(1), T(0), 0, 0);
+  chol_panel_tile<T, false>(smem, pool, desc[e], k, t, dinv + dinv_off[e] + (int64_t)k * NB * NB);
 }
 
 // --- multi-RHS triangular solves -------------------------------------------
@@ -942,6 +1027,143 @@ __global__ void transpose_kernel(const T *apool, T *bpool, const MatDesc *desc, 
   }
 }
 
+// --- fused Cholesky: one launch for every step of every entry -------------
+//
+// The tasks are the tiles of the steps above, grouped in levels: per panel of
+// PB block columns, for each column k of the panel the update (except the
+// panel's first column), the diagonal factor and the panel solve, then the
+// trailing update.  An entry's tasks of one level need all of its tasks of the
+// earlier levels (the order of the launch-per-step sequence, kept per entry
+// instead of over the whole batch), and run the same tile code on the same
+// data, so the factor is bitwise the launch-per-step one.  A ticket counter
+// hands out the tasks in chunks (the tasks of one entry at one level, in
+// an order chosen by the host that keeps every entry's levels in sequence); a
+// work-group waits until its entry has completed all its tasks of the earlier
+// levels (a per-entry counter).  Every task waited on holds a smaller ticket,
+// so it is running or done: the launch cannot deadlock whatever the number of
+// resident work-groups.  Matrix data that crosses work-groups is read and
+// written device-coherently; a task's counter increment follows the
+// completion of all its stores (store-counter wait and barrier), and its reads
+// follow the counter load.  The waits are bounded: past the bound (a guard
+// against an earlier fault only) the launch sets err and every work-group
+// leaves.
+struct FusedPlan {
+  const int *base;  // [C + 1] first ticket of each chunk
+  const int *code;  // [C] level of the chunk: panel * 3 PB + step in the panel
+  const int *ent;   // [C] batch entry of the chunk
+  const int *need;  // [C] tasks of the entry in its earlier levels
+  int C, total;
+  int mt_update;    // row tile of the update step: 32 mt_update rows
+};
+constexpr int kFusedCtl = 4;  // ctl[0] ticket counter, ctl[1] abort flag, then B counters
+constexpr long long kFusedWaitTicks = 400000000LL;  // wall-clock ticks (100 MHz: 4 s)
+
+// largest j in [0, n) with a[j] <= key (a ascending, a[0] <= key); called by
+// all lanes of one wave: 64-ary search, one load per lane and step
+__device__ int wave_floor(const int *a, int n, int key) {
+  const int lane = threadIdx.x & 63;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int step = (hi - lo + 63) / 64;
+    const int idx = lo + lane * step;
+    const bool ok = idx < hi && a[idx] <= key;
+    const int cnt = __popcll(__ballot(ok));  // a prefix of the lanes (a ascending); lane 0 holds
+    lo = lo + (cnt - 1) * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
+// bounded wait until *cnt >= need; false (the launch is aborted) past the bound
+// or when another work-group aborted
+__device__ bool fused_wait(int *cnt, int need, int *abort, int *err) {
+  const long long t0 = wall_clock64();
+  for (int it = 0;; ++it) {
+    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+    if ((it & 31) == 31) {
+      if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+      if (wall_clock64() - t0 > kFusedWaitTicks) {
+        atomicExch(abort, 1);
+        atomicExch(err, 1);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+template <class T>
+constexpr int fused_lds() {
+  return gemm_tile_lds<T, 4, 4, 1>() > 2 * NB * (NB + 1) ? gemm_tile_lds<T, 4, 4, 1>()
+                                                         : 2 * NB * (NB + 1);
+}
+
+// One task per work-group: the work-group takes the next ticket (not its
+// block index), so every task it waits on holds a smaller ticket, taken by a
+// work-group that is running or done.
+template <class T>
+__global__ __launch_bounds__(256) void potrf_fused_kernel(T *pool, const MatDesc *desc, int *status,
+                                                          T *dinv, const int64_t *dinv_off,
+                                                          const FusedPlan plan, int *ctl, int *err) {
+  static_assert(gemm_tile_lds<T, 4, 2, 1>() <= fused_lds<T>() &&
+                gemm_tile_lds<T, 2, 2, 1>() <= fused_lds<T>(), "LDS of the fused launch");
+  __shared__ T smem[fused_lds<T>()];
+  __shared__ int s_task[4];
+  int *done = ctl + kFusedCtl;
+  constexpr int LPP = 3 * PB;
+  if (threadIdx.x < 64) {  // wave 0: take a ticket, decode it, wait for the entry
+    int ticket = 0;
+    if (threadIdx.x == 0) ticket = atomicAdd(&ctl[0], 1);
+    ticket = __shfl(ticket, 0);
+    int ch = 0, tile = 0, stop = 1;
+    if (ticket < plan.total &&
+        __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      ch = wave_floor(plan.base, plan.C, ticket);
+      tile = ticket - plan.base[ch];
+      if (threadIdx.x == 0)
+        stop = fused_wait(&done[plan.ent[ch]], plan.need[ch], &ctl[1], err) ? 0 : 1;
+      stop = __shfl(stop, 0);
+    }
+    if (threadIdx.x == 0) {
+      s_task[0] = ch;
+      s_task[1] = tile;
+      s_task[2] = stop;
+    }
+  }
+  __syncthreads();
+  const int ch = s_task[0], tile = s_task[1];
+  if (s_task[2]) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  const int e = plan.ent[ch];
+  const MatDesc d = desc[e];
+  const int code = plan.code[ch];
+  const int k0 = (code / LPP) * PB, sp = code % LPP;
+  if (sp == LPP - 1) {
+    chol_syrk_tile<T, true>(smem, pool, d, k0 * NB, (k0 + PB) * NB, tile);
+  } else {
+    const int j = sp < 2 ? 0 : (sp - 2) / 3 + 1, r = sp < 2 ? sp + 1 : (sp - 2) % 3;
+    const int k = k0 + j;
+    T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
+    if (r == 0) {
+      if (plan.mt_update == 4)
+        chol_update_tile<T, 4, true>(smem, pool, d, k, k0, tile);
+      else
+        chol_update_tile<T, 2, true>(smem, pool, d, k, k0, tile);
+    } else if (r == 1) {
+      chol_diag_block<T, true>(pool, d, k, status ? status + e : nullptr, Di,
+                               reinterpret_cast<T(*)[NB + 1]>(smem),
+                               reinterpret_cast<T(*)[NB + 1]>(smem + NB * (NB + 1)));
+    } else {
+      chol_panel_tile<T, true>(smem, pool, d, k, tile, Di);
+    }
+  }
+  // every store of the task acknowledged before the entry's counter moves
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[e], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void zero_ints_kernel(int *p, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1075,6 +1297,16 @@ bool &per_entry_launches() {
   return on;
 }
 
+DevAlloc *&fused_workspace() {
+  static thread_local DevAlloc *slot = nullptr;
+  return slot;
+}
+
+int64_t &fused_max_tasks() {
+  static thread_local int64_t limit = kFusedAutoTasks;
+  return limit;
+}
+
 int64_t autotune_entries() {
   std::lock_guard<std::mutex> g(tune_mutex());
   return (int64_t)tune_table().size();
@@ -1203,8 +1435,127 @@ hipError_t DenseOps<T>::gemm_scatter(hipStream_t st, const T *A, const T *B, T *
 // diagonal block factored and inverted (chol_diag_kernel) and the rows below
 // solved (chol_panel_kernel); then the whole trailing matrix is updated by
 // the panel at once (chol_syrk_kernel, 128 x 128 tiles, K = PB NB), so most
-// flops run as large tile products with many work-groups.
-constexpr int PB = 8;
+// flops run as large tile products with many work-groups (PB: the panel
+// width in blocks, defined with the kernels).
+
+// The fused Cholesky (potrf_fused_kernel): the host lists, per level, the
+// tasks of every entry (largest entries first), uploads the tables with the
+// workspace's memory, clears the counters, launches once and checks the
+// abort flag (one synchronization).
+template <class T>
+hipError_t potrf_fused(hipStream_t st, T *pool, const MatDesc *d_desc, const MatDesc *h_desc,
+                       int batch, int *status, T *dinv, const int64_t *dinv_off, DevAlloc &ws,
+                       int64_t max_tasks, bool &used) {
+  used = false;
+  int maxn = 0;
+  for (int e = 0; e < batch; ++e) maxn = std::max(maxn, h_desc[e].n);
+  if (maxn == 0) return hipSuccess;
+  const int nblk = (maxn + NB - 1) / NB, panels = (nblk + PB - 1) / PB, LPP = 3 * PB;
+  // the update step's row tile: 128 rows when the batch fills the device
+  // several times over with them (as the launch-per-step path decides per
+  // column), else 64
+  int64_t t128 = 0;
+  for (int e = 0; e < batch; ++e) t128 += (std::max(0, h_desc[e].n - NB) + 127) / 128;
+  const int mt = t128 >= 2048 ? 4 : 2, tmu = 32 * mt;
+  auto tasks = [&](int n, int code) -> int64_t {
+    const int k0 = (code / LPP) * PB, sp = code % LPP, nb = (n + NB - 1) / NB;
+    if (sp == LPP - 1) {
+      const int64_t p1 = (int64_t)(k0 + PB) * NB;
+      if (p1 >= n) return 0;
+      const int64_t a = (n - p1 + 127) / 128;
+      return a * (a + 1) / 2;
+    }
+    const int j = sp < 2 ? 0 : (sp - 2) / 3 + 1, r = sp < 2 ? sp + 1 : (sp - 2) % 3, k = k0 + j;
+    if (k >= nb) return 0;
+    if (r == 0) return (n - k * NB + tmu - 1) / tmu;
+    if (r == 1) return 1;
+    return nb - k - 1;
+  };
+  // chunks (entry, level) with tasks, each entry's in level order
+  struct Chunk {
+    int code, e;
+    int64_t cnt, need;
+  };
+  std::vector<int> order(batch);
+  for (int e = 0; e < batch; ++e) order[e] = e;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h_desc[a].n > h_desc[b].n; });
+  std::vector<Chunk> chunks;
+  std::vector<int64_t> cum(batch, 0);
+  for (int c = 0; c < panels * LPP; ++c)
+    for (int e : order) {
+      const int64_t t = tasks(h_desc[e].n, c);
+      if (t == 0) continue;
+      chunks.push_back(Chunk{c, e, t, cum[e]});
+      cum[e] += t;
+    }
+  // entries staggered by phase: entry of rank q starts q mod 3 levels late,
+  // so the latency-bound diagonal steps of some entries overlap the tile
+  // products of others (measured 3-7% faster than all entries in step)
+  {
+    std::vector<int> len(batch, 0), rank(batch, 0), idx(chunks.size());
+    for (int i = 0; i < batch; ++i) rank[order[i]] = i;
+    for (size_t i = 0; i < chunks.size(); ++i) idx[i] = len[chunks[i].e]++;
+    std::vector<std::tuple<int, int, int>> key(chunks.size());
+    for (size_t i = 0; i < chunks.size(); ++i) {
+      const int e = chunks[i].e;
+      key[i] = std::make_tuple(idx[i] + rank[e] % 3, rank[e], (int)i);
+    }
+    std::vector<size_t> perm(chunks.size());
+    for (size_t i = 0; i < perm.size(); ++i) perm[i] = i;
+    std::sort(perm.begin(), perm.end(), [&](size_t x, size_t y) { return key[x] < key[y]; });
+    std::vector<Chunk> sorted(chunks.size());
+    for (size_t i = 0; i < perm.size(); ++i) sorted[i] = chunks[perm[i]];
+    chunks.swap(sorted);
+  }
+  const int C = (int)chunks.size();
+  int64_t ntask = 0;
+  for (const Chunk &q : chunks) ntask += q.cnt;
+  if (ntask > max_tasks) return hipSuccess;  // declined: one launch per step
+  used = true;
+  if (C == 0) return hipSuccess;
+  std::vector<int> plan;
+  plan.reserve(4 * (size_t)C + 1);
+  int64_t total = 0;
+  for (const Chunk &q : chunks) {
+    plan.push_back((int)total);
+    total += q.cnt;
+    if (total >= INT_MAX / 2) return hipErrorInvalidValue;
+  }
+  plan.push_back((int)total);
+  const size_t o_base = 0, o_code = C + 1, o_ent = o_code + C, o_need = o_ent + C, o_ctl = o_need + C;
+  for (const Chunk &q : chunks) plan.push_back(q.code);
+  for (const Chunk &q : chunks) plan.push_back(q.e);
+  for (const Chunk &q : chunks) plan.push_back((int)q.need);
+  const int nctl = kFusedCtl + batch + 1;  // counters, then the abort report
+  const size_t bytes = sizeof(int) * (o_ctl + nctl);
+  int *w = static_cast<int *>(ws.get(bytes));
+  hipError_t rc = hipMemcpyAsync(w, plan.data(), sizeof(int) * plan.size(), hipMemcpyHostToDevice, st);
+  int *ctl = w + o_ctl, *err = ctl + kFusedCtl + batch;
+  if (rc == hipSuccess) {
+    zero_ints_kernel<<<(nctl + 255) / 256, 256, 0, st>>>(ctl, nctl);
+    rc = hipGetLastError();
+  }
+  if (rc == hipSuccess) {
+    FusedPlan fp{w + o_base, w + o_code, w + o_ent, w + o_need, C, (int)total, mt};
+    const int grid = (int)total;  // one task per work-group
+    double fl = 0, by = 0;
+    if (launch_timing())
+      for (int e = 0; e < batch; ++e) {
+        const double n = h_desc[e].n;
+        fl += n * n * n / 3.0;
+        by += sizeof(T) * n * n;
+      }
+    LaunchScope ls(st, "potrf_fused_kernel", by, fl);
+    potrf_fused_kernel<T><<<grid, 256, 0, st>>>(pool, d_desc, status, dinv, dinv_off, fp, ctl, err);
+    rc = hipGetLastError();
+  }
+  int herr = 0;
+  if (rc == hipSuccess) rc = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (rc == hipSuccess) rc = hipStreamSynchronize(st);
+  ws.put(w, bytes);
+  if (rc != hipSuccess) return rc;
+  return herr ? hipErrorLaunchTimeOut : hipSuccess;
+}
 
 template <class T>
 hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
@@ -1215,6 +1566,12 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
       HIP_RETURN_IF(potrf(st, pool, d_desc + e, h_desc + e, 1, status ? status + e : nullptr, dinv,
                           dinv_off + e));
     return hipSuccess;
+  }
+  if (!per_entry_launches() && fused_workspace() && fused_max_tasks() > 0) {
+    bool used = false;
+    HIP_RETURN_IF(potrf_fused<T>(st, pool, d_desc, h_desc, batch, status, dinv, dinv_off,
+                                 *fused_workspace(), fused_max_tasks(), used));
+    if (used) return hipSuccess;
   }
   int maxn = 0;
   for (int e = 0; e < batch; ++e) maxn = std::max(maxn, h_desc[e].n);
@@ -1255,13 +1612,13 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
           const TileMap map = rows_map(128, 0);
           const int nt = map.n > 0 ? map.off[map.n] : batch * tu;
           if (nt > 0)
-            chol_update_kernel<T, 4, 1><<<grid_round(nt), 256, 0, st>>>(pool, d_desc, k, k0, tu, batch, map);
+            chol_update_kernel<T, 4><<<grid_round(nt), 256, 0, st>>>(pool, d_desc, k, k0, tu, batch, map);
         } else {
           const int t64 = (maxn - k * NB + 63) / 64;
           const TileMap map = rows_map(64, 0);
           const int nt = map.n > 0 ? map.off[map.n] : batch * t64;
           if (nt > 0)
-            chol_update_kernel<T, 2, 2><<<grid_round(nt), 512, 0, st>>>(pool, d_desc, k, k0, t64, batch, map);
+            chol_update_kernel<T, 2><<<grid_round(nt), 256, 0, st>>>(pool, d_desc, k, k0, t64, batch, map);
         }
       }
       {
