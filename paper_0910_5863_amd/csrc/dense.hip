@@ -403,7 +403,6 @@ __global__ __launch_bounds__(256) void gemm_scatter_kernel(const T *A, const T *
 
 // --- Cholesky -------------------------------------------------------------
 
-// Update of block column k by the columns of its panel to its left:
 // The steps of the blocked Cholesky, one tile each, shared by the launch per
 // step (chol_*_kernel) and the fused launch (potrf_fused_kernel).  COH: the
 // matrix, the inverse blocks and the factor are accessed device-coherently
@@ -1356,6 +1355,14 @@ hipError_t DenseOps<T>::gemm(hipStream_t st, const T *A, const T *B, T *C, const
                            beta, lower, h_desc + e));
     return hipSuccess;
   }
+  // batches larger than a tile map: sub-batches that each launch only
+  // their entries' own tiles
+  if (batch > kMaxMapEntries && h_desc) {
+    for (int e0 = 0; e0 < batch; e0 += kMaxMapEntries)
+      HIP_RETURN_IF(gemm(st, A, B, C, d_desc + e0, std::min(kMaxMapEntries, batch - e0), maxM, maxN,
+                         transA, transB, alpha, beta, lower, h_desc + e0));
+    return hipSuccess;
+  }
   double fl = 0, by = 0;
   if (launch_timing() && h_desc)
     for (int e = 0; e < batch; ++e) {
@@ -1406,6 +1413,12 @@ hipError_t DenseOps<T>::gemm_scatter(hipStream_t st, const T *A, const T *B, T *
       if (h_desc[e].M > 0 && h_desc[e].N > 0)
         HIP_RETURN_IF(gemm_scatter(st, A, B, C, d_desc + e, map, map_off + e, map_rows, 1,
                                    h_desc[e].M, h_desc[e].N, h_desc + e));
+    return hipSuccess;
+  }
+  if (batch > kMaxMapEntries && h_desc) {  // sub-batches, as in gemm
+    for (int e0 = 0; e0 < batch; e0 += kMaxMapEntries)
+      HIP_RETURN_IF(gemm_scatter(st, A, B, C, d_desc + e0, map, map_off + e0, map_rows,
+                                 std::min(kMaxMapEntries, batch - e0), maxM, maxN, h_desc + e0));
     return hipSuccess;
   }
   double fl = 0, by = 0;
@@ -1573,6 +1586,12 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
                                  *fused_workspace(), fused_max_tasks(), used));
     if (used) return hipSuccess;
   }
+  if (batch > kMaxMapEntries) {  // sub-batches, as in gemm
+    for (int e0 = 0; e0 < batch; e0 += kMaxMapEntries)
+      HIP_RETURN_IF(potrf(st, pool, d_desc + e0, h_desc + e0, std::min(kMaxMapEntries, batch - e0),
+                          status ? status + e0 : nullptr, dinv, dinv_off + e0));
+    return hipSuccess;
+  }
   int maxn = 0;
   for (int e = 0; e < batch; ++e) maxn = std::max(maxn, h_desc[e].n);
   if (maxn == 0) return hipSuccess;
@@ -1670,6 +1689,12 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
   if (per_entry_launches() && batch > 1) {
     for (int e = 0; e < batch; ++e)
       HIP_RETURN_IF(trsm(st, pool_a, pool_b, d_desc + e, h_desc + e, 1, transpose, dinv, dinv_off + e));
+    return hipSuccess;
+  }
+  if (batch > kMaxMapEntries) {  // sub-batches, as in gemm
+    for (int e0 = 0; e0 < batch; e0 += kMaxMapEntries)
+      HIP_RETURN_IF(trsm(st, pool_a, pool_b, d_desc + e0, h_desc + e0, std::min(kMaxMapEntries, batch - e0),
+                         transpose, dinv, dinv_off + e0));
     return hipSuccess;
   }
   int maxn = 0, maxr = 0;
@@ -1832,6 +1857,12 @@ template <class T>
 hipError_t symmetrize_lower(hipStream_t st, T *pool, const MatDesc *d_desc, int batch, int maxn,
                             const MatDesc *h_desc) {
   if (batch <= 0 || maxn <= 0) return hipSuccess;
+  if (batch > kMaxMapEntries && h_desc) {  // sub-batches, as in gemm
+    for (int e0 = 0; e0 < batch; e0 += kMaxMapEntries)
+      HIP_RETURN_IF(symmetrize_lower(st, pool, d_desc + e0, std::min(kMaxMapEntries, batch - e0), maxn,
+                                     h_desc + e0));
+    return hipSuccess;
+  }
   const int nt = (maxn + 31) / 32;
   const TileMap map = h_desc ? tile_map(batch, [&](int e) {
     const int t = (h_desc[e].n + 31) / 32;
@@ -1905,6 +1936,12 @@ template <class T>
 hipError_t transpose_batched(hipStream_t st, const T *apool, T *bpool, const MatDesc *d_desc,
                              int batch, int maxn, const MatDesc *h_desc) {
   if (batch <= 0 || maxn <= 0) return hipSuccess;
+  if (batch > kMaxMapEntries && h_desc) {  // sub-batches, as in gemm
+    for (int e0 = 0; e0 < batch; e0 += kMaxMapEntries)
+      HIP_RETURN_IF(transpose_batched(st, apool, bpool, d_desc + e0, std::min(kMaxMapEntries, batch - e0),
+                                      maxn, h_desc + e0));
+    return hipSuccess;
+  }
   const TileMap map = h_desc ? tile_map(batch, [&](int e) {
     const int t = (h_desc[e].n + 31) / 32;
     return t * t;
