@@ -411,7 +411,20 @@ __global__ void gemv_t_kernel(const double *apool, const int64_t *aoff, const in
   double acc[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) acc[q] = 0;
-  for (int r = lane; r < m; r += 64) {
+  // four rows per lane per batch: their loads of A are issued together (the
+  // sums keep the order of one row at a time)
+  int r = lane;
+  for (; r + 192 < m; r += 256) {
+    double a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = A[r + 64 * u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < M; ++q)
+        if (q < nrhs) acc[q] += a[u] * xx[r + 64 * u + q * ldx];
+  }
+  for (; r < m; r += 64) {
     const double a = A[r];
 #pragma unroll
     for (int q = 0; q < M; ++q)
@@ -442,7 +455,20 @@ __global__ void gemv_n_kernel(const double *apool, const int64_t *aoff, const in
   double acc[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) acc[q] = 0;
-  for (int j = 0; j < n; ++j) {
+  // eight columns per batch: their loads of A are issued together (the sums
+  // keep the order of one column at a time)
+  int j = 0;
+  for (; j + 8 <= n; j += 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = A[r + (int64_t)(j + u) * m];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int q = 0; q < M; ++q)
+        if (q < nrhs) acc[q] += a[u] * xx[j + u + q * ldx];
+  }
+  for (; j < n; ++j) {
     const double a = A[r + (int64_t)j * m];
 #pragma unroll
     for (int q = 0; q < M; ++q)
