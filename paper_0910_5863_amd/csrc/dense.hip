@@ -87,20 +87,28 @@ __device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
 // Only the tiles each entry has: the host sums every entry's tile count into
 // off[0..n] (passed by value with the launch), and work-group ids are split at
 // those offsets.  A batch of uneven entries then launches no empty
-// work-groups.  The ids are not remapped per XCD: consecutive ids go to
-// different XCDs, which spreads every entry over all of them; entries whose
-// tiles differ in cost (K) then no longer leave some XCDs idle at the end of
-// a launch (keeping an entry on one XCD measured 4% slower on the adaptive
-// selection at the 64^3 size and no faster on the factorizations).
+// work-groups.  Logical tiles are dealt to the XCDs in chunks of kXcdChunk
+// consecutive tiles (consecutive hardware ids go round-robin to the 8 XCDs;
+// the grid is a multiple of 8 kXcdChunk): a chunk's tiles share operand
+// panels in one L2, and every XCD gets a fine-grained mix of all entries, so
+// entries whose tiles differ in cost (K) do not leave some XCDs idle at the
+// end of a launch (keeping each entry on one XCD measured 4% slower on the
+// adaptive selection at the 64^3 size; chunks of 1 to 16 tiles measured the
+// same).
 // n = 0: not used (the caller falls back to a grid sized by its largest entry).
 constexpr int kMaxMapEntries = 480;
 struct TileMap {
   int n;
   int off[kMaxMapEntries + 1];
 };
+constexpr int kXcdChunk = 8;
 __device__ __forceinline__ bool map_tile(const TileMap &m, int nwg, int &entry, int &tile) {
-  (void)nwg;
-  const int logical = blockIdx.x;
+  const int b = blockIdx.x;
+  int logical = b;
+  if (kXcdChunk > 1 && nwg % (NXCD * kXcdChunk) == 0) {
+    const int x = b % NXCD, i = b / NXCD;
+    logical = ((i / kXcdChunk) * NXCD + x) * kXcdChunk + (i % kXcdChunk);
+  }
   if (logical >= m.off[m.n]) return false;
   int lo = 0, hi = m.n;  // off[lo] <= logical < off[hi]
   while (hi - lo > 1) {
@@ -1183,7 +1191,10 @@ LaunchTiming *&launch_timing() {
 }
 
 namespace {
-inline int grid_round(int n) { return ((n + NXCD - 1) / NXCD) * NXCD; }
+inline int grid_round(int n) {
+  const int g = NXCD * (kXcdChunk > 1 ? kXcdChunk : 1);
+  return ((n + g - 1) / g) * g;
+}
 // the tile map of a launch, cnt(e) tiles for entry e; map.n = 0 (not used)
 // when the batch has more entries than a map holds
 template <class F>

@@ -122,6 +122,12 @@ __global__ void xform_copy_pivots_kernel(const double *pool, const int64_t *offG
   }
 }
 
+// y[idx[i]] += v for i < n (distinct indices)
+__global__ void add_at_kernel(double *y, const int64_t *idx, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[idx[i]] += v;
+}
+
 // gather a sub-block: dst[a + b*ldd] = src[idx_r[a] + idx_c[b]*lds] per entry.
 // A flat launch: entry s owns the blocks [boff[s], boff[s+1]) (GB_CHUNK of its
 // nrows x ncols elements per block, host offsets from gather_offsets), so the
@@ -941,6 +947,14 @@ std::vector<DBuf *> Solver::all_buffers() {
 // elimination and -- when current -- the Schur complements: neither depends
 // on the constraints.
 void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
+  // phase times of the host rebuild (printed when verbose)
+  std::vector<std::pair<const char *, double>> marks;
+  auto tmark = std::chrono::steady_clock::now();
+  auto mark = [&](const char *what) {
+    const auto t = std::chrono::steady_clock::now();
+    marks.emplace_back(what, std::chrono::duration<double>(t - tmark).count());
+    tmark = t;
+  };
   const bool keep_struct = keep_interior && struct_ready;
   drop_pcg_graph();  // it holds the addresses of buffers released here
   for (DBuf *b : cons_buffers()) release(*b);
@@ -1024,6 +1038,7 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_offRR = upload(alloc, st, L.offRR);
   d_offRP = upload(alloc, st, L.offRP);
   d_offPP = upload(alloc, st, L.offPP);
+  mark("layout");
   h_gb_rr = gather_offsets(L.nr, L.nr);
   h_gb_rp = gather_offsets(L.nr, L.np);
   h_gb_pp = gather_offsets(L.np, L.np);
@@ -1032,9 +1047,14 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_gb_pp = upload(alloc, st, h_gb_pp);
   if (!keep_struct) build_structure(P, st);
   // transforms
+  // the rows of every glob's change of variables are stored once per glob
+  // (the substructures sharing it point at the same rows) and W = those rows
+  // minus the unit pivot entries is formed on the device, which keeps the
+  // upload of the adaptive face rows to one copy
   std::vector<GlobXf> gx;
   std::vector<int> gx_ptr(ns + 1, 0), gk_glob, gk_k;
-  std::vector<double> trow, wmat;
+  std::vector<double> trow;
+  std::vector<int64_t> glob_trow(P.cov.size(), -1), piv_idx;
   std::vector<int> pos;
   int64_t scr = 0, scrS = 0;
   for (int s = 0; s < ns; ++s) {
@@ -1047,11 +1067,12 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
       x.sub = s;
       x.m = c.m;
       x.ng = c.n;
-      x.trow_off = (int64_t)trow.size();
-      trow.insert(trow.end(), c.trow.begin(), c.trow.end());
-      for (int k = 0; k < c.m; ++k)
-        for (int t = 0; t < c.n; ++t)
-          wmat.push_back(c.trow[(size_t)k * c.n + t] - (t == c.perm[k] ? 1.0 : 0.0));
+      if (glob_trow[gi] < 0) {
+        glob_trow[gi] = (int64_t)trow.size();
+        trow.insert(trow.end(), c.trow.begin(), c.trow.end());
+        for (int k = 0; k < c.m; ++k) piv_idx.push_back(glob_trow[gi] + (int64_t)k * c.n + c.perm[k]);
+      }
+      x.trow_off = glob_trow[gi];
       x.pos_off = (int64_t)pos.size();
       for (int t = 0; t < c.n; ++t) pos.push_back((int)(L.offG[s] + S.glob_pos[a][t]));
       x.piv_off = (int64_t)pos.size();
@@ -1071,7 +1092,17 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_gx = upload(alloc, st, gx);
   d_gx_ptr = upload(alloc, st, gx_ptr);
   d_trow = upload(alloc, st, trow);
-  d_wmat = upload(alloc, st, wmat);
+  d_wmat.bytes = d_trow.bytes;
+  d_wmat.p = alloc.get(d_wmat.bytes);
+  HIPCHK(hipMemcpyAsync(d_wmat.p, d_trow.p, d_trow.bytes, hipMemcpyDeviceToDevice, st));
+  if (!piv_idx.empty()) {
+    DBuf d_piv = upload(alloc, st, piv_idx);
+    add_at_kernel<<<nblocks((int64_t)piv_idx.size()), TPB, 0, st>>>(d_wmat.as<double>(), d_piv.as<int64_t>(),
+                                                                  (int64_t)piv_idx.size(), -1.0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    release(d_piv);
+  }
   d_pos = upload(alloc, st, pos);
   d_gk_glob = upload(alloc, st, gk_glob);
   d_gk_k = upload(alloc, st, gk_k);
@@ -1099,6 +1130,7 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
     d_xf_map = upload(alloc, st, xmap);
     d_xf_map_off = upload(alloc, st, xmap_off);
   }
+  mark("transforms");
   // r / pi index maps (local interface positions and absolute positions)
   std::vector<int> ridx, pidx, rabs, pabs, pcid, sub_cids;
   std::vector<int64_t> ridx_off(ns), pidx_off(ns);
@@ -1175,6 +1207,7 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   d_descC = upload(alloc, st, h_descC);
   MatDesc dcv{0, 0, (int)nc, 1, (int)std::max<int64_t>(1, nc), (int)std::max<int64_t>(1, nc)};
   d_descCvec = upload(alloc, st, std::vector<MatDesc>{dcv});
+  mark("index maps, descriptors");
   // trsv plans
   auto plan = [&](const std::vector<int> &n, DBuf &f, DBuf &b, DBuf &o, TrsvPlan &p) {
     std::vector<int> fw, bw, off;
@@ -1226,6 +1259,7 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
   int w3 = plan({(int)nc}, d_trsv_c_fwd, d_trsv_c_bwd, d_trsv_c_off, plan_c);
   d_work_i = alloc0(alloc, st, sizeof(int) * (size_t)(4 + std::max(w1, w3)));
   d_status = alloc0(alloc, st, sizeof(int) * (size_t)(2 * ns + 2));
+  mark("triangular-solve plans");
   // matrices
   const bool p32 = factor_precision == 32;
   d_Lrr = alloc0(alloc, st, sizeof(double) * (size_t)L.sRR);
@@ -1271,8 +1305,18 @@ void Solver::build(const Problem &P, hipStream_t st, bool keep_interior) {
     bytes_Lrr_tri += (p32 ? 4.0 : 8.0) * 0.5 * (double)L.nr[s] * (L.nr[s] + 1);
   }
   HIPCHK(hipStreamSynchronize(st));
+  mark("matrices and work vectors");
   factored = false;
   struct_ready = true;
+  if (verbose) {
+    std::string line = "[bddc build]";
+    char buf[96];
+    for (auto &m : marks) {
+      std::snprintf(buf, sizeof buf, " %s %.1f ms;", m.first, 1e3 * m.second);
+      line += buf;
+    }
+    std::fprintf(stderr, "%s\n", line.c_str());
+  }
 }
 
 // The part of the layout that depends only on the mesh and partition: the
