@@ -100,12 +100,19 @@ constexpr int kMaxMapEntries = 480;
 struct TileMap {
   int n;
   int off[kMaxMapEntries + 1];
+  // xb[NXCD] > 0: XCD x takes the logical tiles [xb[x], xb[x+1]) (split by
+  // cost, xcd_balance), the grid being NXCD times the largest share
+  int xb[NXCD + 1];
 };
 constexpr int kXcdChunk = 8;
 __device__ __forceinline__ bool map_tile(const TileMap &m, int nwg, int &entry, int &tile) {
   const int b = blockIdx.x;
   int logical = b;
-  if (kXcdChunk > 1 && nwg % (NXCD * kXcdChunk) == 0) {
+  if (m.xb[NXCD] > 0) {
+    const int x = b % NXCD;
+    logical = m.xb[x] + b / NXCD;
+    if (logical >= m.xb[x + 1]) return false;
+  } else if (kXcdChunk > 1 && nwg % (NXCD * kXcdChunk) == 0) {
     const int x = b % NXCD, i = b / NXCD;
     logical = ((i / kXcdChunk) * NXCD + x) * kXcdChunk + (i % kXcdChunk);
   }
@@ -1201,11 +1208,37 @@ template <class F>
 TileMap tile_map(int batch, F cnt) {
   TileMap m;
   m.n = 0;
+  m.xb[NXCD] = 0;
   if (batch <= 0 || batch > kMaxMapEntries) return m;
   m.off[0] = 0;
   for (int e = 0; e < batch; ++e) m.off[e + 1] = m.off[e] + std::max(0, cnt(e));
   m.n = batch;
   return m;
+}
+// Consecutive tiles in whole runs per XCD, the runs cut where the summed
+// cost (cost(e) per tile of entry e) reaches each eighth of the total: every
+// XCD gets an equal share of the work and mostly whole entries (their
+// operand panels stay in one L2).  Returns the grid.
+template <class F>
+int xcd_balance(TileMap &m, F cost) {
+  if (m.n <= 0 || m.off[m.n] <= 0) return 0;
+  double tot = 0;
+  for (int e = 0; e < m.n; ++e) tot += (double)(m.off[e + 1] - m.off[e]) * std::max(1.0, (double)cost(e));
+  m.xb[0] = 0;
+  int x = 1;
+  double acc = 0;
+  for (int e = 0; e < m.n && x < NXCD; ++e) {
+    const double c = std::max(1.0, (double)cost(e));
+    for (int t = m.off[e]; t < m.off[e + 1] && x < NXCD; ++t) {
+      acc += c;
+      while (x < NXCD && acc >= tot * x / NXCD) m.xb[x++] = t + 1;
+    }
+  }
+  while (x < NXCD) m.xb[x++] = m.off[m.n];
+  m.xb[NXCD] = m.off[m.n];
+  int share = 0;
+  for (int q = 0; q < NXCD; ++q) share = std::max(share, m.xb[q + 1] - m.xb[q]);
+  return NXCD * share;
 }
 inline int blk(int n, int k) { return std::max(0, std::min(NB, n - k * NB)); }
 }  // namespace
@@ -1343,7 +1376,9 @@ static void launch_gemm(hipStream_t st, const T *A, const T *B, T *C, const Gemm
     });
   const int nt = map.n > 0 ? map.off[map.n] : batch * tm * tn;
   if (nt <= 0) return;
-  const dim3 g(grid_round(nt)), b(256);
+  // tiles of different entries differ in cost by their K: XCD shares by cost
+  const int gb = map.n > 0 ? xcd_balance(map, [&](int e) { return h_desc[e].K; }) : 0;
+  const dim3 g(gb > 0 ? gb : grid_round(nt)), b(256);
   if (!transA && !transB)
     gemm_kernel<T, false, false, MT, NT><<<g, b, 0, st>>>(A, B, C, d_desc, tm, tn, alpha, beta, lower, batch, map);
   else if (transA && !transB)
@@ -1676,13 +1711,16 @@ hipError_t DenseOps<T>::potrf(hipStream_t st, T *pool, const MatDesc *d_desc,
           bs += sizeof(T) * (m * (p1 - p0) + m * (m + 1));
         }
       LaunchScope ls(st, "chol_syrk_kernel", bs, fs);
-      const TileMap map = tile_map(batch, [&](int e) {
+      TileMap map = tile_map(batch, [&](int e) {
         const int a = (h_desc[e].n - p1 + 127) / 128;
         return h_desc[e].n > p1 ? a * (a + 1) / 2 : 0;
       });
       const int nt = map.n > 0 ? map.off[map.n] : batch * (tm * (tm + 1) / 2);
+      // tiles of equal cost (K = the panel width): equal runs of consecutive
+      // tiles per XCD
+      const int gb = map.n > 0 ? xcd_balance(map, [](int) { return 1; }) : 0;
       if (nt > 0)
-        chol_syrk_kernel<T><<<grid_round(nt), 256, 0, st>>>(pool, d_desc, p0, p1, tm, batch, map);
+        chol_syrk_kernel<T><<<gb > 0 ? gb : grid_round(nt), 256, 0, st>>>(pool, d_desc, p0, p1, tm, batch, map);
     }
   }
   return hipGetLastError();
@@ -1789,14 +1827,16 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
     const int tq = (maxr + tw - 1) / tw;
     // each entry's own tiles: its row tiles on the unsolved side times its
     // column tiles
-    const TileMap map = tile_map(batch, [&](int e) {
+    TileMap map = tile_map(batch, [&](int e) {
       const int n = h_desc[e].n;
       const int r = bwd ? (p0 < std::min(p1, n) ? p0 : 0) : std::max(0, n - p1);
       return ((r + 127) / 128) * ((h_desc[e].nrhs + tw - 1) / tw);
     });
     const int nt = map.n > 0 ? map.off[map.n] : batch * tm * tq;
     if (nt <= 0) return;
-    const unsigned g = grid_round(nt);
+    // equal runs of consecutive tiles per XCD (tiles of equal cost)
+    const int gb = map.n > 0 ? xcd_balance(map, [](int) { return 1; }) : 0;
+    const unsigned g = gb > 0 ? gb : grid_round(nt);
     if (tw == 128) {
       if (bwd)
         trsm_gemm_kernel<T, true, 4><<<g, 256, 0, st>>>(pool_a, pool_b, d_desc, p0, p1, tm, tq, batch, map);
