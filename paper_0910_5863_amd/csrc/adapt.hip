@@ -1024,6 +1024,14 @@ struct Pool {
     bufs.push_back(b);
     return b.as<T>();
   }
+  // uninitialized (for buffers that every use writes in full before reading)
+  double *raw(int64_t n) {
+    DBuf b;
+    b.bytes = std::max<size_t>(n * sizeof(double), 8);
+    b.p = A->get(b.bytes);
+    bufs.push_back(b);
+    return b.as<double>();
+  }
   double *zeros(hipStream_t st, int64_t n) {
     DBuf b;
     b.bytes = std::max<size_t>(n * sizeof(double), 8);
@@ -1208,7 +1216,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   auto dinv_for = [&](const std::vector<MatDesc> &md, double *&dv, int64_t *&doff) {
     std::vector<int64_t> off;
     const int64_t t = dinv_layout(md.data(), (int)md.size(), off);
-    dv = pool.zeros(stream, t);
+    dv = pool.raw(t);  // every block written by the factorization
     doff = pool.up(stream, off);
   };
   const int nside = 2 * np;
@@ -1274,8 +1282,9 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
       io_u[e] = (int64_t)iu_all.size();
       iu_all.insert(iu_all.end(), uidx[e].begin(), uidx[e].end());
     }
-    double *Snn = pool.zeros(stream, std::max<int64_t>(tnn, 1));
-    double *Snu = pool.zeros(stream, std::max<int64_t>(tnu, 1));
+    // written in full by the gathers below
+    double *Snn = pool.raw(std::max<int64_t>(tnn, 1));
+    double *Snu = pool.raw(std::max<int64_t>(tnu, 1));
     int64_t *d_so = pool.up(stream, src_off), *d_onn = pool.up(stream, o_nn),
             *d_onu = pool.up(stream, o_nu), *d_oo = pool.up(stream, out_off);
     int *d_lds = pool.up(stream, lds), *d_nn = pool.up(stream, nn), *d_nu = pool.up(stream, nu);
@@ -1494,7 +1503,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
       cur.swap(inner);
     }
   }
-  double *Wk = pool.zeros(stream, twk);
+  double *Wk = pool.raw(twk);  // every block written by a gather before use
   double *Sh = Wk;  // Sh of side e at off_sh[e], its S_ss at off_ss[e]
   {
     std::vector<BNode> cur = parents;  // parents of the depth being formed
@@ -1604,7 +1613,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
   }
   std::vector<int64_t> off_ss_i(np), off_ss_j(np);
   for (int p = 0; p < np; ++p) off_ss_i[p] = off_ss[2 * p], off_ss_j[p] = off_ss[2 * p + 1];
-  double *Ssum = pool.zeros(stream, tp), *Xb = pool.zeros(stream, tp), *BJf = pool.zeros(stream, tp);
+  double *Ssum = pool.raw(tp), *Xb = pool.raw(tp), *BJf = pool.raw(tp);  // written in full by pair_sum
   double *d_Q = pool.up(stream, Qall), *d_rho = pool.up(stream, rho);
   int64_t *d_off_i = pool.up(stream, off_i), *d_off_j = pool.up(stream, off_j),
           *d_off_p = pool.up(stream, off_p), *d_q_off = pool.up(stream, q_off);
@@ -1657,7 +1666,7 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
       symmetrize_kernel<<<(unsigned)bo.back(), 256, 0, stream>>>(BJf, d_off_p, d_nsp, pool.up(stream, bo), np);
     HIPCHK(hipGetLastError());
   }
-  double *Mc = pool.zeros(stream, tc), *BJc = pool.zeros(stream, tc);
+  double *Mc = pool.raw(tc), *BJc = pool.raw(tc);  // written in full by pair_restrict
   int *d_call = pool.up(stream, call), *d_nc = pool.up(stream, ncv);
   int64_t *d_c_off = pool.up(stream, c_off), *d_off_c = pool.up(stream, off_c);
   int64_t *d_off_ss_i = pool.up(stream, off_ss_i), *d_off_ss_j = pool.up(stream, off_ss_j);
@@ -1679,8 +1688,8 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
                                                                          (int64_t)zdst.size(), Zd);
     HIPCHK(hipGetLastError());
   }
-  double *T1 = pool.zeros(stream, tcz), *My = pool.zeros(stream, tdd),
-         *By = pool.zeros(stream, tdd), *Cp = pool.zeros(stream, tdd);
+  // written in full by the products (beta = 0) and the transpose below
+  double *T1 = pool.raw(tcz), *My = pool.raw(tdd), *By = pool.raw(tdd), *Cp = pool.raw(tdd);
   std::vector<GemmDesc> g1(np), g2(np);
   for (int p = 0; p < np; ++p) {
     g1[p] = GemmDesc{off_c[p], off_z[p], off_cz[p], ncv[p], dv[p], ncv[p], std::max(1, ncv[p]),
