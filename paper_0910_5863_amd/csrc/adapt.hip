@@ -547,9 +547,126 @@ __device__ void jacobi_eig(double (*H)[LOB_MAXB + 1], double (*V)[LOB_MAXB + 1],
 // U^T V run on the matrix cores.  Blocks live in global memory; every update
 // of a block is row-owned (one thread writes a whole row), so blocks are
 // updated in place.
+// Helpers for the A products of a face pair.  When a launch has few pairs,
+// each pair gets `helpers` extra work-groups that compute row groups of
+// A V for its work-group (the leader): the leader publishes a request (its
+// number, the V and A V blocks) after an agent-scope release; every row
+// group (512 rows) is claimed by one work-group with a compare-and-swap of
+// its claim word from the previous request's number to this one's, computed
+// by the same code as alone (so the bits do not depend on who computed it),
+// and marked done after a release; the leader computes the groups it claims
+// itself and waits only for groups a helper claimed -- a helper that claimed
+// one is running, so the wait ends -- then acquires.  A helper that sees no
+// request for LOB_HELPER_IDLE ticks, or the leader's end, leaves.
+constexpr int LOB_MAXCH = 16;  // row groups of 512 rows per pair (d <= 8192)
+constexpr long long LOB_HELPER_IDLE = 100000000LL;  // wall-clock ticks (1 s at 100 MHz)
+constexpr long long LOB_LEADER_WAIT = 400000000LL;  // bound of the leader's wait (4 s)
+struct LobSync {
+  int gen;        // number of the leader's latest request
+  int finished;   // the leader has left its loop
+  int nv;         // columns of the request
+  int pad;
+  int64_t vin_off, avo_off;  // V and A V of the request (pool offsets)
+  int claim[LOB_MAXCH];      // request number that claimed each row group
+  int done[LOB_MAXCH];       // request number whose row group is complete
+};
+
+// rows [512 g, 512 g + 512) of AVo = A Vin (nv <= LOB_S columns, ld d): Vin
+// staged through LDS in chunks of STAGE_ROWS rows, each wave accumulating up
+// to four 16-row tiles
+__device__ void apply_A_group(const double *A, int d_, const double *Vin, double *AVo, int nv,
+                              int g, double *stage) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int d = opaque(d_);
+  const int nrt = (d + 15) >> 4;
+  const int tg = g * 4 * LOB_NWAVE;
+  const v4d z4 = {0.0, 0.0, 0.0, 0.0};
+  v4d acc[4] = {z4, z4, z4, z4};
+  for (int c0 = 0; c0 < d; c0 += STAGE_ROWS) {
+    const int cn = min(STAGE_ROWS, d - c0);
+    __syncthreads();
+    for (int i = tid; i < cn * LOB_S; i += LOB_NT) {
+      const int c = i % cn, q = i / cn;
+      stage[c * LOB_S + q] = q < nv ? Vin[c0 + c + (int64_t)q * d] : 0.0;
+    }
+    __syncthreads();
+    int r0[4], nt = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int tile = tg + wave + LOB_NWAVE * t;
+      r0[t] = 16 * tile;
+      if (tile < nrt) nt = t + 1;
+    }
+    v4d unused[4];
+    if (nt > 0) tile_mul4<false>(A + (int64_t)c0 * d, d, r0, nt, cn, stage, nv, nullptr, 0, LOB_S, acc, unused);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int tile = tg + wave + LOB_NWAVE * t;
+    if (tile < nrt) tile_store<false>(AVo, d, 16 * tile, nv, acc[t]);
+  }
+}
+
+__device__ __forceinline__ int lob_groups(int d) { return (((d + 15) >> 4) + 4 * LOB_NWAVE - 1) / (4 * LOB_NWAVE); }
+
+// claim row group g of request r for this work-group (one CAS, broadcast)
+__device__ __forceinline__ bool lob_claim(LobSync *sy, int g, int r, int *s_flag) {
+  if (threadIdx.x == 0) *s_flag = atomicCAS(&sy->claim[g], r - 1, r) == r - 1 ? 1 : 0;
+  __syncthreads();
+  const bool mine = *s_flag != 0;
+  __syncthreads();
+  return mine;
+}
+
+// a helper work-group of pair p: row groups of the leader's requests until
+// the leader leaves
+__device__ void lob_helper(double *pool, const LobDesc *desc, LobSync *sync, int p, int h,
+                           double *stage, int *s_int) {
+  const LobDesc D = desc[p];
+  LobSync *sy = sync + p;
+  const double *A = pool + D.a_off;
+  const int ng = lob_groups(D.d);
+  int mine_req = 0;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int r = -1;
+      const long long t0 = wall_clock64();
+      for (int it = 0;; ++it) {
+        if (__hip_atomic_load(&sy->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        const int cur = __hip_atomic_load(&sy->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur > mine_req) {
+          r = cur;
+          break;
+        }
+        if ((it & 31) == 31 && wall_clock64() - t0 > LOB_HELPER_IDLE) break;
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (r > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_int[0] = r;
+    }
+    __syncthreads();
+    const int r = s_int[0];
+    __syncthreads();
+    if (r < 0) return;
+    mine_req = r;
+    const double *Vin = pool + sy->vin_off;
+    double *AVo = pool + sy->avo_off;
+    const int nv = sy->nv;
+    for (int i = 0; i < ng; ++i) {
+      const int g = (h + 1 + i) % ng;
+      if (!lob_claim(sy, g, r, s_int + 1)) continue;
+      apply_A_group(A, D.d, Vin, AVo, nv, g, stage);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_store(&sy->done[g], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobDesc *desc,
                                                         LobOut *out, int maxit, double tol,
-                                                        double tol_ind) {
+                                                        double tol_ind, int na, int helpers,
+                                                        LobSync *sync) {
   __shared__ double Hs[LOB_MAXB][LOB_MAXB + 1];  // projected / Gram matrices
   __shared__ double Qs[LOB_MAXB][LOB_MAXB + 1];  // their eigenvectors
   __shared__ __align__(16) double Cs[LOB_MAXB][2 * LOB_S];  // Ritz coefficients (X part, P part)
@@ -561,7 +678,14 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
   __shared__ double cs[LOB_MAXB / 2 + 1], sn[LOB_MAXB / 2 + 1], red[LOB_NWAVE];
   __shared__ int perm[LOB_MAXB + 2];
   __shared__ int s_keep, s_done;
+  __shared__ int s_int[4];
+  if ((int)blockIdx.x >= na) {  // a helper work-group
+    const int q = (int)blockIdx.x - na;
+    lob_helper(pool, desc, sync, q / helpers, q % helpers, stage, s_int);
+    return;
+  }
   const LobDesc D = desc[blockIdx.x];
+  if (threadIdx.x == 0) s_int[3] = 0;
   const int d_ = D.d, d = d_, s = D.s, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const double *A = pool + D.a_off;
@@ -778,36 +902,54 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
   };
   // AV = A V for nv columns: V staged through LDS in chunks of STAGE_ROWS
   // rows, each wave accumulating up to four 16-row tiles of A V
+  bool lob_abort = false;  // a helper's row group did not complete in time
   auto apply_A = [&](const double *Vin, double *AVo, int nv) {
-    const int d = opaque(d_);
-    const int nrt = (d + 15) >> 4;
-    for (int tg = 0; tg < nrt; tg += 4 * LOB_NWAVE) {
-      v4d acc[4] = {zero4, zero4, zero4, zero4};
-      for (int c0 = 0; c0 < d; c0 += STAGE_ROWS) {
-        const int cn = min(STAGE_ROWS, d - c0);
-        __syncthreads();
-        for (int i = tid; i < cn * LOB_S; i += LOB_NT) {
-          const int c = i % cn, q = i / cn;
-          stage[c * LOB_S + q] = q < nv ? Vin[c0 + c + (int64_t)q * d] : 0.0;
-        }
-        __syncthreads();
-        int r0[4], nt = 0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int tile = tg + wave + LOB_NWAVE * t;
-          r0[t] = 16 * tile;
-          if (tile < nrt) nt = t + 1;
-        }
-        v4d unused[4];
-        if (nt > 0) tile_mul4<false>(A + (int64_t)c0 * d, d, r0, nt, cn, stage, nv, nullptr, 0, LOB_S, acc, unused);
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int tile = tg + wave + LOB_NWAVE * t;
-        if (tile < nrt) tile_store<false>(AVo, d, 16 * tile, nv, acc[t]);
-      }
+    const int ng = lob_groups(d_);
+    if (helpers == 0) {
+      for (int g = 0; g < ng; ++g) apply_A_group(A, d_, Vin, AVo, nv, g, stage);
+      __syncthreads();
+      return;
+    }
+    LobSync *sy = sync + blockIdx.x;
+    // publish the request: every store of V done and released first
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) {
+      const int r = sy->gen + 1;  // only the leader writes gen
+      sy->vin_off = Vin - pool;
+      sy->avo_off = AVo - pool;
+      sy->nv = nv;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&sy->gen, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_int[0] = r;
+      s_int[2] = 0;  // bit g: claimed here
     }
     __syncthreads();
+    const int r = s_int[0];
+    for (int g = 0; g < ng; ++g) {
+      if (!lob_claim(sy, g, r, s_int + 1)) continue;
+      apply_A_group(A, d_, Vin, AVo, nv, g, stage);
+      if (tid == 0) s_int[2] |= 1 << g;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int mine = s_int[2];
+      const long long t0 = wall_clock64();
+      for (int g = 0; g < ng; ++g) {
+        if (mine & (1 << g)) continue;
+        for (int it = 0;; ++it) {
+          if (__hip_atomic_load(&sy->done[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == r) break;
+          if ((it & 31) == 31 && wall_clock64() - t0 > LOB_LEADER_WAIT) {
+            s_int[3] = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (s_int[3]) lob_abort = true;
   };
   // Rayleigh-Ritz on the current n = s + npc + nw columns: theta, and the
   // coefficients of the new X (Cs[:, 0..s)) and of the new P (Cs[:, LOB_S..):
@@ -994,9 +1136,11 @@ __global__ __launch_bounds__(LOB_NT) void lobpcg_kernel(double *pool, const LobD
     npc = kp;
     nw = 0;
   }
+  if (helpers > 0 && tid == 0)
+    __hip_atomic_store(&sync[blockIdx.x].finished, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (tid == 0) {
-    out[blockIdx.x].iters = it;
-    out[blockIdx.x].converged = done ? 1 : 0;
+    out[blockIdx.x].iters = lob_abort ? -1 : it;
+    out[blockIdx.x].converged = done && !lob_abort ? 1 : 0;
     out[blockIdx.x].nconv = nconv;
     for (int q = 0; q < 4; ++q) out[blockIdx.x].ticks[q] = ticks[q];
   }
@@ -1785,6 +1929,12 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
         src, pool.up(stream, so), dst, pool.up(stream, dO), pool.up(stream, len));
     HIPCHK(hipGetLastError());
   };
+  int cu_count = 256;  // compute units (the helper work-groups of LOBPCG)
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+  }
   for (int round = 0; round < 64 && !active.empty(); ++round) {
     const int na = (int)active.size();
     std::vector<LobDesc> lda(na);
@@ -1832,10 +1982,22 @@ AdaptResult run_adapt(Problem &P, Solver &S, AdaptState &st, double tau, int cou
         // unbatched baseline: one face pair per launch
         for (int a = 0; a < na; ++a)
           lobpcg_kernel<<<1, LOB_NT, 0, stream>>>(LP, ldb.as<LobDesc>() + a, outb.as<LobOut>() + a,
-                                                  maxit, tol, tol_ind);
+                                                  maxit, tol, tol_ind, 1, 0, nullptr);
       } else {
-        lobpcg_kernel<<<na, LOB_NT, 0, stream>>>(LP, ldb.as<LobDesc>(), outb.as<LobOut>(), maxit, tol,
-                                                 tol_ind);
+        // few pairs (the later rounds): helper work-groups for the A products,
+        // as many per pair as its row groups and the compute units allow (one
+        // work-group of this kernel per compute unit)
+        int maxd = 0;
+        for (int a = 0; a < na; ++a) maxd = std::max(maxd, lda[a].d);
+        const int groups = (((maxd + 15) / 16) + 4 * LOB_NWAVE - 1) / (4 * LOB_NWAVE);
+        int helpers = 0;
+        if (groups <= LOB_MAXCH) helpers = std::max(0, std::min(groups, cu_count / std::max(1, na)) - 1);
+        LobSync *sync = nullptr;
+        if (helpers > 0)
+          sync = reinterpret_cast<LobSync *>(
+              pool.zeros(stream, (int64_t)(na * sizeof(LobSync) + sizeof(double) - 1) / sizeof(double)));
+        lobpcg_kernel<<<na * (1 + helpers), LOB_NT, 0, stream>>>(LP, ldb.as<LobDesc>(), outb.as<LobOut>(),
+                                                                maxit, tol, tol_ind, na, helpers, sync);
       }
       HIPCHK(hipGetLastError());
     }
