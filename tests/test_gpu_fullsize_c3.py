@@ -12,7 +12,9 @@ against the oracle's stored reference results for the same mesh
 - with the FP32 local factor (factor_precision = 32), the same solution
   tolerance: the outer FP64 PCG and its true-residual check recover the
   accuracy; the error against the oracle is printed.  Its preconditioner is
-  not the oracle's (FP32 factors), so its iterations are only printed.
+  not the oracle's (FP32 factors), so its iterations are only printed;
+- every batched Cholesky run one launch per step, or fused into one launch
+  per factorization: the same bits as the default.
 """
 import numpy as np
 import pytest
@@ -114,3 +116,26 @@ def test_c3_fp32_fallback_keeps_k_rr():
     err = float(np.abs(u32 - u64).max() / np.abs(u64).max())
     print(f"fp32 against fp64 at tau 2: max-rel difference {err:.2e}")
     assert err < 1e-8, err
+
+
+@pytest.mark.parametrize("chol_launch", [1, 2])
+def test_c3_cholesky_launch_modes_bitwise(chol_launch):
+    """Every batched Cholesky of the step (interior fronts, pair eliminations,
+    K_rr, the coarse matrix) one launch per step (1) or fused into one launch
+    per factorization (2): the solution has the bits of the default run (0,
+    which fuses the smaller batches), as do omega, Nc and the iterations."""
+    st = _run()
+    from paper_0910_5863_amd import BDDC
+    g, p = st["g"], st["p"]
+    b = BDDC(autotune=True, chol_launch=chol_launch)
+    b.setup(p, "ce", adaptive_edges=True)
+    ai = b.adapt(g["tau"])
+    b.factor()
+    u, pinfo = b.pcg_solve(torch.from_numpy(p.f).to("cuda:0"))
+    u = u.cpu().numpy()[:, 0]
+    b.close()
+    torch.cuda.empty_cache()
+    ref = st[64]
+    assert (ai.omega, ai.nc) == (ref["ai"].omega, ref["ai"].nc)
+    assert pinfo[0].iters == ref["pinfo"].iters
+    assert np.array_equal(u, ref["u"])
