@@ -263,9 +263,21 @@ __global__ void apply_Tt_kernel(double *b, const GlobXf *gx, int ngx, const doub
   b += blockIdx.y * ld;
   scr += blockIdx.y * ls;
   const GlobXf x = gx[g];
+  const double *wm = wmat + x.trow_off;
+  const double *sc = scr + x.scr_off;
   for (int t = lane; t < x.ng; t += 64) {
     double acc = 0;
-    for (int k = 0; k < x.m; ++k) acc += wmat[x.trow_off + (int64_t)k * x.ng + t] * scr[x.scr_off + k];
+    // eight rows of W per batch: their loads issued together (the sum keeps
+    // the order of one row at a time)
+    int k = 0;
+    for (; k + 8 <= x.m; k += 8) {
+      double w8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) w8[u] = wm[(int64_t)(k + u) * x.ng + t];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += w8[u] * sc[k + u];
+    }
+    for (; k < x.m; ++k) acc += wm[(int64_t)k * x.ng + t] * sc[k];
     b[pos[x.pos_off + t]] += acc;
   }
 }
@@ -283,7 +295,22 @@ __global__ void apply_T_dots_kernel(const double *xv, const GlobXf *gx, const in
   const GlobXf x = gx[gk_glob[w]];
   const int k = gk_k[w];
   double acc = 0;
-  for (int t = lane; t < x.ng; t += 64) acc += trow[x.trow_off + (int64_t)k * x.ng + t] * xv[pos[x.pos_off + t]];
+  const double *tr = trow + x.trow_off + (int64_t)k * x.ng;
+  const int *ps = pos + x.pos_off;
+  // four chunks of 64 entries per batch: their loads issued together (each
+  // lane's sum keeps the order of one chunk at a time)
+  int t = lane;
+  for (; t + 192 < x.ng; t += 256) {
+    double tv[4], xw[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      tv[u] = tr[t + 64 * u];
+      xw[u] = xv[ps[t + 64 * u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += tv[u] * xw[u];
+  }
+  for (; t < x.ng; t += 64) acc += tr[t] * xv[ps[t]];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) scr[x.scr_off + k] = acc;
 }
