@@ -73,32 +73,57 @@ __global__ void mf_pull_kernel(const MfFront *F, const int *ids, const int *chil
   // (a 64-bit division costs several times a 32-bit one)
   const int nu = f.n_child > 0 ? p * fs : 0, ntot = nu + b * b;
   const int e0 = (int)(blk - boff[lo]) * PULL_CHUNK + threadIdx.x;
+  // the items' positions first, then per child all their index loads and
+  // then all their value loads, so that a thread's loads are in flight
+  // together (the sum over the children keeps its order)
+  int pr[PULL_ITEMS], pc[PULL_ITEMS];
+  bool ok[PULL_ITEMS];
 #pragma unroll
   for (int it = 0; it < PULL_ITEMS; ++it) {
     const int e = e0 + it * TPB;
-    if (e >= ntot) break;
-    int pr, pc;
-    const bool in_u = e < nu;
-    if (in_u) {
-      pr = e % p;
-      pc = e / p;
+    ok[it] = e < ntot;
+    pr[it] = pc[it] = 0;
+    if (!ok[it]) continue;
+    if (e < nu) {
+      pr[it] = e % p;
+      pc[it] = e / p;
     } else {
       const int e2 = e - nu;
       const int r = e2 % b, c = e2 / b;
-      if (r < c) continue;
-      pr = p + r;
-      pc = p + c;
+      ok[it] = r >= c;
+      pr[it] = p + r;
+      pc[it] = p + c;
     }
-    double acc = 0;
-    for (int ci = 0; ci < f.n_child; ++ci) {
-      const MfFront ch = F[child_ids[f.child_ptr + ci]];
-      const int i = pmap[ch.pmap_off + pr], j = pmap[ch.pmap_off + pc];
-      if (i >= 0 && j >= 0) acc += csym(C + ch.c_off, ch.b, i, j);
+  }
+  double acc[PULL_ITEMS];
+#pragma unroll
+  for (int it = 0; it < PULL_ITEMS; ++it) acc[it] = 0;
+  for (int ci = 0; ci < f.n_child; ++ci) {
+    const MfFront ch = F[child_ids[f.child_ptr + ci]];
+    const int *pm = pmap + ch.pmap_off;
+    const double *Cc = C + ch.c_off;
+    int ii[PULL_ITEMS], jj[PULL_ITEMS];
+#pragma unroll
+    for (int it = 0; it < PULL_ITEMS; ++it) {
+      ii[it] = ok[it] ? pm[pr[it]] : -1;
+      jj[it] = ok[it] ? pm[pc[it]] : -1;
     }
-    if (in_u)
-      U[f.u_off + e] += acc;
+    double v[PULL_ITEMS];
+#pragma unroll
+    for (int it = 0; it < PULL_ITEMS; ++it)
+      v[it] = (ii[it] >= 0 && jj[it] >= 0) ? csym(Cc, ch.b, ii[it], jj[it]) : 0.0;
+#pragma unroll
+    for (int it = 0; it < PULL_ITEMS; ++it)
+      if (ii[it] >= 0 && jj[it] >= 0) acc[it] += v[it];
+  }
+#pragma unroll
+  for (int it = 0; it < PULL_ITEMS; ++it) {
+    const int e = e0 + it * TPB;
+    if (!ok[it]) continue;
+    if (e < nu)
+      U[f.u_off + e] += acc[it];
     else
-      C[f.c_off + (e - nu)] = acc;
+      C[f.c_off + (e - nu)] = acc[it];
   }
 }
 
