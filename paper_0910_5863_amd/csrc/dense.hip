@@ -492,13 +492,21 @@ __device__ __forceinline__ float readlane(float v, int l) {
 // of the factored block to out (NB x NB, ld NB, zero outside the w x w
 // block).  Wave 0 computes; every thread of the work-group must call (the
 // barriers), and all of them copy the inverse out.  Lane r holds row r of the
-// block in registers; column c is eliminated right-looking with the entries
-// of column c broadcast from their lanes (readlane), so the column steps need
-// no barrier and no LDS traffic.  Per entry the operations and their order
-// are those of the row-by-row elimination: a = a_rc / a_cc, a_rs -= a a_sc for
-// s > c, then l_rc = a_rc / sqrt(a_cc).  The inverse is formed by lane j
-// taking column j by forward substitution against the rows of L broadcast
-// from LDS (D).  *status receives (column+1) of the first non-positive pivot.
+// block in registers.  The columns are taken in sub-blocks of DSB: within a
+// sub-block, column c is eliminated right-looking (l_rc = a_rc / sqrt(a_cc),
+// a_rs -= l_rc l_sc for the sub-block's later columns s, the l_sc broadcast
+// from their lanes by readlane: no barrier, no LDS traffic); the columns after
+// the sub-block then take the rank-DSB update A22 -= L21 L21^T of their lower
+// 16 x 16 tiles as matrix-core products, the panel staged in Y and the
+// products in D (one wave: its LDS accesses complete in order).  The inverse
+// is formed by lane j taking column j by forward substitution against the
+// rows of L broadcast from LDS (D).  *status receives (column+1) of the first
+// non-positive pivot.
+constexpr int DSB = 16;
+static_assert(DSB == 16 && NB % DSB == 0, "the trailing update works on 16 x 16 tiles");
+// orders one wave's LDS accesses across lanes: the hardware completes a wave's
+// LDS operations in issue order, so only the compiler must not move them
+__device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
 template <class T, bool COH>
 __device__ void chol_diag_block(T *pool, const MatDesc &d, int k, int *status, T *out,
                                 T (*D)[NB + 1], T (*Y)[NB + 1]) {
@@ -515,20 +523,54 @@ __device__ void chol_diag_block(T *pool, const MatDesc &d, int k, int *status, T
       row[c] = (r < w && c < w && r >= c) ? gld<COH>(&A[(kb + r) + (int64_t)(kb + c) * lda]) : T(0);
     int fail = 0;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c < w) {  // uniform
-        T piv = readlane(row[c], c);
-        if (!(piv > T(0))) {
-          if (fail == 0) fail = kb + c + 1;
-          piv = T(1);
-        }
-        const T lcc = sqrt(piv);
-        const T a = row[c] / piv;
-        // rows r > c: a_rs -= a a_sc for c < s <= r (entries above the
-        // diagonal, s > r, are updated too and never read)
+    for (int c0 = 0; c0 < NB; c0 += DSB) {
+      if (c0 < w) {  // uniform
 #pragma unroll
-        for (int sc = c + 1; sc < NB; ++sc) row[sc] -= a * readlane(row[c], sc);
-        row[c] = r == c ? lcc : row[c] / lcc;
+        for (int c = c0; c < c0 + DSB; ++c) {
+          if (c < w) {  // uniform
+            T piv = readlane(row[c], c);
+            if (!(piv > T(0))) {
+              if (fail == 0) fail = kb + c + 1;
+              piv = T(1);
+            }
+            const T lcc = sqrt(piv);
+            const T l = r == c ? lcc : row[c] / lcc;
+            row[c] = l;
+            // rows r > c: a_rs -= l_rc l_sc for the sub-block's columns
+            // c < s <= r (entries above the diagonal, s > r, are updated too
+            // and never read)
+#pragma unroll
+            for (int sc = c + 1; sc < c0 + DSB; ++sc) row[sc] -= l * readlane(l, sc);
+          }
+        }
+        if (c0 + DSB < w) {  // uniform: the trailing columns' lower tiles
+          const int l16 = r & 15, kq = r >> 4;
+          wave_lds_order();
+#pragma unroll
+          for (int q = 0; q < DSB; ++q) Y[r][q] = row[c0 + q];
+          wave_lds_order();
+#pragma unroll
+          for (int tj = c0 / 16 + 1; tj < NB / 16; ++tj) {
+#pragma unroll
+            for (int ti = tj; ti < NB / 16; ++ti) {
+              typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+              for (int q = 0; q < DSB; q += 4)
+                acc = Mfma<T>::op(Y[16 * ti + l16][q + kq], Y[16 * tj + l16][q + kq], acc);
+#pragma unroll
+              for (int t = 0; t < 4; ++t) D[16 * ti + Mfma<T>::row(r, t)][16 * tj + l16] = acc[t];
+            }
+          }
+          wave_lds_order();
+          // lane r: a_rs -= (L21 L21^T)_rs for the tiles at or below the
+          // diagonal (s / 16 <= r / 16); D is stale elsewhere and not read
+#pragma unroll
+          for (int sc = c0 + DSB; sc < NB; ++sc) {
+            const T u = D[r][sc];
+            row[sc] -= (sc >> 4) <= (r >> 4) ? u : T(0);
+          }
+          wave_lds_order();
+        }
       }
     }
 #pragma unroll
