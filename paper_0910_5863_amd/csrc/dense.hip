@@ -706,6 +706,45 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(const T *apool, T *bpool
   gemm_tile<T, BWD, false, 2, 2, 1, 4>(Di, B, B, w, d.nrhs, w, NB, d.ldb, d.ldb, T(1), T(0), 0, c0);
 }
 
+// Block row k in one launch (128-column tiles): the update by the panel's
+// solved rows as in trsm_update_kernel<NT = 4>, then, after a barrier, the
+// product with the inverse diagonal block as in trsm_diag_kernel, on the
+// same columns; the same sums in the same order as the two launches.
+template <class T, bool BWD>
+__global__ __launch_bounds__(256) void trsm_step_kernel(const T *apool, T *bpool, const MatDesc *desc,
+                                                        int k, int p0, int p1, int tu, int batch,
+                                                        const T *dinv, const int64_t *dinv_off,
+                                                        const TileMap map) {
+  __shared__ T smem[gemm_tile_lds<T, 2, 4, 1>()];
+  int e, t;
+  if (map.n > 0 ? !map_tile(map, gridDim.x, e, t) : !xcd_remap(gridDim.x, tu, batch, e, t)) return;
+  const MatDesc d = desc[e];
+  const int kb = k * NB;
+  if (kb >= d.n) return;
+  const int w = min(NB, d.n - kb);
+  const int c0 = t * 128;
+  if (c0 >= d.nrhs) return;
+  const T *L = apool + d.a_off;
+  T *B = bpool + d.b_off;
+  if (!BWD) {
+    if (kb > p0) {
+      gemm_tile_s<T, false, false, 2, 4>(smem, L + kb + (int64_t)p0 * d.lda, B + p0, B + kb, w, d.nrhs,
+                                         kb - p0, d.lda, d.ldb, d.ldb, T(-1), T(1), 0, c0);
+      __syncthreads();
+    }
+  } else {
+    const int K = min(p1, d.n) - kb - w;
+    if (K > 0) {
+      gemm_tile_s<T, true, false, 2, 4>(smem, L + (kb + w) + (int64_t)kb * d.lda, B + kb + w, B + kb,
+                                        w, d.nrhs, K, d.lda, d.ldb, d.ldb, T(-1), T(1), 0, c0);
+      __syncthreads();
+    }
+  }
+  const T *Di = dinv + dinv_off[e] + (int64_t)k * NB * NB;
+  gemm_tile_s<T, BWD, false, 2, 4>(smem, Di, B + kb, B + kb, w, d.nrhs, w, NB, d.ldb, d.ldb, T(1), T(0),
+                                   0, c0);
+}
+
 // Update of the rows outside a solved panel of block rows [p0, p1):
 // forward: B[p1:n, :] -= L[p1:n, p0:p1] B[p0:p1, :]
 // backward: B[0:p0, :] -= L[p0:q1, 0:p0]^T B[p0:q1, :], q1 = min(p1, n)
@@ -1812,31 +1851,32 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
       return (h_desc[e].nrhs + cw - 1) / cw;
     });
   };
+  // few tiles: the update and the diagonal product as two launches, the
+  // update with 32-column tiles (twice the work-groups of 64-column ones; the
+  // same sums, in the same order)
   auto update = [&](bool bwd, int k, int p0, int p1) {
-    if (!narrow) {
-      const TileMap map = col_map(128, k, p0, p1, bwd ? 2 : 1);
-      const int nt = map.n > 0 ? map.off[map.n] : batch * tu;
-      if (nt <= 0) return;
-      if (bwd)
-        trsm_update_kernel<T, true, 4, 1><<<grid_round(nt), 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0,
-                                                                         p1, tu, batch, map);
-      else
-        trsm_update_kernel<T, false, 4, 1><<<grid_round(nt), 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0,
-                                                                          p1, tu, batch, map);
-    } else {
-      // 32-column tiles: twice the work-groups of 64-column ones for few
-      // right-hand sides (the same sums, in the same order)
-      const int t32 = (maxr + 31) / 32;
-      const TileMap map = col_map(32, k, p0, p1, bwd ? 2 : 1);
-      const int nt = map.n > 0 ? map.off[map.n] : batch * t32;
-      if (nt <= 0) return;
-      if (bwd)
-        trsm_update_kernel<T, true, 1, 2><<<grid_round(nt), 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0,
-                                                                         p1, t32, batch, map);
-      else
-        trsm_update_kernel<T, false, 1, 2><<<grid_round(nt), 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0,
-                                                                          p1, t32, batch, map);
-    }
+    const int t32 = (maxr + 31) / 32;
+    const TileMap map = col_map(32, k, p0, p1, bwd ? 2 : 1);
+    const int nt = map.n > 0 ? map.off[map.n] : batch * t32;
+    if (nt <= 0) return;
+    if (bwd)
+      trsm_update_kernel<T, true, 1, 2><<<grid_round(nt), 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1,
+                                                                       t32, batch, map);
+    else
+      trsm_update_kernel<T, false, 1, 2><<<grid_round(nt), 512, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1,
+                                                                        t32, batch, map);
+  };
+  // update and diagonal product of block row k in one launch (wide case)
+  auto step = [&](bool bwd, int k, int p0, int p1) {
+    const TileMap map = col_map(128, k, p0, p1, 0);
+    const int nt = map.n > 0 ? map.off[map.n] : batch * tu;
+    if (nt <= 0) return;
+    if (bwd)
+      trsm_step_kernel<T, true><<<grid_round(nt), 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1, tu, batch,
+                                                                dinv, dinv_off, map);
+    else
+      trsm_step_kernel<T, false><<<grid_round(nt), 256, 0, st>>>(pool_a, pool_b, d_desc, k, p0, p1, tu, batch,
+                                                                 dinv, dinv_off, map);
   };
   auto diag = [&](bool bwd, int k) {
     const TileMap map = col_map(NB, k, 0, 0, 0);
@@ -1916,6 +1956,11 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
       const int k1 = std::min(nblk, k0 + PB), p0 = k0 * NB, p1 = k1 * NB;
       for (int k = k0; k < k1; ++k) {
         work(k, p0, p1, fu, bu, fd, bd);
+        if (!narrow) {
+          LaunchScope ls(st, "trsm_step_kernel<fwd>", bu + bd, fu + fd);
+          step(false, k, p0, p1);
+          continue;
+        }
         if (k > k0) {
           LaunchScope ls(st, "trsm_update_kernel<fwd>", bu, fu);
           update(false, k, p0, p1);
@@ -1933,6 +1978,11 @@ hipError_t DenseOps<T>::trsm(hipStream_t st, T *pool_a, T *pool_b, const MatDesc
       const int k1 = std::min(nblk, k0 + PB), p0 = k0 * NB, p1 = k1 * NB;
       for (int k = k1 - 1; k >= k0; --k) {
         work(k, p0, p1, fu, bu, fd, bd);
+        if (!narrow) {
+          LaunchScope ls(st, "trsm_step_kernel<bwd>", bu + bd, fu + fd);
+          step(true, k, p0, p1);
+          continue;
+        }
         if (k < k1 - 1) {
           LaunchScope ls(st, "trsm_update_kernel<bwd>", bu, fu);
           update(true, k, p0, p1);
